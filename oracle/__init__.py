@@ -1,0 +1,232 @@
+"""ctypes binding of the Louvain oracle (plain C, ``louvain_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's CPU-baseline leg
+use it. The GPU library never imports or links it.
+
+Graphs are passed as numpy arrays: offsets int64[n+1], indices int32[nnz], weights
+uint64[nnz]. 128-bit results come back as Python ints.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+MAX_PASSES = 64
+MAX_TRACE = 4096
+
+
+class OrcResult(ctypes.Structure):
+    _fields_ = [
+        ("passes", ctypes.c_int32),
+        ("iterations_total", ctypes.c_int32),
+        ("iterations", ctypes.c_int32 * MAX_PASSES),
+        ("n_pass", ctypes.c_int64 * MAX_PASSES),
+        ("nnz_pass", ctypes.c_int64 * MAX_PASSES),
+        ("cap_hits", ctypes.c_int32),
+        ("n_trace", ctypes.c_int32),
+        ("trace_pass", ctypes.c_int32 * MAX_TRACE),
+        ("trace_moved", ctypes.c_int64 * MAX_TRACE),
+        ("trace_S", ctypes.c_uint64 * (2 * MAX_TRACE)),
+        ("trace_ncand", ctypes.c_int64 * MAX_TRACE),
+        ("qnum_pass", ctypes.c_uint64 * (2 * MAX_PASSES)),
+        ("n_communities", ctypes.c_int64),
+        ("W", ctypes.c_uint64),
+        ("qnum", ctypes.c_uint64 * 2),
+    ]
+
+
+def _i128(lo: int, hi: int) -> int:
+    v = (int(hi) << 64) | int(lo)
+    return v - (1 << 128) if v >= (1 << 127) else v
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        _LIB = ctypes.CDLL(path)
+    return _LIB
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Graph:
+    """Host copy of a symmetric CSR for the oracle."""
+
+    def __init__(self, n, offsets, indices, weights):
+        self.n = int(n)
+        self.off = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.idx = np.ascontiguousarray(indices, dtype=np.int32)
+        self.w = np.ascontiguousarray(weights, dtype=np.uint64)
+        assert self.off.shape == (self.n + 1,)
+        assert self.idx.shape == self.w.shape == (int(self.off[-1]) if self.n else 0,)
+
+    @property
+    def nnz(self):
+        return int(self.idx.shape[0])
+
+    @staticmethod
+    def from_csr(g):
+        """From a ``graphgen.Csr`` (torch tensors on any device; weights reinterpreted as
+        unsigned)."""
+        import torch
+        w = g.weights.cpu()
+        if w.dtype == torch.int32:
+            w = w.numpy().view(np.uint32).astype(np.uint64)
+        else:
+            w = w.numpy().view(np.uint64)
+        return Graph(g.n, g.offsets.cpu().numpy().astype(np.int64),
+                     g.indices.cpu().numpy(), w)
+
+    def args(self):
+        return (ctypes.c_int64(self.n), _p(self.off), _p(self.idx), _p(self.w))
+
+
+def degrees(g: Graph):
+    K = np.zeros(g.n, dtype=np.uint64)
+    W = lib().orc_degrees
+    W.restype = ctypes.c_uint64
+    tot = W(ctypes.c_int64(g.n), _p(g.off), _p(g.w), _p(K))
+    return K, int(tot)
+
+
+def modularity(g: Graph, C):
+    """(Qnum, W, sigma_total) for membership C (labels in [0, n))."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    q = np.zeros(2, dtype=np.uint64)
+    W = np.zeros(1, dtype=np.uint64)
+    s = np.zeros(1, dtype=np.uint64)
+    lib().orc_modularity(*g.args(), _p(C), _p(q), _p(W), _p(s))
+    return _i128(q[0], q[1]), int(W[0]), int(s[0])
+
+
+def threshold(W: int, a: int, b: int, p: int) -> int:
+    out = np.zeros(2, dtype=np.uint64)
+    lib().orc_threshold(ctypes.c_uint64(W), ctypes.c_int32(a), ctypes.c_int32(b),
+                        ctypes.c_int32(p), _p(out))
+    return int(out[0]) | (int(out[1]) << 64)
+
+
+def community_state(g: Graph, K, C):
+    Sig = np.zeros(g.n, dtype=np.uint64)
+    cs = np.zeros(g.n, dtype=np.int32)
+    lib().orc_community_state(ctypes.c_int64(g.n), _p(K), _p(np.ascontiguousarray(C, np.int32)),
+                              _p(Sig), _p(cs))
+    return Sig, cs
+
+
+class State:
+    """Local-moving state of one pass: K, W, C, Sigma, csize (numpy, mutable)."""
+
+    def __init__(self, g: Graph, C=None):
+        self.K, self.W = degrees(g)
+        self.C = np.arange(g.n, dtype=np.int32) if C is None else np.array(C, dtype=np.int32)
+        self.Sig, self.csize = community_state(g, self.K, self.C)
+
+    def copy(self):
+        s = State.__new__(State)
+        s.K, s.W = self.K.copy(), self.W
+        s.C, s.Sig, s.csize = self.C.copy(), self.Sig.copy(), self.csize.copy()
+        return s
+
+
+def sync_iteration(g: Graph, st: State, nthreads: int = 0):
+    """One synchronous iteration in place on ``st``; returns (S, moved, candidate pairs)."""
+    S = np.zeros(2, dtype=np.uint64)
+    moved = ctypes.c_int64(0)
+    nc = ctypes.c_int64(0)
+    lib().orc_sync_iteration(*g.args(), _p(st.K), ctypes.c_uint64(st.W), _p(st.C), _p(st.Sig),
+                             _p(st.csize), ctypes.c_int32(nthreads), _p(S),
+                             ctypes.byref(moved), ctypes.byref(nc))
+    return _i128(S[0], S[1]), moved.value, nc.value
+
+
+def async_iteration(g: Graph, st: State):
+    """One asynchronous (ascending-id) iteration in place; returns (S, moved)."""
+    S = np.zeros(2, dtype=np.uint64)
+    moved = ctypes.c_int64(0)
+    lib().orc_async_iteration(*g.args(), _p(st.K), ctypes.c_uint64(st.W), _p(st.C), _p(st.Sig),
+                              _p(st.csize), _p(S), ctypes.byref(moved))
+    return _i128(S[0], S[1]), moved.value
+
+
+def decide_sample(g: Graph, st: State, verts, swap_rule: bool = True):
+    """Synchronous-rule decisions of the listed vertices against state ``st`` (not modified).
+    Returns (targets int32, gains list of int, candidate counts int64)."""
+    verts = np.ascontiguousarray(verts, dtype=np.int64)
+    t = np.zeros(verts.shape[0], dtype=np.int32)
+    gw = np.zeros(2 * verts.shape[0], dtype=np.uint64)
+    nc = np.zeros(verts.shape[0], dtype=np.int64)
+    lib().orc_decide_sample(*g.args(), _p(st.K), ctypes.c_uint64(st.W), _p(st.C), _p(st.Sig),
+                            _p(st.csize), ctypes.c_int64(verts.shape[0]), _p(verts),
+                            ctypes.c_int32(1 if swap_rule else 0), _p(t), _p(gw), _p(nc))
+    gains = [_i128(gw[2 * k], gw[2 * k + 1]) for k in range(verts.shape[0])]
+    return t, gains, nc
+
+
+def vertex_gains(g: Graph, st: State, i: int):
+    """({community: g_i(community)} over candidate communities other than C[i], stay value)."""
+    cap = g.n
+    comm = np.zeros(cap, dtype=np.int32)
+    gw = np.zeros(2 * cap, dtype=np.uint64)
+    stay = np.zeros(2, dtype=np.uint64)
+    f = lib().orc_vertex_gains
+    f.restype = ctypes.c_int64
+    cnt = f(*g.args(), _p(st.K), ctypes.c_uint64(st.W), _p(st.C), _p(st.Sig),
+            ctypes.c_int64(i), ctypes.c_int64(cap), _p(comm), _p(gw), _p(stay))
+    gains = {int(comm[k]): _i128(gw[2 * k], gw[2 * k + 1]) for k in range(cnt)}
+    return gains, _i128(stay[0], stay[1])
+
+
+def aggregate(g: Graph, C):
+    """Super-vertex graph of membership C: (map, Graph') with rows sorted."""
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    mp = np.zeros(g.n, dtype=np.int32)
+    off = np.zeros(g.n + 1, dtype=np.int64)
+    idx = np.zeros(max(g.nnz, 1), dtype=np.int32)
+    w = np.zeros(max(g.nnz, 1), dtype=np.uint64)
+    nn = ctypes.c_int64(0)
+    nz = ctypes.c_int64(0)
+    lib().orc_aggregate(*g.args(), _p(C), _p(mp), _p(off), _p(idx), _p(w),
+                        ctypes.byref(nn), ctypes.byref(nz))
+    n2, z2 = nn.value, nz.value
+    return mp, Graph(n2, off[:n2 + 1].copy(), idx[:z2].copy(), w[:z2].copy())
+
+
+def run(g: Graph, mode: str = "sync", a: int = 2, b: int = 1, max_iterations: int = 20,
+        max_passes: int = 10, nthreads: int = 0):
+    """Whole Louvain run. Returns (membership int32[n], result dict)."""
+    top = np.zeros(max(g.n, 1), dtype=np.int32)
+    r = OrcResult()
+    lib().orc_run(*g.args(), ctypes.c_int32(0 if mode == "sync" else 1), ctypes.c_int32(a),
+                  ctypes.c_int32(b), ctypes.c_int32(max_iterations), ctypes.c_int32(max_passes),
+                  ctypes.c_int32(nthreads), _p(top), ctypes.byref(r))
+    nt = r.n_trace
+    res = {
+        "passes": r.passes,
+        "iterations_total": r.iterations_total,
+        "iterations": [r.iterations[p] for p in range(r.passes)],
+        "n_pass": [r.n_pass[p] for p in range(r.passes)],
+        "nnz_pass": [r.nnz_pass[p] for p in range(r.passes)],
+        "cap_hits": r.cap_hits,
+        "trace_pass": [r.trace_pass[t] for t in range(nt)],
+        "trace_moved": [r.trace_moved[t] for t in range(nt)],
+        "trace_S": [_i128(r.trace_S[2 * t], r.trace_S[2 * t + 1]) for t in range(nt)],
+        "trace_ncand": [r.trace_ncand[t] for t in range(nt)],
+        "qnum_pass": [_i128(r.qnum_pass[2 * p], r.qnum_pass[2 * p + 1]) for p in range(r.passes)],
+        "n_communities": r.n_communities,
+        "W": r.W,
+        "qnum": _i128(r.qnum[0], r.qnum[1]),
+    }
+    res["q"] = (res["qnum"] / (res["W"] * res["W"])) if res["W"] else 0.0
+    return top[:g.n].copy(), res

@@ -1,0 +1,81 @@
+"""Planted mistakes: each plausible slip in the oracle's arithmetic must fail some pin.
+
+A mutated copy of the oracle's C source is compiled into a temporary directory (the committed
+oracle is untouched), swapped in for the duration of the check, and the pin battery of
+``test_oracle_pins`` is run against it; at least one pin must fail.
+"""
+
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.build as OB
+
+from . import test_oracle_pins as P
+
+MUTATIONS = {
+    "gain_sign": ("i128 g = (i128)W * (i128)acc[c] - Ki * (i128)Sig[c];",
+                  "i128 g = (i128)W * (i128)acc[c] + Ki * (i128)Sig[c];"),
+    "stay_drops_own_degree": ("r.stay = (i128)W * kd - Ki * ((i128)Sig[d] - Ki);",
+                              "r.stay = (i128)W * kd - Ki * ((i128)Sig[d]);"),
+    "tie_to_largest": ("(g == r.best_gain && c < r.best)", "(g == r.best_gain && c > r.best)"),
+    "swap_rule_direction": ("csize[r.best] == 1 && r.best > d", "csize[r.best] == 1 && r.best < d"),
+    "non_strict_move": ("if (r.best >= 0 && r.best_gain > r.stay)",
+                        "if (r.best >= 0 && r.best_gain >= r.stay)"),
+    "self_loop_is_candidate": ("if (j == i) continue; /* self-loop", "if (0) continue; /* self-loop"),
+    "modularity_wrong_index": ("if (C[idx[e]] == C[i]) sigma += w[e];",
+                               "if (idx[e] == C[i]) sigma += w[e];"),
+    "modularity_drops_square": ("sq += (u128)Sig[c] * Sig[c];", "sq += (u128)Sig[c];"),
+    "aggregate_transposed": ("int32_t b = map[idx[e]];", "int32_t b = map[i];"),
+    "threshold_off_by_two": ("u128 div = 2;", "u128 div = 1;"),
+    "sync_reads_current_state": ("Cn[i] = r.target;", "Cn[i] = r.target; C[i] = r.target;"),
+    "async_no_sigma_update": ("Sig[c] += K[i];\n      csize[d] -= 1;", "csize[d] -= 1;"),
+}
+
+
+def battery():
+    """The pins, run against whatever library ``oracle.lib()`` returns."""
+    P.test_threshold_values()
+    for W in [14, 10**6 + 3, 2**62]:
+        P.test_threshold_is_exact_floor(W)
+    P.test_modularity_closed_form_values()
+    P.test_modularity_all_in_one_and_singletons()
+    P.test_modularity_matches_pairwise_definition_with_self_loops()
+    P.test_single_move_identity()
+    P.test_sync_iteration_bruteforce()
+    P.test_sync_zero_gain_move_not_taken()
+    P.test_async_exact_change_per_iteration()
+    P.test_aggregation_invariants()
+    P.test_worked_example_two_triangles()
+    P.test_single_edge_run()
+    P.test_ring_of_cliques_recovered()
+
+
+def test_battery_passes_on_committed_oracle():
+    battery()
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name):
+    old, new = MUTATIONS[name]
+    src = open(OB.SRC).read()
+    assert src.count(old) == 1, name
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "mut.c")
+        lib = os.path.join(d, "libmut.so")
+        open(path, "w").write(src.replace(old, new))
+        subprocess.check_call(["gcc", "-std=gnu11", "-O1", "-fopenmp", "-fPIC", "-shared",
+                               "-w", "-o", lib, path])
+        O.lib()  # make sure the real one is loaded first
+        saved = O._LIB
+        O._LIB = ctypes.CDLL(lib)
+        try:
+            with pytest.raises(AssertionError):
+                battery()
+        finally:
+            O._LIB = saved

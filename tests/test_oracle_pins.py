@@ -1,0 +1,501 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+* closed forms (ring of cliques, all-in-one, singletons, single edge);
+* a library (networkx modularity on self-loop-free graphs);
+* the pairwise Newman-Girvan definition of modularity evaluated with exact fractions;
+* brute force over all set partitions of tiny graphs;
+* the hand-derived worked example in ``tests/golden/two_triangles.json``;
+* invariants (exact modularity change of asynchronous moves, aggregation invariants,
+  thread-count independence of the synchronous rule).
+"""
+
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from graphgen import (csr_from_arcs, csr_from_edges, erdos_renyi, ring_of_cliques, sbm, single_edge,
+                      two_triangles, add_self_loops)
+from graphgen.rng import splitmix64_sequence
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------------------------
+# independent helpers: definitions written from scratch with exact fractions
+
+
+def arcs_of(g: O.Graph):
+    for i in range(g.n):
+        for e in range(g.off[i], g.off[i + 1]):
+            yield i, int(g.idx[e]), int(g.w[e])
+
+
+def q_pairwise(g: O.Graph, C) -> Fraction:
+    """Newman-Girvan modularity from its pairwise definition,
+    Q = (1/W) * sum_{i,j} [A_ij - K_i K_j / W] * delta(C_i, C_j), with A the arc-weight matrix
+    (a self-loop's weight on the diagonal once) and K its row sums."""
+    n = g.n
+    A = {}
+    K = [0] * n
+    for i, j, w in arcs_of(g):
+        A[(i, j)] = A.get((i, j), 0) + w
+        K[i] += w
+    W = sum(K)
+    tot = Fraction(0)
+    for i in range(n):
+        for j in range(n):
+            if C[i] == C[j]:
+                tot += Fraction(A.get((i, j), 0)) - Fraction(K[i] * K[j], W)
+    return tot / W
+
+
+def random_partition(n, k, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, k, size=n).astype(np.int32)
+
+
+def small_graphs():
+    out = []
+    for s in range(6):
+        out.append(O.Graph.from_csr(erdos_renyi(9, 0.35, seed=s, weights=(1, 5))))
+    for s in range(3):
+        out.append(O.Graph.from_csr(erdos_renyi(8, 0.4, seed=10 + s, weights=(1, 7),
+                                                self_loops=True)))
+    out.append(O.Graph.from_csr(two_triangles()))
+    out.append(O.Graph.from_csr(add_self_loops(two_triangles())))
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# generator
+
+
+def test_splitmix64_published_vectors():
+    # First outputs of SplitMix64 seeded with 0 (Steele, Lea, Flood 2014 reference generator).
+    assert splitmix64_sequence(0, 4) == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                         0x06C45D188009454F, 0xF88BB8A8724C81EC]
+
+
+def test_generator_symmetric_simple():
+    g = O.Graph.from_csr(sbm(600, 6, 8.0, 2.0, seed=3, weights=(1, 16)))
+    arcs = {}
+    for i, j, w in arcs_of(g):
+        assert i != j
+        assert (i, j) not in arcs
+        arcs[(i, j)] = w
+    for (i, j), w in arcs.items():
+        assert arcs[(j, i)] == w
+
+
+# ----------------------------------------------------------------------------------------------
+# tolerance threshold (integer form of "total change in modularity > tolerance")
+
+
+def test_threshold_values():
+    assert O.threshold(14, 2, 1, 0) == 0  # 196 / 200
+    assert O.threshold(14, 2, 1, 1) == 0
+    assert O.threshold(100000, 2, 1, 0) == 5 * 10**7
+    assert O.threshold(100000, 2, 1, 1) == 5 * 10**6
+    W = 2**62
+    assert O.threshold(W, 0, 1, 0) == W * W // 2
+    assert O.threshold(W, 2, 1, 3) == W * W // (2 * 10**5)
+    assert O.threshold(W, 2, 1, 40) == 0
+
+
+@pytest.mark.parametrize("W", [1, 7, 14, 999, 10**6 + 3, 2**40 + 1, 2**62])
+def test_threshold_is_exact_floor(W):
+    for a, b, p in [(2, 1, 0), (2, 1, 1), (2, 1, 5), (0, 1, 0), (3, 2, 2), (12, 4, 1)]:
+        T = O.threshold(W, a, b, p)
+        tol = Fraction(1, 10 ** (a + b * p))
+        # S > T  <=>  2S/W^2 > tol for every integer S around the boundary
+        for S in [T - 1, T, T + 1, T + 2]:
+            if S < 0:
+                continue
+            assert (S > T) == (Fraction(2 * S, W * W) > tol)
+
+
+# ----------------------------------------------------------------------------------------------
+# modularity
+
+
+@pytest.mark.parametrize("nc,k", [(8, 5), (30, 5), (4, 3), (5, 6)])
+def test_modularity_ring_of_cliques_closed_form(nc, k):
+    g = O.Graph.from_csr(ring_of_cliques(nc, k))
+    C = np.repeat(np.arange(nc, dtype=np.int32), k)
+    qnum, W, _ = O.modularity(g, C)
+    L = k * (k - 1) // 2
+    assert Fraction(qnum, W * W) == Fraction(L, L + 1) - Fraction(1, nc)
+
+
+def test_modularity_closed_form_values():
+    # ring of 8 K5 -> 69/88; 30 K5 -> 289/330; 4 K3 -> 1/2
+    for (nc, k), q in [((8, 5), Fraction(69, 88)), ((30, 5), Fraction(289, 330)),
+                       ((4, 3), Fraction(1, 2))]:
+        g = O.Graph.from_csr(ring_of_cliques(nc, k))
+        qnum, W, _ = O.modularity(g, np.repeat(np.arange(nc, dtype=np.int32), k))
+        assert Fraction(qnum, W * W) == q
+
+
+def test_modularity_all_in_one_and_singletons():
+    for g in small_graphs():
+        qnum, W, _ = O.modularity(g, np.zeros(g.n, dtype=np.int32))
+        assert qnum == 0
+        K = [0] * g.n
+        loops = 0
+        for i, j, w in arcs_of(g):
+            K[i] += w
+            if i == j:
+                loops += w
+        qnum, W, _ = O.modularity(g, np.arange(g.n, dtype=np.int32))
+        assert qnum == W * loops - sum(x * x for x in K)
+
+
+def test_modularity_single_edge():
+    g = O.Graph.from_csr(single_edge())
+    qnum, W, _ = O.modularity(g, np.array([0, 1], dtype=np.int32))
+    assert Fraction(qnum, W * W) == Fraction(-1, 2)
+    qnum, W, _ = O.modularity(g, np.array([0, 0], dtype=np.int32))
+    assert qnum == 0
+
+
+def test_modularity_matches_networkx():
+    nx = pytest.importorskip("networkx")
+    for s in range(8):
+        g = O.Graph.from_csr(erdos_renyi(40, 0.12, seed=100 + s, weights=(1, 9)))
+        G = nx.Graph()
+        G.add_nodes_from(range(g.n))
+        for i, j, w in arcs_of(g):
+            if i < j:
+                G.add_edge(i, j, weight=w)
+        C = random_partition(g.n, 5, s)
+        comms = [set(np.nonzero(C == c)[0].tolist()) for c in range(5)]
+        comms = [c for c in comms if c]
+        qnx = nx.community.modularity(G, comms, weight="weight")
+        qnum, W, _ = O.modularity(g, C)
+        assert abs(qnum / (W * W) - qnx) < 1e-12
+
+
+def test_modularity_matches_pairwise_definition_with_self_loops():
+    for gi, g in enumerate(small_graphs()):
+        for s in range(3):
+            C = random_partition(g.n, 3, 1000 * gi + s)
+            qnum, W, _ = O.modularity(g, C)
+            assert Fraction(qnum, W * W) == q_pairwise(g, C)
+
+
+# ----------------------------------------------------------------------------------------------
+# gain formula: single-move identity against the pairwise definition
+
+
+def test_single_move_identity():
+    for gi, g in enumerate(small_graphs()):
+        C = random_partition(g.n, 4, 77 + gi)
+        st = O.State(g, C)
+        q0 = q_pairwise(g, C)
+        for i in range(g.n):
+            gains, stay = O.vertex_gains(g, st, i)
+            for c, gval in gains.items():
+                C2 = C.copy()
+                C2[i] = c
+                dq = q_pairwise(g, C2) - q0
+                assert dq == Fraction(2 * (gval - stay), st.W * st.W), (gi, i, c)
+
+
+# ----------------------------------------------------------------------------------------------
+# synchronous rule: every decision checked by brute force over modularity changes
+
+
+def sync_decisions_bruteforce(g: O.Graph, C):
+    """Next membership and S under the synchronous rule, from modularity differences only."""
+    n = g.n
+    q0 = q_pairwise(g, C)
+    W = sum(w for _, _, w in arcs_of(g))
+    csize = {c: int((C == c).sum()) for c in set(C.tolist())}
+    nbr = [set() for _ in range(n)]
+    for i, j, _ in arcs_of(g):
+        if i != j:
+            nbr[i].add(int(C[j]))
+    Cn = C.copy()
+    S = Fraction(0)
+    for i in range(n):
+        d = int(C[i])
+        best, best_dq = None, None
+        for c in sorted(nbr[i] - {d}):
+            C2 = C.copy()
+            C2[i] = c
+            dq = q_pairwise(g, C2) - q0
+            if best is None or dq > best_dq:
+                best, best_dq = c, dq
+        if best is None or best_dq <= 0:
+            continue
+        if csize[d] == 1 and csize[best] == 1 and best > d:
+            continue
+        Cn[i] = best
+        S += best_dq * W * W / 2
+    assert S.denominator == 1
+    return Cn, int(S)
+
+
+def test_sync_iteration_bruteforce():
+    for gi, g in enumerate(small_graphs()):
+        for s in range(2):
+            C = random_partition(g.n, 4 if s else g.n, 5 + gi * 10 + s)
+            if s == 0:
+                C = np.arange(g.n, dtype=np.int32)
+            st = O.State(g, C)
+            S, moved, _ = O.sync_iteration(g, st)
+            Cn, Sb = sync_decisions_bruteforce(g, C)
+            assert np.array_equal(st.C, Cn), (gi, s)
+            assert S == Sb
+            assert moved == int((Cn != C).sum())
+            Sig2, cs2 = O.community_state(g, st.K, st.C)
+            assert np.array_equal(Sig2, st.Sig) and np.array_equal(cs2, st.csize)
+
+
+def path_graph(n):
+    u = torch.arange(n - 1)
+    return O.Graph.from_csr(csr_from_edges(n, u, u + 1))
+
+
+def test_sync_zero_gain_move_not_taken():
+    # path 0-1-2 with C = [0, 0, 2]: vertex 1 has stay = 4*1 - 2*(3-2) = 2 and
+    # g(2) = 4*1 - 2*1 = 2, a move that does not increase modularity, so it stays
+    g = path_graph(3)
+    C = np.array([0, 0, 2], dtype=np.int32)
+    st = O.State(g, C)
+    gains, stay = O.vertex_gains(g, st, 1)
+    assert gains == {2: 2} and stay == 2
+    S, moved, _ = O.sync_iteration(g, st)
+    Cn, Sb = sync_decisions_bruteforce(g, C)
+    assert st.C.tolist() == Cn.tolist() == [0, 0, 0] and S == Sb == 1
+    # unit-weight graphs have many such ties
+    for s in range(4):
+        g = O.Graph.from_csr(erdos_renyi(9, 0.4, seed=50 + s))
+        C = random_partition(g.n, 3, s)
+        st = O.State(g, C)
+        O.sync_iteration(g, st)
+        Cn, _ = sync_decisions_bruteforce(g, C)
+        assert np.array_equal(st.C, Cn)
+
+
+def test_sync_thread_count_invariance():
+    g = O.Graph.from_csr(sbm(3000, 30, 8.0, 2.0, seed=7, weights=(1, 16)))
+    outs = []
+    for t in (1, 3, 8):
+        top, res = O.run(g, "sync", nthreads=t)
+        outs.append((top.tolist(), res["trace_S"], res["qnum"]))
+    assert outs[0] == outs[1] == outs[2]
+
+
+# ----------------------------------------------------------------------------------------------
+# asynchronous rule: every applied gain is the exact modularity change
+
+
+def test_async_exact_change_per_iteration():
+    for gi, g in enumerate(small_graphs() + [O.Graph.from_csr(sbm(500, 5, 8, 2, seed=9,
+                                                                     weights=(1, 16)))]):
+        st = O.State(g)
+        q_prev, W, _ = O.modularity(g, st.C)
+        for _ in range(6):
+            S, moved = O.async_iteration(g, st)
+            q, _, _ = O.modularity(g, st.C)
+            assert q - q_prev == 2 * S
+            assert S >= 0 and (moved > 0) == (S > 0)
+            q_prev = q
+
+
+# ----------------------------------------------------------------------------------------------
+# aggregation invariants
+
+
+def check_aggregation(g: O.Graph, C):
+    st = O.State(g, C)
+    mp, g2 = O.aggregate(g, C)
+    labels = sorted(set(C.tolist()))
+    rank = {c: r for r, c in enumerate(labels)}
+    assert g2.n == len(labels)
+    assert [rank[int(c)] for c in C] == mp.tolist()
+    K2, W2 = O.degrees(g2)
+    assert W2 == st.W
+    assert K2.tolist() == [int(st.Sig[c]) for c in labels]
+    arcs = {}
+    for a, b, w in arcs_of(g2):
+        assert (a, b) not in arcs
+        arcs[(a, b)] = w
+    for (a, b), w in arcs.items():
+        assert arcs[(b, a)] == w
+    for c in labels:
+        sigma_c = sum(w for i, j, w in arcs_of(g) if C[i] == c and C[j] == c)
+        assert arcs.get((rank[c], rank[c]), 0) == sigma_c
+    for a in range(g2.n):
+        row = g2.idx[g2.off[a]:g2.off[a + 1]]
+        assert np.all(np.diff(row) > 0)
+    q1, _, _ = O.modularity(g, C)
+    q2, _, _ = O.modularity(g2, np.arange(g2.n, dtype=np.int32))
+    assert q1 == q2
+
+
+def test_aggregation_invariants():
+    for gi, g in enumerate(small_graphs()):
+        check_aggregation(g, random_partition(g.n, 3, 300 + gi))
+        check_aggregation(g, np.arange(g.n, dtype=np.int32))
+        check_aggregation(g, np.zeros(g.n, dtype=np.int32))
+    g = O.Graph.from_csr(sbm(400, 8, 8, 2, seed=5, weights=(1, 16)))
+    st = O.State(g)
+    O.sync_iteration(g, st)
+    O.sync_iteration(g, st)
+    check_aggregation(g, st.C)
+
+
+def test_aggregation_with_duplicate_arcs():
+    # duplicate arcs in a row mean their summed weight
+    src = torch.tensor([0, 0, 0, 0, 1, 1, 2, 2, 2])
+    dst = torch.tensor([1, 1, 2, 2, 0, 0, 2, 0, 0])
+    w = torch.tensor([2, 3, 1, 1, 3, 2, 4, 1, 1])
+    g = O.Graph.from_csr(csr_from_arcs(3, src, dst, w))
+    mp, g2 = O.aggregate(g, np.array([0, 1, 2], dtype=np.int32))
+    rows = {a: dict(zip(g2.idx[g2.off[a]:g2.off[a + 1]].tolist(),
+                        g2.w[g2.off[a]:g2.off[a + 1]].tolist())) for a in range(3)}
+    assert rows == {0: {1: 5, 2: 2}, 1: {0: 5}, 2: {0: 2, 2: 4}}
+    check_aggregation(g, np.array([0, 0, 1], dtype=np.int32))
+
+
+# ----------------------------------------------------------------------------------------------
+# worked example (golden)
+
+
+def test_worked_example_two_triangles():
+    gold = json.load(open(os.path.join(GOLDEN, "two_triangles.json")))
+    g = O.Graph.from_csr(two_triangles())
+    st = O.State(g)
+    assert st.W == gold["W"] and st.K.tolist() == gold["K"]
+    assert O.modularity(g, st.C)[0] == gold["qnum_singletons"]
+    assert O.threshold(st.W, 2, 1, 0) == gold["threshold_pass0"]
+    assert O.threshold(st.W, 2, 1, 1) == gold["threshold_pass1"]
+    for i, rec in gold["iteration1_gains"].items():
+        gains, stay = O.vertex_gains(g, st, int(i))
+        assert {str(c): v for c, v in gains.items()} == rec["candidates"]
+        assert stay == rec["stay"]
+    for rec in gold["sync_iterations"]:
+        S, moved, _ = O.sync_iteration(g, st)
+        assert st.C.tolist() == rec["C"]
+        assert {str(c): int(st.Sig[c]) for c in range(g.n) if st.csize[c]} == rec["Sigma"]
+        assert {str(c): int(st.csize[c]) for c in range(g.n) if st.csize[c]} == rec["csize"]
+        assert S == rec["S"] and moved == rec["moved"]
+        assert O.modularity(g, st.C)[0] == rec["qnum"]
+    mp, g2 = O.aggregate(g, st.C)
+    assert mp.tolist() == gold["aggregate"]["map"] and g2.n == gold["aggregate"]["n"]
+    arcs = [[a, b, w] for a, b, w in arcs_of(g2)]
+    assert arcs == gold["aggregate"]["arcs"]
+    st2 = O.State(g2)
+    assert st2.K.tolist() == gold["aggregate"]["K"]
+    assert O.modularity(g2, st2.C)[0] == gold["aggregate"]["qnum_singletons"]
+    gains, stay = O.vertex_gains(g2, st2, 0)
+    assert gains == {1: gold["pass1_merge_gain"]} and stay == 0
+    top, res = O.run(g, "sync")
+    assert top.tolist() == gold["final_membership"] and res["qnum"] == gold["final_qnum"]
+    assert Fraction(res["qnum"], res["W"] ** 2) == Fraction(*gold["q_opt"])
+    # asynchronous variant
+    st = O.State(g)
+    for S_exp, q_exp in zip(gold["async_iterations_S"], gold["async_qnum"]):
+        S, _ = O.async_iteration(g, st)
+        assert S == S_exp and O.modularity(g, st.C)[0] == q_exp
+    assert st.C.tolist() == gold["async_labels_before_renumbering"]
+    top, res = O.run(g, "async")
+    assert top.tolist() == gold["final_membership"]
+
+
+def test_single_edge_run():
+    g = O.Graph.from_csr(single_edge())
+    st = O.State(g)
+    S, moved, _ = O.sync_iteration(g, st)
+    # 1 -> 0 allowed, 0 -> 1 blocked by singleton-swap prevention
+    assert st.C.tolist() == [0, 0] and moved == 1
+    top, res = O.run(g, "sync")
+    assert top.tolist() == [0, 0] and res["qnum"] == 0
+
+
+def test_empty_graphs():
+    g = O.Graph(0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.uint64))
+    top, res = O.run(g, "sync")
+    assert top.tolist() == [] and res["qnum"] == 0 and res["passes"] == 0
+    g = O.Graph(5, np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0, np.uint64))
+    top, res = O.run(g, "sync")
+    assert top.tolist() == list(range(5)) and res["qnum"] == 0 and res["passes"] == 0
+
+
+# ----------------------------------------------------------------------------------------------
+# whole runs: brute-force optimum bounds the result; planted structure is recovered
+
+
+def set_partitions(n):
+    """Restricted growth strings of length n (every set partition once)."""
+    a = [0] * n
+
+    def rec(i, m):
+        if i == n:
+            yield list(a)
+            return
+        for v in range(m + 2):
+            a[i] = v
+            yield from rec(i + 1, max(m, v))
+
+    if n == 0:
+        yield []
+        return
+    a[0] = 0
+    yield from rec(1, 0)
+
+
+def q_opt_bruteforce(g: O.Graph) -> Fraction:
+    best = None
+    W = None
+    for part in set_partitions(g.n):
+        qnum, W, _ = O.modularity(g, np.array(part, dtype=np.int32))
+        if best is None or qnum > best:
+            best = qnum
+    return Fraction(best, W * W)
+
+
+def test_set_partition_count():
+    assert sum(1 for _ in set_partitions(6)) == 203
+    assert sum(1 for _ in set_partitions(8)) == 4140
+
+
+def test_bruteforce_bounds_louvain():
+    graphs = [O.Graph.from_csr(two_triangles())]
+    graphs += [O.Graph.from_csr(erdos_renyi(8, 0.4, seed=s, weights=(1, 4))) for s in range(4)]
+    for gi, g in enumerate(graphs):
+        qo = q_opt_bruteforce(g)
+        for mode in ("sync", "async"):
+            top, res = O.run(g, mode)
+            q = Fraction(res["qnum"], res["W"] ** 2)
+            assert q <= qo, (gi, mode)
+            if gi == 0:
+                assert q == qo == Fraction(5, 14)
+
+
+def test_ring_of_cliques_recovered():
+    g = O.Graph.from_csr(ring_of_cliques(8, 5))
+    for mode in ("sync", "async"):
+        top, res = O.run(g, mode)
+        assert res["n_communities"] == 8
+        assert Fraction(res["qnum"], res["W"] ** 2) == Fraction(69, 88)
+        assert top.tolist() == np.repeat(np.arange(8), 5).tolist()
+        # the second pass makes no move: a merge gain is 176*1 - 22*22 < 0
+        assert res["passes"] == 2 and res["iterations"][1] == 1
+
+
+def test_quality_sync_vs_async_sbm10k():
+    g = O.Graph.from_csr(sbm(10000, 100, 8.0, 2.0, seed=1))
+    _, rs = O.run(g, "sync")
+    _, ra = O.run(g, "async")
+    # async passes never lower Q (every applied move raises it exactly; aggregation keeps it)
+    qa = ra["qnum_pass"]
+    assert all(qa[p + 1] >= qa[p] for p in range(len(qa) - 1))
+    assert rs["q"] >= ra["q"] - 0.01
