@@ -1,0 +1,199 @@
+/*
+ * louvain.h -- C ABI of the MI355X (gfx950) Louvain library, liblouvain.so.
+ *
+ * The library runs the static Louvain method of Sahu, "Enhancing Efficiency in Parallel
+ * Louvain Algorithm for Community Detection" (arXiv 2301.12390), section 3.2: passes of a
+ * local-moving phase (every vertex moves to the neighbour community of greatest modularity
+ * increase, repeated while an iteration's total modularity change exceeds a tolerance that
+ * shrinks by a decline factor each pass) and an aggregation phase (communities collapse into
+ * super-vertices, combined edge weights, intra-community edges become self-loops).
+ *
+ * The local-moving phase uses the synchronous (Jacobi) rule the paper compares in section 3.2:
+ * every decision reads only the previous iteration's memberships. It is exact integer
+ * arithmetic throughout, so results are deterministic and independent of scheduling:
+ *   W       = sum of all arc weights; K_i = row sum of i (a self-loop counts once);
+ *   Sigma_c = sum of K_i over community c; k_{i->x} = weight of i's non-self arcs into x;
+ *   gain of placing i into x: g_i(x) = W*k_{i->x} - K_i*(Sigma_x - [x == C_i]*K_i)
+ *   (twice the change in W^2*Q of the move, Blondel et al.'s delta-modularity scaled by W^2/2).
+ * A vertex moves to the candidate (a non-self neighbour's community) of largest g, ties to
+ * the smallest community id, iff that g is strictly larger than g_i(own community) and it is
+ * not a singleton about to swap with a singleton of larger id. An iteration's gain sum S
+ * continues the phase iff S > floor(W^2 / (2*10^(a+b*p))) in pass p (tolerance 10^-a declining
+ * by 10^b per pass; the paper's defaults are a = 2, b = 1).
+ *
+ * Partial asynchrony (section 3.2 recommends it over a fully synchronous rule): with
+ * substeps = K > 1 the vertices of pass p are split into K classes, vertex v going to class
+ * floor(hi32(s) * K / 2^32) where s = SplitMix64 output v+1 of the sequence started at state p
+ * (s = mix(p + (v+1)*0x9E3779B97F4A7C15), Steele et al. 2014). An iteration is then K
+ * synchronous steps, class 0 first, each step reading the memberships left by the steps
+ * before it. K = 1 is the fully synchronous rule.
+ *
+ * Graph format (all functions): a symmetric CSR of arcs. An undirected edge {u,v} is stored as
+ * arcs (u,v) and (v,u); a self-loop (u,u) is stored once. Rows need not be sorted; repeated
+ * arcs in a row mean their summed weight. Weights are integers >= 1.
+ *
+ * Pointers are DEVICE pointers unless marked (host). Inputs and outputs are owned by the
+ * caller and must stay valid until the work enqueued on `stream` has completed; functions
+ * with host outputs synchronise `stream` before returning. The library owns only its context
+ * workspace (tables, scan temporaries, super-vertex graphs), charged to the HBM budget given
+ * at creation. `stream` is a hipStream_t (NULL = the default stream).
+ *
+ * Errors: every function returns an lv_status; no exception crosses the boundary. On error
+ * the outputs are unspecified and the context stays usable (after a sticky HIP error it
+ * should be destroyed). louvain_last_error() describes the last failure. A context is not
+ * thread-safe: use one per host thread.
+ */
+#ifndef LOUVAIN_H
+#define LOUVAIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LV_OK = 0,
+  LV_EINVAL = -1,    /* null pointer, negative size, bad parameter, or invalid graph */
+  LV_ENOMEM = -2,    /* device allocation failed */
+  LV_EHIP = -3,      /* a HIP runtime call or kernel launch failed */
+  LV_EOVERFLOW = -4, /* n >= 2^31, nnz >= 2^31 with int32 offsets, or W > 2^62 */
+  LV_EBUDGET = -5    /* the workspace would exceed the context's HBM budget */
+} lv_status;
+
+/* 128-bit two's-complement integer: value = hi * 2^64 + lo. */
+typedef struct {
+  uint64_t lo;
+  int64_t hi;
+} lv_i128;
+
+typedef struct lv_ctx lv_ctx;
+
+/* Symmetric CSR of arcs (see above). */
+typedef struct {
+  int64_t n;               /* vertices, 0 <= n < 2^31 */
+  int64_t nnz;             /* arcs */
+  const void* offsets;     /* [n+1], int32 if offsets_64 == 0 else int64; offsets[0] == 0 */
+  const int32_t* indices;  /* [nnz], neighbour ids in [0, n) */
+  const void* weights;     /* [nnz], uint32 if weights_64 == 0 else uint64; each >= 1 */
+  int32_t offsets_64;
+  int32_t weights_64;
+} lv_graph;
+
+#define LV_VALIDATE 0x1u   /* check indices, weights and offsets on the device (O(nnz)) */
+#define LV_TRACE 0x2u      /* time the kernels of every iteration with HIP events */
+#define LV_FORCE_WIDE 0x4u /* use 128-bit gains and 64-bit table values even when 64-bit
+                              gains are exact (results are identical; for testing) */
+
+typedef struct {
+  int32_t tolerance_exp10; /* initial tolerance 10^-a, a >= 0 (paper's best: a = 2) */
+  int32_t decline_exp10;   /* tolerance divided by 10^b between passes, b >= 0 (b = 1) */
+  int32_t max_iterations;  /* local-moving iterations per pass, >= 1 (default 20) */
+  int32_t max_passes;      /* passes, 1..64 (default 10) */
+  int32_t substeps;        /* vertex classes per iteration, 1..32 (1 = fully synchronous) */
+  uint32_t flags;          /* LV_* flags */
+} lv_params;
+
+#define LV_MAX_PASSES 64
+#define LV_MAX_TRACE 1024
+
+/* One local-moving iteration (host). */
+typedef struct {
+  int32_t pass, iteration;
+  int32_t wide;            /* 1 if this iteration used 128-bit gains */
+  int32_t substeps;        /* class steps of the iteration (launches of each kernel) */
+  lv_i128 gain_sum;        /* S: sum of the applied gains */
+  int64_t moved;           /* vertices that changed community */
+  int64_t candidates;      /* distinct (vertex, other community) pairs examined */
+  int64_t lds_vertices;    /* vertices decided by the LDS-table move kernel */
+  int64_t lds_arcs;        /* arcs scanned by that kernel */
+  int64_t hub_vertices;    /* vertices decided by the global-table (hub) kernels */
+  int64_t hub_arcs;
+  int64_t lds_candidates;  /* the part of `candidates` found by the LDS-table kernel */
+  int64_t lds_moved;       /* the part of `moved` decided by the LDS-table kernel */
+  float move_ms;           /* LDS move kernel, summed over the class steps (LV_TRACE) */
+  float hub_ms;            /* hub kernels, summed over the class steps (LV_TRACE) */
+  float update_ms;         /* membership/community updates, summed (LV_TRACE) */
+  float iter_ms;           /* whole iteration including the host read-back (LV_TRACE) */
+} lv_iter_trace;
+
+/* Result of louvain_run (host). */
+typedef struct {
+  int32_t passes;                         /* passes that ran a local-moving phase */
+  int32_t iterations_total;
+  int32_t iterations[LV_MAX_PASSES];
+  int64_t n_pass[LV_MAX_PASSES];          /* vertices of the graph pass p ran on */
+  int64_t nnz_pass[LV_MAX_PASSES];        /* arcs of that graph */
+  lv_i128 qnum_pass[LV_MAX_PASSES];       /* W^2*Q after pass p's local-moving phase */
+  int32_t cap_hits;                       /* phases stopped by max_iterations */
+  int32_t n_trace;                        /* records in trace[] (first LV_MAX_TRACE) */
+  int64_t n_communities;                  /* communities of the result */
+  uint64_t W;                             /* total arc weight */
+  lv_i128 q_num;                          /* W^2 * Q of the result, exact */
+  double q;                               /* Q = q_num / W^2 (0 when W == 0) */
+  float total_ms;                         /* host wall time of the call */
+  float aggregate_ms[LV_MAX_PASSES];      /* aggregation duration per pass (LV_TRACE) */
+  lv_iter_trace trace[LV_MAX_TRACE];
+} lv_result;
+
+/* Statistics of louvain_move (host). */
+typedef struct {
+  int32_t iterations;      /* iterations run */
+  int32_t hit_cap;         /* 1 if stopped by max_iterations rather than the tolerance */
+  int64_t moved;           /* total moves */
+  lv_i128 gain_sum;        /* sum of S over the iterations */
+  lv_i128 last_gain;       /* S of the last iteration */
+  int64_t last_moved;      /* moves of the last iteration */
+  int64_t last_candidates; /* candidate pairs of the last iteration */
+} lv_move_stats;
+
+/* Context: binds a device and a workspace limited to hbm_budget_bytes (0 = no limit).
+ * Returns LV_EINVAL for a bad device or null out, LV_EHIP if the device cannot be set. */
+lv_status louvain_ctx_create(int device, uint64_t hbm_budget_bytes, lv_ctx** out);
+void louvain_ctx_destroy(lv_ctx* ctx);
+/* Text of the last failure on this context ("" if none). Valid until the next call. */
+const char* louvain_last_error(const lv_ctx* ctx);
+/* Bytes of device workspace currently held by the context. */
+uint64_t louvain_workspace_bytes(const lv_ctx* ctx);
+
+/* Whole method (section 3.2): passes of local-moving + aggregation until a pass moves nothing,
+ * aggregation stops shrinking the graph, or max_passes is reached.
+ * membership: [n] out, the community of every input vertex in the last level of the
+ * dendrogram (dense ids 0..n_communities-1; the identity if no pass aggregated).
+ * res (host): passes, iterations, per-iteration trace, W and exact Q. */
+lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_t* membership,
+                      lv_result* res, void* stream);
+
+/* One local-moving phase (section 3.2) on an arbitrary state, under pass p's tolerance
+ * (max_iterations = 1 runs exactly one synchronous iteration: the per-iteration parity entry).
+ * K: [n] row sums, or NULL to compute them. W: total arc weight, or 0 to compute it.
+ * C: [n] in/out community labels in [0, n). Sigma: [n] in/out, Sigma[c] = sum of K over c.
+ * csize: [n] in/out, csize[c] = members of c. Sigma and csize must match C on entry.
+ * stats (host, may be NULL). */
+lv_status louvain_move(lv_ctx* ctx, const lv_graph* g, const uint64_t* K, uint64_t W,
+                       int32_t pass_index, const lv_params* p, int32_t* C, uint64_t* Sigma,
+                       int32_t* csize, lv_move_stats* stats, void* stream);
+
+/* Aggregation phase (section 3.2): collapse the communities of C (labels in [0, n)) into
+ * super-vertices numbered by ascending rank of their label. Arcs between communities combine
+ * into super-arcs; arcs inside a community combine into the super-vertex's self-loop.
+ * map: [n] out, super-vertex of every vertex. offsets_out: [n+1] out, int64 when
+ * offsets_64_out else int32. indices_out: [nnz] out. weights_out: [nnz] out, uint64 (sums may
+ * exceed 32 bits). Output rows hold distinct neighbours in unspecified order.
+ * n_out, nnz_out (host): size of the super-vertex graph. */
+lv_status louvain_aggregate(lv_ctx* ctx, const lv_graph* g, const int32_t* C, int32_t* map,
+                            void* offsets_out, int32_t offsets_64_out, int32_t* indices_out,
+                            uint64_t* weights_out, int64_t* n_out, int64_t* nnz_out,
+                            void* stream);
+
+/* Modularity (section 1: Newman-Girvan) of membership C (labels in [0, n)):
+ * q_num = W * sum_c sigma_c - sum_c Sigma_c^2 exactly (sigma_c: weight of arcs inside c),
+ * W = total weight, q = q_num / W^2. All outputs host; any may be NULL. */
+lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, lv_i128* q_num,
+                             uint64_t* W, double* q, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOUVAIN_H */

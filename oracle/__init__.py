@@ -151,6 +151,46 @@ def sync_iteration(g: Graph, st: State, nthreads: int = 0):
     return _i128(S[0], S[1]), moved.value, nc.value
 
 
+def vertex_class(p: int, K: int, v: int) -> int:
+    f = lib().orc_vertex_class
+    f.restype = ctypes.c_int32
+    return int(f(ctypes.c_int32(p), ctypes.c_int32(K), ctypes.c_int64(v)))
+
+
+def sync_step(g: Graph, st: State, verts, nthreads: int = 0):
+    """One synchronous step over the listed vertices (others keep their community), in place;
+    returns (S, moved, candidate pairs)."""
+    verts = np.ascontiguousarray(verts, dtype=np.int32)
+    S = np.zeros(2, dtype=np.uint64)
+    moved = ctypes.c_int64(0)
+    nc = ctypes.c_int64(0)
+    lib().orc_sync_step(*g.args(), _p(st.K), ctypes.c_uint64(st.W), _p(st.C), _p(st.Sig),
+                        _p(st.csize), _p(verts), ctypes.c_int64(verts.shape[0]),
+                        ctypes.c_int32(nthreads), _p(S), ctypes.byref(moved), ctypes.byref(nc))
+    return _i128(S[0], S[1]), moved.value, nc.value
+
+
+def class_lists(n: int, p: int, K: int):
+    """Vertices of each class of pass p (ascending)."""
+    if K == 1:
+        return [np.arange(n, dtype=np.int32)]
+    cls = np.array([vertex_class(p, K, v) for v in range(n)], dtype=np.int32)
+    return [np.nonzero(cls == k)[0].astype(np.int32) for k in range(K)]
+
+
+def substep_iteration(g: Graph, st: State, p: int, K: int, classes=None):
+    """One iteration of K class steps in place; returns (S, moved, candidate pairs)."""
+    if classes is None:
+        classes = class_lists(g.n, p, K)
+    S = moved = nc = 0
+    for vs in classes:
+        a, b, c = sync_step(g, st, vs)
+        S += a
+        moved += b
+        nc += c
+    return S, moved, nc
+
+
 def async_iteration(g: Graph, st: State):
     """One asynchronous (ascending-id) iteration in place; returns (S, moved)."""
     S = np.zeros(2, dtype=np.uint64)
@@ -204,13 +244,15 @@ def aggregate(g: Graph, C):
 
 
 def run(g: Graph, mode: str = "sync", a: int = 2, b: int = 1, max_iterations: int = 20,
-        max_passes: int = 10, nthreads: int = 0):
-    """Whole Louvain run. Returns (membership int32[n], result dict)."""
+        max_passes: int = 10, substeps: int = 1, nthreads: int = 0):
+    """Whole Louvain run. Returns (membership int32[n], result dict).
+    mode "sync": synchronous rule, an iteration being ``substeps`` class steps;
+    mode "async": sequential asynchronous rule."""
     top = np.zeros(max(g.n, 1), dtype=np.int32)
     r = OrcResult()
     lib().orc_run(*g.args(), ctypes.c_int32(0 if mode == "sync" else 1), ctypes.c_int32(a),
                   ctypes.c_int32(b), ctypes.c_int32(max_iterations), ctypes.c_int32(max_passes),
-                  ctypes.c_int32(nthreads), _p(top), ctypes.byref(r))
+                  ctypes.c_int32(substeps), ctypes.c_int32(nthreads), _p(top), ctypes.byref(r))
     nt = r.n_trace
     res = {
         "passes": r.passes,

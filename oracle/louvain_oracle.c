@@ -52,6 +52,24 @@ static void put_i128(uint64_t* out, i128 v) {
   out[1] = (uint64_t)((u128)v >> 64);
 }
 
+/* Vertex classes of the partially asynchronous rule. Section 3.2 of the paper recommends
+ * asynchronous or partially asynchronous vertex processing over a fully synchronous one (it
+ * cites graph colouring as one way). Here the vertices of pass p are split into K classes by a
+ * counter-based SplitMix64 draw (Steele, Lea, Flood 2014): the draw for vertex v is the
+ * (v+1)-th output of the sequence started at state p, mix(p + (v+1)*0x9E3779B97F4A7C15), and
+ * its upper 32 bits select the class floor(hi32 * K / 2^32). */
+static uint64_t splitmix64_finaliser(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int32_t orc_vertex_class(int32_t pass, int32_t K, int64_t v) {
+  uint64_t z = (uint64_t)pass + ((uint64_t)v + 1u) * 0x9E3779B97F4A7C15ull;
+  uint64_t hi = splitmix64_finaliser(z) >> 32;
+  return (int32_t)((hi * (uint64_t)K) >> 32);
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Degrees, total weight, modularity                                                          */
 /* ---------------------------------------------------------------------------------------- */
@@ -240,18 +258,21 @@ void orc_community_state(int64_t n, const uint64_t* K, const int32_t* C, uint64_
   }
 }
 
-/* One synchronous (Jacobi) iteration: all decisions read only (C, Sig, csize) as given, then
- * the new membership is written and Sigma/csize are recomputed from it.
+/* One synchronous (Jacobi) step over a set of vertices: every listed vertex decides from
+ * (C, Sig, csize) as given, then the new memberships are written and Sigma/csize are
+ * recomputed. Unlisted vertices keep their community. verts == NULL means all vertices.
  * In/out: C, Sig, csize. Out: S (two words), moved count, candidate-pair count.
  * nthreads <= 0 uses the OpenMP default; the result does not depend on it. */
-void orc_sync_iteration(int64_t n, const int64_t* off, const int32_t* idx, const uint64_t* w,
-                        const uint64_t* K, uint64_t W, int32_t* C, uint64_t* Sig,
-                        int32_t* csize, int32_t nthreads, uint64_t* S_out, int64_t* moved_out,
-                        int64_t* ncand_out) {
+void orc_sync_step(int64_t n, const int64_t* off, const int32_t* idx, const uint64_t* w,
+                   const uint64_t* K, uint64_t W, int32_t* C, uint64_t* Sig, int32_t* csize,
+                   const int32_t* verts, int64_t nverts, int32_t nthreads, uint64_t* S_out,
+                   int64_t* moved_out, int64_t* ncand_out) {
+  int64_t m = verts ? nverts : n;
   int32_t* Cn = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-  i128* gain = (i128*)malloc(sizeof(i128) * (size_t)(n > 0 ? n : 1));
-  int64_t* nc = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  i128* gain = (i128*)malloc(sizeof(i128) * (size_t)(m > 0 ? m : 1));
+  int64_t* nc = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
   int64_t maxdeg = max_degree(n, off);
+  memcpy(Cn, C, sizeof(int32_t) * (size_t)n);
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -262,21 +283,23 @@ void orc_sync_iteration(int64_t n, const int64_t* off, const int32_t* idx, const
     uint64_t* acc = (uint64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
     int32_t* list = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
 #pragma omp for schedule(dynamic, 1024)
-    for (int64_t i = 0; i < n; i++) {
+    for (int64_t t = 0; t < m; t++) {
+      int64_t i = verts ? verts[t] : t;
       decision r = decide(i, off, idx, w, K, W, C, Sig, csize, 1, acc, list);
       Cn[i] = r.target;
-      gain[i] = r.gain;
-      nc[i] = r.ncand;
+      gain[t] = r.gain;
+      nc[t] = r.ncand;
     }
     free(list);
     free(acc);
   }
   i128 S = 0;
   int64_t moved = 0, ncand = 0;
-  for (int64_t i = 0; i < n; i++) {
-    S += gain[i];
+  for (int64_t t = 0; t < m; t++) {
+    int64_t i = verts ? verts[t] : t;
+    S += gain[t];
     moved += (Cn[i] != C[i]);
-    ncand += nc[i];
+    ncand += nc[t];
   }
   memcpy(C, Cn, sizeof(int32_t) * (size_t)n);
   orc_community_state(n, K, C, Sig, csize);
@@ -286,6 +309,15 @@ void orc_sync_iteration(int64_t n, const int64_t* off, const int32_t* idx, const
   free(nc);
   free(gain);
   free(Cn);
+}
+
+/* One synchronous (Jacobi) iteration: a step over all vertices. */
+void orc_sync_iteration(int64_t n, const int64_t* off, const int32_t* idx, const uint64_t* w,
+                        const uint64_t* K, uint64_t W, int32_t* C, uint64_t* Sig,
+                        int32_t* csize, int32_t nthreads, uint64_t* S_out, int64_t* moved_out,
+                        int64_t* ncand_out) {
+  orc_sync_step(n, off, idx, w, K, W, C, Sig, csize, NULL, 0, nthreads, S_out, moved_out,
+                ncand_out);
 }
 
 /* One asynchronous (Gauss-Seidel) iteration: vertices in ascending id, each decision sees
@@ -421,11 +453,13 @@ static int64_t* copy64(const int64_t* a, int64_t k) {
 
 /* The Louvain method of section 3.2, passes of local-moving + aggregation.
  * mode 0: synchronous rule (the GPU's rule); mode 1: sequential asynchronous rule.
+ * substeps (mode 0): K vertex classes; an iteration is K synchronous steps, class 0 first,
+ * each seeing the moves of the classes before it (K = 1: fully synchronous).
  * a, b: initial tolerance 10^-a, decline factor 10^b (defaults 2 and 1, section 3.2).
  * top[n]: output membership (dense labels of the last level). */
 int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
             int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
-            int32_t nthreads, int32_t* top, orc_result* res) {
+            int32_t substeps, int32_t nthreads, int32_t* top, orc_result* res) {
   memset(res, 0, sizeof(*res));
   for (int64_t v = 0; v < n; v++) top[v] = (int32_t)v;
   int64_t nnz0 = n > 0 ? off0[n] : 0;
@@ -451,6 +485,9 @@ int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t*
   int64_t* off2 = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
   int32_t* idx2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz0 > 0 ? nnz0 : 1));
   uint64_t* w2 = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nnz0 > 0 ? nnz0 : 1));
+  int32_t* cls_verts = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int64_t* cls_start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(substeps + 1));
+  if (substeps < 1) substeps = 1;
 
   for (int32_t p = 0; p < max_pass && p < ORC_MAX_PASSES; p++) {
     /* every vertex starts in its own community; K of a super-vertex is its row sum */
@@ -462,16 +499,36 @@ int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t*
     res->n_pass[p] = cn;
     res->nnz_pass[p] = cnnz;
     res->passes = p + 1;
+    /* vertices of each class, ascending within a class */
+    {
+      int64_t pos = 0;
+      for (int32_t k = 0; k < substeps; k++) {
+        cls_start[k] = pos;
+        for (int64_t v = 0; v < cn; v++)
+          if (substeps == 1 || orc_vertex_class(p, substeps, v) == k) cls_verts[pos++] = (int32_t)v;
+      }
+      cls_start[substeps] = pos;
+    }
     i128 pass_gain = 0;
     int32_t iters = 0, below_tolerance = 0;
     for (int32_t it = 0; it < max_it; it++) {
       uint64_t Sw[2];
       int64_t moved = 0, ncand = 0;
-      if (mode == 0)
-        orc_sync_iteration(cn, off, idx, w, K, W, C, Sig, csize, nthreads, Sw, &moved, &ncand);
-      else
+      i128 S = 0;
+      if (mode == 0) {
+        for (int32_t k = 0; k < substeps; k++) {
+          int64_t mk = 0, nk = 0;
+          orc_sync_step(cn, off, idx, w, K, W, C, Sig, csize, cls_verts + cls_start[k],
+                        cls_start[k + 1] - cls_start[k], nthreads, Sw, &mk, &nk);
+          S += (i128)((u128)Sw[0] | ((u128)Sw[1] << 64));
+          moved += mk;
+          ncand += nk;
+        }
+      } else {
         orc_async_iteration(cn, off, idx, w, K, W, C, Sig, csize, Sw, &moved);
-      i128 S = (i128)((u128)Sw[0] | ((u128)Sw[1] << 64));
+        S = (i128)((u128)Sw[0] | ((u128)Sw[1] << 64));
+      }
+      put_i128(Sw, S);
       if (res->n_trace < ORC_MAX_TRACE) {
         int32_t t = res->n_trace++;
         res->trace_pass[t] = p;
@@ -507,6 +564,7 @@ int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t*
   res->n_communities = cn;
   uint64_t Wq = 0;
   orc_modularity(n, off0, idx0, w0, top, res->qnum, &Wq, NULL);
+  free(cls_start); free(cls_verts);
   free(w2); free(idx2); free(off2); free(map); free(csize); free(Sig); free(C);
   free(w); free(idx); free(off); free(K);
   return 0;

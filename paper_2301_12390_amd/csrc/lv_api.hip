@@ -1,0 +1,775 @@
+// C ABI of liblouvain: context and workspace management, argument checks, and the drivers of
+// the local-moving phase, the aggregation phase and whole runs (section 3.2 of Sahu,
+// arXiv 2301.12390). Declarations and the contract are in include/louvain.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/louvain.h"
+#include "lv_internal.h"
+
+typedef unsigned long long ull;
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+namespace {
+
+enum SlotId {
+  S_K, S_SIG, S_CSIZE, S_C, S_MAP, S_MOVERS, S_LIST, S_OFF64, S_STATS, S_COUNTS, S_SCANP,
+  S_HUBARR, S_TKEYS, S_TVALS, S_OCC, S_OCCCNT, S_PARTIAL, S_A, S_ASTART, S_NEWID, S_CURSOR,
+  S_OLDLABEL, S_DCOUNT, S_ABASE, S_TKEY, S_TW, S_GOFF0, S_GIDX0, S_GW0, S_GOFF1, S_GIDX1, S_GW1,
+  S_BAD, S_AGGOFF, S_COUNT_SLOTS
+};
+
+struct Slot {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+// Word offsets in the device stats slot and in the pinned host buffer.
+constexpr int ST_MISC = 256;      // device: [256, 264) scratch sums, 264 aggregation self-loops
+constexpr int PIN_COUNTS = 0;     // host: 1024 words of class counts
+constexpr int PIN_HUB = 1024;     // host: hub plan totals
+constexpr int PIN_STATS = 1032;   // host: per-step iteration stats (8 words per class step)
+constexpr int PIN_MISC = 1300;    // host: other read-backs
+constexpr int PIN_WORDS = 2048;
+constexpr int STATS_WORDS = 512;
+
+struct lv_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  uint64_t held = 0;
+  Slot slots[S_COUNT_SLOTS];
+  std::string err;
+  ull* pinned = nullptr;  // host-pinned words for small read-backs
+  hipEvent_t ev[6] = {};
+};
+
+namespace {
+
+lv_status fail(lv_ctx* ctx, lv_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+lv_status fail_hip(lv_ctx* ctx, const char* what, hipError_t e) {
+  return fail(ctx, LV_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return fail_hip(ctx, #expr, _e); \
+  } while (0)
+
+#define CHK(expr)                  \
+  do {                             \
+    lv_status _s = (expr);         \
+    if (_s != LV_OK) return _s;    \
+  } while (0)
+
+// Grow-only workspace slot; contents are not preserved when it grows.
+lv_status ws(lv_ctx* ctx, int id, size_t bytes, void** out) {
+  Slot& s = ctx->slots[id];
+  if (bytes == 0) bytes = 8;
+  if (s.bytes >= bytes) {
+    *out = s.p;
+    return LV_OK;
+  }
+  size_t want = bytes + bytes / 8;  // headroom against repeated small growth
+  want = (want + 4095) & ~(size_t)4095;
+  const uint64_t after = ctx->held - s.bytes + want;
+  if (ctx->budget && after > ctx->budget) {
+    want = (bytes + 4095) & ~(size_t)4095;
+    if (ctx->held - s.bytes + want > ctx->budget)
+      return fail(ctx, LV_EBUDGET, "workspace of " + std::to_string(ctx->held - s.bytes + want) +
+                                       " bytes exceeds the HBM budget of " +
+                                       std::to_string(ctx->budget));
+  }
+  if (s.p) {
+    hipError_t e = hipFree(s.p);
+    s.p = nullptr;
+    ctx->held -= s.bytes;
+    s.bytes = 0;
+    if (e != hipSuccess) return fail_hip(ctx, "hipFree", e);
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, LV_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  s.p = p;
+  s.bytes = want;
+  ctx->held += want;
+  *out = p;
+  return LV_OK;
+}
+
+template <typename T>
+lv_status wst(lv_ctx* ctx, int id, int64_t count, T** out) {
+  void* p = nullptr;
+  lv_status st = ws(ctx, id, (size_t)(count > 0 ? count : 1) * sizeof(T), &p);
+  *out = (T*)p;
+  return st;
+}
+
+lv_i128 to_i128(i128 v) {
+  lv_i128 r;
+  r.lo = (uint64_t)(u128)v;
+  r.hi = (int64_t)(uint64_t)((u128)v >> 64);
+  return r;
+}
+
+double q_of(i128 qnum, uint64_t W) {
+  if (W == 0) return 0.0;
+  return (double)qnum / ((double)W * (double)W);
+}
+
+// floor(W^2 / (2 * 10^(a + b*p))): S > T exactly when 2S/W^2 exceeds the pass tolerance.
+u128 tolerance_threshold(uint64_t W, int a, int b, int p) {
+  const u128 W2 = (u128)W * W;
+  const int64_t ex = (int64_t)a + (int64_t)b * p;
+  u128 div = 2;
+  for (int64_t k = 0; k < ex; k++) {
+    if (div > W2 / 10) return 0;
+    div *= 10;
+  }
+  return W2 / div;
+}
+
+constexpr int lv_max_classes() { return 32; }
+
+lv_status check_params(lv_ctx* ctx, const lv_params* p) {
+  if (!p) return fail(ctx, LV_EINVAL, "params is NULL");
+  if (p->tolerance_exp10 < 0 || p->decline_exp10 < 0)
+    return fail(ctx, LV_EINVAL, "tolerance and decline exponents must be >= 0");
+  if (p->max_iterations < 1) return fail(ctx, LV_EINVAL, "max_iterations must be >= 1");
+  if (p->max_passes < 1 || p->max_passes > LV_MAX_PASSES)
+    return fail(ctx, LV_EINVAL, "max_passes must be in 1..64");
+  if (p->substeps < 1 || p->substeps > lv_max_classes())
+    return fail(ctx, LV_EINVAL, "substeps must be in 1..32");
+  return LV_OK;
+}
+
+// Checks the graph descriptor and produces a device view with int64 offsets.
+lv_status import_graph(lv_ctx* ctx, const lv_graph* g, bool validate, hipStream_t s,
+                       lv::DevGraph* out) {
+  if (!g) return fail(ctx, LV_EINVAL, "graph is NULL");
+  if (g->n < 0 || g->nnz < 0) return fail(ctx, LV_EINVAL, "negative n or nnz");
+  if (g->n >= ((int64_t)1 << 31)) return fail(ctx, LV_EOVERFLOW, "n must be < 2^31");
+  if (!g->offsets_64 && g->nnz >= ((int64_t)1 << 31))
+    return fail(ctx, LV_EOVERFLOW, "nnz >= 2^31 needs int64 offsets");
+  if (!g->offsets) return fail(ctx, LV_EINVAL, "offsets is NULL");
+  if (g->nnz > 0 && (!g->indices || !g->weights))
+    return fail(ctx, LV_EINVAL, "indices or weights is NULL");
+  if (((uintptr_t)g->offsets & (g->offsets_64 ? 7 : 3)) || ((uintptr_t)g->indices & 3) ||
+      ((uintptr_t)g->weights & (g->weights_64 ? 7 : 3)))
+    return fail(ctx, LV_EINVAL, "misaligned graph array");
+  out->n = g->n;
+  out->nnz = g->nnz;
+  out->idx = g->indices;
+  out->w = g->weights;
+  out->w64 = g->weights_64 != 0;
+  if (g->offsets_64) {
+    out->off = (const int64_t*)g->offsets;
+  } else {
+    int64_t* o = nullptr;
+    CHK(wst(ctx, S_OFF64, g->n + 1, &o));
+    HIPCHK(lv::widen_offsets((const int32_t*)g->offsets, o, g->n + 1, s));
+    out->off = o;
+  }
+  if (validate) {
+    unsigned int* bad = nullptr;
+    CHK(wst(ctx, S_BAD, 1, &bad));
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(unsigned int), s));
+    HIPCHK(lv::validate_graph(*out, bad, s));
+    int64_t ends[2];
+    unsigned int hb = 0;
+    HIPCHK(hipMemcpyAsync(&ends[0], out->off, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&ends[1], out->off + g->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ends[0] != 0 || ends[1] != g->nnz)
+      return fail(ctx, LV_EINVAL, "offsets[0] must be 0 and offsets[n] must be nnz");
+    if (hb & 1u) return fail(ctx, LV_EINVAL, "offsets decrease");
+    if (hb & 2u) return fail(ctx, LV_EINVAL, "an index is out of range");
+    if (hb & 4u) return fail(ctx, LV_EINVAL, "a weight is zero");
+  }
+  return LV_OK;
+}
+
+// W and max K from row sums already in K (n entries).
+lv_status weight_stats(lv_ctx* ctx, const uint64_t* K, int64_t n, hipStream_t s, uint64_t* W,
+                       uint64_t* maxK) {
+  ull* st = nullptr;
+  CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
+  HIPCHK(lv::zero_words(st + ST_MISC, 2, s));
+  HIPCHK(lv::sum_max_u64(K, n, st + ST_MISC, s));
+  HIPCHK(hipMemcpyAsync(ctx->pinned + PIN_MISC, st + ST_MISC, 2 * sizeof(ull),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *W = ctx->pinned[PIN_MISC];
+  *maxK = ctx->pinned[PIN_MISC + 1];
+  return LV_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Local-moving phase on the state in m (C, Sig, csize by label).
+
+struct Phase {
+  lv::DevGraph g;
+  lv::Buckets b;
+  lv::HubPlan hp[32];  // per vertex class
+  lv::MoveBuffers m;
+  bool wide = false;
+  int classes = 1;
+  int pass = 0;
+};
+
+// Row lists by (vertex class, degree class) and the hub tables of every class; fills ph.b,
+// ph.hp and the buffers of ph.m that depend on them.
+lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
+  const int64_t n = ph.g.n;
+  const int K = ph.classes;
+  int32_t* list = nullptr;
+  ull* counts = nullptr;
+  int64_t* scanp = nullptr;
+  int64_t* hubarr = nullptr;
+  CHK(wst(ctx, S_LIST, n, &list));
+  CHK(wst(ctx, S_COUNTS, 1024, &counts));
+  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &scanp));
+  HIPCHK(lv::bucket_rows(ph.g.off, nullptr, n, K, ph.pass, list, counts,
+                         ctx->pinned + PIN_COUNTS, ph.b, s));
+  int64_t nh_total = 0;
+  for (int k = 0; k < K; k++) nh_total += ph.b.count[8 * k + 7];
+  CHK(wst(ctx, S_HUBARR, 6 * (nh_total + K), &hubarr));
+  lv::HubPlan big;  // largest tables of any class: the buffers are shared by the class steps
+  int64_t off = 0;
+  for (int k = 0; k < K; k++) {
+    const int64_t nh = ph.b.count[8 * k + 7];
+    HIPCHK(lv::plan_hubs(ph.g.off, nullptr, list + ph.b.lstart[8 * k + 7], nh, hubarr + off,
+                         scanp, ctx->pinned + PIN_HUB, ph.hp[k], s));
+    off += 6 * (nh + 1);
+    big.nh = std::max(big.nh, nh);
+    big.slots = std::max(big.slots, ph.hp[k].slots);
+    big.scan_blocks = std::max(big.scan_blocks, ph.hp[k].scan_blocks);
+  }
+  ph.m.list = list;
+  if (big.nh > 0) {
+    CHK(wst(ctx, S_TKEYS, big.slots, &ph.m.tkeys));
+    ull* tv = nullptr;
+    CHK(wst(ctx, S_TVALS, big.slots, &tv));
+    ph.m.tvals = tv;
+    CHK(wst(ctx, S_OCC, big.slots, &ph.m.occ));
+    CHK(wst(ctx, S_OCCCNT, big.nh, &ph.m.occ_count));
+    CHK(wst(ctx, S_PARTIAL, 5 * big.scan_blocks, &ph.m.partial));
+    HIPCHK(lv::hub_reset_tables(big, ph.m, ph.wide, s));
+  }
+  int2* movers = nullptr;
+  CHK(wst(ctx, S_MOVERS, n, &movers));
+  ph.m.movers = movers;
+  ull* st = nullptr;
+  CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
+  ph.m.stats = st;
+  return LV_OK;
+}
+
+struct PhaseOut {
+  int32_t iterations = 0;
+  bool hit_cap = false;
+  i128 gain_sum = 0;
+  int64_t moved = 0;
+  i128 last_gain = 0;
+  int64_t last_moved = 0;
+  int64_t last_candidates = 0;
+};
+
+// Local-moving iterations; each is `classes` synchronous class steps.
+lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, hipStream_t s,
+                    lv_result* res, PhaseOut* out) {
+  const bool trace = (flags & LV_TRACE) != 0;
+  const int K = ph.classes;
+  int64_t lds_v = 0, lds_a = 0, hub_v = 0, hub_a = 0;
+  for (int k = 0; k < K; k++) {
+    for (int j = 0; j < 7; j++) {
+      lds_v += ph.b.count[8 * k + j];
+      lds_a += ph.b.arcs[8 * k + j];
+    }
+    hub_v += ph.b.count[8 * k + 7];
+    hub_a += ph.b.arcs[8 * k + 7];
+  }
+  ull* stats0 = ph.m.stats;
+  *out = PhaseOut();
+  out->hit_cap = true;
+  for (int it = 0; it < max_it; it++) {
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(lv::zero_words(stats0, 8 * K, s));
+    float move_ms = 0, hub_ms = 0, upd_ms = 0;
+    for (int k = 0; k < K; k++) {
+      lv::MoveBuffers m = ph.m;
+      m.stats = stats0 + 8 * k;
+      if (trace) HIPCHK(hipEventRecord(ctx->ev[0], s));
+      HIPCHK(lv::move_lds(ph.g, ph.b, k, m, ph.wide, s));
+      if (trace) HIPCHK(hipEventRecord(ctx->ev[1], s));
+      HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s));
+      if (trace) HIPCHK(hipEventRecord(ctx->ev[2], s));
+      HIPCHK(lv::apply_moves(m, s));
+      if (trace) {
+        HIPCHK(hipEventRecord(ctx->ev[3], s));
+        HIPCHK(hipEventSynchronize(ctx->ev[3]));
+        float a = 0, b = 0, c = 0;
+        HIPCHK(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+        HIPCHK(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+        HIPCHK(hipEventElapsedTime(&c, ctx->ev[2], ctx->ev[3]));
+        move_ms += a;
+        hub_ms += b;
+        upd_ms += c;
+      }
+    }
+    ull* h = ctx->pinned + PIN_STATS;
+    HIPCHK(hipMemcpyAsync(h, stats0, 8 * K * sizeof(ull), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    i128 S = 0;
+    int64_t moved = 0, cand = 0, lds_cand = 0, lds_moved = 0;
+    for (int k = 0; k < K; k++) {
+      const ull* x = h + 8 * k;
+      S += (i128)(((u128)x[1] << 64) | x[0]);
+      moved += (int64_t)x[2];
+      cand += (int64_t)x[3];
+      lds_cand += (int64_t)x[4];
+      lds_moved += (int64_t)x[5];
+    }
+    out->iterations++;
+    out->gain_sum += S;
+    out->moved += moved;
+    out->last_gain = S;
+    out->last_moved = moved;
+    out->last_candidates = cand;
+    if (res && res->n_trace < LV_MAX_TRACE) {
+      lv_iter_trace& r = res->trace[res->n_trace++];
+      memset(&r, 0, sizeof(r));
+      r.pass = ph.pass;
+      r.iteration = it;
+      r.wide = ph.wide ? 1 : 0;
+      r.substeps = K;
+      r.gain_sum = to_i128(S);
+      r.moved = moved;
+      r.candidates = cand;
+      r.lds_candidates = lds_cand;
+      r.lds_moved = lds_moved;
+      r.lds_vertices = lds_v;
+      r.lds_arcs = lds_a;
+      r.hub_vertices = hub_v;
+      r.hub_arcs = hub_a;
+      if (trace) {
+        r.move_ms = move_ms;
+        r.hub_ms = hub_ms;
+        r.update_ms = upd_ms;
+        r.iter_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0)
+                        .count();
+      }
+    }
+    if (!((u128)S > T)) {  // the iteration's modularity change is within the tolerance
+      out->hit_cap = false;
+      break;
+    }
+  }
+  return LV_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Aggregation of graph g under labels C (csize by label; Sig by label or NULL).
+// Outputs: map[n], off_out[n+1] (int64), idx_out, w_out, Kp[n'] (if Sig), n', nnz', and the
+// weight of the super-graph's self-loops.
+lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const int32_t* csize,
+                    const uint64_t* Sig, int32_t* map, int64_t* off_out, int32_t* idx_out,
+                    uint64_t* w_out, uint64_t* Kp, int64_t* n_out, int64_t* nnz_out,
+                    uint64_t* self_out, hipStream_t s) {
+  const int64_t n = g.n;
+  lv::AggBuffers a;
+  CHK(wst(ctx, S_A, n + 1, &a.A));
+  CHK(wst(ctx, S_ASTART, n + 1, &a.astart));
+  CHK(wst(ctx, S_NEWID, n + 1, &a.newid));
+  CHK(wst(ctx, S_CURSOR, n + 1, &a.cursor));
+  CHK(wst(ctx, S_OLDLABEL, n, &a.oldlabel));
+  CHK(wst(ctx, S_DCOUNT, n + 1, &a.dcount));
+  CHK(wst(ctx, S_ABASE, n, &a.abase));
+  CHK(wst(ctx, S_TKEY, g.nnz, &a.tkey));
+  CHK(wst(ctx, S_TW, g.nnz, &a.tw));
+  CHK(wst(ctx, S_LIST, n, &a.list));
+  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &a.partial));
+  CHK(wst(ctx, S_COUNTS, 1024, &a.counts));
+  CHK(wst(ctx, S_STATS, STATS_WORDS, &a.stats));
+  HIPCHK(lv::scan_flags_pos(csize, n, a.newid, a.partial, s));
+  HIPCHK(lv::label_tables(n, csize, a.newid, Sig, a.oldlabel, Kp, s));
+  HIPCHK(lv::fill_i64(a.A, 0, n + 1, s));
+  HIPCHK(lv::label_arcs(g.off, C, n, a.A, s));
+  HIPCHK(lv::scan_i64(a.A, n, a.astart, a.partial, s));
+  HIPCHK(lv::copy_i64(a.cursor, a.astart, n, s));
+  HIPCHK(lv::vertex_map(g.off, C, n, a.newid, a.cursor, map, a.abase, s));
+  HIPCHK(lv::scatter_arcs(g, map, a.abase, a.tkey, a.tw, s));
+  HIPCHK(lv::fill_i64(a.dcount, 0, n + 1, s));
+  a.stats += ST_MISC + 8;
+  HIPCHK(lv::zero_words(a.stats, 1, s));
+  lv::Buckets b;
+  HIPCHK(lv::bucket_rows(nullptr, a.A, n, 1, 0, a.list, a.counts, ctx->pinned + PIN_COUNTS, b,
+                         s));
+  HIPCHK(lv::merge_lds(b, a, s));
+  const int64_t nh = b.count[7];
+  if (nh > 0) {
+    lv::HubPlan hp;
+    CHK(wst(ctx, S_HUBARR, 6 * (nh + 1), &a.hub_arrays));
+    HIPCHK(lv::plan_hubs(nullptr, a.A, a.list + b.lstart[7], nh, a.hub_arrays, a.partial,
+                         ctx->pinned + PIN_HUB, hp, s));
+    CHK(wst(ctx, S_TKEYS, hp.slots, &a.tkeys));
+    ull* tv = nullptr;
+    CHK(wst(ctx, S_TVALS, hp.slots, &tv));
+    a.tvals = tv;
+    CHK(wst(ctx, S_OCC, hp.slots, &a.occ));
+    CHK(wst(ctx, S_OCCCNT, nh, &a.occ_count));
+    HIPCHK(lv::merge_hubs(b, hp, a, s));
+  }
+  ull* hm = ctx->pinned + PIN_MISC;
+  HIPCHK(hipMemcpyAsync(hm, a.newid + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t np = (int64_t)hm[0];
+  HIPCHK(lv::scan_i64(a.dcount, np, off_out, a.partial, s));
+  HIPCHK(hipMemcpyAsync(hm, off_out + np, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hm + 1, a.stats, sizeof(ull), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t nnzp = (int64_t)hm[0];
+  const uint64_t self = hm[1];
+  HIPCHK(lv::compact_rows(off_out, np, nnzp, a.oldlabel, a.astart, a.tkey, a.tw, idx_out, w_out,
+                          s));
+  *n_out = np;
+  *nnz_out = nnzp;
+  if (self_out) *self_out = self;
+  return LV_OK;
+}
+
+// Qnum of singletons on g: W * (self-loop weight) - sum K^2.
+lv_status singleton_qnum(lv_ctx* ctx, const lv::DevGraph& g, const uint64_t* K, uint64_t W,
+                         hipStream_t s, i128* q) {
+  ull* st = nullptr;
+  CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
+  ull* d = st + ST_MISC;
+  ull* h = ctx->pinned + PIN_MISC;
+  HIPCHK(lv::zero_words(d, 3, s));
+  HIPCHK(lv::intra_weight(g, nullptr, d, s));
+  HIPCHK(lv::sum_squares_u64(K, g.n, d + 1, s));
+  HIPCHK(hipMemcpyAsync(h, d, 3 * sizeof(ull), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const u128 sq = ((u128)h[2] << 64) | h[1];
+  *q = (i128)((u128)W * h[0]) - (i128)sq;
+  return LV_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+
+extern "C" {
+
+lv_status louvain_ctx_create(int device, uint64_t hbm_budget_bytes, lv_ctx** out) {
+  if (!out) return LV_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return LV_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return LV_EHIP;
+  lv_ctx* ctx = new lv_ctx();
+  ctx->device = device;
+  ctx->budget = hbm_budget_bytes;
+  if (hipHostMalloc((void**)&ctx->pinned, PIN_WORDS * sizeof(ull), hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return LV_EHIP;
+  }
+  memset(ctx->pinned, 0, PIN_WORDS * sizeof(ull));
+  for (int i = 0; i < 6; i++) {
+    if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
+      louvain_ctx_destroy(ctx);
+      return LV_EHIP;
+    }
+  }
+  *out = ctx;
+  return LV_OK;
+}
+
+void louvain_ctx_destroy(lv_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (int i = 0; i < S_COUNT_SLOTS; i++)
+    if (ctx->slots[i].p) (void)hipFree(ctx->slots[i].p);
+  for (int i = 0; i < 6; i++)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+const char* louvain_last_error(const lv_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+uint64_t louvain_workspace_bytes(const lv_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, lv_i128* q_num,
+                             uint64_t* W_out, double* q_out, void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  lv::DevGraph dg;
+  CHK(import_graph(ctx, g, false, s, &dg));
+  if (dg.n > 0 && !C) return fail(ctx, LV_EINVAL, "C is NULL");
+  uint64_t* K = nullptr;
+  uint64_t* Sig = nullptr;
+  CHK(wst(ctx, S_K, dg.n, &K));
+  CHK(wst(ctx, S_SIG, dg.n, &Sig));
+  HIPCHK(lv::fill_u64(K, 0, dg.n, s));
+  HIPCHK(lv::fill_u64(Sig, 0, dg.n, s));
+  HIPCHK(lv::row_sums(dg, K, s));
+  HIPCHK(lv::sigma_by_label(K, C, dg.n, Sig, s));
+  ull* st = nullptr;
+  CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
+  ull* d = st + ST_MISC;
+  ull* h = ctx->pinned + PIN_MISC;
+  HIPCHK(lv::zero_words(d, 5, s));
+  HIPCHK(lv::sum_max_u64(K, dg.n, d, s));
+  HIPCHK(lv::intra_weight(dg, C, d + 2, s));
+  HIPCHK(lv::sum_squares_u64(Sig, dg.n, d + 3, s));
+  HIPCHK(hipMemcpyAsync(h, d, 5 * sizeof(ull), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const uint64_t W = h[0];
+  if (W > ((uint64_t)1 << 62)) return fail(ctx, LV_EOVERFLOW, "total weight exceeds 2^62");
+  const u128 sq = ((u128)h[4] << 64) | h[3];
+  const i128 qn = (i128)((u128)W * h[2]) - (i128)sq;
+  if (q_num) *q_num = to_i128(qn);
+  if (W_out) *W_out = W;
+  if (q_out) *q_out = q_of(qn, W);
+  return LV_OK;
+}
+
+lv_status louvain_move(lv_ctx* ctx, const lv_graph* g, const uint64_t* Kin, uint64_t Win,
+                       int32_t pass_index, const lv_params* p, int32_t* C, uint64_t* Sigma,
+                       int32_t* csize, lv_move_stats* stats, void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  CHK(check_params(ctx, p));
+  if (pass_index < 0) return fail(ctx, LV_EINVAL, "pass_index must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  Phase ph;
+  CHK(import_graph(ctx, g, (p->flags & LV_VALIDATE) != 0, s, &ph.g));
+  if (ph.g.n > 0 && (!C || !Sigma || !csize))
+    return fail(ctx, LV_EINVAL, "C, Sigma or csize is NULL");
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (ph.g.n == 0) return LV_OK;
+  const uint64_t* K = Kin;
+  if (!K) {
+    uint64_t* Kw = nullptr;
+    CHK(wst(ctx, S_K, ph.g.n, &Kw));
+    HIPCHK(lv::fill_u64(Kw, 0, ph.g.n, s));
+    HIPCHK(lv::row_sums(ph.g, Kw, s));
+    K = Kw;
+  }
+  uint64_t W = 0, maxK = 0;
+  CHK(weight_stats(ctx, K, ph.g.n, s, &W, &maxK));
+  if (Win) W = Win;
+  if (W > ((uint64_t)1 << 62)) return fail(ctx, LV_EOVERFLOW, "total weight exceeds 2^62");
+  if (W == 0) return LV_OK;
+  ph.m.K = K;
+  ph.m.C = C;
+  ph.m.Sig = Sigma;
+  ph.m.csize = csize;
+  ph.m.W = W;
+  ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)W * maxK < ((u128)1 << 63));
+  ph.classes = p->substeps;
+  ph.pass = pass_index;
+  CHK(plan_phase(ctx, ph, s));
+  PhaseOut po;
+  CHK(run_phase(ctx, ph, tolerance_threshold(W, p->tolerance_exp10, p->decline_exp10, pass_index),
+                p->max_iterations, p->flags, s, nullptr, &po));
+  if (stats) {
+    stats->iterations = po.iterations;
+    stats->hit_cap = po.hit_cap ? 1 : 0;
+    stats->moved = po.moved;
+    stats->gain_sum = to_i128(po.gain_sum);
+    stats->last_gain = to_i128(po.last_gain);
+    stats->last_moved = po.last_moved;
+    stats->last_candidates = po.last_candidates;
+  }
+  return LV_OK;
+}
+
+lv_status louvain_aggregate(lv_ctx* ctx, const lv_graph* g, const int32_t* C, int32_t* map,
+                            void* offsets_out, int32_t offsets_64_out, int32_t* indices_out,
+                            uint64_t* weights_out, int64_t* n_out, int64_t* nnz_out,
+                            void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  lv::DevGraph dg;
+  CHK(import_graph(ctx, g, false, s, &dg));
+  if (!n_out || !nnz_out) return fail(ctx, LV_EINVAL, "n_out or nnz_out is NULL");
+  if (!offsets_out || (dg.n > 0 && (!C || !map)) || (dg.nnz > 0 && (!indices_out || !weights_out)))
+    return fail(ctx, LV_EINVAL, "an output or C is NULL");
+  int32_t* csize = nullptr;
+  CHK(wst(ctx, S_CSIZE, dg.n, &csize));
+  HIPCHK(lv::fill_i32(csize, 0, dg.n, s));
+  HIPCHK(lv::count_labels(C, dg.n, csize, s));
+  int64_t* off64 = nullptr;
+  if (offsets_64_out) {
+    off64 = (int64_t*)offsets_out;
+  } else {
+    CHK(wst(ctx, S_AGGOFF, dg.n + 1, &off64));
+  }
+  int64_t np = 0, nnzp = 0;
+  CHK(aggregate(ctx, dg, C, csize, nullptr, map, off64, indices_out, weights_out, nullptr, &np,
+                &nnzp, nullptr, s));
+  if (!offsets_64_out) HIPCHK(lv::narrow_offsets(off64, (int32_t*)offsets_out, np + 1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *n_out = np;
+  *nnz_out = nnzp;
+  return LV_OK;
+}
+
+lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_t* membership,
+                      lv_result* res, void* stream) {
+  if (!ctx) return LV_EINVAL;
+  const auto t_start = std::chrono::steady_clock::now();
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  CHK(check_params(ctx, p));
+  if (!res) return fail(ctx, LV_EINVAL, "res is NULL");
+  memset(res, 0, sizeof(*res));
+  hipStream_t s = (hipStream_t)stream;
+  lv::DevGraph g0;
+  CHK(import_graph(ctx, g, (p->flags & LV_VALIDATE) != 0, s, &g0));
+  const int64_t n0 = g0.n;
+  if (n0 > 0 && !membership) return fail(ctx, LV_EINVAL, "membership is NULL");
+  res->n_communities = n0;
+  if (n0 == 0) return LV_OK;
+  const bool trace = (p->flags & LV_TRACE) != 0;
+
+  uint64_t* K = nullptr;
+  int32_t* C = nullptr;
+  uint64_t* Sig = nullptr;
+  int32_t* csize = nullptr;
+  int32_t* map = nullptr;
+  CHK(wst(ctx, S_K, n0, &K));
+  CHK(wst(ctx, S_C, n0, &C));
+  CHK(wst(ctx, S_SIG, n0, &Sig));
+  CHK(wst(ctx, S_CSIZE, n0, &csize));
+  CHK(wst(ctx, S_MAP, n0, &map));
+  HIPCHK(lv::fill_u64(K, 0, n0, s));
+  HIPCHK(lv::row_sums(g0, K, s));
+  uint64_t W = 0, maxK = 0;
+  CHK(weight_stats(ctx, K, n0, s, &W, &maxK));
+  res->W = W;
+  HIPCHK(lv::iota_i32(membership, n0, s));
+  if (W > ((uint64_t)1 << 62)) return fail(ctx, LV_EOVERFLOW, "total weight exceeds 2^62");
+  if (W == 0) {
+    HIPCHK(hipStreamSynchronize(s));
+    res->total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                             t_start).count();
+    return LV_OK;
+  }
+
+  lv::DevGraph cur = g0;
+  int64_t n_comm = n0;
+  i128 qnum = 0;
+  bool have_q = false;
+  int which = 0;  // next super-graph buffer set
+  for (int pass = 0; pass < p->max_passes; pass++) {
+    HIPCHK(lv::init_state(cur.n, K, C, Sig, csize, s));
+    Phase ph;
+    ph.g = cur;
+    ph.m.K = K;
+    ph.m.C = C;
+    ph.m.Sig = Sig;
+    ph.m.csize = csize;
+    ph.m.W = W;
+    ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)W * maxK < ((u128)1 << 63));
+    ph.classes = p->substeps;
+    ph.pass = pass;
+    CHK(plan_phase(ctx, ph, s));
+    PhaseOut po;
+    CHK(run_phase(ctx, ph, tolerance_threshold(W, p->tolerance_exp10, p->decline_exp10, pass),
+                  p->max_iterations, p->flags, s, res, &po));
+    res->passes = pass + 1;
+    res->iterations[pass] = po.iterations;
+    res->iterations_total += po.iterations;
+    res->n_pass[pass] = cur.n;
+    res->nnz_pass[pass] = cur.nnz;
+    if (po.hit_cap) res->cap_hits++;
+    if (po.gain_sum == 0) {
+      // no vertex moved: the partition is that of the previous level
+      if (!have_q) {
+        CHK(singleton_qnum(ctx, cur, K, W, s, &qnum));
+        have_q = true;
+      }
+      res->qnum_pass[pass] = to_i128(qnum);
+      break;
+    }
+    // aggregation into the other buffer set
+    int64_t* noff = nullptr;
+    int32_t* nidx = nullptr;
+    ull* nw = nullptr;
+    CHK(wst(ctx, which ? S_GOFF1 : S_GOFF0, cur.n + 1, &noff));
+    CHK(wst(ctx, which ? S_GIDX1 : S_GIDX0, cur.nnz, &nidx));
+    CHK(wst(ctx, which ? S_GW1 : S_GW0, cur.nnz, &nw));
+    if (trace) HIPCHK(hipEventRecord(ctx->ev[4], s));
+    int64_t np = 0, nnzp = 0;
+    uint64_t self = 0;
+    CHK(aggregate(ctx, cur, C, csize, Sig, map, noff, nidx, (uint64_t*)nw, K, &np, &nnzp, &self,
+                  s));
+    HIPCHK(lv::compose_membership(membership, n0, map, s));
+    if (trace) {
+      HIPCHK(hipEventRecord(ctx->ev[5], s));
+      HIPCHK(hipEventSynchronize(ctx->ev[5]));
+      HIPCHK(hipEventElapsedTime(&res->aggregate_ms[pass], ctx->ev[4], ctx->ev[5]));
+    }
+    // W^2 Q of this pass = that of singletons on the super-vertex graph
+    ull* st = nullptr;
+    CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
+    ull* d = st + ST_MISC;
+    ull* h = ctx->pinned + PIN_MISC;
+    HIPCHK(lv::zero_words(d, 4, s));
+    HIPCHK(lv::sum_squares_u64(K, np, d, s));
+    HIPCHK(lv::sum_max_u64(K, np, d + 2, s));
+    HIPCHK(hipMemcpyAsync(h, d, 4 * sizeof(ull), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const u128 sq = ((u128)h[1] << 64) | h[0];
+    qnum = (i128)((u128)W * self) - (i128)sq;
+    have_q = true;
+    maxK = h[3];
+    res->qnum_pass[pass] = to_i128(qnum);
+    const bool shrunk = np < cur.n;
+    lv::DevGraph nxt;
+    nxt.n = np;
+    nxt.nnz = nnzp;
+    nxt.off = noff;
+    nxt.idx = nidx;
+    nxt.w = nw;
+    nxt.w64 = true;
+    cur = nxt;
+    n_comm = np;
+    which ^= 1;
+    if (!shrunk) break;
+  }
+  res->n_communities = n_comm;
+  res->q_num = to_i128(qnum);
+  res->q = q_of(qnum, W);
+  HIPCHK(hipStreamSynchronize(s));
+  res->total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                           t_start).count();
+  return LV_OK;
+}
+
+}  // extern "C"

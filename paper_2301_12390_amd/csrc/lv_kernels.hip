@@ -1,0 +1,1412 @@
+// gfx950 kernels of the Louvain library: pass set-up, degree classes, the synchronous
+// local-moving iteration, community updates, modularity pieces and aggregation.
+//
+// Method: section 3.2 of Sahu, arXiv 2301.12390 (local-moving phase, aggregation phase,
+// synchronous vs asynchronous variants, per-worker hashtables of community -> weight).
+#include <hip/hip_runtime.h>
+
+#include "lv_device.h"
+#include "lv_internal.h"
+
+namespace lv {
+
+static inline unsigned grid_for(int64_t n, int64_t per_block = kBlock, int64_t cap = 16384) {
+  int64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+#define LV_LAUNCH(kernel, grid, block, shm, stream, ...)                          \
+  do {                                                                            \
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shm, stream, __VA_ARGS__); \
+  } while (0)
+
+// =============================================================================================
+// Elementwise
+
+__global__ void k_fill_u64(uint64_t* a, uint64_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+__global__ void k_fill_i32(int32_t* a, int32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+__global__ void k_fill_i64(int64_t* a, int64_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+__global__ void k_iota_i32(int32_t* a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = (int32_t)i;
+}
+__global__ void k_copy_i64(int64_t* d, const int64_t* s, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+__global__ void k_widen_offsets(const int32_t* in, int64_t* out, int64_t m) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int64_t)in[i];
+}
+__global__ void k_narrow_offsets(const int64_t* in, int32_t* out, int64_t m) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int32_t)in[i];
+}
+__global__ void k_widen_weights(const uint32_t* in, uint64_t* out, int64_t m) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (uint64_t)in[i];
+}
+
+hipError_t fill_u64(uint64_t* a, uint64_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_fill_u64, grid_for(n), kBlock, 0, s, a, v, n);
+  return hipGetLastError();
+}
+hipError_t fill_i32(int32_t* a, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_fill_i32, grid_for(n), kBlock, 0, s, a, v, n);
+  return hipGetLastError();
+}
+hipError_t fill_i64(int64_t* a, int64_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_fill_i64, grid_for(n), kBlock, 0, s, a, v, n);
+  return hipGetLastError();
+}
+hipError_t iota_i32(int32_t* a, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_iota_i32, grid_for(n), kBlock, 0, s, a, n);
+  return hipGetLastError();
+}
+hipError_t copy_i64(int64_t* d, const int64_t* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_copy_i64, grid_for(n), kBlock, 0, s, d, src, n);
+  return hipGetLastError();
+}
+hipError_t widen_offsets(const int32_t* in, int64_t* out, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  LV_LAUNCH(k_widen_offsets, grid_for(m), kBlock, 0, s, in, out, m);
+  return hipGetLastError();
+}
+hipError_t narrow_offsets(const int64_t* in, int32_t* out, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  LV_LAUNCH(k_narrow_offsets, grid_for(m), kBlock, 0, s, in, out, m);
+  return hipGetLastError();
+}
+hipError_t widen_weights(const uint32_t* in, uint64_t* out, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  LV_LAUNCH(k_widen_weights, grid_for(m), kBlock, 0, s, in, out, m);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_words(ull* a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0;
+}
+hipError_t zero_words(ull* a, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_zero_words, grid_for(n), kBlock, 0, s, a, n);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Reductions over vertex arrays
+
+__global__ __launch_bounds__(kBlock) void k_sum_max(const uint64_t* a, int64_t n, ull* out) {
+  __shared__ ull red[kBlock / 64];
+  ull sum = 0, mx = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    ull v = a[i];
+    sum += v;
+    mx = v > mx ? v : mx;
+  }
+  ull bs = block_sum_u64(sum, red);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    ull o = __shfl_xor(mx, m, 64);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(&out[1], mx);
+  if (threadIdx.x == 0 && bs) atomicAdd(&out[0], bs);
+}
+hipError_t sum_max_u64(const uint64_t* a, int64_t n, ull* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_sum_max, grid_for(n, kBlock, 4096), kBlock, 0, s, a, n, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_squares(const uint64_t* a, int64_t n, ull* out) {
+  __shared__ u128 red[kBlock / 64];
+  u128 sum = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    u128 v = a[i];
+    sum += v * v;
+  }
+  u128 bs = block_sum_u128(sum, red);
+  if (threadIdx.x == 0 && bs) atomic_add_u128(out, bs);
+}
+hipError_t sum_squares_u64(const uint64_t* a, int64_t n, ull* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_sum_squares, grid_for(n, kBlock, 4096), kBlock, 0, s, a, n, out);
+  return hipGetLastError();
+}
+
+template <typename WT>
+__global__ void k_validate(const int64_t* off, int64_t n, int64_t nnz, const int32_t* idx,
+                           const WT* w, unsigned int* bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (off[i + 1] < off[i]) atomicOr(bad, 1u);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t j = idx[e];
+    if (j < 0 || (int64_t)j >= n) atomicOr(bad, 2u);
+    if (w[e] == 0) atomicOr(bad, 4u);
+  }
+}
+hipError_t validate_graph(const DevGraph& g, unsigned int* bad, hipStream_t s) {
+  int64_t m = g.n > g.nnz ? g.n : g.nnz;
+  if (m <= 0) return hipSuccess;
+  if (g.w64)
+    LV_LAUNCH(k_validate<uint64_t>, grid_for(m), kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
+              (const uint64_t*)g.w, bad);
+  else
+    LV_LAUNCH(k_validate<uint32_t>, grid_for(m), kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
+              (const uint32_t*)g.w, bad);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Exclusive scan (reduce, scan the block partials, rescan with offsets). Each block covers
+// kScanTile consecutive elements, kScanItems per thread.
+
+constexpr int kScanItems = 8;
+constexpr int64_t kScanTile = (int64_t)kBlock * kScanItems;
+
+int64_t scan_partial_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+struct ReadI64 {
+  const int64_t* a;
+  __device__ int64_t operator()(int64_t i) const { return a[i]; }
+};
+struct ReadPos {
+  const int32_t* a;
+  __device__ int64_t operator()(int64_t i) const { return a[i] > 0 ? 1 : 0; }
+};
+
+template <typename F>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(F f, int64_t n, int64_t* partial) {
+  __shared__ ull red[kBlock / 64];
+  const int64_t base = blockIdx.x * kScanTile;
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; k++) {
+    int64_t i = base + k * kBlock + threadIdx.x;
+    if (i < n) s += f(i);
+  }
+  ull t = block_sum_u64((ull)s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = (int64_t)t;
+}
+
+// Inclusive scan of one value per thread across the block; returns the exclusive prefix and
+// the block total.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t x, int64_t* total, int64_t* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  int64_t wbase = 0, tot = 0;
+  for (int i = 0; i < kBlock / 64; i++) {
+    if (i < wave) wbase += sh[i];
+    tot += sh[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + inc - x;
+}
+
+// Single block: exclusive scan of partial[0..nb) in place, partial[nb] = total.
+__global__ __launch_bounds__(kBlock) void k_scan_partials(int64_t* partial, int64_t nb) {
+  __shared__ int64_t sh[kBlock / 64];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kBlock) {
+    int64_t i = base + threadIdx.x;
+    int64_t x = i < nb ? partial[i] : 0;
+    int64_t tot;
+    int64_t ex = block_exclusive_scan(x, &tot, sh);
+    if (i < nb) partial[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) partial[nb] = carry;
+}
+
+template <typename F>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(F f, int64_t n, const int64_t* partial,
+                                                       int64_t* out) {
+  __shared__ int64_t sh[kBlock / 64];
+  const int64_t base = blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; k++) {
+    int64_t i = base + k;
+    v[k] = i < n ? f(i) : 0;
+    s += v[k];
+  }
+  int64_t tot;
+  int64_t ex = block_exclusive_scan(s, &tot, sh) + partial[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; k++) {
+    int64_t i = base + k;
+    if (i < n) out[i] = ex;
+    ex += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = partial[gridDim.x];
+}
+
+template <typename F>
+static hipError_t scan_impl(F f, int64_t n, int64_t* out, int64_t* partial, hipStream_t s) {
+  if (n <= 0) {
+    LV_LAUNCH(k_fill_i64, 1, 1, 0, s, out, (int64_t)0, (int64_t)1);
+    return hipGetLastError();
+  }
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  LV_LAUNCH(k_scan_reduce<F>, (unsigned)nb, kBlock, 0, s, f, n, partial);
+  LV_LAUNCH(k_scan_partials, 1, kBlock, 0, s, partial, nb);
+  LV_LAUNCH(k_scan_apply<F>, (unsigned)nb, kBlock, 0, s, f, n, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t scan_i64(const int64_t* x, int64_t n, int64_t* out, int64_t* partial, hipStream_t s) {
+  return scan_impl(ReadI64{x}, n, out, partial, s);
+}
+hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* partial,
+                          hipStream_t s) {
+  return scan_impl(ReadPos{x}, n, out, partial, s);
+}
+
+// =============================================================================================
+// Arc-segment kernels: thread t covers arcs [t*kSeg, (t+1)*kSeg), finds the row of its first
+// arc by binary search over the offsets and walks forward. Work is balanced by arcs, so hub
+// rows do not serialise on one thread.
+
+constexpr int64_t kSeg = 16;
+
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t n, int64_t nnz,
+                                                    const WT* w, uint64_t* K) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t e0 = t * kSeg;
+  if (e0 >= nnz) return;
+  const int64_t e1 = e0 + kSeg < nnz ? e0 + kSeg : nnz;
+  int64_t r = row_of_arc(off, n, e0);
+  int64_t rend = off[r + 1];
+  ull acc = 0;
+  for (int64_t e = e0; e < e1; e++) {
+    while (e >= rend) {
+      if (acc) atomicAdd((ull*)&K[r], acc);
+      acc = 0;
+      r++;
+      rend = off[r + 1];
+    }
+    acc += (ull)w[e];
+  }
+  if (acc) atomicAdd((ull*)&K[r], acc);
+}
+
+hipError_t row_sums(const DevGraph& g, uint64_t* K, hipStream_t s) {
+  if (g.nnz <= 0) return hipSuccess;
+  const int64_t threads = (g.nnz + kSeg - 1) / kSeg;
+  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
+  if (g.w64)
+    LV_LAUNCH(k_row_sums<uint64_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, (const uint64_t*)g.w,
+              K);
+  else
+    LV_LAUNCH(k_row_sums<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, (const uint32_t*)g.w,
+              K);
+  return hipGetLastError();
+}
+
+// Weight of the arcs whose endpoints share a label (C == nullptr: self-loops).
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_intra_weight(const int64_t* off, int64_t n,
+                                                        int64_t nnz, const int32_t* idx,
+                                                        const WT* w, const int32_t* C,
+                                                        ull* out) {
+  __shared__ ull red[kBlock / 64];
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t e0 = t * kSeg;
+  ull acc = 0;
+  if (e0 < nnz) {
+    const int64_t e1 = e0 + kSeg < nnz ? e0 + kSeg : nnz;
+    int64_t r = row_of_arc(off, n, e0);
+    int64_t rend = off[r + 1];
+    int32_t cr = C ? C[r] : (int32_t)r;
+    for (int64_t e = e0; e < e1; e++) {
+      while (e >= rend) {
+        r++;
+        rend = off[r + 1];
+        cr = C ? C[r] : (int32_t)r;
+      }
+      const int32_t j = idx[e];
+      const int32_t cj = C ? C[j] : j;
+      if (cj == cr) acc += (ull)w[e];
+    }
+  }
+  ull b = block_sum_u64(acc, red);
+  if (threadIdx.x == 0 && b) atomicAdd(out, b);
+}
+
+hipError_t intra_weight(const DevGraph& g, const int32_t* C, ull* out, hipStream_t s) {
+  if (g.nnz <= 0) return hipSuccess;
+  const int64_t threads = (g.nnz + kSeg - 1) / kSeg;
+  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
+  if (g.w64)
+    LV_LAUNCH(k_intra_weight<uint64_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
+              (const uint64_t*)g.w, C, out);
+  else
+    LV_LAUNCH(k_intra_weight<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
+              (const uint32_t*)g.w, C, out);
+  return hipGetLastError();
+}
+
+__global__ void k_sigma_by_label(const uint64_t* K, const int32_t* C, int64_t n, uint64_t* Sig) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (K[i]) atomicAdd((ull*)&Sig[C[i]], (ull)K[i]);
+}
+hipError_t sigma_by_label(const uint64_t* K, const int32_t* C, int64_t n, uint64_t* Sig,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_sigma_by_label, grid_for(n), kBlock, 0, s, K, C, n, Sig);
+  return hipGetLastError();
+}
+
+__global__ void k_count_labels(const int32_t* C, int64_t n, int32_t* csize) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&csize[C[i]], 1);
+}
+hipError_t count_labels(const int32_t* C, int64_t n, int32_t* csize, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_count_labels, grid_for(n), kBlock, 0, s, C, n, csize);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Pass set-up: every vertex its own community (section 3.2).
+
+__global__ void k_init_state(int64_t n, const uint64_t* K, int32_t* C, uint64_t* Sig,
+                             int32_t* csize) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    C[i] = (int32_t)i;
+    Sig[i] = K[i];
+    csize[i] = 1;
+  }
+}
+hipError_t init_state(int64_t n, const uint64_t* K, int32_t* C, uint64_t* Sig, int32_t* csize,
+                      hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_init_state, grid_for(n), kBlock, 0, s, n, K, C, Sig, csize);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Degree classes. Items with length 0 (isolated vertices, empty communities) are skipped: an
+// isolated vertex has no neighbour community to move to.
+
+__device__ __forceinline__ int64_t item_len(const int64_t* off, const int64_t* len, int64_t i) {
+  return len ? len[i] : off[i + 1] - off[i];
+}
+
+// Segment of item i: 8 * (vertex class) + degree class.
+__device__ __forceinline__ int segment_of(int64_t L, int K, int pass, int64_t i) {
+  const int k = K > 1 ? vertex_class(pass, K, i) : 0;
+  return 8 * k + bucket_of(L);
+}
+
+// counts[0 .. 8K): items per segment, counts[256 .. 256 + 8K): total length per segment.
+__global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* off, const int64_t* len,
+                                                        int64_t m, int K, int pass, ull* counts) {
+  __shared__ ull c[2 * 8 * kMaxClasses];
+  const int nseg = 8 * K;
+  for (int t = threadIdx.x; t < 2 * 8 * kMaxClasses; t += blockDim.x) c[t] = 0;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t L = item_len(off, len, i);
+    if (L > 0) {
+      const int sg = segment_of(L, K, pass, i);
+      atomicAdd(&c[sg], 1ull);
+      atomicAdd(&c[8 * kMaxClasses + sg], (ull)L);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nseg; t += blockDim.x) {
+    if (c[t]) atomicAdd(&counts[t], c[t]);
+    if (c[8 * kMaxClasses + t]) atomicAdd(&counts[8 * kMaxClasses + t], c[8 * kMaxClasses + t]);
+  }
+}
+
+// starts: first list position per segment; cursor: per-segment fill counters (zero).
+__global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* off, const int64_t* len,
+                                                       int64_t m, int K, int pass,
+                                                       const ull* starts, ull* cursor,
+                                                       int32_t* list) {
+  __shared__ int cnt[8 * kMaxClasses];
+  __shared__ ull base[8 * kMaxClasses];
+  const int nseg = 8 * K;
+  for (int64_t tile = (int64_t)blockIdx.x * kBlock; tile < m;
+       tile += (int64_t)gridDim.x * kBlock) {
+    for (int t = threadIdx.x; t < nseg; t += blockDim.x) cnt[t] = 0;
+    __syncthreads();
+    const int64_t i = tile + threadIdx.x;
+    int sg = -1, rank = 0;
+    if (i < m) {
+      const int64_t L = item_len(off, len, i);
+      if (L > 0) {
+        sg = segment_of(L, K, pass, i);
+        rank = atomicAdd(&cnt[sg], 1);
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nseg; t += blockDim.x)
+      if (cnt[t]) base[t] = atomicAdd(&cursor[t], (ull)cnt[t]);
+    __syncthreads();
+    if (sg >= 0) list[(int64_t)starts[sg] + (int64_t)base[sg] + rank] = (int32_t)i;
+    __syncthreads();
+  }
+}
+
+hipError_t bucket_rows(const int64_t* off, const int64_t* len, int64_t m, int K, int pass,
+                       int32_t* list, ull* counts, ull* host_counts, Buckets& b, hipStream_t s) {
+  b = Buckets();
+  b.classes = K;
+  if (m <= 0) return hipSuccess;
+  const int nseg = 8 * K;
+  // counts layout: [0, 256) items, [256, 512) lengths, [512, 768) cursors, [768, 1024) starts
+  LV_LAUNCH(k_zero_words, 4, kBlock, 0, s, counts, (int64_t)768);
+  LV_LAUNCH(k_bucket_count, grid_for(m, kBlock, 4096), kBlock, 0, s, off, len, m, K, pass, counts);
+  hipError_t e = hipMemcpyAsync(host_counts, counts, 512 * sizeof(ull), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  int64_t acc = 0;
+  ull* hstarts = host_counts + 768;
+  for (int sg = 0; sg < nseg; sg++) {
+    b.count[sg] = (int64_t)host_counts[sg];
+    b.arcs[sg] = (int64_t)host_counts[8 * kMaxClasses + sg];
+    b.lstart[sg] = acc;
+    hstarts[sg] = (ull)acc;
+    acc += b.count[sg];
+  }
+  b.lstart[nseg] = acc;
+  if (acc == 0) return hipSuccess;
+  e = hipMemcpyAsync(counts + 768, hstarts, nseg * sizeof(ull), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  LV_LAUNCH(k_bucket_fill, grid_for(m, kBlock, 8192), kBlock, 0, s, off, len, m, K, pass,
+            counts + 768, counts + 512, list);
+  return hipGetLastError();
+}
+
+// Hub decomposition. arrays = [nchunk | tsize | nscan] (nh each), scanned into
+// chunk_start/tab_start/scan_start which overwrite... (separate outputs of nh+1 each).
+__global__ void k_hub_sizes(const int64_t* off, const int64_t* len, const int32_t* hubs,
+                            int64_t nh, int64_t* nchunk, int64_t* tsize, int64_t* nscan) {
+  for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < nh;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t L = item_len(off, len, hubs[h]);
+    nchunk[h] = (L + kHubChunk - 1) / kHubChunk;
+    int64_t t = 1;
+    while (t < 2 * L) t <<= 1;
+    tsize[h] = t;
+    nscan[h] = (L + kHubScanChunk - 1) / kHubScanChunk;
+  }
+}
+
+hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs, int64_t nh,
+                     int64_t* arrays, int64_t* partial, ull* host_buf, HubPlan& hp,
+                     hipStream_t s) {
+  hp = HubPlan();
+  hp.nh = nh;
+  if (nh <= 0) return hipSuccess;
+  // arrays layout: 3 input arrays of nh, then 3 outputs of nh+1
+  int64_t* nchunk = arrays;
+  int64_t* tsize = arrays + nh;
+  int64_t* nscan = arrays + 2 * nh;
+  hp.chunk_start = arrays + 3 * nh;
+  hp.tab_start = hp.chunk_start + (nh + 1);
+  hp.scan_start = hp.tab_start + (nh + 1);
+  LV_LAUNCH(k_hub_sizes, grid_for(nh), kBlock, 0, s, off, len, hubs, nh, nchunk, tsize, nscan);
+  hipError_t e;
+  if ((e = scan_i64(nchunk, nh, hp.chunk_start, partial, s)) != hipSuccess) return e;
+  if ((e = scan_i64(tsize, nh, hp.tab_start, partial, s)) != hipSuccess) return e;
+  if ((e = scan_i64(nscan, nh, hp.scan_start, partial, s)) != hipSuccess) return e;
+  e = hipMemcpyAsync(&host_buf[0], hp.chunk_start + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(&host_buf[1], hp.tab_start + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(&host_buf[2], hp.scan_start + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  hp.chunks = (int64_t)host_buf[0];
+  hp.slots = (int64_t)host_buf[1];
+  hp.scan_blocks = (int64_t)host_buf[2];
+  return hipSuccess;
+}
+
+// =============================================================================================
+// Synchronous local-moving iteration, LDS-table path (rows of up to 1024 arcs).
+//
+// One group of G lanes decides one vertex v (every class of the fused kernel has its own G and
+// table size). The group accumulates k_{v->c} for the communities of v's non-self neighbours
+// into an LDS open-addressing table (the per-worker hashtable of section 3.2, one per group),
+// then every lane scans its share of slots computing the exact gain
+// g(c) = W*k_{v->c} - K_v*Sigma_c, and the group reduces (gain, -c) to the best candidate.
+// All reads are of the previous iteration's C, Sigma and csize; movers are appended to a list
+// applied after the kernel, so the outcome does not depend on scheduling.
+
+template <typename WT>
+struct MoveArgs {
+  const int64_t* off;
+  const int32_t* idx;
+  const WT* w;
+  const uint64_t* K;
+  const int32_t* C;
+  const uint64_t* Sig;
+  const int32_t* csize;
+  uint64_t W;
+  const int32_t* list;
+  int64_t bstart[8];  // first block of class k; bstart[7] = total blocks
+  int64_t lstart[8];  // first list position of class k; lstart[7] = end of class 6
+  int2* movers;
+  ull* stats;
+};
+
+struct BlockShared {
+  u128 red128[kBlock / 64];
+  ull red64[kBlock / 64];
+  typename Gain<true>::T bg[kBlock / 64];
+  int32_t bc[kBlock / 64];
+  ull kd[kBlock / 64];
+  int mcount;
+  ull mbase;
+};
+
+template <bool WIDE, typename WT, int G, int LOG2H>
+__device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, int64_t lbase,
+                                           int64_t lcount, unsigned char* smem,
+                                           BlockShared& sh) {
+  typedef Gain<WIDE> Ar;
+  typedef typename Ar::T T;
+  typedef typename Ar::V V;
+  constexpr int H = 1 << LOG2H;
+  constexpr int NG = kBlock / G;
+  int32_t* keys = (int32_t*)smem;
+  V* vals = (V*)(smem + (size_t)NG * H * sizeof(int32_t));
+  const int gid = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t li = lb * NG + gid;
+  const bool valid = li < lcount;
+  const int32_t v = valid ? a.list[lbase + li] : 0;
+  int32_t* gk = keys + gid * H;
+  V* gv = vals + gid * H;
+  for (int s = lane; s < H; s += G) {
+    gk[s] = kEmpty;
+    gv[s] = 0;
+  }
+  if (threadIdx.x == 0) sh.mcount = 0;
+  __syncthreads();
+  int64_t e0 = 0, e1 = 0;
+  if (valid) {
+    e0 = a.off[v];
+    e1 = a.off[v + 1];
+  }
+  for (int64_t e = e0 + lane; e < e1; e += G) {
+    const int32_t j = ld_stream(a.idx + e);
+    const V wv = (V)ld_stream(a.w + e);
+    if (j != v) table_add<V>(gk, gv, LOG2H, a.C[j], wv);
+  }
+  __syncthreads();
+  T bg = Ar::lowest();
+  int32_t bc = INT32_MAX;
+  ull kd = 0;
+  ull nc = 0;
+  int32_t d = 0;
+  uint64_t Ki = 0;
+  if (valid) {
+    d = a.C[v];
+    Ki = a.K[v];
+    for (int s = lane; s < H; s += G) {
+      const int32_t c = gk[s];
+      if (c == kEmpty) continue;
+      const ull kv = (ull)gv[s];
+      if (c == d) {
+        kd = kv;
+        continue;
+      }
+      nc++;
+      const T g = Ar::of(a.W, kv, Ki, a.Sig[c]);
+      if (better(g, c, bg, bc)) {
+        bg = g;
+        bc = c;
+      }
+    }
+  }
+  // group argmax of (gain, -community) and the own-community weight
+  constexpr int WG = G < 64 ? G : 64;
+#pragma unroll
+  for (int m = WG / 2; m >= 1; m >>= 1) {
+    const T og = Ar::shfl_xor(bg, m, WG);
+    const int32_t oc = __shfl_xor(bc, m, WG);
+    const ull ok = __shfl_xor(kd, m, WG);
+    if (better(og, oc, bg, bc)) {
+      bg = og;
+      bc = oc;
+    }
+    kd += ok;
+  }
+  if (G > 64) {
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      sh.bg[wave] = (typename Gain<true>::T)bg;
+      sh.bc[wave] = bc;
+      sh.kd[wave] = kd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int i = 1; i < kBlock / 64; i++) {
+        const T og = (T)sh.bg[i];
+        if (better(og, sh.bc[i], bg, bc)) {
+          bg = og;
+          bc = sh.bc[i];
+        }
+        kd += sh.kd[i];
+      }
+    }
+  }
+  u128 gain = 0;
+  bool moved = false;
+  int local = 0;
+  if (valid && lane == 0 && bc != INT32_MAX) {
+    const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
+    if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
+      moved = true;
+      gain = Ar::diff(bg, stay);
+      local = atomicAdd(&sh.mcount, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && sh.mcount) {
+    sh.mbase = atomicAdd(&a.stats[2], (ull)sh.mcount);
+    atomicAdd(&a.stats[5], (ull)sh.mcount);
+  }
+  __syncthreads();
+  if (moved) a.movers[sh.mbase + local] = make_int2(v, bc);
+  const u128 bsum = block_sum_u128(gain, sh.red128);
+  const ull ncs = block_sum_u64(nc, sh.red64);
+  if (threadIdx.x == 0) {
+    if (bsum) atomic_add_u128(&a.stats[0], bsum);
+    if (ncs) {
+      atomicAdd(&a.stats[3], ncs);
+      atomicAdd(&a.stats[4], ncs);
+    }
+  }
+}
+
+template <bool WIDE, typename WT>
+__global__ __launch_bounds__(kBlock) void k_move_lds(MoveArgs<WT> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ BlockShared sh;
+  const int64_t b = blockIdx.x;
+  int k = 0;
+  while (k < 6 && b >= a.bstart[k + 1]) k++;
+  const int64_t lb = b - a.bstart[k];
+  const int64_t lbase = a.lstart[k], lcount = a.lstart[k + 1] - a.lstart[k];
+  switch (k) {
+    case 0: move_group<WIDE, WT, bucket_group(0), bucket_log2h(0)>(a, lb, lbase, lcount, smem, sh); break;
+    case 1: move_group<WIDE, WT, bucket_group(1), bucket_log2h(1)>(a, lb, lbase, lcount, smem, sh); break;
+    case 2: move_group<WIDE, WT, bucket_group(2), bucket_log2h(2)>(a, lb, lbase, lcount, smem, sh); break;
+    case 3: move_group<WIDE, WT, bucket_group(3), bucket_log2h(3)>(a, lb, lbase, lcount, smem, sh); break;
+    case 4: move_group<WIDE, WT, bucket_group(4), bucket_log2h(4)>(a, lb, lbase, lcount, smem, sh); break;
+    case 5: move_group<WIDE, WT, bucket_group(5), bucket_log2h(5)>(a, lb, lbase, lcount, smem, sh); break;
+    default: move_group<WIDE, WT, bucket_group(6), bucket_log2h(6)>(a, lb, lbase, lcount, smem, sh); break;
+  }
+}
+
+static size_t lds_table_bytes(int k, size_t vbytes) {
+  return (size_t)bucket_rows_per_block(k) * ((size_t)1 << bucket_log2h(k)) * (4 + vbytes);
+}
+
+template <bool WIDE, typename WT>
+static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
+                             hipStream_t s) {
+  MoveArgs<WT> a;
+  a.off = g.off;
+  a.idx = g.idx;
+  a.w = (const WT*)g.w;
+  a.K = m.K;
+  a.C = m.C;
+  a.Sig = m.Sig;
+  a.csize = m.csize;
+  a.W = m.W;
+  a.list = m.list;
+  a.movers = m.movers;
+  a.stats = m.stats;
+  int64_t blocks = 0;
+  size_t shm = 0;
+  const int base = 8 * cls;
+  for (int k = 0; k < 7; k++) {
+    a.bstart[k] = blocks;
+    a.lstart[k] = b.lstart[base + k];
+    const int64_t rpb = bucket_rows_per_block(k);
+    blocks += (b.count[base + k] + rpb - 1) / rpb;
+    if (b.count[base + k]) {
+      size_t t = lds_table_bytes(k, sizeof(typename Gain<WIDE>::V));
+      shm = t > shm ? t : shm;
+    }
+  }
+  a.bstart[7] = blocks;
+  a.lstart[7] = b.lstart[base + 7];
+  if (blocks == 0) return hipSuccess;
+  LV_LAUNCH((k_move_lds<WIDE, WT>), (unsigned)blocks, kBlock, shm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t move_lds(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
+                    bool wide, hipStream_t s) {
+  if (wide)
+    return g.w64 ? move_lds_t<true, uint64_t>(g, b, cls, m, s)
+                 : move_lds_t<true, uint32_t>(g, b, cls, m, s);
+  return g.w64 ? move_lds_t<false, uint64_t>(g, b, cls, m, s)
+               : move_lds_t<false, uint32_t>(g, b, cls, m, s);
+}
+
+// =============================================================================================
+// Hub path (rows longer than 1024 arcs): global-memory tables, one power-of-two table of at
+// least twice the row length per hub. Three kernels: accumulate (blocks over kHubChunk-arc
+// chunks, new keys append their slot to an occupied list), scan (blocks over the occupied
+// list: gains, block-best partials, slots reset for the next iteration), decide (per hub).
+
+__device__ __forceinline__ int64_t find_segment(const int64_t* start, int64_t cnt, int64_t x) {
+  int64_t lo = 0, hi = cnt;  // start[lo] <= x < start[hi]
+  while (hi - lo > 1) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (start[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int ilog2_i64(int64_t x) { return 63 - __clzll((long long)x); }
+
+template <typename WT, typename V>
+struct HubArgs {
+  const int64_t* off;
+  const int32_t* idx;
+  const WT* w;
+  const uint64_t* K;
+  const int32_t* C;
+  const uint64_t* Sig;
+  const int32_t* csize;
+  uint64_t W;
+  const int32_t* hubs;
+  int64_t nh;
+  const int64_t* chunk_start;
+  const int64_t* tab_start;
+  const int64_t* scan_start;
+  int32_t* tkeys;
+  V* tvals;
+  int32_t* occ;
+  int32_t* occ_count;
+  ull* partial;  // 5 words per scan block: gain lo, gain hi, community, kd, candidates
+  int2* movers;
+  ull* stats;
+};
+
+template <typename WT, typename V>
+__global__ __launch_bounds__(kBlock) void k_hub_accumulate(HubArgs<WT, V> a) {
+  const int64_t b = blockIdx.x;
+  const int64_t h = find_segment(a.chunk_start, a.nh, b);
+  const int32_t v = a.hubs[h];
+  const int64_t rb = a.off[v], re = a.off[v + 1];
+  const int64_t e0 = rb + (b - a.chunk_start[h]) * kHubChunk;
+  const int64_t e1 = e0 + kHubChunk < re ? e0 + kHubChunk : re;
+  const int64_t ts = a.tab_start[h];
+  const int lg = ilog2_i64(a.tab_start[h + 1] - ts);
+  int32_t* keys = a.tkeys + ts;
+  V* vals = a.tvals + ts;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+    const int32_t j = ld_stream(a.idx + e);
+    const V wv = (V)ld_stream(a.w + e);
+    if (j == v) continue;
+    uint32_t slot;
+    if (table_add<V>(keys, vals, lg, a.C[j], wv, &slot)) {
+      const int p = atomicAdd(&a.occ_count[h], 1);
+      a.occ[ts + p] = (int32_t)slot;
+    }
+  }
+}
+
+template <bool WIDE, typename WT>
+__global__ __launch_bounds__(kBlock) void k_hub_scan(HubArgs<WT, typename Gain<WIDE>::V> a) {
+  typedef Gain<WIDE> Ar;
+  typedef typename Ar::T T;
+  __shared__ typename Gain<true>::T sbg[kBlock / 64];
+  __shared__ int32_t sbc[kBlock / 64];
+  __shared__ ull skd[kBlock / 64];
+  __shared__ ull snc[kBlock / 64];
+  const int64_t b = blockIdx.x;
+  const int64_t h = find_segment(a.scan_start, a.nh, b);
+  const int32_t v = a.hubs[h];
+  const int64_t ts = a.tab_start[h];
+  const int64_t cnt = a.occ_count[h];
+  const int64_t p0 = (b - a.scan_start[h]) * kHubScanChunk;
+  const int64_t p1 = p0 + kHubScanChunk < cnt ? p0 + kHubScanChunk : cnt;
+  const int32_t d = a.C[v];
+  const uint64_t Ki = a.K[v];
+  T bg = Ar::lowest();
+  int32_t bc = INT32_MAX;
+  ull kd = 0, nc = 0;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
+    const int64_t s = ts + a.occ[ts + p];
+    const int32_t c = a.tkeys[s];
+    const ull kv = (ull)a.tvals[s];
+    a.tkeys[s] = kEmpty;
+    a.tvals[s] = 0;
+    if (c == d) {
+      kd = kv;
+      continue;
+    }
+    nc++;
+    const T g = Ar::of(a.W, kv, Ki, a.Sig[c]);
+    if (better(g, c, bg, bc)) {
+      bg = g;
+      bc = c;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const T og = Ar::shfl_xor(bg, m, 64);
+    const int32_t oc = __shfl_xor(bc, m, 64);
+    if (better(og, oc, bg, bc)) {
+      bg = og;
+      bc = oc;
+    }
+    kd += __shfl_xor(kd, m, 64);
+    nc += __shfl_xor(nc, m, 64);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sbg[wave] = (typename Gain<true>::T)bg;
+    sbc[wave] = bc;
+    skd[wave] = kd;
+    snc[wave] = nc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kBlock / 64; i++) {
+      const T og = (T)sbg[i];
+      if (better(og, sbc[i], bg, bc)) {
+        bg = og;
+        bc = sbc[i];
+      }
+      kd += skd[i];
+      nc += snc[i];
+    }
+    const i128 wideg = (i128)bg;
+    ull* out = a.partial + 5 * b;
+    out[0] = (ull)(u128)wideg;
+    out[1] = (ull)((u128)wideg >> 64);
+    out[2] = (ull)(uint32_t)bc;
+    out[3] = kd;
+    out[4] = nc;
+  }
+}
+
+template <bool WIDE, typename WT>
+__global__ __launch_bounds__(kBlock) void k_hub_decide(HubArgs<WT, typename Gain<WIDE>::V> a) {
+  typedef Gain<WIDE> Ar;
+  typedef typename Ar::T T;
+  __shared__ u128 red[kBlock / 64];
+  __shared__ ull red64[kBlock / 64];
+  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  u128 gain = 0;
+  ull nc = 0;
+  if (h < a.nh) {
+    const int32_t v = a.hubs[h];
+    T bg = Ar::lowest();
+    int32_t bc = INT32_MAX;
+    ull kd = 0;
+    for (int64_t p = a.scan_start[h]; p < a.scan_start[h + 1]; p++) {
+      const ull* in = a.partial + 5 * p;
+      const T og = (T)(i128)(((u128)in[1] << 64) | in[0]);
+      const int32_t oc = (int32_t)(uint32_t)in[2];
+      if (better(og, oc, bg, bc)) {
+        bg = og;
+        bc = oc;
+      }
+      kd += in[3];
+      nc += in[4];
+    }
+    a.occ_count[h] = 0;
+    if (bc != INT32_MAX) {
+      const int32_t d = a.C[v];
+      const uint64_t Ki = a.K[v];
+      const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
+      if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
+        gain = Ar::diff(bg, stay);
+        const ull p = atomicAdd(&a.stats[2], 1ull);
+        a.movers[p] = make_int2(v, bc);
+      }
+    }
+  }
+  const u128 bs = block_sum_u128(gain, red);
+  const ull ns = block_sum_u64(nc, red64);
+  if (threadIdx.x == 0) {
+    if (bs) atomic_add_u128(&a.stats[0], bs);
+    if (ns) atomicAdd(&a.stats[3], ns);
+  }
+}
+
+template <typename V>
+__global__ void k_hub_reset(int32_t* keys, V* vals, int64_t slots, int32_t* occ_count,
+                            int64_t nh) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < slots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    keys[i] = kEmpty;
+    vals[i] = 0;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nh;
+       i += (int64_t)gridDim.x * blockDim.x)
+    occ_count[i] = 0;
+}
+
+hipError_t hub_reset_tables(const HubPlan& hp, const MoveBuffers& m, bool wide, hipStream_t s) {
+  if (hp.nh <= 0) return hipSuccess;
+  const int64_t n = hp.slots > hp.nh ? hp.slots : hp.nh;
+  if (wide)
+    LV_LAUNCH(k_hub_reset<ull>, grid_for(n), kBlock, 0, s, m.tkeys, (ull*)m.tvals,
+              hp.slots, m.occ_count, hp.nh);
+  else
+    LV_LAUNCH(k_hub_reset<uint32_t>, grid_for(n), kBlock, 0, s, m.tkeys, (uint32_t*)m.tvals,
+              hp.slots, m.occ_count, hp.nh);
+  return hipGetLastError();
+}
+
+template <bool WIDE, typename WT>
+static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, const HubPlan& hp,
+                              const MoveBuffers& m, hipStream_t s) {
+  typedef typename Gain<WIDE>::V V;
+  HubArgs<WT, V> a;
+  a.off = g.off;
+  a.idx = g.idx;
+  a.w = (const WT*)g.w;
+  a.K = m.K;
+  a.C = m.C;
+  a.Sig = m.Sig;
+  a.csize = m.csize;
+  a.W = m.W;
+  a.hubs = m.list + b.lstart[8 * cls + 7];
+  a.nh = hp.nh;
+  a.chunk_start = hp.chunk_start;
+  a.tab_start = hp.tab_start;
+  a.scan_start = hp.scan_start;
+  a.tkeys = m.tkeys;
+  a.tvals = (V*)m.tvals;
+  a.occ = m.occ;
+  a.occ_count = m.occ_count;
+  a.partial = m.partial;
+  a.movers = m.movers;
+  a.stats = m.stats;
+  LV_LAUNCH((k_hub_accumulate<WT, V>), (unsigned)hp.chunks, kBlock, 0, s, a);
+  LV_LAUNCH((k_hub_scan<WIDE, WT>), (unsigned)hp.scan_blocks, kBlock, 0, s, a);
+  LV_LAUNCH((k_hub_decide<WIDE, WT>), grid_for(hp.nh, kBlock, 1 << 30), kBlock, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const HubPlan& hp,
+                     const MoveBuffers& m, bool wide, hipStream_t s) {
+  if (hp.nh <= 0) return hipSuccess;
+  if (wide)
+    return g.w64 ? move_hubs_t<true, uint64_t>(g, b, cls, hp, m, s)
+                 : move_hubs_t<true, uint32_t>(g, b, cls, hp, m, s);
+  return g.w64 ? move_hubs_t<false, uint64_t>(g, b, cls, hp, m, s)
+               : move_hubs_t<false, uint32_t>(g, b, cls, hp, m, s);
+}
+
+// Apply the iteration's moves: C, Sigma and csize of the next iteration. Integer atomics
+// commute, so the result is independent of the order of the movers.
+__global__ void k_apply_moves(const int2* movers, const ull* stats, const uint64_t* K,
+                              int32_t* C, uint64_t* Sig, int32_t* csize) {
+  const int64_t m = (int64_t)stats[2];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int2 mv = movers[i];
+    const int32_t v = mv.x, c = mv.y;
+    const int32_t d = C[v];
+    const ull k = (ull)K[v];
+    C[v] = c;
+    atomicAdd((ull*)&Sig[c], k);
+    atomicAdd((ull*)&Sig[d], (ull)(0ull - k));
+    atomicAdd(&csize[c], 1);
+    atomicSub(&csize[d], 1);
+  }
+}
+
+hipError_t apply_moves(const MoveBuffers& m, hipStream_t s) {
+  LV_LAUNCH(k_apply_moves, 1024, kBlock, 0, s, m.movers, m.stats, m.K, m.C, m.Sig, m.csize);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Aggregation (section 3.2): communities -> super-vertices.
+
+__global__ void k_label_arcs(const int64_t* off, const int32_t* C, int64_t n, int64_t* A) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t L = off[i + 1] - off[i];
+    if (L) atomicAdd((ull*)&A[C[i]], (ull)L);
+  }
+}
+hipError_t label_arcs(const int64_t* off, const int32_t* C, int64_t n, int64_t* A,
+                      hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_label_arcs, grid_for(n), kBlock, 0, s, off, C, n, A);
+  return hipGetLastError();
+}
+
+__global__ void k_label_tables(int64_t n, const int32_t* csize, const int64_t* newid,
+                               const uint64_t* Sig, int32_t* oldlabel, uint64_t* Kp) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    if (csize[c] > 0) {
+      const int64_t a = newid[c];
+      oldlabel[a] = (int32_t)c;
+      if (Kp) Kp[a] = Sig[c];
+    }
+  }
+}
+hipError_t label_tables(int64_t n, const int32_t* csize, const int64_t* newid,
+                        const uint64_t* Sig, int32_t* oldlabel, uint64_t* Kp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_label_tables, grid_for(n), kBlock, 0, s, n, csize, newid, Sig, oldlabel, Kp);
+  return hipGetLastError();
+}
+
+__global__ void k_vertex_map(const int64_t* off, const int32_t* C, int64_t n,
+                             const int64_t* newid, int64_t* cursor, int32_t* map,
+                             int64_t* abase) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = C[i];
+    map[i] = (int32_t)newid[c];
+    const int64_t L = off[i + 1] - off[i];
+    abase[i] = L ? (int64_t)atomicAdd((ull*)&cursor[c], (ull)L) : 0;
+  }
+}
+hipError_t vertex_map(const int64_t* off, const int32_t* C, int64_t n, const int64_t* newid,
+                      int64_t* cursor, int32_t* map, int64_t* abase, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_vertex_map, grid_for(n), kBlock, 0, s, off, C, n, newid, cursor, map, abase);
+  return hipGetLastError();
+}
+
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_scatter_arcs(const int64_t* off, int64_t n,
+                                                        int64_t nnz, const int32_t* idx,
+                                                        const WT* w, const int32_t* map,
+                                                        const int64_t* abase, int32_t* tkey,
+                                                        uint64_t* tw) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t e0 = t * kSeg;
+  if (e0 >= nnz) return;
+  const int64_t e1 = e0 + kSeg < nnz ? e0 + kSeg : nnz;
+  int64_t r = row_of_arc(off, n, e0);
+  int64_t rb = off[r], rend = off[r + 1];
+  int64_t base = abase[r];
+  for (int64_t e = e0; e < e1; e++) {
+    while (e >= rend) {
+      r++;
+      rb = rend;
+      rend = off[r + 1];
+      base = abase[r];
+    }
+    const int64_t dst = base + (e - rb);
+    tkey[dst] = map[idx[e]];
+    tw[dst] = (uint64_t)w[e];
+  }
+}
+hipError_t scatter_arcs(const DevGraph& g, const int32_t* map, const int64_t* abase,
+                        int32_t* tkey, uint64_t* tw, hipStream_t s) {
+  if (g.nnz <= 0) return hipSuccess;
+  const int64_t threads = (g.nnz + kSeg - 1) / kSeg;
+  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
+  if (g.w64)
+    LV_LAUNCH(k_scatter_arcs<uint64_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
+              (const uint64_t*)g.w, map, abase, tkey, tw);
+  else
+    LV_LAUNCH(k_scatter_arcs<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
+              (const uint32_t*)g.w, map, abase, tkey, tw);
+  return hipGetLastError();
+}
+
+// Merge: the arcs of each community (contiguous in tkey/tw, range astart[c]..astart[c+1])
+// are combined by target super-vertex in an LDS table (communities of up to 1024 arcs) or a
+// global table (larger ones); the distinct (target, summed weight) pairs are written back to
+// the front of the community's range, and their count to dcount[newid[c]].
+struct MergeArgs {
+  const int64_t* astart;
+  const int64_t* newid;
+  int32_t* tkey;
+  uint64_t* tw;
+  int64_t* dcount;
+  ull* stats;  // [0] += weight of self super-arcs
+  const int32_t* list;
+  int64_t bstart[8];
+  int64_t lstart[8];
+};
+
+template <int G, int LOG2H>
+__device__ __forceinline__ void merge_group(const MergeArgs& a, int64_t lb, int64_t lbase,
+                                            int64_t lcount, unsigned char* smem, int* gcount,
+                                            ull* red) {
+  constexpr int H = 1 << LOG2H;
+  constexpr int NG = kBlock / G;
+  int32_t* keys = (int32_t*)smem;
+  ull* vals = (ull*)(smem + (size_t)NG * H * sizeof(int32_t));
+  const int gid = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t li = lb * NG + gid;
+  const bool valid = li < lcount;
+  const int32_t c = valid ? a.list[lbase + li] : 0;
+  int32_t* gk = keys + gid * H;
+  ull* gv = vals + gid * H;
+  for (int s = lane; s < H; s += G) {
+    gk[s] = kEmpty;
+    gv[s] = 0;
+  }
+  if (lane == 0) gcount[gid] = 0;
+  __syncthreads();
+  int64_t e0 = 0, e1 = 0;
+  if (valid) {
+    e0 = a.astart[c];
+    e1 = a.astart[c + 1];
+  }
+  for (int64_t e = e0 + lane; e < e1; e += G) table_add<ull>(gk, gv, LOG2H, a.tkey[e], a.tw[e]);
+  __syncthreads();
+  ull self = 0;
+  if (valid) {
+    const int32_t me = (int32_t)a.newid[c];
+    for (int s = lane; s < H; s += G) {
+      const int32_t key = gk[s];
+      if (key == kEmpty) continue;
+      const int p = atomicAdd(&gcount[gid], 1);
+      a.tkey[e0 + p] = key;
+      a.tw[e0 + p] = gv[s];
+      if (key == me) self = gv[s];
+    }
+  }
+  __syncthreads();
+  if (valid && lane == 0) a.dcount[a.newid[c]] = gcount[gid];
+  const ull bs = block_sum_u64(self, red);
+  if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_lds(MergeArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int gcount[kBlock / 4];
+  __shared__ ull red[kBlock / 64];
+  const int64_t b = blockIdx.x;
+  int k = 0;
+  while (k < 6 && b >= a.bstart[k + 1]) k++;
+  const int64_t lb = b - a.bstart[k];
+  const int64_t lbase = a.lstart[k], lcount = a.lstart[k + 1] - a.lstart[k];
+  switch (k) {
+    case 0: merge_group<bucket_group(0), bucket_log2h(0)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 1: merge_group<bucket_group(1), bucket_log2h(1)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 2: merge_group<bucket_group(2), bucket_log2h(2)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 3: merge_group<bucket_group(3), bucket_log2h(3)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 4: merge_group<bucket_group(4), bucket_log2h(4)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 5: merge_group<bucket_group(5), bucket_log2h(5)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    default: merge_group<bucket_group(6), bucket_log2h(6)>(a, lb, lbase, lcount, smem, gcount, red); break;
+  }
+}
+
+hipError_t merge_lds(const Buckets& b, const AggBuffers& ag, hipStream_t s) {
+  MergeArgs a;
+  a.astart = ag.astart;
+  a.newid = ag.newid;
+  a.tkey = ag.tkey;
+  a.tw = ag.tw;
+  a.dcount = ag.dcount;
+  a.stats = ag.stats;
+  a.list = ag.list;
+  int64_t blocks = 0;
+  size_t shm = 0;
+  for (int k = 0; k < 7; k++) {
+    a.bstart[k] = blocks;
+    a.lstart[k] = b.lstart[k];
+    const int64_t rpb = bucket_rows_per_block(k);
+    blocks += (b.count[k] + rpb - 1) / rpb;
+    if (b.count[k]) {
+      size_t t = lds_table_bytes(k, 8);
+      shm = t > shm ? t : shm;
+    }
+  }
+  a.bstart[7] = blocks;
+  a.lstart[7] = b.lstart[7];
+  if (blocks == 0) return hipSuccess;
+  LV_LAUNCH(k_merge_lds, (unsigned)blocks, kBlock, shm, s, a);
+  return hipGetLastError();
+}
+
+struct MergeHubArgs {
+  const int64_t* astart;
+  const int64_t* newid;
+  int32_t* tkey;
+  uint64_t* tw;
+  int64_t* dcount;
+  ull* stats;
+  const int32_t* hubs;
+  int64_t nh;
+  const int64_t* chunk_start;
+  const int64_t* tab_start;
+  const int64_t* scan_start;
+  int32_t* tkeys;
+  ull* tvals;
+  int32_t* occ;
+  int32_t* occ_count;
+};
+
+__global__ __launch_bounds__(kBlock) void k_merge_hub_accumulate(MergeHubArgs a) {
+  const int64_t b = blockIdx.x;
+  const int64_t h = find_segment(a.chunk_start, a.nh, b);
+  const int32_t c = a.hubs[h];
+  const int64_t rb = a.astart[c], re = a.astart[c + 1];
+  const int64_t e0 = rb + (b - a.chunk_start[h]) * kHubChunk;
+  const int64_t e1 = e0 + kHubChunk < re ? e0 + kHubChunk : re;
+  const int64_t ts = a.tab_start[h];
+  const int lg = ilog2_i64(a.tab_start[h + 1] - ts);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+    uint32_t slot;
+    if (table_add<ull>(a.tkeys + ts, a.tvals + ts, lg, a.tkey[e], a.tw[e], &slot)) {
+      const int p = atomicAdd(&a.occ_count[h], 1);
+      a.occ[ts + p] = (int32_t)slot;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_hub_emit(MergeHubArgs a) {
+  __shared__ ull red[kBlock / 64];
+  const int64_t b = blockIdx.x;
+  const int64_t h = find_segment(a.scan_start, a.nh, b);
+  const int32_t c = a.hubs[h];
+  const int64_t ts = a.tab_start[h];
+  const int64_t cnt = a.occ_count[h];
+  const int64_t p0 = (b - a.scan_start[h]) * kHubScanChunk;
+  const int64_t p1 = p0 + kHubScanChunk < cnt ? p0 + kHubScanChunk : cnt;
+  const int64_t base = a.astart[c];
+  const int32_t me = (int32_t)a.newid[c];
+  ull self = 0;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
+    const int64_t s = ts + a.occ[ts + p];
+    const int32_t key = a.tkeys[s];
+    const ull val = a.tvals[s];
+    a.tkeys[s] = kEmpty;
+    a.tvals[s] = 0;
+    a.tkey[base + p] = key;
+    a.tw[base + p] = val;
+    if (key == me) self = val;
+  }
+  if (b == a.scan_start[h] && threadIdx.x == 0) a.dcount[me] = cnt;
+  const ull bs = block_sum_u64(self, red);
+  if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
+}
+
+hipError_t merge_hubs(const Buckets& b, const HubPlan& hp, const AggBuffers& ag, hipStream_t s) {
+  if (hp.nh <= 0) return hipSuccess;
+  MergeHubArgs a;
+  a.astart = ag.astart;
+  a.newid = ag.newid;
+  a.tkey = ag.tkey;
+  a.tw = ag.tw;
+  a.dcount = ag.dcount;
+  a.stats = ag.stats;
+  a.hubs = ag.list + b.lstart[7];
+  a.nh = hp.nh;
+  a.chunk_start = hp.chunk_start;
+  a.tab_start = hp.tab_start;
+  a.scan_start = hp.scan_start;
+  a.tkeys = ag.tkeys;
+  a.tvals = ag.tvals;
+  a.occ = ag.occ;
+  a.occ_count = ag.occ_count;
+  const int64_t n = hp.slots > hp.nh ? hp.slots : hp.nh;
+  LV_LAUNCH(k_hub_reset<ull>, grid_for(n), kBlock, 0, s, ag.tkeys, ag.tvals, hp.slots,
+            ag.occ_count, hp.nh);
+  LV_LAUNCH(k_merge_hub_accumulate, (unsigned)hp.chunks, kBlock, 0, s, a);
+  LV_LAUNCH(k_merge_hub_emit, (unsigned)hp.scan_blocks, kBlock, 0, s, a);
+  return hipGetLastError();
+}
+
+// Gather the merged rows into the output CSR (thread per kSeg output arcs).
+__global__ __launch_bounds__(kBlock) void k_compact_rows(const int64_t* offp, int64_t np,
+                                                        int64_t nnzp, const int32_t* oldlabel,
+                                                        const int64_t* astart,
+                                                        const int32_t* tkey, const uint64_t* tw,
+                                                        int32_t* idx_out, uint64_t* w_out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t e0 = t * kSeg;
+  if (e0 >= nnzp) return;
+  const int64_t e1 = e0 + kSeg < nnzp ? e0 + kSeg : nnzp;
+  int64_t r = row_of_arc(offp, np, e0);
+  int64_t rb = offp[r], rend = offp[r + 1];
+  int64_t src = astart[oldlabel[r]];
+  for (int64_t e = e0; e < e1; e++) {
+    while (e >= rend) {
+      r++;
+      rb = rend;
+      rend = offp[r + 1];
+      src = astart[oldlabel[r]];
+    }
+    idx_out[e] = tkey[src + (e - rb)];
+    w_out[e] = tw[src + (e - rb)];
+  }
+}
+hipError_t compact_rows(const int64_t* offp, int64_t np, int64_t nnzp, const int32_t* oldlabel,
+                        const int64_t* astart, const int32_t* tkey, const uint64_t* tw,
+                        int32_t* idx_out, uint64_t* w_out, hipStream_t s) {
+  if (nnzp <= 0) return hipSuccess;
+  const int64_t threads = (nnzp + kSeg - 1) / kSeg;
+  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
+  LV_LAUNCH(k_compact_rows, grid, kBlock, 0, s, offp, np, nnzp, oldlabel, astart, tkey, tw,
+            idx_out, w_out);
+  return hipGetLastError();
+}
+
+__global__ void k_compose(int32_t* top, int64_t n, const int32_t* map) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    top[i] = map[top[i]];
+}
+hipError_t compose_membership(int32_t* top, int64_t n, const int32_t* map, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_compose, grid_for(n), kBlock, 0, s, top, n, map);
+  return hipGetLastError();
+}
+
+}  // namespace lv

@@ -1,0 +1,315 @@
+"""Python binding of liblouvain.so (the C ABI in include/louvain.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels. Device
+buffers are torch tensors on the GPU, streams are torch's current stream. The library must have
+been built (``paper_2301_12390_amd.build``); loading fails loudly otherwise.
+"""
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblouvain.so")
+
+LV_OK = 0
+STATUS = {0: "LV_OK", -1: "LV_EINVAL", -2: "LV_ENOMEM", -3: "LV_EHIP", -4: "LV_EOVERFLOW",
+          -5: "LV_EBUDGET"}
+
+LV_VALIDATE = 0x1
+LV_TRACE = 0x2
+LV_FORCE_WIDE = 0x4
+
+LV_MAX_PASSES = 64
+LV_MAX_TRACE = 1024
+
+
+class LvI128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_int64)]
+
+    def value(self) -> int:
+        return (int(self.hi) << 64) | int(self.lo)
+
+
+class LvGraph(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("offsets", ctypes.c_void_p),
+        ("indices", ctypes.c_void_p),
+        ("weights", ctypes.c_void_p),
+        ("offsets_64", ctypes.c_int32),
+        ("weights_64", ctypes.c_int32),
+    ]
+
+
+class LvParams(ctypes.Structure):
+    _fields_ = [
+        ("tolerance_exp10", ctypes.c_int32),
+        ("decline_exp10", ctypes.c_int32),
+        ("max_iterations", ctypes.c_int32),
+        ("max_passes", ctypes.c_int32),
+        ("substeps", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class LvIterTrace(ctypes.Structure):
+    _fields_ = [
+        ("pass_", ctypes.c_int32),
+        ("iteration", ctypes.c_int32),
+        ("wide", ctypes.c_int32),
+        ("substeps", ctypes.c_int32),
+        ("gain_sum", LvI128),
+        ("moved", ctypes.c_int64),
+        ("candidates", ctypes.c_int64),
+        ("lds_vertices", ctypes.c_int64),
+        ("lds_arcs", ctypes.c_int64),
+        ("hub_vertices", ctypes.c_int64),
+        ("hub_arcs", ctypes.c_int64),
+        ("lds_candidates", ctypes.c_int64),
+        ("lds_moved", ctypes.c_int64),
+        ("move_ms", ctypes.c_float),
+        ("hub_ms", ctypes.c_float),
+        ("update_ms", ctypes.c_float),
+        ("iter_ms", ctypes.c_float),
+    ]
+
+
+class LvResult(ctypes.Structure):
+    _fields_ = [
+        ("passes", ctypes.c_int32),
+        ("iterations_total", ctypes.c_int32),
+        ("iterations", ctypes.c_int32 * LV_MAX_PASSES),
+        ("n_pass", ctypes.c_int64 * LV_MAX_PASSES),
+        ("nnz_pass", ctypes.c_int64 * LV_MAX_PASSES),
+        ("qnum_pass", LvI128 * LV_MAX_PASSES),
+        ("cap_hits", ctypes.c_int32),
+        ("n_trace", ctypes.c_int32),
+        ("n_communities", ctypes.c_int64),
+        ("W", ctypes.c_uint64),
+        ("q_num", LvI128),
+        ("q", ctypes.c_double),
+        ("total_ms", ctypes.c_float),
+        ("aggregate_ms", ctypes.c_float * LV_MAX_PASSES),
+        ("trace", LvIterTrace * LV_MAX_TRACE),
+    ]
+
+
+class LvMoveStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("hit_cap", ctypes.c_int32),
+        ("moved", ctypes.c_int64),
+        ("gain_sum", LvI128),
+        ("last_gain", LvI128),
+        ("last_moved", ctypes.c_int64),
+        ("last_candidates", ctypes.c_int64),
+    ]
+
+
+# Every symbol the header declares, with its ctypes signature.
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "louvain_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "louvain_ctx_destroy": (None, [_P]),
+    "louvain_last_error": (ctypes.c_char_p, [_P]),
+    "louvain_workspace_bytes": (ctypes.c_uint64, [_P]),
+    "louvain_run": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.POINTER(LvParams), _P,
+                                   ctypes.POINTER(LvResult), _P]),
+    "louvain_move": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.c_uint64,
+                                    ctypes.c_int32, ctypes.POINTER(LvParams), _P, _P, _P,
+                                    ctypes.POINTER(LvMoveStats), _P]),
+    "louvain_aggregate": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, _P, _P,
+                                         ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64), _P]),
+    "louvain_modularity": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.POINTER(LvI128),
+                                          ctypes.POINTER(ctypes.c_uint64),
+                                          ctypes.POINTER(ctypes.c_double), _P]),
+}
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblouvain.so and declare its signatures. Raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2301_12390_amd.build` "
+            "(hipcc, gfx950); there is no fallback implementation")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+class LouvainError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def graph_struct(g) -> LvGraph:
+    """lv_graph for a CSR whose tensors are on the GPU (graphgen.Csr or any object with n,
+    offsets, indices, weights)."""
+    off, idx, w = g.offsets, g.indices, g.weights
+    for t in (off, idx, w):
+        if not t.is_cuda:
+            raise ValueError("graph tensors must be on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("graph tensors must be contiguous")
+    if off.dtype not in (torch.int32, torch.int64) or idx.dtype != torch.int32:
+        raise ValueError("offsets must be int32/int64 and indices int32")
+    if w.dtype not in (torch.int32, torch.int64):
+        raise ValueError("weights must be int32 (uint32 bits) or int64 (uint64 bits)")
+    return LvGraph(int(g.n), int(idx.numel()), off.data_ptr(), idx.data_ptr() if idx.numel() else 0,
+                   w.data_ptr() if w.numel() else 0, 1 if off.dtype == torch.int64 else 0,
+                   1 if w.dtype == torch.int64 else 0)
+
+
+DEFAULT_SUBSTEPS = 8
+
+
+def params_struct(tolerance_exp10=2, decline_exp10=1, max_iterations=20, max_passes=10,
+                  substeps=DEFAULT_SUBSTEPS, flags=0):
+    return LvParams(tolerance_exp10, decline_exp10, max_iterations, max_passes, substeps, flags)
+
+
+def result_dict(r: LvResult) -> dict:
+    P = r.passes
+    tr = []
+    for t in range(r.n_trace):
+        x = r.trace[t]
+        tr.append({
+            "pass": x.pass_, "iteration": x.iteration, "wide": x.wide, "substeps": x.substeps,
+            "S": x.gain_sum.value(), "moved": x.moved, "candidates": x.candidates,
+            "lds_vertices": x.lds_vertices, "lds_arcs": x.lds_arcs,
+            "hub_vertices": x.hub_vertices, "hub_arcs": x.hub_arcs,
+            "lds_candidates": x.lds_candidates, "lds_moved": x.lds_moved,
+            "move_ms": x.move_ms, "hub_ms": x.hub_ms, "update_ms": x.update_ms,
+            "iter_ms": x.iter_ms,
+        })
+    return {
+        "passes": P,
+        "iterations_total": r.iterations_total,
+        "iterations": [r.iterations[p] for p in range(P)],
+        "n_pass": [r.n_pass[p] for p in range(P)],
+        "nnz_pass": [r.nnz_pass[p] for p in range(P)],
+        "qnum_pass": [r.qnum_pass[p].value() for p in range(P)],
+        "cap_hits": r.cap_hits,
+        "n_communities": r.n_communities,
+        "W": r.W,
+        "qnum": r.q_num.value(),
+        "q": r.q,
+        "total_ms": r.total_ms,
+        "aggregate_ms": [r.aggregate_ms[p] for p in range(P)],
+        "trace": tr,
+    }
+
+
+class Louvain:
+    """A library context bound to one GPU, with a workspace limited to ``hbm_budget`` bytes
+    (0 = unlimited)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self.lib.louvain_ctx_create(device, hbm_budget, ctypes.byref(h))
+        if st != LV_OK:
+            raise LouvainError(st, "louvain_ctx_create failed")
+        self.h = h
+        self._result = LvResult()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.louvain_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != LV_OK:
+            msg = self.lib.louvain_last_error(self.h)
+            raise LouvainError(st, msg.decode() if msg else "")
+
+    def workspace_bytes(self) -> int:
+        return int(self.lib.louvain_workspace_bytes(self.h))
+
+    def run(self, g, tolerance_exp10=2, decline_exp10=1, max_iterations=20, max_passes=10,
+            substeps=DEFAULT_SUBSTEPS, flags=0, membership=None):
+        """Whole method. Returns (membership int32 tensor [n], result dict)."""
+        gs = graph_struct(g)
+        if membership is None:
+            membership = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.indices.device)
+        p = params_struct(tolerance_exp10, decline_exp10, max_iterations, max_passes, substeps,
+                          flags)
+        r = self._result
+        st = self.lib.louvain_run(self.h, ctypes.byref(gs), ctypes.byref(p), _ptr(membership),
+                                  ctypes.byref(r), _stream())
+        self._check(st)
+        return membership[:g.n], result_dict(r)
+
+    def move(self, g, C, Sigma, csize, K=None, W=0, pass_index=0, tolerance_exp10=2,
+             decline_exp10=1, max_iterations=20, substeps=DEFAULT_SUBSTEPS, flags=0) -> dict:
+        """One local-moving phase in place on (C, Sigma, csize); Sigma is an int64 tensor of
+        uint64 values. Returns the phase statistics."""
+        gs = graph_struct(g)
+        p = params_struct(tolerance_exp10, decline_exp10, max_iterations, 1, substeps, flags)
+        ms = LvMoveStats()
+        st = self.lib.louvain_move(self.h, ctypes.byref(gs), _ptr(K), int(W), pass_index,
+                                   ctypes.byref(p), _ptr(C), _ptr(Sigma), _ptr(csize),
+                                   ctypes.byref(ms), _stream())
+        self._check(st)
+        return {"iterations": ms.iterations, "hit_cap": ms.hit_cap, "moved": ms.moved,
+                "gain_sum": ms.gain_sum.value(), "last_gain": ms.last_gain.value(),
+                "last_moved": ms.last_moved, "last_candidates": ms.last_candidates}
+
+    def aggregate(self, g, C, offsets_64=True):
+        """Super-vertex graph of C. Returns (map int32 [n], (n', offsets, indices, weights))
+        with weights as int64 (uint64 values)."""
+        gs = graph_struct(g)
+        dev = g.indices.device
+        n, nnz = int(g.n), int(g.indices.numel())
+        mp = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        off = torch.empty(n + 1, dtype=torch.int64 if offsets_64 else torch.int32, device=dev)
+        idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        w = torch.empty(max(nnz, 1), dtype=torch.int64, device=dev)
+        n_out = ctypes.c_int64()
+        nnz_out = ctypes.c_int64()
+        st = self.lib.louvain_aggregate(self.h, ctypes.byref(gs), _ptr(C), _ptr(mp), _ptr(off),
+                                        1 if offsets_64 else 0, _ptr(idx), _ptr(w),
+                                        ctypes.byref(n_out), ctypes.byref(nnz_out), _stream())
+        self._check(st)
+        n2, z2 = n_out.value, nnz_out.value
+        return mp[:n], (n2, off[:n2 + 1], idx[:z2], w[:z2])
+
+    def modularity(self, g, C):
+        """(Qnum, W, q) of membership C."""
+        gs = graph_struct(g)
+        q = LvI128()
+        W = ctypes.c_uint64()
+        qd = ctypes.c_double()
+        st = self.lib.louvain_modularity(self.h, ctypes.byref(gs), _ptr(C), ctypes.byref(q),
+                                         ctypes.byref(W), ctypes.byref(qd), _stream())
+        self._check(st)
+        return q.value(), int(W.value), float(qd.value)

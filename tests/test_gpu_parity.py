@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+Per iteration (louvain_move with max_iterations = 1): C, Sigma, csize, S, moved count and the
+number of candidate pairs. Per call: modularity (exact W^2 Q), aggregation (canonicalised
+super-vertex CSR and map), and whole runs (membership, exact Q, iterations per pass, per-
+iteration S and moves).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from graphgen import (add_self_loops, csr_from_arcs, erdos_renyi, lattice_shortcuts, rmat,
+                      ring_of_cliques, sbm, single_edge, two_triangles)
+from graphgen.csr import Csr
+
+from .gpu_util import assert_state_equal, canonical_rows_fast, gpu_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lv(gpu_device):
+    from paper_2301_12390_amd import Louvain, build as B
+    if not __import__("os").path.exists(B.LIB):
+        B.build()
+    ctx = Louvain(0)
+    yield ctx
+    ctx.close()
+
+
+def star(n_leaves: int, weight_fn=None) -> Csr:
+    u = torch.zeros(n_leaves, dtype=torch.int64)
+    v = torch.arange(1, n_leaves + 1)
+    from graphgen import csr_from_edges
+    return csr_from_edges(n_leaves + 1, u, v, weight_fn, name=f"star{n_leaves}")
+
+
+def dup_arcs_graph() -> Csr:
+    # duplicate arcs and self-loops in rows (allowed by the input contract)
+    src = torch.tensor([0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4, 4])
+    dst = torch.tensor([1, 1, 2, 0, 0, 1, 0, 2, 3, 2, 4, 3, 4, 4])
+    w = torch.tensor([2, 3, 1, 3, 2, 7, 1, 5, 4, 4, 2, 2, 1, 1])
+    return csr_from_arcs(5, src, dst, w, name="dup-arcs")
+
+
+def corpus():
+    gs = [
+        two_triangles(),
+        single_edge(),
+        ring_of_cliques(8, 5),
+        ring_of_cliques(30, 5),
+        dup_arcs_graph(),
+        add_self_loops(erdos_renyi(300, 0.03, seed=4, weights=(1, 9))),
+        erdos_renyi(200, 0.05, seed=5, weights=(1, 9), self_loops=True),
+        sbm(3000, 30, 8.0, 2.0, seed=2, weights=(1, 16)),
+        lattice_shortcuts(5000, seed=3),
+        rmat(12, seed=7),
+        rmat(14, seed=3, weights=(1, 16), offsets_dtype=torch.int64),
+        star(3000),
+    ]
+    return gs
+
+
+CORPUS = corpus()
+IDS = [g.name for g in CORPUS]
+
+
+def run_iterations(lv, g, st, flags=0, max_iters=40, ctx="", substeps=1, pass_index=0):
+    """Alternate one GPU iteration and one oracle iteration from the same state."""
+    og = O.Graph.from_csr(g)
+    dg = g.to("cuda:0")
+    C, Sig, cs, K = gpu_state(st)
+    classes = O.class_lists(g.n, pass_index, substeps)
+    for it in range(max_iters):
+        stats = lv.move(dg, C, Sig, cs, K=K, W=st.W, max_iterations=1, flags=flags,
+                        substeps=substeps, pass_index=pass_index)
+        S, moved, ncand = O.substep_iteration(og, st, pass_index, substeps, classes)
+        torch.cuda.synchronize()
+        assert_state_equal(st, C, Sig, cs, f"{ctx} iteration {it}")
+        assert stats["last_gain"] == S, (ctx, it, stats["last_gain"], S)
+        assert stats["last_moved"] == moved, (ctx, it)
+        assert stats["last_candidates"] == ncand, (ctx, it, stats["last_candidates"], ncand)
+        if moved == 0:
+            return it + 1
+    return max_iters
+
+
+@pytest.mark.parametrize("K", [1, 8])
+@pytest.mark.parametrize("g", CORPUS, ids=IDS)
+def test_move_iterations_from_singletons(lv, g, K):
+    st = O.State(O.Graph.from_csr(g))
+    run_iterations(lv, g, st, ctx=g.name, substeps=K)
+
+
+@pytest.mark.parametrize("g", CORPUS, ids=IDS)
+def test_move_iterations_wide_arithmetic(lv, g):
+    st = O.State(O.Graph.from_csr(g))
+    run_iterations(lv, g, st, flags=0x4, max_iters=6, ctx=g.name + " wide")
+    st = O.State(O.Graph.from_csr(g))
+    run_iterations(lv, g, st, flags=0x4, max_iters=4, ctx=g.name + " wide K3", substeps=3,
+                   pass_index=2)
+
+
+@pytest.mark.parametrize("g", CORPUS[2:], ids=IDS[2:])
+def test_move_iterations_from_random_partition(lv, g):
+    rng = np.random.default_rng(11)
+    C = rng.integers(0, max(2, g.n // 7), size=g.n).astype(np.int32)
+    st = O.State(O.Graph.from_csr(g), C)
+    run_iterations(lv, g, st, max_iters=5, ctx=g.name + " random")
+    st = O.State(O.Graph.from_csr(g), C)
+    run_iterations(lv, g, st, max_iters=5, ctx=g.name + " random K5", substeps=5, pass_index=1)
+
+
+def test_move_hub_with_large_community(lv):
+    # a star whose leaves already sit in a few large communities: the hub's row is long and
+    # its candidate set small, and the leaves see huge Sigma values
+    g = star(5000, weight_fn=lambda lo, hi: (hi % 13) + 1)
+    C = (np.arange(g.n) % 4).astype(np.int32)
+    st = O.State(O.Graph.from_csr(g), C)
+    run_iterations(lv, g, st, max_iters=4, ctx="star partition")
+
+
+@pytest.mark.parametrize("g", CORPUS, ids=IDS)
+def test_modularity(lv, g):
+    og = O.Graph.from_csr(g)
+    dg = g.to("cuda:0")
+    rng = np.random.default_rng(3)
+    for C in [np.arange(g.n, dtype=np.int32), np.zeros(g.n, dtype=np.int32),
+              rng.integers(0, max(1, g.n // 5), size=g.n).astype(np.int32)]:
+        q, W, qd = lv.modularity(dg, torch.from_numpy(C).to("cuda:0"))
+        qo, Wo, _ = O.modularity(og, C)
+        assert (q, W) == (qo, Wo)
+        assert abs(qd - qo / (Wo * Wo)) <= 4e-16 * max(1.0, abs(qd))
+
+
+@pytest.mark.parametrize("g", CORPUS, ids=IDS)
+@pytest.mark.parametrize("offsets_64", [True, False])
+def test_aggregate(lv, g, offsets_64):
+    og = O.Graph.from_csr(g)
+    dg = g.to("cuda:0")
+    rng = np.random.default_rng(5)
+    cases = [rng.integers(0, max(1, g.n // 4), size=g.n).astype(np.int32),
+             np.arange(g.n, dtype=np.int32), np.zeros(g.n, dtype=np.int32)]
+    st = O.State(og)
+    O.sync_iteration(og, st)
+    cases.append(st.C.copy())
+    for C in cases:
+        mp, (n2, off, idx, w) = lv.aggregate(dg, torch.from_numpy(C).to("cuda:0"),
+                                             offsets_64=offsets_64)
+        mo, g2 = O.aggregate(og, C)
+        assert np.array_equal(mp.cpu().numpy(), mo)
+        assert n2 == g2.n
+        off_c, idx_c, w_c = canonical_rows_fast(n2, off.cpu().numpy(), idx.cpu().numpy(),
+                                                w.cpu().numpy())
+        assert np.array_equal(off_c, g2.off)
+        assert np.array_equal(idx_c, g2.idx)
+        assert np.array_equal(w_c, g2.w)
+
+
+def check_run(lv, g, flags=0, substeps=8, **kw):
+    og = O.Graph.from_csr(g)
+    okw = {{"tolerance_exp10": "a", "decline_exp10": "b"}.get(k, k): v for k, v in kw.items()}
+    top, ref = O.run(og, "sync", substeps=substeps, **okw)
+    memb, res = lv.run(g.to("cuda:0"), flags=flags, substeps=substeps, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(memb.cpu().numpy(), top), g.name
+    assert res["qnum"] == ref["qnum"] and res["W"] == ref["W"]
+    assert res["passes"] == ref["passes"]
+    assert res["iterations"] == ref["iterations"]
+    assert res["n_pass"] == ref["n_pass"] and res["nnz_pass"] == ref["nnz_pass"]
+    assert res["qnum_pass"] == ref["qnum_pass"]
+    assert res["n_communities"] == ref["n_communities"]
+    assert res["cap_hits"] == ref["cap_hits"]
+    assert [t["S"] for t in res["trace"]] == ref["trace_S"]
+    assert [t["moved"] for t in res["trace"]] == ref["trace_moved"]
+    assert [t["candidates"] for t in res["trace"]] == ref["trace_ncand"]
+    return res, ref
+
+
+@pytest.mark.parametrize("K", [1, 8])
+@pytest.mark.parametrize("g", CORPUS, ids=IDS)
+def test_run(lv, g, K):
+    check_run(lv, g, substeps=K)
+
+
+@pytest.mark.parametrize("K", [2, 3, 32])
+def test_run_other_class_counts(lv, K):
+    check_run(lv, sbm(3000, 30, 8.0, 2.0, seed=2, weights=(1, 16)), substeps=K)
+    check_run(lv, rmat(13, seed=9), substeps=K)
+
+
+def test_run_parameters(lv):
+    g = sbm(4000, 40, 8.0, 2.0, seed=9, weights=(1, 16))
+    for kw in [dict(tolerance_exp10=0), dict(tolerance_exp10=6, decline_exp10=2),
+               dict(max_iterations=1), dict(max_iterations=3, max_passes=2),
+               dict(max_passes=1)]:
+        check_run(lv, g, **kw)
+    check_run(lv, g, flags=0x4)  # 128-bit gains everywhere: identical results
+    check_run(lv, g, flags=0x4, substeps=1)
+
+
+def test_run_sbm10k(lv):
+    from graphgen import config_graph
+    g = config_graph("sbm10k")
+    res, ref = check_run(lv, g)
+    _, ra = O.run(O.Graph.from_csr(g), "async")
+    assert res["q"] >= ra["q"] - 0.01
+    check_run(lv, g, substeps=1)
+
+
+def test_run_rmat16_hubs(lv):
+    g = rmat(16, seed=1)
+    deg = g.degrees()
+    assert int(deg.max()) > 1024  # hub path exercised
+    res, ref = check_run(lv, g)
+    _, ra = O.run(O.Graph.from_csr(g), "async")
+    assert res["q"] >= ra["q"] - 0.01, (res["q"], ra["q"])
+    # the fully synchronous rule matches its oracle too (its quality is lower on this graph)
+    check_run(lv, g, substeps=1)
+
+
+def test_run_deterministic(lv):
+    g = rmat(15, seed=5, weights=(1, 16))
+    dg = g.to("cuda:0")
+    a, ra = lv.run(dg)
+    b, rb = lv.run(dg)
+    assert torch.equal(a, b) and ra["qnum"] == rb["qnum"]
+    assert [t["S"] for t in ra["trace"]] == [t["S"] for t in rb["trace"]]
+
+
+def test_generator_same_on_gpu():
+    from graphgen import csr_sha256
+    for make in [lambda d: sbm(3000, 30, 8.0, 2.0, seed=2, weights=(1, 16), device=d),
+                 lambda d: rmat(14, seed=3, weights=(1, 16), offsets_dtype=torch.int64,
+                                device=d)]:
+        assert csr_sha256(make("cpu")) == csr_sha256(make("cuda:0"))
+
+
+def test_empty_and_edgeless(lv):
+    dev = "cuda:0"
+    g = Csr(0, torch.zeros(1, dtype=torch.int32, device=dev),
+            torch.zeros(0, dtype=torch.int32, device=dev),
+            torch.zeros(0, dtype=torch.int32, device=dev))
+    memb, res = lv.run(g)
+    assert memb.numel() == 0 and res["passes"] == 0 and res["qnum"] == 0
+    g = Csr(5, torch.zeros(6, dtype=torch.int32, device=dev),
+            torch.zeros(0, dtype=torch.int32, device=dev),
+            torch.zeros(0, dtype=torch.int32, device=dev))
+    memb, res = lv.run(g)
+    assert memb.cpu().tolist() == list(range(5)) and res["q"] == 0.0 and res["passes"] == 0
+    # only self-loops: nobody has a candidate
+    g = csr_from_arcs(4, torch.arange(4), torch.arange(4), torch.tensor([1, 2, 3, 4])).to(dev)
+    memb, res = lv.run(g)
+    assert memb.cpu().tolist() == [0, 1, 2, 3]
+    top, ref = O.run(O.Graph.from_csr(g), "sync")
+    assert res["qnum"] == ref["qnum"]
+
+
+def test_errors(lv):
+    from paper_2301_12390_amd import LouvainError
+    g = two_triangles().to("cuda:0")
+    with pytest.raises(LouvainError, match="EINVAL"):
+        lv.run(g, max_iterations=0)
+    with pytest.raises(LouvainError, match="EINVAL"):
+        lv.run(g, max_passes=65)
+    with pytest.raises(LouvainError, match="EINVAL"):
+        lv.run(g, tolerance_exp10=-1)
+    bad = Csr(6, g.offsets, g.indices.clone(), g.weights)
+    bad.indices[3] = 99
+    with pytest.raises(LouvainError, match="EINVAL"):
+        lv.run(bad, flags=0x1)
+    zero_w = Csr(6, g.offsets, g.indices, torch.zeros_like(g.weights))
+    with pytest.raises(LouvainError, match="EINVAL"):
+        lv.run(zero_w, flags=0x1)
+    # the context stays usable after errors
+    memb, res = lv.run(g)
+    assert memb.cpu().tolist() == [0, 0, 0, 1, 1, 1]
+
+
+def test_budget():
+    from paper_2301_12390_amd import Louvain, LouvainError
+    small = Louvain(0, hbm_budget=1 << 12)
+    g = sbm(2000, 20, 8.0, 2.0, seed=1).to("cuda:0")
+    with pytest.raises(LouvainError, match="EBUDGET"):
+        small.run(g)
+    small.close()
+    big = Louvain(0, hbm_budget=1 << 30)
+    memb, res = big.run(g)
+    assert big.workspace_bytes() <= 1 << 30
+    big.close()

@@ -34,6 +34,10 @@ MUTATIONS = {
     "aggregate_transposed": ("int32_t b = map[idx[e]];", "int32_t b = map[i];"),
     "threshold_off_by_two": ("u128 div = 2;", "u128 div = 1;"),
     "sync_reads_current_state": ("Cn[i] = r.target;", "Cn[i] = r.target; C[i] = r.target;"),
+    "class_hash_constant": ("z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
+                            "z = (z ^ (z >> 27)) * 0x94D049BB133111EAull;"),
+    "step_moves_unlisted": ("int64_t i = verts ? verts[t] : t;\n      decision",
+                            "int64_t i = verts ? (verts[t] + 1) % n : t;\n      decision"),
     "async_no_sigma_update": ("Sig[c] += K[i];\n      csize[d] -= 1;", "csize[d] -= 1;"),
 }
 
@@ -49,6 +53,8 @@ def battery():
     P.test_single_move_identity()
     P.test_sync_iteration_bruteforce()
     P.test_sync_zero_gain_move_not_taken()
+    P.test_vertex_class_matches_splitmix64()
+    P.test_sync_step_on_a_subset_bruteforce()
     P.test_async_exact_change_per_iteration()
     P.test_aggregation_invariants()
     P.test_worked_example_two_triangles()

@@ -210,8 +210,9 @@ def test_single_move_identity():
 # synchronous rule: every decision checked by brute force over modularity changes
 
 
-def sync_decisions_bruteforce(g: O.Graph, C):
-    """Next membership and S under the synchronous rule, from modularity differences only."""
+def sync_decisions_bruteforce(g: O.Graph, C, subset=None):
+    """Next membership and S under the synchronous rule, from modularity differences only.
+    With ``subset``, only those vertices decide; the others keep their community."""
     n = g.n
     q0 = q_pairwise(g, C)
     W = sum(w for _, _, w in arcs_of(g))
@@ -222,7 +223,7 @@ def sync_decisions_bruteforce(g: O.Graph, C):
             nbr[i].add(int(C[j]))
     Cn = C.copy()
     S = Fraction(0)
-    for i in range(n):
+    for i in (range(n) if subset is None else subset):
         d = int(C[i])
         best, best_dq = None, None
         for c in sorted(nbr[i] - {d}):
@@ -281,6 +282,74 @@ def test_sync_zero_gain_move_not_taken():
         O.sync_iteration(g, st)
         Cn, _ = sync_decisions_bruteforce(g, C)
         assert np.array_equal(st.C, Cn)
+
+
+def test_vertex_class_matches_splitmix64():
+    # class of v in pass p: upper 32 bits of the (v+1)-th SplitMix64 output from state p,
+    # scaled to [0, K); computed here with Python integers, independently of the C code
+    from graphgen.rng import GAMMA, MASK64, mix_int
+    for p in (0, 1, 7):
+        for K in (2, 3, 8, 32):
+            for v in list(range(50)) + [12345, 2**31 - 1]:
+                z = (p + (v + 1) * GAMMA) & MASK64
+                expect = ((mix_int(z) >> 32) * K) >> 32
+                assert O.vertex_class(p, K, v) == expect
+    # the classes are near-uniform
+    cls = [O.vertex_class(0, 8, v) for v in range(8000)]
+    counts = np.bincount(cls, minlength=8)
+    assert counts.min() > 850 and counts.max() < 1150
+
+
+def test_sync_step_on_a_subset_bruteforce():
+    for gi, g in enumerate(small_graphs()):
+        rng = np.random.default_rng(40 + gi)
+        for C in [np.arange(g.n, dtype=np.int32), random_partition(g.n, 3, gi)]:
+            subset = sorted(rng.choice(g.n, size=max(1, g.n // 2), replace=False).tolist())
+            st = O.State(g, C)
+            S, moved, _ = O.sync_step(g, st, subset)
+            Cn, Sb = sync_decisions_bruteforce(g, C, subset)
+            assert np.array_equal(st.C, Cn) and S == Sb, gi
+
+
+def test_substep_iteration_is_a_sequence_of_steps():
+    g = O.Graph.from_csr(sbm(600, 6, 8.0, 2.0, seed=4, weights=(1, 16)))
+    K = 4
+    classes = O.class_lists(g.n, 0, K)
+    assert sorted(np.concatenate(classes).tolist()) == list(range(g.n))
+    st = O.State(g)
+    ref = st.copy()
+    S, moved, nc = O.substep_iteration(g, st, 0, K)
+    S2 = m2 = 0
+    for vs in classes:
+        a, b, _ = O.sync_step(g, ref, vs)
+        S2 += a
+        m2 += b
+    assert np.array_equal(st.C, ref.C) and S == S2 and moved == m2
+    # with one class, a substep iteration is the synchronous iteration
+    st1 = O.State(g)
+    st2 = O.State(g)
+    assert O.substep_iteration(g, st1, 0, 1) == O.sync_iteration(g, st2)
+    assert np.array_equal(st1.C, st2.C)
+
+
+def test_substep_run_bounded_by_optimum():
+    for s in range(3):
+        g = O.Graph.from_csr(erdos_renyi(8, 0.45, seed=70 + s, weights=(1, 4)))
+        qo = q_opt_bruteforce(g)
+        for K in (2, 4):
+            top, res = O.run(g, "sync", substeps=K)
+            assert Fraction(res["qnum"], res["W"] ** 2) <= qo
+            assert O.modularity(g, top)[0] == res["qnum"]
+
+
+def test_quality_substeps_vs_async():
+    # the fully synchronous rule oscillates on skewed graphs; classes processed in turn
+    # (partial asynchrony) stay within 0.01 of the asynchronous rule
+    from graphgen import rmat
+    g = O.Graph.from_csr(rmat(16, seed=1))
+    _, ra = O.run(g, "async")
+    _, r8 = O.run(g, "sync", substeps=8)
+    assert r8["q"] >= ra["q"] - 0.01, (r8["q"], ra["q"])
 
 
 def test_sync_thread_count_invariance():
