@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Louvain TEPS on one MI355X.
+
+A step is one whole Louvain run (section 3.2 of Sahu, arXiv 2301.12390: passes of local moving
+and aggregation until convergence, tolerance 0.01 declining x10 per pass, then the modularity of
+the result) through the C ABI of liblouvain.so, on a graph already resident in HBM.
+
+Default workload: R-MAT scale 25 (33,554,432 vertices, edge factor 16, a,b,c,d = 0.57, 0.19,
+0.19, 0.05, symmetrised, self-loops and repeats removed, weights uniform 1..16, int64 offsets,
+seed 1), generated on the GPU. TEPS = input arcs / run time.
+
+Printed (stdout, one JSON line): the metric, the roofline of the dominant kernel (the LDS-table
+move kernel, algorithmic bytes over its HIP-event-timed launches in the timed region), and the
+CPU oracle timed on a bounded sample of the same workload. Progress goes to stderr.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Louvain TEPS (R-MAT s25); batched graphs/s vs one-by-one; serving p50/p99 ms"
+HBM_PEAK_GBPS = 8000.0
+PROFILE_PMC = os.path.join(ROOT, "profiles", "move_lds_rmat25_pmc.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2301_12390_amd", "csrc", "lv_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# Algorithmic bytes of the LDS-table move kernel (what the method must move, not cache lines):
+# per decided vertex: its row offset (o = 4 or 8 B, the input's offset width), C[v] 4, K[v] 8,
+# Sigma[own] 8, csize[own] 4, csize[best] 4 and its decision 4 -> o + 32 B; per arc: neighbour
+# id 4, weight 4, C[neighbour] 4 -> 12 B; per distinct candidate community: Sigma[c] 8 B.
+BYTES_PER_VERTEX_BASE = 32
+BYTES_PER_ARC = 12
+BYTES_PER_CANDIDATE = 8
+
+
+def kernel_src_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def load_traffic(workload):
+    """Measured HBM bytes per launch of the move kernel from the committed rocprofv3 PMC
+    summary, if it was taken on this workload with the current kernel source."""
+    try:
+        d = json.load(open(PROFILE_PMC))
+    except (OSError, ValueError):
+        return None
+    if d.get("workload") != workload or d.get("kernel_src_sha256") != kernel_src_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(g, res_trace, seconds, substeps, n_arcs_input):
+    """The oracle (plain C, OpenMP) on a bounded sample: the class steps of the first
+    local-moving iteration of pass 0 on the same graph, as many as fit in ~`seconds`. Its arc
+    rate is scaled to the whole run by the arcs the run's iterations scan."""
+    import numpy as np
+    import oracle as O
+
+    t0 = time.perf_counter()
+    og = O.Graph.from_csr(g)
+    st = O.State(og)
+    classes = O.class_lists(og.n, 0, substeps)
+    deg = np.diff(og.off)
+    prep = time.perf_counter() - t0
+    log(f"oracle prepared in {prep:.1f}s")
+    arcs = 0
+    steps = 0
+    t1 = time.perf_counter()
+    for vs in classes:
+        O.sync_step(og, st, vs)
+        arcs += int(deg[vs].sum())
+        steps += 1
+        if time.perf_counter() - t1 >= seconds:
+            break
+    el = time.perf_counter() - t1
+    rate = arcs / el
+    scanned = sum(t["lds_arcs"] + t["hub_arcs"] for t in res_trace)
+    est_run = scanned / rate
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": n_arcs_input / est_run,
+        "unit": "TEPS",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{steps} of {substeps} synchronous class steps of pass 0 iteration 0 "
+                   f"({arcs} arcs, {el:.1f}s); run time estimated as the {scanned} arcs the "
+                   f"run's local-moving iterations scan at that rate (aggregation excluded)"),
+        "sample_seconds": round(el, 3),
+        "arcs_per_second": rate,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat25",
+                    help="rmat25 (default), rmat22, sbm10k or rmatNN")
+    ap.add_argument("--substeps", type=int, default=8,
+                    help="vertex classes per local-moving iteration (1 = fully synchronous)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the method would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from graphgen import config_graph
+    from paper_2301_12390_amd import LV_TRACE, Louvain
+    from paper_2301_12390_amd import build as lib_build
+
+    if not os.path.exists(lib_build.LIB):
+        lib_build.build()
+    dev = torch.device("cuda:0")
+    log(f"device {torch.cuda.get_device_name(0)}")
+    t0 = time.perf_counter()
+    g = config_graph(args.workload, device=dev)
+    torch.cuda.synchronize()
+    log(f"generated {args.workload}: n={g.n} nnz={g.nnz} in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.empty_cache()
+
+    lv = Louvain(0)
+    for w in range(args.warmup):
+        _, res = lv.run(g, substeps=args.substeps, flags=LV_TRACE)
+        log(f"warmup {w}: {res['total_ms']:.1f} ms, Q={res['q']:.6f}, passes={res['passes']}, "
+            f"iterations={res['iterations']}")
+    torch.cuda.synchronize()
+    results = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        memb, res = lv.run(g, substeps=args.substeps, flags=LV_TRACE)
+        results.append(res)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1000.0 / args.steps
+    teps = g.nnz / (ms_per_step / 1000.0)
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {teps / 1e9:.3f} GTEPS")
+
+    # roofline of the LDS-table move kernel over the timed region
+    o_bytes = 8 if g.offsets.dtype == torch.int64 else 4
+    lds_ms = lds_launch = lds_bytes = 0.0
+    hub_ms = upd_ms = agg_ms = 0.0
+    wide = False
+    for r in results:
+        for t in r["trace"]:
+            lds_ms += t["move_ms"]
+            hub_ms += t["hub_ms"]
+            upd_ms += t["update_ms"]
+            lds_launch += t["lds_launches"]
+            lds_bytes += ((o_bytes + BYTES_PER_VERTEX_BASE) * t["lds_vertices"]
+                          + BYTES_PER_ARC * t["lds_arcs"]
+                          + BYTES_PER_CANDIDATE * t["lds_candidates"])
+            wide = wide or bool(t["wide"])
+        agg_ms += sum(r["aggregate_ms"])
+    avg_launch_ms = lds_ms / max(lds_launch, 1)
+    bytes_per_launch = lds_bytes / max(lds_launch, 1)
+    achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if lds_ms > 0 else 0.0
+    traffic = load_traffic(args.workload)
+    r0 = results[0]
+    move_teps = sum(t["lds_arcs"] + t["hub_arcs"] for t in r0["trace"]) / max(
+        sum(t["move_ms"] + t["hub_ms"] for t in r0["trace"]) / 1000.0, 1e-12)
+
+    line = {
+        "metric": METRIC,
+        "value": teps,
+        "unit": "TEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i128" if wide else "i64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "n": g.n,
+            "nnz": g.nnz,
+            "W": r0["W"],
+            "offsets": str(g.offsets.dtype).replace("torch.", ""),
+            "tolerance": "1e-2, declining x10 per pass",
+            "substeps": args.substeps,
+            "passes": r0["passes"],
+            "iterations": r0["iterations"],
+            "communities": r0["n_communities"],
+            "Q": r0["q"],
+        },
+        "roofline": {
+            "kernel": "k_move_lds",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "avg_launch_ms": avg_launch_ms,
+            "launches": int(lds_launch),
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+        "breakdown_ms_per_step": {
+            "move_lds": lds_ms / args.steps,
+            "move_hubs": hub_ms / args.steps,
+            "update": upd_ms / args.steps,
+            "aggregate": agg_ms / args.steps,
+        },
+        "move_teps": move_teps,
+    }
+    del memb
+    if not args.no_cpu_baseline:
+        log("cpu baseline: copying the graph to the host")
+        gc = g.to("cpu")
+        del g
+        torch.cuda.empty_cache()
+        line["cpu_baseline"] = cpu_baseline(gc, r0["trace"], args.cpu_seconds, args.substeps,
+                                            gc.nnz)
+        log(f"cpu baseline: {line['cpu_baseline']['value'] / 1e6:.2f} MTEPS")
+    lv.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

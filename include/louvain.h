@@ -101,7 +101,9 @@ typedef struct {
 typedef struct {
   int32_t pass, iteration;
   int32_t wide;            /* 1 if this iteration used 128-bit gains */
-  int32_t substeps;        /* class steps of the iteration (launches of each kernel) */
+  int32_t substeps;        /* class steps of the iteration */
+  int32_t lds_launches;    /* launches of the LDS-table move kernel in the iteration */
+  int32_t hub_launches;    /* class steps that ran the hub kernels */
   lv_i128 gain_sum;        /* S: sum of the applied gains */
   int64_t moved;           /* vertices that changed community */
   int64_t candidates;      /* distinct (vertex, other community) pairs examined */

@@ -172,10 +172,11 @@ def sync_step(g: Graph, st: State, verts, nthreads: int = 0):
 
 def class_lists(n: int, p: int, K: int):
     """Vertices of each class of pass p (ascending)."""
-    if K == 1:
-        return [np.arange(n, dtype=np.int32)]
-    cls = np.array([vertex_class(p, K, v) for v in range(n)], dtype=np.int32)
-    return [np.nonzero(cls == k)[0].astype(np.int32) for k in range(K)]
+    verts = np.zeros(max(n, 1), dtype=np.int32)
+    start = np.zeros(K + 1, dtype=np.int64)
+    lib().orc_class_lists(ctypes.c_int64(n), ctypes.c_int32(p), ctypes.c_int32(K), _p(verts),
+                          _p(start))
+    return [verts[start[k]:start[k + 1]].copy() for k in range(K)]
 
 
 def substep_iteration(g: Graph, st: State, p: int, K: int, classes=None):

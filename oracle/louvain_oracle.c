@@ -70,6 +70,17 @@ int32_t orc_vertex_class(int32_t pass, int32_t K, int64_t v) {
   return (int32_t)((hi * (uint64_t)K) >> 32);
 }
 
+/* Vertices of each class of pass p, ascending within a class: verts[start[k] .. start[k+1]). */
+void orc_class_lists(int64_t n, int32_t pass, int32_t K, int32_t* verts, int64_t* start) {
+  int64_t pos = 0;
+  for (int32_t k = 0; k < K; k++) {
+    start[k] = pos;
+    for (int64_t v = 0; v < n; v++)
+      if (K == 1 || orc_vertex_class(pass, K, v) == k) verts[pos++] = (int32_t)v;
+  }
+  start[K] = pos;
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Degrees, total weight, modularity                                                          */
 /* ---------------------------------------------------------------------------------------- */

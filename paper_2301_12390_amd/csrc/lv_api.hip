@@ -22,7 +22,7 @@ enum SlotId {
   S_K, S_SIG, S_CSIZE, S_C, S_MAP, S_MOVERS, S_LIST, S_OFF64, S_STATS, S_COUNTS, S_SCANP,
   S_HUBARR, S_TKEYS, S_TVALS, S_OCC, S_OCCCNT, S_PARTIAL, S_A, S_ASTART, S_NEWID, S_CURSOR,
   S_OLDLABEL, S_DCOUNT, S_ABASE, S_TKEY, S_TW, S_GOFF0, S_GIDX0, S_GW0, S_GOFF1, S_GIDX1, S_GW1,
-  S_BAD, S_AGGOFF, S_COUNT_SLOTS
+  S_BAD, S_AGGOFF, S_BPART, S_MPART, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -34,12 +34,15 @@ struct Slot {
 
 // Word offsets in the device stats slot and in the pinned host buffer.
 constexpr int ST_MISC = 256;      // device: [256, 264) scratch sums, 264 aggregation self-loops
-constexpr int PIN_COUNTS = 0;     // host: 1024 words of class counts
-constexpr int PIN_HUB = 1024;     // host: hub plan totals
-constexpr int PIN_STATS = 1032;   // host: per-step iteration stats (8 words per class step)
-constexpr int PIN_MISC = 1300;    // host: other read-backs
+constexpr int PIN_COUNTS = 0;     // host: 1536 words of class counts
+constexpr int PIN_HUB = 1536;     // host: hub plan totals
+constexpr int PIN_STATS = 1544;   // host: per-step iteration stats (8 words per class step)
+constexpr int PIN_MISC = 1808;    // host: other read-backs
 constexpr int PIN_WORDS = 2048;
+constexpr int DEG = 12;           // degree classes per vertex class (list segment stride)
 constexpr int STATS_WORDS = 512;
+constexpr int kEvents = 4 * 32 + 2;
+constexpr int EV_AGG = 4 * 32;
 
 struct lv_ctx {
   int device = 0;
@@ -47,8 +50,9 @@ struct lv_ctx {
   uint64_t held = 0;
   Slot slots[S_COUNT_SLOTS];
   std::string err;
+  size_t max_lds = 65536;  // largest LDS allocation of one workgroup on this device
   ull* pinned = nullptr;  // host-pinned words for small read-backs
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[kEvents] = {};  // 4 per class step, then 2 for aggregation
 };
 
 namespace {
@@ -243,19 +247,24 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   int64_t* scanp = nullptr;
   int64_t* hubarr = nullptr;
   CHK(wst(ctx, S_LIST, n, &list));
-  CHK(wst(ctx, S_COUNTS, 1024, &counts));
+  CHK(wst(ctx, S_COUNTS, 1536, &counts));
   CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &scanp));
   HIPCHK(lv::bucket_rows(ph.g.off, nullptr, n, K, ph.pass, list, counts,
                          ctx->pinned + PIN_COUNTS, ph.b, s));
+  const int hf = lv::hub_first_class(ctx->max_lds, ph.wide);
+  ph.m.hub_first = hf;
+  auto hub_rows = [&](int k) {
+    return ph.b.lstart[DEG * k + DEG] - ph.b.lstart[DEG * k + hf];
+  };
   int64_t nh_total = 0;
-  for (int k = 0; k < K; k++) nh_total += ph.b.count[8 * k + 7];
+  for (int k = 0; k < K; k++) nh_total += hub_rows(k);
   CHK(wst(ctx, S_HUBARR, 6 * (nh_total + K), &hubarr));
   lv::HubPlan big;  // largest tables of any class: the buffers are shared by the class steps
   int64_t off = 0;
   for (int k = 0; k < K; k++) {
-    const int64_t nh = ph.b.count[8 * k + 7];
-    HIPCHK(lv::plan_hubs(ph.g.off, nullptr, list + ph.b.lstart[8 * k + 7], nh, hubarr + off,
-                         scanp, ctx->pinned + PIN_HUB, ph.hp[k], s));
+    const int64_t nh = hub_rows(k);
+    HIPCHK(lv::plan_hubs(ph.g.off, nullptr, list + ph.b.lstart[DEG * k + hf], nh, n,
+                         hubarr + off, scanp, ctx->pinned + PIN_HUB, ph.hp[k], s));
     off += 6 * (nh + 1);
     big.nh = std::max(big.nh, nh);
     big.slots = std::max(big.slots, ph.hp[k].slots);
@@ -272,9 +281,11 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
     CHK(wst(ctx, S_PARTIAL, 5 * big.scan_blocks, &ph.m.partial));
     HIPCHK(lv::hub_reset_tables(big, ph.m, ph.wide, s));
   }
-  int2* movers = nullptr;
-  CHK(wst(ctx, S_MOVERS, n, &movers));
-  ph.m.movers = movers;
+  CHK(wst(ctx, S_MOVERS, n, &ph.m.tgt));
+  int64_t max_blocks = 1;
+  for (int k = 0; k < K; k++)
+    max_blocks = std::max(max_blocks, lv::move_lds_blocks(ph.b, k, hf));
+  CHK(wst(ctx, S_BPART, 4 * max_blocks, &ph.m.block_partial));
   ull* st = nullptr;
   CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
   ph.m.stats = st;
@@ -296,14 +307,18 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
                     lv_result* res, PhaseOut* out) {
   const bool trace = (flags & LV_TRACE) != 0;
   const int K = ph.classes;
+  const int hf = ph.m.hub_first;
   int64_t lds_v = 0, lds_a = 0, hub_v = 0, hub_a = 0;
   for (int k = 0; k < K; k++) {
-    for (int j = 0; j < 7; j++) {
-      lds_v += ph.b.count[8 * k + j];
-      lds_a += ph.b.arcs[8 * k + j];
+    for (int j = 0; j < DEG; j++) {
+      if (j < hf) {
+        lds_v += ph.b.count[DEG * k + j];
+        lds_a += ph.b.arcs[DEG * k + j];
+      } else {
+        hub_v += ph.b.count[DEG * k + j];
+        hub_a += ph.b.arcs[DEG * k + j];
+      }
     }
-    hub_v += ph.b.count[8 * k + 7];
-    hub_a += ph.b.arcs[8 * k + 7];
   }
   ull* stats0 = ph.m.stats;
   *out = PhaseOut();
@@ -311,31 +326,48 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
   for (int it = 0; it < max_it; it++) {
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(lv::zero_words(stats0, 8 * K, s));
-    float move_ms = 0, hub_ms = 0, upd_ms = 0;
     for (int k = 0; k < K; k++) {
       lv::MoveBuffers m = ph.m;
       m.stats = stats0 + 8 * k;
-      if (trace) HIPCHK(hipEventRecord(ctx->ev[0], s));
+      hipEvent_t* ev = ctx->ev + 4 * k;
+      if (trace) HIPCHK(hipEventRecord(ev[0], s));
       HIPCHK(lv::move_lds(ph.g, ph.b, k, m, ph.wide, s));
-      if (trace) HIPCHK(hipEventRecord(ctx->ev[1], s));
+      if (trace) HIPCHK(hipEventRecord(ev[1], s));
       HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s));
-      if (trace) HIPCHK(hipEventRecord(ctx->ev[2], s));
-      HIPCHK(lv::apply_moves(m, s));
+      if (trace) HIPCHK(hipEventRecord(ev[2], s));
+      HIPCHK(lv::apply_moves(ph.b, k, m, s));
+      if (trace) HIPCHK(hipEventRecord(ev[3], s));
+    }
+    ull* h = ctx->pinned + PIN_STATS;
+    HIPCHK(hipMemcpyAsync(h, stats0, 8 * K * sizeof(ull), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float move_ms = 0, hub_ms = 0, upd_ms = 0;
+    int lds_launches = 0, hub_launches = 0;
+    for (int k = 0; k < K; k++) {
+      for (int j = 0; j < hf; j++) {
+        // the fused kernel covers classes 0..6 in one launch; each workgroup tier is one more
+        if (j < 7) {
+          if (j == 0) {
+            int64_t rows = 0;
+            for (int q = 0; q < 7; q++) rows += ph.b.count[DEG * k + q];
+            lds_launches += rows > 0;
+          }
+        } else {
+          lds_launches += ph.b.count[DEG * k + j] > 0;
+        }
+      }
+      hub_launches += ph.hp[k].nh > 0;
       if (trace) {
-        HIPCHK(hipEventRecord(ctx->ev[3], s));
-        HIPCHK(hipEventSynchronize(ctx->ev[3]));
+        hipEvent_t* ev = ctx->ev + 4 * k;
         float a = 0, b = 0, c = 0;
-        HIPCHK(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
-        HIPCHK(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
-        HIPCHK(hipEventElapsedTime(&c, ctx->ev[2], ctx->ev[3]));
+        HIPCHK(hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIPCHK(hipEventElapsedTime(&b, ev[1], ev[2]));
+        HIPCHK(hipEventElapsedTime(&c, ev[2], ev[3]));
         move_ms += a;
         hub_ms += b;
         upd_ms += c;
       }
     }
-    ull* h = ctx->pinned + PIN_STATS;
-    HIPCHK(hipMemcpyAsync(h, stats0, 8 * K * sizeof(ull), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
     i128 S = 0;
     int64_t moved = 0, cand = 0, lds_cand = 0, lds_moved = 0;
     for (int k = 0; k < K; k++) {
@@ -359,6 +391,8 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
       r.iteration = it;
       r.wide = ph.wide ? 1 : 0;
       r.substeps = K;
+      r.lds_launches = lds_launches;
+      r.hub_launches = hub_launches;
       r.gain_sum = to_i128(S);
       r.moved = moved;
       r.candidates = cand;
@@ -405,7 +439,7 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   CHK(wst(ctx, S_TW, g.nnz, &a.tw));
   CHK(wst(ctx, S_LIST, n, &a.list));
   CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &a.partial));
-  CHK(wst(ctx, S_COUNTS, 1024, &a.counts));
+  CHK(wst(ctx, S_COUNTS, 1536, &a.counts));
   CHK(wst(ctx, S_STATS, STATS_WORDS, &a.stats));
   HIPCHK(lv::scan_flags_pos(csize, n, a.newid, a.partial, s));
   HIPCHK(lv::label_tables(n, csize, a.newid, Sig, a.oldlabel, Kp, s));
@@ -421,12 +455,18 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   lv::Buckets b;
   HIPCHK(lv::bucket_rows(nullptr, a.A, n, 1, 0, a.list, a.counts, ctx->pinned + PIN_COUNTS, b,
                          s));
+  // the super-vertex count bounds the distinct targets of any community
+  ull* hm = ctx->pinned + PIN_MISC;
+  HIPCHK(hipMemcpyAsync(hm, a.newid + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t np = (int64_t)hm[0];
+  CHK(wst(ctx, S_MPART, lv::merge_lds_blocks(b), &a.block_partial));
   HIPCHK(lv::merge_lds(b, a, s));
-  const int64_t nh = b.count[7];
+  const int64_t nh = b.lstart[DEG] - b.lstart[7];  // communities of more than 1024 arcs
   if (nh > 0) {
     lv::HubPlan hp;
     CHK(wst(ctx, S_HUBARR, 6 * (nh + 1), &a.hub_arrays));
-    HIPCHK(lv::plan_hubs(nullptr, a.A, a.list + b.lstart[7], nh, a.hub_arrays, a.partial,
+    HIPCHK(lv::plan_hubs(nullptr, a.A, a.list + b.lstart[7], nh, np, a.hub_arrays, a.partial,
                          ctx->pinned + PIN_HUB, hp, s));
     CHK(wst(ctx, S_TKEYS, hp.slots, &a.tkeys));
     ull* tv = nullptr;
@@ -436,10 +476,6 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
     CHK(wst(ctx, S_OCCCNT, nh, &a.occ_count));
     HIPCHK(lv::merge_hubs(b, hp, a, s));
   }
-  ull* hm = ctx->pinned + PIN_MISC;
-  HIPCHK(hipMemcpyAsync(hm, a.newid + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const int64_t np = (int64_t)hm[0];
   HIPCHK(lv::scan_i64(a.dcount, np, off_out, a.partial, s));
   HIPCHK(hipMemcpyAsync(hm, off_out + np, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(hm + 1, a.stats, sizeof(ull), hipMemcpyDeviceToHost, s));
@@ -487,12 +523,16 @@ lv_status louvain_ctx_create(int device, uint64_t hbm_budget_bytes, lv_ctx** out
   lv_ctx* ctx = new lv_ctx();
   ctx->device = device;
   ctx->budget = hbm_budget_bytes;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+          hipSuccess && lds > 0)
+    ctx->max_lds = (size_t)lds;
   if (hipHostMalloc((void**)&ctx->pinned, PIN_WORDS * sizeof(ull), hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return LV_EHIP;
   }
   memset(ctx->pinned, 0, PIN_WORDS * sizeof(ull));
-  for (int i = 0; i < 6; i++) {
+  for (int i = 0; i < kEvents; i++) {
     if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
       louvain_ctx_destroy(ctx);
       return LV_EHIP;
@@ -507,7 +547,7 @@ void louvain_ctx_destroy(lv_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   for (int i = 0; i < S_COUNT_SLOTS; i++)
     if (ctx->slots[i].p) (void)hipFree(ctx->slots[i].p);
-  for (int i = 0; i < 6; i++)
+  for (int i = 0; i < kEvents; i++)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
@@ -724,16 +764,16 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
     CHK(wst(ctx, which ? S_GOFF1 : S_GOFF0, cur.n + 1, &noff));
     CHK(wst(ctx, which ? S_GIDX1 : S_GIDX0, cur.nnz, &nidx));
     CHK(wst(ctx, which ? S_GW1 : S_GW0, cur.nnz, &nw));
-    if (trace) HIPCHK(hipEventRecord(ctx->ev[4], s));
+    if (trace) HIPCHK(hipEventRecord(ctx->ev[EV_AGG], s));
     int64_t np = 0, nnzp = 0;
     uint64_t self = 0;
     CHK(aggregate(ctx, cur, C, csize, Sig, map, noff, nidx, (uint64_t*)nw, K, &np, &nnzp, &self,
                   s));
     HIPCHK(lv::compose_membership(membership, n0, map, s));
     if (trace) {
-      HIPCHK(hipEventRecord(ctx->ev[5], s));
-      HIPCHK(hipEventSynchronize(ctx->ev[5]));
-      HIPCHK(hipEventElapsedTime(&res->aggregate_ms[pass], ctx->ev[4], ctx->ev[5]));
+      HIPCHK(hipEventRecord(ctx->ev[EV_AGG + 1], s));
+      HIPCHK(hipEventSynchronize(ctx->ev[EV_AGG + 1]));
+      HIPCHK(hipEventElapsedTime(&res->aggregate_ms[pass], ctx->ev[EV_AGG], ctx->ev[EV_AGG + 1]));
     }
     // W^2 Q of this pass = that of singletons on the super-vertex graph
     ull* st = nullptr;

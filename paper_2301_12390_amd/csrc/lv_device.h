@@ -15,10 +15,10 @@ constexpr int kBlock = 256;        // threads of every general-purpose kernel
 constexpr int32_t kEmpty = -1;     // empty table key (community ids are >= 0)
 constexpr int kNumBuckets = 8;     // degree classes, the last one being hubs
 
-// Degree classes of the local-moving and aggregation kernels. Class k holds rows of length in
-// (kBucketMax[k-1], kBucketMax[k]]; class 7 (hub) is everything longer than kBucketMax[6].
-// Each non-hub class has a fixed group width (lanes per row) and table size with room for
-// twice the row length, so open addressing always finds a free slot.
+// Degree classes of the local-moving and aggregation kernels. Class k < 7 holds rows of length
+// in (bucket_max(k-1), bucket_max(k)] and is handled by the fused LDS kernel: each class has a
+// fixed group width (lanes per row) and a table with room for twice the row length, so open
+// addressing always finds a free slot.
 __host__ __device__ constexpr int64_t bucket_max(int k) {
   return k == 0 ? 4 : k == 1 ? 8 : k == 2 ? 16 : k == 3 ? 32 : k == 4 ? 64 : k == 5 ? 256 : 1024;
 }
@@ -30,6 +30,16 @@ __host__ __device__ constexpr int bucket_log2h(int k) {
 }
 __host__ __device__ constexpr int bucket_rows_per_block(int k) { return kBlock / bucket_group(k); }
 
+// Degree classes 7, 8, 9 (rows of up to 2048, 4096, 8192 arcs) are decided by one 1024-thread
+// workgroup per row with an LDS table of 4096, 8192 or 16384 slots when the device allows such
+// a workgroup allocation; class 10 (longer rows), and any class whose table does not fit, use
+// the global-table hub path. kDegClasses is the stride of the (vertex class, degree class)
+// segments.
+constexpr int kDegClasses = 12;
+constexpr int kFusedClasses = 7;
+constexpr int kHubClass = 10;
+__host__ __device__ constexpr int wg_log2h(int k) { return k == 7 ? 12 : k == 8 ? 13 : 14; }
+
 __host__ __device__ inline int bucket_of(int64_t len) {
   if (len <= 4) return 0;
   if (len <= 8) return 1;
@@ -38,7 +48,10 @@ __host__ __device__ inline int bucket_of(int64_t len) {
   if (len <= 64) return 4;
   if (len <= 256) return 5;
   if (len <= 1024) return 6;
-  return 7;
+  if (len <= 2048) return 7;
+  if (len <= 4096) return 8;
+  if (len <= 8192) return 9;
+  return kHubClass;
 }
 
 // Partial asynchrony: at most kMaxClasses vertex classes per iteration. The class of vertex v
@@ -56,7 +69,7 @@ __host__ __device__ inline int vertex_class(int32_t pass, int32_t K, int64_t v) 
 
 // Hub rows use global-memory tables: accumulation blocks cover kHubChunk arcs each, and the
 // scan blocks cover kHubScanChunk occupied slots each.
-constexpr int64_t kHubChunk = 4096;
+constexpr int64_t kHubChunk = 2048;
 constexpr int64_t kHubScanChunk = 2048;
 
 // ---------------------------------------------------------------------------------------------
@@ -195,6 +208,23 @@ __device__ __forceinline__ ull block_sum_u64(ull x, ull* red) {
 // Row of arc e: the largest r with off[r] <= e (off has n+1 entries, off[n] = nnz > e).
 __device__ __forceinline__ int64_t row_of_arc(const int64_t* off, int64_t n, int64_t e) {
   int64_t lo = 0, hi = n;  // invariant: off[lo] <= e < off[hi]
+  while (hi - lo > 1) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (off[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Row of arc e given a row r with off[r] <= e (e < off[n]): a few linear steps (the common case
+// of short rows), then a binary search, so long runs of empty rows cost O(log n), not O(run).
+__device__ __forceinline__ int64_t advance_row(const int64_t* off, int64_t n, int64_t r,
+                                               int64_t e) {
+#pragma unroll 1
+  for (int k = 0; k < 4; k++) {
+    if (e < off[r + 1]) return r;
+    r++;
+  }
+  int64_t lo = r, hi = n;  // off[lo] <= e < off[hi]
   while (hi - lo > 1) {
     int64_t mid = lo + ((hi - lo) >> 1);
     if (off[mid] <= e) lo = mid; else hi = mid;

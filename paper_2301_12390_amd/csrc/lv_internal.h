@@ -15,12 +15,12 @@ struct DevGraph {
   bool w64 = false;  // weights are uint64 (else uint32)
 };
 
-// Rows grouped by (vertex class k, degree class j), list segment 8k + j.
+// Rows grouped by (vertex class k, degree class j), list segment 12k + j (12 = kDegClasses).
 struct Buckets {
   int classes = 1;
-  int64_t count[256] = {0};   // rows per segment
-  int64_t arcs[256] = {0};    // arcs per segment
-  int64_t lstart[257] = {0};  // first list position per segment (lstart[8K] = total)
+  int64_t count[384] = {0};   // rows per segment
+  int64_t arcs[384] = {0};    // arcs per segment
+  int64_t lstart[385] = {0};  // first list position per segment (lstart[12K] = total)
 };
 
 // Hub (global-table) work decomposition of one pass.
@@ -63,16 +63,16 @@ hipError_t row_sums(const DevGraph& g, uint64_t* K, hipStream_t s);  // K must b
 hipError_t init_state(int64_t n, const uint64_t* K, int32_t* C, uint64_t* Sig, int32_t* csize,
                       hipStream_t s);
 // Classify rows (lengths from offsets, or from `len` if non-null over m items) by vertex
-// class (K classes of pass `pass`) and degree class. counts: device scratch of 1024 words;
-// host_counts: 1024 pinned words. Host result in `b` (synchronises the stream).
+// class (K classes of pass `pass`) and degree class. counts: device scratch of 1536 words;
+// host_counts: 1536 pinned words. Host result in `b` (synchronises the stream).
 hipError_t bucket_rows(const int64_t* off, const int64_t* len, int64_t m, int K, int pass,
                        int32_t* list, unsigned long long* counts,
                        unsigned long long* host_counts, Buckets& b, hipStream_t s);
-// Hub decomposition: sizes/starts for the rows in list[b.lstart[7] .. b.lstart[8]).
-// tmp: 3 * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.
+// Hub decomposition of the rows hubs[0 .. nh) whose keys take at most `cap` distinct values.
+// arrays: 6 * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.
 hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs, int64_t nh,
-                     int64_t* arrays, int64_t* partial, unsigned long long* host_buf,
-                     HubPlan& hp, hipStream_t s);
+                     int64_t cap, int64_t* arrays, int64_t* partial,
+                     unsigned long long* host_buf, HubPlan& hp, hipStream_t s);
 
 // ---- local-moving iteration
 struct MoveBuffers {
@@ -82,7 +82,8 @@ struct MoveBuffers {
   int32_t* csize = nullptr;
   uint64_t W = 0;
   const int32_t* list = nullptr;
-  int2* movers = nullptr;
+  int32_t* tgt = nullptr;               // [n] decision of every vertex of the class step
+  unsigned long long* block_partial = nullptr;  // 4 words per block of the LDS move kernel
   // per class step, 8 words: [0..1] S, [2] moved, [3] candidates, [4] LDS-kernel candidates,
   // [5] LDS-kernel moves
   unsigned long long* stats = nullptr;
@@ -91,7 +92,12 @@ struct MoveBuffers {
   int32_t* occ = nullptr;
   int32_t* occ_count = nullptr;
   unsigned long long* partial = nullptr;  // hub scan partials: 5 words per scan block
+  int hub_first = 10;                     // first degree class on the global-table path
 };
+
+// First degree class that takes the global-table path, given the largest LDS allocation a
+// workgroup may make and the table value width (wide: 8-byte values).
+int hub_first_class(size_t max_lds_per_block, bool wide);
 hipError_t zero_words(unsigned long long* a, int64_t n, hipStream_t s);
 // LDS-table move kernel over the rows of vertex class `cls`.
 hipError_t move_lds(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
@@ -100,7 +106,9 @@ hipError_t hub_reset_tables(const HubPlan& hp, const MoveBuffers& m, bool wide, 
 // Hub kernels over the hub rows of vertex class `cls` (plan hp made for those rows).
 hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const HubPlan& hp,
                      const MoveBuffers& m, bool wide, hipStream_t s);
-hipError_t apply_moves(const MoveBuffers& m, hipStream_t s);
+hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s);
+// Block records the LDS move kernels of class cls write (sizes block_partial).
+int64_t move_lds_blocks(const Buckets& b, int cls, int hub_first);
 
 // ---- modularity pieces
 // out[0] += sum of w over arcs (r, j) with C[r] == C[j] (C == nullptr: r == j, i.e. loops)
@@ -126,7 +134,8 @@ struct AggBuffers {
   int64_t* partial = nullptr;  // scan scratch
   unsigned long long* counts = nullptr;  // 32 words
   unsigned long long* stats = nullptr;   // [0] self-loop weight total
-  int64_t* hub_arrays = nullptr;         // 3 * (n + 1)
+  unsigned long long* block_partial = nullptr;  // 1 word per block of the LDS merge kernel
+  int64_t* hub_arrays = nullptr;         // 6 * (hubs + 1)
   int32_t* tkeys = nullptr;              // global tables (sized by caller from plan)
   unsigned long long* tvals = nullptr;
   int32_t* occ = nullptr;
@@ -141,6 +150,7 @@ hipError_t vertex_map(const int64_t* off, const int32_t* C, int64_t n, const int
 hipError_t scatter_arcs(const DevGraph& g, const int32_t* map, const int64_t* abase,
                         int32_t* tkey, uint64_t* tw, hipStream_t s);
 hipError_t merge_lds(const Buckets& b, const AggBuffers& a, hipStream_t s);
+int64_t merge_lds_blocks(const Buckets& b);  // sizes block_partial
 hipError_t merge_hubs(const Buckets& b, const HubPlan& hp, const AggBuffers& a, hipStream_t s);
 hipError_t compact_rows(const int64_t* offp, int64_t np, int64_t nnzp, const int32_t* oldlabel,
                         const int64_t* astart, const int32_t* tkey, const uint64_t* tw,

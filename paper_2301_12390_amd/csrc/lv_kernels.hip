@@ -319,10 +319,10 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t
   int64_t rend = off[r + 1];
   ull acc = 0;
   for (int64_t e = e0; e < e1; e++) {
-    while (e >= rend) {
+    if (e >= rend) {
       if (acc) atomicAdd((ull*)&K[r], acc);
       acc = 0;
-      r++;
+      r = advance_row(off, n, r + 1, e);
       rend = off[r + 1];
     }
     acc += (ull)w[e];
@@ -359,8 +359,8 @@ __global__ __launch_bounds__(kBlock) void k_intra_weight(const int64_t* off, int
     int64_t rend = off[r + 1];
     int32_t cr = C ? C[r] : (int32_t)r;
     for (int64_t e = e0; e < e1; e++) {
-      while (e >= rend) {
-        r++;
+      if (e >= rend) {
+        r = advance_row(off, n, r + 1, e);
         rend = off[r + 1];
         cr = C ? C[r] : (int32_t)r;
       }
@@ -436,18 +436,20 @@ __device__ __forceinline__ int64_t item_len(const int64_t* off, const int64_t* l
   return len ? len[i] : off[i + 1] - off[i];
 }
 
-// Segment of item i: 8 * (vertex class) + degree class.
+// Segment of item i: kDegClasses * (vertex class) + degree class.
+constexpr int kMaxSeg = kDegClasses * kMaxClasses;
+
 __device__ __forceinline__ int segment_of(int64_t L, int K, int pass, int64_t i) {
   const int k = K > 1 ? vertex_class(pass, K, i) : 0;
-  return 8 * k + bucket_of(L);
+  return kDegClasses * k + bucket_of(L);
 }
 
-// counts[0 .. 8K): items per segment, counts[256 .. 256 + 8K): total length per segment.
+// counts[0 .. nseg): items per segment, counts[kMaxSeg .. kMaxSeg + nseg): total length.
 __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* off, const int64_t* len,
                                                         int64_t m, int K, int pass, ull* counts) {
-  __shared__ ull c[2 * 8 * kMaxClasses];
-  const int nseg = 8 * K;
-  for (int t = threadIdx.x; t < 2 * 8 * kMaxClasses; t += blockDim.x) c[t] = 0;
+  __shared__ ull c[2 * kMaxSeg];
+  const int nseg = kDegClasses * K;
+  for (int t = threadIdx.x; t < 2 * kMaxSeg; t += blockDim.x) c[t] = 0;
   __syncthreads();
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -455,13 +457,13 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* off, con
     if (L > 0) {
       const int sg = segment_of(L, K, pass, i);
       atomicAdd(&c[sg], 1ull);
-      atomicAdd(&c[8 * kMaxClasses + sg], (ull)L);
+      atomicAdd(&c[kMaxSeg + sg], (ull)L);
     }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < nseg; t += blockDim.x) {
     if (c[t]) atomicAdd(&counts[t], c[t]);
-    if (c[8 * kMaxClasses + t]) atomicAdd(&counts[8 * kMaxClasses + t], c[8 * kMaxClasses + t]);
+    if (c[kMaxSeg + t]) atomicAdd(&counts[kMaxSeg + t], c[kMaxSeg + t]);
   }
 }
 
@@ -470,9 +472,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* off, cons
                                                        int64_t m, int K, int pass,
                                                        const ull* starts, ull* cursor,
                                                        int32_t* list) {
-  __shared__ int cnt[8 * kMaxClasses];
-  __shared__ ull base[8 * kMaxClasses];
-  const int nseg = 8 * K;
+  __shared__ int cnt[kMaxSeg];
+  __shared__ ull base[kMaxSeg];
+  const int nseg = kDegClasses * K;
   for (int64_t tile = (int64_t)blockIdx.x * kBlock; tile < m;
        tile += (int64_t)gridDim.x * kBlock) {
     for (int t = threadIdx.x; t < nseg; t += blockDim.x) cnt[t] = 0;
@@ -500,48 +502,54 @@ hipError_t bucket_rows(const int64_t* off, const int64_t* len, int64_t m, int K,
   b = Buckets();
   b.classes = K;
   if (m <= 0) return hipSuccess;
-  const int nseg = 8 * K;
-  // counts layout: [0, 256) items, [256, 512) lengths, [512, 768) cursors, [768, 1024) starts
-  LV_LAUNCH(k_zero_words, 4, kBlock, 0, s, counts, (int64_t)768);
+  const int nseg = kDegClasses * K;
+  // counts layout (kMaxSeg words each): items, lengths, fill cursors, segment starts
+  LV_LAUNCH(k_zero_words, 8, kBlock, 0, s, counts, (int64_t)(3 * kMaxSeg));
   LV_LAUNCH(k_bucket_count, grid_for(m, kBlock, 4096), kBlock, 0, s, off, len, m, K, pass, counts);
-  hipError_t e = hipMemcpyAsync(host_counts, counts, 512 * sizeof(ull), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(host_counts, counts, 2 * kMaxSeg * sizeof(ull),
+                                hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   int64_t acc = 0;
-  ull* hstarts = host_counts + 768;
+  ull* hstarts = host_counts + 3 * kMaxSeg;
   for (int sg = 0; sg < nseg; sg++) {
     b.count[sg] = (int64_t)host_counts[sg];
-    b.arcs[sg] = (int64_t)host_counts[8 * kMaxClasses + sg];
+    b.arcs[sg] = (int64_t)host_counts[kMaxSeg + sg];
     b.lstart[sg] = acc;
     hstarts[sg] = (ull)acc;
     acc += b.count[sg];
   }
   b.lstart[nseg] = acc;
   if (acc == 0) return hipSuccess;
-  e = hipMemcpyAsync(counts + 768, hstarts, nseg * sizeof(ull), hipMemcpyHostToDevice, s);
+  e = hipMemcpyAsync(counts + 3 * kMaxSeg, hstarts, nseg * sizeof(ull), hipMemcpyHostToDevice,
+                     s);
   if (e != hipSuccess) return e;
   LV_LAUNCH(k_bucket_fill, grid_for(m, kBlock, 8192), kBlock, 0, s, off, len, m, K, pass,
-            counts + 768, counts + 512, list);
+            counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
   return hipGetLastError();
 }
 
 // Hub decomposition. arrays = [nchunk | tsize | nscan] (nh each), scanned into
 // chunk_start/tab_start/scan_start which overwrite... (separate outputs of nh+1 each).
+// Per hub row of length L whose keys take at most `cap` distinct values: accumulation chunks,
+// a power-of-two table of at least 2 * min(L, cap) slots, and scan blocks for its occupied list.
 __global__ void k_hub_sizes(const int64_t* off, const int64_t* len, const int32_t* hubs,
-                            int64_t nh, int64_t* nchunk, int64_t* tsize, int64_t* nscan) {
+                            int64_t nh, int64_t cap, int64_t* nchunk, int64_t* tsize,
+                            int64_t* nscan) {
   for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < nh;
        h += (int64_t)gridDim.x * blockDim.x) {
     const int64_t L = item_len(off, len, hubs[h]);
+    const int64_t D = L < cap ? L : cap;
     nchunk[h] = (L + kHubChunk - 1) / kHubChunk;
     int64_t t = 1;
-    while (t < 2 * L) t <<= 1;
+    while (t < 2 * D) t <<= 1;
     tsize[h] = t;
-    nscan[h] = (L + kHubScanChunk - 1) / kHubScanChunk;
+    nscan[h] = (D + kHubScanChunk - 1) / kHubScanChunk;
   }
 }
 
 hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs, int64_t nh,
-                     int64_t* arrays, int64_t* partial, ull* host_buf, HubPlan& hp,
+                     int64_t cap, int64_t* arrays, int64_t* partial, ull* host_buf, HubPlan& hp,
                      hipStream_t s) {
   hp = HubPlan();
   hp.nh = nh;
@@ -553,7 +561,8 @@ hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs
   hp.chunk_start = arrays + 3 * nh;
   hp.tab_start = hp.chunk_start + (nh + 1);
   hp.scan_start = hp.tab_start + (nh + 1);
-  LV_LAUNCH(k_hub_sizes, grid_for(nh), kBlock, 0, s, off, len, hubs, nh, nchunk, tsize, nscan);
+  LV_LAUNCH(k_hub_sizes, grid_for(nh), kBlock, 0, s, off, len, hubs, nh, cap, nchunk, tsize,
+            nscan);
   hipError_t e;
   if ((e = scan_i64(nchunk, nh, hp.chunk_start, partial, s)) != hipSuccess) return e;
   if ((e = scan_i64(tsize, nh, hp.tab_start, partial, s)) != hipSuccess) return e;
@@ -579,8 +588,8 @@ hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs
 // into an LDS open-addressing table (the per-worker hashtable of section 3.2, one per group),
 // then every lane scans its share of slots computing the exact gain
 // g(c) = W*k_{v->c} - K_v*Sigma_c, and the group reduces (gain, -c) to the best candidate.
-// All reads are of the previous iteration's C, Sigma and csize; movers are appended to a list
-// applied after the kernel, so the outcome does not depend on scheduling.
+// All reads are of the previous iteration's C, Sigma and csize; every vertex writes its decision,
+// and the decisions are applied after the kernel, so the outcome does not depend on scheduling.
 
 template <typename WT>
 struct MoveArgs {
@@ -595,8 +604,8 @@ struct MoveArgs {
   const int32_t* list;
   int64_t bstart[8];  // first block of class k; bstart[7] = total blocks
   int64_t lstart[8];  // first list position of class k; lstart[7] = end of class 6
-  int2* movers;
-  ull* stats;
+  int32_t* tgt;       // decision of every vertex: its community after the step
+  ull* partial;       // per block: gain sum (2 words), moves, candidate pairs
 };
 
 struct BlockShared {
@@ -605,8 +614,6 @@ struct BlockShared {
   typename Gain<true>::T bg[kBlock / 64];
   int32_t bc[kBlock / 64];
   ull kd[kBlock / 64];
-  int mcount;
-  ull mbase;
 };
 
 template <bool WIDE, typename WT, int G, int LOG2H>
@@ -630,7 +637,6 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
     gk[s] = kEmpty;
     gv[s] = 0;
   }
-  if (threadIdx.x == 0) sh.mcount = 0;
   __syncthreads();
   int64_t e0 = 0, e1 = 0;
   if (valid) {
@@ -701,31 +707,29 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
     }
   }
   u128 gain = 0;
-  bool moved = false;
-  int local = 0;
-  if (valid && lane == 0 && bc != INT32_MAX) {
-    const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
-    if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
-      moved = true;
-      gain = Ar::diff(bg, stay);
-      local = atomicAdd(&sh.mcount, 1);
+  ull moved = 0;
+  if (valid && lane == 0) {
+    int32_t target = d;
+    if (bc != INT32_MAX) {
+      const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
+      if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
+        target = bc;
+        moved = 1;
+        gain = Ar::diff(bg, stay);
+      }
     }
+    a.tgt[v] = target;
   }
-  __syncthreads();
-  if (threadIdx.x == 0 && sh.mcount) {
-    sh.mbase = atomicAdd(&a.stats[2], (ull)sh.mcount);
-    atomicAdd(&a.stats[5], (ull)sh.mcount);
-  }
-  __syncthreads();
-  if (moved) a.movers[sh.mbase + local] = make_int2(v, bc);
+  // block totals go to this block's own record: no contended atomics in the hot kernel
   const u128 bsum = block_sum_u128(gain, sh.red128);
-  const ull ncs = block_sum_u64(nc, sh.red64);
+  const ull bm = block_sum_u64(moved, sh.red64);
+  const ull bn = block_sum_u64(nc, sh.red64);
   if (threadIdx.x == 0) {
-    if (bsum) atomic_add_u128(&a.stats[0], bsum);
-    if (ncs) {
-      atomicAdd(&a.stats[3], ncs);
-      atomicAdd(&a.stats[4], ncs);
-    }
+    ull* o = a.partial + 4 * (int64_t)blockIdx.x;
+    o[0] = (ull)bsum;
+    o[1] = (ull)(bsum >> 64);
+    o[2] = bm;
+    o[3] = bn;
   }
 }
 
@@ -749,6 +753,174 @@ __global__ __launch_bounds__(kBlock) void k_move_lds(MoveArgs<WT> a) {
   }
 }
 
+// Sum of the move kernel's per-block records into the class step's statistics: [0..1] gain sum,
+// [2] moves, [3] candidate pairs, with [4], [5] repeating [3], [2] for the LDS kernel alone.
+__global__ __launch_bounds__(kBlock) void k_reduce_move_partials(const ull* part, int64_t nb,
+                                                                ull* stats) {
+  __shared__ u128 red[kBlock / 64];
+  __shared__ ull red64[kBlock / 64];
+  u128 sg = 0;
+  ull sm = 0, sc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nb;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const ull* p = part + 4 * i;
+    sg += ((u128)p[1] << 64) | p[0];
+    sm += p[2];
+    sc += p[3];
+  }
+  sg = block_sum_u128(sg, red);
+  sm = block_sum_u64(sm, red64);
+  sc = block_sum_u64(sc, red64);
+  if (threadIdx.x == 0) {
+    if (sg) atomic_add_u128(stats, sg);
+    if (sm) {
+      atomicAdd(&stats[2], sm);
+      atomicAdd(&stats[5], sm);
+    }
+    if (sc) {
+      atomicAdd(&stats[3], sc);
+      atomicAdd(&stats[4], sc);
+    }
+  }
+}
+
+// Workgroup-per-row tier (degree classes 7..9): one 1024-thread workgroup decides one vertex
+// with an LDS table of 2^LOG2H slots (twice the longest row of the class).
+constexpr int kWgBlock = 1024;
+
+template <typename WT>
+struct WgArgs {
+  const int64_t* off;
+  const int32_t* idx;
+  const WT* w;
+  const uint64_t* K;
+  const int32_t* C;
+  const uint64_t* Sig;
+  const int32_t* csize;
+  uint64_t W;
+  const int32_t* rows;  // the class's rows
+  int32_t* tgt;
+  ull* partial;         // this launch's block records
+};
+
+template <bool WIDE, typename WT, int LOG2H>
+__global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
+  typedef Gain<WIDE> Ar;
+  typedef typename Ar::T T;
+  typedef typename Ar::V V;
+  constexpr int H = 1 << LOG2H;
+  constexpr int NW = kWgBlock / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ typename Gain<true>::T sbg[NW];
+  __shared__ int32_t sbc[NW];
+  __shared__ ull skd[NW];
+  __shared__ ull snc[NW];
+  int32_t* keys = (int32_t*)smem;
+  V* vals = (V*)(smem + (size_t)H * sizeof(int32_t));
+  const int32_t v = a.rows[blockIdx.x];
+  for (int s = threadIdx.x; s < H; s += kWgBlock) {
+    keys[s] = kEmpty;
+    vals[s] = 0;
+  }
+  __syncthreads();
+  const int64_t e0 = a.off[v], e1 = a.off[v + 1];
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kWgBlock) {
+    const int32_t j = ld_stream(a.idx + e);
+    const V wv = (V)ld_stream(a.w + e);
+    if (j != v) table_add<V>(keys, vals, LOG2H, a.C[j], wv);
+  }
+  __syncthreads();
+  const int32_t d = a.C[v];
+  const uint64_t Ki = a.K[v];
+  T bg = Ar::lowest();
+  int32_t bc = INT32_MAX;
+  ull kd = 0, nc = 0;
+  for (int s = threadIdx.x; s < H; s += kWgBlock) {
+    const int32_t c = keys[s];
+    if (c == kEmpty) continue;
+    const ull kv = (ull)vals[s];
+    if (c == d) {
+      kd = kv;
+      continue;
+    }
+    nc++;
+    const T g = Ar::of(a.W, kv, Ki, a.Sig[c]);
+    if (better(g, c, bg, bc)) {
+      bg = g;
+      bc = c;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const T og = Ar::shfl_xor(bg, m, 64);
+    const int32_t oc = __shfl_xor(bc, m, 64);
+    if (better(og, oc, bg, bc)) {
+      bg = og;
+      bc = oc;
+    }
+    kd += __shfl_xor(kd, m, 64);
+    nc += __shfl_xor(nc, m, 64);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sbg[wave] = (typename Gain<true>::T)bg;
+    sbc[wave] = bc;
+    skd[wave] = kd;
+    snc[wave] = nc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < NW; i++) {
+      const T og = (T)sbg[i];
+      if (better(og, sbc[i], bg, bc)) {
+        bg = og;
+        bc = sbc[i];
+      }
+      kd += skd[i];
+      nc += snc[i];
+    }
+    int32_t target = d;
+    u128 gain = 0;
+    ull moved = 0;
+    if (bc != INT32_MAX) {
+      const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
+      if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
+        target = bc;
+        moved = 1;
+        gain = Ar::diff(bg, stay);
+      }
+    }
+    a.tgt[v] = target;
+    ull* o = a.partial + 4 * (int64_t)blockIdx.x;
+    o[0] = (ull)gain;
+    o[1] = (ull)(gain >> 64);
+    o[2] = moved;
+    o[3] = nc;
+  }
+}
+
+static size_t wg_table_bytes(int k, size_t vbytes) { return ((size_t)1 << wg_log2h(k)) * (4 + vbytes); }
+
+int hub_first_class(size_t max_lds, bool wide) {
+  const size_t vb = wide ? 8 : 4;
+  int k = kFusedClasses;
+  while (k < kHubClass && wg_table_bytes(k, vb) + 2048 <= max_lds) k++;
+  return k;
+}
+
+template <bool WIDE, typename WT, int LOG2H>
+static hipError_t launch_wg(const WgArgs<WT>& a, int64_t rows, hipStream_t s) {
+  const size_t shm = ((size_t)1 << LOG2H) * (4 + sizeof(typename Gain<WIDE>::V));
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_move_wg<WIDE, WT, LOG2H>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    attr = true;
+  }
+  LV_LAUNCH((k_move_wg<WIDE, WT, LOG2H>), (unsigned)rows, kWgBlock, shm, s, a);
+  return hipGetLastError();
+}
+
 static size_t lds_table_bytes(int k, size_t vbytes) {
   return (size_t)bucket_rows_per_block(k) * ((size_t)1 << bucket_log2h(k)) * (4 + vbytes);
 }
@@ -766,12 +938,12 @@ static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const
   a.csize = m.csize;
   a.W = m.W;
   a.list = m.list;
-  a.movers = m.movers;
-  a.stats = m.stats;
+  a.tgt = m.tgt;
+  a.partial = m.block_partial;
   int64_t blocks = 0;
   size_t shm = 0;
-  const int base = 8 * cls;
-  for (int k = 0; k < 7; k++) {
+  const int base = kDegClasses * cls;
+  for (int k = 0; k < kFusedClasses; k++) {
     a.bstart[k] = blocks;
     a.lstart[k] = b.lstart[base + k];
     const int64_t rpb = bucket_rows_per_block(k);
@@ -782,10 +954,45 @@ static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const
     }
   }
   a.bstart[7] = blocks;
-  a.lstart[7] = b.lstart[base + 7];
-  if (blocks == 0) return hipSuccess;
-  LV_LAUNCH((k_move_lds<WIDE, WT>), (unsigned)blocks, kBlock, shm, s, a);
+  a.lstart[7] = b.lstart[base + kFusedClasses];
+  if (blocks > 0) LV_LAUNCH((k_move_lds<WIDE, WT>), (unsigned)blocks, kBlock, shm, s, a);
+  int64_t records = blocks;
+  WgArgs<WT> wa;
+  wa.off = g.off;
+  wa.idx = g.idx;
+  wa.w = (const WT*)g.w;
+  wa.K = m.K;
+  wa.C = m.C;
+  wa.Sig = m.Sig;
+  wa.csize = m.csize;
+  wa.W = m.W;
+  wa.tgt = m.tgt;
+  for (int k = kFusedClasses; k < m.hub_first; k++) {
+    const int64_t rows = b.count[base + k];
+    if (rows == 0) continue;
+    wa.rows = m.list + b.lstart[base + k];
+    wa.partial = m.block_partial + 4 * records;
+    hipError_t e = hipSuccess;
+    if (k == 7) e = launch_wg<WIDE, WT, wg_log2h(7)>(wa, rows, s);
+    else if (k == 8) e = launch_wg<WIDE, WT, wg_log2h(8)>(wa, rows, s);
+    else e = launch_wg<WIDE, WT, wg_log2h(9)>(wa, rows, s);
+    if (e != hipSuccess) return e;
+    records += rows;
+  }
+  if (records == 0) return hipSuccess;
+  LV_LAUNCH(k_reduce_move_partials, grid_for(records, kBlock, 256), kBlock, 0, s,
+            m.block_partial, records, m.stats);
   return hipGetLastError();
+}
+
+int64_t move_lds_blocks(const Buckets& b, int cls, int hub_first) {
+  int64_t blocks = 0;
+  for (int k = 0; k < kFusedClasses; k++) {
+    const int64_t rpb = bucket_rows_per_block(k);
+    blocks += (b.count[kDegClasses * cls + k] + rpb - 1) / rpb;
+  }
+  for (int k = kFusedClasses; k < hub_first; k++) blocks += b.count[kDegClasses * cls + k];
+  return blocks;
 }
 
 hipError_t move_lds(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
@@ -814,6 +1021,45 @@ __device__ __forceinline__ int64_t find_segment(const int64_t* start, int64_t cn
 
 __device__ __forceinline__ int ilog2_i64(int64_t x) { return 63 - __clzll((long long)x); }
 
+// A block first combines its chunk of a hub row in an LDS table of kHubLds slots (chunks of
+// kHubChunk arcs, so the table is at most half full), then adds each distinct key once to the
+// row's global table; keys new to the global table append their slot to the row's occupied
+// list, one atomic per wavefront.
+constexpr int kHubLds = 2 * (int)kHubChunk;
+constexpr int kHubLdsLog2 = 12;
+static_assert((1 << kHubLdsLog2) == kHubLds, "LDS hub table size");
+
+template <typename V>
+__device__ __forceinline__ void hub_lds_init(int32_t* lk, V* lv) {
+  for (int s = threadIdx.x; s < kHubLds; s += kBlock) {
+    lk[s] = kEmpty;
+    lv[s] = 0;
+  }
+  __syncthreads();
+}
+
+template <typename V>
+__device__ __forceinline__ void hub_flush(const int32_t* lk, const V* lv, int32_t* gk, V* gv,
+                                          int glog2, int32_t* occ, int32_t* occ_count) {
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int base = 0; base < kHubLds; base += kBlock) {
+    const int s = base + threadIdx.x;
+    const int32_t key = lk[s];
+    bool fresh = false;
+    uint32_t slot = 0;
+    if (key != kEmpty) fresh = table_add<V>(gk, gv, glog2, key, lv[s], &slot);
+    const ull mask = __ballot(fresh);
+    if (mask) {
+      const int leader = __ffsll((long long)mask) - 1;
+      int first = 0;
+      if (lane == leader) first = atomicAdd(occ_count, __popcll(mask));
+      first = __shfl(first, leader);
+      if (fresh) occ[first + __popcll(mask & ((1ull << lane) - 1))] = (int32_t)slot;
+    }
+  }
+}
+
 template <typename WT, typename V>
 struct HubArgs {
   const int64_t* off;
@@ -834,12 +1080,14 @@ struct HubArgs {
   int32_t* occ;
   int32_t* occ_count;
   ull* partial;  // 5 words per scan block: gain lo, gain hi, community, kd, candidates
-  int2* movers;
+  int32_t* tgt;
   ull* stats;
 };
 
 template <typename WT, typename V>
 __global__ __launch_bounds__(kBlock) void k_hub_accumulate(HubArgs<WT, V> a) {
+  __shared__ int32_t lk[kHubLds];
+  __shared__ V lv[kHubLds];
   const int64_t b = blockIdx.x;
   const int64_t h = find_segment(a.chunk_start, a.nh, b);
   const int32_t v = a.hubs[h];
@@ -848,18 +1096,13 @@ __global__ __launch_bounds__(kBlock) void k_hub_accumulate(HubArgs<WT, V> a) {
   const int64_t e1 = e0 + kHubChunk < re ? e0 + kHubChunk : re;
   const int64_t ts = a.tab_start[h];
   const int lg = ilog2_i64(a.tab_start[h + 1] - ts);
-  int32_t* keys = a.tkeys + ts;
-  V* vals = a.tvals + ts;
+  hub_lds_init<V>(lk, lv);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
     const int32_t j = ld_stream(a.idx + e);
     const V wv = (V)ld_stream(a.w + e);
-    if (j == v) continue;
-    uint32_t slot;
-    if (table_add<V>(keys, vals, lg, a.C[j], wv, &slot)) {
-      const int p = atomicAdd(&a.occ_count[h], 1);
-      a.occ[ts + p] = (int32_t)slot;
-    }
+    if (j != v) table_add<V>(lk, lv, kHubLdsLog2, a.C[j], wv);
   }
+  hub_flush<V>(lk, lv, a.tkeys + ts, a.tvals + ts, lg, a.occ + ts, a.occ_count + h);
 }
 
 template <bool WIDE, typename WT>
@@ -964,16 +1207,18 @@ __global__ __launch_bounds__(kBlock) void k_hub_decide(HubArgs<WT, typename Gain
       nc += in[4];
     }
     a.occ_count[h] = 0;
+    const int32_t d = a.C[v];
+    int32_t target = d;
     if (bc != INT32_MAX) {
-      const int32_t d = a.C[v];
       const uint64_t Ki = a.K[v];
       const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
       if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
         gain = Ar::diff(bg, stay);
-        const ull p = atomicAdd(&a.stats[2], 1ull);
-        a.movers[p] = make_int2(v, bc);
+        target = bc;
+        atomicAdd(&a.stats[2], 1ull);
       }
     }
+    a.tgt[v] = target;
   }
   const u128 bs = block_sum_u128(gain, red);
   const ull ns = block_sum_u64(nc, red64);
@@ -1021,7 +1266,7 @@ static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, cons
   a.Sig = m.Sig;
   a.csize = m.csize;
   a.W = m.W;
-  a.hubs = m.list + b.lstart[8 * cls + 7];
+  a.hubs = m.list + b.lstart[kDegClasses * cls + m.hub_first];
   a.nh = hp.nh;
   a.chunk_start = hp.chunk_start;
   a.tab_start = hp.tab_start;
@@ -1031,7 +1276,7 @@ static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, cons
   a.occ = m.occ;
   a.occ_count = m.occ_count;
   a.partial = m.partial;
-  a.movers = m.movers;
+  a.tgt = m.tgt;
   a.stats = m.stats;
   LV_LAUNCH((k_hub_accumulate<WT, V>), (unsigned)hp.chunks, kBlock, 0, s, a);
   LV_LAUNCH((k_hub_scan<WIDE, WT>), (unsigned)hp.scan_blocks, kBlock, 0, s, a);
@@ -1049,16 +1294,16 @@ hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const HubPlan
                : move_hubs_t<false, uint32_t>(g, b, cls, hp, m, s);
 }
 
-// Apply the iteration's moves: C, Sigma and csize of the next iteration. Integer atomics
-// commute, so the result is independent of the order of the movers.
-__global__ void k_apply_moves(const int2* movers, const ull* stats, const uint64_t* K,
-                              int32_t* C, uint64_t* Sig, int32_t* csize) {
-  const int64_t m = (int64_t)stats[2];
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+// Apply a class step's decisions: C, Sigma and csize after the step. Integer atomics commute,
+// so the result is independent of the order of the movers.
+__global__ void k_apply_moves(const int32_t* verts, int64_t count, const int32_t* tgt,
+                              const uint64_t* K, int32_t* C, uint64_t* Sig, int32_t* csize) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int2 mv = movers[i];
-    const int32_t v = mv.x, c = mv.y;
+    const int32_t v = verts[i];
+    const int32_t c = tgt[v];
     const int32_t d = C[v];
+    if (c == d) continue;
     const ull k = (ull)K[v];
     C[v] = c;
     atomicAdd((ull*)&Sig[c], k);
@@ -1068,8 +1313,12 @@ __global__ void k_apply_moves(const int2* movers, const ull* stats, const uint64
   }
 }
 
-hipError_t apply_moves(const MoveBuffers& m, hipStream_t s) {
-  LV_LAUNCH(k_apply_moves, 1024, kBlock, 0, s, m.movers, m.stats, m.K, m.C, m.Sig, m.csize);
+hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s) {
+  const int64_t first = b.lstart[kDegClasses * cls];
+  const int64_t count = b.lstart[kDegClasses * cls + kDegClasses] - first;
+  if (count <= 0) return hipSuccess;
+  LV_LAUNCH(k_apply_moves, grid_for(count, kBlock, 8192), kBlock, 0, s, m.list + first, count,
+            m.tgt, m.K, m.C, m.Sig, m.csize);
   return hipGetLastError();
 }
 
@@ -1140,9 +1389,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_arcs(const int64_t* off, int
   int64_t rb = off[r], rend = off[r + 1];
   int64_t base = abase[r];
   for (int64_t e = e0; e < e1; e++) {
-    while (e >= rend) {
-      r++;
-      rb = rend;
+    if (e >= rend) {
+      r = advance_row(off, n, r + 1, e);
+      rb = off[r];
       rend = off[r + 1];
       base = abase[r];
     }
@@ -1175,7 +1424,7 @@ struct MergeArgs {
   int32_t* tkey;
   uint64_t* tw;
   int64_t* dcount;
-  ull* stats;  // [0] += weight of self super-arcs
+  ull* partial;  // per block: weight of its self super-arcs
   const int32_t* list;
   int64_t bstart[8];
   int64_t lstart[8];
@@ -1223,7 +1472,26 @@ __device__ __forceinline__ void merge_group(const MergeArgs& a, int64_t lb, int6
   __syncthreads();
   if (valid && lane == 0) a.dcount[a.newid[c]] = gcount[gid];
   const ull bs = block_sum_u64(self, red);
-  if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = bs;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_sum(const ull* part, int64_t nb, ull* out) {
+  __shared__ ull red[kBlock / 64];
+  ull t = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nb;
+       i += (int64_t)gridDim.x * blockDim.x)
+    t += part[i];
+  t = block_sum_u64(t, red);
+  if (threadIdx.x == 0 && t) atomicAdd(out, t);
+}
+
+int64_t merge_lds_blocks(const Buckets& b) {
+  int64_t blocks = 0;
+  for (int k = 0; k < kFusedClasses; k++) {
+    const int64_t rpb = bucket_rows_per_block(k);
+    blocks += (b.count[k] + rpb - 1) / rpb;
+  }
+  return blocks;
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge_lds(MergeArgs a) {
@@ -1253,11 +1521,11 @@ hipError_t merge_lds(const Buckets& b, const AggBuffers& ag, hipStream_t s) {
   a.tkey = ag.tkey;
   a.tw = ag.tw;
   a.dcount = ag.dcount;
-  a.stats = ag.stats;
+  a.partial = ag.block_partial;
   a.list = ag.list;
   int64_t blocks = 0;
   size_t shm = 0;
-  for (int k = 0; k < 7; k++) {
+  for (int k = 0; k < kFusedClasses; k++) {
     a.bstart[k] = blocks;
     a.lstart[k] = b.lstart[k];
     const int64_t rpb = bucket_rows_per_block(k);
@@ -1271,6 +1539,8 @@ hipError_t merge_lds(const Buckets& b, const AggBuffers& ag, hipStream_t s) {
   a.lstart[7] = b.lstart[7];
   if (blocks == 0) return hipSuccess;
   LV_LAUNCH(k_merge_lds, (unsigned)blocks, kBlock, shm, s, a);
+  LV_LAUNCH(k_reduce_sum, grid_for(blocks, kBlock, 256), kBlock, 0, s, a.partial, blocks,
+            ag.stats);
   return hipGetLastError();
 }
 
@@ -1293,6 +1563,8 @@ struct MergeHubArgs {
 };
 
 __global__ __launch_bounds__(kBlock) void k_merge_hub_accumulate(MergeHubArgs a) {
+  __shared__ int32_t lk[kHubLds];
+  __shared__ ull lv[kHubLds];
   const int64_t b = blockIdx.x;
   const int64_t h = find_segment(a.chunk_start, a.nh, b);
   const int32_t c = a.hubs[h];
@@ -1301,13 +1573,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_hub_accumulate(MergeHubArgs a)
   const int64_t e1 = e0 + kHubChunk < re ? e0 + kHubChunk : re;
   const int64_t ts = a.tab_start[h];
   const int lg = ilog2_i64(a.tab_start[h + 1] - ts);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    uint32_t slot;
-    if (table_add<ull>(a.tkeys + ts, a.tvals + ts, lg, a.tkey[e], a.tw[e], &slot)) {
-      const int p = atomicAdd(&a.occ_count[h], 1);
-      a.occ[ts + p] = (int32_t)slot;
-    }
-  }
+  hub_lds_init<ull>(lk, lv);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock)
+    table_add<ull>(lk, lv, kHubLdsLog2, a.tkey[e], (ull)a.tw[e]);
+  hub_flush<ull>(lk, lv, a.tkeys + ts, a.tvals + ts, lg, a.occ + ts, a.occ_count + h);
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge_hub_emit(MergeHubArgs a) {
@@ -1346,7 +1615,7 @@ hipError_t merge_hubs(const Buckets& b, const HubPlan& hp, const AggBuffers& ag,
   a.tw = ag.tw;
   a.dcount = ag.dcount;
   a.stats = ag.stats;
-  a.hubs = ag.list + b.lstart[7];
+  a.hubs = ag.list + b.lstart[kFusedClasses];
   a.nh = hp.nh;
   a.chunk_start = hp.chunk_start;
   a.tab_start = hp.tab_start;
@@ -1377,9 +1646,9 @@ __global__ __launch_bounds__(kBlock) void k_compact_rows(const int64_t* offp, in
   int64_t rb = offp[r], rend = offp[r + 1];
   int64_t src = astart[oldlabel[r]];
   for (int64_t e = e0; e < e1; e++) {
-    while (e >= rend) {
-      r++;
-      rb = rend;
+    if (e >= rend) {
+      r = advance_row(offp, np, r + 1, e);
+      rb = offp[r];
       rend = offp[r + 1];
       src = astart[oldlabel[r]];
     }

@@ -61,6 +61,8 @@ class LvIterTrace(ctypes.Structure):
         ("iteration", ctypes.c_int32),
         ("wide", ctypes.c_int32),
         ("substeps", ctypes.c_int32),
+        ("lds_launches", ctypes.c_int32),
+        ("hub_launches", ctypes.c_int32),
         ("gain_sum", LvI128),
         ("moved", ctypes.c_int64),
         ("candidates", ctypes.c_int64),
@@ -197,6 +199,7 @@ def result_dict(r: LvResult) -> dict:
         x = r.trace[t]
         tr.append({
             "pass": x.pass_, "iteration": x.iteration, "wide": x.wide, "substeps": x.substeps,
+            "lds_launches": x.lds_launches, "hub_launches": x.hub_launches,
             "S": x.gain_sum.value(), "moved": x.moved, "candidates": x.candidates,
             "lds_vertices": x.lds_vertices, "lds_arcs": x.lds_arcs,
             "hub_vertices": x.hub_vertices, "hub_arcs": x.hub_arcs,
