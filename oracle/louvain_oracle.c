@@ -363,6 +363,11 @@ void orc_async_iteration(int64_t n, const int64_t* off, const int32_t* idx, cons
 /* Aggregation                                                                                 */
 /* ---------------------------------------------------------------------------------------- */
 
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
 /* Collapse each community into a super-vertex (section 3.2's aggregation phase): labels are
  * renumbered by ascending rank among used labels; the super-arc (a, b) weighs the sum of the
  * arcs (i, j) with new ids (a, b), so arcs inside a community become the self-loop of its
@@ -402,14 +407,8 @@ void orc_aggregate(int64_t n, const int64_t* off, const int32_t* idx, const uint
         acc[b] += w[e];
       }
     }
-    /* sort the touched neighbours (insertion into a counting pass over 0..nn-1 would also do;
-       a simple sort keeps this readable) */
-    for (int64_t x = 1; x < nl; x++) {
-      int32_t key = list[x];
-      int64_t y = x - 1;
-      while (y >= 0 && list[y] > key) { list[y + 1] = list[y]; y--; }
-      list[y + 1] = key;
-    }
+    /* emit the neighbours in ascending order */
+    qsort(list, (size_t)nl, sizeof(int32_t), cmp_i32);
     for (int64_t t = 0; t < nl; t++) {
       idx_out[pos] = list[t];
       w_out[pos] = acc[list[t]];

@@ -1,0 +1,167 @@
+"""Parity at the benchmark's full sizes.
+
+* R-MAT scale 25 (1.05e9 arcs, the timed workload): the whole first local-moving iteration of
+  pass 0 (8 class steps) against the oracle, element by element; the modularity of a whole
+  GPU run recomputed by the oracle; aggregation checked on every vertex's map, every
+  super-vertex's degree and total weight, and on sampled super-rows computed by definition.
+* R-MAT scale 22 (1.28e8 arcs): a whole run against the oracle's whole run, and the quality gate
+  against the sequential asynchronous oracle.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from graphgen import config_graph
+
+from .gpu_util import gpu_state
+
+pytestmark = pytest.mark.gpu
+
+K_CLASSES = 8
+
+
+@pytest.fixture(scope="module")
+def lv(gpu_device):
+    from paper_2301_12390_amd import Louvain
+    ctx = Louvain(0)
+    yield ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def rmat25(gpu_device):
+    print("generating rmat25 on the GPU", flush=True)
+    g = config_graph("rmat25", device="cuda:0")
+    og = O.Graph.from_csr(g)
+    yield g, og
+    del g, og
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def rmat25_iter0(rmat25):
+    """Oracle state before and after iteration 0 of pass 0."""
+    g, og = rmat25
+    st0 = O.State(og)
+    st = st0.copy()
+    classes = O.class_lists(og.n, 0, K_CLASSES)
+    print("oracle: iteration 0 of pass 0 on rmat25", flush=True)
+    S, moved, nc = O.substep_iteration(og, st, 0, K_CLASSES, classes)
+    return st0, st, (S, moved, nc)
+
+
+@pytest.mark.timeout(600)
+def test_rmat25_first_iteration_exact(lv, rmat25, rmat25_iter0):
+    g, og = rmat25
+    st0, st, (S, moved, nc) = rmat25_iter0
+    C, Sig, cs, K = gpu_state(st0)
+    stats = lv.move(g, C, Sig, cs, K=K, W=st0.W, max_iterations=1, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    assert stats["last_gain"] == S and stats["last_moved"] == moved
+    assert stats["last_candidates"] == nc
+    assert np.array_equal(C.cpu().numpy(), st.C)
+    assert np.array_equal(Sig.cpu().numpy().view(np.uint64), st.Sig)
+    assert np.array_equal(cs.cpu().numpy(), st.csize)
+
+
+@pytest.mark.timeout(600)
+def test_rmat25_run_modularity_and_labels(lv, rmat25, rmat25_iter0):
+    g, og = rmat25
+    st0, st, (S, moved, _) = rmat25_iter0
+    memb, res = lv.run(g, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    m = memb.cpu().numpy()
+    # the first iteration of the run is the one checked above
+    assert res["trace"][0]["S"] == S and res["trace"][0]["moved"] == moved
+    assert res["W"] == st0.W
+    # labels are dense 0..k-1 and all used
+    k = res["n_communities"]
+    assert m.min() >= 0 and m.max() == k - 1
+    assert np.unique(m).size == k
+    qnum, W, _ = O.modularity(og, m)
+    assert qnum == res["qnum"] and W == res["W"]
+
+
+@pytest.mark.timeout(600)
+def test_rmat25_aggregate(lv, rmat25, rmat25_iter0):
+    g, og = rmat25
+    st0, st, _ = rmat25_iter0
+    C = st.C
+    mp, (n2, off, idx, w) = lv.aggregate(g, torch.from_numpy(C).to("cuda:0"))
+    torch.cuda.synchronize()
+    labels, inv = np.unique(C, return_inverse=True)
+    assert n2 == labels.size
+    assert np.array_equal(mp.cpu().numpy(), inv.astype(np.int32))
+    off = off.cpu().numpy()
+    idx = idx.cpu().numpy()
+    w = w.cpu().numpy().view(np.uint64)
+    # every super-vertex's weighted degree is its community's Sigma, and W is preserved
+    w_ext = np.append(w, np.uint64(0))
+    rowsum = np.add.reduceat(w_ext, off[:-1])
+    empty = off[1:] == off[:-1]
+    rowsum = np.where(empty, np.uint64(0), rowsum)
+    assert np.array_equal(rowsum.astype(np.uint64), st.Sig[labels])
+    assert int(w.sum(dtype=np.uint64)) == st0.W
+    # rows hold distinct neighbours
+    rows = np.repeat(np.arange(n2, dtype=np.int64), np.diff(off))
+    key = rows * n2 + idx
+    assert np.unique(key).size == key.size
+    # sampled super-rows against their definition: sum of w over arcs (i, j) with
+    # map[i] = a, by target map[j]
+    rng = np.random.default_rng(1)
+    deg2 = np.diff(off)
+    big = np.argsort(deg2)[-20:]
+    sample = np.unique(np.concatenate([rng.choice(n2, 200, replace=False), big]))
+    newid = inv.astype(np.int64)
+    members_mask = np.isin(newid, sample)
+    verts = np.nonzero(members_mask)[0]
+    starts, ends = og.off[verts], og.off[verts + 1]
+    lens = ends - starts
+    arc_pos = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + \
+        np.arange(lens.sum())
+    src = np.repeat(newid[verts], lens)
+    dst = newid[og.idx[arc_pos]]
+    wt = og.w[arc_pos]
+    k2 = src * n2 + dst
+    order = np.argsort(k2, kind="stable")
+    k2, wt = k2[order], wt[order]
+    uk, first = np.unique(k2, return_index=True)
+    sums = np.add.reduceat(wt, first)
+    expect = {}
+    for key_, val in zip(uk.tolist(), sums.tolist()):
+        expect.setdefault(key_ // n2, {})[key_ % n2] = val
+    for a in sample.tolist():
+        got = dict(zip(idx[off[a]:off[a + 1]].tolist(), w[off[a]:off[a + 1]].tolist()))
+        assert got == expect.get(a, {}), a
+
+
+@pytest.fixture(scope="module")
+def rmat22(gpu_device):
+    g = config_graph("rmat22", device="cuda:0")
+    return g, O.Graph.from_csr(g)
+
+
+@pytest.mark.timeout(900)
+def test_rmat22_whole_run_exact(lv, rmat22):
+    g, og = rmat22
+    print("oracle: whole synchronous run on rmat22", flush=True)
+    top, ref = O.run(og, "sync", substeps=K_CLASSES)
+    memb, res = lv.run(g, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    assert np.array_equal(memb.cpu().numpy(), top)
+    assert res["qnum"] == ref["qnum"] and res["iterations"] == ref["iterations"]
+    assert [t["S"] for t in res["trace"]] == ref["trace_S"]
+    assert [t["moved"] for t in res["trace"]] == ref["trace_moved"]
+    assert res["qnum_pass"] == ref["qnum_pass"] and res["nnz_pass"] == ref["nnz_pass"]
+
+
+@pytest.mark.timeout(900)
+def test_rmat22_quality_vs_async(lv, rmat22):
+    g, og = rmat22
+    print("oracle: sequential asynchronous run on rmat22", flush=True)
+    _, ra = O.run(og, "async")
+    _, res = lv.run(g, substeps=K_CLASSES)
+    print(f"rmat22: Q gpu {res['q']:.6f}, Q async {ra['q']:.6f}", flush=True)
+    assert res["q"] >= ra["q"] - 0.01
