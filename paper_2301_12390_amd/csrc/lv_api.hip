@@ -22,7 +22,8 @@ enum SlotId {
   S_K, S_SIG, S_CSIZE, S_C, S_MAP, S_MOVERS, S_LIST, S_OFF64, S_STATS, S_COUNTS, S_SCANP,
   S_HUBARR, S_TKEYS, S_TVALS, S_OCC, S_OCCCNT, S_PARTIAL, S_A, S_ASTART, S_NEWID, S_CURSOR,
   S_OLDLABEL, S_DCOUNT, S_ABASE, S_TKEY, S_TW, S_GOFF0, S_GIDX0, S_GW0, S_GOFF1, S_GIDX1, S_GW1,
-  S_BAD, S_AGGOFF, S_BPART, S_MPART, S_COUNT_SLOTS
+  S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
+  S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -189,6 +190,8 @@ lv_status import_graph(lv_ctx* ctx, const lv_graph* g, bool validate, hipStream_
     HIPCHK(lv::widen_offsets((const int32_t*)g->offsets, o, g->n + 1, s));
     out->off = o;
   }
+  out->rs = out->off;
+  out->re = out->off + 1;
   if (validate) {
     unsigned int* bad = nullptr;
     CHK(wst(ctx, S_BAD, 1, &bad));
@@ -249,7 +252,7 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   CHK(wst(ctx, S_LIST, n, &list));
   CHK(wst(ctx, S_COUNTS, 1536, &counts));
   CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &scanp));
-  HIPCHK(lv::bucket_rows(ph.g.off, nullptr, n, K, ph.pass, list, counts,
+  HIPCHK(lv::bucket_rows(ph.g.rs, ph.g.re, nullptr, n, K, ph.pass, list, counts,
                          ctx->pinned + PIN_COUNTS, ph.b, s));
   const int hf = lv::hub_first_class(ctx->max_lds, ph.wide);
   ph.m.hub_first = hf;
@@ -263,7 +266,7 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   int64_t off = 0;
   for (int k = 0; k < K; k++) {
     const int64_t nh = hub_rows(k);
-    HIPCHK(lv::plan_hubs(ph.g.off, nullptr, list + ph.b.lstart[DEG * k + hf], nh, n,
+    HIPCHK(lv::plan_hubs(ph.g.rs, ph.g.re, nullptr, list + ph.b.lstart[DEG * k + hf], nh, n,
                          hubarr + off, scanp, ctx->pinned + PIN_HUB, ph.hp[k], s));
     off += 6 * (nh + 1);
     big.nh = std::max(big.nh, nh);
@@ -419,74 +422,65 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Aggregation of graph g under labels C (csize by label; Sig by label or NULL).
-// Outputs: map[n], off_out[n+1] (int64), idx_out, w_out, Kp[n'] (if Sig), n', nnz', and the
-// weight of the super-graph's self-loops.
+// Aggregation of graph g under labels C (csize by label; Sig by label or NULL). Merged rows go
+// to okey/ow (g.nnz entries) at their community's flat position. Outputs: map[n], Kp[n'] (if
+// Sig), the buffers describing the rows (*out), n', nnz' and the weight of the self super-arcs.
 lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const int32_t* csize,
-                    const uint64_t* Sig, int32_t* map, int64_t* off_out, int32_t* idx_out,
-                    uint64_t* w_out, uint64_t* Kp, int64_t* n_out, int64_t* nnz_out,
-                    uint64_t* self_out, hipStream_t s) {
+                    const uint64_t* Sig, int32_t* map, int32_t* okey, uint64_t* ow, uint64_t* Kp,
+                    lv::AggBuffers* out, int64_t* n_out, int64_t* nnz_out, uint64_t* self_out,
+                    hipStream_t s) {
   const int64_t n = g.n;
   lv::AggBuffers a;
-  CHK(wst(ctx, S_A, n + 1, &a.A));
-  CHK(wst(ctx, S_ASTART, n + 1, &a.astart));
   CHK(wst(ctx, S_NEWID, n + 1, &a.newid));
-  CHK(wst(ctx, S_CURSOR, n + 1, &a.cursor));
+  CHK(wst(ctx, S_MCOUNT, n, &a.mcount));
+  CHK(wst(ctx, S_MSTART, n + 1, &a.mstart));
+  CHK(wst(ctx, S_ASTART, n, &a.astart));
+  CHK(wst(ctx, S_A, n, &a.A));
   CHK(wst(ctx, S_OLDLABEL, n, &a.oldlabel));
   CHK(wst(ctx, S_DCOUNT, n + 1, &a.dcount));
-  CHK(wst(ctx, S_ABASE, n, &a.abase));
-  CHK(wst(ctx, S_TKEY, g.nnz, &a.tkey));
-  CHK(wst(ctx, S_TW, g.nnz, &a.tw));
+  CHK(wst(ctx, S_MEMBERS, n, &a.members));
+  CHK(wst(ctx, S_GSCAN, n + 1, &a.gscan));
   CHK(wst(ctx, S_LIST, n, &a.list));
   CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &a.partial));
   CHK(wst(ctx, S_COUNTS, 1536, &a.counts));
-  CHK(wst(ctx, S_STATS, STATS_WORDS, &a.stats));
-  HIPCHK(lv::scan_flags_pos(csize, n, a.newid, a.partial, s));
-  HIPCHK(lv::label_tables(n, csize, a.newid, Sig, a.oldlabel, Kp, s));
-  HIPCHK(lv::fill_i64(a.A, 0, n + 1, s));
-  HIPCHK(lv::label_arcs(g.off, C, n, a.A, s));
-  HIPCHK(lv::scan_i64(a.A, n, a.astart, a.partial, s));
-  HIPCHK(lv::copy_i64(a.cursor, a.astart, n, s));
-  HIPCHK(lv::vertex_map(g.off, C, n, a.newid, a.cursor, map, a.abase, s));
-  HIPCHK(lv::scatter_arcs(g, map, a.abase, a.tkey, a.tw, s));
-  HIPCHK(lv::fill_i64(a.dcount, 0, n + 1, s));
-  a.stats += ST_MISC + 8;
-  HIPCHK(lv::zero_words(a.stats, 1, s));
+  ull* st = nullptr;
+  CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
+  a.map = map;
+  a.okey = okey;
+  a.ow = ow;
+  a.stats = st + ST_MISC + 8;
+  HIPCHK(lv::zero_words(a.stats, 2, s));
+  HIPCHK(lv::aggregate_prepare(g, C, csize, Sig, Kp, map, a, s));
   lv::Buckets b;
-  HIPCHK(lv::bucket_rows(nullptr, a.A, n, 1, 0, a.list, a.counts, ctx->pinned + PIN_COUNTS, b,
-                         s));
+  HIPCHK(lv::bucket_rows(nullptr, nullptr, a.A, n, 1, 0, a.list, a.counts,
+                         ctx->pinned + PIN_COUNTS, b, s));
   // the super-vertex count bounds the distinct targets of any community
   ull* hm = ctx->pinned + PIN_MISC;
   HIPCHK(hipMemcpyAsync(hm, a.newid + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const int64_t np = (int64_t)hm[0];
+  HIPCHK(lv::fill_i64(a.dcount, 0, np + 1, s));
   CHK(wst(ctx, S_MPART, lv::merge_lds_blocks(b), &a.block_partial));
-  HIPCHK(lv::merge_lds(b, a, s));
+  HIPCHK(lv::merge_lds(g, b, a, s));
   const int64_t nh = b.lstart[DEG] - b.lstart[7];  // communities of more than 1024 arcs
   if (nh > 0) {
     lv::HubPlan hp;
     CHK(wst(ctx, S_HUBARR, 6 * (nh + 1), &a.hub_arrays));
-    HIPCHK(lv::plan_hubs(nullptr, a.A, a.list + b.lstart[7], nh, np, a.hub_arrays, a.partial,
-                         ctx->pinned + PIN_HUB, hp, s));
+    HIPCHK(lv::plan_hubs(nullptr, nullptr, a.A, a.list + b.lstart[7], nh, np, a.hub_arrays,
+                         a.partial, ctx->pinned + PIN_HUB, hp, s));
     CHK(wst(ctx, S_TKEYS, hp.slots, &a.tkeys));
-    ull* tv = nullptr;
-    CHK(wst(ctx, S_TVALS, hp.slots, &tv));
-    a.tvals = tv;
+    CHK(wst(ctx, S_TVALS, hp.slots, &a.tvals));
     CHK(wst(ctx, S_OCC, hp.slots, &a.occ));
     CHK(wst(ctx, S_OCCCNT, nh, &a.occ_count));
-    HIPCHK(lv::merge_hubs(b, hp, a, s));
+    HIPCHK(lv::merge_hubs(g, b, hp, a, s));
   }
-  HIPCHK(lv::scan_i64(a.dcount, np, off_out, a.partial, s));
-  HIPCHK(hipMemcpyAsync(hm, off_out + np, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hm + 1, a.stats, sizeof(ull), hipMemcpyDeviceToHost, s));
+  HIPCHK(lv::sum_i64(a.dcount, np, a.stats + 1, s));
+  HIPCHK(hipMemcpyAsync(hm, a.stats, 2 * sizeof(ull), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const int64_t nnzp = (int64_t)hm[0];
-  const uint64_t self = hm[1];
-  HIPCHK(lv::compact_rows(off_out, np, nnzp, a.oldlabel, a.astart, a.tkey, a.tw, idx_out, w_out,
-                          s));
   *n_out = np;
-  *nnz_out = nnzp;
-  if (self_out) *self_out = self;
+  *nnz_out = (int64_t)hm[1];
+  if (self_out) *self_out = hm[0];
+  *out = a;
   return LV_OK;
 }
 
@@ -663,15 +657,22 @@ lv_status louvain_aggregate(lv_ctx* ctx, const lv_graph* g, const int32_t* C, in
   CHK(wst(ctx, S_CSIZE, dg.n, &csize));
   HIPCHK(lv::fill_i32(csize, 0, dg.n, s));
   HIPCHK(lv::count_labels(C, dg.n, csize, s));
+  int32_t* okey = nullptr;
+  uint64_t* ow = nullptr;
+  CHK(wst(ctx, S_TKEY, dg.nnz, &okey));
+  CHK(wst(ctx, S_TW, dg.nnz, &ow));
   int64_t* off64 = nullptr;
   if (offsets_64_out) {
     off64 = (int64_t*)offsets_out;
   } else {
     CHK(wst(ctx, S_AGGOFF, dg.n + 1, &off64));
   }
+  lv::AggBuffers a;
   int64_t np = 0, nnzp = 0;
-  CHK(aggregate(ctx, dg, C, csize, nullptr, map, off64, indices_out, weights_out, nullptr, &np,
-                &nnzp, nullptr, s));
+  CHK(aggregate(ctx, dg, C, csize, nullptr, map, okey, ow, nullptr, &a, &np, &nnzp, nullptr, s));
+  HIPCHK(lv::scan_i64(a.dcount, np, off64, a.partial, s));
+  HIPCHK(lv::compact_rows(off64, np, nnzp, a.oldlabel, a.astart, okey, ow, indices_out,
+                          weights_out, s));
   if (!offsets_64_out) HIPCHK(lv::narrow_offsets(off64, (int32_t*)offsets_out, np + 1, s));
   HIPCHK(hipStreamSynchronize(s));
   *n_out = np;
@@ -757,18 +758,21 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
       res->qnum_pass[pass] = to_i128(qnum);
       break;
     }
-    // aggregation into the other buffer set
-    int64_t* noff = nullptr;
+    // aggregation into the other buffer set: rows stay where the merge writes them
+    int64_t* nrs = nullptr;
+    int64_t* nre = nullptr;
     int32_t* nidx = nullptr;
-    ull* nw = nullptr;
-    CHK(wst(ctx, which ? S_GOFF1 : S_GOFF0, cur.n + 1, &noff));
+    uint64_t* nw = nullptr;
+    CHK(wst(ctx, which ? S_GOFF1 : S_GOFF0, cur.n, &nrs));
+    CHK(wst(ctx, which ? S_GRE1 : S_GRE0, cur.n, &nre));
     CHK(wst(ctx, which ? S_GIDX1 : S_GIDX0, cur.nnz, &nidx));
     CHK(wst(ctx, which ? S_GW1 : S_GW0, cur.nnz, &nw));
     if (trace) HIPCHK(hipEventRecord(ctx->ev[EV_AGG], s));
     int64_t np = 0, nnzp = 0;
     uint64_t self = 0;
-    CHK(aggregate(ctx, cur, C, csize, Sig, map, noff, nidx, (uint64_t*)nw, K, &np, &nnzp, &self,
-                  s));
+    lv::AggBuffers ab;
+    CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s));
+    HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
     HIPCHK(lv::compose_membership(membership, n0, map, s));
     if (trace) {
       HIPCHK(hipEventRecord(ctx->ev[EV_AGG + 1], s));
@@ -794,7 +798,9 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
     lv::DevGraph nxt;
     nxt.n = np;
     nxt.nnz = nnzp;
-    nxt.off = noff;
+    nxt.rs = nrs;
+    nxt.re = nre;
+    nxt.off = nullptr;
     nxt.idx = nidx;
     nxt.w = nw;
     nxt.w64 = true;

@@ -6,10 +6,14 @@
 
 namespace lv {
 
-// A CSR on the device with int64 offsets (int32 inputs are widened once per call).
+// A graph on the device: row v spans arcs [rs[v], re[v]) of idx/w. For a CSR, rs = off and
+// re = off + 1 (off has n+1 int64 entries; int32 inputs are widened once per call) and `off`
+// is set; super-vertex graphs keep rows where the aggregation wrote them (off is null).
 struct DevGraph {
-  int64_t n = 0, nnz = 0;
-  const int64_t* off = nullptr;
+  int64_t n = 0, nnz = 0;          // vertices, arcs
+  const int64_t* rs = nullptr;
+  const int64_t* re = nullptr;
+  const int64_t* off = nullptr;    // contiguous CSR offsets, or null
   const int32_t* idx = nullptr;
   const void* w = nullptr;
   bool w64 = false;  // weights are uint64 (else uint32)
@@ -65,14 +69,14 @@ hipError_t init_state(int64_t n, const uint64_t* K, int32_t* C, uint64_t* Sig, i
 // Classify rows (lengths from offsets, or from `len` if non-null over m items) by vertex
 // class (K classes of pass `pass`) and degree class. counts: device scratch of 1536 words;
 // host_counts: 1536 pinned words. Host result in `b` (synchronises the stream).
-hipError_t bucket_rows(const int64_t* off, const int64_t* len, int64_t m, int K, int pass,
-                       int32_t* list, unsigned long long* counts,
+hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
+                       int K, int pass, int32_t* list, unsigned long long* counts,
                        unsigned long long* host_counts, Buckets& b, hipStream_t s);
 // Hub decomposition of the rows hubs[0 .. nh) whose keys take at most `cap` distinct values.
 // arrays: 6 * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.
-hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs, int64_t nh,
-                     int64_t cap, int64_t* arrays, int64_t* partial,
-                     unsigned long long* host_buf, HubPlan& hp, hipStream_t s);
+hipError_t plan_hubs(const int64_t* rs, const int64_t* re, const int64_t* len,
+                     const int32_t* hubs, int64_t nh, int64_t cap, int64_t* arrays,
+                     int64_t* partial, unsigned long long* host_buf, HubPlan& hp, hipStream_t s);
 
 // ---- local-moving iteration
 struct MoveBuffers {
@@ -120,38 +124,44 @@ hipError_t count_labels(const int32_t* C, int64_t n, int32_t* csize, hipStream_t
 
 // ---- aggregation
 struct AggBuffers {
-  // per label (n entries unless noted)
-  int64_t* A = nullptr;        // arcs per label [n+1] (scanned in place to starts)
-  int64_t* astart = nullptr;   // [n+1]
+  // per label (n entries, +1 where noted)
   int64_t* newid = nullptr;    // [n+1] exclusive rank of used labels
-  int64_t* cursor = nullptr;   // [n]
+  int32_t* mcount = nullptr;   // [n] members with arcs, then fill cursors
+  int64_t* mstart = nullptr;   // [n+1] first member slot per label
+  int64_t* astart = nullptr;   // [n] first flat arc per label
+  int64_t* A = nullptr;        // [n] arcs per label
   int32_t* oldlabel = nullptr; // [n] label of each new id
-  int64_t* dcount = nullptr;   // [n+1] distinct neighbours per new id, scanned to offsets
-  int64_t* abase = nullptr;    // [n] per vertex
-  int32_t* tkey = nullptr;     // [nnz]
-  uint64_t* tw = nullptr;      // [nnz]
+  int64_t* dcount = nullptr;   // [n+1] distinct targets per new id
+  // per member slot / vertex
+  int32_t* members = nullptr;  // [n] vertices with arcs, grouped by label
+  int64_t* gscan = nullptr;    // [n+1] first flat arc of each member slot
+  int32_t* map = nullptr;      // [n] new id of each vertex
+  // output rows (at astart[c] for community c) and scratch
+  int32_t* okey = nullptr;     // [nnz]
+  uint64_t* ow = nullptr;      // [nnz]
   int32_t* list = nullptr;     // [n]
   int64_t* partial = nullptr;  // scan scratch
-  unsigned long long* counts = nullptr;  // 32 words
-  unsigned long long* stats = nullptr;   // [0] self-loop weight total
+  unsigned long long* counts = nullptr;  // 1536 words
+  unsigned long long* stats = nullptr;   // [0] weight of self super-arcs
   unsigned long long* block_partial = nullptr;  // 1 word per block of the LDS merge kernel
   int64_t* hub_arrays = nullptr;         // 6 * (hubs + 1)
-  int32_t* tkeys = nullptr;              // global tables (sized by caller from plan)
+  int32_t* tkeys = nullptr;              // global tables (sized from the hub plan)
   unsigned long long* tvals = nullptr;
   int32_t* occ = nullptr;
-  int32_t* occ_count = nullptr;          // [n]
+  int32_t* occ_count = nullptr;
 };
-hipError_t label_arcs(const int64_t* off, const int32_t* C, int64_t n, int64_t* A,
-                      hipStream_t s);
-hipError_t label_tables(int64_t n, const int32_t* csize, const int64_t* newid,
-                        const uint64_t* Sig, int32_t* oldlabel, uint64_t* Kp, hipStream_t s);
-hipError_t vertex_map(const int64_t* off, const int32_t* C, int64_t n, const int64_t* newid,
-                      int64_t* cursor, int32_t* map, int64_t* abase, hipStream_t s);
-hipError_t scatter_arcs(const DevGraph& g, const int32_t* map, const int64_t* abase,
-                        int32_t* tkey, uint64_t* tw, hipStream_t s);
-hipError_t merge_lds(const Buckets& b, const AggBuffers& a, hipStream_t s);
+// Renumbering, member lists and flat arc ranges (everything before the merge).
+hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t* csize,
+                             const uint64_t* Sig, uint64_t* Kp, int32_t* map,
+                             const AggBuffers& a, hipStream_t s);
+hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& a, hipStream_t s);
 int64_t merge_lds_blocks(const Buckets& b);  // sizes block_partial
-hipError_t merge_hubs(const Buckets& b, const HubPlan& hp, const AggBuffers& a, hipStream_t s);
+hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const HubPlan& hp,
+                      const AggBuffers& a, hipStream_t s);
+// rs[a], re[a] of the super-vertex graph's rows in okey/ow
+hipError_t super_rows(int64_t np, const AggBuffers& a, int64_t* rs, int64_t* re, hipStream_t s);
+hipError_t sum_i64(const int64_t* a, int64_t n, unsigned long long* out, hipStream_t s);
+// Gather gapped rows (row a at astart[oldlabel[a]], length offp[a+1]-offp[a]) into a CSR.
 hipError_t compact_rows(const int64_t* offp, int64_t np, int64_t nnzp, const int32_t* oldlabel,
                         const int64_t* astart, const int32_t* tkey, const uint64_t* tw,
                         int32_t* idx_out, uint64_t* w_out, hipStream_t s);

@@ -204,6 +204,22 @@ struct ReadPos {
   const int32_t* a;
   __device__ int64_t operator()(int64_t i) const { return a[i] > 0 ? 1 : 0; }
 };
+struct ReadI32 {
+  const int32_t* a;
+  __device__ int64_t operator()(int64_t i) const { return (int64_t)a[i]; }
+};
+// Degree of the member in slot p, 0 past the last member (*count slots are filled).
+struct ReadMemberDegGuard {
+  const int32_t* members;
+  const int64_t* rs;
+  const int64_t* re;
+  const int64_t* count;
+  __device__ int64_t operator()(int64_t p) const {
+    if (p >= *count) return 0;
+    const int32_t v = members[p];
+    return re[v] - rs[v];
+  }
+};
 
 template <typename F>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(F f, int64_t n, int64_t* partial) {
@@ -432,8 +448,9 @@ hipError_t init_state(int64_t n, const uint64_t* K, int32_t* C, uint64_t* Sig, i
 // Degree classes. Items with length 0 (isolated vertices, empty communities) are skipped: an
 // isolated vertex has no neighbour community to move to.
 
-__device__ __forceinline__ int64_t item_len(const int64_t* off, const int64_t* len, int64_t i) {
-  return len ? len[i] : off[i + 1] - off[i];
+__device__ __forceinline__ int64_t item_len(const int64_t* rs, const int64_t* re,
+                                            const int64_t* len, int64_t i) {
+  return len ? len[i] : re[i] - rs[i];
 }
 
 // Segment of item i: kDegClasses * (vertex class) + degree class.
@@ -445,15 +462,16 @@ __device__ __forceinline__ int segment_of(int64_t L, int K, int pass, int64_t i)
 }
 
 // counts[0 .. nseg): items per segment, counts[kMaxSeg .. kMaxSeg + nseg): total length.
-__global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* off, const int64_t* len,
-                                                        int64_t m, int K, int pass, ull* counts) {
+__global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, const int64_t* re,
+                                                        const int64_t* len, int64_t m, int K,
+                                                        int pass, ull* counts) {
   __shared__ ull c[2 * kMaxSeg];
   const int nseg = kDegClasses * K;
   for (int t = threadIdx.x; t < 2 * kMaxSeg; t += blockDim.x) c[t] = 0;
   __syncthreads();
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t L = item_len(off, len, i);
+    const int64_t L = item_len(rs, re, len, i);
     if (L > 0) {
       const int sg = segment_of(L, K, pass, i);
       atomicAdd(&c[sg], 1ull);
@@ -468,9 +486,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* off, con
 }
 
 // starts: first list position per segment; cursor: per-segment fill counters (zero).
-__global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* off, const int64_t* len,
-                                                       int64_t m, int K, int pass,
-                                                       const ull* starts, ull* cursor,
+__global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const int64_t* re,
+                                                       const int64_t* len, int64_t m, int K,
+                                                       int pass, const ull* starts, ull* cursor,
                                                        int32_t* list) {
   __shared__ int cnt[kMaxSeg];
   __shared__ ull base[kMaxSeg];
@@ -482,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* off, cons
     const int64_t i = tile + threadIdx.x;
     int sg = -1, rank = 0;
     if (i < m) {
-      const int64_t L = item_len(off, len, i);
+      const int64_t L = item_len(rs, re, len, i);
       if (L > 0) {
         sg = segment_of(L, K, pass, i);
         rank = atomicAdd(&cnt[sg], 1);
@@ -497,15 +515,17 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* off, cons
   }
 }
 
-hipError_t bucket_rows(const int64_t* off, const int64_t* len, int64_t m, int K, int pass,
-                       int32_t* list, ull* counts, ull* host_counts, Buckets& b, hipStream_t s) {
+hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
+                       int K, int pass, int32_t* list, ull* counts, ull* host_counts, Buckets& b,
+                       hipStream_t s) {
   b = Buckets();
   b.classes = K;
   if (m <= 0) return hipSuccess;
   const int nseg = kDegClasses * K;
   // counts layout (kMaxSeg words each): items, lengths, fill cursors, segment starts
   LV_LAUNCH(k_zero_words, 8, kBlock, 0, s, counts, (int64_t)(3 * kMaxSeg));
-  LV_LAUNCH(k_bucket_count, grid_for(m, kBlock, 4096), kBlock, 0, s, off, len, m, K, pass, counts);
+  LV_LAUNCH(k_bucket_count, grid_for(m, kBlock, 4096), kBlock, 0, s, rs, re, len, m, K, pass,
+            counts);
   hipError_t e = hipMemcpyAsync(host_counts, counts, 2 * kMaxSeg * sizeof(ull),
                                 hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
@@ -524,7 +544,7 @@ hipError_t bucket_rows(const int64_t* off, const int64_t* len, int64_t m, int K,
   e = hipMemcpyAsync(counts + 3 * kMaxSeg, hstarts, nseg * sizeof(ull), hipMemcpyHostToDevice,
                      s);
   if (e != hipSuccess) return e;
-  LV_LAUNCH(k_bucket_fill, grid_for(m, kBlock, 8192), kBlock, 0, s, off, len, m, K, pass,
+  LV_LAUNCH(k_bucket_fill, grid_for(m, kBlock, 8192), kBlock, 0, s, rs, re, len, m, K, pass,
             counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
   return hipGetLastError();
 }
@@ -533,12 +553,12 @@ hipError_t bucket_rows(const int64_t* off, const int64_t* len, int64_t m, int K,
 // chunk_start/tab_start/scan_start which overwrite... (separate outputs of nh+1 each).
 // Per hub row of length L whose keys take at most `cap` distinct values: accumulation chunks,
 // a power-of-two table of at least 2 * min(L, cap) slots, and scan blocks for its occupied list.
-__global__ void k_hub_sizes(const int64_t* off, const int64_t* len, const int32_t* hubs,
-                            int64_t nh, int64_t cap, int64_t* nchunk, int64_t* tsize,
-                            int64_t* nscan) {
+__global__ void k_hub_sizes(const int64_t* rs, const int64_t* re, const int64_t* len,
+                            const int32_t* hubs, int64_t nh, int64_t cap, int64_t* nchunk,
+                            int64_t* tsize, int64_t* nscan) {
   for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < nh;
        h += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t L = item_len(off, len, hubs[h]);
+    const int64_t L = item_len(rs, re, len, hubs[h]);
     const int64_t D = L < cap ? L : cap;
     nchunk[h] = (L + kHubChunk - 1) / kHubChunk;
     int64_t t = 1;
@@ -548,9 +568,9 @@ __global__ void k_hub_sizes(const int64_t* off, const int64_t* len, const int32_
   }
 }
 
-hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs, int64_t nh,
-                     int64_t cap, int64_t* arrays, int64_t* partial, ull* host_buf, HubPlan& hp,
-                     hipStream_t s) {
+hipError_t plan_hubs(const int64_t* rs, const int64_t* re, const int64_t* len,
+                     const int32_t* hubs, int64_t nh, int64_t cap, int64_t* arrays,
+                     int64_t* partial, ull* host_buf, HubPlan& hp, hipStream_t s) {
   hp = HubPlan();
   hp.nh = nh;
   if (nh <= 0) return hipSuccess;
@@ -561,7 +581,7 @@ hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs
   hp.chunk_start = arrays + 3 * nh;
   hp.tab_start = hp.chunk_start + (nh + 1);
   hp.scan_start = hp.tab_start + (nh + 1);
-  LV_LAUNCH(k_hub_sizes, grid_for(nh), kBlock, 0, s, off, len, hubs, nh, cap, nchunk, tsize,
+  LV_LAUNCH(k_hub_sizes, grid_for(nh), kBlock, 0, s, rs, re, len, hubs, nh, cap, nchunk, tsize,
             nscan);
   hipError_t e;
   if ((e = scan_i64(nchunk, nh, hp.chunk_start, partial, s)) != hipSuccess) return e;
@@ -593,7 +613,8 @@ hipError_t plan_hubs(const int64_t* off, const int64_t* len, const int32_t* hubs
 
 template <typename WT>
 struct MoveArgs {
-  const int64_t* off;
+  const int64_t* rs;
+  const int64_t* re;
   const int32_t* idx;
   const WT* w;
   const uint64_t* K;
@@ -640,8 +661,8 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
   __syncthreads();
   int64_t e0 = 0, e1 = 0;
   if (valid) {
-    e0 = a.off[v];
-    e1 = a.off[v + 1];
+    e0 = a.rs[v];
+    e1 = a.re[v];
   }
   for (int64_t e = e0 + lane; e < e1; e += G) {
     const int32_t j = ld_stream(a.idx + e);
@@ -790,7 +811,8 @@ constexpr int kWgBlock = 1024;
 
 template <typename WT>
 struct WgArgs {
-  const int64_t* off;
+  const int64_t* rs;
+  const int64_t* re;
   const int32_t* idx;
   const WT* w;
   const uint64_t* K;
@@ -823,7 +845,7 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
     vals[s] = 0;
   }
   __syncthreads();
-  const int64_t e0 = a.off[v], e1 = a.off[v + 1];
+  const int64_t e0 = a.rs[v], e1 = a.re[v];
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kWgBlock) {
     const int32_t j = ld_stream(a.idx + e);
     const V wv = (V)ld_stream(a.w + e);
@@ -929,7 +951,8 @@ template <bool WIDE, typename WT>
 static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
                              hipStream_t s) {
   MoveArgs<WT> a;
-  a.off = g.off;
+  a.rs = g.rs;
+  a.re = g.re;
   a.idx = g.idx;
   a.w = (const WT*)g.w;
   a.K = m.K;
@@ -958,7 +981,8 @@ static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const
   if (blocks > 0) LV_LAUNCH((k_move_lds<WIDE, WT>), (unsigned)blocks, kBlock, shm, s, a);
   int64_t records = blocks;
   WgArgs<WT> wa;
-  wa.off = g.off;
+  wa.rs = g.rs;
+  wa.re = g.re;
   wa.idx = g.idx;
   wa.w = (const WT*)g.w;
   wa.K = m.K;
@@ -1062,7 +1086,8 @@ __device__ __forceinline__ void hub_flush(const int32_t* lk, const V* lv, int32_
 
 template <typename WT, typename V>
 struct HubArgs {
-  const int64_t* off;
+  const int64_t* rs;
+  const int64_t* re;
   const int32_t* idx;
   const WT* w;
   const uint64_t* K;
@@ -1091,9 +1116,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_accumulate(HubArgs<WT, V> a) {
   const int64_t b = blockIdx.x;
   const int64_t h = find_segment(a.chunk_start, a.nh, b);
   const int32_t v = a.hubs[h];
-  const int64_t rb = a.off[v], re = a.off[v + 1];
+  const int64_t rb = a.rs[v], rend = a.re[v];
   const int64_t e0 = rb + (b - a.chunk_start[h]) * kHubChunk;
-  const int64_t e1 = e0 + kHubChunk < re ? e0 + kHubChunk : re;
+  const int64_t e1 = e0 + kHubChunk < rend ? e0 + kHubChunk : rend;
   const int64_t ts = a.tab_start[h];
   const int lg = ilog2_i64(a.tab_start[h + 1] - ts);
   hub_lds_init<V>(lk, lv);
@@ -1258,7 +1283,8 @@ static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, cons
                               const MoveBuffers& m, hipStream_t s) {
   typedef typename Gain<WIDE>::V V;
   HubArgs<WT, V> a;
-  a.off = g.off;
+  a.rs = g.rs;
+  a.re = g.re;
   a.idx = g.idx;
   a.w = (const WT*)g.w;
   a.K = m.K;
@@ -1324,25 +1350,46 @@ hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStrea
 
 // =============================================================================================
 // Aggregation (section 3.2): communities -> super-vertices.
+//
+// Used labels are renumbered by rank (scan of csize > 0). The vertices of each community that
+// have arcs are listed contiguously (counting sort by label), and an exclusive scan of their
+// degrees in that order gives every community a flat arc range [astart[c], astart[c] + A[c]) and
+// every member the flat index of its first arc. A group (or, for communities of more than 1024
+// arcs, a set of blocks) walks the community's flat range, reads each arc from its member's row,
+// and combines the arcs by target super-vertex in an open-addressing table. The distinct
+// (target, summed weight) pairs are written to the front of the community's range in the
+// output arrays: the super-vertex graph keeps the rows where they were produced (row a spans
+// [rs[a], re[a]) of those arrays), so no compaction pass is needed between passes.
 
-__global__ void k_label_arcs(const int64_t* off, const int32_t* C, int64_t n, int64_t* A) {
+// Vertices with arcs per label.
+__global__ void k_count_members(const int64_t* rs, const int64_t* re, const int32_t* C,
+                                int64_t n, int32_t* mcount) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (re[i] > rs[i]) atomicAdd(&mcount[C[i]], 1);
+}
+
+// map[v] = new id of v's community; members with arcs placed in their community's slot range.
+__global__ void k_fill_members(const int64_t* rs, const int64_t* re, const int32_t* C, int64_t n,
+                               const int64_t* newid, const int64_t* mstart, int32_t* mcur,
+                               int32_t* map, int32_t* members) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t L = off[i + 1] - off[i];
-    if (L) atomicAdd((ull*)&A[C[i]], (ull)L);
+    const int32_t c = C[i];
+    map[i] = (int32_t)newid[c];
+    if (re[i] > rs[i]) members[mstart[c] + atomicAdd(&mcur[c], 1)] = (int32_t)i;
   }
 }
-hipError_t label_arcs(const int64_t* off, const int32_t* C, int64_t n, int64_t* A,
-                      hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  LV_LAUNCH(k_label_arcs, grid_for(n), kBlock, 0, s, off, C, n, A);
-  return hipGetLastError();
-}
 
-__global__ void k_label_tables(int64_t n, const int32_t* csize, const int64_t* newid,
-                               const uint64_t* Sig, int32_t* oldlabel, uint64_t* Kp) {
+// Per used label: its new id's tables, its flat arc range and arc count.
+__global__ void k_label_ranges(int64_t n, const int32_t* csize, const int64_t* newid,
+                               const int64_t* mstart, const int64_t* gscan, const uint64_t* Sig,
+                               int32_t* oldlabel, uint64_t* Kp, int64_t* astart, int64_t* A) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a0 = gscan[mstart[c]];
+    astart[c] = a0;
+    A[c] = gscan[mstart[c + 1]] - a0;
     if (csize[c] > 0) {
       const int64_t a = newid[c];
       oldlabel[a] = (int32_t)c;
@@ -1350,112 +1397,105 @@ __global__ void k_label_tables(int64_t n, const int32_t* csize, const int64_t* n
     }
   }
 }
-hipError_t label_tables(int64_t n, const int32_t* csize, const int64_t* newid,
-                        const uint64_t* Sig, int32_t* oldlabel, uint64_t* Kp, hipStream_t s) {
+
+hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t* csize,
+                             const uint64_t* Sig, uint64_t* Kp, int32_t* map,
+                             const AggBuffers& a, hipStream_t s) {
+  const int64_t n = g.n;
   if (n <= 0) return hipSuccess;
-  LV_LAUNCH(k_label_tables, grid_for(n), kBlock, 0, s, n, csize, newid, Sig, oldlabel, Kp);
+  hipError_t e;
+  if ((e = scan_flags_pos(csize, n, a.newid, a.partial, s)) != hipSuccess) return e;
+  LV_LAUNCH(k_fill_i32, grid_for(n), kBlock, 0, s, a.mcount, 0, n);
+  LV_LAUNCH(k_count_members, grid_for(n), kBlock, 0, s, g.rs, g.re, C, n, a.mcount);
+  if ((e = scan_impl(ReadI32{a.mcount}, n, a.mstart, a.partial, s)) != hipSuccess) return e;
+  LV_LAUNCH(k_fill_i32, grid_for(n), kBlock, 0, s, a.mcount, 0, n);  // reused as cursors
+  LV_LAUNCH(k_fill_members, grid_for(n), kBlock, 0, s, g.rs, g.re, C, n, a.newid, a.mstart,
+            a.mcount, map, a.members);
+  // members occupy mstart[n] slots; gscan over them (mstart[n] + 1 entries)
+  // the number of members is only known on the device: scan over n slots, the tail past
+  // mstart[n] reads members left from before and is never used
+  if ((e = scan_impl(ReadMemberDegGuard{a.members, g.rs, g.re, a.mstart + n}, n, a.gscan,
+                     a.partial, s)) != hipSuccess)
+    return e;
+  LV_LAUNCH(k_label_ranges, grid_for(n), kBlock, 0, s, n, csize, a.newid, a.mstart, a.gscan,
+            Sig, a.oldlabel, Kp, a.astart, a.A);
   return hipGetLastError();
 }
 
-__global__ void k_vertex_map(const int64_t* off, const int32_t* C, int64_t n,
-                             const int64_t* newid, int64_t* cursor, int32_t* map,
-                             int64_t* abase) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = C[i];
-    map[i] = (int32_t)newid[c];
-    const int64_t L = off[i + 1] - off[i];
-    abase[i] = L ? (int64_t)atomicAdd((ull*)&cursor[c], (ull)L) : 0;
+// Largest member index i in [0, mc) with start[i] <= t (start[0] = 0 <= t).
+template <typename T>
+__device__ __forceinline__ int member_at(const T* start, int mc, int64_t t) {
+  int lo = 0, hi = mc;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)start[mid] <= t) lo = mid; else hi = mid;
   }
-}
-hipError_t vertex_map(const int64_t* off, const int32_t* C, int64_t n, const int64_t* newid,
-                      int64_t* cursor, int32_t* map, int64_t* abase, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  LV_LAUNCH(k_vertex_map, grid_for(n), kBlock, 0, s, off, C, n, newid, cursor, map, abase);
-  return hipGetLastError();
+  return lo;
 }
 
 template <typename WT>
-__global__ __launch_bounds__(kBlock) void k_scatter_arcs(const int64_t* off, int64_t n,
-                                                        int64_t nnz, const int32_t* idx,
-                                                        const WT* w, const int32_t* map,
-                                                        const int64_t* abase, int32_t* tkey,
-                                                        uint64_t* tw) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t e0 = t * kSeg;
-  if (e0 >= nnz) return;
-  const int64_t e1 = e0 + kSeg < nnz ? e0 + kSeg : nnz;
-  int64_t r = row_of_arc(off, n, e0);
-  int64_t rb = off[r], rend = off[r + 1];
-  int64_t base = abase[r];
-  for (int64_t e = e0; e < e1; e++) {
-    if (e >= rend) {
-      r = advance_row(off, n, r + 1, e);
-      rb = off[r];
-      rend = off[r + 1];
-      base = abase[r];
-    }
-    const int64_t dst = base + (e - rb);
-    tkey[dst] = map[idx[e]];
-    tw[dst] = (uint64_t)w[e];
-  }
-}
-hipError_t scatter_arcs(const DevGraph& g, const int32_t* map, const int64_t* abase,
-                        int32_t* tkey, uint64_t* tw, hipStream_t s) {
-  if (g.nnz <= 0) return hipSuccess;
-  const int64_t threads = (g.nnz + kSeg - 1) / kSeg;
-  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
-  if (g.w64)
-    LV_LAUNCH(k_scatter_arcs<uint64_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
-              (const uint64_t*)g.w, map, abase, tkey, tw);
-  else
-    LV_LAUNCH(k_scatter_arcs<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
-              (const uint32_t*)g.w, map, abase, tkey, tw);
-  return hipGetLastError();
-}
-
-// Merge: the arcs of each community (contiguous in tkey/tw, range astart[c]..astart[c+1])
-// are combined by target super-vertex in an LDS table (communities of up to 1024 arcs) or a
-// global table (larger ones); the distinct (target, summed weight) pairs are written back to
-// the front of the community's range, and their count to dcount[newid[c]].
 struct MergeArgs {
+  const int64_t* rs;
+  const int32_t* idx;
+  const WT* w;
+  const int32_t* map;
+  const int32_t* members;
+  const int64_t* mstart;
+  const int64_t* gscan;
   const int64_t* astart;
+  const int64_t* A;
   const int64_t* newid;
-  int32_t* tkey;
-  uint64_t* tw;
-  int64_t* dcount;
-  ull* partial;  // per block: weight of its self super-arcs
+  int32_t* okey;     // output arrays: row of community c at astart[c]
+  uint64_t* ow;
+  int64_t* dcount;   // distinct targets per new id
+  ull* partial;      // per block: weight of its self super-arcs
   const int32_t* list;
   int64_t bstart[8];
   int64_t lstart[8];
 };
 
-template <int G, int LOG2H>
-__device__ __forceinline__ void merge_group(const MergeArgs& a, int64_t lb, int64_t lbase,
+template <typename WT, int G, int LOG2H>
+__device__ __forceinline__ void merge_group(const MergeArgs<WT>& a, int64_t lb, int64_t lbase,
                                             int64_t lcount, unsigned char* smem, int* gcount,
                                             ull* red) {
   constexpr int H = 1 << LOG2H;
+  constexpr int M = H / 2;  // members <= arcs <= H/2
   constexpr int NG = kBlock / G;
   int32_t* keys = (int32_t*)smem;
   ull* vals = (ull*)(smem + (size_t)NG * H * sizeof(int32_t));
+  int32_t* mvert = (int32_t*)(smem + (size_t)NG * H * (sizeof(int32_t) + sizeof(ull)));
+  int32_t* mfirst = mvert + NG * M;
   const int gid = threadIdx.x / G, lane = threadIdx.x % G;
   const int64_t li = lb * NG + gid;
   const bool valid = li < lcount;
   const int32_t c = valid ? a.list[lbase + li] : 0;
   int32_t* gk = keys + gid * H;
   ull* gv = vals + gid * H;
+  int32_t* gm = mvert + gid * M;
+  int32_t* gf = mfirst + gid * M;
   for (int s = lane; s < H; s += G) {
     gk[s] = kEmpty;
     gv[s] = 0;
   }
+  int64_t a0 = 0, L = 0;
+  int mc = 0;
+  if (valid) {
+    const int64_t m0 = a.mstart[c];
+    mc = (int)(a.mstart[c + 1] - m0);
+    a0 = a.astart[c];
+    L = a.A[c];
+    for (int i = lane; i < mc; i += G) {
+      gm[i] = a.members[m0 + i];
+      gf[i] = (int32_t)(a.gscan[m0 + i] - a0);
+    }
+  }
   if (lane == 0) gcount[gid] = 0;
   __syncthreads();
-  int64_t e0 = 0, e1 = 0;
-  if (valid) {
-    e0 = a.astart[c];
-    e1 = a.astart[c + 1];
+  for (int64_t t = lane; t < L; t += G) {
+    const int i = member_at(gf, mc, t);
+    const int64_t e = a.rs[gm[i]] + (t - gf[i]);
+    table_add<ull>(gk, gv, LOG2H, a.map[a.idx[e]], (ull)a.w[e]);
   }
-  for (int64_t e = e0 + lane; e < e1; e += G) table_add<ull>(gk, gv, LOG2H, a.tkey[e], a.tw[e]);
   __syncthreads();
   ull self = 0;
   if (valid) {
@@ -1464,8 +1504,8 @@ __device__ __forceinline__ void merge_group(const MergeArgs& a, int64_t lb, int6
       const int32_t key = gk[s];
       if (key == kEmpty) continue;
       const int p = atomicAdd(&gcount[gid], 1);
-      a.tkey[e0 + p] = key;
-      a.tw[e0 + p] = gv[s];
+      a.okey[a0 + p] = key;
+      a.ow[a0 + p] = gv[s];
       if (key == me) self = gv[s];
     }
   }
@@ -1494,7 +1534,8 @@ int64_t merge_lds_blocks(const Buckets& b) {
   return blocks;
 }
 
-__global__ __launch_bounds__(kBlock) void k_merge_lds(MergeArgs a) {
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_merge_lds(MergeArgs<WT> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int gcount[kBlock / 4];
   __shared__ ull red[kBlock / 64];
@@ -1504,22 +1545,38 @@ __global__ __launch_bounds__(kBlock) void k_merge_lds(MergeArgs a) {
   const int64_t lb = b - a.bstart[k];
   const int64_t lbase = a.lstart[k], lcount = a.lstart[k + 1] - a.lstart[k];
   switch (k) {
-    case 0: merge_group<bucket_group(0), bucket_log2h(0)>(a, lb, lbase, lcount, smem, gcount, red); break;
-    case 1: merge_group<bucket_group(1), bucket_log2h(1)>(a, lb, lbase, lcount, smem, gcount, red); break;
-    case 2: merge_group<bucket_group(2), bucket_log2h(2)>(a, lb, lbase, lcount, smem, gcount, red); break;
-    case 3: merge_group<bucket_group(3), bucket_log2h(3)>(a, lb, lbase, lcount, smem, gcount, red); break;
-    case 4: merge_group<bucket_group(4), bucket_log2h(4)>(a, lb, lbase, lcount, smem, gcount, red); break;
-    case 5: merge_group<bucket_group(5), bucket_log2h(5)>(a, lb, lbase, lcount, smem, gcount, red); break;
-    default: merge_group<bucket_group(6), bucket_log2h(6)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 0: merge_group<WT, bucket_group(0), bucket_log2h(0)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 1: merge_group<WT, bucket_group(1), bucket_log2h(1)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 2: merge_group<WT, bucket_group(2), bucket_log2h(2)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 3: merge_group<WT, bucket_group(3), bucket_log2h(3)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 4: merge_group<WT, bucket_group(4), bucket_log2h(4)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    case 5: merge_group<WT, bucket_group(5), bucket_log2h(5)>(a, lb, lbase, lcount, smem, gcount, red); break;
+    default: merge_group<WT, bucket_group(6), bucket_log2h(6)>(a, lb, lbase, lcount, smem, gcount, red); break;
   }
 }
 
-hipError_t merge_lds(const Buckets& b, const AggBuffers& ag, hipStream_t s) {
-  MergeArgs a;
+static size_t merge_table_bytes(int k) {
+  // table (key + 8-byte value) and the member arrays (vertex + first flat arc)
+  const size_t H = (size_t)1 << bucket_log2h(k);
+  return (size_t)bucket_rows_per_block(k) * (H * 12 + (H / 2) * 8);
+}
+
+template <typename WT>
+static hipError_t merge_lds_t(const DevGraph& g, const Buckets& b, const AggBuffers& ag,
+                              hipStream_t s) {
+  MergeArgs<WT> a;
+  a.rs = g.rs;
+  a.idx = g.idx;
+  a.w = (const WT*)g.w;
+  a.map = ag.map;
+  a.members = ag.members;
+  a.mstart = ag.mstart;
+  a.gscan = ag.gscan;
   a.astart = ag.astart;
+  a.A = ag.A;
   a.newid = ag.newid;
-  a.tkey = ag.tkey;
-  a.tw = ag.tw;
+  a.okey = ag.okey;
+  a.ow = ag.ow;
   a.dcount = ag.dcount;
   a.partial = ag.block_partial;
   a.list = ag.list;
@@ -1530,25 +1587,37 @@ hipError_t merge_lds(const Buckets& b, const AggBuffers& ag, hipStream_t s) {
     a.lstart[k] = b.lstart[k];
     const int64_t rpb = bucket_rows_per_block(k);
     blocks += (b.count[k] + rpb - 1) / rpb;
-    if (b.count[k]) {
-      size_t t = lds_table_bytes(k, 8);
-      shm = t > shm ? t : shm;
-    }
+    if (b.count[k]) shm = std::max(shm, merge_table_bytes(k));
   }
   a.bstart[7] = blocks;
-  a.lstart[7] = b.lstart[7];
+  a.lstart[7] = b.lstart[kFusedClasses];
   if (blocks == 0) return hipSuccess;
-  LV_LAUNCH(k_merge_lds, (unsigned)blocks, kBlock, shm, s, a);
+  LV_LAUNCH(k_merge_lds<WT>, (unsigned)blocks, kBlock, shm, s, a);
   LV_LAUNCH(k_reduce_sum, grid_for(blocks, kBlock, 256), kBlock, 0, s, a.partial, blocks,
             ag.stats);
   return hipGetLastError();
 }
 
+hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& ag, hipStream_t s) {
+  return g.w64 ? merge_lds_t<uint64_t>(g, b, ag, s) : merge_lds_t<uint32_t>(g, b, ag, s);
+}
+
+// Communities of more than 1024 arcs: blocks over kHubChunk-arc pieces of the flat range,
+// each thread covering 8 consecutive flat arcs (one member search, then a forward walk).
+template <typename WT>
 struct MergeHubArgs {
+  const int64_t* rs;
+  const int32_t* idx;
+  const WT* w;
+  const int32_t* map;
+  const int32_t* members;
+  const int64_t* mstart;
+  const int64_t* gscan;
   const int64_t* astart;
+  const int64_t* A;
   const int64_t* newid;
-  int32_t* tkey;
-  uint64_t* tw;
+  int32_t* okey;
+  uint64_t* ow;
   int64_t* dcount;
   ull* stats;
   const int32_t* hubs;
@@ -1562,24 +1631,45 @@ struct MergeHubArgs {
   int32_t* occ_count;
 };
 
-__global__ __launch_bounds__(kBlock) void k_merge_hub_accumulate(MergeHubArgs a) {
+constexpr int kMergePerThread = (int)(kHubChunk / kBlock);
+
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_merge_hub_accumulate(MergeHubArgs<WT> a) {
   __shared__ int32_t lk[kHubLds];
   __shared__ ull lv[kHubLds];
   const int64_t b = blockIdx.x;
   const int64_t h = find_segment(a.chunk_start, a.nh, b);
   const int32_t c = a.hubs[h];
-  const int64_t rb = a.astart[c], re = a.astart[c + 1];
-  const int64_t e0 = rb + (b - a.chunk_start[h]) * kHubChunk;
-  const int64_t e1 = e0 + kHubChunk < re ? e0 + kHubChunk : re;
+  const int64_t m0 = a.mstart[c];
+  const int mc = (int)(a.mstart[c + 1] - m0);
+  const int64_t a0 = a.astart[c], L = a.A[c];
   const int64_t ts = a.tab_start[h];
   const int lg = ilog2_i64(a.tab_start[h + 1] - ts);
   hub_lds_init<ull>(lk, lv);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock)
-    table_add<ull>(lk, lv, kHubLdsLog2, a.tkey[e], (ull)a.tw[e]);
+  const int64_t t0 = (b - a.chunk_start[h]) * kHubChunk + (int64_t)threadIdx.x * kMergePerThread;
+  const int64_t t1 = t0 + kMergePerThread < L ? t0 + kMergePerThread : L;
+  if (t0 < t1) {
+    // member holding flat arc t0 (first flat arcs are a0 + gscan offsets)
+    int i = member_at(a.gscan + m0, mc, a0 + t0);
+    int64_t next = i + 1 < mc ? a.gscan[m0 + i + 1] - a0 : L;
+    int64_t first = a.gscan[m0 + i] - a0;
+    int32_t v = a.members[m0 + i];
+    for (int64_t t = t0; t < t1; t++) {
+      while (t >= next) {
+        i++;
+        first = next;
+        next = i + 1 < mc ? a.gscan[m0 + i + 1] - a0 : L;
+        v = a.members[m0 + i];
+      }
+      const int64_t e = a.rs[v] + (t - first);
+      table_add<ull>(lk, lv, kHubLdsLog2, a.map[a.idx[e]], (ull)a.w[e]);
+    }
+  }
   hub_flush<ull>(lk, lv, a.tkeys + ts, a.tvals + ts, lg, a.occ + ts, a.occ_count + h);
 }
 
-__global__ __launch_bounds__(kBlock) void k_merge_hub_emit(MergeHubArgs a) {
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_merge_hub_emit(MergeHubArgs<WT> a) {
   __shared__ ull red[kBlock / 64];
   const int64_t b = blockIdx.x;
   const int64_t h = find_segment(a.scan_start, a.nh, b);
@@ -1592,13 +1682,13 @@ __global__ __launch_bounds__(kBlock) void k_merge_hub_emit(MergeHubArgs a) {
   const int32_t me = (int32_t)a.newid[c];
   ull self = 0;
   for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
-    const int64_t s = ts + a.occ[ts + p];
-    const int32_t key = a.tkeys[s];
-    const ull val = a.tvals[s];
-    a.tkeys[s] = kEmpty;
-    a.tvals[s] = 0;
-    a.tkey[base + p] = key;
-    a.tw[base + p] = val;
+    const int64_t sl = ts + a.occ[ts + p];
+    const int32_t key = a.tkeys[sl];
+    const ull val = a.tvals[sl];
+    a.tkeys[sl] = kEmpty;
+    a.tvals[sl] = 0;
+    a.okey[base + p] = key;
+    a.ow[base + p] = val;
     if (key == me) self = val;
   }
   if (b == a.scan_start[h] && threadIdx.x == 0) a.dcount[me] = cnt;
@@ -1606,13 +1696,22 @@ __global__ __launch_bounds__(kBlock) void k_merge_hub_emit(MergeHubArgs a) {
   if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
 }
 
-hipError_t merge_hubs(const Buckets& b, const HubPlan& hp, const AggBuffers& ag, hipStream_t s) {
-  if (hp.nh <= 0) return hipSuccess;
-  MergeHubArgs a;
+template <typename WT>
+static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const HubPlan& hp,
+                               const AggBuffers& ag, hipStream_t s) {
+  MergeHubArgs<WT> a;
+  a.rs = g.rs;
+  a.idx = g.idx;
+  a.w = (const WT*)g.w;
+  a.map = ag.map;
+  a.members = ag.members;
+  a.mstart = ag.mstart;
+  a.gscan = ag.gscan;
   a.astart = ag.astart;
+  a.A = ag.A;
   a.newid = ag.newid;
-  a.tkey = ag.tkey;
-  a.tw = ag.tw;
+  a.okey = ag.okey;
+  a.ow = ag.ow;
   a.dcount = ag.dcount;
   a.stats = ag.stats;
   a.hubs = ag.list + b.lstart[kFusedClasses];
@@ -1627,8 +1726,46 @@ hipError_t merge_hubs(const Buckets& b, const HubPlan& hp, const AggBuffers& ag,
   const int64_t n = hp.slots > hp.nh ? hp.slots : hp.nh;
   LV_LAUNCH(k_hub_reset<ull>, grid_for(n), kBlock, 0, s, ag.tkeys, ag.tvals, hp.slots,
             ag.occ_count, hp.nh);
-  LV_LAUNCH(k_merge_hub_accumulate, (unsigned)hp.chunks, kBlock, 0, s, a);
-  LV_LAUNCH(k_merge_hub_emit, (unsigned)hp.scan_blocks, kBlock, 0, s, a);
+  LV_LAUNCH(k_merge_hub_accumulate<WT>, (unsigned)hp.chunks, kBlock, 0, s, a);
+  LV_LAUNCH(k_merge_hub_emit<WT>, (unsigned)hp.scan_blocks, kBlock, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const HubPlan& hp,
+                      const AggBuffers& ag, hipStream_t s) {
+  if (hp.nh <= 0) return hipSuccess;
+  return g.w64 ? merge_hubs_t<uint64_t>(g, b, hp, ag, s) : merge_hubs_t<uint32_t>(g, b, hp, ag, s);
+}
+
+// Rows of the super-vertex graph where the merge left them.
+__global__ void k_super_rows(int64_t np, const int32_t* oldlabel, const int64_t* astart,
+                             const int64_t* dcount, int64_t* rs, int64_t* re) {
+  for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < np;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = astart[oldlabel[a]];
+    rs[a] = r;
+    re[a] = r + dcount[a];
+  }
+}
+hipError_t super_rows(int64_t np, const AggBuffers& ag, int64_t* rs, int64_t* re, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  LV_LAUNCH(k_super_rows, grid_for(np), kBlock, 0, s, np, ag.oldlabel, ag.astart, ag.dcount, rs,
+            re);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_i64(const int64_t* a, int64_t n, ull* out) {
+  __shared__ ull red[kBlock / 64];
+  ull t = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    t += (ull)a[i];
+  t = block_sum_u64(t, red);
+  if (threadIdx.x == 0 && t) atomicAdd(out, t);
+}
+hipError_t sum_i64(const int64_t* a, int64_t n, unsigned long long* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_sum_i64, grid_for(n, kBlock, 1024), kBlock, 0, s, a, n, out);
   return hipGetLastError();
 }
 
