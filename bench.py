@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "Louvain TEPS (R-MAT s25); batched graphs/s vs one-by-one; serving p50/p99 ms"
 HBM_PEAK_GBPS = 8000.0
-PROFILE_PMC = os.path.join(ROOT, "profiles", "move_lds_rmat25_pmc.json")
+PROFILE_PMC = os.path.join(ROOT, "profiles", "k_move_lds_rmat25_pmc.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2301_12390_amd", "csrc", "lv_kernels.hip")
 
 
@@ -44,16 +44,46 @@ BYTES_PER_ARC = 12
 BYTES_PER_CANDIDATE = 8
 
 
+def save_graph(path, workload, g):
+    import numpy as np
+    with open(path, "wb") as f:
+        hdr = {"workload": workload, "n": g.n, "nnz": g.nnz,
+               "offsets": str(g.offsets.dtype).replace("torch.", ""),
+               "weights": str(g.weights.dtype).replace("torch.", "")}
+        b = json.dumps(hdr).encode()
+        f.write(len(b).to_bytes(8, "little"))
+        f.write(b)
+        for t in (g.offsets, g.indices, g.weights):
+            t.cpu().numpy().tofile(f)
+
+
+def load_graph(path, workload, dev):
+    import numpy as np
+    import torch
+    from graphgen import Csr
+    with open(path, "rb") as f:
+        hl = int.from_bytes(f.read(8), "little")
+        hdr = json.loads(f.read(hl).decode())
+        assert hdr["workload"] == workload, (hdr["workload"], workload)
+        n, nnz = hdr["n"], hdr["nnz"]
+        off = np.fromfile(f, dtype=hdr["offsets"], count=n + 1)
+        idx = np.fromfile(f, dtype=np.int32, count=nnz)
+        w = np.fromfile(f, dtype=hdr["weights"], count=nnz)
+    return Csr(n, torch.from_numpy(off).to(dev), torch.from_numpy(idx).to(dev),
+               torch.from_numpy(w).to(dev), workload)
+
+
 def kernel_src_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
 
 
 def load_traffic(workload):
-    """Measured HBM bytes per launch of the move kernel from the committed rocprofv3 PMC
-    summary, if it was taken on this workload with the current kernel source."""
+    """Measured HBM bytes per launch of k_move_lds from the committed rocprofv3 PMC summary
+    (its ```json block), if it was taken on this workload with the current kernel source."""
     try:
-        d = json.load(open(PROFILE_PMC))
-    except (OSError, ValueError):
+        text = open(PROFILE_PMC).read()
+        d = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
         return None
     if d.get("workload") != workload or d.get("kernel_src_sha256") != kernel_src_sha():
         return None
@@ -85,7 +115,7 @@ def cpu_baseline(g, res_trace, seconds, substeps, n_arcs_input):
             break
     el = time.perf_counter() - t1
     rate = arcs / el
-    scanned = sum(t["lds_arcs"] + t["hub_arcs"] for t in res_trace)
+    scanned = sum(t["fused_arcs"] + t["wg_arcs"] + t["hub_arcs"] for t in res_trace)
     est_run = scanned / rate
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
@@ -112,6 +142,12 @@ def main():
                     help="vertex classes per local-moving iteration (1 = fully synchronous)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-cache", default="",
+                    help="file to load the workload graph from, or to save it to after "
+                         "generating it (raw little-endian arrays)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the timed region, copy a buffer of this many MiB once (a plain "
+                         "copy kernel of known size, to scale profiler byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -131,10 +167,30 @@ def main():
     dev = torch.device("cuda:0")
     log(f"device {torch.cuda.get_device_name(0)}")
     t0 = time.perf_counter()
-    g = config_graph(args.workload, device=dev)
-    torch.cuda.synchronize()
-    log(f"generated {args.workload}: n={g.n} nnz={g.nnz} in {time.perf_counter() - t0:.1f}s")
+    if args.graph_cache and os.path.exists(args.graph_cache):
+        g = load_graph(args.graph_cache, args.workload, dev)
+        log(f"loaded {args.workload}: n={g.n} nnz={g.nnz} in {time.perf_counter() - t0:.1f}s")
+    else:
+        g = config_graph(args.workload, device=dev)
+        torch.cuda.synchronize()
+        log(f"generated {args.workload}: n={g.n} nnz={g.nnz} in {time.perf_counter() - t0:.1f}s")
+        if args.graph_cache:
+            save_graph(args.graph_cache, args.workload, g)
+            log(f"saved to {args.graph_cache}")
     torch.cuda.empty_cache()
+    if args.steps <= 0:
+        return
+
+    if args.copy_calibration_mib > 0:
+        words = args.copy_calibration_mib * (1 << 18)
+        src = torch.ones(words, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
+        torch.cuda.empty_cache()
 
     lv = Louvain(0)
     for w in range(args.warmup):
@@ -153,29 +209,31 @@ def main():
     teps = g.nnz / (ms_per_step / 1000.0)
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {teps / 1e9:.3f} GTEPS")
 
-    # roofline of the LDS-table move kernel over the timed region
+    # roofline of k_move_lds (the fused LDS-table move kernel) over the timed region
     o_bytes = 8 if g.offsets.dtype == torch.int64 else 4
-    lds_ms = lds_launch = lds_bytes = 0.0
-    hub_ms = upd_ms = agg_ms = 0.0
+    f_ms = f_launch = f_bytes = 0.0
+    wg_ms = hub_ms = upd_ms = agg_ms = 0.0
     wide = False
     for r in results:
         for t in r["trace"]:
-            lds_ms += t["move_ms"]
+            f_ms += t["fused_ms"]
+            wg_ms += t["wg_ms"]
             hub_ms += t["hub_ms"]
             upd_ms += t["update_ms"]
-            lds_launch += t["lds_launches"]
-            lds_bytes += ((o_bytes + BYTES_PER_VERTEX_BASE) * t["lds_vertices"]
-                          + BYTES_PER_ARC * t["lds_arcs"]
-                          + BYTES_PER_CANDIDATE * t["lds_candidates"])
+            f_launch += t["fused_launches"]
+            f_bytes += ((o_bytes + BYTES_PER_VERTEX_BASE) * t["fused_vertices"]
+                        + BYTES_PER_ARC * t["fused_arcs"]
+                        + BYTES_PER_CANDIDATE * t["fused_candidates"])
             wide = wide or bool(t["wide"])
         agg_ms += sum(r["aggregate_ms"])
-    avg_launch_ms = lds_ms / max(lds_launch, 1)
-    bytes_per_launch = lds_bytes / max(lds_launch, 1)
-    achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if lds_ms > 0 else 0.0
+    avg_launch_ms = f_ms / max(f_launch, 1)
+    bytes_per_launch = f_bytes / max(f_launch, 1)
+    achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if f_ms > 0 else 0.0
     traffic = load_traffic(args.workload)
     r0 = results[0]
-    move_teps = sum(t["lds_arcs"] + t["hub_arcs"] for t in r0["trace"]) / max(
-        sum(t["move_ms"] + t["hub_ms"] for t in r0["trace"]) / 1000.0, 1e-12)
+    scanned = sum(t["fused_arcs"] + t["wg_arcs"] + t["hub_arcs"] for t in r0["trace"])
+    move_ms = sum(t["fused_ms"] + t["wg_ms"] + t["hub_ms"] for t in r0["trace"])
+    move_teps = scanned / max(move_ms / 1000.0, 1e-12)
 
     line = {
         "metric": METRIC,
@@ -200,6 +258,8 @@ def main():
             "substeps": args.substeps,
             "passes": r0["passes"],
             "iterations": r0["iterations"],
+            "n_per_pass": r0["n_pass"],
+            "arcs_per_pass": r0["nnz_pass"],
             "communities": r0["n_communities"],
             "Q": r0["q"],
         },
@@ -212,12 +272,13 @@ def main():
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
             "avg_launch_ms": avg_launch_ms,
-            "launches": int(lds_launch),
+            "launches": int(f_launch),
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "breakdown_ms_per_step": {
-            "move_lds": lds_ms / args.steps,
-            "move_hubs": hub_ms / args.steps,
+            "k_move_lds": f_ms / args.steps,
+            "k_move_wg": wg_ms / args.steps,
+            "hub_kernels": hub_ms / args.steps,
             "update": upd_ms / args.steps,
             "aggregate": agg_ms / args.steps,
         },

@@ -97,26 +97,29 @@ typedef struct {
 #define LV_MAX_PASSES 64
 #define LV_MAX_TRACE 1024
 
-/* One local-moving iteration (host). */
+/* One local-moving iteration (host). The move kernels are: the fused LDS-table kernel
+ * (k_move_lds, rows of up to 1024 arcs), the workgroup-per-row kernel (k_move_wg, rows of up
+ * to 8192 arcs when the device allows its LDS table) and the global-table hub kernels. */
 typedef struct {
   int32_t pass, iteration;
   int32_t wide;            /* 1 if this iteration used 128-bit gains */
   int32_t substeps;        /* class steps of the iteration */
-  int32_t lds_launches;    /* launches of the LDS-table move kernel in the iteration */
+  int32_t fused_launches;  /* launches of k_move_lds */
+  int32_t wg_launches;     /* launches of k_move_wg */
   int32_t hub_launches;    /* class steps that ran the hub kernels */
+  int32_t reserved;
   lv_i128 gain_sum;        /* S: sum of the applied gains */
   int64_t moved;           /* vertices that changed community */
   int64_t candidates;      /* distinct (vertex, other community) pairs examined */
-  int64_t lds_vertices;    /* vertices decided by the LDS-table move kernel */
-  int64_t lds_arcs;        /* arcs scanned by that kernel */
-  int64_t hub_vertices;    /* vertices decided by the global-table (hub) kernels */
-  int64_t hub_arcs;
-  int64_t lds_candidates;  /* the part of `candidates` found by the LDS-table kernel */
-  int64_t lds_moved;       /* the part of `moved` decided by the LDS-table kernel */
-  float move_ms;           /* LDS move kernel, summed over the class steps (LV_TRACE) */
-  float hub_ms;            /* hub kernels, summed over the class steps (LV_TRACE) */
-  float update_ms;         /* membership/community updates, summed (LV_TRACE) */
+  int64_t fused_vertices, fused_arcs, fused_candidates; /* work of k_move_lds */
+  int64_t wg_vertices, wg_arcs, wg_candidates;          /* work of k_move_wg */
+  int64_t hub_vertices, hub_arcs;                       /* work of the hub kernels */
+  float fused_ms;          /* k_move_lds, summed over the class steps (LV_TRACE) */
+  float wg_ms;             /* k_move_wg and the step's reduction (LV_TRACE) */
+  float hub_ms;            /* hub kernels (LV_TRACE) */
+  float update_ms;         /* membership/community updates (LV_TRACE) */
   float iter_ms;           /* whole iteration including the host read-back (LV_TRACE) */
+  float reserved2;
 } lv_iter_trace;
 
 /* Result of louvain_run (host). */

@@ -23,7 +23,7 @@ enum SlotId {
   S_HUBARR, S_TKEYS, S_TVALS, S_OCC, S_OCCCNT, S_PARTIAL, S_A, S_ASTART, S_NEWID, S_CURSOR,
   S_OLDLABEL, S_DCOUNT, S_ABASE, S_TKEY, S_TW, S_GOFF0, S_GIDX0, S_GW0, S_GOFF1, S_GIDX1, S_GW1,
   S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
-  S_COUNT_SLOTS
+  S_REC, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -42,8 +42,9 @@ constexpr int PIN_MISC = 1808;    // host: other read-backs
 constexpr int PIN_WORDS = 2048;
 constexpr int DEG = 12;           // degree classes per vertex class (list segment stride)
 constexpr int STATS_WORDS = 512;
-constexpr int kEvents = 4 * 32 + 2;
-constexpr int EV_AGG = 4 * 32;
+constexpr int kEvStep = 5;  // events per class step
+constexpr int kEvents = kEvStep * 32 + 2;
+constexpr int EV_AGG = kEvStep * 32;
 
 struct lv_ctx {
   int device = 0;
@@ -53,7 +54,7 @@ struct lv_ctx {
   std::string err;
   size_t max_lds = 65536;  // largest LDS allocation of one workgroup on this device
   ull* pinned = nullptr;  // host-pinned words for small read-backs
-  hipEvent_t ev[kEvents] = {};  // 4 per class step, then 2 for aggregation
+  hipEvent_t ev[kEvents] = {};  // kEvStep per class step, then 2 for aggregation
 };
 
 namespace {
@@ -311,17 +312,28 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
   const bool trace = (flags & LV_TRACE) != 0;
   const int K = ph.classes;
   const int hf = ph.m.hub_first;
-  int64_t lds_v = 0, lds_a = 0, hub_v = 0, hub_a = 0;
+  // the work of each kernel family per iteration (fixed within the phase)
+  int64_t fv = 0, fa = 0, wv = 0, wa = 0, hv = 0, ha = 0;
+  int fl = 0, wl = 0, hl = 0;
   for (int k = 0; k < K; k++) {
+    int64_t rows = 0;
     for (int j = 0; j < DEG; j++) {
-      if (j < hf) {
-        lds_v += ph.b.count[DEG * k + j];
-        lds_a += ph.b.arcs[DEG * k + j];
+      const int64_t c = ph.b.count[DEG * k + j], a = ph.b.arcs[DEG * k + j];
+      if (j < 7) {
+        fv += c;
+        fa += a;
+        rows += c;
+      } else if (j < hf) {
+        wv += c;
+        wa += a;
+        wl += c > 0;
       } else {
-        hub_v += ph.b.count[DEG * k + j];
-        hub_a += ph.b.arcs[DEG * k + j];
+        hv += c;
+        ha += a;
       }
     }
+    fl += rows > 0;
+    hl += ph.hp[k].nh > 0;
   }
   ull* stats0 = ph.m.stats;
   *out = PhaseOut();
@@ -332,54 +344,44 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
     for (int k = 0; k < K; k++) {
       lv::MoveBuffers m = ph.m;
       m.stats = stats0 + 8 * k;
-      hipEvent_t* ev = ctx->ev + 4 * k;
+      hipEvent_t* ev = ctx->ev + kEvStep * k;
       if (trace) HIPCHK(hipEventRecord(ev[0], s));
-      HIPCHK(lv::move_lds(ph.g, ph.b, k, m, ph.wide, s));
+      HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
       if (trace) HIPCHK(hipEventRecord(ev[1], s));
-      HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s));
+      HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s));
       if (trace) HIPCHK(hipEventRecord(ev[2], s));
-      HIPCHK(lv::apply_moves(ph.b, k, m, s));
+      HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s));
       if (trace) HIPCHK(hipEventRecord(ev[3], s));
+      HIPCHK(lv::apply_moves(ph.b, k, m, s));
+      if (trace) HIPCHK(hipEventRecord(ev[4], s));
     }
     ull* h = ctx->pinned + PIN_STATS;
     HIPCHK(hipMemcpyAsync(h, stats0, 8 * K * sizeof(ull), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    float move_ms = 0, hub_ms = 0, upd_ms = 0;
-    int lds_launches = 0, hub_launches = 0;
-    for (int k = 0; k < K; k++) {
-      for (int j = 0; j < hf; j++) {
-        // the fused kernel covers classes 0..6 in one launch; each workgroup tier is one more
-        if (j < 7) {
-          if (j == 0) {
-            int64_t rows = 0;
-            for (int q = 0; q < 7; q++) rows += ph.b.count[DEG * k + q];
-            lds_launches += rows > 0;
-          }
-        } else {
-          lds_launches += ph.b.count[DEG * k + j] > 0;
-        }
-      }
-      hub_launches += ph.hp[k].nh > 0;
-      if (trace) {
-        hipEvent_t* ev = ctx->ev + 4 * k;
-        float a = 0, b = 0, c = 0;
-        HIPCHK(hipEventElapsedTime(&a, ev[0], ev[1]));
-        HIPCHK(hipEventElapsedTime(&b, ev[1], ev[2]));
-        HIPCHK(hipEventElapsedTime(&c, ev[2], ev[3]));
-        move_ms += a;
-        hub_ms += b;
-        upd_ms += c;
+    float t_fused = 0, t_wg = 0, t_hub = 0, t_upd = 0;
+    if (trace) {
+      for (int k = 0; k < K; k++) {
+        hipEvent_t* ev = ctx->ev + kEvStep * k;
+        float x = 0;
+        HIPCHK(hipEventElapsedTime(&x, ev[0], ev[1]));
+        t_fused += x;
+        HIPCHK(hipEventElapsedTime(&x, ev[1], ev[2]));
+        t_wg += x;
+        HIPCHK(hipEventElapsedTime(&x, ev[2], ev[3]));
+        t_hub += x;
+        HIPCHK(hipEventElapsedTime(&x, ev[3], ev[4]));
+        t_upd += x;
       }
     }
     i128 S = 0;
-    int64_t moved = 0, cand = 0, lds_cand = 0, lds_moved = 0;
+    int64_t moved = 0, cand = 0, fcand = 0, wcand = 0;
     for (int k = 0; k < K; k++) {
       const ull* x = h + 8 * k;
       S += (i128)(((u128)x[1] << 64) | x[0]);
       moved += (int64_t)x[2];
       cand += (int64_t)x[3];
-      lds_cand += (int64_t)x[4];
-      lds_moved += (int64_t)x[5];
+      fcand += (int64_t)x[4];
+      wcand += (int64_t)x[5];
     }
     out->iterations++;
     out->gain_sum += S;
@@ -394,21 +396,25 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
       r.iteration = it;
       r.wide = ph.wide ? 1 : 0;
       r.substeps = K;
-      r.lds_launches = lds_launches;
-      r.hub_launches = hub_launches;
+      r.fused_launches = fl;
+      r.wg_launches = wl;
+      r.hub_launches = hl;
       r.gain_sum = to_i128(S);
       r.moved = moved;
       r.candidates = cand;
-      r.lds_candidates = lds_cand;
-      r.lds_moved = lds_moved;
-      r.lds_vertices = lds_v;
-      r.lds_arcs = lds_a;
-      r.hub_vertices = hub_v;
-      r.hub_arcs = hub_a;
+      r.fused_vertices = fv;
+      r.fused_arcs = fa;
+      r.fused_candidates = fcand;
+      r.wg_vertices = wv;
+      r.wg_arcs = wa;
+      r.wg_candidates = wcand;
+      r.hub_vertices = hv;
+      r.hub_arcs = ha;
       if (trace) {
-        r.move_ms = move_ms;
-        r.hub_ms = hub_ms;
-        r.update_ms = upd_ms;
+        r.fused_ms = t_fused;
+        r.wg_ms = t_wg;
+        r.hub_ms = t_hub;
+        r.update_ms = t_upd;
         r.iter_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0)
                         .count();
       }
@@ -616,10 +622,11 @@ lv_status louvain_move(lv_ctx* ctx, const lv_graph* g, const uint64_t* Kin, uint
   if (Win) W = Win;
   if (W > ((uint64_t)1 << 62)) return fail(ctx, LV_EOVERFLOW, "total weight exceeds 2^62");
   if (W == 0) return LV_OK;
+  void* rec = nullptr;
+  CHK(ws(ctx, S_REC, (size_t)ph.g.n * lv::kRecBytes, &rec));
+  HIPCHK(lv::pack_state(ph.g.n, C, Sigma, csize, rec, s));
   ph.m.K = K;
-  ph.m.C = C;
-  ph.m.Sig = Sigma;
-  ph.m.csize = csize;
+  ph.m.rec = rec;
   ph.m.W = W;
   ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)W * maxK < ((u128)1 << 63));
   ph.classes = p->substeps;
@@ -628,6 +635,8 @@ lv_status louvain_move(lv_ctx* ctx, const lv_graph* g, const uint64_t* Kin, uint
   PhaseOut po;
   CHK(run_phase(ctx, ph, tolerance_threshold(W, p->tolerance_exp10, p->decline_exp10, pass_index),
                 p->max_iterations, p->flags, s, nullptr, &po));
+  HIPCHK(lv::unpack_state(ph.g.n, rec, C, Sigma, csize, s));
+  HIPCHK(hipStreamSynchronize(s));
   if (stats) {
     stats->iterations = po.iterations;
     stats->hit_cap = po.hit_cap ? 1 : 0;
@@ -727,14 +736,14 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
   i128 qnum = 0;
   bool have_q = false;
   int which = 0;  // next super-graph buffer set
+  void* rec = nullptr;
+  CHK(ws(ctx, S_REC, (size_t)n0 * lv::kRecBytes, &rec));
   for (int pass = 0; pass < p->max_passes; pass++) {
-    HIPCHK(lv::init_state(cur.n, K, C, Sig, csize, s));
+    HIPCHK(lv::init_state(cur.n, K, rec, s));
     Phase ph;
     ph.g = cur;
     ph.m.K = K;
-    ph.m.C = C;
-    ph.m.Sig = Sig;
-    ph.m.csize = csize;
+    ph.m.rec = rec;
     ph.m.W = W;
     ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)W * maxK < ((u128)1 << 63));
     ph.classes = p->substeps;
@@ -771,6 +780,7 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
     int64_t np = 0, nnzp = 0;
     uint64_t self = 0;
     lv::AggBuffers ab;
+    HIPCHK(lv::unpack_state(cur.n, rec, C, Sig, csize, s));
     CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s));
     HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
     HIPCHK(lv::compose_membership(membership, n0, map, s));

@@ -30,6 +30,11 @@ __host__ __device__ constexpr int bucket_log2h(int k) {
 }
 __host__ __device__ constexpr int bucket_rows_per_block(int k) { return kBlock / bucket_group(k); }
 
+// The move kernel decides rows of up to 8 arcs (degree classes 0 and 1) with one thread per row,
+// combining repeated communities in registers; the other classes use the group widths above.
+__host__ __device__ constexpr int move_group_size(int k) { return k < 2 ? 1 : bucket_group(k); }
+__host__ __device__ constexpr int move_rows_per_block(int k) { return kBlock / move_group_size(k); }
+
 // Degree classes 7, 8, 9 (rows of up to 2048, 4096, 8192 arcs) are decided by one 1024-thread
 // workgroup per row with an LDS table of 4096, 8192 or 16384 slots when the device allows such
 // a workgroup allocation; class 10 (longer rows), and any class whose table does not fit, use
@@ -66,6 +71,16 @@ __host__ __device__ inline int vertex_class(int32_t pass, int32_t K, int64_t v) 
   z ^= z >> 31;
   return (int)(((z >> 32) * (uint64_t)(uint32_t)K) >> 32);
 }
+
+// Community state of the local-moving phase, one record per index x in [0, n): the community
+// of vertex x, and the size and total weight Sigma of the community labelled x. Packing them
+// puts Sigma[j] on the cache line that the gather of C[j] fetches, so a candidate community
+// whose label is a neighbour of the deciding vertex costs no further memory traffic.
+struct __align__(16) VRec {
+  int32_t c;
+  int32_t size;
+  unsigned long long sig;
+};
 
 // Hub rows use global-memory tables: accumulation blocks cover kHubChunk arcs each, and the
 // scan blocks cover kHubScanChunk occupied slots each.

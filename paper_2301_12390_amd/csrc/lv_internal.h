@@ -64,8 +64,13 @@ hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* pa
 
 // ---- pass set-up
 hipError_t row_sums(const DevGraph& g, uint64_t* K, hipStream_t s);  // K must be zero
-hipError_t init_state(int64_t n, const uint64_t* K, int32_t* C, uint64_t* Sig, int32_t* csize,
-                      hipStream_t s);
+// Community state as 16-byte records {C[x], csize[x], Sigma[x]} (see lv_device.h).
+constexpr size_t kRecBytes = 16;
+hipError_t init_state(int64_t n, const uint64_t* K, void* rec, hipStream_t s);
+hipError_t pack_state(int64_t n, const int32_t* C, const uint64_t* Sig, const int32_t* csize,
+                      void* rec, hipStream_t s);
+hipError_t unpack_state(int64_t n, const void* rec, int32_t* C, uint64_t* Sig, int32_t* csize,
+                        hipStream_t s);
 // Classify rows (lengths from offsets, or from `len` if non-null over m items) by vertex
 // class (K classes of pass `pass`) and degree class. counts: device scratch of 1536 words;
 // host_counts: 1536 pinned words. Host result in `b` (synchronises the stream).
@@ -81,15 +86,13 @@ hipError_t plan_hubs(const int64_t* rs, const int64_t* re, const int64_t* len,
 // ---- local-moving iteration
 struct MoveBuffers {
   const uint64_t* K = nullptr;
-  int32_t* C = nullptr;
-  uint64_t* Sig = nullptr;
-  int32_t* csize = nullptr;
+  void* rec = nullptr;                  // [n] community state records
   uint64_t W = 0;
   const int32_t* list = nullptr;
   int32_t* tgt = nullptr;               // [n] decision of every vertex of the class step
   unsigned long long* block_partial = nullptr;  // 4 words per block of the LDS move kernel
-  // per class step, 8 words: [0..1] S, [2] moved, [3] candidates, [4] LDS-kernel candidates,
-  // [5] LDS-kernel moves
+  // per class step, 8 words: [0..1] S, [2] moved, [3] candidates, [4] candidates of the fused
+  // kernel, [5] candidates of the workgroup kernel
   unsigned long long* stats = nullptr;
   int32_t* tkeys = nullptr;             // hub tables
   void* tvals = nullptr;
@@ -103,9 +106,13 @@ struct MoveBuffers {
 // workgroup may make and the table value width (wide: 8-byte values).
 int hub_first_class(size_t max_lds_per_block, bool wide);
 hipError_t zero_words(unsigned long long* a, int64_t n, hipStream_t s);
-// LDS-table move kernel over the rows of vertex class `cls`.
-hipError_t move_lds(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
-                    bool wide, hipStream_t s);
+// Fused LDS-table move kernel (degree classes 0..6) over the rows of vertex class `cls`.
+hipError_t move_fused(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
+                      bool wide, hipStream_t s);
+// Workgroup-per-row kernel (classes 7 .. hub_first-1) of class `cls`, then the reduction of the
+// block records of both kernels into m.stats.
+hipError_t move_wg(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m, bool wide,
+                   hipStream_t s);
 hipError_t hub_reset_tables(const HubPlan& hp, const MoveBuffers& m, bool wide, hipStream_t s);
 // Hub kernels over the hub rows of vertex class `cls` (plan hp made for those rows).
 hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const HubPlan& hp,

@@ -428,19 +428,53 @@ hipError_t count_labels(const int32_t* C, int64_t n, int32_t* csize, hipStream_t
 // =============================================================================================
 // Pass set-up: every vertex its own community (section 3.2).
 
-__global__ void k_init_state(int64_t n, const uint64_t* K, int32_t* C, uint64_t* Sig,
-                             int32_t* csize) {
+__global__ void k_init_state(int64_t n, const uint64_t* K, VRec* rec) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    C[i] = (int32_t)i;
-    Sig[i] = K[i];
-    csize[i] = 1;
+    VRec r;
+    r.c = (int32_t)i;
+    r.size = 1;
+    r.sig = K[i];
+    rec[i] = r;
   }
 }
-hipError_t init_state(int64_t n, const uint64_t* K, int32_t* C, uint64_t* Sig, int32_t* csize,
-                      hipStream_t s) {
+hipError_t init_state(int64_t n, const uint64_t* K, void* rec, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  LV_LAUNCH(k_init_state, grid_for(n), kBlock, 0, s, n, K, C, Sig, csize);
+  LV_LAUNCH(k_init_state, grid_for(n), kBlock, 0, s, n, K, (VRec*)rec);
+  return hipGetLastError();
+}
+
+__global__ void k_pack_state(int64_t n, const int32_t* C, const uint64_t* Sig,
+                             const int32_t* csize, VRec* rec) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    VRec r;
+    r.c = C[i];
+    r.size = csize[i];
+    r.sig = Sig[i];
+    rec[i] = r;
+  }
+}
+__global__ void k_unpack_state(int64_t n, const VRec* rec, int32_t* C, uint64_t* Sig,
+                               int32_t* csize) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const VRec r = rec[i];
+    C[i] = r.c;
+    csize[i] = r.size;
+    Sig[i] = r.sig;
+  }
+}
+hipError_t pack_state(int64_t n, const int32_t* C, const uint64_t* Sig, const int32_t* csize,
+                      void* rec, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_pack_state, grid_for(n), kBlock, 0, s, n, C, Sig, csize, (VRec*)rec);
+  return hipGetLastError();
+}
+hipError_t unpack_state(int64_t n, const void* rec, int32_t* C, uint64_t* Sig, int32_t* csize,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_unpack_state, grid_for(n), kBlock, 0, s, n, (const VRec*)rec, C, Sig, csize);
   return hipGetLastError();
 }
 
@@ -618,9 +652,7 @@ struct MoveArgs {
   const int32_t* idx;
   const WT* w;
   const uint64_t* K;
-  const int32_t* C;
-  const uint64_t* Sig;
-  const int32_t* csize;
+  const VRec* rec;
   uint64_t W;
   const int32_t* list;
   int64_t bstart[8];  // first block of class k; bstart[7] = total blocks
@@ -667,7 +699,7 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
   for (int64_t e = e0 + lane; e < e1; e += G) {
     const int32_t j = ld_stream(a.idx + e);
     const V wv = (V)ld_stream(a.w + e);
-    if (j != v) table_add<V>(gk, gv, LOG2H, a.C[j], wv);
+    if (j != v) table_add<V>(gk, gv, LOG2H, a.rec[j].c, wv);
   }
   __syncthreads();
   T bg = Ar::lowest();
@@ -677,7 +709,7 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
   int32_t d = 0;
   uint64_t Ki = 0;
   if (valid) {
-    d = a.C[v];
+    d = a.rec[v].c;
     Ki = a.K[v];
     for (int s = lane; s < H; s += G) {
       const int32_t c = gk[s];
@@ -688,7 +720,7 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
         continue;
       }
       nc++;
-      const T g = Ar::of(a.W, kv, Ki, a.Sig[c]);
+      const T g = Ar::of(a.W, kv, Ki, a.rec[c].sig);
       if (better(g, c, bg, bc)) {
         bg = g;
         bc = c;
@@ -732,8 +764,9 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
   if (valid && lane == 0) {
     int32_t target = d;
     if (bc != INT32_MAX) {
-      const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
-      if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
+      const VRec rd = a.rec[d];
+      const T stay = Ar::of(a.W, kd, Ki, rd.sig - Ki);
+      if (bg > stay && !(rd.size == 1 && a.rec[bc].size == 1 && bc > d)) {
         target = bc;
         moved = 1;
         gain = Ar::diff(bg, stay);
@@ -742,6 +775,115 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
     a.tgt[v] = target;
   }
   // block totals go to this block's own record: no contended atomics in the hot kernel
+  const u128 bsum = block_sum_u128(gain, sh.red128);
+  const ull bm = block_sum_u64(moved, sh.red64);
+  const ull bn = block_sum_u64(nc, sh.red64);
+  if (threadIdx.x == 0) {
+    ull* o = a.partial + 4 * (int64_t)blockIdx.x;
+    o[0] = (ull)bsum;
+    o[1] = (ull)(bsum >> 64);
+    o[2] = bm;
+    o[3] = bn;
+  }
+}
+
+// Rows of at most MAXD arcs: one thread per vertex. The communities of the neighbours and their
+// weights stay in registers; repeats are combined into the first occurrence. When a candidate
+// community is labelled by the neighbour that shows it (C[j] = j), its Sigma and size come with
+// that neighbour's record and need no further load.
+template <bool WIDE, typename WT, int MAXD>
+__device__ __forceinline__ void move_regs(const MoveArgs<WT>& a, int64_t lb, int64_t lbase,
+                                          int64_t lcount, BlockShared& sh) {
+  typedef Gain<WIDE> Ar;
+  typedef typename Ar::T T;
+  const int64_t li = lb * kBlock + threadIdx.x;
+  u128 gain = 0;
+  ull moved = 0, nc = 0;
+  if (li < lcount) {
+    const int32_t v = a.list[lbase + li];
+    const int64_t e0 = a.rs[v];
+    const int L = (int)(a.re[v] - e0);
+    const VRec rv = a.rec[v];
+    const uint64_t Ki = a.K[v];
+    int32_t key[MAXD];
+    ull kw[MAXD], sg[MAXD];
+    int32_t sz[MAXD];
+    bool known[MAXD];
+#pragma unroll
+    for (int i = 0; i < MAXD; i++) {
+      key[i] = kEmpty;
+      kw[i] = 0;
+      sg[i] = 0;
+      sz[i] = 0;
+      known[i] = false;
+      if (i < L) {
+        const int32_t j = ld_stream(a.idx + e0 + i);
+        const ull wv = (ull)ld_stream(a.w + e0 + i);
+        if (j != v) {
+          const VRec rj = a.rec[j];
+          key[i] = rj.c;
+          kw[i] = wv;
+          if (rj.c == j) {
+            known[i] = true;
+            sg[i] = rj.sig;
+            sz[i] = rj.size;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 1; i < MAXD; i++) {
+#pragma unroll
+      for (int p = 0; p < i; p++) {
+        if (key[i] != kEmpty && key[p] == key[i]) {
+          kw[p] += kw[i];
+          if (known[i] && !known[p]) {
+            known[p] = true;
+            sg[p] = sg[i];
+            sz[p] = sz[i];
+          }
+          key[i] = kEmpty;
+        }
+      }
+    }
+    const int32_t d = rv.c;
+    ull kd = 0;
+    T bg = Ar::lowest();
+    int32_t bc = INT32_MAX;
+    bool bknown = false;
+    int32_t bsize = 0;
+#pragma unroll
+    for (int i = 0; i < MAXD; i++) {
+      if (key[i] == kEmpty) continue;
+      if (key[i] == d) {
+        kd = kw[i];
+        continue;
+      }
+      nc++;
+      const ull sc = known[i] ? sg[i] : a.rec[key[i]].sig;
+      const T g = Ar::of(a.W, kw[i], Ki, sc);
+      if (better(g, key[i], bg, bc)) {
+        bg = g;
+        bc = key[i];
+        bknown = known[i];
+        bsize = sz[i];
+      }
+    }
+    int32_t target = d;
+    if (bc != INT32_MAX) {
+      const VRec rd = d == v ? rv : a.rec[d];
+      const T stay = Ar::of(a.W, kd, Ki, rd.sig - Ki);
+      if (bg > stay) {
+        const int32_t bs = bknown ? bsize : a.rec[bc].size;
+        if (!(rd.size == 1 && bs == 1 && bc > d)) {
+          target = bc;
+          moved = 1;
+          gain = Ar::diff(bg, stay);
+        }
+      }
+    }
+    a.tgt[v] = target;
+  }
   const u128 bsum = block_sum_u128(gain, sh.red128);
   const ull bm = block_sum_u64(moved, sh.red64);
   const ull bn = block_sum_u64(nc, sh.red64);
@@ -764,8 +906,8 @@ __global__ __launch_bounds__(kBlock) void k_move_lds(MoveArgs<WT> a) {
   const int64_t lb = b - a.bstart[k];
   const int64_t lbase = a.lstart[k], lcount = a.lstart[k + 1] - a.lstart[k];
   switch (k) {
-    case 0: move_group<WIDE, WT, bucket_group(0), bucket_log2h(0)>(a, lb, lbase, lcount, smem, sh); break;
-    case 1: move_group<WIDE, WT, bucket_group(1), bucket_log2h(1)>(a, lb, lbase, lcount, smem, sh); break;
+    case 0: move_regs<WIDE, WT, 4>(a, lb, lbase, lcount, sh); break;
+    case 1: move_regs<WIDE, WT, 8>(a, lb, lbase, lcount, sh); break;
     case 2: move_group<WIDE, WT, bucket_group(2), bucket_log2h(2)>(a, lb, lbase, lcount, smem, sh); break;
     case 3: move_group<WIDE, WT, bucket_group(3), bucket_log2h(3)>(a, lb, lbase, lcount, smem, sh); break;
     case 4: move_group<WIDE, WT, bucket_group(4), bucket_log2h(4)>(a, lb, lbase, lcount, smem, sh); break;
@@ -774,34 +916,32 @@ __global__ __launch_bounds__(kBlock) void k_move_lds(MoveArgs<WT> a) {
   }
 }
 
-// Sum of the move kernel's per-block records into the class step's statistics: [0..1] gain sum,
-// [2] moves, [3] candidate pairs, with [4], [5] repeating [3], [2] for the LDS kernel alone.
+// Sum of the move kernels' per-block records into the class step's statistics: [0..1] gain
+// sum, [2] moves, [3] candidate pairs, [4] those of the fused kernel (records < nfused),
+// [5] those of the workgroup kernel.
 __global__ __launch_bounds__(kBlock) void k_reduce_move_partials(const ull* part, int64_t nb,
-                                                                ull* stats) {
+                                                                int64_t nfused, ull* stats) {
   __shared__ u128 red[kBlock / 64];
   __shared__ ull red64[kBlock / 64];
   u128 sg = 0;
-  ull sm = 0, sc = 0;
+  ull sm = 0, sf = 0, sw = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nb;
        i += (int64_t)gridDim.x * blockDim.x) {
     const ull* p = part + 4 * i;
     sg += ((u128)p[1] << 64) | p[0];
     sm += p[2];
-    sc += p[3];
+    if (i < nfused) sf += p[3]; else sw += p[3];
   }
   sg = block_sum_u128(sg, red);
   sm = block_sum_u64(sm, red64);
-  sc = block_sum_u64(sc, red64);
+  sf = block_sum_u64(sf, red64);
+  sw = block_sum_u64(sw, red64);
   if (threadIdx.x == 0) {
     if (sg) atomic_add_u128(stats, sg);
-    if (sm) {
-      atomicAdd(&stats[2], sm);
-      atomicAdd(&stats[5], sm);
-    }
-    if (sc) {
-      atomicAdd(&stats[3], sc);
-      atomicAdd(&stats[4], sc);
-    }
+    if (sm) atomicAdd(&stats[2], sm);
+    if (sf + sw) atomicAdd(&stats[3], sf + sw);
+    if (sf) atomicAdd(&stats[4], sf);
+    if (sw) atomicAdd(&stats[5], sw);
   }
 }
 
@@ -816,9 +956,7 @@ struct WgArgs {
   const int32_t* idx;
   const WT* w;
   const uint64_t* K;
-  const int32_t* C;
-  const uint64_t* Sig;
-  const int32_t* csize;
+  const VRec* rec;
   uint64_t W;
   const int32_t* rows;  // the class's rows
   int32_t* tgt;
@@ -849,10 +987,10 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kWgBlock) {
     const int32_t j = ld_stream(a.idx + e);
     const V wv = (V)ld_stream(a.w + e);
-    if (j != v) table_add<V>(keys, vals, LOG2H, a.C[j], wv);
+    if (j != v) table_add<V>(keys, vals, LOG2H, a.rec[j].c, wv);
   }
   __syncthreads();
-  const int32_t d = a.C[v];
+  const int32_t d = a.rec[v].c;
   const uint64_t Ki = a.K[v];
   T bg = Ar::lowest();
   int32_t bc = INT32_MAX;
@@ -866,7 +1004,7 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
       continue;
     }
     nc++;
-    const T g = Ar::of(a.W, kv, Ki, a.Sig[c]);
+    const T g = Ar::of(a.W, kv, Ki, a.rec[c].sig);
     if (better(g, c, bg, bc)) {
       bg = g;
       bc = c;
@@ -905,8 +1043,9 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
     u128 gain = 0;
     ull moved = 0;
     if (bc != INT32_MAX) {
-      const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
-      if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
+      const VRec rd = a.rec[d];
+      const T stay = Ar::of(a.W, kd, Ki, rd.sig - Ki);
+      if (bg > stay && !(rd.size == 1 && a.rec[bc].size == 1 && bc > d)) {
         target = bc;
         moved = 1;
         gain = Ar::diff(bg, stay);
@@ -943,22 +1082,30 @@ static hipError_t launch_wg(const WgArgs<WT>& a, int64_t rows, hipStream_t s) {
   return hipGetLastError();
 }
 
+static int64_t fused_blocks(const Buckets& b, int cls) {
+  int64_t blocks = 0;
+  for (int k = 0; k < kFusedClasses; k++) {
+    const int64_t rpb = move_rows_per_block(k);
+    blocks += (b.count[kDegClasses * cls + k] + rpb - 1) / rpb;
+  }
+  return blocks;
+}
+
 static size_t lds_table_bytes(int k, size_t vbytes) {
-  return (size_t)bucket_rows_per_block(k) * ((size_t)1 << bucket_log2h(k)) * (4 + vbytes);
+  if (move_group_size(k) == 1) return 0;  // register path
+  return (size_t)move_rows_per_block(k) * ((size_t)1 << bucket_log2h(k)) * (4 + vbytes);
 }
 
 template <bool WIDE, typename WT>
-static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
-                             hipStream_t s) {
+static hipError_t move_fused_t(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
+                               hipStream_t s) {
   MoveArgs<WT> a;
   a.rs = g.rs;
   a.re = g.re;
   a.idx = g.idx;
   a.w = (const WT*)g.w;
   a.K = m.K;
-  a.C = m.C;
-  a.Sig = m.Sig;
-  a.csize = m.csize;
+  a.rec = (const VRec*)m.rec;
   a.W = m.W;
   a.list = m.list;
   a.tgt = m.tgt;
@@ -969,7 +1116,7 @@ static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const
   for (int k = 0; k < kFusedClasses; k++) {
     a.bstart[k] = blocks;
     a.lstart[k] = b.lstart[base + k];
-    const int64_t rpb = bucket_rows_per_block(k);
+    const int64_t rpb = move_rows_per_block(k);
     blocks += (b.count[base + k] + rpb - 1) / rpb;
     if (b.count[base + k]) {
       size_t t = lds_table_bytes(k, sizeof(typename Gain<WIDE>::V));
@@ -979,16 +1126,22 @@ static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const
   a.bstart[7] = blocks;
   a.lstart[7] = b.lstart[base + kFusedClasses];
   if (blocks > 0) LV_LAUNCH((k_move_lds<WIDE, WT>), (unsigned)blocks, kBlock, shm, s, a);
-  int64_t records = blocks;
+  return hipGetLastError();
+}
+
+template <bool WIDE, typename WT>
+static hipError_t move_wg_t(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
+                            hipStream_t s) {
+  const int base = kDegClasses * cls;
+  const int64_t fused = fused_blocks(b, cls);
+  int64_t records = fused;
   WgArgs<WT> wa;
   wa.rs = g.rs;
   wa.re = g.re;
   wa.idx = g.idx;
   wa.w = (const WT*)g.w;
   wa.K = m.K;
-  wa.C = m.C;
-  wa.Sig = m.Sig;
-  wa.csize = m.csize;
+  wa.rec = (const VRec*)m.rec;
   wa.W = m.W;
   wa.tgt = m.tgt;
   for (int k = kFusedClasses; k < m.hub_first; k++) {
@@ -1005,27 +1158,32 @@ static hipError_t move_lds_t(const DevGraph& g, const Buckets& b, int cls, const
   }
   if (records == 0) return hipSuccess;
   LV_LAUNCH(k_reduce_move_partials, grid_for(records, kBlock, 256), kBlock, 0, s,
-            m.block_partial, records, m.stats);
+            m.block_partial, records, fused, m.stats);
   return hipGetLastError();
 }
 
 int64_t move_lds_blocks(const Buckets& b, int cls, int hub_first) {
-  int64_t blocks = 0;
-  for (int k = 0; k < kFusedClasses; k++) {
-    const int64_t rpb = bucket_rows_per_block(k);
-    blocks += (b.count[kDegClasses * cls + k] + rpb - 1) / rpb;
-  }
+  int64_t blocks = fused_blocks(b, cls);
   for (int k = kFusedClasses; k < hub_first; k++) blocks += b.count[kDegClasses * cls + k];
   return blocks;
 }
 
-hipError_t move_lds(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
-                    bool wide, hipStream_t s) {
+hipError_t move_fused(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
+                      bool wide, hipStream_t s) {
   if (wide)
-    return g.w64 ? move_lds_t<true, uint64_t>(g, b, cls, m, s)
-                 : move_lds_t<true, uint32_t>(g, b, cls, m, s);
-  return g.w64 ? move_lds_t<false, uint64_t>(g, b, cls, m, s)
-               : move_lds_t<false, uint32_t>(g, b, cls, m, s);
+    return g.w64 ? move_fused_t<true, uint64_t>(g, b, cls, m, s)
+                 : move_fused_t<true, uint32_t>(g, b, cls, m, s);
+  return g.w64 ? move_fused_t<false, uint64_t>(g, b, cls, m, s)
+               : move_fused_t<false, uint32_t>(g, b, cls, m, s);
+}
+
+hipError_t move_wg(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m, bool wide,
+                   hipStream_t s) {
+  if (wide)
+    return g.w64 ? move_wg_t<true, uint64_t>(g, b, cls, m, s)
+                 : move_wg_t<true, uint32_t>(g, b, cls, m, s);
+  return g.w64 ? move_wg_t<false, uint64_t>(g, b, cls, m, s)
+               : move_wg_t<false, uint32_t>(g, b, cls, m, s);
 }
 
 // =============================================================================================
@@ -1091,9 +1249,7 @@ struct HubArgs {
   const int32_t* idx;
   const WT* w;
   const uint64_t* K;
-  const int32_t* C;
-  const uint64_t* Sig;
-  const int32_t* csize;
+  const VRec* rec;
   uint64_t W;
   const int32_t* hubs;
   int64_t nh;
@@ -1125,7 +1281,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_accumulate(HubArgs<WT, V> a) {
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
     const int32_t j = ld_stream(a.idx + e);
     const V wv = (V)ld_stream(a.w + e);
-    if (j != v) table_add<V>(lk, lv, kHubLdsLog2, a.C[j], wv);
+    if (j != v) table_add<V>(lk, lv, kHubLdsLog2, a.rec[j].c, wv);
   }
   hub_flush<V>(lk, lv, a.tkeys + ts, a.tvals + ts, lg, a.occ + ts, a.occ_count + h);
 }
@@ -1145,7 +1301,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_scan(HubArgs<WT, typename Gain<W
   const int64_t cnt = a.occ_count[h];
   const int64_t p0 = (b - a.scan_start[h]) * kHubScanChunk;
   const int64_t p1 = p0 + kHubScanChunk < cnt ? p0 + kHubScanChunk : cnt;
-  const int32_t d = a.C[v];
+  const int32_t d = a.rec[v].c;
   const uint64_t Ki = a.K[v];
   T bg = Ar::lowest();
   int32_t bc = INT32_MAX;
@@ -1161,7 +1317,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_scan(HubArgs<WT, typename Gain<W
       continue;
     }
     nc++;
-    const T g = Ar::of(a.W, kv, Ki, a.Sig[c]);
+    const T g = Ar::of(a.W, kv, Ki, a.rec[c].sig);
     if (better(g, c, bg, bc)) {
       bg = g;
       bc = c;
@@ -1232,12 +1388,13 @@ __global__ __launch_bounds__(kBlock) void k_hub_decide(HubArgs<WT, typename Gain
       nc += in[4];
     }
     a.occ_count[h] = 0;
-    const int32_t d = a.C[v];
+    const int32_t d = a.rec[v].c;
     int32_t target = d;
     if (bc != INT32_MAX) {
       const uint64_t Ki = a.K[v];
-      const T stay = Ar::of(a.W, kd, Ki, a.Sig[d] - Ki);
-      if (bg > stay && !(a.csize[d] == 1 && a.csize[bc] == 1 && bc > d)) {
+      const VRec rd = a.rec[d];
+      const T stay = Ar::of(a.W, kd, Ki, rd.sig - Ki);
+      if (bg > stay && !(rd.size == 1 && a.rec[bc].size == 1 && bc > d)) {
         gain = Ar::diff(bg, stay);
         target = bc;
         atomicAdd(&a.stats[2], 1ull);
@@ -1288,9 +1445,7 @@ static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, cons
   a.idx = g.idx;
   a.w = (const WT*)g.w;
   a.K = m.K;
-  a.C = m.C;
-  a.Sig = m.Sig;
-  a.csize = m.csize;
+  a.rec = (const VRec*)m.rec;
   a.W = m.W;
   a.hubs = m.list + b.lstart[kDegClasses * cls + m.hub_first];
   a.nh = hp.nh;
@@ -1323,19 +1478,19 @@ hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const HubPlan
 // Apply a class step's decisions: C, Sigma and csize after the step. Integer atomics commute,
 // so the result is independent of the order of the movers.
 __global__ void k_apply_moves(const int32_t* verts, int64_t count, const int32_t* tgt,
-                              const uint64_t* K, int32_t* C, uint64_t* Sig, int32_t* csize) {
+                              const uint64_t* K, VRec* rec) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = verts[i];
     const int32_t c = tgt[v];
-    const int32_t d = C[v];
+    const int32_t d = rec[v].c;
     if (c == d) continue;
     const ull k = (ull)K[v];
-    C[v] = c;
-    atomicAdd((ull*)&Sig[c], k);
-    atomicAdd((ull*)&Sig[d], (ull)(0ull - k));
-    atomicAdd(&csize[c], 1);
-    atomicSub(&csize[d], 1);
+    rec[v].c = c;
+    atomicAdd(&rec[c].sig, k);
+    atomicAdd(&rec[d].sig, (ull)(0ull - k));
+    atomicAdd(&rec[c].size, 1);
+    atomicSub(&rec[d].size, 1);
   }
 }
 
@@ -1344,7 +1499,7 @@ hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStrea
   const int64_t count = b.lstart[kDegClasses * cls + kDegClasses] - first;
   if (count <= 0) return hipSuccess;
   LV_LAUNCH(k_apply_moves, grid_for(count, kBlock, 8192), kBlock, 0, s, m.list + first, count,
-            m.tgt, m.K, m.C, m.Sig, m.csize);
+            m.tgt, m.K, (VRec*)m.rec);
   return hipGetLastError();
 }
 

@@ -61,21 +61,27 @@ class LvIterTrace(ctypes.Structure):
         ("iteration", ctypes.c_int32),
         ("wide", ctypes.c_int32),
         ("substeps", ctypes.c_int32),
-        ("lds_launches", ctypes.c_int32),
+        ("fused_launches", ctypes.c_int32),
+        ("wg_launches", ctypes.c_int32),
         ("hub_launches", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("gain_sum", LvI128),
         ("moved", ctypes.c_int64),
         ("candidates", ctypes.c_int64),
-        ("lds_vertices", ctypes.c_int64),
-        ("lds_arcs", ctypes.c_int64),
+        ("fused_vertices", ctypes.c_int64),
+        ("fused_arcs", ctypes.c_int64),
+        ("fused_candidates", ctypes.c_int64),
+        ("wg_vertices", ctypes.c_int64),
+        ("wg_arcs", ctypes.c_int64),
+        ("wg_candidates", ctypes.c_int64),
         ("hub_vertices", ctypes.c_int64),
         ("hub_arcs", ctypes.c_int64),
-        ("lds_candidates", ctypes.c_int64),
-        ("lds_moved", ctypes.c_int64),
-        ("move_ms", ctypes.c_float),
+        ("fused_ms", ctypes.c_float),
+        ("wg_ms", ctypes.c_float),
         ("hub_ms", ctypes.c_float),
         ("update_ms", ctypes.c_float),
         ("iter_ms", ctypes.c_float),
+        ("reserved2", ctypes.c_float),
     ]
 
 
@@ -199,13 +205,15 @@ def result_dict(r: LvResult) -> dict:
         x = r.trace[t]
         tr.append({
             "pass": x.pass_, "iteration": x.iteration, "wide": x.wide, "substeps": x.substeps,
-            "lds_launches": x.lds_launches, "hub_launches": x.hub_launches,
+            "fused_launches": x.fused_launches, "wg_launches": x.wg_launches,
+            "hub_launches": x.hub_launches,
             "S": x.gain_sum.value(), "moved": x.moved, "candidates": x.candidates,
-            "lds_vertices": x.lds_vertices, "lds_arcs": x.lds_arcs,
+            "fused_vertices": x.fused_vertices, "fused_arcs": x.fused_arcs,
+            "fused_candidates": x.fused_candidates,
+            "wg_vertices": x.wg_vertices, "wg_arcs": x.wg_arcs, "wg_candidates": x.wg_candidates,
             "hub_vertices": x.hub_vertices, "hub_arcs": x.hub_arcs,
-            "lds_candidates": x.lds_candidates, "lds_moved": x.lds_moved,
-            "move_ms": x.move_ms, "hub_ms": x.hub_ms, "update_ms": x.update_ms,
-            "iter_ms": x.iter_ms,
+            "fused_ms": x.fused_ms, "wg_ms": x.wg_ms, "hub_ms": x.hub_ms,
+            "update_ms": x.update_ms, "iter_ms": x.iter_ms,
         })
     return {
         "passes": P,

@@ -62,8 +62,9 @@ int main(void) {
   S(lv_graph) F(lv_graph, nnz) F(lv_graph, offsets) F(lv_graph, indices) F(lv_graph, weights)
   F(lv_graph, offsets_64) F(lv_graph, weights_64)
   S(lv_params) F(lv_params, flags)
-  S(lv_iter_trace) F(lv_iter_trace, lds_launches) F(lv_iter_trace, gain_sum) F(lv_iter_trace, lds_candidates)
-  F(lv_iter_trace, move_ms) F(lv_iter_trace, iter_ms)
+  S(lv_iter_trace) F(lv_iter_trace, wg_launches) F(lv_iter_trace, gain_sum)
+  F(lv_iter_trace, fused_candidates) F(lv_iter_trace, hub_arcs) F(lv_iter_trace, fused_ms)
+  F(lv_iter_trace, iter_ms)
   S(lv_result) F(lv_result, iterations) F(lv_result, n_pass) F(lv_result, qnum_pass)
   F(lv_result, cap_hits) F(lv_result, n_communities) F(lv_result, W) F(lv_result, q_num)
   F(lv_result, q) F(lv_result, total_ms) F(lv_result, aggregate_ms) F(lv_result, trace)
