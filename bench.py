@@ -131,6 +131,95 @@ def cpu_baseline(g, res_trace, seconds, substeps, n_arcs_input):
     }
 
 
+def _read_csv(path):
+    import csv
+    import gzip
+    opener = gzip.open if path.endswith(".gz") else open
+    with opener(path, "rt") as f:
+        return list(csv.DictReader(f))
+
+
+def _short_name(name):
+    name = name.replace("lv::", "")
+    return name.split("(")[0] if "(" in name else name
+
+
+def summarize_stats(csv_path, out_path, command):
+    """Markdown summary of a `rocprofv3 --kernel-trace --stats` kernel_stats.csv."""
+    rows = _read_csv(csv_path)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows if "lv::" in r["Name"])
+    lines = ["# Kernel time, R-MAT scale 25 Louvain runs", "",
+             "Made by:", "", "```", command, "```", "",
+             f"Library kernels total: {total / 1e6:.1f} ms over all profiled runs "
+             "(warm-up and timed steps).", "",
+             "| kernel | calls | total ms | average us | share |",
+             "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        if "lv::" not in r["Name"]:
+            continue
+        t = float(r["TotalDurationNs"])
+        lines.append(f"| `{_short_name(r['Name'])}` | {int(r['Calls'])} | {t / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {100 * t / total:.1f}% |")
+    open(out_path, "w").write("\n".join(lines) + "\n")
+
+
+def summarize_pmc(fetch_csv, write_csv, bench_json, out_path, command, workload, copy_mib):
+    """Markdown summary of the FETCH_SIZE and WRITE_SIZE passes: per-launch HBM bytes of
+    k_move_lds, each counter scaled by what it reads for the plain copy of copy_mib MiB."""
+    import numpy as np
+    per = {}
+    for ctr, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in _read_csv(path) if r["Counter_Name"] == ctr]
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+                and int(r["Grid_Size"]) > 0]
+        if not copy:
+            raise SystemExit(f"{path}: no calibration copy dispatch")
+        copy_kib = max(copy)
+        scale = copy_mib * 1024.0 / copy_kib
+        by_kernel = {}
+        for r in rows:
+            by_kernel.setdefault(_short_name(r["Kernel_Name"]), []).append(
+                float(r["Counter_Value"]))
+        per[ctr] = {"copy_raw_kib": copy_kib, "scale": scale, "by_kernel": by_kernel}
+    key = [k for k in per["FETCH_SIZE"]["by_kernel"] if k.startswith("void k_move_lds")]
+    fetch = np.concatenate([per["FETCH_SIZE"]["by_kernel"][k] for k in key])
+    write = np.concatenate([per["WRITE_SIZE"]["by_kernel"][k] for k in key])
+    fs, ws = per["FETCH_SIZE"]["scale"], per["WRITE_SIZE"]["scale"]
+    fetch_b = float(fetch.mean()) * 1024 * fs
+    write_b = float(write.mean()) * 1024 * ws
+    bj = json.load(open(bench_json))
+    alg = bj["roofline"]["algorithmic_bytes_per_launch"]
+    d = {"workload": workload, "kernel": "k_move_lds", "kernel_src_sha256": kernel_src_sha(),
+         "launches": int(fetch.size),
+         "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+         "bytes_per_launch": fetch_b + write_b,
+         "algorithmic_bytes_per_launch": alg,
+         "calibration": {"copy_bytes": copy_mib << 20,
+                         "fetch_raw_kib": per["FETCH_SIZE"]["copy_raw_kib"], "fetch_scale": fs,
+                         "write_raw_kib": per["WRITE_SIZE"]["copy_raw_kib"], "write_scale": ws}}
+    lines = [f"# HBM traffic of k_move_lds, {workload}", "",
+             "Made by (one counter per run, then this summary):", "", "```", command, "```", "",
+             f"Calibration: a plain device copy of {copy_mib} MiB reads FETCH_SIZE = "
+             f"{per['FETCH_SIZE']['copy_raw_kib']:.0f} KiB and WRITE_SIZE = "
+             f"{per['WRITE_SIZE']['copy_raw_kib']:.0f} KiB, so the counters are scaled by "
+             f"{fs:.3f} and {ws:.3f}.", "",
+             f"k_move_lds over {fetch.size} launches: {fetch_b / 1e6:.1f} MB fetched and "
+             f"{write_b / 1e6:.1f} MB written per launch, against {alg / 1e6:.1f} MB of "
+             f"algorithmic bytes ({(fetch_b + write_b) / alg:.2f}x).", "",
+             "| kernel | launches | fetch MB / launch | write MB / launch |",
+             "|---|---:|---:|---:|"]
+    fk = per["FETCH_SIZE"]["by_kernel"]
+    wk = per["WRITE_SIZE"]["by_kernel"]
+    tops = sorted(fk, key=lambda k: -sum(fk[k]))[:12]
+    for k in tops:
+        f = np.mean(fk[k]) * 1024 * fs / 1e6
+        w = np.mean(wk.get(k, [0.0])) * 1024 * ws / 1e6
+        lines.append(f"| `{k.replace('void ', '')}` | {len(fk[k])} | {f:.1f} | {w:.1f} |")
+    lines += ["", "```json", json.dumps(d, indent=1), "```"]
+    open(out_path, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,12 +237,26 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the timed region, copy a buffer of this many MiB once (a plain "
                          "copy kernel of known size, to scale profiler byte counters)")
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("KERNEL_STATS_CSV", "OUT_MD"),
+                    help="write a markdown summary of a rocprofv3 --stats run and exit")
+    ap.add_argument("--summarize-pmc", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "OUT_MD"),
+                    help="write the k_move_lds HBM-traffic summary of two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE; with --copy-calibration-mib) and exit")
+    ap.add_argument("--command", default="", help="command text recorded in a summary")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats, args.command)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.command, args.workload,
+                      args.copy_calibration_mib or 1024)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the method would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
