@@ -22,5 +22,6 @@ from .generators import (  # noqa: F401
     single_edge,
     erdos_renyi,
     add_self_loops,
+    planted_hubs,
     config_graph,
 )

@@ -19,6 +19,7 @@ _T_SBM_IN = 4
 _T_SBM_OUT = 5
 _T_LAT = 6
 _T_ER = 7
+_T_HUBS = 8
 
 
 def _pair_weights(key: int, n: int, wmin: int, wmax: int):
@@ -243,6 +244,33 @@ def erdos_renyi(n: int, p: float, seed: int = 1, weights=(1, 1), self_loops: boo
         wfn = _pair_weights(stream_key(seed, _T_WEIGHT, n, 11), n, weights[0], weights[1])
     return csr_from_edges(n, u, v, wfn, offsets_dtype=offsets_dtype, keep_self_loops=self_loops,
                           name=f"er-n{n}-p{p}-seed{seed}")
+
+
+def planted_hubs(base: Csr, hub_degrees, seed: int = 1, weights=(1, 1)) -> Csr:
+    """``base`` plus hub vertices: hub i (vertex (i * 7919 + 1) mod n) gets edges to
+    hub_degrees[i] uniform random vertices (repeats collapse, so its degree is at most that).
+    Gives power-law-like rows far longer than one workgroup's table on a small graph."""
+    n = base.n
+    dev = base.device
+    o = base.offsets.to(torch.int64)
+    src = torch.repeat_interleave(torch.arange(n, dtype=torch.int64, device=dev), o[1:] - o[:-1])
+    dst = base.indices.to(torch.int64)
+    keep = src < dst
+    us, vs = [src[keep]], [dst[keep]]
+    key = stream_key(seed, _T_HUBS, n, len(hub_degrees))
+    start = 0
+    for i, d in enumerate(hub_degrees):
+        h = (i * 7919 + 1) % n
+        ctr = torch.arange(start, start + d, dtype=torch.int64, device=dev)
+        start += d
+        us.append(torch.full((d,), h, dtype=torch.int64, device=dev))
+        vs.append(below(draw(key, ctr), n))
+    wfn = None
+    if weights != (1, 1):
+        wfn = _pair_weights(stream_key(seed, _T_WEIGHT, n, 12), n, weights[0], weights[1])
+    return csr_from_edges(n, torch.cat(us), torch.cat(vs), wfn,
+                          offsets_dtype=base.offsets.dtype,
+                          name=f"{base.name}+hubs{list(hub_degrees)}-seed{seed}")
 
 
 def add_self_loops(g: Csr, weight: int = 1) -> Csr:

@@ -84,6 +84,10 @@ typedef struct {
 #define LV_TRACE 0x2u      /* time the kernels of every iteration with HIP events */
 #define LV_FORCE_WIDE 0x4u /* use 128-bit gains and 64-bit table values even when 64-bit
                               gains are exact (results are identical; for testing) */
+#define LV_SMALL_PARTS 0x8u /* split long rows and large communities into many hash
+                               partitions with tiny workgroup tables, so that the partitioned
+                               and multi-round code paths run on small graphs (results are
+                               identical; slower; for testing) */
 
 typedef struct {
   int32_t tolerance_exp10; /* initial tolerance 10^-a, a >= 0 (paper's best: a = 2) */

@@ -8,6 +8,7 @@ ABI in ``include/louvain.h``. ``louvain`` is the Python binding.
 
 from .louvain import (  # noqa: F401
     LV_FORCE_WIDE,
+    LV_SMALL_PARTS,
     LV_TRACE,
     LV_VALIDATE,
     Louvain,

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "../../include/louvain.h"
+#include "lv_device.h"
 #include "lv_internal.h"
 
 typedef unsigned long long ull;
@@ -20,7 +21,7 @@ namespace {
 
 enum SlotId {
   S_K, S_SIG, S_CSIZE, S_C, S_MAP, S_MOVERS, S_LIST, S_OFF64, S_STATS, S_COUNTS, S_SCANP,
-  S_HUBARR, S_TKEYS, S_TVALS, S_OCC, S_OCCCNT, S_PARTIAL, S_A, S_ASTART, S_NEWID, S_CURSOR,
+  S_HUBARR, S_PK, S_PV, S_HOFF, S_NFLUSH, S_PARTIAL, S_A, S_ASTART, S_NEWID, S_CURSOR,
   S_OLDLABEL, S_DCOUNT, S_ABASE, S_TKEY, S_TW, S_GOFF0, S_GIDX0, S_GW0, S_GOFF1, S_GIDX1, S_GW1,
   S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
   S_REC, S_COUNT_SLOTS
@@ -32,6 +33,9 @@ struct Slot {
 };
 
 }  // namespace
+
+// Partition size divisor (as a shift) under LV_SMALL_PARTS.
+constexpr int kSmallPartShift = 6;
 
 // Word offsets in the device stats slot and in the pinned host buffer.
 constexpr int ST_MISC = 256;      // device: [256, 264) scratch sums, 264 aggregation self-loops
@@ -53,6 +57,7 @@ struct lv_ctx {
   Slot slots[S_COUNT_SLOTS];
   std::string err;
   size_t max_lds = 65536;  // largest LDS allocation of one workgroup on this device
+  int part_shift = 0;      // LV_SMALL_PARTS of the current call
   ull* pinned = nullptr;  // host-pinned words for small read-backs
   hipEvent_t ev[kEvents] = {};  // kEvStep per class step, then 2 for aggregation
 };
@@ -234,7 +239,7 @@ lv_status weight_stats(lv_ctx* ctx, const uint64_t* K, int64_t n, hipStream_t s,
 struct Phase {
   lv::DevGraph g;
   lv::Buckets b;
-  lv::HubPlan hp[32];  // per vertex class
+  lv::PartPlan hp[32];  // per vertex class: two-phase plan of its hub rows
   lv::MoveBuffers m;
   bool wide = false;
   int classes = 1;
@@ -262,28 +267,31 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   };
   int64_t nh_total = 0;
   for (int k = 0; k < K; k++) nh_total += hub_rows(k);
-  CHK(wst(ctx, S_HUBARR, 6 * (nh_total + K), &hubarr));
-  lv::HubPlan big;  // largest tables of any class: the buffers are shared by the class steps
-  int64_t off = 0;
+  CHK(wst(ctx, S_HUBARR, lv::kPlanWords * (nh_total + K), &hubarr));
+  // the pair, bound and partial buffers are shared by the class steps: sized for the largest
+  const int vb = ph.wide ? 8 : 4;
+  int64_t max_chunks = 0, max_walkers = 0, max_parts = 0, max_hoff = 0, off = 0;
   for (int k = 0; k < K; k++) {
     const int64_t nh = hub_rows(k);
-    HIPCHK(lv::plan_hubs(ph.g.rs, ph.g.re, nullptr, list + ph.b.lstart[DEG * k + hf], nh, n,
-                         hubarr + off, scanp, ctx->pinned + PIN_HUB, ph.hp[k], s));
-    off += 6 * (nh + 1);
-    big.nh = std::max(big.nh, nh);
-    big.slots = std::max(big.slots, ph.hp[k].slots);
-    big.scan_blocks = std::max(big.scan_blocks, ph.hp[k].scan_blocks);
+    HIPCHK(lv::plan_parts(ph.g.rs, ph.g.re, nullptr, list + ph.b.lstart[DEG * k + hf], nh, n, vb,
+                          false, ctx->part_shift, hubarr + off, scanp, ctx->pinned + PIN_HUB,
+                          ph.hp[k], s));
+    off += lv::kPlanWords * (nh + 1);
+    max_chunks = std::max(max_chunks, ph.hp[k].chunks);
+    max_walkers = std::max(max_walkers, ph.hp[k].blocks);
+    max_parts = std::max(max_parts, ph.hp[k].parts);
+    max_hoff = std::max(max_hoff, ph.hp[k].hoff_entries);
   }
   ph.m.list = list;
-  if (big.nh > 0) {
-    CHK(wst(ctx, S_TKEYS, big.slots, &ph.m.tkeys));
-    ull* tv = nullptr;
-    CHK(wst(ctx, S_TVALS, big.slots, &tv));
-    ph.m.tvals = tv;
-    CHK(wst(ctx, S_OCC, big.slots, &ph.m.occ));
-    CHK(wst(ctx, S_OCCCNT, big.nh, &ph.m.occ_count));
-    CHK(wst(ctx, S_PARTIAL, 5 * big.scan_blocks, &ph.m.partial));
-    HIPCHK(lv::hub_reset_tables(big, ph.m, ph.wide, s));
+  if (max_chunks > 0) {
+    const int64_t pairs = max_chunks * lv::part_chunk(vb);
+    CHK(wst(ctx, S_PK, pairs, &ph.m.pk));
+    uint8_t* pv = nullptr;
+    CHK(wst(ctx, S_PV, pairs * vb, &pv));
+    ph.m.pv = pv;
+    CHK(wst(ctx, S_HOFF, max_hoff, &ph.m.hoff));
+    CHK(wst(ctx, S_NFLUSH, max_walkers, &ph.m.nflush));
+    CHK(wst(ctx, S_PARTIAL, 5 * max_parts, &ph.m.partial));
   }
   CHK(wst(ctx, S_MOVERS, n, &ph.m.tgt));
   int64_t max_blocks = 1;
@@ -470,15 +478,16 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   HIPCHK(lv::merge_lds(g, b, a, s));
   const int64_t nh = b.lstart[DEG] - b.lstart[7];  // communities of more than 1024 arcs
   if (nh > 0) {
-    lv::HubPlan hp;
-    CHK(wst(ctx, S_HUBARR, 6 * (nh + 1), &a.hub_arrays));
-    HIPCHK(lv::plan_hubs(nullptr, nullptr, a.A, a.list + b.lstart[7], nh, np, a.hub_arrays,
-                         a.partial, ctx->pinned + PIN_HUB, hp, s));
-    CHK(wst(ctx, S_TKEYS, hp.slots, &a.tkeys));
-    CHK(wst(ctx, S_TVALS, hp.slots, &a.tvals));
-    CHK(wst(ctx, S_OCC, hp.slots, &a.occ));
-    CHK(wst(ctx, S_OCCCNT, nh, &a.occ_count));
-    HIPCHK(lv::merge_hubs(g, b, hp, a, s));
+    lv::PartPlan pp;
+    CHK(wst(ctx, S_HUBARR, lv::kPlanWords * (nh + 1), &a.hub_arrays));
+    HIPCHK(lv::plan_parts(nullptr, nullptr, a.A, a.list + b.lstart[7], nh, np, 8, true,
+                          ctx->part_shift, a.hub_arrays, a.partial, ctx->pinned + PIN_HUB, pp, s));
+    const int64_t pairs = pp.chunks * lv::part_chunk(8);
+    CHK(wst(ctx, S_PK, pairs, &a.pk));
+    CHK(wst(ctx, S_PV, pairs, &a.pv));
+    CHK(wst(ctx, S_HOFF, pp.hoff_entries, &a.hoff));
+    CHK(wst(ctx, S_NFLUSH, pp.blocks, &a.nflush));
+    HIPCHK(lv::merge_hubs(g, b, pp, a, s));
   }
   HIPCHK(lv::sum_i64(a.dcount, np, a.stats + 1, s));
   HIPCHK(hipMemcpyAsync(hm, a.stats, 2 * sizeof(ull), hipMemcpyDeviceToHost, s));
@@ -527,6 +536,11 @@ lv_status louvain_ctx_create(int device, uint64_t hbm_budget_bytes, lv_ctx** out
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
           hipSuccess && lds > 0)
     ctx->max_lds = (size_t)lds;
+  // the two-phase kernels take part_lds_bytes(4) of dynamic LDS plus their own shared arrays
+  if (ctx->max_lds < lv::part_lds_bytes(4) + 4096) {
+    delete ctx;
+    return LV_EHIP;
+  }
   if (hipHostMalloc((void**)&ctx->pinned, PIN_WORDS * sizeof(ull), hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return LV_EHIP;
@@ -602,6 +616,7 @@ lv_status louvain_move(lv_ctx* ctx, const lv_graph* g, const uint64_t* Kin, uint
   HIPCHK(hipSetDevice(ctx->device));
   CHK(check_params(ctx, p));
   if (pass_index < 0) return fail(ctx, LV_EINVAL, "pass_index must be >= 0");
+  ctx->part_shift = (p->flags & LV_SMALL_PARTS) ? kSmallPartShift : 0;
   hipStream_t s = (hipStream_t)stream;
   Phase ph;
   CHK(import_graph(ctx, g, (p->flags & LV_VALIDATE) != 0, s, &ph.g));
@@ -656,6 +671,7 @@ lv_status louvain_aggregate(lv_ctx* ctx, const lv_graph* g, const int32_t* C, in
   if (!ctx) return LV_EINVAL;
   ctx->err.clear();
   HIPCHK(hipSetDevice(ctx->device));
+  ctx->part_shift = 0;
   hipStream_t s = (hipStream_t)stream;
   lv::DevGraph dg;
   CHK(import_graph(ctx, g, false, s, &dg));
@@ -697,6 +713,7 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
   HIPCHK(hipSetDevice(ctx->device));
   CHK(check_params(ctx, p));
   if (!res) return fail(ctx, LV_EINVAL, "res is NULL");
+  ctx->part_shift = (p->flags & LV_SMALL_PARTS) ? kSmallPartShift : 0;
   memset(res, 0, sizeof(*res));
   hipStream_t s = (hipStream_t)stream;
   lv::DevGraph g0;

@@ -82,10 +82,50 @@ struct __align__(16) VRec {
   unsigned long long sig;
 };
 
-// Hub rows use global-memory tables: accumulation blocks cover kHubChunk arcs each, and the
-// scan blocks cover kHubScanChunk occupied slots each.
-constexpr int64_t kHubChunk = 2048;
-constexpr int64_t kHubScanChunk = 2048;
+// Items too long for one workgroup's table (hub rows of the local-moving phase, communities with
+// many arcs in the aggregation) are combined in two phases of kPartBlock-thread workgroups.
+// Phase 1: each chunk of part_chunk(vb) arcs is combined in an LDS table of twice that many
+// slots, and its distinct keys are written out grouped by partition (the top bits of a
+// bijective hash of the key). Phase 2: one workgroup per (item, partition) combines the
+// partition's keys from every chunk in an LDS table of 2^part_log2h(vb) slots. vb is the byte
+// width of the summed values (4 or 8). Partitions are sized for half a table on average; a
+// partition that holds more distinct keys is processed in several rounds over sub-ranges of the
+// hash, which always ends because the hash is a bijection.
+constexpr int kPartBlock = 1024;
+constexpr int kMaxParts = 4096;
+constexpr int kPartTile = 1024;  // bound rows whose segments phase 2 holds in LDS at once
+__host__ __device__ constexpr int part_chunk(int vb) { return vb == 4 ? 8192 : 4096; }
+__host__ __device__ constexpr int part_log2h(int vb) { return vb == 4 ? 14 : 13; }
+// LDS of the phase kernels: keys, values, and kAuxInts ints of partition counters (phase 1) or
+// segment bounds (phase 2: an int64 start and an int length per row of a tile).
+constexpr int kAuxInts = kMaxParts + 4;
+static_assert(kAuxInts * 4 >= kPartTile * 12 + 4, "phase-2 segment tile fits the aux LDS");
+__host__ __device__ constexpr size_t part_lds_bytes(int vb) {
+  return ((size_t)1 << part_log2h(vb)) * (4 + (size_t)vb) + (size_t)kAuxInts * 4;
+}
+
+// Keys a phase-2 round may claim before it is abandoned: 3/4 of the table, or (testing shift)
+// a small fraction of the reduced partition size so that most partitions take several rounds.
+__host__ __device__ constexpr int part_cap(int log2h) { return 3 * (1 << log2h) / 4; }
+__host__ __device__ constexpr int part_round_cap(int log2h, int shift) {
+  return shift == 0 ? part_cap(log2h)
+                    : (((1 << log2h) >> (shift + 3)) > 8 ? ((1 << log2h) >> (shift + 3)) : 8);
+}
+
+// MurmurHash3's 32-bit finaliser (Appleby): a bijection on 32-bit values.
+__host__ __device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Partition of a key among 2^lp partitions.
+__device__ __forceinline__ int part_of(int32_t key, int lp) {
+  return lp == 0 ? 0 : (int)(fmix32((uint32_t)key) >> (32 - lp));
+}
 
 // ---------------------------------------------------------------------------------------------
 // Exact gains. Narrow: 64-bit, exact when W * max_i K_i < 2^63 (both products and their
@@ -132,6 +172,9 @@ __device__ __forceinline__ bool better(T g, int32_t c, T bg, int32_t bc) {
   return g > bg || (g == bg && c < bc);
 }
 
+// Marks a table slot whose community's Sigma was not seen with the key (Sigma <= W <= 2^62).
+constexpr unsigned long long kNoSig = ~0ull;
+
 // ---------------------------------------------------------------------------------------------
 // Open-addressing tables (linear probing, multiplicative hashing on the top bits).
 
@@ -155,6 +198,26 @@ __device__ __forceinline__ bool table_add(int32_t* keys, V* vals, int log2h, int
     }
     s = (s + 1u) & mask;
   }
+}
+
+// As table_add, for a table that may receive more keys than it can hold: once `cap` slots are
+// claimed (counted in *fresh), or when no free slot is found, *overflow is set and the table's
+// contents are to be discarded by the caller. Keys already present are still combined.
+template <typename V>
+__device__ __forceinline__ void table_add_capped(int32_t* keys, V* vals, int log2h, int32_t key,
+                                                 V w, int* fresh, int cap, int* overflow) {
+  const uint32_t mask = (1u << log2h) - 1u;
+  uint32_t s = slot_of(key, log2h);
+  for (uint32_t probe = 0; probe <= mask; probe++) {
+    const int32_t prev = atomicCAS(&keys[s], kEmpty, key);
+    if (prev == kEmpty || prev == key) {
+      atomicAdd(&vals[s], w);
+      if (prev == kEmpty && atomicAdd(fresh, 1) >= cap) atomicExch(overflow, 1);
+      return;
+    }
+    s = (s + 1u) & mask;
+  }
+  atomicExch(overflow, 1);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -27,16 +27,23 @@ struct Buckets {
   int64_t lstart[385] = {0};  // first list position per segment (lstart[12K] = total)
 };
 
-// Hub (global-table) work decomposition of one pass.
-struct HubPlan {
-  int64_t nh = 0;             // hub rows
-  int64_t chunks = 0;         // accumulation blocks
-  int64_t slots = 0;          // table slots (sum of per-row power-of-two sizes)
-  int64_t scan_blocks = 0;    // scan blocks
+// Two-phase decomposition of the long items of one launch (see part_chunk in lv_device.h).
+struct PartPlan {
+  int64_t nh = 0;             // items
+  int vb = 4;                 // value bytes (4 or 8)
+  int shift = 0;              // partitions sized for (table / 2) >> shift keys (testing: > 0)
+  int64_t chunks = 0;         // chunk rows (one pair region of part_chunk(vb) and bound row each)
+  int64_t blocks = 0;         // phase-1 workgroups
+  int64_t parts = 0;          // phase-2 workgroups
+  int64_t hoff_entries = 0;   // segment bounds
+  int64_t* rper = nullptr;         // [nh] chunks per phase-1 workgroup
+  int64_t* nparts = nullptr;       // [nh] partitions per item
   int64_t* chunk_start = nullptr;  // [nh+1]
-  int64_t* tab_start = nullptr;    // [nh+1]
-  int64_t* scan_start = nullptr;   // [nh+1]
+  int64_t* block_start = nullptr;  // [nh+1]
+  int64_t* part_start = nullptr;   // [nh+1]
+  int64_t* hoff_start = nullptr;   // [nh+1]
 };
+constexpr int64_t kPlanWords = 10;  // plan arrays: kPlanWords * (nh + 1) int64
 
 // ---- elementwise / reductions
 hipError_t fill_u64(uint64_t* a, uint64_t v, int64_t n, hipStream_t s);
@@ -77,11 +84,16 @@ hipError_t unpack_state(int64_t n, const void* rec, int32_t* C, uint64_t* Sig, i
 hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
                        int K, int pass, int32_t* list, unsigned long long* counts,
                        unsigned long long* host_counts, Buckets& b, hipStream_t s);
-// Hub decomposition of the rows hubs[0 .. nh) whose keys take at most `cap` distinct values.
-// arrays: 6 * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.
-hipError_t plan_hubs(const int64_t* rs, const int64_t* re, const int64_t* len,
-                     const int32_t* hubs, int64_t nh, int64_t cap, int64_t* arrays,
-                     int64_t* partial, unsigned long long* host_buf, HubPlan& hp, hipStream_t s);
+// Two-phase plan for the items items[0 .. nh) (lengths from rs/re, or len[item]) whose keys
+// take at most `cap` distinct values; vb: value bytes; merge: one-chunk items need no phase 2.
+// arrays: kPlanWords * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.
+// Synchronises the stream.
+// shift > 0 (testing) divides the partition size by 2^shift and caps the phase-2 tables so
+// that partitions take several rounds.
+hipError_t plan_parts(const int64_t* rs, const int64_t* re, const int64_t* len,
+                      const int32_t* items, int64_t nh, int64_t cap, int vb, bool merge,
+                      int shift, int64_t* arrays, int64_t* partial,
+                      unsigned long long* host_buf, PartPlan& pp, hipStream_t s);
 
 // ---- local-moving iteration
 struct MoveBuffers {
@@ -94,15 +106,15 @@ struct MoveBuffers {
   // per class step, 8 words: [0..1] S, [2] moved, [3] candidates, [4] candidates of the fused
   // kernel, [5] candidates of the workgroup kernel
   unsigned long long* stats = nullptr;
-  int32_t* tkeys = nullptr;             // hub tables
-  void* tvals = nullptr;
-  int32_t* occ = nullptr;
-  int32_t* occ_count = nullptr;
-  unsigned long long* partial = nullptr;  // hub scan partials: 5 words per scan block
-  int hub_first = 10;                     // first degree class on the global-table path
+  int32_t* pk = nullptr;                // hub phase-1 pairs (keys, values of the gain width)
+  void* pv = nullptr;
+  int32_t* hoff = nullptr;              // hub segment bounds
+  int32_t* nflush = nullptr;            // table flushes of every hub phase-1 workgroup
+  unsigned long long* partial = nullptr;  // hub phase-2 partials: 5 words per workgroup
+  int hub_first = 10;                     // first degree class on the two-phase hub path
 };
 
-// First degree class that takes the global-table path, given the largest LDS allocation a
+// First degree class that takes the two-phase hub path, given the largest LDS allocation a
 // workgroup may make and the table value width (wide: 8-byte values).
 int hub_first_class(size_t max_lds_per_block, bool wide);
 hipError_t zero_words(unsigned long long* a, int64_t n, hipStream_t s);
@@ -113,9 +125,8 @@ hipError_t move_fused(const DevGraph& g, const Buckets& b, int cls, const MoveBu
 // block records of both kernels into m.stats.
 hipError_t move_wg(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m, bool wide,
                    hipStream_t s);
-hipError_t hub_reset_tables(const HubPlan& hp, const MoveBuffers& m, bool wide, hipStream_t s);
 // Hub kernels over the hub rows of vertex class `cls` (plan hp made for those rows).
-hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const HubPlan& hp,
+hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const PartPlan& pp,
                      const MoveBuffers& m, bool wide, hipStream_t s);
 hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s);
 // Block records the LDS move kernels of class cls write (sizes block_partial).
@@ -151,11 +162,11 @@ struct AggBuffers {
   unsigned long long* counts = nullptr;  // 1536 words
   unsigned long long* stats = nullptr;   // [0] weight of self super-arcs
   unsigned long long* block_partial = nullptr;  // 1 word per block of the LDS merge kernel
-  int64_t* hub_arrays = nullptr;         // 6 * (hubs + 1)
-  int32_t* tkeys = nullptr;              // global tables (sized from the hub plan)
-  unsigned long long* tvals = nullptr;
-  int32_t* occ = nullptr;
-  int32_t* occ_count = nullptr;
+  int64_t* hub_arrays = nullptr;         // kPlanWords * (hubs + 1)
+  int32_t* pk = nullptr;                 // phase-1 pairs of the large communities
+  unsigned long long* pv = nullptr;
+  int32_t* hoff = nullptr;               // their segment bounds
+  int32_t* nflush = nullptr;             // table flushes of every phase-1 workgroup
 };
 // Renumbering, member lists and flat arc ranges (everything before the merge).
 hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t* csize,
@@ -163,7 +174,7 @@ hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t*
                              const AggBuffers& a, hipStream_t s);
 hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& a, hipStream_t s);
 int64_t merge_lds_blocks(const Buckets& b);  // sizes block_partial
-hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const HubPlan& hp,
+hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const PartPlan& pp,
                       const AggBuffers& a, hipStream_t s);
 // rs[a], re[a] of the super-vertex graph's rows in okey/ow
 hipError_t super_rows(int64_t np, const AggBuffers& a, int64_t* rs, int64_t* re, hipStream_t s);

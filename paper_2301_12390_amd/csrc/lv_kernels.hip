@@ -324,32 +324,60 @@ hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* pa
 
 constexpr int64_t kSeg = 16;
 
+// First r in [0, n] with off[r] >= e (off non-decreasing, n + 1 entries).
+__device__ __forceinline__ int64_t first_row_at(const int64_t* off, int64_t n, int64_t e) {
+  int64_t lo = 0, hi = n;  // off[hi] >= e; answer in [lo, hi]
+  if (off[0] >= e) return 0;
+  while (hi - lo > 1) {  // off[lo] < e <= off[hi]
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (off[mid] >= e) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+// Row sums without atomics: workgroup b owns the rows whose first arc lies in its range of
+// kRowTile arcs and sums each of them whole: rows of at most kShortRow arcs one per thread, longer
+// ones one per wavefront (coalesced). Rows of no arcs, and rows starting at nnz, keep K = 0.
+constexpr int64_t kRowTile = 4096;
+constexpr int64_t kShortRow = 32;
+
 template <typename WT>
 __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t n, int64_t nnz,
                                                     const WT* w, uint64_t* K) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t e0 = t * kSeg;
-  if (e0 >= nnz) return;
-  const int64_t e1 = e0 + kSeg < nnz ? e0 + kSeg : nnz;
-  int64_t r = row_of_arc(off, n, e0);
-  int64_t rend = off[r + 1];
-  ull acc = 0;
-  for (int64_t e = e0; e < e1; e++) {
-    if (e >= rend) {
-      if (acc) atomicAdd((ull*)&K[r], acc);
-      acc = 0;
-      r = advance_row(off, n, r + 1, e);
-      rend = off[r + 1];
+  __shared__ int64_t span[2];
+  __shared__ int32_t longs[kRowTile / kShortRow];
+  __shared__ int nlong;
+  const int64_t lo = (int64_t)blockIdx.x * kRowTile;
+  const int64_t hi = lo + kRowTile < nnz ? lo + kRowTile : nnz;
+  if (threadIdx.x < 2) span[threadIdx.x] = first_row_at(off, n, threadIdx.x == 0 ? lo : hi);
+  if (threadIdx.x == 0) nlong = 0;
+  __syncthreads();
+  const int64_t r0 = span[0], r1 = span[1];  // rows r0 .. r1-1 start in [lo, hi)
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
+    const int64_t e0 = off[r], e1 = off[r + 1];
+    if (e1 - e0 > kShortRow) {
+      longs[atomicAdd(&nlong, 1)] = (int32_t)(r - r0);
+      continue;
     }
-    acc += (ull)w[e];
+    ull acc = 0;
+    for (int64_t e = e0; e < e1; e++) acc += (ull)w[e];
+    K[r] = acc;
   }
-  if (acc) atomicAdd((ull*)&K[r], acc);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nlong; i += kBlock / 64) {
+    const int64_t r = r0 + longs[i];
+    const int64_t e0 = off[r], e1 = off[r + 1];
+    ull acc = 0;
+    for (int64_t e = e0 + lane; e < e1; e += 64) acc += (ull)ld_stream(w + e);
+    acc = group_sum_u64<64>(acc);
+    if (lane == 0) K[r] = acc;
+  }
 }
 
 hipError_t row_sums(const DevGraph& g, uint64_t* K, hipStream_t s) {
   if (g.nnz <= 0) return hipSuccess;
-  const int64_t threads = (g.nnz + kSeg - 1) / kSeg;
-  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
+  const unsigned grid = (unsigned)((g.nnz + kRowTile - 1) / kRowTile);
   if (g.w64)
     LV_LAUNCH(k_row_sums<uint64_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, (const uint64_t*)g.w,
               K);
@@ -583,54 +611,77 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
   return hipGetLastError();
 }
 
-// Hub decomposition. arrays = [nchunk | tsize | nscan] (nh each), scanned into
-// chunk_start/tab_start/scan_start which overwrite... (separate outputs of nh+1 each).
-// Per hub row of length L whose keys take at most `cap` distinct values: accumulation chunks,
-// a power-of-two table of at least 2 * min(L, cap) slots, and scan blocks for its occupied list.
-__global__ void k_hub_sizes(const int64_t* rs, const int64_t* re, const int64_t* len,
-                            const int32_t* hubs, int64_t nh, int64_t cap, int64_t* nchunk,
-                            int64_t* tsize, int64_t* nscan) {
+// Two-phase decomposition of long items (see part_chunk). Per item of length L whose keys take
+// at most min(L, cap) distinct values: nck = ceil(L / Q) chunks, walked by phase-1 workgroups of
+// R consecutive chunks each (R grows with nck so that an item has at most kPartBlocksPerItem of
+// them); P partitions (a power of two, at most kMaxParts, sized for (table / 2) >> shift keys
+// each; 1 if the item is one chunk); nck * (P + 1) segment bounds (one row per chunk, of which
+// a workgroup uses one per table flush); and the phase-2 workgroups (none for a one-chunk item
+// of the aggregation, which phase 1 finishes by itself).
+constexpr int64_t kPartBlocksPerItem = 256;
+
+__global__ void k_part_sizes(const int64_t* rs, const int64_t* re, const int64_t* len,
+                             const int32_t* items, int64_t nh, int64_t cap, int vb, int merge,
+                             int shift, int64_t* nck, int64_t* nblk, int64_t* rper,
+                             int64_t* nparts, int64_t* hsz, int64_t* p2) {
+  const int64_t Q = part_chunk(vb);
+  const int64_t T = (((int64_t)1 << part_log2h(vb)) / 2) >> shift;
   for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < nh;
        h += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t L = item_len(rs, re, len, hubs[h]);
+    const int64_t L = item_len(rs, re, len, items[h]);
+    const int64_t c = (L + Q - 1) / Q;
+    const int64_t per = shift ? 4 : kPartBlocksPerItem;  // testing: several chunks per walker
+    const int64_t R = (c + per - 1) / per;
     const int64_t D = L < cap ? L : cap;
-    nchunk[h] = (L + kHubChunk - 1) / kHubChunk;
-    int64_t t = 1;
-    while (t < 2 * D) t <<= 1;
-    tsize[h] = t;
-    nscan[h] = (D + kHubScanChunk - 1) / kHubScanChunk;
+    int64_t P = 1;
+    if (c > 1)
+      while (P * T < D && P < kMaxParts) P <<= 1;
+    nck[h] = c;
+    rper[h] = R;
+    nblk[h] = (c + R - 1) / R;
+    nparts[h] = P;
+    hsz[h] = c * (P + 1);
+    p2[h] = (merge && c == 1) ? 0 : P;
   }
 }
 
-hipError_t plan_hubs(const int64_t* rs, const int64_t* re, const int64_t* len,
-                     const int32_t* hubs, int64_t nh, int64_t cap, int64_t* arrays,
-                     int64_t* partial, ull* host_buf, HubPlan& hp, hipStream_t s) {
-  hp = HubPlan();
-  hp.nh = nh;
+hipError_t plan_parts(const int64_t* rs, const int64_t* re, const int64_t* len,
+                      const int32_t* items, int64_t nh, int64_t cap, int vb, bool merge,
+                      int shift, int64_t* arrays, int64_t* partial, ull* host_buf,
+                      PartPlan& pp, hipStream_t s) {
+  pp = PartPlan();
+  pp.nh = nh;
+  pp.vb = vb;
+  pp.shift = shift;
   if (nh <= 0) return hipSuccess;
-  // arrays layout: 3 input arrays of nh, then 3 outputs of nh+1
-  int64_t* nchunk = arrays;
-  int64_t* tsize = arrays + nh;
-  int64_t* nscan = arrays + 2 * nh;
-  hp.chunk_start = arrays + 3 * nh;
-  hp.tab_start = hp.chunk_start + (nh + 1);
-  hp.scan_start = hp.tab_start + (nh + 1);
-  LV_LAUNCH(k_hub_sizes, grid_for(nh), kBlock, 0, s, rs, re, len, hubs, nh, cap, nchunk, tsize,
-            nscan);
+  int64_t* nck = arrays;
+  int64_t* nblk = arrays + nh;
+  int64_t* hsz = arrays + 2 * nh;
+  int64_t* p2 = arrays + 3 * nh;
+  pp.rper = arrays + 4 * nh;
+  pp.nparts = arrays + 5 * nh;
+  pp.chunk_start = arrays + 6 * nh;
+  pp.block_start = pp.chunk_start + (nh + 1);
+  pp.part_start = pp.block_start + (nh + 1);
+  pp.hoff_start = pp.part_start + (nh + 1);
+  LV_LAUNCH(k_part_sizes, grid_for(nh), kBlock, 0, s, rs, re, len, items, nh, cap, vb,
+            merge ? 1 : 0, shift, nck, nblk, pp.rper, pp.nparts, hsz, p2);
   hipError_t e;
-  if ((e = scan_i64(nchunk, nh, hp.chunk_start, partial, s)) != hipSuccess) return e;
-  if ((e = scan_i64(tsize, nh, hp.tab_start, partial, s)) != hipSuccess) return e;
-  if ((e = scan_i64(nscan, nh, hp.scan_start, partial, s)) != hipSuccess) return e;
-  e = hipMemcpyAsync(&host_buf[0], hp.chunk_start + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(&host_buf[1], hp.tab_start + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(&host_buf[2], hp.scan_start + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
+  if ((e = scan_i64(nck, nh, pp.chunk_start, partial, s)) != hipSuccess) return e;
+  if ((e = scan_i64(nblk, nh, pp.block_start, partial, s)) != hipSuccess) return e;
+  if ((e = scan_i64(p2, nh, pp.part_start, partial, s)) != hipSuccess) return e;
+  if ((e = scan_i64(hsz, nh, pp.hoff_start, partial, s)) != hipSuccess) return e;
+  int64_t* const src[4] = {pp.chunk_start + nh, pp.block_start + nh, pp.part_start + nh,
+                           pp.hoff_start + nh};
+  for (int i = 0; i < 4; i++) {
+    e = hipMemcpyAsync(&host_buf[i], src[i], sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+  }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  hp.chunks = (int64_t)host_buf[0];
-  hp.slots = (int64_t)host_buf[1];
-  hp.scan_blocks = (int64_t)host_buf[2];
+  pp.chunks = (int64_t)host_buf[0];
+  pp.blocks = (int64_t)host_buf[1];
+  pp.parts = (int64_t)host_buf[2];
+  pp.hoff_entries = (int64_t)host_buf[3];
   return hipSuccess;
 }
 
@@ -948,6 +999,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_move_partials(const ull* part
 // Workgroup-per-row tier (degree classes 7..9): one 1024-thread workgroup decides one vertex
 // with an LDS table of 2^LOG2H slots (twice the longest row of the class).
 constexpr int kWgBlock = 1024;
+// LDS a workgroup-tier table may take with its Sigma cache (any device the library accepts has
+// at least part_lds_bytes(4) + 4096 bytes per workgroup)
+constexpr size_t kWgSigLds = 144 * 1024;
 
 template <typename WT>
 struct WgArgs {
@@ -963,7 +1017,9 @@ struct WgArgs {
   ull* partial;         // this launch's block records
 };
 
-template <bool WIDE, typename WT, int LOG2H>
+// SIGC: the table also caches Sigma of candidates seen through a neighbour labelling its own
+// community (when the LDS allows the extra 8 bytes per slot).
+template <bool WIDE, typename WT, int LOG2H, bool SIGC>
 __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
   typedef Gain<WIDE> Ar;
   typedef typename Ar::T T;
@@ -977,17 +1033,28 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
   __shared__ ull snc[NW];
   int32_t* keys = (int32_t*)smem;
   V* vals = (V*)(smem + (size_t)H * sizeof(int32_t));
+  ull* sigs = (ull*)(smem + (size_t)H * (sizeof(int32_t) + sizeof(V)));
   const int32_t v = a.rows[blockIdx.x];
   for (int s = threadIdx.x; s < H; s += kWgBlock) {
     keys[s] = kEmpty;
     vals[s] = 0;
+    if (SIGC) sigs[s] = kNoSig;
   }
   __syncthreads();
   const int64_t e0 = a.rs[v], e1 = a.re[v];
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kWgBlock) {
     const int32_t j = ld_stream(a.idx + e);
     const V wv = (V)ld_stream(a.w + e);
-    if (j != v) table_add<V>(keys, vals, LOG2H, a.rec[j].c, wv);
+    if (j != v) {
+      if (SIGC) {
+        const VRec rj = a.rec[j];
+        uint32_t slot;
+        table_add<V>(keys, vals, LOG2H, rj.c, wv, &slot);
+        if (rj.c == j) sigs[slot] = rj.sig;
+      } else {
+        table_add<V>(keys, vals, LOG2H, a.rec[j].c, wv);
+      }
+    }
   }
   __syncthreads();
   const int32_t d = a.rec[v].c;
@@ -1004,7 +1071,8 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
       continue;
     }
     nc++;
-    const T g = Ar::of(a.W, kv, Ki, a.rec[c].sig);
+    const ull sc = SIGC ? sigs[s] : kNoSig;
+    const T g = Ar::of(a.W, kv, Ki, sc != kNoSig ? sc : a.rec[c].sig);
     if (better(g, c, bg, bc)) {
       bg = g;
       bc = c;
@@ -1071,14 +1139,16 @@ int hub_first_class(size_t max_lds, bool wide) {
 
 template <bool WIDE, typename WT, int LOG2H>
 static hipError_t launch_wg(const WgArgs<WT>& a, int64_t rows, hipStream_t s) {
-  const size_t shm = ((size_t)1 << LOG2H) * (4 + sizeof(typename Gain<WIDE>::V));
+  constexpr size_t vb = sizeof(typename Gain<WIDE>::V);
+  constexpr bool SIGC = ((size_t)1 << LOG2H) * (4 + vb + 8) <= kWgSigLds;
+  const size_t shm = ((size_t)1 << LOG2H) * (4 + vb + (SIGC ? 8 : 0));
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_move_wg<WIDE, WT, LOG2H>,
+    (void)hipFuncSetAttribute((const void*)k_move_wg<WIDE, WT, LOG2H, SIGC>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     attr = true;
   }
-  LV_LAUNCH((k_move_wg<WIDE, WT, LOG2H>), (unsigned)rows, kWgBlock, shm, s, a);
+  LV_LAUNCH((k_move_wg<WIDE, WT, LOG2H, SIGC>), (unsigned)rows, kWgBlock, shm, s, a);
   return hipGetLastError();
 }
 
@@ -1187,10 +1257,9 @@ hipError_t move_wg(const DevGraph& g, const Buckets& b, int cls, const MoveBuffe
 }
 
 // =============================================================================================
-// Hub path (rows longer than 1024 arcs): global-memory tables, one power-of-two table of at
-// least twice the row length per hub. Three kernels: accumulate (blocks over kHubChunk-arc
-// chunks, new keys append their slot to an occupied list), scan (blocks over the occupied
-// list: gains, block-best partials, slots reset for the next iteration), decide (per hub).
+// Two-phase path for long items (hub rows here, large communities in the aggregation): the
+// per-worker hashtable of section 3.2 split by a hash partition of the keys so that every piece
+// fits in LDS (see part_chunk). No global hash table and no global atomics on keys.
 
 __device__ __forceinline__ int64_t find_segment(const int64_t* start, int64_t cnt, int64_t x) {
   int64_t lo = 0, hi = cnt;  // start[lo] <= x < start[hi]
@@ -1203,42 +1272,187 @@ __device__ __forceinline__ int64_t find_segment(const int64_t* start, int64_t cn
 
 __device__ __forceinline__ int ilog2_i64(int64_t x) { return 63 - __clzll((long long)x); }
 
-// A block first combines its chunk of a hub row in an LDS table of kHubLds slots (chunks of
-// kHubChunk arcs, so the table is at most half full), then adds each distinct key once to the
-// row's global table; keys new to the global table append their slot to the row's occupied
-// list, one atomic per wavefront.
-constexpr int kHubLds = 2 * (int)kHubChunk;
-constexpr int kHubLdsLog2 = 12;
-static_assert((1 << kHubLdsLog2) == kHubLds, "LDS hub table size");
-
-template <typename V>
-__device__ __forceinline__ void hub_lds_init(int32_t* lk, V* lv) {
-  for (int s = threadIdx.x; s < kHubLds; s += kBlock) {
-    lk[s] = kEmpty;
-    lv[s] = 0;
+// Exclusive scan in place of a[0 .. n), n <= 4 * kPartBlock, by a kPartBlock-thread workgroup.
+// Returns the total in every thread. wsum: kPartBlock / 64 + 1 shared ints.
+__device__ int block_scan_excl(int* a, int n, int* wsum) {
+  constexpr int NW = kPartBlock / 64;
+  const int per = (n + kPartBlock - 1) / kPartBlock;
+  const int i0 = threadIdx.x * per;
+  int loc[4];
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    loc[i] = (i < per && i0 + i < n) ? a[i0 + i] : 0;
+    sum += loc[i];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < NW; w++) {
+      const int x = wsum[w];
+      wsum[w] = t;
+      t += x;
+    }
+    wsum[NW] = t;
   }
   __syncthreads();
+  int run = wsum[wave] + incl - sum;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    if (i < per && i0 + i < n) a[i0 + i] = run;
+    run += loc[i];
+  }
+  const int total = wsum[NW];
+  __syncthreads();
+  return total;
 }
 
 template <typename V>
-__device__ __forceinline__ void hub_flush(const int32_t* lk, const V* lv, int32_t* gk, V* gv,
-                                          int glog2, int32_t* occ, int32_t* occ_count) {
+__device__ __forceinline__ void part_table_clear(int32_t* keys, V* vals, int H) {
+  for (int s = threadIdx.x; s < H; s += kPartBlock) {
+    keys[s] = kEmpty;
+    vals[s] = 0;
+  }
+}
+
+// Phase-1 table flush: the table's keys written to pk/pv + base grouped by partition, with the
+// partition bounds (offsets from pk/pv) in hoff_row[0 .. P]. Returns the number of keys.
+template <typename V>
+__device__ int part_emit(const int32_t* keys, const V* vals, int H, int P, int* cnt, int* wsum,
+                         int32_t* hoff_row, int base, int32_t* pk, V* pv) {
+  const int lp = ilog2_i64(P);
+  for (int p = threadIdx.x; p < P; p += kPartBlock) cnt[p] = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  for (int base = 0; base < kHubLds; base += kBlock) {
-    const int s = base + threadIdx.x;
-    const int32_t key = lk[s];
-    bool fresh = false;
-    uint32_t slot = 0;
-    if (key != kEmpty) fresh = table_add<V>(gk, gv, glog2, key, lv[s], &slot);
-    const ull mask = __ballot(fresh);
-    if (mask) {
-      const int leader = __ffsll((long long)mask) - 1;
-      int first = 0;
-      if (lane == leader) first = atomicAdd(occ_count, __popcll(mask));
-      first = __shfl(first, leader);
-      if (fresh) occ[first + __popcll(mask & ((1ull << lane) - 1))] = (int32_t)slot;
+  for (int s = threadIdx.x; s < H; s += kPartBlock)
+    if (keys[s] != kEmpty) atomicAdd(&cnt[part_of(keys[s], lp)], 1);
+  __syncthreads();
+  const int total = block_scan_excl(cnt, P, wsum);
+  for (int p = threadIdx.x; p < P; p += kPartBlock) hoff_row[p] = base + cnt[p];
+  if (threadIdx.x == 0) hoff_row[P] = base + total;
+  __syncthreads();
+  for (int s = threadIdx.x; s < H; s += kPartBlock) {
+    const int32_t key = keys[s];
+    if (key == kEmpty) continue;
+    const int pos = base + atomicAdd(&cnt[part_of(key, lp)], 1);
+    pk[pos] = key;
+    pv[pos] = vals[s];
+  }
+  return total;
+}
+
+// Phase-1 walk of chunks [k0, k1) of an item: acc(k, keys, vals, flags) adds chunk k to the LDS
+// table, counting newly claimed slots in flags[0]; the table is flushed (part_emit) into the
+// next bound row (hoff_rows, P + 1 entries each) whenever the next chunk might push it past 3/4
+// full, and at the end. The pairs go to the workgroup's region pk/pv (room for k1 - k0 chunks,
+// which the flushed keys cannot exceed). Returns the number of flushes.
+template <typename V, int LOG2H, typename Acc>
+__device__ int part_walk(Acc& acc, int64_t k0, int64_t k1, int P, int32_t* keys, V* vals,
+                         int* cnt, int* wsum, int* flags, int32_t* hoff_rows, int32_t* pk,
+                         V* pv) {
+  constexpr int H = 1 << LOG2H;
+  constexpr int Q = part_chunk((int)sizeof(V));
+  static_assert(2 * Q == H, "phase-1 table holds two chunks");
+  int flushes = 0, written = 0;
+  part_table_clear<V>(keys, vals, H);
+  if (threadIdx.x == 0) flags[0] = 0;
+  __syncthreads();
+  for (int64_t k = k0; k < k1; k++) {
+    if (flags[0] > Q / 2) {
+      written += part_emit<V>(keys, vals, H, P, cnt, wsum, hoff_rows + flushes * (P + 1),
+                              written, pk, pv);
+      flushes++;
+      __syncthreads();
+      part_table_clear<V>(keys, vals, H);
+      if (threadIdx.x == 0) flags[0] = 0;
+      __syncthreads();
     }
+    acc(k, keys, vals, flags);
+    __syncthreads();
+  }
+  if (flags[0] > 0) {
+    part_emit<V>(keys, vals, H, P, cnt, wsum, hoff_rows + flushes * (P + 1), written, pk, pv);
+    flushes++;
+  }
+  return flushes;
+}
+
+// Phase 2: combine partition p of an item into the LDS table, in rounds over sub-ranges of the
+// key hash when the partition holds more distinct keys than a round may claim (cap); fin(keys,
+// vals, H) consumes each completed round. The item's bound rows (one per chunk, nck of them,
+// from hrow) belong to its phase-1 workgroups, R consecutive rows each, of which workgroup i
+// used the first nflush[i]; its pairs are at pk/pv + (i * R) * Q. cap <= part_cap(LOG2H), so
+// the claims made before every thread sees the overflow still find free slots. flags: 4 shared
+// ints (claimed slots, overflow, and two for fin).
+template <typename V, int LOG2H, typename Fin>
+__device__ void part_reduce(const int32_t* pk, const V* pv, const int32_t* hrow,
+                            const int32_t* nflush, int64_t nck, int64_t R, int P, int p, int cap,
+                            int32_t* keys, V* vals, unsigned char* aux, int* wsum, int* flags,
+                            Fin& fin) {
+  constexpr int H = 1 << LOG2H;
+  constexpr int Q = part_chunk((int)sizeof(V));
+  static_assert(part_cap(LOG2H) + kPartBlock <= H, "claims past the cap must find free slots");
+  int64_t* sbeg = (int64_t*)aux;                             // first pair of each row's segment
+  int* sstart = (int*)(aux + kPartTile * sizeof(int64_t));  // exclusive scan of their lengths
+  const int lp = ilog2_i64(P);
+  const uint64_t pbeg = (uint64_t)p << (32 - lp);
+  const uint64_t pend = (uint64_t)(p + 1) << (32 - lp);
+  uint64_t lo = pbeg, width = pend - pbeg;
+  while (lo < pend) {
+    const uint64_t hi = lo + width < pend ? lo + width : pend;
+    part_table_clear<V>(keys, vals, H);
+    if (threadIdx.x == 0) {
+      flags[0] = 0;
+      flags[1] = 0;
+    }
+    __syncthreads();
+    for (int64_t t0 = 0; t0 < nck; t0 += kPartTile) {
+      const int nt = (int)(nck - t0 < kPartTile ? nck - t0 : kPartTile);
+      for (int i = threadIdx.x; i < nt; i += kPartBlock) {
+        const int64_t r = t0 + i;
+        const int64_t blk = r / R;
+        int len = 0;
+        if (r - blk * R < nflush[blk]) {
+          const int32_t* row = hrow + r * (int64_t)(P + 1);
+          const int32_t s0 = row[p];
+          sbeg[i] = blk * R * Q + s0;
+          len = row[p + 1] - s0;
+        }
+        sstart[i] = len;
+      }
+      __syncthreads();
+      const int total = block_scan_excl(sstart, nt, wsum);
+      for (int f = threadIdx.x; f < total; f += kPartBlock) {
+        if (*(volatile int*)&flags[1]) break;
+        int a = 0, b = nt;  // sstart[a] <= f < sstart[b] (segment a is the non-empty one)
+        while (b - a > 1) {
+          const int mid = (a + b) >> 1;
+          if (sstart[mid] <= f) a = mid; else b = mid;
+        }
+        const int64_t pos = sbeg[a] + (f - sstart[a]);
+        const int32_t key = pk[pos];
+        const uint64_t hk = fmix32((uint32_t)key);
+        if (hk >= lo && hk < hi)
+          table_add_capped<V>(keys, vals, LOG2H, key, pv[pos], &flags[0], cap, &flags[1]);
+      }
+      __syncthreads();
+    }
+    const int over = flags[1];
+    __syncthreads();
+    if (over) {
+      width = (hi - lo) / 2 > 0 ? (hi - lo) / 2 : 1;
+      continue;
+    }
+    fin(keys, vals, H);
+    __syncthreads();
+    lo = hi;
   }
 }
 
@@ -1254,75 +1468,148 @@ struct HubArgs {
   const int32_t* hubs;
   int64_t nh;
   const int64_t* chunk_start;
-  const int64_t* tab_start;
-  const int64_t* scan_start;
-  int32_t* tkeys;
-  V* tvals;
-  int32_t* occ;
-  int32_t* occ_count;
-  ull* partial;  // 5 words per scan block: gain lo, gain hi, community, kd, candidates
+  const int64_t* block_start;
+  const int64_t* part_start;
+  const int64_t* hoff_start;
+  const int64_t* rper;
+  const int64_t* nparts;
+  int32_t* pk;       // phase-1 pairs, part_chunk(sizeof(V)) per chunk
+  V* pv;
+  int32_t* hoff;     // segment bounds
+  int32_t* nflush;   // flushes of every phase-1 workgroup
+  int cap;           // phase-2 claim cap per round
+  ull* partial;      // 5 words per phase-2 workgroup: gain lo, gain hi, community, kd, candidates
   int32_t* tgt;
   ull* stats;
 };
 
+// Phase 1 of the hub rows: workgroup i of hub h walks chunks [i R, (i + 1) R) of its row.
 template <typename WT, typename V>
-__global__ __launch_bounds__(kBlock) void k_hub_accumulate(HubArgs<WT, V> a) {
-  __shared__ int32_t lk[kHubLds];
-  __shared__ V lv[kHubLds];
-  const int64_t b = blockIdx.x;
-  const int64_t h = find_segment(a.chunk_start, a.nh, b);
-  const int32_t v = a.hubs[h];
-  const int64_t rb = a.rs[v], rend = a.re[v];
-  const int64_t e0 = rb + (b - a.chunk_start[h]) * kHubChunk;
-  const int64_t e1 = e0 + kHubChunk < rend ? e0 + kHubChunk : rend;
-  const int64_t ts = a.tab_start[h];
-  const int lg = ilog2_i64(a.tab_start[h + 1] - ts);
-  hub_lds_init<V>(lk, lv);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    const int32_t j = ld_stream(a.idx + e);
-    const V wv = (V)ld_stream(a.w + e);
-    if (j != v) table_add<V>(lk, lv, kHubLdsLog2, a.rec[j].c, wv);
+struct HubChunk {
+  const HubArgs<WT, V>* a;
+  int32_t v;
+  int64_t e0, e1;  // the row
+  template <int LOG2H>
+  __device__ void add(int64_t k, int32_t* keys, V* vals, int* flags) {
+    constexpr int Q = part_chunk((int)sizeof(V));
+    const int64_t c0 = e0 + k * Q;
+    const int64_t c1 = c0 + Q < e1 ? c0 + Q : e1;
+    int fresh = 0;
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += kPartBlock) {
+      const int32_t j = ld_stream(a->idx + e);
+      const V wv = (V)ld_stream(a->w + e);
+      if (j != v) fresh += table_add<V>(keys, vals, LOG2H, a->rec[j].c, wv);
+    }
+    if (fresh) atomicAdd(&flags[0], fresh);
   }
-  hub_flush<V>(lk, lv, a.tkeys + ts, a.tvals + ts, lg, a.occ + ts, a.occ_count + h);
+  __device__ void operator()(int64_t k, int32_t* keys, V* vals, int* flags) {
+    add<part_log2h((int)sizeof(V))>(k, keys, vals, flags);
+  }
+};
+
+template <typename WT, typename V>
+__global__ __launch_bounds__(kPartBlock) void k_hub_part(HubArgs<WT, V> a) {
+  constexpr int LOG2H = part_log2h((int)sizeof(V));
+  constexpr int H = 1 << LOG2H;
+  constexpr int Q = part_chunk((int)sizeof(V));
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int wsum[kPartBlock / 64 + 1];
+  __shared__ int flags[4];
+  int32_t* keys = (int32_t*)smem;
+  V* vals = (V*)(smem + (size_t)H * 4);
+  int* cnt = (int*)(smem + (size_t)H * (4 + sizeof(V)));
+  const int64_t b = blockIdx.x;
+  const int64_t h = find_segment(a.block_start, a.nh, b);
+  const int64_t i = b - a.block_start[h];
+  const int64_t R = a.rper[h];
+  const int64_t row0 = a.chunk_start[h], nck = a.chunk_start[h + 1] - row0;
+  const int64_t k0 = i * R, k1 = k0 + R < nck ? k0 + R : nck;
+  const int P = (int)a.nparts[h];
+  HubChunk<WT, V> acc;
+  acc.a = &a;
+  acc.v = a.hubs[h];
+  acc.e0 = a.rs[acc.v];
+  acc.e1 = a.re[acc.v];
+  const int nf = part_walk<V, LOG2H>(acc, k0, k1, P, keys, vals, cnt, wsum, flags,
+                                     a.hoff + a.hoff_start[h] + k0 * (P + 1),
+                                     a.pk + (row0 + k0) * Q, a.pv + (row0 + k0) * Q);
+  if (threadIdx.x == 0) a.nflush[b] = nf;
 }
 
-template <bool WIDE, typename WT>
-__global__ __launch_bounds__(kBlock) void k_hub_scan(HubArgs<WT, typename Gain<WIDE>::V> a) {
+// Per-thread best candidate over completed phase-2 rounds of one hub.
+template <bool WIDE>
+struct HubFin {
   typedef Gain<WIDE> Ar;
   typedef typename Ar::T T;
-  __shared__ typename Gain<true>::T sbg[kBlock / 64];
-  __shared__ int32_t sbc[kBlock / 64];
-  __shared__ ull skd[kBlock / 64];
-  __shared__ ull snc[kBlock / 64];
-  const int64_t b = blockIdx.x;
-  const int64_t h = find_segment(a.scan_start, a.nh, b);
-  const int32_t v = a.hubs[h];
-  const int64_t ts = a.tab_start[h];
-  const int64_t cnt = a.occ_count[h];
-  const int64_t p0 = (b - a.scan_start[h]) * kHubScanChunk;
-  const int64_t p1 = p0 + kHubScanChunk < cnt ? p0 + kHubScanChunk : cnt;
-  const int32_t d = a.rec[v].c;
-  const uint64_t Ki = a.K[v];
-  T bg = Ar::lowest();
-  int32_t bc = INT32_MAX;
-  ull kd = 0, nc = 0;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
-    const int64_t s = ts + a.occ[ts + p];
-    const int32_t c = a.tkeys[s];
-    const ull kv = (ull)a.tvals[s];
-    a.tkeys[s] = kEmpty;
-    a.tvals[s] = 0;
-    if (c == d) {
-      kd = kv;
-      continue;
-    }
-    nc++;
-    const T g = Ar::of(a.W, kv, Ki, a.rec[c].sig);
-    if (better(g, c, bg, bc)) {
-      bg = g;
-      bc = c;
+  const VRec* rec;
+  uint64_t W, Ki;
+  int32_t d;
+  T bg;
+  int32_t bc;
+  ull kd, nc;
+  template <typename V>
+  __device__ void operator()(const int32_t* keys, const V* vals, int H) {
+    for (int s = threadIdx.x; s < H; s += kPartBlock) {
+      const int32_t c = keys[s];
+      if (c == kEmpty) continue;
+      const ull kv = (ull)vals[s];
+      if (c == d) {
+        kd += kv;
+        continue;
+      }
+      nc++;
+      const T g = Ar::of(W, kv, Ki, rec[c].sig);
+      if (better(g, c, bg, bc)) {
+        bg = g;
+        bc = c;
+      }
     }
   }
+};
+
+// Phase 2 of the hub rows: partition p of hub h -> its best (gain, community), the weight to
+// the hub's own community and the candidate count, as a partial record.
+template <bool WIDE, typename WT>
+__global__ __launch_bounds__(kPartBlock) void k_hub_reduce(
+    HubArgs<WT, typename Gain<WIDE>::V> a) {
+  typedef Gain<WIDE> Ar;
+  typedef typename Ar::T T;
+  typedef typename Ar::V V;
+  constexpr int LOG2H = part_log2h((int)sizeof(V));
+  constexpr int H = 1 << LOG2H;
+  constexpr int Q = part_chunk((int)sizeof(V));
+  constexpr int NW = kPartBlock / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int wsum[NW + 1];
+  __shared__ int flags[4];
+  __shared__ typename Gain<true>::T sbg[NW];
+  __shared__ int32_t sbc[NW];
+  __shared__ ull skd[NW];
+  __shared__ ull snc[NW];
+  int32_t* keys = (int32_t*)smem;
+  V* vals = (V*)(smem + (size_t)H * 4);
+  unsigned char* aux = smem + (size_t)H * (4 + sizeof(V));
+  const int64_t b = blockIdx.x;
+  const int64_t h = find_segment(a.part_start, a.nh, b);
+  const int p = (int)(b - a.part_start[h]);
+  const int P = (int)a.nparts[h];
+  const int64_t c0 = a.chunk_start[h], nck = a.chunk_start[h + 1] - c0;
+  const int32_t v = a.hubs[h];
+  HubFin<WIDE> fin;
+  fin.rec = a.rec;
+  fin.W = a.W;
+  fin.Ki = a.K[v];
+  fin.d = a.rec[v].c;
+  fin.bg = Ar::lowest();
+  fin.bc = INT32_MAX;
+  fin.kd = 0;
+  fin.nc = 0;
+  part_reduce<V, LOG2H>(a.pk + c0 * Q, a.pv + c0 * Q, a.hoff + a.hoff_start[h],
+                        a.nflush + a.block_start[h], nck, a.rper[h], P, p, a.cap, keys, vals,
+                        aux, wsum, flags, fin);
+  T bg = fin.bg;
+  int32_t bc = fin.bc;
+  ull kd = fin.kd, nc = fin.nc;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
     const T og = Ar::shfl_xor(bg, m, 64);
@@ -1343,7 +1630,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_scan(HubArgs<WT, typename Gain<W
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < kBlock / 64; i++) {
+    for (int i = 1; i < NW; i++) {
       const T og = (T)sbg[i];
       if (better(og, sbc[i], bg, bc)) {
         bg = og;
@@ -1370,13 +1657,13 @@ __global__ __launch_bounds__(kBlock) void k_hub_decide(HubArgs<WT, typename Gain
   __shared__ ull red64[kBlock / 64];
   const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   u128 gain = 0;
-  ull nc = 0;
+  ull nc = 0, moved = 0;
   if (h < a.nh) {
     const int32_t v = a.hubs[h];
     T bg = Ar::lowest();
     int32_t bc = INT32_MAX;
     ull kd = 0;
-    for (int64_t p = a.scan_start[h]; p < a.scan_start[h + 1]; p++) {
+    for (int64_t p = a.part_start[h]; p < a.part_start[h + 1]; p++) {
       const ull* in = a.partial + 5 * p;
       const T og = (T)(i128)(((u128)in[1] << 64) | in[0]);
       const int32_t oc = (int32_t)(uint32_t)in[2];
@@ -1387,7 +1674,6 @@ __global__ __launch_bounds__(kBlock) void k_hub_decide(HubArgs<WT, typename Gain
       kd += in[3];
       nc += in[4];
     }
-    a.occ_count[h] = 0;
     const int32_t d = a.rec[v].c;
     int32_t target = d;
     if (bc != INT32_MAX) {
@@ -1397,48 +1683,32 @@ __global__ __launch_bounds__(kBlock) void k_hub_decide(HubArgs<WT, typename Gain
       if (bg > stay && !(rd.size == 1 && a.rec[bc].size == 1 && bc > d)) {
         gain = Ar::diff(bg, stay);
         target = bc;
-        atomicAdd(&a.stats[2], 1ull);
+        moved = 1;
       }
     }
     a.tgt[v] = target;
   }
   const u128 bs = block_sum_u128(gain, red);
   const ull ns = block_sum_u64(nc, red64);
+  const ull ms = block_sum_u64(moved, red64);
   if (threadIdx.x == 0) {
     if (bs) atomic_add_u128(&a.stats[0], bs);
+    if (ms) atomicAdd(&a.stats[2], ms);
     if (ns) atomicAdd(&a.stats[3], ns);
   }
 }
 
-template <typename V>
-__global__ void k_hub_reset(int32_t* keys, V* vals, int64_t slots, int32_t* occ_count,
-                            int64_t nh) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < slots;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    keys[i] = kEmpty;
-    vals[i] = 0;
-  }
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nh;
-       i += (int64_t)gridDim.x * blockDim.x)
-    occ_count[i] = 0;
-}
-
-hipError_t hub_reset_tables(const HubPlan& hp, const MoveBuffers& m, bool wide, hipStream_t s) {
-  if (hp.nh <= 0) return hipSuccess;
-  const int64_t n = hp.slots > hp.nh ? hp.slots : hp.nh;
-  if (wide)
-    LV_LAUNCH(k_hub_reset<ull>, grid_for(n), kBlock, 0, s, m.tkeys, (ull*)m.tvals,
-              hp.slots, m.occ_count, hp.nh);
-  else
-    LV_LAUNCH(k_hub_reset<uint32_t>, grid_for(n), kBlock, 0, s, m.tkeys, (uint32_t*)m.tvals,
-              hp.slots, m.occ_count, hp.nh);
-  return hipGetLastError();
+template <typename K>
+static void allow_part_lds(K kernel, int vb) {
+  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)part_lds_bytes(vb));
 }
 
 template <bool WIDE, typename WT>
-static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, const HubPlan& hp,
+static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, const PartPlan& pp,
                               const MoveBuffers& m, hipStream_t s) {
   typedef typename Gain<WIDE>::V V;
+  constexpr int vb = (int)sizeof(V);
   HubArgs<WT, V> a;
   a.rs = g.rs;
   a.re = g.re;
@@ -1448,31 +1718,42 @@ static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, cons
   a.rec = (const VRec*)m.rec;
   a.W = m.W;
   a.hubs = m.list + b.lstart[kDegClasses * cls + m.hub_first];
-  a.nh = hp.nh;
-  a.chunk_start = hp.chunk_start;
-  a.tab_start = hp.tab_start;
-  a.scan_start = hp.scan_start;
-  a.tkeys = m.tkeys;
-  a.tvals = (V*)m.tvals;
-  a.occ = m.occ;
-  a.occ_count = m.occ_count;
+  a.nh = pp.nh;
+  a.chunk_start = pp.chunk_start;
+  a.block_start = pp.block_start;
+  a.part_start = pp.part_start;
+  a.hoff_start = pp.hoff_start;
+  a.rper = pp.rper;
+  a.nparts = pp.nparts;
+  a.pk = m.pk;
+  a.pv = (V*)m.pv;
+  a.hoff = m.hoff;
+  a.nflush = m.nflush;
+  a.cap = part_round_cap(part_log2h(vb), pp.shift);
   a.partial = m.partial;
   a.tgt = m.tgt;
   a.stats = m.stats;
-  LV_LAUNCH((k_hub_accumulate<WT, V>), (unsigned)hp.chunks, kBlock, 0, s, a);
-  LV_LAUNCH((k_hub_scan<WIDE, WT>), (unsigned)hp.scan_blocks, kBlock, 0, s, a);
-  LV_LAUNCH((k_hub_decide<WIDE, WT>), grid_for(hp.nh, kBlock, 1 << 30), kBlock, 0, s, a);
+  static bool attr = false;
+  if (!attr) {
+    allow_part_lds(k_hub_part<WT, V>, vb);
+    allow_part_lds(k_hub_reduce<WIDE, WT>, vb);
+    attr = true;
+  }
+  const size_t shm = part_lds_bytes(vb);
+  LV_LAUNCH((k_hub_part<WT, V>), (unsigned)pp.blocks, kPartBlock, shm, s, a);
+  LV_LAUNCH((k_hub_reduce<WIDE, WT>), (unsigned)pp.parts, kPartBlock, shm, s, a);
+  LV_LAUNCH((k_hub_decide<WIDE, WT>), grid_for(pp.nh, kBlock, 1 << 30), kBlock, 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const HubPlan& hp,
+hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const PartPlan& pp,
                      const MoveBuffers& m, bool wide, hipStream_t s) {
-  if (hp.nh <= 0) return hipSuccess;
+  if (pp.nh <= 0) return hipSuccess;
   if (wide)
-    return g.w64 ? move_hubs_t<true, uint64_t>(g, b, cls, hp, m, s)
-                 : move_hubs_t<true, uint32_t>(g, b, cls, hp, m, s);
-  return g.w64 ? move_hubs_t<false, uint64_t>(g, b, cls, hp, m, s)
-               : move_hubs_t<false, uint32_t>(g, b, cls, hp, m, s);
+    return g.w64 ? move_hubs_t<true, uint64_t>(g, b, cls, pp, m, s)
+                 : move_hubs_t<true, uint32_t>(g, b, cls, pp, m, s);
+  return g.w64 ? move_hubs_t<false, uint64_t>(g, b, cls, pp, m, s)
+               : move_hubs_t<false, uint32_t>(g, b, cls, pp, m, s);
 }
 
 // Apply a class step's decisions: C, Sigma and csize after the step. Integer atomics commute,
@@ -1757,8 +2038,10 @@ hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& ag, 
   return g.w64 ? merge_lds_t<uint64_t>(g, b, ag, s) : merge_lds_t<uint32_t>(g, b, ag, s);
 }
 
-// Communities of more than 1024 arcs: blocks over kHubChunk-arc pieces of the flat range,
-// each thread covering 8 consecutive flat arcs (one member search, then a forward walk).
+// Communities of more than 1024 arcs: the two-phase path over their flat arc ranges (values are
+// 8-byte weight sums). Phase 1 covers part_chunk(8) flat arcs per workgroup, each thread a run
+// of consecutive flat arcs (one member search, then a forward walk); a community of one chunk is
+// finished there, others are finished by one phase-2 workgroup per partition.
 template <typename WT>
 struct MergeHubArgs {
   const int64_t* rs;
@@ -1773,86 +2056,201 @@ struct MergeHubArgs {
   const int64_t* newid;
   int32_t* okey;
   uint64_t* ow;
-  int64_t* dcount;
-  ull* stats;
+  int64_t* dcount;   // distinct targets per new id (zero before the merge)
+  ull* stats;        // [0] weight of self super-arcs
   const int32_t* hubs;
   int64_t nh;
   const int64_t* chunk_start;
-  const int64_t* tab_start;
-  const int64_t* scan_start;
-  int32_t* tkeys;
-  ull* tvals;
-  int32_t* occ;
-  int32_t* occ_count;
+  const int64_t* block_start;
+  const int64_t* part_start;
+  const int64_t* hoff_start;
+  const int64_t* rper;
+  const int64_t* nparts;
+  int32_t* pk;
+  ull* pv;
+  int32_t* hoff;
+  int32_t* nflush;
+  int cap;
 };
 
-constexpr int kMergePerThread = (int)(kHubChunk / kBlock);
+constexpr int kMergeChunk = part_chunk(8);
+constexpr int kMergeLog2H = part_log2h(8);
+constexpr int kMergePerThread = kMergeChunk / kPartBlock;
 
-template <typename WT>
-__global__ __launch_bounds__(kBlock) void k_merge_hub_accumulate(MergeHubArgs<WT> a) {
-  __shared__ int32_t lk[kHubLds];
-  __shared__ ull lv[kHubLds];
-  const int64_t b = blockIdx.x;
-  const int64_t h = find_segment(a.chunk_start, a.nh, b);
-  const int32_t c = a.hubs[h];
-  const int64_t m0 = a.mstart[c];
-  const int mc = (int)(a.mstart[c + 1] - m0);
-  const int64_t a0 = a.astart[c], L = a.A[c];
-  const int64_t ts = a.tab_start[h];
-  const int lg = ilog2_i64(a.tab_start[h + 1] - ts);
-  hub_lds_init<ull>(lk, lv);
-  const int64_t t0 = (b - a.chunk_start[h]) * kHubChunk + (int64_t)threadIdx.x * kMergePerThread;
-  const int64_t t1 = t0 + kMergePerThread < L ? t0 + kMergePerThread : L;
-  if (t0 < t1) {
-    // member holding flat arc t0 (first flat arcs are a0 + gscan offsets)
-    int i = member_at(a.gscan + m0, mc, a0 + t0);
-    int64_t next = i + 1 < mc ? a.gscan[m0 + i + 1] - a0 : L;
-    int64_t first = a.gscan[m0 + i] - a0;
-    int32_t v = a.members[m0 + i];
-    for (int64_t t = t0; t < t1; t++) {
-      while (t >= next) {
-        i++;
-        first = next;
-        next = i + 1 < mc ? a.gscan[m0 + i + 1] - a0 : L;
-        v = a.members[m0 + i];
-      }
-      const int64_t e = a.rs[v] + (t - first);
-      table_add<ull>(lk, lv, kHubLdsLog2, a.map[a.idx[e]], (ull)a.w[e]);
+// Write the LDS table's entries to the community's output row at row + base + (claimed
+// position), base = atomicAdd(dcount, entries) when `shared_row`, else 0 with *dcount = entries.
+// Returns the weight of the entry keyed `me` (this thread's share). flags[2..3]: shared ints.
+__device__ ull merge_emit_table(const int32_t* keys, const ull* vals, int H, int32_t me,
+                                int32_t* okey, uint64_t* ow, int64_t* dcount, bool shared_row,
+                                int* flags, int64_t* base_sh) {
+  int mine = 0;
+  for (int s = threadIdx.x; s < H; s += kPartBlock) mine += keys[s] != kEmpty;
+  if (threadIdx.x == 0) {
+    flags[2] = 0;
+    flags[3] = 0;
+  }
+  __syncthreads();
+  if (mine) atomicAdd(&flags[2], mine);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = flags[2];
+    if (shared_row) {
+      *base_sh = tot ? (int64_t)atomicAdd((ull*)dcount, (ull)tot) : 0;
+    } else {
+      *base_sh = 0;
+      *dcount = tot;
     }
   }
-  hub_flush<ull>(lk, lv, a.tkeys + ts, a.tvals + ts, lg, a.occ + ts, a.occ_count + h);
+  __syncthreads();
+  const int64_t base = *base_sh;
+  ull self = 0;
+  for (int s = threadIdx.x; s < H; s += kPartBlock) {
+    const int32_t key = keys[s];
+    if (key == kEmpty) continue;
+    const int64_t pos = base + atomicAdd(&flags[3], 1);
+    okey[pos] = key;
+    ow[pos] = vals[s];
+    if (key == me) self = vals[s];
+  }
+  return self;
 }
 
+__device__ __forceinline__ ull part_block_sum(ull x, ull* red) {
+  x = group_sum_u64<64>(x);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  ull t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kPartBlock / 64; i++) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+// Chunk k of community c's flat arc range: each thread a run of kMergePerThread consecutive flat
+// arcs (one member search, then a forward walk), keyed by the target's new id.
 template <typename WT>
-__global__ __launch_bounds__(kBlock) void k_merge_hub_emit(MergeHubArgs<WT> a) {
-  __shared__ ull red[kBlock / 64];
-  const int64_t b = blockIdx.x;
-  const int64_t h = find_segment(a.scan_start, a.nh, b);
-  const int32_t c = a.hubs[h];
-  const int64_t ts = a.tab_start[h];
-  const int64_t cnt = a.occ_count[h];
-  const int64_t p0 = (b - a.scan_start[h]) * kHubScanChunk;
-  const int64_t p1 = p0 + kHubScanChunk < cnt ? p0 + kHubScanChunk : cnt;
-  const int64_t base = a.astart[c];
-  const int32_t me = (int32_t)a.newid[c];
-  ull self = 0;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
-    const int64_t sl = ts + a.occ[ts + p];
-    const int32_t key = a.tkeys[sl];
-    const ull val = a.tvals[sl];
-    a.tkeys[sl] = kEmpty;
-    a.tvals[sl] = 0;
-    a.okey[base + p] = key;
-    a.ow[base + p] = val;
-    if (key == me) self = val;
+struct MergeChunk {
+  const MergeHubArgs<WT>* a;
+  int64_t m0, a0, L;
+  int mc;
+  __device__ void operator()(int64_t k, int32_t* keys, ull* vals, int* flags) {
+    const int64_t t0 = k * kMergeChunk + (int64_t)threadIdx.x * kMergePerThread;
+    const int64_t t1 = t0 + kMergePerThread < L ? t0 + kMergePerThread : L;
+    int fresh = 0;
+    if (t0 < t1) {
+      // member holding flat arc t0 (first flat arcs are a0 + gscan offsets)
+      int i = member_at(a->gscan + m0, mc, a0 + t0);
+      int64_t next = i + 1 < mc ? a->gscan[m0 + i + 1] - a0 : L;
+      int64_t first = a->gscan[m0 + i] - a0;
+      int32_t v = a->members[m0 + i];
+      for (int64_t t = t0; t < t1; t++) {
+        while (t >= next) {
+          i++;
+          first = next;
+          next = i + 1 < mc ? a->gscan[m0 + i + 1] - a0 : L;
+          v = a->members[m0 + i];
+        }
+        const int64_t e = a->rs[v] + (t - first);
+        fresh += table_add<ull>(keys, vals, kMergeLog2H, a->map[a->idx[e]], (ull)a->w[e]);
+      }
+    }
+    if (fresh) atomicAdd(&flags[0], fresh);
   }
-  if (b == a.scan_start[h] && threadIdx.x == 0) a.dcount[me] = cnt;
-  const ull bs = block_sum_u64(self, red);
+};
+
+template <typename WT>
+__global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
+  constexpr int H = 1 << kMergeLog2H;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int wsum[kPartBlock / 64 + 1];
+  __shared__ int flags[4];
+  __shared__ int64_t base_sh;
+  __shared__ ull red[kPartBlock / 64];
+  int32_t* keys = (int32_t*)smem;
+  ull* vals = (ull*)(smem + (size_t)H * 4);
+  int* cnt = (int*)(smem + (size_t)H * 12);
+  const int64_t b = blockIdx.x;
+  const int64_t h = find_segment(a.block_start, a.nh, b);
+  const int64_t i = b - a.block_start[h];
+  const int64_t R = a.rper[h];
+  const int64_t row0 = a.chunk_start[h], nck = a.chunk_start[h + 1] - row0;
+  const int64_t k0 = i * R, k1 = k0 + R < nck ? k0 + R : nck;
+  const int32_t c = a.hubs[h];
+  MergeChunk<WT> acc;
+  acc.a = &a;
+  acc.m0 = a.mstart[c];
+  acc.mc = (int)(a.mstart[c + 1] - acc.m0);
+  acc.a0 = a.astart[c];
+  acc.L = a.A[c];
+  if (nck == 1) {
+    // the whole community in one table: write its row directly
+    part_table_clear<ull>(keys, vals, H);
+    __syncthreads();
+    acc(0, keys, vals, flags);
+    __syncthreads();
+    const int32_t me = (int32_t)a.newid[c];
+    const ull self = merge_emit_table(keys, vals, H, me, a.okey + acc.a0, a.ow + acc.a0,
+                                      a.dcount + me, false, flags, &base_sh);
+    const ull bs = part_block_sum(self, red);
+    if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
+    return;
+  }
+  const int P = (int)a.nparts[h];
+  const int nf = part_walk<ull, kMergeLog2H>(acc, k0, k1, P, keys, vals, cnt, wsum, flags,
+                                             a.hoff + a.hoff_start[h] + k0 * (P + 1),
+                                             a.pk + (row0 + k0) * kMergeChunk,
+                                             a.pv + (row0 + k0) * kMergeChunk);
+  if (threadIdx.x == 0) a.nflush[b] = nf;
+}
+
+struct MergeFin {
+  int32_t me;
+  int32_t* okey;
+  uint64_t* ow;
+  int64_t* dcount;
+  int* flags;
+  int64_t* base_sh;
+  ull self;
+  __device__ void operator()(const int32_t* keys, const ull* vals, int H) {
+    self += merge_emit_table(keys, vals, H, me, okey, ow, dcount, true, flags, base_sh);
+  }
+};
+
+template <typename WT>
+__global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT> a) {
+  constexpr int H = 1 << kMergeLog2H;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int wsum[kPartBlock / 64 + 1];
+  __shared__ int flags[4];
+  __shared__ int64_t base_sh;
+  __shared__ ull red[kPartBlock / 64];
+  int32_t* keys = (int32_t*)smem;
+  ull* vals = (ull*)(smem + (size_t)H * 4);
+  unsigned char* aux = smem + (size_t)H * 12;
+  const int64_t b = blockIdx.x;
+  const int64_t h = find_segment(a.part_start, a.nh, b);
+  const int p = (int)(b - a.part_start[h]);
+  const int P = (int)a.nparts[h];
+  const int64_t c0 = a.chunk_start[h], nck = a.chunk_start[h + 1] - c0;
+  const int32_t c = a.hubs[h];
+  const int64_t a0 = a.astart[c];
+  MergeFin fin;
+  fin.me = (int32_t)a.newid[c];
+  fin.okey = a.okey + a0;
+  fin.ow = a.ow + a0;
+  fin.dcount = a.dcount + fin.me;
+  fin.flags = flags;
+  fin.base_sh = &base_sh;
+  fin.self = 0;
+  part_reduce<ull, kMergeLog2H>(a.pk + c0 * kMergeChunk, a.pv + c0 * kMergeChunk,
+                                a.hoff + a.hoff_start[h], a.nflush + a.block_start[h], nck,
+                                a.rper[h], P, p, a.cap, keys, vals, aux, wsum, flags, fin);
+  const ull bs = part_block_sum(fin.self, red);
   if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
 }
 
 template <typename WT>
-static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const HubPlan& hp,
+static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPlan& pp,
                                const AggBuffers& ag, hipStream_t s) {
   MergeHubArgs<WT> a;
   a.rs = g.rs;
@@ -1870,26 +2268,34 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const HubPla
   a.dcount = ag.dcount;
   a.stats = ag.stats;
   a.hubs = ag.list + b.lstart[kFusedClasses];
-  a.nh = hp.nh;
-  a.chunk_start = hp.chunk_start;
-  a.tab_start = hp.tab_start;
-  a.scan_start = hp.scan_start;
-  a.tkeys = ag.tkeys;
-  a.tvals = ag.tvals;
-  a.occ = ag.occ;
-  a.occ_count = ag.occ_count;
-  const int64_t n = hp.slots > hp.nh ? hp.slots : hp.nh;
-  LV_LAUNCH(k_hub_reset<ull>, grid_for(n), kBlock, 0, s, ag.tkeys, ag.tvals, hp.slots,
-            ag.occ_count, hp.nh);
-  LV_LAUNCH(k_merge_hub_accumulate<WT>, (unsigned)hp.chunks, kBlock, 0, s, a);
-  LV_LAUNCH(k_merge_hub_emit<WT>, (unsigned)hp.scan_blocks, kBlock, 0, s, a);
+  a.nh = pp.nh;
+  a.chunk_start = pp.chunk_start;
+  a.block_start = pp.block_start;
+  a.part_start = pp.part_start;
+  a.hoff_start = pp.hoff_start;
+  a.rper = pp.rper;
+  a.nparts = pp.nparts;
+  a.pk = ag.pk;
+  a.pv = ag.pv;
+  a.hoff = ag.hoff;
+  a.nflush = ag.nflush;
+  a.cap = part_round_cap(kMergeLog2H, pp.shift);
+  static bool attr = false;
+  if (!attr) {
+    allow_part_lds(k_merge_part<WT>, 8);
+    allow_part_lds(k_merge_reduce<WT>, 8);
+    attr = true;
+  }
+  const size_t shm = part_lds_bytes(8);
+  LV_LAUNCH(k_merge_part<WT>, (unsigned)pp.blocks, kPartBlock, shm, s, a);
+  if (pp.parts > 0) LV_LAUNCH(k_merge_reduce<WT>, (unsigned)pp.parts, kPartBlock, shm, s, a);
   return hipGetLastError();
 }
 
-hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const HubPlan& hp,
+hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const PartPlan& pp,
                       const AggBuffers& ag, hipStream_t s) {
-  if (hp.nh <= 0) return hipSuccess;
-  return g.w64 ? merge_hubs_t<uint64_t>(g, b, hp, ag, s) : merge_hubs_t<uint32_t>(g, b, hp, ag, s);
+  if (pp.nh <= 0) return hipSuccess;
+  return g.w64 ? merge_hubs_t<uint64_t>(g, b, pp, ag, s) : merge_hubs_t<uint32_t>(g, b, pp, ag, s);
 }
 
 // Rows of the super-vertex graph where the merge left them.

@@ -20,6 +20,7 @@ STATUS = {0: "LV_OK", -1: "LV_EINVAL", -2: "LV_ENOMEM", -3: "LV_EHIP", -4: "LV_E
 LV_VALIDATE = 0x1
 LV_TRACE = 0x2
 LV_FORCE_WIDE = 0x4
+LV_SMALL_PARTS = 0x8
 
 LV_MAX_PASSES = 64
 LV_MAX_TRACE = 1024

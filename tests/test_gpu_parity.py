@@ -11,13 +11,16 @@ import pytest
 import torch
 
 import oracle as O
-from graphgen import (add_self_loops, csr_from_arcs, erdos_renyi, lattice_shortcuts, rmat,
-                      ring_of_cliques, sbm, single_edge, two_triangles)
+from graphgen import (add_self_loops, csr_from_arcs, erdos_renyi, lattice_shortcuts,
+                      planted_hubs, rmat, ring_of_cliques, sbm, single_edge, two_triangles)
 from graphgen.csr import Csr
 
 from .gpu_util import assert_state_equal, canonical_rows_fast, gpu_state
 
 pytestmark = pytest.mark.gpu
+
+LV_FORCE_WIDE = 0x4
+LV_SMALL_PARTS = 0x8  # many hash partitions with tiny tables: multi-partition, multi-round paths
 
 
 @pytest.fixture(scope="module")
@@ -122,6 +125,54 @@ def test_move_hub_with_large_community(lv):
     run_iterations(lv, g, st, max_iters=4, ctx="star partition")
 
 
+def hub_graphs():
+    """Rows far longer than a workgroup table (two-phase hub path of the move, and of the merge
+    once the hubs' neighbourhoods form communities)."""
+    return [
+        planted_hubs(sbm(40000, 400, 8.0, 2.0, seed=4, weights=(1, 16)),
+                     [100000, 33000, 17000, 9000, 5000], seed=2, weights=(1, 16)),
+        planted_hubs(rmat(14, seed=3), [60000, 20000], seed=5),
+    ]
+
+
+HUBS = hub_graphs()
+HUB_IDS = ["sbm40k+hubs", "rmat14+hubs"]
+PART_FLAGS = [0, LV_SMALL_PARTS, LV_SMALL_PARTS | LV_FORCE_WIDE]
+
+
+def test_hub_graphs_have_hub_rows():
+    # rows of more than 8192 arcs take the two-phase hub path, in more than one chunk
+    for g in HUBS:
+        assert int(g.degrees().max()) > 8192
+
+
+@pytest.mark.parametrize("flags", PART_FLAGS)
+@pytest.mark.parametrize("K", [1, 8])
+@pytest.mark.parametrize("gi", [0, 1], ids=HUB_IDS)
+def test_move_iterations_hub_rows(lv, gi, K, flags):
+    g = HUBS[gi]
+    st = O.State(O.Graph.from_csr(g))
+    run_iterations(lv, g, st, flags=flags, max_iters=8, substeps=K,
+                   ctx=f"{g.name} K{K} flags{flags}")
+    # hubs whose neighbours sit in a few large communities
+    C = (np.arange(g.n) % 5).astype(np.int32)
+    st = O.State(O.Graph.from_csr(g), C)
+    run_iterations(lv, g, st, flags=flags, max_iters=3, substeps=K, pass_index=1,
+                   ctx=f"{g.name} K{K} flags{flags} mod5")
+
+
+@pytest.mark.parametrize("flags", PART_FLAGS)
+@pytest.mark.parametrize("gi", [0, 1], ids=HUB_IDS)
+def test_run_hub_graphs(lv, gi, flags):
+    check_run(lv, HUBS[gi], flags=flags)
+
+
+@pytest.mark.parametrize("g", CORPUS, ids=IDS)
+def test_run_small_partitions(lv, g):
+    # the large communities of the aggregation take the multi-partition, multi-round path
+    check_run(lv, g, flags=LV_SMALL_PARTS)
+
+
 @pytest.mark.parametrize("g", CORPUS, ids=IDS)
 def test_modularity(lv, g):
     og = O.Graph.from_csr(g)
@@ -219,6 +270,7 @@ def test_run_rmat16_hubs(lv):
     assert res["q"] >= ra["q"] - 0.01, (res["q"], ra["q"])
     # the fully synchronous rule matches its oracle too (its quality is lower on this graph)
     check_run(lv, g, substeps=1)
+    check_run(lv, g, flags=LV_SMALL_PARTS)
 
 
 def test_run_deterministic(lv):
