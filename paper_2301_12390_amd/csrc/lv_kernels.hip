@@ -324,20 +324,10 @@ hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* pa
 
 constexpr int64_t kSeg = 16;
 
-// First r in [0, n] with off[r] >= e (off non-decreasing, n + 1 entries).
-__device__ __forceinline__ int64_t first_row_at(const int64_t* off, int64_t n, int64_t e) {
-  int64_t lo = 0, hi = n;  // off[hi] >= e; answer in [lo, hi]
-  if (off[0] >= e) return 0;
-  while (hi - lo > 1) {  // off[lo] < e <= off[hi]
-    const int64_t mid = lo + ((hi - lo) >> 1);
-    if (off[mid] >= e) hi = mid; else lo = mid;
-  }
-  return hi;
-}
-
-// Row sums without atomics: workgroup b owns the rows whose first arc lies in its range of
-// kRowTile arcs and sums each of them whole: rows of at most kShortRow arcs one per thread, longer
-// ones one per wavefront (coalesced). Rows of no arcs, and rows starting at nnz, keep K = 0.
+// Row sums: workgroup b sums the arcs of its range [lo, hi) of kRowTile arcs, attributing them
+// to the rows they belong to: up to kShortRow arcs of a row one per thread, longer stretches one
+// per wavefront (coalesced). A row lying wholly inside the range is stored; the (at most two)
+// rows crossing its ends are added atomically. K must be zero (rows of no arcs keep 0).
 constexpr int64_t kRowTile = 4096;
 constexpr int64_t kShortRow = 32;
 
@@ -345,33 +335,39 @@ template <typename WT>
 __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t n, int64_t nnz,
                                                     const WT* w, uint64_t* K) {
   __shared__ int64_t span[2];
-  __shared__ int32_t longs[kRowTile / kShortRow];
+  __shared__ int64_t longs[kRowTile / kShortRow + 2];
   __shared__ int nlong;
   const int64_t lo = (int64_t)blockIdx.x * kRowTile;
   const int64_t hi = lo + kRowTile < nnz ? lo + kRowTile : nnz;
-  if (threadIdx.x < 2) span[threadIdx.x] = first_row_at(off, n, threadIdx.x == 0 ? lo : hi);
+  if (threadIdx.x < 2) span[threadIdx.x] = row_of_arc(off, n, threadIdx.x == 0 ? lo : hi - 1);
   if (threadIdx.x == 0) nlong = 0;
   __syncthreads();
-  const int64_t r0 = span[0], r1 = span[1];  // rows r0 .. r1-1 start in [lo, hi)
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-    const int64_t e0 = off[r], e1 = off[r + 1];
+  for (int64_t r = span[0] + threadIdx.x; r <= span[1]; r += kBlock) {
+    const int64_t b0 = off[r], b1 = off[r + 1];
+    const int64_t e0 = b0 > lo ? b0 : lo, e1 = b1 < hi ? b1 : hi;
+    if (e1 <= e0) continue;
     if (e1 - e0 > kShortRow) {
-      longs[atomicAdd(&nlong, 1)] = (int32_t)(r - r0);
+      longs[atomicAdd(&nlong, 1)] = r;
       continue;
     }
     ull acc = 0;
     for (int64_t e = e0; e < e1; e++) acc += (ull)w[e];
-    K[r] = acc;
+    if (b0 >= lo && b1 <= hi) K[r] = acc;
+    else atomicAdd((ull*)&K[r], acc);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = wave; i < nlong; i += kBlock / 64) {
-    const int64_t r = r0 + longs[i];
-    const int64_t e0 = off[r], e1 = off[r + 1];
+    const int64_t r = longs[i];
+    const int64_t b0 = off[r], b1 = off[r + 1];
+    const int64_t e0 = b0 > lo ? b0 : lo, e1 = b1 < hi ? b1 : hi;
     ull acc = 0;
     for (int64_t e = e0 + lane; e < e1; e += 64) acc += (ull)ld_stream(w + e);
     acc = group_sum_u64<64>(acc);
-    if (lane == 0) K[r] = acc;
+    if (lane == 0) {
+      if (b0 >= lo && b1 <= hi) K[r] = acc;
+      else atomicAdd((ull*)&K[r], acc);
+    }
   }
 }
 
