@@ -12,7 +12,7 @@ shortcuts for road networks.
 """
 
 from .rng import splitmix64_mix, draw, stream_key  # noqa: F401
-from .csr import Csr, csr_from_arcs, csr_from_edges, csr_sha256  # noqa: F401
+from .csr import Csr, csr_from_arcs, csr_from_edges, csr_sha256, pack_graphs  # noqa: F401
 from .generators import (  # noqa: F401
     rmat,
     sbm,

@@ -130,3 +130,27 @@ def csr_sha256(g: Csr) -> str:
     h.update(g.indices.to(torch.int32).cpu().numpy().tobytes())
     h.update(g.weights.to(torch.int64).cpu().numpy().tobytes())
     return h.hexdigest()
+
+
+def pack_graphs(graphs, device=None, offsets_dtype=None):
+    """One CSR holding the given graphs with consecutive vertex ids (graph g owns vertices
+    vptr[g] .. vptr[g+1]-1 and arcs aptr[g] .. aptr[g+1]-1). Returns (packed, vptr, aptr) with
+    vptr and aptr as Python lists. Weights are widened to the widest input type."""
+    assert graphs, "no graphs"
+    dev = device if device is not None else graphs[0].device
+    wdt = torch.int64 if any(g.weights.dtype == torch.int64 for g in graphs) else torch.int32
+    vptr, aptr = [0], [0]
+    offs, idxs, ws = [], [], []
+    for g in graphs:
+        offs.append(g.offsets[:-1].to(dev, torch.int64) + aptr[-1])
+        idxs.append(g.indices.to(dev, torch.int64) + vptr[-1])
+        ws.append(g.weights.to(dev, wdt))
+        vptr.append(vptr[-1] + g.n)
+        aptr.append(aptr[-1] + g.nnz)
+    nnz = aptr[-1]
+    if offsets_dtype is None:
+        offsets_dtype = torch.int64 if nnz >= (1 << 31) else torch.int32
+    offs.append(torch.tensor([nnz], dtype=torch.int64, device=dev))
+    packed = Csr(vptr[-1], torch.cat(offs).to(offsets_dtype), torch.cat(idxs).to(torch.int32),
+                 torch.cat(ws), name=f"batch-{len(graphs)}")
+    return packed, vptr, aptr

@@ -156,6 +156,19 @@ typedef struct {
   int64_t last_candidates; /* candidate pairs of the last iteration */
 } lv_move_stats;
 
+/* Result of one graph of a batch (host). */
+typedef struct {
+  int32_t passes;                      /* passes run on this graph */
+  int32_t iterations_total;
+  int32_t iterations[LV_MAX_PASSES];   /* local-moving iterations of every pass */
+  uint32_t cap_hits;                   /* phases that stopped at max_iterations */
+  int32_t reserved;
+  int64_t n_communities;               /* communities of the graph's last level */
+  uint64_t W;                          /* total arc weight of the graph */
+  lv_i128 q_num;                       /* W^2 * Q exactly */
+  double q;
+} lv_graph_result;
+
 /* Context: binds a device and a workspace limited to hbm_budget_bytes (0 = no limit).
  * Returns LV_EINVAL for a bad device or null out, LV_EHIP if the device cannot be set. */
 lv_status louvain_ctx_create(int device, uint64_t hbm_budget_bytes, lv_ctx** out);
@@ -194,6 +207,22 @@ lv_status louvain_aggregate(lv_ctx* ctx, const lv_graph* g, const int32_t* C, in
                             void* offsets_out, int32_t offsets_64_out, int32_t* indices_out,
                             uint64_t* weights_out, int64_t* n_out, int64_t* nnz_out,
                             void* stream);
+
+/* Batch of independent graphs in one run (section 3.2 applied to every graph at once; the
+ * kernels of every step cover all graphs, so many small graphs fill the device together).
+ * packed: one CSR of the G graphs with consecutive global vertex ids: graph g owns vertices
+ * graph_vptr[g] .. graph_vptr[g+1]-1 and arcs graph_aptr[g] .. graph_aptr[g+1]-1, and no arc
+ * joins two graphs. graph_vptr, graph_aptr: (host) [G+1], from 0 to n and nnz, non-decreasing
+ * (LV_VALIDATE also checks them against the offsets and indices on the device).
+ * Every graph has its own W, tolerance schedule, convergence and stop rules, and its vertex
+ * classes hash ids local to the graph, so its result equals louvain_run on that graph alone.
+ * membership: [n] out, community of every vertex as a dense id local to its graph.
+ * per_graph (host): [G] results. G >= 1; errors as louvain_run (a graph with W > 2^62 gives
+ * LV_EOVERFLOW for the whole batch). LV_TRACE is ignored. */
+lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
+                              const int64_t* graph_vptr, const int64_t* graph_aptr,
+                              const lv_params* p, int32_t* membership,
+                              lv_graph_result* per_graph, void* stream);
 
 /* Modularity (section 1: Newman-Girvan) of membership C (labels in [0, n)):
  * q_num = W * sum_c sigma_c - sum_c Sigma_c^2 exactly (sigma_c: weight of arcs inside c),

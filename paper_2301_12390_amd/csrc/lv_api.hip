@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/louvain.h"
 #include "lv_device.h"
@@ -24,7 +25,7 @@ enum SlotId {
   S_HUBARR, S_PK, S_PV, S_HOFF, S_NFLUSH, S_PARTIAL, S_A, S_ASTART, S_NEWID, S_CURSOR,
   S_OLDLABEL, S_DCOUNT, S_ABASE, S_TKEY, S_TW, S_GOFF0, S_GIDX0, S_GW0, S_GOFF1, S_GIDX1, S_GW1,
   S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
-  S_REC, S_COUNT_SLOTS
+  S_REC, S_GID0, S_GIDA, S_GIDB, S_GBASE, S_GWORDS, S_GACT, S_APTR, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -58,6 +59,8 @@ struct lv_ctx {
   std::string err;
   size_t max_lds = 65536;  // largest LDS allocation of one workgroup on this device
   int part_shift = 0;      // LV_SMALL_PARTS of the current call
+  void* bpin = nullptr;    // pinned host words of batched runs (grow-only)
+  size_t bpin_bytes = 0;
   ull* pinned = nullptr;  // host-pinned words for small read-backs
   hipEvent_t ev[kEvents] = {};  // kEvStep per class step, then 2 for aggregation
 };
@@ -258,7 +261,8 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   CHK(wst(ctx, S_LIST, n, &list));
   CHK(wst(ctx, S_COUNTS, 1536, &counts));
   CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &scanp));
-  HIPCHK(lv::bucket_rows(ph.g.rs, ph.g.re, nullptr, n, K, ph.pass, list, counts,
+  HIPCHK(lv::bucket_rows(ph.g.rs, ph.g.re, nullptr, n, K, ph.pass, ph.m.gs.gid, ph.m.gs.gbase,
+                         list, counts,
                          ctx->pinned + PIN_COUNTS, ph.b, s));
   const int hf = lv::hub_first_class(ctx->max_lds, ph.wide);
   ph.m.hub_first = hf;
@@ -304,6 +308,18 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   return LV_OK;
 }
 
+// Per-graph iteration state of a batch (host side; device arrays in the phase's GraphSet).
+struct BatchPhase {
+  int64_t G = 0;
+  std::vector<u128> T;         // tolerance threshold of every graph for this pass
+  std::vector<uint8_t> act;    // graphs still iterating
+  std::vector<i128> passgain;  // gain sum over the pass
+  std::vector<int32_t> iters;  // iterations this pass
+  std::vector<uint8_t> capped; // stopped at max_iterations
+  ull* hS = nullptr;           // pinned: 2G words of per-graph gain sums
+  uint8_t* hact = nullptr;     // pinned: G activity flags
+};
+
 struct PhaseOut {
   int32_t iterations = 0;
   bool hit_cap = false;
@@ -316,7 +332,7 @@ struct PhaseOut {
 
 // Local-moving iterations; each is `classes` synchronous class steps.
 lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, hipStream_t s,
-                    lv_result* res, PhaseOut* out) {
+                    lv_result* res, PhaseOut* out, BatchPhase* bp = nullptr) {
   const bool trace = (flags & LV_TRACE) != 0;
   const int K = ph.classes;
   const int hf = ph.m.hub_first;
@@ -349,6 +365,7 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
   for (int it = 0; it < max_it; it++) {
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(lv::zero_words(stats0, 8 * K, s));
+    if (bp) HIPCHK(lv::zero_words(ph.m.gs.gS, 2 * bp->G, s));
     for (int k = 0; k < K; k++) {
       lv::MoveBuffers m = ph.m;
       m.stats = stats0 + 8 * k;
@@ -365,6 +382,9 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
     }
     ull* h = ctx->pinned + PIN_STATS;
     HIPCHK(hipMemcpyAsync(h, stats0, 8 * K * sizeof(ull), hipMemcpyDeviceToHost, s));
+    if (bp)
+      HIPCHK(hipMemcpyAsync(bp->hS, ph.m.gs.gS, 2 * bp->G * sizeof(ull), hipMemcpyDeviceToHost,
+                            s));
     HIPCHK(hipStreamSynchronize(s));
     float t_fused = 0, t_wg = 0, t_hub = 0, t_upd = 0;
     if (trace) {
@@ -427,6 +447,27 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
                         .count();
       }
     }
+    if (bp) {
+      // per graph: the same rule on its own S and threshold; the phase ends when none iterates
+      bool any = false;
+      for (int64_t g = 0; g < bp->G; g++) {
+        if (!bp->act[g]) continue;
+        const i128 Sg = (i128)(((u128)bp->hS[2 * g + 1] << 64) | bp->hS[2 * g]);
+        bp->passgain[g] += Sg;
+        bp->iters[g]++;
+        if (!((u128)Sg > bp->T[g])) bp->act[g] = 0;
+        else if (it + 1 == max_it) bp->capped[g] = 1, bp->act[g] = 0;
+        any = any || bp->act[g];
+      }
+      if (!any) {
+        out->hit_cap = false;
+        break;
+      }
+      memcpy(bp->hact, bp->act.data(), (size_t)bp->G);
+      HIPCHK(hipMemcpyAsync((void*)ph.m.gs.act, bp->hact, (size_t)bp->G, hipMemcpyHostToDevice,
+                            s));
+      continue;
+    }
     if (!((u128)S > T)) {  // the iteration's modularity change is within the tolerance
       out->hit_cap = false;
       break;
@@ -445,6 +486,7 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
                     hipStream_t s) {
   const int64_t n = g.n;
   lv::AggBuffers a;
+  a.gs = out->gs;  // batches: graph of every label and per-graph self super-arc weights
   CHK(wst(ctx, S_NEWID, n + 1, &a.newid));
   CHK(wst(ctx, S_MCOUNT, n, &a.mcount));
   CHK(wst(ctx, S_MSTART, n + 1, &a.mstart));
@@ -466,7 +508,7 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   HIPCHK(lv::zero_words(a.stats, 2, s));
   HIPCHK(lv::aggregate_prepare(g, C, csize, Sig, Kp, map, a, s));
   lv::Buckets b;
-  HIPCHK(lv::bucket_rows(nullptr, nullptr, a.A, n, 1, 0, a.list, a.counts,
+  HIPCHK(lv::bucket_rows(nullptr, nullptr, a.A, n, 1, 0, nullptr, nullptr, a.list, a.counts,
                          ctx->pinned + PIN_COUNTS, b, s));
   // the super-vertex count bounds the distinct targets of any community
   ull* hm = ctx->pinned + PIN_MISC;
@@ -513,6 +555,23 @@ lv_status singleton_qnum(lv_ctx* ctx, const lv::DevGraph& g, const uint64_t* K, 
   HIPCHK(hipStreamSynchronize(s));
   const u128 sq = ((u128)h[2] << 64) | h[1];
   *q = (i128)((u128)W * h[0]) - (i128)sq;
+  return LV_OK;
+}
+
+// Pinned host memory of at least `bytes` for batched runs (grow-only, freed with the context).
+lv_status batch_pinned(lv_ctx* ctx, size_t bytes, void** out) {
+  if (ctx->bpin_bytes < bytes) {
+    if (ctx->bpin) (void)hipHostFree(ctx->bpin);
+    ctx->bpin = nullptr;
+    ctx->bpin_bytes = 0;
+    hipError_t e = hipHostMalloc(&ctx->bpin, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ctx->bpin = nullptr;
+      return fail_hip(ctx, "hipHostMalloc", e);
+    }
+    ctx->bpin_bytes = bytes;
+  }
+  *out = ctx->bpin;
   return LV_OK;
 }
 
@@ -564,6 +623,7 @@ void louvain_ctx_destroy(lv_ctx* ctx) {
   for (int i = 0; i < kEvents; i++)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->bpin) (void)hipHostFree(ctx->bpin);
   delete ctx;
 }
 
@@ -842,6 +902,233 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
   HIPCHK(hipStreamSynchronize(s));
   res->total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
                                                            t_start).count();
+  return LV_OK;
+}
+
+// Many graphs in one run: the packed union goes through the same kernels as one graph, with each
+// vertex's W, tolerance, iteration state and class hash taken from its own graph, so that every
+// graph's result equals that of louvain_run on it alone.
+lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
+                              const int64_t* graph_vptr, const int64_t* graph_aptr,
+                              const lv_params* p, int32_t* membership,
+                              lv_graph_result* per_graph, void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  CHK(check_params(ctx, p));
+  if (G < 1) return fail(ctx, LV_EINVAL, "G must be >= 1");
+  if (!graph_vptr || !graph_aptr || !per_graph)
+    return fail(ctx, LV_EINVAL, "graph_vptr, graph_aptr or per_graph is NULL");
+  if (!packed) return fail(ctx, LV_EINVAL, "graph is NULL");
+  if (graph_vptr[0] != 0 || graph_aptr[0] != 0 || graph_vptr[G] != packed->n ||
+      graph_aptr[G] != packed->nnz)
+    return fail(ctx, LV_EINVAL, "graph_vptr/graph_aptr must start at 0 and end at n/nnz");
+  for (int32_t g = 0; g < G; g++)
+    if (graph_vptr[g + 1] < graph_vptr[g] || graph_aptr[g + 1] < graph_aptr[g])
+      return fail(ctx, LV_EINVAL, "graph_vptr/graph_aptr must be non-decreasing");
+  ctx->part_shift = (p->flags & LV_SMALL_PARTS) ? kSmallPartShift : 0;
+  memset(per_graph, 0, sizeof(lv_graph_result) * (size_t)G);
+  for (int32_t g = 0; g < G; g++) per_graph[g].n_communities = graph_vptr[g + 1] - graph_vptr[g];
+  hipStream_t s = (hipStream_t)stream;
+  lv::DevGraph g0;
+  CHK(import_graph(ctx, packed, (p->flags & LV_VALIDATE) != 0, s, &g0));
+  const int64_t n0 = g0.n;
+  if (n0 > 0 && !membership) return fail(ctx, LV_EINVAL, "membership is NULL");
+  if (n0 == 0) return LV_OK;
+
+  // per-graph device words: Wg [G], gS [2G], gself [G], gsq [2G]; act [G] bytes; graph bases:
+  // three arrays of G + 1 (level 0, then two alternating levels); aptr for validation
+  ull* gw = nullptr;
+  uint8_t* gact = nullptr;
+  int64_t* gbase = nullptr;
+  int64_t* aptr_d = nullptr;
+  int32_t* gid0 = nullptr;
+  CHK(wst(ctx, S_GWORDS, 6 * (int64_t)G, &gw));
+  CHK(wst(ctx, S_GACT, G, &gact));
+  CHK(wst(ctx, S_GBASE, 3 * ((int64_t)G + 1), &gbase));
+  CHK(wst(ctx, S_GID0, n0, &gid0));
+  ull* Wg = gw;
+  ull* gS = gw + G;
+  ull* gself = gw + 3 * (int64_t)G;
+  ull* gsq = gw + 4 * (int64_t)G;
+  void* pin = nullptr;
+  CHK(batch_pinned(ctx, (size_t)G * (6 * sizeof(ull) + 1) + 64, &pin));
+  ull* hw = (ull*)pin;                       // 4G words of read-backs
+  uint8_t* hact = (uint8_t*)(hw + 4 * (int64_t)G);
+  HIPCHK(hipMemcpyAsync(gbase, graph_vptr, ((size_t)G + 1) * sizeof(int64_t),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(lv::graph_ids(gbase, G, n0, gid0, s));
+  if (p->flags & LV_VALIDATE) {
+    CHK(wst(ctx, S_APTR, (int64_t)G + 1, &aptr_d));
+    unsigned int* bad = nullptr;
+    CHK(wst(ctx, S_BAD, 1, &bad));
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(unsigned int), s));
+    HIPCHK(hipMemcpyAsync(aptr_d, graph_aptr, ((size_t)G + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(lv::validate_batch(g0, gid0, gbase, aptr_d, G, bad, s));
+    unsigned int hb = 0;
+    HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hb & 1u) return fail(ctx, LV_EINVAL, "graph_aptr does not match the offsets");
+    if (hb & 2u) return fail(ctx, LV_EINVAL, "an arc joins two graphs of the batch");
+  }
+
+  uint64_t* K = nullptr;
+  int32_t* C = nullptr;
+  uint64_t* Sig = nullptr;
+  int32_t* csize = nullptr;
+  int32_t* map = nullptr;
+  CHK(wst(ctx, S_K, n0, &K));
+  CHK(wst(ctx, S_C, n0, &C));
+  CHK(wst(ctx, S_SIG, n0, &Sig));
+  CHK(wst(ctx, S_CSIZE, n0, &csize));
+  CHK(wst(ctx, S_MAP, n0, &map));
+  HIPCHK(lv::fill_u64(K, 0, n0, s));
+  HIPCHK(lv::row_sums(g0, K, s));
+  uint64_t Wtot = 0, maxK = 0;
+  CHK(weight_stats(ctx, K, n0, s, &Wtot, &maxK));
+  HIPCHK(lv::zero_words(Wg, G, s));
+  HIPCHK(lv::graph_sums(K, n0, gid0, false, Wg, s));
+  HIPCHK(hipMemcpyAsync(hw, Wg, (size_t)G * sizeof(ull), hipMemcpyDeviceToHost, s));
+  HIPCHK(lv::iota_i32(membership, n0, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<uint64_t> W(G);
+  std::vector<uint8_t> done(G);
+  std::vector<i128> qnum(G, 0);
+  uint64_t maxW = 0;
+  for (int32_t g = 0; g < G; g++) {
+    W[g] = hw[g];
+    per_graph[g].W = W[g];
+    done[g] = W[g] == 0;  // no arcs: identity membership, Q = 0, no pass
+    maxW = std::max(maxW, W[g]);
+  }
+  if (maxW > ((uint64_t)1 << 62)) return fail(ctx, LV_EOVERFLOW, "a graph's weight exceeds 2^62");
+
+  lv::DevGraph cur = g0;
+  const int32_t* gid = gid0;
+  int64_t* gb_cur = gbase;
+  int which = 0;
+  void* rec = nullptr;
+  CHK(ws(ctx, S_REC, (size_t)n0 * lv::kRecBytes, &rec));
+  BatchPhase bp;
+  bp.G = G;
+  bp.hS = hw;
+  bp.hact = hact;
+  for (int pass = 0; pass < p->max_passes; pass++) {
+    bool any = false;
+    for (int32_t g = 0; g < G; g++) any = any || !done[g];
+    if (!any) break;
+    HIPCHK(lv::init_state(cur.n, K, rec, s));
+    Phase ph;
+    ph.g = cur;
+    ph.m.K = K;
+    ph.m.rec = rec;
+    ph.m.W = Wtot;
+    ph.m.gs.G = G;
+    ph.m.gs.gid = gid;
+    ph.m.gs.gbase = gb_cur;
+    ph.m.gs.Wg = (const uint64_t*)Wg;
+    ph.m.gs.act = gact;
+    ph.m.gs.gS = gS;
+    ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)maxW * maxK < ((u128)1 << 63));
+    ph.classes = p->substeps;
+    ph.pass = pass;
+    bp.T.assign(G, 0);
+    bp.act.assign(G, 0);
+    bp.passgain.assign(G, 0);
+    bp.iters.assign(G, 0);
+    bp.capped.assign(G, 0);
+    for (int32_t g = 0; g < G; g++) {
+      bp.act[g] = !done[g];
+      bp.T[g] = tolerance_threshold(W[g], p->tolerance_exp10, p->decline_exp10, pass);
+    }
+    memcpy(hact, bp.act.data(), (size_t)G);
+    HIPCHK(hipMemcpyAsync(gact, hact, (size_t)G, hipMemcpyHostToDevice, s));
+    CHK(plan_phase(ctx, ph, s));
+    PhaseOut po;
+    CHK(run_phase(ctx, ph, 0, p->max_iterations, p->flags & ~LV_TRACE, s, nullptr, &po, &bp));
+    std::vector<uint8_t> ran(G, 0);
+    for (int32_t g = 0; g < G; g++) {
+      if (done[g]) continue;
+      ran[g] = 1;
+      lv_graph_result& r = per_graph[g];
+      r.passes = pass + 1;
+      r.iterations[pass] = bp.iters[g];
+      r.iterations_total += bp.iters[g];
+      r.cap_hits += bp.capped[g];
+      if (bp.passgain[g] == 0) done[g] = 1;  // no move: the partition is that of this level
+    }
+    // aggregate the whole union (a graph with no move maps to itself); per-graph Qnum of the
+    // new level = that of singletons on it
+    int64_t* nrs = nullptr;
+    int64_t* nre = nullptr;
+    int32_t* nidx = nullptr;
+    uint64_t* nw = nullptr;
+    int32_t* ngid = nullptr;
+    CHK(wst(ctx, which ? S_GOFF1 : S_GOFF0, cur.n, &nrs));
+    CHK(wst(ctx, which ? S_GRE1 : S_GRE0, cur.n, &nre));
+    CHK(wst(ctx, which ? S_GIDX1 : S_GIDX0, cur.nnz, &nidx));
+    CHK(wst(ctx, which ? S_GW1 : S_GW0, cur.nnz, &nw));
+    CHK(wst(ctx, which ? S_GIDB : S_GIDA, cur.n, &ngid));
+    int64_t* gb_next = gbase + ((int64_t)G + 1) * (which ? 2 : 1);
+    int64_t np = 0, nnzp = 0;
+    uint64_t self = 0;
+    lv::AggBuffers ab;
+    ab.gs.gid = gid;
+    ab.gs.gself = gself;
+    HIPCHK(lv::zero_words(gself, G, s));
+    HIPCHK(lv::unpack_state(cur.n, rec, C, Sig, csize, s));
+    CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s));
+    HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
+    HIPCHK(lv::compose_membership(membership, n0, map, s));
+    HIPCHK(lv::next_gbase(ab.newid, gb_cur, G, gb_next, s));
+    HIPCHK(lv::graph_ids(gb_next, G, np, ngid, s));
+    HIPCHK(lv::zero_words(gsq, 2 * (int64_t)G, s));
+    HIPCHK(lv::graph_sums(K, np, ngid, true, gsq, s));
+    ull* d = nullptr;
+    {
+      ull* st = nullptr;
+      CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
+      d = st + ST_MISC;
+    }
+    HIPCHK(lv::zero_words(d, 2, s));
+    HIPCHK(lv::sum_max_u64(K, np, d, s));
+    HIPCHK(hipMemcpyAsync(hw, gself, 3 * (size_t)G * sizeof(ull), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hw + 3 * (int64_t)G, d, 2 * sizeof(ull), hipMemcpyDeviceToHost, s));
+    std::vector<int64_t> nb_old(G + 1), nb_new(G + 1);
+    HIPCHK(hipMemcpyAsync(nb_old.data(), gb_cur, ((size_t)G + 1) * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(nb_new.data(), gb_next, ((size_t)G + 1) * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    maxK = hw[3 * (int64_t)G + 1];
+    for (int32_t g = 0; g < G; g++) {
+      per_graph[g].n_communities = nb_new[g + 1] - nb_new[g];
+      if (!ran[g]) continue;
+      const u128 sq = ((u128)hw[G + 2 * (int64_t)g + 1] << 64) | hw[G + 2 * (int64_t)g];
+      qnum[g] = (i128)((u128)W[g] * hw[g]) - (i128)sq;
+      if (nb_new[g + 1] - nb_new[g] == nb_old[g + 1] - nb_old[g]) done[g] = 1;  // no shrink
+    }
+    lv::DevGraph nxt;
+    nxt.n = np;
+    nxt.nnz = nnzp;
+    nxt.rs = nrs;
+    nxt.re = nre;
+    nxt.off = nullptr;
+    nxt.idx = nidx;
+    nxt.w = nw;
+    nxt.w64 = true;
+    cur = nxt;
+    gid = ngid;
+    gb_cur = gb_next;
+    which ^= 1;
+  }
+  HIPCHK(lv::localize_membership(membership, n0, gid0, gb_cur, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int32_t g = 0; g < G; g++) {
+    per_graph[g].q_num = to_i128(qnum[g]);
+    per_graph[g].q = q_of(qnum[g], W[g]);
+  }
   return LV_OK;
 }
 

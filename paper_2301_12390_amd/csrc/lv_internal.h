@@ -19,6 +19,18 @@ struct DevGraph {
   bool w64 = false;  // weights are uint64 (else uint32)
 };
 
+// A batch of graphs packed with consecutive vertex ids, each with its own W and iteration state
+// (gid null: a single graph, whose W is passed separately).
+struct GraphSet {
+  int64_t G = 0;
+  const int32_t* gid = nullptr;       // [n] graph of every vertex
+  const int64_t* gbase = nullptr;     // [G+1] first vertex of every graph
+  const uint64_t* Wg = nullptr;       // [G] total weight
+  const uint8_t* act = nullptr;       // [G] graphs iterating in this phase
+  unsigned long long* gS = nullptr;   // [2G] gain sum of the iteration per graph (128-bit)
+  unsigned long long* gself = nullptr;  // [G] weight of self super-arcs made by an aggregation
+};
+
 // Rows grouped by (vertex class k, degree class j), list segment 12k + j (12 = kDegClasses).
 struct Buckets {
   int classes = 1;
@@ -79,11 +91,13 @@ hipError_t pack_state(int64_t n, const int32_t* C, const uint64_t* Sig, const in
 hipError_t unpack_state(int64_t n, const void* rec, int32_t* C, uint64_t* Sig, int32_t* csize,
                         hipStream_t s);
 // Classify rows (lengths from offsets, or from `len` if non-null over m items) by vertex
-// class (K classes of pass `pass`) and degree class. counts: device scratch of 1536 words;
+// class (K classes of pass `pass`, hashing ids local to their graph when gid is given) and
+// degree class. counts: device scratch of 1536 words;
 // host_counts: 1536 pinned words. Host result in `b` (synchronises the stream).
 hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
-                       int K, int pass, int32_t* list, unsigned long long* counts,
-                       unsigned long long* host_counts, Buckets& b, hipStream_t s);
+                       int K, int pass, const int32_t* gid, const int64_t* gbase, int32_t* list,
+                       unsigned long long* counts, unsigned long long* host_counts, Buckets& b,
+                       hipStream_t s);
 // Two-phase plan for the items items[0 .. nh) (lengths from rs/re, or len[item]) whose keys
 // take at most `cap` distinct values; vb: value bytes; merge: one-chunk items need no phase 2.
 // arrays: kPlanWords * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.
@@ -112,6 +126,7 @@ struct MoveBuffers {
   int32_t* nflush = nullptr;            // table flushes of every hub phase-1 workgroup
   unsigned long long* partial = nullptr;  // hub phase-2 partials: 5 words per workgroup
   int hub_first = 10;                     // first degree class on the two-phase hub path
+  GraphSet gs;                            // batch of graphs, if any
 };
 
 // First degree class that takes the two-phase hub path, given the largest LDS allocation a
@@ -167,6 +182,7 @@ struct AggBuffers {
   unsigned long long* pv = nullptr;
   int32_t* hoff = nullptr;               // their segment bounds
   int32_t* nflush = nullptr;             // table flushes of every phase-1 workgroup
+  GraphSet gs;                           // batches: gid (of labels) and gself are used
 };
 // Renumbering, member lists and flat arc ranges (everything before the merge).
 hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t* csize,
@@ -184,5 +200,19 @@ hipError_t compact_rows(const int64_t* offp, int64_t np, int64_t nnzp, const int
                         const int64_t* astart, const int32_t* tkey, const uint64_t* tw,
                         int32_t* idx_out, uint64_t* w_out, hipStream_t s);
 hipError_t compose_membership(int32_t* top, int64_t n, const int32_t* map, hipStream_t s);
+
+// ---- batches of graphs (consecutive vertex ranges gbase[g] .. gbase[g+1])
+hipError_t graph_ids(const int64_t* gbase, int64_t G, int64_t n, int32_t* gid, hipStream_t s);
+// out[g] += sum over graph g of x (squares: out[2g..2g+1] += sum of x^2, 128-bit)
+hipError_t graph_sums(const uint64_t* x, int64_t n, const int32_t* gid, bool squares,
+                      unsigned long long* out, hipStream_t s);
+// out[g] = newid[gbase[g]] for g = 0 .. G
+hipError_t next_gbase(const int64_t* newid, const int64_t* gbase, int64_t G, int64_t* out,
+                      hipStream_t s);
+hipError_t localize_membership(int32_t* memb, int64_t n, const int32_t* gid0,
+                               const int64_t* gfinal, hipStream_t s);
+// *bad |= 1 if a graph's first arc is not at aptr[g], |= 2 if an arc leaves its graph.
+hipError_t validate_batch(const DevGraph& g, const int32_t* gid, const int64_t* gbase,
+                          const int64_t* aptr, int64_t G, unsigned int* bad, hipStream_t s);
 
 }  // namespace lv

@@ -514,15 +514,20 @@ __device__ __forceinline__ int64_t item_len(const int64_t* rs, const int64_t* re
 // Segment of item i: kDegClasses * (vertex class) + degree class.
 constexpr int kMaxSeg = kDegClasses * kMaxClasses;
 
-__device__ __forceinline__ int segment_of(int64_t L, int K, int pass, int64_t i) {
-  const int k = K > 1 ? vertex_class(pass, K, i) : 0;
+// Vertex classes hash the id of a vertex within its own graph: i - gbase[gid[i]] in a batch of
+// graphs packed with consecutive ids (gid null: one graph).
+__device__ __forceinline__ int segment_of(int64_t L, int K, int pass, int64_t i,
+                                          const int32_t* gid, const int64_t* gbase) {
+  const int64_t loc = gid ? i - gbase[gid[i]] : i;
+  const int k = K > 1 ? vertex_class(pass, K, loc) : 0;
   return kDegClasses * k + bucket_of(L);
 }
 
 // counts[0 .. nseg): items per segment, counts[kMaxSeg .. kMaxSeg + nseg): total length.
 __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, const int64_t* re,
                                                         const int64_t* len, int64_t m, int K,
-                                                        int pass, ull* counts) {
+                                                        int pass, const int32_t* gid,
+                                                        const int64_t* gbase, ull* counts) {
   __shared__ ull c[2 * kMaxSeg];
   const int nseg = kDegClasses * K;
   for (int t = threadIdx.x; t < 2 * kMaxSeg; t += blockDim.x) c[t] = 0;
@@ -531,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, cons
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t L = item_len(rs, re, len, i);
     if (L > 0) {
-      const int sg = segment_of(L, K, pass, i);
+      const int sg = segment_of(L, K, pass, i, gid, gbase);
       atomicAdd(&c[sg], 1ull);
       atomicAdd(&c[kMaxSeg + sg], (ull)L);
     }
@@ -546,8 +551,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, cons
 // starts: first list position per segment; cursor: per-segment fill counters (zero).
 __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const int64_t* re,
                                                        const int64_t* len, int64_t m, int K,
-                                                       int pass, const ull* starts, ull* cursor,
-                                                       int32_t* list) {
+                                                       int pass, const int32_t* gid,
+                                                       const int64_t* gbase, const ull* starts,
+                                                       ull* cursor, int32_t* list) {
   __shared__ int cnt[kMaxSeg];
   __shared__ ull base[kMaxSeg];
   const int nseg = kDegClasses * K;
@@ -560,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const
     if (i < m) {
       const int64_t L = item_len(rs, re, len, i);
       if (L > 0) {
-        sg = segment_of(L, K, pass, i);
+        sg = segment_of(L, K, pass, i, gid, gbase);
         rank = atomicAdd(&cnt[sg], 1);
       }
     }
@@ -574,8 +580,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const
 }
 
 hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
-                       int K, int pass, int32_t* list, ull* counts, ull* host_counts, Buckets& b,
-                       hipStream_t s) {
+                       int K, int pass, const int32_t* gid, const int64_t* gbase, int32_t* list,
+                       ull* counts, ull* host_counts, Buckets& b, hipStream_t s) {
   b = Buckets();
   b.classes = K;
   if (m <= 0) return hipSuccess;
@@ -583,7 +589,7 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
   // counts layout (kMaxSeg words each): items, lengths, fill cursors, segment starts
   LV_LAUNCH(k_zero_words, 8, kBlock, 0, s, counts, (int64_t)(3 * kMaxSeg));
   LV_LAUNCH(k_bucket_count, grid_for(m, kBlock, 4096), kBlock, 0, s, rs, re, len, m, K, pass,
-            counts);
+            gid, gbase, counts);
   hipError_t e = hipMemcpyAsync(host_counts, counts, 2 * kMaxSeg * sizeof(ull),
                                 hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
@@ -603,7 +609,7 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
                      s);
   if (e != hipSuccess) return e;
   LV_LAUNCH(k_bucket_fill, grid_for(m, kBlock, 8192), kBlock, 0, s, rs, re, len, m, K, pass,
-            counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
+            gid, gbase, counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
   return hipGetLastError();
 }
 
@@ -692,6 +698,20 @@ hipError_t plan_parts(const int64_t* rs, const int64_t* re, const int64_t* len,
 // All reads are of the previous iteration's C, Sigma and csize; every vertex writes its decision,
 // and the decisions are applied after the kernel, so the outcome does not depend on scheduling.
 
+// Batches of graphs (GraphSet): W and graph of vertex v, false if its graph is not iterating in
+// this phase; and the per-graph gain sums of the iteration.
+__device__ __forceinline__ bool gs_vertex(const GraphSet& gs, int32_t v, uint64_t* W,
+                                          int32_t* g) {
+  if (!gs.gid) return true;
+  const int32_t x = gs.gid[v];
+  *g = x;
+  *W = gs.Wg[x];
+  return gs.act[x] != 0;
+}
+__device__ __forceinline__ void gs_add_gain(const GraphSet& gs, int32_t g, u128 gain) {
+  if (gs.gS) atomic_add_u128(gs.gS + 2 * g, gain);
+}
+
 template <typename WT>
 struct MoveArgs {
   const int64_t* rs;
@@ -706,6 +726,7 @@ struct MoveArgs {
   int64_t lstart[8];  // first list position of class k; lstart[7] = end of class 6
   int32_t* tgt;       // decision of every vertex: its community after the step
   ull* partial;       // per block: gain sum (2 words), moves, candidate pairs
+  GraphSet gs;        // batch of graphs (gs.gid null: one graph, W above)
 };
 
 struct BlockShared {
@@ -738,8 +759,11 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
     gv[s] = 0;
   }
   __syncthreads();
+  uint64_t W = a.W;
+  int32_t gr = 0;
+  const bool on = valid && gs_vertex(a.gs, v, &W, &gr);
   int64_t e0 = 0, e1 = 0;
-  if (valid) {
+  if (on) {
     e0 = a.rs[v];
     e1 = a.re[v];
   }
@@ -767,7 +791,7 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
         continue;
       }
       nc++;
-      const T g = Ar::of(a.W, kv, Ki, a.rec[c].sig);
+      const T g = Ar::of(W, kv, Ki, a.rec[c].sig);
       if (better(g, c, bg, bc)) {
         bg = g;
         bc = c;
@@ -812,11 +836,12 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
     int32_t target = d;
     if (bc != INT32_MAX) {
       const VRec rd = a.rec[d];
-      const T stay = Ar::of(a.W, kd, Ki, rd.sig - Ki);
+      const T stay = Ar::of(W, kd, Ki, rd.sig - Ki);
       if (bg > stay && !(rd.size == 1 && a.rec[bc].size == 1 && bc > d)) {
         target = bc;
         moved = 1;
         gain = Ar::diff(bg, stay);
+        gs_add_gain(a.gs, gr, gain);
       }
     }
     a.tgt[v] = target;
@@ -846,10 +871,12 @@ __device__ __forceinline__ void move_regs(const MoveArgs<WT>& a, int64_t lb, int
   const int64_t li = lb * kBlock + threadIdx.x;
   u128 gain = 0;
   ull moved = 0, nc = 0;
+  uint64_t W = a.W;
+  int32_t gr = 0;
   if (li < lcount) {
     const int32_t v = a.list[lbase + li];
     const int64_t e0 = a.rs[v];
-    const int L = (int)(a.re[v] - e0);
+    const int L = gs_vertex(a.gs, v, &W, &gr) ? (int)(a.re[v] - e0) : 0;
     const VRec rv = a.rec[v];
     const uint64_t Ki = a.K[v];
     int32_t key[MAXD];
@@ -908,7 +935,7 @@ __device__ __forceinline__ void move_regs(const MoveArgs<WT>& a, int64_t lb, int
       }
       nc++;
       const ull sc = known[i] ? sg[i] : a.rec[key[i]].sig;
-      const T g = Ar::of(a.W, kw[i], Ki, sc);
+      const T g = Ar::of(W, kw[i], Ki, sc);
       if (better(g, key[i], bg, bc)) {
         bg = g;
         bc = key[i];
@@ -919,13 +946,14 @@ __device__ __forceinline__ void move_regs(const MoveArgs<WT>& a, int64_t lb, int
     int32_t target = d;
     if (bc != INT32_MAX) {
       const VRec rd = d == v ? rv : a.rec[d];
-      const T stay = Ar::of(a.W, kd, Ki, rd.sig - Ki);
+      const T stay = Ar::of(W, kd, Ki, rd.sig - Ki);
       if (bg > stay) {
         const int32_t bs = bknown ? bsize : a.rec[bc].size;
         if (!(rd.size == 1 && bs == 1 && bc > d)) {
           target = bc;
           moved = 1;
           gain = Ar::diff(bg, stay);
+          gs_add_gain(a.gs, gr, gain);
         }
       }
     }
@@ -1011,6 +1039,7 @@ struct WgArgs {
   const int32_t* rows;  // the class's rows
   int32_t* tgt;
   ull* partial;         // this launch's block records
+  GraphSet gs;
 };
 
 // SIGC: the table also caches Sigma of candidates seen through a neighbour labelling its own
@@ -1037,7 +1066,10 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
     if (SIGC) sigs[s] = kNoSig;
   }
   __syncthreads();
-  const int64_t e0 = a.rs[v], e1 = a.re[v];
+  uint64_t W = a.W;
+  int32_t gr = 0;
+  const bool on = gs_vertex(a.gs, v, &W, &gr);
+  const int64_t e0 = a.rs[v], e1 = on ? a.re[v] : e0;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kWgBlock) {
     const int32_t j = ld_stream(a.idx + e);
     const V wv = (V)ld_stream(a.w + e);
@@ -1068,7 +1100,7 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
     }
     nc++;
     const ull sc = SIGC ? sigs[s] : kNoSig;
-    const T g = Ar::of(a.W, kv, Ki, sc != kNoSig ? sc : a.rec[c].sig);
+    const T g = Ar::of(W, kv, Ki, sc != kNoSig ? sc : a.rec[c].sig);
     if (better(g, c, bg, bc)) {
       bg = g;
       bc = c;
@@ -1108,11 +1140,12 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
     ull moved = 0;
     if (bc != INT32_MAX) {
       const VRec rd = a.rec[d];
-      const T stay = Ar::of(a.W, kd, Ki, rd.sig - Ki);
+      const T stay = Ar::of(W, kd, Ki, rd.sig - Ki);
       if (bg > stay && !(rd.size == 1 && a.rec[bc].size == 1 && bc > d)) {
         target = bc;
         moved = 1;
         gain = Ar::diff(bg, stay);
+        gs_add_gain(a.gs, gr, gain);
       }
     }
     a.tgt[v] = target;
@@ -1176,6 +1209,7 @@ static hipError_t move_fused_t(const DevGraph& g, const Buckets& b, int cls, con
   a.list = m.list;
   a.tgt = m.tgt;
   a.partial = m.block_partial;
+  a.gs = m.gs;
   int64_t blocks = 0;
   size_t shm = 0;
   const int base = kDegClasses * cls;
@@ -1210,6 +1244,7 @@ static hipError_t move_wg_t(const DevGraph& g, const Buckets& b, int cls, const 
   wa.rec = (const VRec*)m.rec;
   wa.W = m.W;
   wa.tgt = m.tgt;
+  wa.gs = m.gs;
   for (int k = kFusedClasses; k < m.hub_first; k++) {
     const int64_t rows = b.count[base + k];
     if (rows == 0) continue;
@@ -1477,6 +1512,7 @@ struct HubArgs {
   ull* partial;      // 5 words per phase-2 workgroup: gain lo, gain hi, community, kd, candidates
   int32_t* tgt;
   ull* stats;
+  GraphSet gs;
 };
 
 // Phase 1 of the hub rows: workgroup i of hub h walks chunks [i R, (i + 1) R) of its row.
@@ -1526,7 +1562,11 @@ __global__ __launch_bounds__(kPartBlock) void k_hub_part(HubArgs<WT, V> a) {
   acc.v = a.hubs[h];
   acc.e0 = a.rs[acc.v];
   acc.e1 = a.re[acc.v];
-  const int nf = part_walk<V, LOG2H>(acc, k0, k1, P, keys, vals, cnt, wsum, flags,
+  uint64_t W;
+  int32_t gr;
+  // a hub of a graph that is not iterating walks nothing (no rows: phase 2 finds no key)
+  const int64_t k1w = gs_vertex(a.gs, acc.v, &W, &gr) ? k1 : k0;
+  const int nf = part_walk<V, LOG2H>(acc, k0, k1w, P, keys, vals, cnt, wsum, flags,
                                      a.hoff + a.hoff_start[h] + k0 * (P + 1),
                                      a.pk + (row0 + k0) * Q, a.pv + (row0 + k0) * Q);
   if (threadIdx.x == 0) a.nflush[b] = nf;
@@ -1594,6 +1634,8 @@ __global__ __launch_bounds__(kPartBlock) void k_hub_reduce(
   HubFin<WIDE> fin;
   fin.rec = a.rec;
   fin.W = a.W;
+  int32_t gr = 0;
+  gs_vertex(a.gs, v, &fin.W, &gr);
   fin.Ki = a.K[v];
   fin.d = a.rec[v].c;
   fin.bg = Ar::lowest();
@@ -1672,14 +1714,18 @@ __global__ __launch_bounds__(kBlock) void k_hub_decide(HubArgs<WT, typename Gain
     }
     const int32_t d = a.rec[v].c;
     int32_t target = d;
+    uint64_t W = a.W;
+    int32_t gr = 0;
+    gs_vertex(a.gs, v, &W, &gr);  // an inactive graph's hub has no candidate (bc unset)
     if (bc != INT32_MAX) {
       const uint64_t Ki = a.K[v];
       const VRec rd = a.rec[d];
-      const T stay = Ar::of(a.W, kd, Ki, rd.sig - Ki);
+      const T stay = Ar::of(W, kd, Ki, rd.sig - Ki);
       if (bg > stay && !(rd.size == 1 && a.rec[bc].size == 1 && bc > d)) {
         gain = Ar::diff(bg, stay);
         target = bc;
         moved = 1;
+        gs_add_gain(a.gs, gr, gain);
       }
     }
     a.tgt[v] = target;
@@ -1729,6 +1775,7 @@ static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, cons
   a.partial = m.partial;
   a.tgt = m.tgt;
   a.stats = m.stats;
+  a.gs = m.gs;
   static bool attr = false;
   if (!attr) {
     allow_part_lds(k_hub_part<WT, V>, vb);
@@ -1884,6 +1931,8 @@ struct MergeArgs {
   const int32_t* list;
   int64_t bstart[8];
   int64_t lstart[8];
+  const int32_t* gid;  // batches: graph of every label, and per-graph self super-arc weights
+  ull* gself;
 };
 
 template <typename WT, int G, int LOG2H>
@@ -1938,7 +1987,10 @@ __device__ __forceinline__ void merge_group(const MergeArgs<WT>& a, int64_t lb, 
       const int p = atomicAdd(&gcount[gid], 1);
       a.okey[a0 + p] = key;
       a.ow[a0 + p] = gv[s];
-      if (key == me) self = gv[s];
+      if (key == me) {
+        self = gv[s];
+        if (a.gself) atomicAdd(&a.gself[a.gid[c]], self);
+      }
     }
   }
   __syncthreads();
@@ -2012,6 +2064,8 @@ static hipError_t merge_lds_t(const DevGraph& g, const Buckets& b, const AggBuff
   a.dcount = ag.dcount;
   a.partial = ag.block_partial;
   a.list = ag.list;
+  a.gid = ag.gs.gid;
+  a.gself = ag.gs.gself;
   int64_t blocks = 0;
   size_t shm = 0;
   for (int k = 0; k < kFusedClasses; k++) {
@@ -2067,6 +2121,8 @@ struct MergeHubArgs {
   int32_t* hoff;
   int32_t* nflush;
   int cap;
+  const int32_t* gid;  // batches: graph of every label, and per-graph self super-arc weights
+  ull* gself;
 };
 
 constexpr int kMergeChunk = part_chunk(8);
@@ -2078,7 +2134,7 @@ constexpr int kMergePerThread = kMergeChunk / kPartBlock;
 // Returns the weight of the entry keyed `me` (this thread's share). flags[2..3]: shared ints.
 __device__ ull merge_emit_table(const int32_t* keys, const ull* vals, int H, int32_t me,
                                 int32_t* okey, uint64_t* ow, int64_t* dcount, bool shared_row,
-                                int* flags, int64_t* base_sh) {
+                                int* flags, int64_t* base_sh, ull* gself) {
   int mine = 0;
   for (int s = threadIdx.x; s < H; s += kPartBlock) mine += keys[s] != kEmpty;
   if (threadIdx.x == 0) {
@@ -2106,7 +2162,10 @@ __device__ ull merge_emit_table(const int32_t* keys, const ull* vals, int H, int
     const int64_t pos = base + atomicAdd(&flags[3], 1);
     okey[pos] = key;
     ow[pos] = vals[s];
-    if (key == me) self = vals[s];
+    if (key == me) {
+      self = vals[s];
+      if (gself) atomicAdd(gself, self);
+    }
   }
   return self;
 }
@@ -2186,7 +2245,8 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
     __syncthreads();
     const int32_t me = (int32_t)a.newid[c];
     const ull self = merge_emit_table(keys, vals, H, me, a.okey + acc.a0, a.ow + acc.a0,
-                                      a.dcount + me, false, flags, &base_sh);
+                                      a.dcount + me, false, flags, &base_sh,
+                                      a.gself ? a.gself + a.gid[c] : nullptr);
     const ull bs = part_block_sum(self, red);
     if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
     return;
@@ -2206,9 +2266,10 @@ struct MergeFin {
   int64_t* dcount;
   int* flags;
   int64_t* base_sh;
+  ull* gself;
   ull self;
   __device__ void operator()(const int32_t* keys, const ull* vals, int H) {
-    self += merge_emit_table(keys, vals, H, me, okey, ow, dcount, true, flags, base_sh);
+    self += merge_emit_table(keys, vals, H, me, okey, ow, dcount, true, flags, base_sh, gself);
   }
 };
 
@@ -2237,6 +2298,7 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT> a)
   fin.dcount = a.dcount + fin.me;
   fin.flags = flags;
   fin.base_sh = &base_sh;
+  fin.gself = a.gself ? a.gself + a.gid[c] : nullptr;
   fin.self = 0;
   part_reduce<ull, kMergeLog2H>(a.pk + c0 * kMergeChunk, a.pv + c0 * kMergeChunk,
                                 a.hoff + a.hoff_start[h], a.nflush + a.block_start[h], nck,
@@ -2275,6 +2337,8 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPl
   a.pv = ag.pv;
   a.hoff = ag.hoff;
   a.nflush = ag.nflush;
+  a.gid = ag.gs.gid;
+  a.gself = ag.gs.gself;
   a.cap = part_round_cap(kMergeLog2H, pp.shift);
   static bool attr = false;
   if (!attr) {
@@ -2358,6 +2422,111 @@ hipError_t compact_rows(const int64_t* offp, int64_t np, int64_t nnzp, const int
   const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
   LV_LAUNCH(k_compact_rows, grid, kBlock, 0, s, offp, np, nnzp, oldlabel, astart, tkey, tw,
             idx_out, w_out);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Batches of graphs packed with consecutive vertex ids: graph g owns vertices
+// [gbase[g], gbase[g+1]). Communities never span graphs, so the aggregation of the union keeps
+// every graph's super-vertices consecutive and in order.
+
+__global__ void k_graph_ids(const int64_t* gbase, int64_t G, int64_t n, int32_t* gid) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = G;  // gbase[lo] <= v < gbase[hi]
+    while (hi - lo > 1) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (gbase[mid] <= v) lo = mid; else hi = mid;
+    }
+    gid[v] = (int32_t)lo;
+  }
+}
+hipError_t graph_ids(const int64_t* gbase, int64_t G, int64_t n, int32_t* gid, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_graph_ids, grid_for(n), kBlock, 0, s, gbase, G, n, gid);
+  return hipGetLastError();
+}
+
+// Per-graph sums of x (out[g], 64-bit) or of x^2 (out[2g..2g+1], 128-bit) over the vertices.
+// Each thread covers kSeg consecutive vertices and flushes when the graph changes.
+template <bool SQ>
+__global__ void k_graph_sum(const uint64_t* x, int64_t n, const int32_t* gid, ull* out) {
+  const int64_t v0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * kSeg;
+  if (v0 >= n) return;
+  const int64_t v1 = v0 + kSeg < n ? v0 + kSeg : n;
+  int32_t g = gid[v0];
+  u128 acc = 0;
+  for (int64_t v = v0; v <= v1; v++) {
+    const int32_t gv = v < v1 ? gid[v] : -1;
+    if (gv != g) {
+      if (acc) {
+        if (SQ) atomic_add_u128(out + 2 * g, acc);
+        else atomicAdd(out + g, (ull)acc);
+      }
+      acc = 0;
+      g = gv;
+    }
+    if (v < v1) acc += SQ ? (u128)x[v] * x[v] : (u128)x[v];
+  }
+}
+hipError_t graph_sums(const uint64_t* x, int64_t n, const int32_t* gid, bool squares,
+                      unsigned long long* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t threads = (n + kSeg - 1) / kSeg;
+  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
+  if (squares) LV_LAUNCH(k_graph_sum<true>, grid, kBlock, 0, s, x, n, gid, out);
+  else LV_LAUNCH(k_graph_sum<false>, grid, kBlock, 0, s, x, n, gid, out);
+  return hipGetLastError();
+}
+
+// First super-vertex of every graph after an aggregation: the rank of its first label.
+__global__ void k_next_gbase(const int64_t* newid, const int64_t* gbase, int64_t G,
+                             int64_t* out) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g <= G;
+       g += (int64_t)gridDim.x * blockDim.x)
+    out[g] = newid[gbase[g]];
+}
+hipError_t next_gbase(const int64_t* newid, const int64_t* gbase, int64_t G, int64_t* out,
+                      hipStream_t s) {
+  LV_LAUNCH(k_next_gbase, grid_for(G + 1), kBlock, 0, s, newid, gbase, G, out);
+  return hipGetLastError();
+}
+
+// Membership as ids within each graph.
+__global__ void k_localize(int32_t* memb, int64_t n, const int32_t* gid0, const int64_t* gfinal) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    memb[v] -= (int32_t)gfinal[gid0[v]];
+}
+hipError_t localize_membership(int32_t* memb, int64_t n, const int32_t* gid0,
+                               const int64_t* gfinal, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_localize, grid_for(n), kBlock, 0, s, memb, n, gid0, gfinal);
+  return hipGetLastError();
+}
+
+// Batch layout checks: every graph's first arc is at aptr[g] and every arc stays in its graph.
+__global__ void k_validate_batch(const int64_t* off, int64_t n, int64_t nnz, const int32_t* idx,
+                                 const int32_t* gid, const int64_t* gbase, const int64_t* aptr,
+                                 int64_t G, unsigned int* bad) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t <= G && off[gbase[t]] != aptr[t]) atomicOr(bad, 1u);
+  const int64_t e0 = t * kSeg;
+  if (e0 >= nnz) return;
+  const int64_t e1 = e0 + kSeg < nnz ? e0 + kSeg : nnz;
+  int64_t r = row_of_arc(off, n, e0);
+  for (int64_t e = e0; e < e1; e++) {
+    if (e >= off[r + 1]) r = advance_row(off, n, r + 1, e);
+    const int32_t g = gid[r];
+    const int32_t j = idx[e];
+    if (j < gbase[g] || j >= gbase[g + 1]) atomicOr(bad, 2u);
+  }
+}
+hipError_t validate_batch(const DevGraph& g, const int32_t* gid, const int64_t* gbase,
+                          const int64_t* aptr, int64_t G, unsigned int* bad, hipStream_t s) {
+  const int64_t threads = std::max((g.nnz + kSeg - 1) / kSeg, G + 1);
+  LV_LAUNCH(k_validate_batch, grid_for(threads, kBlock, 1 << 30), kBlock, 0, s, g.off, g.n,
+            g.nnz, g.idx, gid, gbase, aptr, G, bad);
   return hipGetLastError();
 }
 

@@ -118,6 +118,20 @@ class LvMoveStats(ctypes.Structure):
     ]
 
 
+class LvGraphResult(ctypes.Structure):
+    _fields_ = [
+        ("passes", ctypes.c_int32),
+        ("iterations_total", ctypes.c_int32),
+        ("iterations", ctypes.c_int32 * LV_MAX_PASSES),
+        ("cap_hits", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
+        ("n_communities", ctypes.c_int64),
+        ("W", ctypes.c_uint64),
+        ("q_num", LvI128),
+        ("q", ctypes.c_double),
+    ]
+
+
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -136,6 +150,11 @@ SIGNATURES = {
     "louvain_modularity": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.POINTER(LvI128),
                                           ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_double), _P]),
+    "louvain_run_batched": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(LvParams), _P,
+                                           ctypes.POINTER(LvGraphResult), _P]),
 }
 
 _LIB = None
@@ -280,6 +299,34 @@ class Louvain:
                                   ctypes.byref(r), _stream())
         self._check(st)
         return membership[:g.n], result_dict(r)
+
+    def run_batched(self, packed, vptr, aptr, tolerance_exp10=2, decline_exp10=1,
+                    max_iterations=20, max_passes=10, substeps=DEFAULT_SUBSTEPS, flags=0,
+                    membership=None):
+        """Many graphs in one run. packed: one CSR of the graphs with consecutive vertex ids;
+        vptr, aptr: the G + 1 vertex and arc bounds (host sequences). Returns (membership int32
+        tensor [n] of ids local to each graph, list of per-graph result dicts)."""
+        gs = graph_struct(packed)
+        G = len(vptr) - 1
+        vp = (ctypes.c_int64 * (G + 1))(*[int(x) for x in vptr])
+        ap = (ctypes.c_int64 * (G + 1))(*[int(x) for x in aptr])
+        if membership is None:
+            membership = torch.empty(max(packed.n, 1), dtype=torch.int32,
+                                     device=packed.indices.device)
+        p = params_struct(tolerance_exp10, decline_exp10, max_iterations, max_passes, substeps,
+                          flags)
+        res = (LvGraphResult * G)()
+        st = self.lib.louvain_run_batched(self.h, ctypes.byref(gs), G, vp, ap, ctypes.byref(p),
+                                          _ptr(membership), res, _stream())
+        self._check(st)
+        out = []
+        for r in res:
+            P = r.passes
+            out.append({"passes": P, "iterations_total": r.iterations_total,
+                        "iterations": [r.iterations[i] for i in range(P)],
+                        "cap_hits": r.cap_hits, "n_communities": r.n_communities, "W": r.W,
+                        "qnum": r.q_num.value(), "q": r.q})
+        return membership[:packed.n], out
 
     def move(self, g, C, Sigma, csize, K=None, W=0, pass_index=0, tolerance_exp10=2,
              decline_exp10=1, max_iterations=20, substeps=DEFAULT_SUBSTEPS, flags=0) -> dict:

@@ -31,7 +31,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = header_functions()
-    assert len(names) == 8, names
+    assert len(names) == 9, names
     for name in names:
         assert hasattr(lib, name), name
 
@@ -70,6 +70,9 @@ int main(void) {
   F(lv_result, q) F(lv_result, total_ms) F(lv_result, aggregate_ms) F(lv_result, trace)
   S(lv_move_stats) F(lv_move_stats, moved) F(lv_move_stats, gain_sum)
   F(lv_move_stats, last_candidates)
+  S(lv_graph_result) F(lv_graph_result, iterations) F(lv_graph_result, cap_hits)
+  F(lv_graph_result, n_communities) F(lv_graph_result, W) F(lv_graph_result, q_num)
+  F(lv_graph_result, q)
   return 0;
 }
 """
@@ -85,7 +88,8 @@ def test_struct_layout_matches_header():
                                "-o", exe])
         out = subprocess.check_output([exe]).decode().split("\n")
     cmap = {"lv_graph": L.LvGraph, "lv_params": L.LvParams, "lv_iter_trace": L.LvIterTrace,
-            "lv_result": L.LvResult, "lv_move_stats": L.LvMoveStats}
+            "lv_result": L.LvResult, "lv_move_stats": L.LvMoveStats,
+            "lv_graph_result": L.LvGraphResult}
     checked = 0
     for line in out:
         if not line:
