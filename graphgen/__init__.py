@@ -23,5 +23,9 @@ from .generators import (  # noqa: F401
     erdos_renyi,
     add_self_loops,
     planted_hubs,
+    batch_sizes,
+    batch_graph,
+    batch_config,
+    serving_pool,
     config_graph,
 )

@@ -9,7 +9,7 @@ import math
 import torch
 
 from .csr import Csr, csr_from_arcs, csr_from_edges
-from .rng import below, draw, low32, srl, stream_key, top32
+from .rng import below, draw, low32, mix_int, srl, stream_key, top32
 
 # stream tags
 _T_RMAT = 1
@@ -20,6 +20,8 @@ _T_SBM_OUT = 5
 _T_LAT = 6
 _T_ER = 7
 _T_HUBS = 8
+_T_BATCH = 9
+_T_SERVE = 10
 
 
 def _pair_weights(key: int, n: int, wmin: int, wmax: int):
@@ -139,20 +141,22 @@ def sbm(n: int = 10000, blocks: int = 100, deg_in: float = 8.0, deg_out: float =
     key_in = stream_key(seed, _T_SBM_IN, n, blocks)
     key_out = stream_key(seed, _T_SBM_OUT, n, blocks)
     us, vs = [], []
-    for bidx in range(blocks):
-        lo = _block_start(n, blocks, bidx)
-        hi = _block_start(n, blocks, bidx + 1)
-        sz = hi - lo
+    starts = [_block_start(n, blocks, b) for b in range(blocks + 1)]
+    sizes = [starts[b + 1] - starts[b] for b in range(blocks)]
+    # intra-block pairs of all blocks of one size at once (block sizes take at most two values);
+    # each pair's draw is at its own counter, so the order of generation does not matter
+    for sz in sorted(set(sizes)):
         if sz < 2:
             continue
+        lo = torch.tensor([starts[b] for b in range(blocks) if sizes[b] == sz], dtype=torch.int64,
+                          device=device)
         iu, iv = torch.triu_indices(sz, sz, offset=1, device=device)
-        iu = iu.to(torch.int64) + lo
-        iv = iv.to(torch.int64) + lo
-        d = draw(key_in, iu * n + iv)
-        keep = srl(d, 11) < thr_in
-        us.append(iu[keep])
-        vs.append(iv[keep])
-    sizes = [_block_start(n, blocks, b + 1) - _block_start(n, blocks, b) for b in range(blocks)]
+        for part in torch.split(lo, max(1, (1 << 24) // iu.numel())):
+            bu = (part[:, None] + iu[None, :].to(torch.int64)).reshape(-1)
+            bv = (part[:, None] + iv[None, :].to(torch.int64)).reshape(-1)
+            keep = srl(draw(key_in, bu * n + bv), 11) < thr_in
+            us.append(bu[keep])
+            vs.append(bv[keep])
     inter_pairs = (n * n - sum(z * z for z in sizes)) // 2
     M = int(round(p_out * inter_pairs))
     if M > 0:
@@ -289,6 +293,54 @@ def add_self_loops(g: Csr, weight: int = 1) -> Csr:
                    torch.full((add.numel(),), weight, dtype=torch.int64, device=g.device)])
     return csr_from_arcs(g.n, src, dst, w, offsets_dtype=g.offsets.dtype,
                          weights_dtype=g.weights.dtype, name=g.name + "+loops")
+
+
+def batch_sizes(count: int = 2048, seed: int = 1, nmin: int = 200, nmax: int = 200001):
+    """Vertex counts of a batch: n_g = floor(exp(U(ln nmin, ln nmax))) with U from the 53 top
+    bits of draw g of the batch's stream."""
+    key = stream_key(seed, _T_BATCH, count)
+    u = srl(draw(key, torch.arange(count, dtype=torch.int64)), 11).tolist()
+    lo, hi = math.log(nmin), math.log(nmax)
+    return [int(math.floor(math.exp(lo + (x / float(1 << 53)) * (hi - lo)))) for x in u]
+
+
+def batch_graph(g: int, n: int, seed: int = 1, device="cpu") -> Csr:
+    """Graph g of a batch: even g an SBM with max(1, round(n/100)) near-equal blocks, expected
+    intra/inter degree 8/2; odd g an r x c lattice plus 10% shortcuts; weights 1..16; graph
+    seed = SplitMix64 finaliser of (seed xor g)."""
+    gseed = mix_int(seed ^ g)
+    if g % 2 == 0:
+        return sbm(n, max(1, round(n / 100)), 8.0, 2.0, seed=gseed, weights=(1, 16),
+                   device=device)
+    return lattice_shortcuts(n, 0.1, seed=gseed, weights=(1, 16), device=device)
+
+
+def batch_config(count: int = 2048, seed: int = 1, device="cpu"):
+    """The batched workload: ``count`` graphs (see batch_sizes and batch_graph)."""
+    return [batch_graph(g, n, seed, device) for g, n in enumerate(batch_sizes(count, seed))]
+
+
+def serving_pool(count: int = 32, seed: int = 1, nmin: int = 1000, nmax: int = 4000000,
+                 device="cpu"):
+    """Request graphs of the serving workload: n log-uniform in [nmin, nmax]; R-MAT (0.57,
+    0.19, 0.19, 0.05, edge factor 16, scale ceil(log2 n), endpoints >= n redrawn) or SBM
+    (round(n / 100) blocks, expected intra/inter degree 8/2) with probability 1/2 each; weights
+    1..16. Returns the graphs (a pool that requests draw from)."""
+    key = stream_key(seed, _T_SERVE, count)
+    d = draw(key, torch.arange(2 * count, dtype=torch.int64)).tolist()
+    lo, hi = math.log(nmin), math.log(nmax + 1)
+    out = []
+    for i in range(count):
+        u = ((d[2 * i] >> 11) & ((1 << 53) - 1)) / float(1 << 53)
+        n = int(math.floor(math.exp(lo + u * (hi - lo))))
+        gseed = mix_int(seed ^ (i + 0x5E5E))
+        if (d[2 * i + 1] >> 63) & 1:
+            sc = max(1, (n - 1).bit_length())
+            out.append(rmat(sc, 16, seed=gseed, weights=(1, 16), device=device, n=n))
+        else:
+            out.append(sbm(n, max(1, round(n / 100)), 8.0, 2.0, seed=gseed, weights=(1, 16),
+                           device=device))
+    return out
 
 
 def config_graph(name: str, device="cpu") -> Csr:
