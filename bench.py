@@ -315,6 +315,139 @@ def run_batched_bench(args, dev):
     print(json.dumps(line), flush=True)
 
 
+def run_serving_bench(args, dev):
+    """Serving: Poisson arrivals of requests drawn from a pool of pre-generated graphs held in
+    pinned host memory. The server admits whatever has arrived, copies those graphs to the GPU,
+    runs them as one louvain_run_batched call and copies the memberships back; latency is
+    arrival to membership on the host (queueing, H2D and D2H included)."""
+    from collections import deque
+
+    import numpy as np
+    import torch
+
+    from graphgen import serving_pool
+    from paper_2301_12390_amd import Louvain
+
+    t0 = time.perf_counter()
+    pool = serving_pool(args.pool, device=dev)
+    torch.cuda.synchronize()
+    host = []
+    for g in pool:
+        host.append((g.n, g.offsets.to(torch.int64).cpu().pin_memory(),
+                     g.indices.cpu().pin_memory(), g.weights.cpu().pin_memory()))
+    sizes = [h[0] for h in host]
+    arcs = [int(h[2].numel()) for h in host]
+    del pool
+    torch.cuda.empty_cache()
+    log(f"request pool: {len(host)} graphs, n {min(sizes)}..{max(sizes)}, mean arcs "
+        f"{sum(arcs) / len(arcs):.0f}, generated in {time.perf_counter() - t0:.1f}s")
+    cap_arcs = max(args.serve_batch_arcs, max(arcs))
+    cap_n = max(args.serve_batch_arcs // 8, max(sizes)) + 1
+    off_d = torch.empty(cap_n + 1, dtype=torch.int64, device=dev)
+    idx_d = torch.empty(cap_arcs, dtype=torch.int32, device=dev)
+    w_d = torch.empty(cap_arcs, dtype=torch.int32, device=dev)
+    lv = Louvain(0)
+
+    def serve(batch):
+        """H2D copy of the requests' graphs into one packed CSR, run, membership to host."""
+        from graphgen.csr import Csr
+        vptr, aptr = [0], [0]
+        for r in batch:
+            n, o, i, w = host[r]
+            v0, a0 = vptr[-1], aptr[-1]
+            m = int(i.numel())
+            off_d[v0:v0 + n].copy_(o[:-1], non_blocking=True)
+            off_d[v0:v0 + n] += a0
+            idx_d[a0:a0 + m].copy_(i, non_blocking=True)
+            idx_d[a0:a0 + m] += v0
+            w_d[a0:a0 + m].copy_(w, non_blocking=True)
+            vptr.append(v0 + n)
+            aptr.append(a0 + m)
+        off_d[vptr[-1]] = aptr[-1]
+        packed = Csr(vptr[-1], off_d[:vptr[-1] + 1], idx_d[:aptr[-1]], w_d[:aptr[-1]])
+        memb, res = lv.run_batched(packed, vptr, aptr, substeps=args.substeps)
+        return memb.cpu(), res
+
+    serve([0])  # warm-up
+    per_rate = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        rng = np.random.default_rng(1000 + int(rate))
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 2) + 16))
+        arr = arr[arr <= args.serve_seconds]
+        which = rng.integers(0, len(host), size=arr.size)
+        queue = deque()
+        lat = []
+        batches = 0
+        nxt = 0
+        start = time.perf_counter()
+        stop = args.serve_seconds * 2  # admission ends at serve_seconds; the queue drains until
+        while True:
+            now = time.perf_counter() - start
+            while nxt < arr.size and arr[nxt] <= now:
+                queue.append(nxt)
+                nxt += 1
+            if not queue:
+                if nxt >= arr.size:
+                    break
+                time.sleep(max(0.0, arr[nxt] - now))
+                continue
+            if now > stop:
+                break
+            batch, tot, totn = [], 0, 0
+            while queue and (not batch or (tot + arcs[which[queue[0]]] <= args.serve_batch_arcs
+                                           and totn + sizes[which[queue[0]]] < cap_n)):
+                r = queue.popleft()
+                batch.append(r)
+                tot += arcs[which[r]]
+                totn += sizes[which[r]]
+            serve([int(which[r]) for r in batch])
+            done = time.perf_counter() - start
+            lat.extend(done - arr[r] for r in batch)
+            batches += 1
+        el = time.perf_counter() - start
+        lat_ms = np.array(lat) * 1000.0
+        rec = {
+            "rate": rate, "offered": int(arr.size), "completed": len(lat),
+            "unfinished": int(arr.size - len(lat)),
+            "completed_per_s": len(lat) / el,
+            "p50_ms": float(np.percentile(lat_ms, 50)) if lat else None,
+            "p99_ms": float(np.percentile(lat_ms, 99)) if lat else None,
+            "batches": batches, "mean_batch": len(lat) / max(batches, 1),
+            "seconds": el,
+        }
+        per_rate.append(rec)
+        log(f"rate {rate:g}/s: {rec['completed']} of {rec['offered']} done, "
+            f"{rec['completed_per_s']:.1f}/s, p50 {rec['p50_ms']:.1f} ms, "
+            f"p99 {rec['p99_ms']:.1f} ms, {batches} batches")
+    lv.close()
+    first = per_rate[0]
+    line = {
+        "metric": METRIC,
+        "value": first["p99_ms"],
+        "unit": "ms (p99 latency at the first rate)",
+        "n_gpus": 1,
+        "steps": len(per_rate),
+        "warmup": 1,
+        "ms_per_step": first["p50_ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i64",
+        "data": "synthetic",
+        "config": {
+            "workload": "serving",
+            "pool_graphs": len(host),
+            "pool_mean_arcs": sum(arcs) / len(arcs),
+            "serve_seconds": args.serve_seconds,
+            "batch_arc_budget": args.serve_batch_arcs,
+            "substeps": args.substeps,
+            "rates": per_rate,
+        },
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,9 +455,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch-count", type=int, default=2048,
                     help="graphs of the batched workload")
+    ap.add_argument("--rates", default="50,200,800",
+                    help="serving: request rates (per second), comma separated")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="serving: seconds of arrivals per rate (the queue then drains)")
+    ap.add_argument("--pool", type=int, default=32, help="serving: distinct request graphs")
+    ap.add_argument("--serve-batch-arcs", type=int, default=1 << 28,
+                    help="serving: most arcs the server runs in one batch")
     ap.add_argument("--workload", default="rmat25",
-                    help="rmat25 (default), rmat22, sbm10k, rmatNN, or batched (the batch of "
-                         "--batch-count SBM and lattice graphs, graphs/s)")
+                    help="rmat25 (default), rmat22, sbm10k, rmatNN, batched (the batch of "
+                         "--batch-count SBM and lattice graphs, graphs/s) or serving (Poisson "
+                         "requests at --rates, p50/p99 latency)")
     ap.add_argument("--substeps", type=int, default=8,
                     help="vertex classes per local-moving iteration (1 = fully synchronous)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -369,6 +510,9 @@ def main():
     log(f"device {torch.cuda.get_device_name(0)}")
     if args.workload == "batched":
         run_batched_bench(args, dev)
+        return
+    if args.workload == "serving":
+        run_serving_bench(args, dev)
         return
     t0 = time.perf_counter()
     if args.graph_cache and os.path.exists(args.graph_cache):
