@@ -30,9 +30,8 @@ __host__ __device__ constexpr int bucket_log2h(int k) {
 }
 __host__ __device__ constexpr int bucket_rows_per_block(int k) { return kBlock / bucket_group(k); }
 
-// The move kernel decides rows of up to 8 arcs (degree classes 0 and 1) with one thread per row,
-// combining repeated communities in registers; the other classes use the group widths above.
-__host__ __device__ constexpr int move_group_size(int k) { return k < 2 ? 1 : bucket_group(k); }
+// Lanes per row of the move kernel in degree class k.
+__host__ __device__ constexpr int move_group_size(int k) { return bucket_group(k); }
 __host__ __device__ constexpr int move_rows_per_block(int k) { return kBlock / move_group_size(k); }
 
 // Degree classes 7, 8, 9 (rows of up to 2048, 4096, 8192 arcs) are decided by one 1024-thread

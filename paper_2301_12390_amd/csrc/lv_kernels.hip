@@ -859,118 +859,6 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
   }
 }
 
-// Rows of at most MAXD arcs: one thread per vertex. The communities of the neighbours and their
-// weights stay in registers; repeats are combined into the first occurrence. When a candidate
-// community is labelled by the neighbour that shows it (C[j] = j), its Sigma and size come with
-// that neighbour's record and need no further load.
-template <bool WIDE, typename WT, int MAXD>
-__device__ __forceinline__ void move_regs(const MoveArgs<WT>& a, int64_t lb, int64_t lbase,
-                                          int64_t lcount, BlockShared& sh) {
-  typedef Gain<WIDE> Ar;
-  typedef typename Ar::T T;
-  const int64_t li = lb * kBlock + threadIdx.x;
-  u128 gain = 0;
-  ull moved = 0, nc = 0;
-  uint64_t W = a.W;
-  int32_t gr = 0;
-  if (li < lcount) {
-    const int32_t v = a.list[lbase + li];
-    const int64_t e0 = a.rs[v];
-    const int L = gs_vertex(a.gs, v, &W, &gr) ? (int)(a.re[v] - e0) : 0;
-    const VRec rv = a.rec[v];
-    const uint64_t Ki = a.K[v];
-    int32_t key[MAXD];
-    ull kw[MAXD], sg[MAXD];
-    int32_t sz[MAXD];
-    bool known[MAXD];
-#pragma unroll
-    for (int i = 0; i < MAXD; i++) {
-      key[i] = kEmpty;
-      kw[i] = 0;
-      sg[i] = 0;
-      sz[i] = 0;
-      known[i] = false;
-      if (i < L) {
-        const int32_t j = ld_stream(a.idx + e0 + i);
-        const ull wv = (ull)ld_stream(a.w + e0 + i);
-        if (j != v) {
-          const VRec rj = a.rec[j];
-          key[i] = rj.c;
-          kw[i] = wv;
-          if (rj.c == j) {
-            known[i] = true;
-            sg[i] = rj.sig;
-            sz[i] = rj.size;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 1; i < MAXD; i++) {
-#pragma unroll
-      for (int p = 0; p < i; p++) {
-        if (key[i] != kEmpty && key[p] == key[i]) {
-          kw[p] += kw[i];
-          if (known[i] && !known[p]) {
-            known[p] = true;
-            sg[p] = sg[i];
-            sz[p] = sz[i];
-          }
-          key[i] = kEmpty;
-        }
-      }
-    }
-    const int32_t d = rv.c;
-    ull kd = 0;
-    T bg = Ar::lowest();
-    int32_t bc = INT32_MAX;
-    bool bknown = false;
-    int32_t bsize = 0;
-#pragma unroll
-    for (int i = 0; i < MAXD; i++) {
-      if (key[i] == kEmpty) continue;
-      if (key[i] == d) {
-        kd = kw[i];
-        continue;
-      }
-      nc++;
-      const ull sc = known[i] ? sg[i] : a.rec[key[i]].sig;
-      const T g = Ar::of(W, kw[i], Ki, sc);
-      if (better(g, key[i], bg, bc)) {
-        bg = g;
-        bc = key[i];
-        bknown = known[i];
-        bsize = sz[i];
-      }
-    }
-    int32_t target = d;
-    if (bc != INT32_MAX) {
-      const VRec rd = d == v ? rv : a.rec[d];
-      const T stay = Ar::of(W, kd, Ki, rd.sig - Ki);
-      if (bg > stay) {
-        const int32_t bs = bknown ? bsize : a.rec[bc].size;
-        if (!(rd.size == 1 && bs == 1 && bc > d)) {
-          target = bc;
-          moved = 1;
-          gain = Ar::diff(bg, stay);
-          gs_add_gain(a.gs, gr, gain);
-        }
-      }
-    }
-    a.tgt[v] = target;
-  }
-  const u128 bsum = block_sum_u128(gain, sh.red128);
-  const ull bm = block_sum_u64(moved, sh.red64);
-  const ull bn = block_sum_u64(nc, sh.red64);
-  if (threadIdx.x == 0) {
-    ull* o = a.partial + 4 * (int64_t)blockIdx.x;
-    o[0] = (ull)bsum;
-    o[1] = (ull)(bsum >> 64);
-    o[2] = bm;
-    o[3] = bn;
-  }
-}
-
 template <bool WIDE, typename WT>
 __global__ __launch_bounds__(kBlock) void k_move_lds(MoveArgs<WT> a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -981,8 +869,8 @@ __global__ __launch_bounds__(kBlock) void k_move_lds(MoveArgs<WT> a) {
   const int64_t lb = b - a.bstart[k];
   const int64_t lbase = a.lstart[k], lcount = a.lstart[k + 1] - a.lstart[k];
   switch (k) {
-    case 0: move_regs<WIDE, WT, 4>(a, lb, lbase, lcount, sh); break;
-    case 1: move_regs<WIDE, WT, 8>(a, lb, lbase, lcount, sh); break;
+    case 0: move_group<WIDE, WT, bucket_group(0), bucket_log2h(0)>(a, lb, lbase, lcount, smem, sh); break;
+    case 1: move_group<WIDE, WT, bucket_group(1), bucket_log2h(1)>(a, lb, lbase, lcount, smem, sh); break;
     case 2: move_group<WIDE, WT, bucket_group(2), bucket_log2h(2)>(a, lb, lbase, lcount, smem, sh); break;
     case 3: move_group<WIDE, WT, bucket_group(3), bucket_log2h(3)>(a, lb, lbase, lcount, smem, sh); break;
     case 4: move_group<WIDE, WT, bucket_group(4), bucket_log2h(4)>(a, lb, lbase, lcount, smem, sh); break;
@@ -1157,6 +1045,19 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
   }
 }
 
+// Degree class 7 (rows of 1025..2048 arcs): one 256-thread group per row with a table of
+// 2^kGrp7Log2H slots, in a launch of its own (in the fused launch its table would raise the LDS
+// of every block).
+constexpr int kGrp7Log2H = 12;
+
+template <bool WIDE, typename WT>
+__global__ __launch_bounds__(kBlock) void k_move_grp7(MoveArgs<WT> a, int64_t lbase,
+                                                     int64_t lcount) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ BlockShared sh;
+  move_group<WIDE, WT, kBlock, kGrp7Log2H>(a, blockIdx.x, lbase, lcount, smem, sh);
+}
+
 static size_t wg_table_bytes(int k, size_t vbytes) { return ((size_t)1 << wg_log2h(k)) * (4 + vbytes); }
 
 int hub_first_class(size_t max_lds, bool wide) {
@@ -1191,13 +1092,11 @@ static int64_t fused_blocks(const Buckets& b, int cls) {
 }
 
 static size_t lds_table_bytes(int k, size_t vbytes) {
-  if (move_group_size(k) == 1) return 0;  // register path
   return (size_t)move_rows_per_block(k) * ((size_t)1 << bucket_log2h(k)) * (4 + vbytes);
 }
 
-template <bool WIDE, typename WT>
-static hipError_t move_fused_t(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
-                               hipStream_t s) {
+template <typename WT>
+static MoveArgs<WT> move_args(const DevGraph& g, const MoveBuffers& m) {
   MoveArgs<WT> a;
   a.rs = g.rs;
   a.re = g.re;
@@ -1210,6 +1109,13 @@ static hipError_t move_fused_t(const DevGraph& g, const Buckets& b, int cls, con
   a.tgt = m.tgt;
   a.partial = m.block_partial;
   a.gs = m.gs;
+  return a;
+}
+
+template <bool WIDE, typename WT>
+static hipError_t move_fused_t(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
+                               hipStream_t s) {
+  MoveArgs<WT> a = move_args<WT>(g, m);
   int64_t blocks = 0;
   size_t shm = 0;
   const int base = kDegClasses * cls;
@@ -1251,8 +1157,14 @@ static hipError_t move_wg_t(const DevGraph& g, const Buckets& b, int cls, const 
     wa.rows = m.list + b.lstart[base + k];
     wa.partial = m.block_partial + 4 * records;
     hipError_t e = hipSuccess;
-    if (k == 7) e = launch_wg<WIDE, WT, wg_log2h(7)>(wa, rows, s);
-    else if (k == 8) e = launch_wg<WIDE, WT, wg_log2h(8)>(wa, rows, s);
+    if (k == 7) {
+      MoveArgs<WT> a = move_args<WT>(g, m);
+      a.partial = wa.partial;
+      const size_t shm = ((size_t)1 << kGrp7Log2H) * (4 + sizeof(typename Gain<WIDE>::V));
+      LV_LAUNCH((k_move_grp7<WIDE, WT>), (unsigned)rows, kBlock, shm, s, a, b.lstart[base + k],
+                rows);
+      e = hipGetLastError();
+    } else if (k == 8) e = launch_wg<WIDE, WT, wg_log2h(8)>(wa, rows, s);
     else e = launch_wg<WIDE, WT, wg_log2h(9)>(wa, rows, s);
     if (e != hipSuccess) return e;
     records += rows;
