@@ -82,8 +82,9 @@ typedef struct {
 
 #define LV_VALIDATE 0x1u   /* check indices, weights and offsets on the device (O(nnz)) */
 #define LV_TRACE 0x2u      /* time the kernels of every iteration with HIP events */
-#define LV_FORCE_WIDE 0x4u /* use 128-bit gains and 64-bit table values even when 64-bit
-                              gains are exact (results are identical; for testing) */
+#define LV_FORCE_WIDE 0x4u /* use 128-bit gains, 64-bit table values and 64-bit super-arc
+                              weights even where narrower ones are exact (results are
+                              identical; for testing) */
 #define LV_SMALL_PARTS 0x8u /* split long rows and large communities into many hash
                                partitions with tiny workgroup tables, so that the partitioned
                                and multi-round code paths run on small graphs (results are

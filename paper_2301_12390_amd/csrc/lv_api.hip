@@ -480,10 +480,12 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
 // Aggregation of graph g under labels C (csize by label; Sig by label or NULL). Merged rows go
 // to okey/ow (g.nnz entries) at their community's flat position. Outputs: map[n], Kp[n'] (if
 // Sig), the buffers describing the rows (*out), n', nnz' and the weight of the self super-arcs.
+// With allow_w32 and Sig, the super-arc weights are written as uint32 when every Sigma is below
+// 2^32 (out->w32 tells which).
 lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const int32_t* csize,
                     const uint64_t* Sig, int32_t* map, int32_t* okey, uint64_t* ow, uint64_t* Kp,
                     lv::AggBuffers* out, int64_t* n_out, int64_t* nnz_out, uint64_t* self_out,
-                    hipStream_t s) {
+                    hipStream_t s, bool allow_w32 = false) {
   const int64_t n = g.n;
   lv::AggBuffers a;
   a.gs = out->gs;  // batches: graph of every label and per-graph self super-arc weights
@@ -512,9 +514,17 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
                          ctx->pinned + PIN_COUNTS, b, s));
   // the super-vertex count bounds the distinct targets of any community
   ull* hm = ctx->pinned + PIN_MISC;
+  ull* sm = st + ST_MISC + 12;  // sum and max of Sigma
+  const bool check32 = allow_w32 && Sig;
+  if (check32) {
+    HIPCHK(lv::zero_words(sm, 2, s));
+    HIPCHK(lv::sum_max_u64(Sig, n, sm, s));
+    HIPCHK(hipMemcpyAsync(hm + 1, sm, 2 * sizeof(ull), hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(hipMemcpyAsync(hm, a.newid + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const int64_t np = (int64_t)hm[0];
+  a.w32 = check32 && hm[2] < ((ull)1 << 32);
   HIPCHK(lv::fill_i64(a.dcount, 0, np + 1, s));
   CHK(wst(ctx, S_MPART, lv::merge_lds_blocks(b), &a.block_partial));
   HIPCHK(lv::merge_lds(g, b, a, s));
@@ -858,7 +868,8 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
     uint64_t self = 0;
     lv::AggBuffers ab;
     HIPCHK(lv::unpack_state(cur.n, rec, C, Sig, csize, s));
-    CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s));
+    CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s,
+                  (p->flags & LV_FORCE_WIDE) == 0));
     HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
     HIPCHK(lv::compose_membership(membership, n0, map, s));
     if (trace) {
@@ -890,7 +901,7 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
     nxt.off = nullptr;
     nxt.idx = nidx;
     nxt.w = nw;
-    nxt.w64 = true;
+    nxt.w64 = !ab.w32;
     cur = nxt;
     n_comm = np;
     which ^= 1;
@@ -1078,7 +1089,8 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     ab.gs.gself = gself;
     HIPCHK(lv::zero_words(gself, G, s));
     HIPCHK(lv::unpack_state(cur.n, rec, C, Sig, csize, s));
-    CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s));
+    CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s,
+                  (p->flags & LV_FORCE_WIDE) == 0));
     HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
     HIPCHK(lv::compose_membership(membership, n0, map, s));
     HIPCHK(lv::next_gbase(ab.newid, gb_cur, G, gb_next, s));
@@ -1117,7 +1129,7 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     nxt.off = nullptr;
     nxt.idx = nidx;
     nxt.w = nw;
-    nxt.w64 = true;
+    nxt.w64 = !ab.w32;
     cur = nxt;
     gid = ngid;
     gb_cur = gb_next;

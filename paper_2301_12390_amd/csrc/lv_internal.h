@@ -171,7 +171,8 @@ struct AggBuffers {
   int32_t* map = nullptr;      // [n] new id of each vertex
   // output rows (at astart[c] for community c) and scratch
   int32_t* okey = nullptr;     // [nnz]
-  uint64_t* ow = nullptr;      // [nnz]
+  uint64_t* ow = nullptr;      // [nnz] (read as uint32 [nnz] when w32)
+  bool w32 = false;            // super-arc weights written as uint32
   int32_t* list = nullptr;     // [n]
   int64_t* partial = nullptr;  // scan scratch
   unsigned long long* counts = nullptr;  // 1536 words

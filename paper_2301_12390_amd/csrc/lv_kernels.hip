@@ -1824,6 +1824,23 @@ __device__ __forceinline__ int member_at(const T* start, int mc, int64_t t) {
   return lo;
 }
 
+// Super-arc weights: 32-bit when every community's Sigma (which bounds the weight of each of
+// its super-arcs) is below 2^32, else 64-bit.
+struct WOut {
+  uint64_t* w64;
+  uint32_t* w32;
+  __device__ __forceinline__ void put(int64_t i, ull v) const {
+    if (w32) w32[i] = (uint32_t)v;
+    else w64[i] = v;
+  }
+  __device__ __forceinline__ WOut at(int64_t off) const {
+    WOut o;
+    o.w64 = w32 ? nullptr : w64 + off;
+    o.w32 = w32 ? w32 + off : nullptr;
+    return o;
+  }
+};
+
 template <typename WT>
 struct MergeArgs {
   const int64_t* rs;
@@ -1837,7 +1854,7 @@ struct MergeArgs {
   const int64_t* A;
   const int64_t* newid;
   int32_t* okey;     // output arrays: row of community c at astart[c]
-  uint64_t* ow;
+  WOut ow;
   int64_t* dcount;   // distinct targets per new id
   ull* partial;      // per block: weight of its self super-arcs
   const int32_t* list;
@@ -1898,7 +1915,7 @@ __device__ __forceinline__ void merge_group(const MergeArgs<WT>& a, int64_t lb, 
       if (key == kEmpty) continue;
       const int p = atomicAdd(&gcount[gid], 1);
       a.okey[a0 + p] = key;
-      a.ow[a0 + p] = gv[s];
+      a.ow.put(a0 + p, gv[s]);
       if (key == me) {
         self = gv[s];
         if (a.gself) atomicAdd(&a.gself[a.gid[c]], self);
@@ -1972,7 +1989,8 @@ static hipError_t merge_lds_t(const DevGraph& g, const Buckets& b, const AggBuff
   a.A = ag.A;
   a.newid = ag.newid;
   a.okey = ag.okey;
-  a.ow = ag.ow;
+  a.ow.w64 = ag.ow;
+  a.ow.w32 = ag.w32 ? (uint32_t*)ag.ow : nullptr;
   a.dcount = ag.dcount;
   a.partial = ag.block_partial;
   a.list = ag.list;
@@ -2017,7 +2035,7 @@ struct MergeHubArgs {
   const int64_t* A;
   const int64_t* newid;
   int32_t* okey;
-  uint64_t* ow;
+  WOut ow;
   int64_t* dcount;   // distinct targets per new id (zero before the merge)
   ull* stats;        // [0] weight of self super-arcs
   const int32_t* hubs;
@@ -2045,7 +2063,7 @@ constexpr int kMergePerThread = kMergeChunk / kPartBlock;
 // position), base = atomicAdd(dcount, entries) when `shared_row`, else 0 with *dcount = entries.
 // Returns the weight of the entry keyed `me` (this thread's share). flags[2..3]: shared ints.
 __device__ ull merge_emit_table(const int32_t* keys, const ull* vals, int H, int32_t me,
-                                int32_t* okey, uint64_t* ow, int64_t* dcount, bool shared_row,
+                                int32_t* okey, WOut ow, int64_t* dcount, bool shared_row,
                                 int* flags, int64_t* base_sh, ull* gself) {
   int mine = 0;
   for (int s = threadIdx.x; s < H; s += kPartBlock) mine += keys[s] != kEmpty;
@@ -2073,7 +2091,7 @@ __device__ ull merge_emit_table(const int32_t* keys, const ull* vals, int H, int
     if (key == kEmpty) continue;
     const int64_t pos = base + atomicAdd(&flags[3], 1);
     okey[pos] = key;
-    ow[pos] = vals[s];
+    ow.put(pos, vals[s]);
     if (key == me) {
       self = vals[s];
       if (gself) atomicAdd(gself, self);
@@ -2156,7 +2174,7 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
     acc(0, keys, vals, flags);
     __syncthreads();
     const int32_t me = (int32_t)a.newid[c];
-    const ull self = merge_emit_table(keys, vals, H, me, a.okey + acc.a0, a.ow + acc.a0,
+    const ull self = merge_emit_table(keys, vals, H, me, a.okey + acc.a0, a.ow.at(acc.a0),
                                       a.dcount + me, false, flags, &base_sh,
                                       a.gself ? a.gself + a.gid[c] : nullptr);
     const ull bs = part_block_sum(self, red);
@@ -2174,7 +2192,7 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
 struct MergeFin {
   int32_t me;
   int32_t* okey;
-  uint64_t* ow;
+  WOut ow;
   int64_t* dcount;
   int* flags;
   int64_t* base_sh;
@@ -2206,7 +2224,7 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT> a)
   MergeFin fin;
   fin.me = (int32_t)a.newid[c];
   fin.okey = a.okey + a0;
-  fin.ow = a.ow + a0;
+  fin.ow = a.ow.at(a0);
   fin.dcount = a.dcount + fin.me;
   fin.flags = flags;
   fin.base_sh = &base_sh;
@@ -2234,7 +2252,8 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPl
   a.A = ag.A;
   a.newid = ag.newid;
   a.okey = ag.okey;
-  a.ow = ag.ow;
+  a.ow.w64 = ag.ow;
+  a.ow.w32 = ag.w32 ? (uint32_t*)ag.ow : nullptr;
   a.dcount = ag.dcount;
   a.stats = ag.stats;
   a.hubs = ag.list + b.lstart[kFusedClasses];
