@@ -47,7 +47,7 @@ constexpr int PIN_MISC = 1808;    // host: other read-backs
 constexpr int PIN_WORDS = 2048;
 constexpr int DEG = 12;           // degree classes per vertex class (list segment stride)
 constexpr int STATS_WORDS = 512;
-constexpr int kEvStep = 5;  // events per class step
+constexpr int kEvStep = 8;  // timing events per class step
 constexpr int kEvents = kEvStep * 32 + 2;
 constexpr int EV_AGG = kEvStep * 32;
 
@@ -63,6 +63,10 @@ struct lv_ctx {
   size_t bpin_bytes = 0;
   ull* pinned = nullptr;  // host-pinned words for small read-backs
   hipEvent_t ev[kEvents] = {};  // kEvStep per class step, then 2 for aggregation
+  // the move tiers of a class step run concurrently: the workgroup tier on side[0], the hub
+  // path on side[1], forked from and joined back into the caller's stream
+  hipStream_t side[2] = {};
+  hipEvent_t fork[32] = {}, join0[32] = {}, join1[32] = {};
 };
 
 namespace {
@@ -370,15 +374,28 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
       lv::MoveBuffers m = ph.m;
       m.stats = stats0 + 8 * k;
       hipEvent_t* ev = ctx->ev + kEvStep * k;
+      hipStream_t s1 = ctx->side[0], s2 = ctx->side[1];
+      // the three tiers decide disjoint vertices from the same state: run them concurrently
+      HIPCHK(hipEventRecord(ctx->fork[k], s));
+      HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
+      HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
       if (trace) HIPCHK(hipEventRecord(ev[0], s));
       HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
       if (trace) HIPCHK(hipEventRecord(ev[1], s));
-      HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s));
-      if (trace) HIPCHK(hipEventRecord(ev[2], s));
-      HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s));
-      if (trace) HIPCHK(hipEventRecord(ev[3], s));
+      if (trace) HIPCHK(hipEventRecord(ev[2], s1));
+      HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
+      if (trace) HIPCHK(hipEventRecord(ev[3], s1));
+      if (trace) HIPCHK(hipEventRecord(ev[4], s2));
+      HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s2));
+      if (trace) HIPCHK(hipEventRecord(ev[5], s2));
+      HIPCHK(hipEventRecord(ctx->join0[k], s1));
+      HIPCHK(hipEventRecord(ctx->join1[k], s2));
+      HIPCHK(hipStreamWaitEvent(s, ctx->join0[k], 0));
+      HIPCHK(hipStreamWaitEvent(s, ctx->join1[k], 0));
+      if (trace) HIPCHK(hipEventRecord(ev[6], s));
+      HIPCHK(lv::reduce_move_partials(ph.b, k, m, s));
       HIPCHK(lv::apply_moves(ph.b, k, m, s));
-      if (trace) HIPCHK(hipEventRecord(ev[4], s));
+      if (trace) HIPCHK(hipEventRecord(ev[7], s));
     }
     ull* h = ctx->pinned + PIN_STATS;
     HIPCHK(hipMemcpyAsync(h, stats0, 8 * K * sizeof(ull), hipMemcpyDeviceToHost, s));
@@ -393,11 +410,11 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
         float x = 0;
         HIPCHK(hipEventElapsedTime(&x, ev[0], ev[1]));
         t_fused += x;
-        HIPCHK(hipEventElapsedTime(&x, ev[1], ev[2]));
-        t_wg += x;
         HIPCHK(hipEventElapsedTime(&x, ev[2], ev[3]));
+        t_wg += x;
+        HIPCHK(hipEventElapsedTime(&x, ev[4], ev[5]));
         t_hub += x;
-        HIPCHK(hipEventElapsedTime(&x, ev[3], ev[4]));
+        HIPCHK(hipEventElapsedTime(&x, ev[6], ev[7]));
         t_upd += x;
       }
     }
@@ -621,6 +638,20 @@ lv_status louvain_ctx_create(int device, uint64_t hbm_budget_bytes, lv_ctx** out
       return LV_EHIP;
     }
   }
+  for (int i = 0; i < 2; i++) {
+    if (hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking) != hipSuccess) {
+      louvain_ctx_destroy(ctx);
+      return LV_EHIP;
+    }
+  }
+  for (int i = 0; i < 32; i++) {
+    if (hipEventCreateWithFlags(&ctx->fork[i], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join0[i], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join1[i], hipEventDisableTiming) != hipSuccess) {
+      louvain_ctx_destroy(ctx);
+      return LV_EHIP;
+    }
+  }
   *out = ctx;
   return LV_OK;
 }
@@ -632,6 +663,13 @@ void louvain_ctx_destroy(lv_ctx* ctx) {
     if (ctx->slots[i].p) (void)hipFree(ctx->slots[i].p);
   for (int i = 0; i < kEvents; i++)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  for (int i = 0; i < 32; i++) {
+    if (ctx->fork[i]) (void)hipEventDestroy(ctx->fork[i]);
+    if (ctx->join0[i]) (void)hipEventDestroy(ctx->join0[i]);
+    if (ctx->join1[i]) (void)hipEventDestroy(ctx->join1[i]);
+  }
+  for (int i = 0; i < 2; i++)
+    if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->bpin) (void)hipHostFree(ctx->bpin);
   delete ctx;

@@ -136,10 +136,12 @@ hipError_t zero_words(unsigned long long* a, int64_t n, hipStream_t s);
 // Fused LDS-table move kernel (degree classes 0..6) over the rows of vertex class `cls`.
 hipError_t move_fused(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m,
                       bool wide, hipStream_t s);
-// Workgroup-per-row kernel (classes 7 .. hub_first-1) of class `cls`, then the reduction of the
-// block records of both kernels into m.stats.
+// Kernels of degree classes 7 .. hub_first-1 of class `cls` (a 256-thread group per row for
+// class 7, a 1024-thread workgroup per row above).
 hipError_t move_wg(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m, bool wide,
                    hipStream_t s);
+// Reduction of the block records of move_fused and move_wg into m.stats (after both).
+hipError_t reduce_move_partials(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s);
 // Hub kernels over the hub rows of vertex class `cls` (plan hp made for those rows).
 hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const PartPlan& pp,
                      const MoveBuffers& m, bool wide, hipStream_t s);

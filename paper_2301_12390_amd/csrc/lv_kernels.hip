@@ -1169,6 +1169,12 @@ static hipError_t move_wg_t(const DevGraph& g, const Buckets& b, int cls, const 
     if (e != hipSuccess) return e;
     records += rows;
   }
+  return hipSuccess;
+}
+
+hipError_t reduce_move_partials(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s) {
+  const int64_t fused = fused_blocks(b, cls);
+  const int64_t records = move_lds_blocks(b, cls, m.hub_first);
   if (records == 0) return hipSuccess;
   LV_LAUNCH(k_reduce_move_partials, grid_for(records, kBlock, 256), kBlock, 0, s,
             m.block_partial, records, fused, m.stats);
