@@ -249,17 +249,19 @@ def run_batched_bench(args, dev):
     gps = G / (ms_per_step / 1000.0)
     log(f"batched: {ms_per_step:.1f} ms per batch, {gps:.1f} graphs/s")
     # one by one, over the same graphs already in HBM
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    q_single = []
-    for g in graphs:
-        _, r = lv.run(g, substeps=args.substeps)
-        q_single.append(r["qnum"])
-    torch.cuda.synchronize()
-    obo = time.perf_counter() - t2
-    obo_gps = G / obo
-    same = all(a == b["qnum"] for a, b in zip(q_single, res))
-    log(f"one by one: {obo * 1000:.1f} ms, {obo_gps:.1f} graphs/s; identical Qnum: {same}")
+    obo_gps, same = None, None
+    if not args.no_one_by_one:
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        q_single = []
+        for g in graphs:
+            _, r = lv.run(g, substeps=args.substeps)
+            q_single.append(r["qnum"])
+        torch.cuda.synchronize()
+        obo = time.perf_counter() - t2
+        obo_gps = G / obo
+        same = all(a == b["qnum"] for a, b in zip(q_single, res))
+        log(f"one by one: {obo * 1000:.1f} ms, {obo_gps:.1f} graphs/s; identical Qnum: {same}")
     qs = [r["q"] for r in res]
     line = {
         "metric": METRIC,
@@ -282,7 +284,7 @@ def run_batched_bench(args, dev):
             "substeps": args.substeps,
             "teps": packed.nnz / (ms_per_step / 1000.0),
             "one_by_one_graphs_per_s": obo_gps,
-            "speedup_vs_one_by_one": gps / obo_gps,
+            "speedup_vs_one_by_one": gps / obo_gps if obo_gps else None,
             "identical_to_one_by_one": same,
             "mean_q": sum(qs) / len(qs),
         },
@@ -455,6 +457,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch-count", type=int, default=2048,
                     help="graphs of the batched workload")
+    ap.add_argument("--no-one-by-one", action="store_true",
+                    help="batched: skip the graph-by-graph comparison run")
     ap.add_argument("--rates", default="50,200,800",
                     help="serving: request rates (per second), comma separated")
     ap.add_argument("--serve-seconds", type=float, default=20.0,

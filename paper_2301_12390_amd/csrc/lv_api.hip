@@ -266,7 +266,7 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   CHK(wst(ctx, S_COUNTS, 1536, &counts));
   CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &scanp));
   HIPCHK(lv::bucket_rows(ph.g.rs, ph.g.re, nullptr, n, K, ph.pass, ph.m.gs.gid, ph.m.gs.gbase,
-                         list, counts,
+                         ph.m.gs.act, list, counts,
                          ctx->pinned + PIN_COUNTS, ph.b, s));
   const int hf = lv::hub_first_class(ctx->max_lds, ph.wide);
   ph.m.hub_first = hf;
@@ -322,6 +322,8 @@ struct BatchPhase {
   std::vector<uint8_t> capped; // stopped at max_iterations
   ull* hS = nullptr;           // pinned: 2G words of per-graph gain sums
   uint8_t* hact = nullptr;     // pinned: G activity flags
+  std::vector<int64_t> size;   // vertices of every graph at this level
+  int64_t listed = 0;          // vertices of the graphs in the current lists
 };
 
 struct PhaseOut {
@@ -374,11 +376,23 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
       lv::MoveBuffers m = ph.m;
       m.stats = stats0 + 8 * k;
       hipEvent_t* ev = ctx->ev + kEvStep * k;
-      hipStream_t s1 = ctx->side[0], s2 = ctx->side[1];
-      // the three tiers decide disjoint vertices from the same state: run them concurrently
-      HIPCHK(hipEventRecord(ctx->fork[k], s));
-      HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
-      HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
+      // the three tiers decide disjoint vertices from the same state: when at least two of them
+      // have real work they run concurrently, forked onto the side streams and joined back
+      int64_t ta = 0, tb = 0, tc = 0;
+      for (int j = 0; j < DEG; j++) {
+        const int64_t arcs = ph.b.arcs[DEG * k + j];
+        if (j < 7) ta += arcs;
+        else if (j < hf) tb += arcs;
+        else tc += arcs;
+      }
+      const int64_t kBig = (int64_t)1 << 20;
+      const bool par = (ta >= kBig) + (tb >= kBig) + (tc >= kBig) >= 2;
+      hipStream_t s1 = par ? ctx->side[0] : s, s2 = par ? ctx->side[1] : s;
+      if (par) {
+        HIPCHK(hipEventRecord(ctx->fork[k], s));
+        HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
+        HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
+      }
       if (trace) HIPCHK(hipEventRecord(ev[0], s));
       HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
       if (trace) HIPCHK(hipEventRecord(ev[1], s));
@@ -388,10 +402,12 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
       if (trace) HIPCHK(hipEventRecord(ev[4], s2));
       HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s2));
       if (trace) HIPCHK(hipEventRecord(ev[5], s2));
-      HIPCHK(hipEventRecord(ctx->join0[k], s1));
-      HIPCHK(hipEventRecord(ctx->join1[k], s2));
-      HIPCHK(hipStreamWaitEvent(s, ctx->join0[k], 0));
-      HIPCHK(hipStreamWaitEvent(s, ctx->join1[k], 0));
+      if (par) {
+        HIPCHK(hipEventRecord(ctx->join0[k], s1));
+        HIPCHK(hipEventRecord(ctx->join1[k], s2));
+        HIPCHK(hipStreamWaitEvent(s, ctx->join0[k], 0));
+        HIPCHK(hipStreamWaitEvent(s, ctx->join1[k], 0));
+      }
       if (trace) HIPCHK(hipEventRecord(ev[6], s));
       HIPCHK(lv::reduce_move_partials(ph.b, k, m, s));
       HIPCHK(lv::apply_moves(ph.b, k, m, s));
@@ -483,6 +499,14 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
       memcpy(bp->hact, bp->act.data(), (size_t)bp->G);
       HIPCHK(hipMemcpyAsync((void*)ph.m.gs.act, bp->hact, (size_t)bp->G, hipMemcpyHostToDevice,
                             s));
+      // once most listed vertices belong to graphs that stopped, list only the others again
+      int64_t live = 0;
+      for (int64_t g = 0; g < bp->G; g++)
+        if (bp->act[g]) live += bp->size[g];
+      if (2 * live < bp->listed) {
+        CHK(plan_phase(ctx, ph, s));
+        bp->listed = live;
+      }
       continue;
     }
     if (!((u128)S > T)) {  // the iteration's modularity change is within the tolerance
@@ -527,7 +551,8 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   HIPCHK(lv::zero_words(a.stats, 2, s));
   HIPCHK(lv::aggregate_prepare(g, C, csize, Sig, Kp, map, a, s));
   lv::Buckets b;
-  HIPCHK(lv::bucket_rows(nullptr, nullptr, a.A, n, 1, 0, nullptr, nullptr, a.list, a.counts,
+  HIPCHK(lv::bucket_rows(nullptr, nullptr, a.A, n, 1, 0, nullptr, nullptr, nullptr, a.list,
+                         a.counts,
                          ctx->pinned + PIN_COUNTS, b, s));
   // the super-vertex count bounds the distinct targets of any community
   ull* hm = ctx->pinned + PIN_MISC;
@@ -1063,6 +1088,8 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
   bp.G = G;
   bp.hS = hw;
   bp.hact = hact;
+  bp.size.resize(G);
+  for (int32_t g = 0; g < G; g++) bp.size[g] = graph_vptr[g + 1] - graph_vptr[g];
   for (int pass = 0; pass < p->max_passes; pass++) {
     bool any = false;
     for (int32_t g = 0; g < G; g++) any = any || !done[g];
@@ -1093,6 +1120,9 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     }
     memcpy(hact, bp.act.data(), (size_t)G);
     HIPCHK(hipMemcpyAsync(gact, hact, (size_t)G, hipMemcpyHostToDevice, s));
+    bp.listed = 0;
+    for (int32_t g = 0; g < G; g++)
+      if (bp.act[g]) bp.listed += bp.size[g];
     CHK(plan_phase(ctx, ph, s));
     PhaseOut po;
     CHK(run_phase(ctx, ph, 0, p->max_iterations, p->flags & ~LV_TRACE, s, nullptr, &po, &bp));
@@ -1154,6 +1184,7 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     maxK = hw[3 * (int64_t)G + 1];
     for (int32_t g = 0; g < G; g++) {
       per_graph[g].n_communities = nb_new[g + 1] - nb_new[g];
+      bp.size[g] = nb_new[g + 1] - nb_new[g];
       if (!ran[g]) continue;
       const u128 sq = ((u128)hw[G + 2 * (int64_t)g + 1] << 64) | hw[G + 2 * (int64_t)g];
       qnum[g] = (i128)((u128)W[g] * hw[g]) - (i128)sq;

@@ -92,12 +92,12 @@ hipError_t unpack_state(int64_t n, const void* rec, int32_t* C, uint64_t* Sig, i
                         hipStream_t s);
 // Classify rows (lengths from offsets, or from `len` if non-null over m items) by vertex
 // class (K classes of pass `pass`, hashing ids local to their graph when gid is given) and
-// degree class. counts: device scratch of 1536 words;
+// degree class; with act, rows of graphs g with act[g] == 0 are left out. counts: device scratch of 1536 words;
 // host_counts: 1536 pinned words. Host result in `b` (synchronises the stream).
 hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
-                       int K, int pass, const int32_t* gid, const int64_t* gbase, int32_t* list,
-                       unsigned long long* counts, unsigned long long* host_counts, Buckets& b,
-                       hipStream_t s);
+                       int K, int pass, const int32_t* gid, const int64_t* gbase,
+                       const uint8_t* act, int32_t* list, unsigned long long* counts,
+                       unsigned long long* host_counts, Buckets& b, hipStream_t s);
 // Two-phase plan for the items items[0 .. nh) (lengths from rs/re, or len[item]) whose keys
 // take at most `cap` distinct values; vb: value bytes; merge: one-chunk items need no phase 2.
 // arrays: kPlanWords * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.

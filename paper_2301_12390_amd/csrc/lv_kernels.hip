@@ -515,7 +515,8 @@ __device__ __forceinline__ int64_t item_len(const int64_t* rs, const int64_t* re
 constexpr int kMaxSeg = kDegClasses * kMaxClasses;
 
 // Vertex classes hash the id of a vertex within its own graph: i - gbase[gid[i]] in a batch of
-// graphs packed with consecutive ids (gid null: one graph).
+// graphs packed with consecutive ids (gid null: one graph). In a batch, rows of graphs that are
+// not iterating (act[gid[i]] == 0) are left out of the lists.
 __device__ __forceinline__ int segment_of(int64_t L, int K, int pass, int64_t i,
                                           const int32_t* gid, const int64_t* gbase) {
   const int64_t loc = gid ? i - gbase[gid[i]] : i;
@@ -524,10 +525,16 @@ __device__ __forceinline__ int segment_of(int64_t L, int K, int pass, int64_t i,
 }
 
 // counts[0 .. nseg): items per segment, counts[kMaxSeg .. kMaxSeg + nseg): total length.
+__device__ __forceinline__ bool listed(int64_t L, int64_t i, const int32_t* gid,
+                                       const uint8_t* act) {
+  return L > 0 && (!act || act[gid[i]]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, const int64_t* re,
                                                         const int64_t* len, int64_t m, int K,
                                                         int pass, const int32_t* gid,
-                                                        const int64_t* gbase, ull* counts) {
+                                                        const int64_t* gbase, const uint8_t* act,
+                                                        ull* counts) {
   __shared__ ull c[2 * kMaxSeg];
   const int nseg = kDegClasses * K;
   for (int t = threadIdx.x; t < 2 * kMaxSeg; t += blockDim.x) c[t] = 0;
@@ -535,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, cons
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t L = item_len(rs, re, len, i);
-    if (L > 0) {
+    if (listed(L, i, gid, act)) {
       const int sg = segment_of(L, K, pass, i, gid, gbase);
       atomicAdd(&c[sg], 1ull);
       atomicAdd(&c[kMaxSeg + sg], (ull)L);
@@ -552,8 +559,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, cons
 __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const int64_t* re,
                                                        const int64_t* len, int64_t m, int K,
                                                        int pass, const int32_t* gid,
-                                                       const int64_t* gbase, const ull* starts,
-                                                       ull* cursor, int32_t* list) {
+                                                       const int64_t* gbase, const uint8_t* act,
+                                                       const ull* starts, ull* cursor,
+                                                       int32_t* list) {
   __shared__ int cnt[kMaxSeg];
   __shared__ ull base[kMaxSeg];
   const int nseg = kDegClasses * K;
@@ -565,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const
     int sg = -1, rank = 0;
     if (i < m) {
       const int64_t L = item_len(rs, re, len, i);
-      if (L > 0) {
+      if (listed(L, i, gid, act)) {
         sg = segment_of(L, K, pass, i, gid, gbase);
         rank = atomicAdd(&cnt[sg], 1);
       }
@@ -580,8 +588,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const
 }
 
 hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
-                       int K, int pass, const int32_t* gid, const int64_t* gbase, int32_t* list,
-                       ull* counts, ull* host_counts, Buckets& b, hipStream_t s) {
+                       int K, int pass, const int32_t* gid, const int64_t* gbase,
+                       const uint8_t* act, int32_t* list, ull* counts, ull* host_counts,
+                       Buckets& b, hipStream_t s) {
   b = Buckets();
   b.classes = K;
   if (m <= 0) return hipSuccess;
@@ -589,7 +598,7 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
   // counts layout (kMaxSeg words each): items, lengths, fill cursors, segment starts
   LV_LAUNCH(k_zero_words, 8, kBlock, 0, s, counts, (int64_t)(3 * kMaxSeg));
   LV_LAUNCH(k_bucket_count, grid_for(m, kBlock, 4096), kBlock, 0, s, rs, re, len, m, K, pass,
-            gid, gbase, counts);
+            gid, gbase, act, counts);
   hipError_t e = hipMemcpyAsync(host_counts, counts, 2 * kMaxSeg * sizeof(ull),
                                 hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
@@ -609,7 +618,7 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
                      s);
   if (e != hipSuccess) return e;
   LV_LAUNCH(k_bucket_fill, grid_for(m, kBlock, 8192), kBlock, 0, s, rs, re, len, m, K, pass,
-            gid, gbase, counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
+            gid, gbase, act, counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
   return hipGetLastError();
 }
 
@@ -698,6 +707,45 @@ hipError_t plan_parts(const int64_t* rs, const int64_t* re, const int64_t* len,
 // All reads are of the previous iteration's C, Sigma and csize; every vertex writes its decision,
 // and the decisions are applied after the kernel, so the outcome does not depend on scheduling.
 
+// Adds arcs e0 + lane, e0 + lane + S, ... (< e1) of vertex v's row to an LDS table keyed by the
+// neighbour's community, self-loops skipped. Each lane first issues U independent index loads and
+// U independent record gathers, then makes its U table updates, so that U gathers per lane are
+// in flight instead of one. With SIGC, a neighbour that labels its own community also stores that
+// community's Sigma in sigs. Returns the number of slots this lane claimed.
+template <typename V, typename WT, int U, bool SIGC>
+__device__ __forceinline__ int accumulate_row(const int32_t* idx, const WT* w, const VRec* rec,
+                                              int32_t v, int64_t e0, int64_t e1, int lane, int S,
+                                              int32_t* keys, V* vals, ull* sigs, int log2h) {
+  int fresh = 0;
+  for (int64_t e = e0 + lane; e < e1; e += (int64_t)U * S) {
+    int32_t j[U];
+    V wv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t eu = e + (int64_t)u * S;
+      j[u] = eu < e1 ? ld_stream(idx + eu) : v;
+      wv[u] = eu < e1 ? (V)ld_stream(w + eu) : (V)0;
+    }
+    VRec r[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (SIGC) {
+        if (j[u] != v) r[u] = rec[j[u]];
+      } else {
+        r[u].c = j[u] != v ? rec[j[u]].c : kEmpty;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (j[u] == v) continue;
+      uint32_t slot;
+      fresh += table_add<V>(keys, vals, log2h, r[u].c, wv[u], &slot);
+      if (SIGC && r[u].c == j[u]) sigs[slot] = r[u].sig;
+    }
+  }
+  return fresh;
+}
+
 // Batches of graphs (GraphSet): W and graph of vertex v, false if its graph is not iterating in
 // this phase; and the per-graph gain sums of the iteration.
 __device__ __forceinline__ bool gs_vertex(const GraphSet& gs, int32_t v, uint64_t* W,
@@ -767,11 +815,10 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
     e0 = a.rs[v];
     e1 = a.re[v];
   }
-  for (int64_t e = e0 + lane; e < e1; e += G) {
-    const int32_t j = ld_stream(a.idx + e);
-    const V wv = (V)ld_stream(a.w + e);
-    if (j != v) table_add<V>(gk, gv, LOG2H, a.rec[j].c, wv);
-  }
+  // lanes per row cover a class's longest row in one round for classes 0..4; rows of classes 5
+  // and up take several arcs per lane, gathered together
+  constexpr int U = (1 << LOG2H) / 2 > G ? 4 : 1;
+  accumulate_row<V, WT, U, false>(a.idx, a.w, a.rec, v, e0, e1, lane, G, gk, gv, nullptr, LOG2H);
   __syncthreads();
   T bg = Ar::lowest();
   int32_t bc = INT32_MAX;
@@ -958,20 +1005,8 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
   int32_t gr = 0;
   const bool on = gs_vertex(a.gs, v, &W, &gr);
   const int64_t e0 = a.rs[v], e1 = on ? a.re[v] : e0;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kWgBlock) {
-    const int32_t j = ld_stream(a.idx + e);
-    const V wv = (V)ld_stream(a.w + e);
-    if (j != v) {
-      if (SIGC) {
-        const VRec rj = a.rec[j];
-        uint32_t slot;
-        table_add<V>(keys, vals, LOG2H, rj.c, wv, &slot);
-        if (rj.c == j) sigs[slot] = rj.sig;
-      } else {
-        table_add<V>(keys, vals, LOG2H, a.rec[j].c, wv);
-      }
-    }
-  }
+  accumulate_row<V, WT, 4, SIGC>(a.idx, a.w, a.rec, v, e0, e1, threadIdx.x, kWgBlock, keys, vals,
+                                 sigs, LOG2H);
   __syncthreads();
   const int32_t d = a.rec[v].c;
   const uint64_t Ki = a.K[v];
@@ -1444,12 +1479,8 @@ struct HubChunk {
     constexpr int Q = part_chunk((int)sizeof(V));
     const int64_t c0 = e0 + k * Q;
     const int64_t c1 = c0 + Q < e1 ? c0 + Q : e1;
-    int fresh = 0;
-    for (int64_t e = c0 + threadIdx.x; e < c1; e += kPartBlock) {
-      const int32_t j = ld_stream(a->idx + e);
-      const V wv = (V)ld_stream(a->w + e);
-      if (j != v) fresh += table_add<V>(keys, vals, LOG2H, a->rec[j].c, wv);
-    }
+    const int fresh = accumulate_row<V, WT, 4, false>(a->idx, a->w, a->rec, v, c0, c1, threadIdx.x,
+                                                      kPartBlock, keys, vals, nullptr, LOG2H);
     if (fresh) atomicAdd(&flags[0], fresh);
   }
   __device__ void operator()(int64_t k, int32_t* keys, V* vals, int* flags) {
@@ -1830,6 +1861,16 @@ __device__ __forceinline__ int member_at(const T* start, int mc, int64_t t) {
   return lo;
 }
 
+// Largest member index i in [lo, hi) with start[i] <= t, given start[lo] <= t.
+template <typename T>
+__device__ __forceinline__ int member_in(const T* start, int lo, int hi, int64_t t) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)start[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Super-arc weights: 32-bit when every community's Sigma (which bounds the weight of each of
 // its super-arcs) is below 2^32, else 64-bit.
 struct WOut {
@@ -1907,10 +1948,31 @@ __device__ __forceinline__ void merge_group(const MergeArgs<WT>& a, int64_t lb, 
   }
   if (lane == 0) gcount[gid] = 0;
   __syncthreads();
-  for (int64_t t = lane; t < L; t += G) {
-    const int i = member_at(gf, mc, t);
-    const int64_t e = a.rs[gm[i]] + (t - gf[i]);
-    table_add<ull>(gk, gv, LOG2H, a.map[a.idx[e]], (ull)a.w[e]);
+  constexpr int U = (1 << LOG2H) / 2 > G ? 4 : 1;  // arcs per lane gathered together
+  for (int64_t t = lane; t < L; t += (int64_t)U * G) {
+    int64_t e[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t tu = t + (int64_t)u * G;
+      e[u] = -1;
+      if (tu < L) {
+        const int i = member_at(gf, mc, tu);
+        e[u] = a.rs[gm[i]] + (tu - gf[i]);
+      }
+    }
+    int32_t j[U];
+    ull wv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      j[u] = e[u] >= 0 ? a.idx[e[u]] : 0;
+      wv[u] = e[u] >= 0 ? (ull)a.w[e[u]] : 0;
+    }
+    int32_t key[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) key[u] = e[u] >= 0 ? a.map[j[u]] : kEmpty;
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (key[u] != kEmpty) table_add<ull>(gk, gv, LOG2H, key[u], wv[u]);
   }
   __syncthreads();
   ull self = 0;
@@ -2118,32 +2180,58 @@ __device__ __forceinline__ ull part_block_sum(ull x, ull* red) {
 }
 
 // Chunk k of community c's flat arc range: each thread a run of kMergePerThread consecutive flat
-// arcs (one member search, then a forward walk), keyed by the target's new id.
+// arcs (one member search, then a forward walk), keyed by the target's new id. The members
+// covering the chunk are located once per chunk, so each thread searches only among them.
 template <typename WT>
 struct MergeChunk {
   const MergeHubArgs<WT>* a;
   int64_t m0, a0, L;
   int mc;
   __device__ void operator()(int64_t k, int32_t* keys, ull* vals, int* flags) {
-    const int64_t t0 = k * kMergeChunk + (int64_t)threadIdx.x * kMergePerThread;
-    const int64_t t1 = t0 + kMergePerThread < L ? t0 + kMergePerThread : L;
+    __shared__ int span[2];
+    const int64_t c0 = k * kMergeChunk;
+    const int64_t c1 = c0 + kMergeChunk < L ? c0 + kMergeChunk : L;
+    if (threadIdx.x < 2)
+      span[threadIdx.x] = member_at(a->gscan + m0, mc, a0 + (threadIdx.x == 0 ? c0 : c1 - 1));
+    __syncthreads();
+    const int64_t t0 = c0 + (int64_t)threadIdx.x * kMergePerThread;
+    const int64_t t1 = t0 + kMergePerThread < c1 ? t0 + kMergePerThread : c1;
     int fresh = 0;
     if (t0 < t1) {
       // member holding flat arc t0 (first flat arcs are a0 + gscan offsets)
-      int i = member_at(a->gscan + m0, mc, a0 + t0);
+      int i = member_in(a->gscan + m0, span[0], span[1] + 1, a0 + t0);
       int64_t next = i + 1 < mc ? a->gscan[m0 + i + 1] - a0 : L;
       int64_t first = a->gscan[m0 + i] - a0;
       int32_t v = a->members[m0 + i];
-      for (int64_t t = t0; t < t1; t++) {
-        while (t >= next) {
-          i++;
-          first = next;
-          next = i + 1 < mc ? a->gscan[m0 + i + 1] - a0 : L;
-          v = a->members[m0 + i];
+      // positions of this thread's arcs, then their loads and gathers together
+      int64_t e[kMergePerThread];
+#pragma unroll
+      for (int u = 0; u < kMergePerThread; u++) {
+        const int64_t t = t0 + u;
+        e[u] = -1;
+        if (t < t1) {
+          while (t >= next) {
+            i++;
+            first = next;
+            next = i + 1 < mc ? a->gscan[m0 + i + 1] - a0 : L;
+            v = a->members[m0 + i];
+          }
+          e[u] = a->rs[v] + (t - first);
         }
-        const int64_t e = a->rs[v] + (t - first);
-        fresh += table_add<ull>(keys, vals, kMergeLog2H, a->map[a->idx[e]], (ull)a->w[e]);
       }
+      int32_t j[kMergePerThread];
+      ull wv[kMergePerThread];
+#pragma unroll
+      for (int u = 0; u < kMergePerThread; u++) {
+        j[u] = e[u] >= 0 ? a->idx[e[u]] : 0;
+        wv[u] = e[u] >= 0 ? (ull)a->w[e[u]] : 0;
+      }
+      int32_t key[kMergePerThread];
+#pragma unroll
+      for (int u = 0; u < kMergePerThread; u++) key[u] = e[u] >= 0 ? a->map[j[u]] : kEmpty;
+#pragma unroll
+      for (int u = 0; u < kMergePerThread; u++)
+        if (key[u] != kEmpty) fresh += table_add<ull>(keys, vals, kMergeLog2H, key[u], wv[u]);
     }
     if (fresh) atomicAdd(&flags[0], fresh);
   }
