@@ -152,7 +152,9 @@ def summarize_stats(csv_path, out_path, command):
     lines = ["# Kernel time, R-MAT scale 25 Louvain runs", "",
              "Made by:", "", "```", command, "```", "",
              f"Library kernels total: {total / 1e6:.1f} ms over all profiled runs "
-             "(warm-up and timed steps).", "",
+             "(warm-up and timed steps). The move kernels of a class step run concurrently on "
+             "up to three streams, so their durations overlap: shares are of summed kernel "
+             "time, not of wall time.", "",
              "| kernel | calls | total ms | average us | share |",
              "|---|---:|---:|---:|---:|"]
     for r in rows:
@@ -623,6 +625,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
+            "traffic_gbps": (traffic / (avg_launch_ms / 1000.0) / 1e9
+                             if traffic and avg_launch_ms > 0 else None),
             "avg_launch_ms": avg_launch_ms,
             "launches": int(f_launch),
             "algorithmic_bytes_per_launch": bytes_per_launch,
