@@ -165,3 +165,28 @@ def test_rmat22_quality_vs_async(lv, rmat22):
     _, res = lv.run(g, substeps=K_CLASSES)
     print(f"rmat22: Q gpu {res['q']:.6f}, Q async {ra['q']:.6f}", flush=True)
     assert res["q"] >= ra["q"] - 0.01
+
+
+@pytest.mark.timeout(900)
+def test_batched_workload_sampled(lv):
+    """The 2048-graph batch in one louvain_run_batched call, as bench.py times it; every graph's
+    community count and the Qnum of a sample of graphs (the largest ones and a spread of the
+    rest) against the oracle's run on the graph alone."""
+    from graphgen import batch_config, pack_graphs
+    print("generating the 2048-graph batch on the GPU", flush=True)
+    graphs = batch_config(2048, device="cuda:0")
+    packed, vptr, aptr = pack_graphs(graphs, device="cuda:0")
+    memb, res = lv.run_batched(packed, vptr, aptr, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    memb = memb.cpu().numpy()
+    for g in range(len(graphs)):
+        m = memb[vptr[g]:vptr[g + 1]]
+        assert m.min() >= 0 and m.max() == res[g]["n_communities"] - 1, g
+    sizes = np.array([gr.n for gr in graphs])
+    sample = sorted(set(np.argsort(sizes)[-4:].tolist()) | set(range(0, 2048, 97)))
+    for g in sample:
+        gr = graphs[g].to("cpu")
+        top, ref = O.run(O.Graph.from_csr(gr), "sync", substeps=K_CLASSES)
+        assert np.array_equal(memb[vptr[g]:vptr[g + 1]], top), g
+        assert res[g]["qnum"] == ref["qnum"] and res[g]["iterations"] == ref["iterations"], g
+    print(f"checked {len(sample)} of 2048 graphs against the oracle", flush=True)
