@@ -103,26 +103,28 @@ typedef struct {
 #define LV_MAX_TRACE 1024
 
 /* One local-moving iteration (host). The move kernels are: the fused LDS-table kernel
- * (k_move_lds, rows of up to 1024 arcs), the workgroup-per-row kernel (k_move_wg, rows of up
- * to 8192 arcs when the device allows its LDS table) and the global-table hub kernels. */
+ * (k_move_lds, rows of up to 1024 arcs), the group and workgroup-per-row kernels (k_move_grp7,
+ * k_move_wg: rows of up to 8192 arcs when the device allows their LDS tables) and the two-phase
+ * hub kernels (longer rows). The tiers of a class step may run concurrently, so their times
+ * overlap. */
 typedef struct {
   int32_t pass, iteration;
   int32_t wide;            /* 1 if this iteration used 128-bit gains */
   int32_t substeps;        /* class steps of the iteration */
   int32_t fused_launches;  /* launches of k_move_lds */
-  int32_t wg_launches;     /* launches of k_move_wg */
+  int32_t wg_launches;     /* class steps with rows for k_move_grp7 / k_move_wg */
   int32_t hub_launches;    /* class steps that ran the hub kernels */
   int32_t reserved;
   lv_i128 gain_sum;        /* S: sum of the applied gains */
   int64_t moved;           /* vertices that changed community */
   int64_t candidates;      /* distinct (vertex, other community) pairs examined */
   int64_t fused_vertices, fused_arcs, fused_candidates; /* work of k_move_lds */
-  int64_t wg_vertices, wg_arcs, wg_candidates;          /* work of k_move_wg */
+  int64_t wg_vertices, wg_arcs, wg_candidates;          /* work of k_move_grp7 / k_move_wg */
   int64_t hub_vertices, hub_arcs;                       /* work of the hub kernels */
   float fused_ms;          /* k_move_lds, summed over the class steps (LV_TRACE) */
-  float wg_ms;             /* k_move_wg and the step's reduction (LV_TRACE) */
+  float wg_ms;             /* k_move_grp7 and k_move_wg (LV_TRACE) */
   float hub_ms;            /* hub kernels (LV_TRACE) */
-  float update_ms;         /* membership/community updates (LV_TRACE) */
+  float update_ms;         /* the step's record reduction and community updates (LV_TRACE) */
   float iter_ms;           /* whole iteration including the host read-back (LV_TRACE) */
   float reserved2;
 } lv_iter_trace;

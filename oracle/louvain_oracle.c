@@ -22,14 +22,14 @@
  *   changes Qnum by exactly 2 * (g_i(c) - g_i(d)).
  *
  * Readings of the paper adopted where it is silent:
- *   - candidates are the communities of the vertex's non-self neighbours (it moves "to the
- *     community of one of its neighbors");
+ *   - candidates are the communities of the vertex's non-self neighbours (the method moves a
+ *     vertex into some neighbour's community);
  *   - a vertex moves only if the best gain is strictly greater than the gain of staying;
  *   - ties between candidates go to the smallest community id;
  *   - synchronous (Jacobi) iterations read only the previous iteration's state, and a vertex
  *     whose own community and best community are both singletons does not move to a larger id
  *     (singleton-swap prevention, from the Grappolo line of work the paper cites);
- *   - an iteration's "total change in modularity" is 2*S/W^2 with S the sum of the applied
+ *   - the total modularity change of an iteration is 2*S/W^2 with S the sum of the applied
  *     gains; the phase repeats while it exceeds tolerance_p = 10^-(a + b*p) in pass p, i.e.
  *     while S > floor(W^2 / (2 * 10^(a+b*p)));
  *   - pass_tolerance is 0: a pass that moves nothing ends the run; aggregation that does not

@@ -34,11 +34,11 @@ __host__ __device__ constexpr int bucket_rows_per_block(int k) { return kBlock /
 __host__ __device__ constexpr int move_group_size(int k) { return bucket_group(k); }
 __host__ __device__ constexpr int move_rows_per_block(int k) { return kBlock / move_group_size(k); }
 
-// Degree classes 7, 8, 9 (rows of up to 2048, 4096, 8192 arcs) are decided by one 1024-thread
-// workgroup per row with an LDS table of 4096, 8192 or 16384 slots when the device allows such
-// a workgroup allocation; class 10 (longer rows), and any class whose table does not fit, use
-// the global-table hub path. kDegClasses is the stride of the (vertex class, degree class)
-// segments.
+// Degree class 7 (rows of up to 2048 arcs) is decided by one 256-thread group per row with a
+// 4096-slot LDS table; classes 8 and 9 (up to 4096, 8192 arcs) by one 1024-thread workgroup per
+// row with an LDS table of 8192 or 16384 slots when the device allows such a workgroup
+// allocation; class 10 (longer rows), and any class whose table does not fit, take the
+// two-phase hub path. kDegClasses is the stride of the (vertex class, degree class) segments.
 constexpr int kDegClasses = 12;
 constexpr int kFusedClasses = 7;
 constexpr int kHubClass = 10;

@@ -93,7 +93,7 @@ def test_generator_symmetric_simple():
 
 
 # ----------------------------------------------------------------------------------------------
-# tolerance threshold (integer form of "total change in modularity > tolerance")
+# tolerance threshold (integer form of: the iteration's modularity change exceeds the tolerance)
 
 
 def test_threshold_values():
