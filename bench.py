@@ -452,6 +452,61 @@ def run_serving_bench(args, dev):
     print(json.dumps(line), flush=True)
 
 
+def run_sweep_bench(args, dev):
+    """Tolerance and decline-factor sweep (section 3.2's parameter study): Q, time, iterations
+    and passes of louvain_run for initial tolerance 10^-a and decline factor 10^b on the
+    synthetic graphs, with the sequential asynchronous oracle's Q beside them where it is cheap
+    (graphs of up to ~2e7 arcs)."""
+    import torch
+
+    import oracle as O
+    from graphgen import config_graph
+    from paper_2301_12390_amd import Louvain
+
+    lv = Louvain(0)
+    tols = [int(x) for x in args.sweep_tolerances.split(",")]
+    decls = [int(x) for x in args.sweep_declines.split(",")]
+    grid = [(a, 1) for a in tols] + [(2, b) for b in decls if b != 1]
+    out = []
+    for name in args.sweep_graphs.split(","):
+        g = config_graph(name, device=dev)
+        torch.cuda.synchronize()
+        q_async = None
+        if g.nnz <= args.sweep_async_arcs:
+            _, ra = O.run(O.Graph.from_csr(g.to("cpu")), "async")
+            q_async = ra["q"]
+        rows = []
+        for a, b in grid:
+            lv.run(g, tolerance_exp10=a, decline_exp10=b, substeps=args.substeps)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r = lv.run(g, tolerance_exp10=a, decline_exp10=b, substeps=args.substeps)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1000.0
+            rows.append({"tolerance": f"1e-{a}", "decline": 10 ** b, "q": r["q"],
+                         "ms": ms, "passes": r["passes"], "iterations": r["iterations"],
+                         "iterations_total": r["iterations_total"], "cap_hits": r["cap_hits"]})
+            log(f"{name} tol 1e-{a} decline 1e{b}: Q {r['q']:.6f}, {ms:.1f} ms, "
+                f"{r['iterations_total']} iterations in {r['passes']} passes")
+        out.append({"graph": name, "n": g.n, "nnz": g.nnz, "q_async_oracle": q_async,
+                    "runs": rows})
+        del g
+        torch.cuda.empty_cache()
+    lv.close()
+    base = next(r for r in out[-1]["runs"] if r["tolerance"] == "1e-2" and r["decline"] == 10)
+    line = {
+        "metric": METRIC,
+        "value": out[-1]["nnz"] / (base["ms"] / 1000.0),
+        "unit": "TEPS (last graph, tolerance 1e-2, decline 10)",
+        "n_gpus": 1, "steps": len(grid), "warmup": 1, "ms_per_step": base["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i64",
+        "data": "synthetic",
+        "config": {"workload": "sweep", "substeps": args.substeps, "graphs": out},
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -461,6 +516,14 @@ def main():
                     help="graphs of the batched workload")
     ap.add_argument("--no-one-by-one", action="store_true",
                     help="batched: skip the graph-by-graph comparison run")
+    ap.add_argument("--sweep-graphs", default="sbm10k,rmat22",
+                    help="sweep: workloads to sweep (config names)")
+    ap.add_argument("--sweep-tolerances", default="0,1,2,3,4,6,8,12",
+                    help="sweep: initial tolerance exponents a (tolerance 10^-a), decline 10")
+    ap.add_argument("--sweep-declines", default="1,2,3,4",
+                    help="sweep: decline exponents b (factor 10^b) at tolerance 1e-2")
+    ap.add_argument("--sweep-async-arcs", type=int, default=20000000,
+                    help="sweep: largest graph (arcs) given the asynchronous oracle's Q")
     ap.add_argument("--rates", default="50,200,800",
                     help="serving: request rates (per second), comma separated")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -470,8 +533,9 @@ def main():
                     help="serving: most arcs the server runs in one batch")
     ap.add_argument("--workload", default="rmat25",
                     help="rmat25 (default), rmat22, sbm10k, rmatNN, batched (the batch of "
-                         "--batch-count SBM and lattice graphs, graphs/s) or serving (Poisson "
-                         "requests at --rates, p50/p99 latency)")
+                         "--batch-count SBM and lattice graphs, graphs/s), serving (Poisson "
+                         "requests at --rates, p50/p99 latency) or sweep (tolerance and "
+                         "decline-factor study)")
     ap.add_argument("--substeps", type=int, default=8,
                     help="vertex classes per local-moving iteration (1 = fully synchronous)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -519,6 +583,9 @@ def main():
         return
     if args.workload == "serving":
         run_serving_bench(args, dev)
+        return
+    if args.workload == "sweep":
+        run_sweep_bench(args, dev)
         return
     t0 = time.perf_counter()
     if args.graph_cache and os.path.exists(args.graph_cache):

@@ -252,6 +252,17 @@ def test_run_parameters(lv):
     check_run(lv, g, flags=0x4, substeps=1)
 
 
+SWEEP = [(0, 1), (1, 1), (3, 1), (4, 1), (6, 1), (8, 1), (12, 1), (2, 2), (2, 3), (2, 4)]
+
+
+@pytest.mark.parametrize("a,b", SWEEP, ids=[f"tol1e-{a}-decl1e{b}" for a, b in SWEEP])
+def test_run_tolerance_sweep(lv, a, b):
+    # the tolerance / decline-factor study of bench.py --workload sweep, against the oracle
+    check_run(lv, sbm(3000, 30, 8.0, 2.0, seed=2, weights=(1, 16)), tolerance_exp10=a,
+              decline_exp10=b)
+    check_run(lv, rmat(13, seed=9), tolerance_exp10=a, decline_exp10=b)
+
+
 def test_run_sbm10k(lv):
     from graphgen import config_graph
     g = config_graph("sbm10k")
