@@ -245,15 +245,24 @@ def aggregate(g: Graph, C):
 
 
 def run(g: Graph, mode: str = "sync", a: int = 2, b: int = 1, max_iterations: int = 20,
-        max_passes: int = 10, substeps: int = 1, nthreads: int = 0):
+        max_passes: int = 10, substeps: int = 1, nthreads: int = 0, levels: bool = False):
     """Whole Louvain run. Returns (membership int32[n], result dict).
     mode "sync": synchronous rule, an iteration being ``substeps`` class steps;
-    mode "async": sequential asynchronous rule."""
+    mode "async": sequential asynchronous rule.
+    levels: also return, as result["levels"] (int32[L, n]), the membership of the input
+    vertices after each of the L aggregations (the last one equals the membership)."""
     top = np.zeros(max(g.n, 1), dtype=np.int32)
     r = OrcResult()
-    lib().orc_run(*g.args(), ctypes.c_int32(0 if mode == "sync" else 1), ctypes.c_int32(a),
-                  ctypes.c_int32(b), ctypes.c_int32(max_iterations), ctypes.c_int32(max_passes),
-                  ctypes.c_int32(substeps), ctypes.c_int32(nthreads), _p(top), ctypes.byref(r))
+    common = (*g.args(), ctypes.c_int32(0 if mode == "sync" else 1), ctypes.c_int32(a),
+              ctypes.c_int32(b), ctypes.c_int32(max_iterations), ctypes.c_int32(max_passes),
+              ctypes.c_int32(substeps), ctypes.c_int32(nthreads), _p(top), ctypes.byref(r))
+    if levels:
+        max_levels = max(1, min(max_passes, MAX_PASSES))
+        lv = np.zeros((max_levels, max(g.n, 1)), dtype=np.int32)
+        nl = ctypes.c_int32(0)
+        lib().orc_run_levels(*common, _p(lv), ctypes.c_int32(max_levels), ctypes.byref(nl))
+    else:
+        lib().orc_run(*common)
     nt = r.n_trace
     res = {
         "passes": r.passes,
@@ -272,4 +281,6 @@ def run(g: Graph, mode: str = "sync", a: int = 2, b: int = 1, max_iterations: in
         "qnum": _i128(r.qnum[0], r.qnum[1]),
     }
     res["q"] = (res["qnum"] / (res["W"] * res["W"])) if res["W"] else 0.0
+    if levels:
+        res["levels"] = lv[:nl.value, :g.n].copy()
     return top[:g.n].copy(), res

@@ -466,11 +466,16 @@ static int64_t* copy64(const int64_t* a, int64_t k) {
  * substeps (mode 0): K vertex classes; an iteration is K synchronous steps, class 0 first,
  * each seeing the moves of the classes before it (K = 1: fully synchronous).
  * a, b: initial tolerance 10^-a, decline factor 10^b (defaults 2 and 1, section 3.2).
- * top[n]: output membership (dense labels of the last level). */
-int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
-            int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
-            int32_t substeps, int32_t nthreads, int32_t* top, orc_result* res) {
+ * top[n]: output membership (dense labels of the last level).
+ * levels (may be NULL): levels[l*n + v] = community of input vertex v after the l-th
+ * aggregation, for l < *n_levels <= max_levels; the hierarchy the passes build (section 3.2:
+ * each pass's communities become the vertices of the next). */
+static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
+                    int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
+                    int32_t substeps, int32_t nthreads, int32_t* top, orc_result* res,
+                    int32_t* levels, int32_t max_levels, int32_t* n_levels) {
   memset(res, 0, sizeof(*res));
+  if (n_levels) *n_levels = 0;
   for (int64_t v = 0; v < n; v++) top[v] = (int32_t)v;
   int64_t nnz0 = n > 0 ? off0[n] : 0;
   uint64_t* K = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
@@ -562,6 +567,10 @@ int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t*
     int64_t nn = 0, nnz2 = 0;
     orc_aggregate(cn, off, idx, w, C, map, off2, idx2, w2, &nn, &nnz2);
     for (int64_t v = 0; v < n; v++) top[v] = map[top[v]];
+    if (levels && n_levels && *n_levels < max_levels) {
+      memcpy(levels + (size_t)(*n_levels) * (size_t)n, top, sizeof(int32_t) * (size_t)n);
+      (*n_levels)++;
+    }
     int shrunk = nn < cn;
     /* the super-vertex graph becomes the current graph */
     memcpy(off, off2, sizeof(int64_t) * (size_t)(nn + 1));
@@ -578,4 +587,20 @@ int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t*
   free(w2); free(idx2); free(off2); free(map); free(csize); free(Sig); free(C);
   free(w); free(idx); free(off); free(K);
   return 0;
+}
+
+int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
+            int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
+            int32_t substeps, int32_t nthreads, int32_t* top, orc_result* res) {
+  return run_impl(n, off0, idx0, w0, mode, a, b, max_it, max_pass, substeps, nthreads, top, res,
+                  NULL, 0, NULL);
+}
+
+/* orc_run that also keeps every level of the hierarchy (levels[max_levels * n]). */
+int orc_run_levels(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
+                   int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
+                   int32_t substeps, int32_t nthreads, int32_t* top, orc_result* res,
+                   int32_t* levels, int32_t max_levels, int32_t* n_levels) {
+  return run_impl(n, off0, idx0, w0, mode, a, b, max_it, max_pass, substeps, nthreads, top, res,
+                  levels, max_levels, n_levels);
 }

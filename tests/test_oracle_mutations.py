@@ -39,6 +39,10 @@ MUTATIONS = {
     "step_moves_unlisted": ("int64_t i = verts ? verts[t] : t;\n      decision",
                             "int64_t i = verts ? (verts[t] + 1) % n : t;\n      decision"),
     "async_no_sigma_update": ("Sig[c] += K[i];\n      csize[d] -= 1;", "csize[d] -= 1;"),
+    "level_records_pass_map": ("memcpy(levels + (size_t)(*n_levels) * (size_t)n, top,",
+                               "memcpy(levels + (size_t)(*n_levels) * (size_t)n, map,"),
+    "level_cap_off_by_one": ("if (levels && n_levels && *n_levels < max_levels) {",
+                             "if (levels && n_levels && *n_levels + 1 < max_levels) {"),
 }
 
 
@@ -60,6 +64,8 @@ def battery():
     P.test_worked_example_two_triangles()
     P.test_single_edge_run()
     P.test_ring_of_cliques_recovered()
+    P.test_levels_ring_of_k4_hand_derived()
+    P.test_levels_edge_cases()
 
 
 def test_battery_passes_on_committed_oracle():

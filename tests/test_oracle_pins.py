@@ -568,3 +568,73 @@ def test_quality_sync_vs_async_sbm10k():
     qa = ra["qnum_pass"]
     assert all(qa[p + 1] >= qa[p] for p in range(len(qa) - 1))
     assert rs["q"] >= ra["q"] - 0.01
+
+
+# ----------------------------------------------------------------------------------------------
+# the hierarchy: membership of the input vertices after each aggregation
+
+
+def check_levels(g: O.Graph, top, res):
+    L = res["levels"]
+    W = res["W"]
+    assert L.shape[1] == g.n
+    if W == 0 or len(L) == 0:
+        return
+    # the last level is the returned membership
+    assert (L[-1] == top).all()
+    for l in range(len(L)):
+        k = int(L[l].max()) + 1
+        # dense labels; the l-th aggregation leaves the vertex count the next pass starts with
+        assert sorted(set(L[l].tolist())) == list(range(k))
+        if l + 1 < res["passes"]:
+            assert k == res["n_pass"][l + 1]
+        # aggregation keeps Q: the l-th level, evaluated on the INPUT graph with the pairwise
+        # definition, has the Q reported after the l-th local-moving phase
+        assert q_pairwise(g, L[l]) == Fraction(res["qnum_pass"][l], W * W), l
+        if l > 0:
+            # each community of level l-1 lies inside one community of level l
+            pairs = set(zip(L[l - 1].tolist(), L[l].tolist()))
+            assert len(pairs) == len(set(L[l - 1].tolist()))
+
+
+@pytest.mark.parametrize("mode,sub", [("sync", 1), ("sync", 8), ("async", 1)])
+def test_levels_invariants(mode, sub):
+    graphs = small_graphs() + [O.Graph.from_csr(ring_of_cliques(30, 3)),
+                               O.Graph.from_csr(ring_of_cliques(64, 3))]
+    for g in graphs:
+        top, res = O.run(g, mode, substeps=sub, levels=True)
+        plain, res2 = O.run(g, mode, substeps=sub)
+        assert (plain == top).all() and res2["qnum"] == res["qnum"]
+        check_levels(g, top, res)
+        # an aggregation per pass, except a last pass in which nothing moved
+        assert len(res["levels"]) in (res["passes"] - 1, res["passes"])
+
+
+def test_levels_ring_of_k4_hand_derived():
+    """Ring of 16 K4 cliques, asynchronous rule. Pass 0 gathers each clique (as in the (8, 5)
+    ring). Pass 1 runs on a ring of 16 super-vertices with self-loop weight 12, ring weight 1,
+    K = 14, W = 224: vertex 0 gains 224*1 - 14*14 = 28 towards either ring neighbour and takes
+    the smaller id 1; vertex 1 then sees 28 for staying and 28 for moving on, so it stays;
+    vertex 2 sees 224 - 14*28 < 0 towards {0, 1} and 28 towards 3, and so on: the cliques pair
+    up as {2j, 2j+1}. Pass 2: merging two pairs gains 224*1 - 28*28 < 0, nothing moves.
+    Qnum (= W^2 Q) of the two levels: 16 (12*224 - 14^2) and 8 (26*224 - 28^2)."""
+    g = O.Graph.from_csr(ring_of_cliques(16, 4))
+    top, res = O.run(g, "async", levels=True)
+    v = np.arange(64)
+    L = res["levels"]
+    assert len(L) == 2 and res["passes"] == 3
+    assert (L[0] == v // 4).all()
+    assert (L[1] == v // 8).all()
+    assert res["qnum_pass"][:2] == [16 * (12 * 224 - 14 ** 2), 8 * (26 * 224 - 28 ** 2)]
+    check_levels(g, top, res)
+
+
+def test_levels_edge_cases():
+    # no arcs: no level; a single edge: one level joining the two ends
+    g = O.Graph.from_csr(single_edge())
+    top, res = O.run(g, "sync", levels=True)
+    assert res["levels"].tolist() == [[0, 0]]
+    # max_passes = 1 caps the hierarchy at one level
+    g = O.Graph.from_csr(ring_of_cliques(64, 3))
+    top, res = O.run(g, "sync", max_passes=1, levels=True)
+    assert len(res["levels"]) == 1 and (res["levels"][0] == top).all()
