@@ -189,6 +189,19 @@ uint64_t louvain_workspace_bytes(const lv_ctx* ctx);
 lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_t* membership,
                       lv_result* res, void* stream);
 
+/* louvain_run that also returns the whole dendrogram. In section 3.2 the communities a pass
+ * finds become the vertices of the next pass, so every aggregation yields a coarser partition
+ * of the input vertices that nests the previous one.
+ * levels: [max_levels * n] out (device, caller-owned): levels[l*n + v] is the community of input
+ * vertex v after the l-th aggregation (dense ids, l = 0 the finest); rows at and beyond
+ * *n_levels are not written. The last written row equals membership; no row is written when no
+ * pass aggregated. max_levels must be >= p->max_passes (else LV_EINVAL, nothing run), which
+ * bounds the aggregations. n_levels (host) out: rows written. Other arguments and errors as
+ * louvain_run; the dendrogram adds one n-int device copy per aggregation. */
+lv_status louvain_run_levels(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
+                             int32_t* membership, int32_t* levels, int32_t max_levels,
+                             int32_t* n_levels, lv_result* res, void* stream);
+
 /* One local-moving phase (section 3.2) on an arbitrary state, under pass p's tolerance
  * (max_iterations = 1 runs exactly one synchronous iteration: the per-iteration parity entry).
  * K: [n] row sums, or NULL to compute them. W: total arc weight, or 0 to compute it.

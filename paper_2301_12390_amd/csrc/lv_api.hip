@@ -838,14 +838,21 @@ lv_status louvain_aggregate(lv_ctx* ctx, const lv_graph* g, const int32_t* C, in
   return LV_OK;
 }
 
-lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_t* membership,
-                      lv_result* res, void* stream) {
+}  // extern "C"
+
+// The whole method; levels (may be NULL) receives a copy of the membership after every
+// aggregation, *n_levels counting them.
+static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
+                            int32_t* membership, int32_t* levels, int32_t max_levels,
+                            int32_t* n_levels, lv_result* res, void* stream) {
   if (!ctx) return LV_EINVAL;
   const auto t_start = std::chrono::steady_clock::now();
   ctx->err.clear();
   HIPCHK(hipSetDevice(ctx->device));
   CHK(check_params(ctx, p));
   if (!res) return fail(ctx, LV_EINVAL, "res is NULL");
+  int32_t nlev = 0;
+  if (n_levels) *n_levels = 0;
   ctx->part_shift = (p->flags & LV_SMALL_PARTS) ? kSmallPartShift : 0;
   memset(res, 0, sizeof(*res));
   hipStream_t s = (hipStream_t)stream;
@@ -853,6 +860,7 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
   CHK(import_graph(ctx, g, (p->flags & LV_VALIDATE) != 0, s, &g0));
   const int64_t n0 = g0.n;
   if (n0 > 0 && !membership) return fail(ctx, LV_EINVAL, "membership is NULL");
+  if (n_levels && n0 > 0 && !levels) return fail(ctx, LV_EINVAL, "levels is NULL");
   res->n_communities = n0;
   if (n0 == 0) return LV_OK;
   const bool trace = (p->flags & LV_TRACE) != 0;
@@ -935,6 +943,11 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
                   (p->flags & LV_FORCE_WIDE) == 0));
     HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
     HIPCHK(lv::compose_membership(membership, n0, map, s));
+    if (levels && nlev < max_levels) {
+      HIPCHK(hipMemcpyAsync(levels + (size_t)nlev * (size_t)n0, membership,
+                            sizeof(int32_t) * (size_t)n0, hipMemcpyDeviceToDevice, s));
+      nlev++;
+    }
     if (trace) {
       HIPCHK(hipEventRecord(ctx->ev[EV_AGG + 1], s));
       HIPCHK(hipEventSynchronize(ctx->ev[EV_AGG + 1]));
@@ -974,9 +987,30 @@ lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_
   res->q_num = to_i128(qnum);
   res->q = q_of(qnum, W);
   HIPCHK(hipStreamSynchronize(s));
+  if (n_levels) *n_levels = nlev;
   res->total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
                                                            t_start).count();
   return LV_OK;
+}
+
+extern "C" {
+
+lv_status louvain_run(lv_ctx* ctx, const lv_graph* g, const lv_params* p, int32_t* membership,
+                      lv_result* res, void* stream) {
+  return run_single(ctx, g, p, membership, nullptr, 0, nullptr, res, stream);
+}
+
+lv_status louvain_run_levels(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
+                             int32_t* membership, int32_t* levels, int32_t max_levels,
+                             int32_t* n_levels, lv_result* res, void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  if (!n_levels) return fail(ctx, LV_EINVAL, "n_levels is NULL");
+  *n_levels = 0;
+  if (!p) return fail(ctx, LV_EINVAL, "params is NULL");
+  if (max_levels < p->max_passes)
+    return fail(ctx, LV_EINVAL, "max_levels is below max_passes");
+  return run_single(ctx, g, p, membership, levels, max_levels, n_levels, res, stream);
 }
 
 // Many graphs in one run: the packed union goes through the same kernels as one graph, with each

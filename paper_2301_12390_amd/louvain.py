@@ -141,6 +141,9 @@ SIGNATURES = {
     "louvain_workspace_bytes": (ctypes.c_uint64, [_P]),
     "louvain_run": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.POINTER(LvParams), _P,
                                    ctypes.POINTER(LvResult), _P]),
+    "louvain_run_levels": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.POINTER(LvParams),
+                                          _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(LvResult), _P]),
     "louvain_move": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.c_uint64,
                                     ctypes.c_int32, ctypes.POINTER(LvParams), _P, _P, _P,
                                     ctypes.POINTER(LvMoveStats), _P]),
@@ -299,6 +302,25 @@ class Louvain:
                                   ctypes.byref(r), _stream())
         self._check(st)
         return membership[:g.n], result_dict(r)
+
+    def run_levels(self, g, tolerance_exp10=2, decline_exp10=1, max_iterations=20,
+                   max_passes=10, substeps=DEFAULT_SUBSTEPS, flags=0):
+        """Whole method keeping the dendrogram. Returns (membership int32 tensor [n], levels
+        int32 tensor [L, n] with the membership after each of the L aggregations, result
+        dict)."""
+        gs = graph_struct(g)
+        dev = g.indices.device
+        membership = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+        levels = torch.empty((max_passes, max(g.n, 1)), dtype=torch.int32, device=dev)
+        p = params_struct(tolerance_exp10, decline_exp10, max_iterations, max_passes, substeps,
+                          flags)
+        r = self._result
+        nl = ctypes.c_int32(0)
+        st = self.lib.louvain_run_levels(self.h, ctypes.byref(gs), ctypes.byref(p),
+                                         _ptr(membership), _ptr(levels), max_passes,
+                                         ctypes.byref(nl), ctypes.byref(r), _stream())
+        self._check(st)
+        return membership[:g.n], levels[:nl.value, :g.n], result_dict(r)
 
     def run_batched(self, packed, vptr, aptr, tolerance_exp10=2, decline_exp10=1,
                     max_iterations=20, max_passes=10, substeps=DEFAULT_SUBSTEPS, flags=0,

@@ -85,6 +85,34 @@ def test_rmat25_run_modularity_and_labels(lv, rmat25, rmat25_iter0):
 
 
 @pytest.mark.timeout(600)
+def test_rmat25_levels_properties(lv, rmat25):
+    """The dendrogram at full size, through properties that hold at any size: each level's
+    modularity on the input graph (oracle) equals the run's Q after that pass (aggregation keeps
+    Q), levels nest, the last level is the membership of louvain_run."""
+    g, og = rmat25
+    memb, res = lv.run(g, substeps=K_CLASSES)
+    memb2, levels, res2 = lv.run_levels(g, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    assert res2["qnum"] == res["qnum"] and res2["qnum_pass"] == res["qnum_pass"]
+    m = memb.cpu().numpy()
+    assert np.array_equal(memb2.cpu().numpy(), m)
+    L = levels.cpu().numpy()
+    assert L.shape[0] >= 1 and np.array_equal(L[-1], m)
+    for l in range(L.shape[0]):
+        print(f"level {l}: oracle modularity", flush=True)
+        qnum, W, _ = O.modularity(og, L[l])
+        assert qnum == res["qnum_pass"][l] and W == res["W"], l
+        k = int(L[l].max()) + 1
+        if l + 1 < res["passes"]:
+            assert k == res["n_pass"][l + 1]
+        if l > 0:
+            # nesting: the finer label determines the coarser one
+            coarse = np.full(int(L[l - 1].max()) + 1, -1, dtype=np.int64)
+            coarse[L[l - 1]] = L[l]
+            assert np.array_equal(coarse[L[l - 1]], L[l]), l
+
+
+@pytest.mark.timeout(600)
 def test_rmat25_aggregate(lv, rmat25, rmat25_iter0):
     g, og = rmat25
     st0, st, _ = rmat25_iter0
@@ -147,7 +175,7 @@ def rmat22(gpu_device):
 def test_rmat22_whole_run_exact(lv, rmat22):
     g, og = rmat22
     print("oracle: whole synchronous run on rmat22", flush=True)
-    top, ref = O.run(og, "sync", substeps=K_CLASSES)
+    top, ref = O.run(og, "sync", substeps=K_CLASSES, levels=True)
     memb, res = lv.run(g, substeps=K_CLASSES)
     torch.cuda.synchronize()
     assert np.array_equal(memb.cpu().numpy(), top)
@@ -155,6 +183,14 @@ def test_rmat22_whole_run_exact(lv, rmat22):
     assert [t["S"] for t in res["trace"]] == ref["trace_S"]
     assert [t["moved"] for t in res["trace"]] == ref["trace_moved"]
     assert res["qnum_pass"] == ref["qnum_pass"] and res["nnz_pass"] == ref["nnz_pass"]
+    # the dendrogram, level by level
+    memb2, levels, res2 = lv.run_levels(g, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    assert np.array_equal(memb2.cpu().numpy(), top) and res2["qnum"] == ref["qnum"]
+    L = levels.cpu().numpy()
+    assert L.shape == ref["levels"].shape
+    for l in range(L.shape[0]):
+        assert np.array_equal(L[l], ref["levels"][l]), l
 
 
 @pytest.mark.timeout(900)

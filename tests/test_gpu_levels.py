@@ -1,0 +1,123 @@
+"""GPU parity of the dendrogram (louvain_run_levels) against the oracle's per-level membership.
+
+Every level, the level count, the final membership and the run's exact results must equal the
+oracle's run with the same rule and parameters; louvain_run_levels must also agree with
+louvain_run on the same input.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from graphgen import ring_of_cliques, sbm
+from graphgen.csr import Csr
+
+from .test_gpu_parity import CORPUS, HUB_IDS, HUBS, IDS, LV_FORCE_WIDE, LV_SMALL_PARTS
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lv(gpu_device):
+    from paper_2301_12390_amd import Louvain, build as B
+    if not __import__("os").path.exists(B.LIB):
+        B.build()
+    ctx = Louvain(0)
+    yield ctx
+    ctx.close()
+
+
+def check_levels(lv, g, flags=0, substeps=8, **kw):
+    og = O.Graph.from_csr(g)
+    okw = {{"tolerance_exp10": "a", "decline_exp10": "b"}.get(k, k): v for k, v in kw.items()}
+    top, ref = O.run(og, "sync", substeps=substeps, levels=True, **okw)
+    dg = g.to("cuda:0")
+    memb, levels, res = lv.run_levels(dg, flags=flags, substeps=substeps, **kw)
+    memb1, res1 = lv.run(dg, flags=flags, substeps=substeps, **kw)
+    torch.cuda.synchronize()
+    L = levels.cpu().numpy()
+    assert L.shape == ref["levels"].shape, (g.name, L.shape, ref["levels"].shape)
+    for l in range(L.shape[0]):
+        assert np.array_equal(L[l], ref["levels"][l]), (g.name, l)
+    assert np.array_equal(memb.cpu().numpy(), top)
+    assert np.array_equal(memb1.cpu().numpy(), top)
+    for key in ("qnum", "W", "passes", "iterations", "qnum_pass", "n_pass", "nnz_pass"):
+        assert res[key] == ref[key], key
+        assert res1[key] == res[key], key
+    return L, res
+
+
+@pytest.mark.parametrize("K", [1, 8])
+@pytest.mark.parametrize("g", CORPUS, ids=IDS)
+def test_levels(lv, g, K):
+    check_levels(lv, g, substeps=K)
+
+
+@pytest.mark.parametrize("flags", [0, LV_SMALL_PARTS | LV_FORCE_WIDE])
+@pytest.mark.parametrize("gi", [0, 1], ids=HUB_IDS)
+def test_levels_hub_graphs(lv, gi, flags):
+    check_levels(lv, HUBS[gi], flags=flags)
+
+
+def test_levels_deep_hierarchy(lv):
+    # rings of small cliques aggregate several times (3 to 4 levels)
+    for g in [ring_of_cliques(64, 3), ring_of_cliques(200, 3), ring_of_cliques(16, 4)]:
+        for K in (1, 8):
+            L, res = check_levels(lv, g, substeps=K)
+            assert L.shape[0] >= 2
+
+
+def test_levels_capped_by_max_passes(lv):
+    g = sbm(3000, 30, 8.0, 2.0, seed=2, weights=(1, 16))
+    for mp in (1, 2):
+        L, res = check_levels(lv, g, max_passes=mp)
+        assert L.shape[0] <= mp
+
+
+def test_levels_parameters(lv):
+    g = sbm(4000, 40, 8.0, 2.0, seed=9, weights=(1, 16))
+    for kw in [dict(tolerance_exp10=0), dict(tolerance_exp10=6, decline_exp10=2)]:
+        check_levels(lv, g, **kw)
+
+
+def test_levels_empty_and_edgeless(lv):
+    dev = "cuda:0"
+    for n in (0, 5):
+        g = Csr(n, torch.zeros(n + 1, dtype=torch.int32, device=dev),
+                torch.zeros(0, dtype=torch.int32, device=dev),
+                torch.zeros(0, dtype=torch.int32, device=dev))
+        memb, levels, res = lv.run_levels(g)
+        assert levels.shape[0] == 0 and memb.cpu().tolist() == list(range(n))
+
+
+def test_levels_errors(lv):
+    """max_levels below max_passes and a NULL n_levels are refused before anything runs."""
+    from paper_2301_12390_amd.louvain import graph_struct, params_struct, _ptr
+    from graphgen import two_triangles
+    g = two_triangles().to("cuda:0")
+    gs = graph_struct(g)
+    p = params_struct(max_passes=4)
+    memb = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    levels = torch.full((4, g.n), -7, dtype=torch.int32, device="cuda:0")
+    nl = ctypes.c_int32(99)
+    st = lv.lib.louvain_run_levels(lv.h, ctypes.byref(gs), ctypes.byref(p), _ptr(memb),
+                                   _ptr(levels), 3, ctypes.byref(nl), ctypes.byref(lv._result),
+                                   None)
+    assert st != 0 and nl.value == 0
+    assert b"max_levels" in lv.lib.louvain_last_error(lv.h)
+    st = lv.lib.louvain_run_levels(lv.h, ctypes.byref(gs), ctypes.byref(p), _ptr(memb),
+                                   _ptr(levels), 4, None, ctypes.byref(lv._result), None)
+    assert st != 0
+    torch.cuda.synchronize()
+    assert (levels.cpu() == -7).all()
+    # the context stays usable; two triangles aggregate once
+    st = lv.lib.louvain_run_levels(lv.h, ctypes.byref(gs), ctypes.byref(p), _ptr(memb),
+                                   _ptr(levels), 4, ctypes.byref(nl), ctypes.byref(lv._result),
+                                   None)
+    torch.cuda.synchronize()
+    assert st == 0 and nl.value == 1
+    assert levels[0].cpu().tolist() == [0, 0, 0, 1, 1, 1]
+    assert (levels[1:].cpu() == -7).all()
