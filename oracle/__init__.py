@@ -284,3 +284,63 @@ def run(g: Graph, mode: str = "sync", a: int = 2, b: int = 1, max_iterations: in
     if levels:
         res["levels"] = lv[:nl.value, :g.n].copy()
     return top[:g.n].copy(), res
+
+
+# ----------------------------------------------------------------------------------------------
+# graph preparation (section 3.1.2 and Table 1): edge list -> undirected weighted CSR
+
+PREP_SYM = 0x1
+PREP_LOOPS = 0x2
+PREP_MAX = 0x4
+
+
+def prepare(n: int, src, dst, w=None, flags: int = PREP_SYM | PREP_LOOPS):
+    """Edge list (int32 src, dst; uint32 weights or None for ones) -> (off int64[n+1],
+    idx int32[nnz], w uint64[nnz]), rows sorted by neighbour, repeated arcs combined (sum, or
+    max with PREP_MAX). Raises ValueError on an endpoint outside [0, n) or a zero weight."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    m = src.size
+    cap = m * (2 if flags & PREP_SYM else 1) + (n if flags & PREP_LOOPS else 0)
+    off = np.zeros(n + 1, dtype=np.int64)
+    idx = np.zeros(max(cap, 1), dtype=np.int32)
+    wo = np.zeros(max(cap, 1), dtype=np.uint64)
+    wp = None
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.uint32)
+        wp = _p(w)
+    f = lib().orc_prepare
+    f.restype = ctypes.c_int64
+    nnz = f(ctypes.c_int64(n), ctypes.c_int64(m), _p(src), _p(dst), wp, ctypes.c_uint32(flags),
+            _p(off), _p(idx), _p(wo))
+    if nnz < 0:
+        raise ValueError("edge endpoint out of range or zero weight")
+    return off, idx[:nnz].copy(), wo[:nnz].copy()
+
+
+def prepare_row(n: int, src, dst, w, flags: int, r: int):
+    """Row r of prepare() computed alone from the edge list (numpy, O(m) per row): the
+    neighbours of r with their combined weights, ascending. For checking sampled rows of a
+    graph too large to prepare on the host."""
+    src = np.asarray(src)
+    dst = np.asarray(dst)
+    wv = np.ones(src.size, dtype=np.uint64) if w is None else np.asarray(w).astype(np.uint64)
+    out_sel = src == r
+    nb = [dst[out_sel].astype(np.int64)]
+    ws = [wv[out_sel]]
+    if flags & PREP_SYM:
+        in_sel = (dst == r) & (src != r)
+        nb.append(src[in_sel].astype(np.int64))
+        ws.append(wv[in_sel])
+    if flags & PREP_LOOPS:
+        nb.append(np.array([r], dtype=np.int64))
+        ws.append(np.ones(1, dtype=np.uint64))
+    nb = np.concatenate(nb)
+    ws = np.concatenate(ws)
+    uniq, inv = np.unique(nb, return_inverse=True)
+    acc = np.zeros(uniq.size, dtype=np.uint64)
+    if flags & PREP_MAX:
+        np.maximum.at(acc, inv, ws)
+    else:
+        np.add.at(acc, inv, ws)
+    return uniq.astype(np.int32), acc

@@ -41,6 +41,14 @@ MUTATIONS = {
     "async_no_sigma_update": ("Sig[c] += K[i];\n      csize[d] -= 1;", "csize[d] -= 1;"),
     "level_records_pass_map": ("memcpy(levels + (size_t)(*n_levels) * (size_t)n, top,",
                                "memcpy(levels + (size_t)(*n_levels) * (size_t)n, map,"),
+    "prep_reverses_loops": ("if ((flags & ORC_PREP_SYM) && src[e] != dst[e]) {",
+                            "if ((flags & ORC_PREP_SYM)) {"),
+    "prep_max_sums": ("if (flags & ORC_PREP_MAX) {\n        if (a[i].w > wout[nnz - 1])",
+                      "if (0) {\n        if (a[i].w > wout[nnz - 1])"),
+    "prep_merges_across_rows": ("idx[nnz - 1] == a[i].v && i > 0 && a[i - 1].u == a[i].u",
+                                "idx[nnz - 1] == a[i].v"),
+    "prep_loop_weight_two": ("a[k].v = (int32_t)v; a[k].w = 1; k++;",
+                             "a[k].v = (int32_t)v; a[k].w = 2; k++;"),
     "level_cap_off_by_one": ("if (levels && n_levels && *n_levels < max_levels) {",
                              "if (levels && n_levels && *n_levels + 1 < max_levels) {"),
 }
@@ -66,6 +74,10 @@ def battery():
     P.test_ring_of_cliques_recovered()
     P.test_levels_ring_of_k4_hand_derived()
     P.test_levels_edge_cases()
+    from . import test_oracle_prepare as PP
+    PP.test_golden_small()
+    for f in PP.FLAG_SETS:
+        PP.test_matches_dense_definition(f)
 
 
 def test_battery_passes_on_committed_oracle():
