@@ -15,6 +15,7 @@ from .rng import splitmix64_mix, draw, stream_key  # noqa: F401
 from .csr import Csr, csr_from_arcs, csr_from_edges, csr_sha256, pack_graphs  # noqa: F401
 from .generators import (  # noqa: F401
     rmat,
+    rmat_edges,
     sbm,
     lattice_shortcuts,
     ring_of_cliques,

@@ -40,20 +40,12 @@ def _pair_weights(key: int, n: int, wmin: int, wmax: int):
     return fn
 
 
-def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
-         seed: int = 1, permute: bool = True, weights=(1, 1), offsets_dtype=torch.int32,
-         device="cpu", chunk: int = 1 << 24, n: int = None) -> Csr:
-    """R-MAT graph (Chakrabarti, Zhan, Faloutsos 2004) as a symmetric simple CSR.
-
-    ``edge_factor * 2^scale`` directed endpoint pairs are drawn; each of the ``scale`` levels
-    picks a quadrant with probabilities (a, b, c, 1-a-b-c) by comparing a 32-bit draw with
-    integer thresholds. Ids are then relabelled by a seeded random permutation (Graph500
-    practice), self-loops are dropped, edges are symmetrised and repeats removed. Weights are
-    drawn per unordered pair, uniform in ``weights = (wmin, wmax)``.
-
-    If ``n`` is given and is not a power of two, endpoints >= n are redrawn at the next counter
-    (the graph then has n vertices and ``scale = ceil(log2 n)``).
-    """
+def rmat_edges(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
+               c: float = 0.19, seed: int = 1, permute: bool = True, device="cpu",
+               chunk: int = 1 << 24, n: int = None):
+    """The raw R-MAT edge list behind ``rmat``: (n, u, v) with int64 endpoint tensors of
+    ``edge_factor * n`` drawn pairs, self-loops and repeats included (an edge-list file as
+    graph preparation receives it)."""
     N = 1 << scale
     if n is None:
         n = N
@@ -105,6 +97,24 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
         u = newid[u]
         v = newid[v]
         del newid
+    return n, u, v
+
+
+def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+         seed: int = 1, permute: bool = True, weights=(1, 1), offsets_dtype=torch.int32,
+         device="cpu", chunk: int = 1 << 24, n: int = None) -> Csr:
+    """R-MAT graph (Chakrabarti, Zhan, Faloutsos 2004) as a symmetric simple CSR.
+
+    ``edge_factor * 2^scale`` directed endpoint pairs are drawn; each of the ``scale`` levels
+    picks a quadrant with probabilities (a, b, c, 1-a-b-c) by comparing a 32-bit draw with
+    integer thresholds. Ids are then relabelled by a seeded random permutation (Graph500
+    practice), self-loops are dropped, edges are symmetrised and repeats removed. Weights are
+    drawn per unordered pair, uniform in ``weights = (wmin, wmax)``.
+
+    If ``n`` is given and is not a power of two, endpoints >= n are redrawn at the next counter
+    (the graph then has n vertices and ``scale = ceil(log2 n)``).
+    """
+    n, u, v = rmat_edges(scale, edge_factor, a, b, c, seed, permute, device, chunk, n)
     wfn = None
     if weights != (1, 1):
         wfn = _pair_weights(stream_key(seed, _T_WEIGHT, scale), n, weights[0], weights[1])

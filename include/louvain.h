@@ -246,6 +246,34 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
 lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, lv_i128* q_num,
                              uint64_t* W, double* q, void* stream);
 
+/* Graph preparation flags of louvain_prepare. */
+#define LV_PREP_SYMMETRIZE 0x1u /* add the reverse (v, u, w) of every edge (u, v, w), u != v */
+#define LV_PREP_SELF_LOOPS 0x2u /* add a self-loop of weight 1 on every vertex */
+#define LV_PREP_MAX 0x4u        /* repeated arcs combine by max (default: by sum) */
+
+/* Graph preparation (section 3.1.2 and Table 1: the inputs of the method are edge lists made
+ * undirected by adding every edge's reverse, with unit weights and a self-loop on every
+ * vertex): turns an edge list into the symmetric CSR every function above takes.
+ * src, dst: [m] int32 endpoints in [0, n). weights: [m] uint32 >= 1, or NULL for all ones.
+ * The arcs are the edges, their reverses (LV_PREP_SYMMETRIZE; a self-loop edge stays one arc)
+ * and one loop per vertex (LV_PREP_SELF_LOOPS); arcs with equal (source, neighbour) combine
+ * into one, by sum or, with LV_PREP_MAX, by max (so LV_PREP_SYMMETRIZE | LV_PREP_SELF_LOOPS |
+ * LV_PREP_MAX with NULL weights gives the paper's unit-weight graphs).
+ * Outputs: offsets_out [n+1] (int64 if offsets_64_out else int32), indices_out [nnz] and
+ * weights_out [nnz] (uint64 if weights_64_out else uint32), rows in ascending neighbour order.
+ * capacity: entries available in indices_out and weights_out. nnz_out (host): arcs of the
+ * prepared graph. With indices_out and weights_out both NULL the call only counts (*nnz_out).
+ * Errors: LV_EINVAL for a bad argument or flag, an endpoint outside [0, n), a zero weight, or
+ * capacity < nnz (then *nnz_out holds the needed size); LV_EOVERFLOW for n >= 2^31, more than
+ * 2^40 arcs, nnz >= 2^31 with int32 offsets, or a combined weight above 2^32-1 with uint32
+ * weights. Workspace: about 24 bytes per arc before combining (sort keys and weights, double
+ * buffered). */
+lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
+                          const int32_t* dst, const uint32_t* weights, uint32_t flags,
+                          void* offsets_out, int32_t offsets_64_out, int32_t* indices_out,
+                          void* weights_out, int32_t weights_64_out, int64_t capacity,
+                          int64_t* nnz_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,10 +8,15 @@ ABI in ``include/louvain.h``. ``louvain`` is the Python binding.
 
 from .louvain import (  # noqa: F401
     LV_FORCE_WIDE,
+    LV_PREP_MAX,
+    LV_PREP_PAPER,
+    LV_PREP_SELF_LOOPS,
+    LV_PREP_SYMMETRIZE,
     LV_SMALL_PARTS,
     LV_TRACE,
     LV_VALIDATE,
     Louvain,
     LouvainError,
+    PreparedGraph,
     load_library,
 )

@@ -25,7 +25,8 @@ enum SlotId {
   S_HUBARR, S_PK, S_PV, S_HOFF, S_NFLUSH, S_PARTIAL, S_A, S_ASTART, S_NEWID, S_CURSOR,
   S_OLDLABEL, S_DCOUNT, S_ABASE, S_TKEY, S_TW, S_GOFF0, S_GIDX0, S_GW0, S_GOFF1, S_GIDX1, S_GW1,
   S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
-  S_REC, S_GID0, S_GIDA, S_GIDB, S_GBASE, S_GWORDS, S_GACT, S_APTR, S_COUNT_SLOTS
+  S_REC, S_GID0, S_GIDA, S_GIDB, S_GBASE, S_GWORDS, S_GACT, S_APTR, S_PKEY0, S_PKEY1, S_PVAL0,
+  S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PW, S_POFF, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -1244,6 +1245,123 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     per_graph[g].q_num = to_i128(qnum[g]);
     per_graph[g].q = q_of(qnum[g], W[g]);
   }
+  return LV_OK;
+}
+
+// Graph preparation: expand the edge list into arcs, radix-sort them by (source, neighbour),
+// combine runs of equal arcs and write the CSR.
+lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
+                          const int32_t* dst, const uint32_t* weights, uint32_t flags,
+                          void* offsets_out, int32_t offsets_64_out, int32_t* indices_out,
+                          void* weights_out, int32_t weights_64_out, int64_t capacity,
+                          int64_t* nnz_out, void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  if (!nnz_out) return fail(ctx, LV_EINVAL, "nnz_out is NULL");
+  *nnz_out = 0;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (n < 0 || m < 0 || capacity < 0) return fail(ctx, LV_EINVAL, "negative size");
+  if (n >= ((int64_t)1 << 31)) return fail(ctx, LV_EOVERFLOW, "n must be below 2^31");
+  if (flags & ~(LV_PREP_SYMMETRIZE | LV_PREP_SELF_LOOPS | LV_PREP_MAX))
+    return fail(ctx, LV_EINVAL, "unknown preparation flag");
+  if (m > 0 && (!src || !dst)) return fail(ctx, LV_EINVAL, "src or dst is NULL");
+  const bool query = !indices_out && !weights_out;
+  if (!query && (!offsets_out || !indices_out || !weights_out))
+    return fail(ctx, LV_EINVAL, "offsets_out, indices_out or weights_out is NULL");
+  const bool sym = (flags & LV_PREP_SYMMETRIZE) != 0, loops = (flags & LV_PREP_SELF_LOOPS) != 0;
+  if (m > ((int64_t)1 << 60)) return fail(ctx, LV_EOVERFLOW, "too many edges");
+  const int64_t N = m * (sym ? 2 : 1) + (loops ? n : 0);
+  if (N >= ((int64_t)1 << 40) || N / lv::kPrepTile >= ((int64_t)1 << 31))
+    return fail(ctx, LV_EOVERFLOW, "too many arcs");
+  if (N == 0) {
+    if (!query) {
+      if (offsets_64_out)
+        HIPCHK(lv::fill_i64((int64_t*)offsets_out, 0, n + 1, s));
+      else
+        HIPCHK(lv::fill_i32((int32_t*)offsets_out, 0, n + 1, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    return LV_OK;
+  }
+  const int b = lv::prep_key_bits(n);
+  const int64_t ntiles = (N + lv::kPrepTile - 1) / lv::kPrepTile;
+  uint64_t* k0 = nullptr;
+  uint64_t* k1 = nullptr;
+  uint32_t* v0 = nullptr;
+  uint32_t* v1 = nullptr;
+  unsigned int* bad = nullptr;
+  CHK(wst(ctx, S_PKEY0, N, &k0));
+  CHK(wst(ctx, S_PKEY1, N, &k1));
+  CHK(wst(ctx, S_PVAL0, N, &v0));
+  CHK(wst(ctx, S_PVAL1, N, &v1));
+  CHK(wst(ctx, S_BAD, 1, &bad));
+  HIPCHK(lv::fill_i32((int32_t*)bad, 0, 1, s));
+  HIPCHK(lv::prep_expand(n, m, src, dst, weights, flags, b, k0, v0, bad, s));
+  unsigned int hb = 0;
+  HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hb & 1u) return fail(ctx, LV_EINVAL, "an edge endpoint is out of range");
+  if (hb & 2u) return fail(ctx, LV_EINVAL, "a weight is zero");
+  // LSD passes over the 2b key bits, digits as even as possible
+  const int B = 2 * b;
+  const int passes = (B + lv::kRadixBits - 1) / lv::kRadixBits;
+  int32_t* hist = nullptr;
+  int64_t* offs = nullptr;
+  int64_t* scanp = nullptr;
+  const int64_t hist_n = ((int64_t)1 << lv::kRadixBits) * ntiles;
+  CHK(wst(ctx, S_PHIST, hist_n, &hist));
+  CHK(wst(ctx, S_POFFS, hist_n + 1, &offs));
+  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(hist_n + 1) + 1, &scanp));
+  int shift = 0;
+  for (int p = 0; p < passes; p++) {
+    const int bits = (B - shift + (passes - p) - 1) / (passes - p);
+    const int64_t hn = ((int64_t)1 << bits) * ntiles;
+    HIPCHK(lv::radix_hist(k0, N, shift, bits, hist, s));
+    HIPCHK(lv::scan_i32(hist, hn, offs, scanp, s));
+    HIPCHK(lv::radix_scatter(k0, v0, k1, v1, N, shift, bits, offs, s));
+    std::swap(k0, k1);
+    std::swap(v0, v1);
+    shift += bits;
+  }
+  int32_t* theads = nullptr;
+  int64_t* tslot = nullptr;
+  CHK(wst(ctx, S_PTILE, ntiles, &theads));
+  CHK(wst(ctx, S_PSLOT, ntiles + 1, &tslot));
+  HIPCHK(lv::prep_heads(k0, N, theads, s));
+  HIPCHK(lv::scan_i32(theads, ntiles, tslot, scanp, s));
+  int64_t nnz = 0;
+  HIPCHK(hipMemcpyAsync(&nnz, tslot + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *nnz_out = nnz;
+  if (query) return LV_OK;
+  if (capacity < nnz)
+    return fail(ctx, LV_EINVAL, "capacity " + std::to_string(capacity) + " is below the " +
+                                    std::to_string(nnz) + " arcs of the prepared graph");
+  if (!offsets_64_out && nnz >= ((int64_t)1 << 31))
+    return fail(ctx, LV_EOVERFLOW, "nnz >= 2^31 needs int64 offsets");
+  ull* wout = nullptr;
+  if (weights_64_out)
+    wout = (ull*)weights_out;
+  else
+    CHK(wst(ctx, S_PW, nnz, &wout));
+  HIPCHK(lv::fill_u64((uint64_t*)wout, 0, nnz, s));
+  int64_t* off64 = nullptr;
+  if (offsets_64_out)
+    off64 = (int64_t*)offsets_out;
+  else
+    CHK(wst(ctx, S_POFF, n + 1, &off64));
+  HIPCHK(lv::prep_emit(k0, v0, N, n, b, (flags & LV_PREP_MAX) != 0, tslot, off64, indices_out,
+                       wout, s));
+  if (!offsets_64_out) HIPCHK(lv::narrow_offsets(off64, (int32_t*)offsets_out, n + 1, s));
+  if (!weights_64_out) {
+    HIPCHK(lv::fill_i32((int32_t*)bad, 0, 1, s));
+    HIPCHK(lv::prep_narrow_weights(wout, (uint32_t*)weights_out, nnz, bad, s));
+    HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (!weights_64_out && (hb & 4u))
+    return fail(ctx, LV_EOVERFLOW, "a combined weight exceeds 32 bits; use 64-bit weights");
   return LV_OK;
 }
 

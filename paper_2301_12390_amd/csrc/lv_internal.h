@@ -78,6 +78,7 @@ hipError_t validate_graph(const DevGraph& g, unsigned int* bad, hipStream_t s);
 // scan_partial_elems(n) int64 entries.
 int64_t scan_partial_elems(int64_t n);
 hipError_t scan_i64(const int64_t* x, int64_t n, int64_t* out, int64_t* partial, hipStream_t s);
+hipError_t scan_i32(const int32_t* x, int64_t n, int64_t* out, int64_t* partial, hipStream_t s);
 hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* partial,
                           hipStream_t s);  // counts x[i] > 0
 
@@ -217,5 +218,25 @@ hipError_t localize_membership(int32_t* memb, int64_t n, const int32_t* gid0,
 // *bad |= 1 if a graph's first arc is not at aptr[g], |= 2 if an arc leaves its graph.
 hipError_t validate_batch(const DevGraph& g, const int32_t* gid, const int64_t* gbase,
                           const int64_t* aptr, int64_t G, unsigned int* bad, hipStream_t s);
+
+// ---- graph preparation (lv_prep.hip)
+constexpr uint32_t kPrepSym = 0x1u, kPrepLoops = 0x2u, kPrepMax = 0x4u;
+constexpr int64_t kPrepTile = 4096;  // items per workgroup of the sort and emit kernels
+constexpr int kRadixBits = 8;        // largest digit of one sort pass
+int prep_key_bits(int64_t n);        // bits of a vertex id in the sort key
+hipError_t prep_expand(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                       const uint32_t* w, uint32_t flags, int b, uint64_t* keys, uint32_t* vals,
+                       unsigned int* bad, hipStream_t s);
+hipError_t radix_hist(const uint64_t* keys, int64_t N, int shift, int bits, int32_t* hist,
+                      hipStream_t s);
+hipError_t radix_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                         uint32_t* vout, int64_t N, int shift, int bits, const int64_t* offs,
+                         hipStream_t s);
+hipError_t prep_heads(const uint64_t* keys, int64_t N, int32_t* tile_heads, hipStream_t s);
+hipError_t prep_emit(const uint64_t* keys, const uint32_t* vals, int64_t N, int64_t n, int b,
+                     bool combine_max, const int64_t* tile_slot, int64_t* off, int32_t* idx,
+                     unsigned long long* w, hipStream_t s);
+hipError_t prep_narrow_weights(const unsigned long long* w, uint32_t* out, int64_t nnz,
+                               unsigned int* bad, hipStream_t s);
 
 }  // namespace lv

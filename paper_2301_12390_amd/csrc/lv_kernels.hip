@@ -312,6 +312,9 @@ static hipError_t scan_impl(F f, int64_t n, int64_t* out, int64_t* partial, hipS
 hipError_t scan_i64(const int64_t* x, int64_t n, int64_t* out, int64_t* partial, hipStream_t s) {
   return scan_impl(ReadI64{x}, n, out, partial, s);
 }
+hipError_t scan_i32(const int32_t* x, int64_t n, int64_t* out, int64_t* partial, hipStream_t s) {
+  return scan_impl(ReadI32{x}, n, out, partial, s);
+}
 hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* partial,
                           hipStream_t s) {
   return scan_impl(ReadPos{x}, n, out, partial, s);

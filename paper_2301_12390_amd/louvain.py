@@ -6,6 +6,7 @@ been built (``paper_2301_12390_amd.build``); loading fails loudly otherwise.
 """
 
 import ctypes
+from dataclasses import dataclass
 import os
 
 import torch
@@ -144,6 +145,10 @@ SIGNATURES = {
     "louvain_run_levels": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.POINTER(LvParams),
                                           _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(LvResult), _P]),
+    "louvain_prepare": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P, _P,
+                                       ctypes.c_uint32, _P, ctypes.c_int32, _P, _P,
+                                       ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64), _P]),
     "louvain_move": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.c_uint64,
                                     ctypes.c_int32, ctypes.POINTER(LvParams), _P, _P, _P,
                                     ctypes.POINTER(LvMoveStats), _P]),
@@ -214,6 +219,27 @@ def graph_struct(g) -> LvGraph:
 
 
 DEFAULT_SUBSTEPS = 8
+
+LV_PREP_SYMMETRIZE = 0x1
+LV_PREP_SELF_LOOPS = 0x2
+LV_PREP_MAX = 0x4
+# the paper's input graphs: reversed edges, unit weights, a self-loop on every vertex
+LV_PREP_PAPER = LV_PREP_SYMMETRIZE | LV_PREP_SELF_LOOPS | LV_PREP_MAX
+
+
+@dataclass
+class PreparedGraph:
+    """CSR written by louvain_prepare (tensors on the GPU; weights int32 holding uint32 bits or
+    int64 holding uint64)."""
+    n: int
+    offsets: torch.Tensor
+    indices: torch.Tensor
+    weights: torch.Tensor
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.indices.numel())
 
 
 def params_struct(tolerance_exp10=2, decline_exp10=1, max_iterations=20, max_passes=10,
@@ -321,6 +347,47 @@ class Louvain:
                                          ctypes.byref(nl), ctypes.byref(r), _stream())
         self._check(st)
         return membership[:g.n], levels[:nl.value, :g.n], result_dict(r)
+
+    def prepare(self, n, src, dst, weights=None, flags=LV_PREP_PAPER, offsets_64=True,
+                weights_64=False, capacity=None) -> PreparedGraph:
+        """Edge list (int32 GPU tensors src, dst; weights int32 holding uint32 bits, or None for
+        ones) -> the symmetric CSR the method takes. Sizes the outputs with the upper bound
+        m (x2 with LV_PREP_SYMMETRIZE) + n (with LV_PREP_SELF_LOOPS) unless capacity is given,
+        then trims them to the arcs written."""
+        for t in (src, dst) + ((weights,) if weights is not None else ()):
+            if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.int32:
+                raise ValueError("src, dst and weights must be contiguous int32 GPU tensors")
+        m = int(src.numel())
+        if int(dst.numel()) != m or (weights is not None and int(weights.numel()) != m):
+            raise ValueError("src, dst and weights must have the same length")
+        dev = src.device
+        if capacity is None:
+            capacity = m * (2 if flags & LV_PREP_SYMMETRIZE else 1) + (
+                n if flags & LV_PREP_SELF_LOOPS else 0)
+        off = torch.empty(n + 1, dtype=torch.int64 if offsets_64 else torch.int32, device=dev)
+        idx = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        w = torch.empty(max(capacity, 1), dtype=torch.int64 if weights_64 else torch.int32,
+                        device=dev)
+        nnz = ctypes.c_int64(0)
+        st = self.lib.louvain_prepare(self.h, n, m, _ptr(src) if m else None,
+                                      _ptr(dst) if m else None,
+                                      _ptr(weights) if weights is not None and m else None,
+                                      flags, _ptr(off), 1 if offsets_64 else 0, _ptr(idx),
+                                      _ptr(w), 1 if weights_64 else 0, capacity,
+                                      ctypes.byref(nnz), _stream())
+        self._check(st)
+        k = nnz.value
+        return PreparedGraph(n, off, idx[:k], w[:k], name="prepared")
+
+    def prepare_count(self, n, src, dst, flags=LV_PREP_PAPER) -> int:
+        """Arcs louvain_prepare would write (the size query)."""
+        m = int(src.numel())
+        nnz = ctypes.c_int64(0)
+        st = self.lib.louvain_prepare(self.h, n, m, _ptr(src) if m else None,
+                                      _ptr(dst) if m else None, None, flags, None, 1, None,
+                                      None, 0, 0, ctypes.byref(nnz), _stream())
+        self._check(st)
+        return nnz.value
 
     def run_batched(self, packed, vptr, aptr, tolerance_exp10=2, decline_exp10=1,
                     max_iterations=20, max_passes=10, substeps=DEFAULT_SUBSTEPS, flags=0,
