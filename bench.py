@@ -27,8 +27,14 @@ if ROOT not in sys.path:
 
 METRIC = "Louvain TEPS (R-MAT s25); batched graphs/s vs one-by-one; serving p50/p99 ms"
 HBM_PEAK_GBPS = 8000.0
-PROFILE_PMC = os.path.join(ROOT, "profiles", "k_move_lds_rmat25_pmc.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2301_12390_amd", "csrc", "lv_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2301_12390_amd", "csrc")
+# the kernel whose roofline a workload reports: its source file and its PMC summary
+PMC_KERNELS = {
+    "k_move_lds": (os.path.join(CSRC, "lv_kernels.hip"),
+                   os.path.join(ROOT, "profiles", "k_move_lds_rmat25_pmc.md")),
+    "k_radix_onesweep": (os.path.join(CSRC, "lv_prep.hip"),
+                         os.path.join(ROOT, "profiles", "k_radix_onesweep_prepare_rmat25_pmc.md")),
+}
 
 
 def log(msg):
@@ -73,19 +79,19 @@ def load_graph(path, workload, dev):
                torch.from_numpy(w).to(dev), workload)
 
 
-def kernel_src_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+def kernel_src_sha(kernel="k_move_lds"):
+    return hashlib.sha256(open(PMC_KERNELS[kernel][0], "rb").read()).hexdigest()
 
 
-def load_traffic(workload):
-    """Measured HBM bytes per launch of k_move_lds from the committed rocprofv3 PMC summary
+def load_traffic(workload, kernel="k_move_lds"):
+    """Measured HBM bytes per launch of the kernel from its committed rocprofv3 PMC summary
     (its ```json block), if it was taken on this workload with the current kernel source."""
     try:
-        text = open(PROFILE_PMC).read()
+        text = open(PMC_KERNELS[kernel][1]).read()
         d = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, ValueError, IndexError):
         return None
-    if d.get("workload") != workload or d.get("kernel_src_sha256") != kernel_src_sha():
+    if d.get("workload") != workload or d.get("kernel_src_sha256") != kernel_src_sha(kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -140,21 +146,23 @@ def _read_csv(path):
 
 
 def _short_name(name):
-    name = name.replace("lv::", "")
+    name = name.replace("lv::", "").replace("(anonymous namespace)::", "")
     return name.split("(")[0] if "(" in name else name
 
 
-def summarize_stats(csv_path, out_path, command):
+def summarize_stats(csv_path, out_path, command, title="R-MAT scale 25 Louvain runs"):
     """Markdown summary of a `rocprofv3 --kernel-trace --stats` kernel_stats.csv."""
     rows = _read_csv(csv_path)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     total = sum(float(r["TotalDurationNs"]) for r in rows if "lv::" in r["Name"])
-    lines = ["# Kernel time, R-MAT scale 25 Louvain runs", "",
+    overlap = any("k_move_lds" in r["Name"] for r in rows)
+    lines = [f"# Kernel time, {title}", "",
              "Made by:", "", "```", command, "```", "",
              f"Library kernels total: {total / 1e6:.1f} ms over all profiled runs "
-             "(warm-up and timed steps). The move kernels of a class step run concurrently on "
-             "up to three streams, so their durations overlap: shares are of summed kernel "
-             "time, not of wall time.", "",
+             "(warm-up and timed steps)." + (
+                 " The move kernels of a class step run concurrently on up to three streams, "
+                 "so their durations overlap: shares are of summed kernel time, not of wall "
+                 "time." if overlap else ""), "",
              "| kernel | calls | total ms | average us | share |",
              "|---|---:|---:|---:|---:|"]
     for r in rows:
@@ -166,9 +174,10 @@ def summarize_stats(csv_path, out_path, command):
     open(out_path, "w").write("\n".join(lines) + "\n")
 
 
-def summarize_pmc(fetch_csv, write_csv, bench_json, out_path, command, workload, copy_mib):
+def summarize_pmc(fetch_csv, write_csv, bench_json, out_path, command, workload, copy_mib,
+                  kernel="k_move_lds"):
     """Markdown summary of the FETCH_SIZE and WRITE_SIZE passes: per-launch HBM bytes of
-    k_move_lds, each counter scaled by what it reads for the plain copy of copy_mib MiB."""
+    `kernel`, each counter scaled by what it reads for the plain copy of copy_mib MiB."""
     import numpy as np
     per = {}
     for ctr, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
@@ -184,7 +193,8 @@ def summarize_pmc(fetch_csv, write_csv, bench_json, out_path, command, workload,
             by_kernel.setdefault(_short_name(r["Kernel_Name"]), []).append(
                 float(r["Counter_Value"]))
         per[ctr] = {"copy_raw_kib": copy_kib, "scale": scale, "by_kernel": by_kernel}
-    key = [k for k in per["FETCH_SIZE"]["by_kernel"] if k.startswith("void k_move_lds")]
+    key = [k for k in per["FETCH_SIZE"]["by_kernel"]
+           if k.replace("void ", "").replace("(anonymous namespace)::", "").startswith(kernel)]
     fetch = np.concatenate([per["FETCH_SIZE"]["by_kernel"][k] for k in key])
     write = np.concatenate([per["WRITE_SIZE"]["by_kernel"][k] for k in key])
     fs, ws = per["FETCH_SIZE"]["scale"], per["WRITE_SIZE"]["scale"]
@@ -192,7 +202,7 @@ def summarize_pmc(fetch_csv, write_csv, bench_json, out_path, command, workload,
     write_b = float(write.mean()) * 1024 * ws
     bj = json.load(open(bench_json))
     alg = bj["roofline"]["algorithmic_bytes_per_launch"]
-    d = {"workload": workload, "kernel": "k_move_lds", "kernel_src_sha256": kernel_src_sha(),
+    d = {"workload": workload, "kernel": kernel, "kernel_src_sha256": kernel_src_sha(kernel),
          "launches": int(fetch.size),
          "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
          "bytes_per_launch": fetch_b + write_b,
@@ -200,13 +210,13 @@ def summarize_pmc(fetch_csv, write_csv, bench_json, out_path, command, workload,
          "calibration": {"copy_bytes": copy_mib << 20,
                          "fetch_raw_kib": per["FETCH_SIZE"]["copy_raw_kib"], "fetch_scale": fs,
                          "write_raw_kib": per["WRITE_SIZE"]["copy_raw_kib"], "write_scale": ws}}
-    lines = [f"# HBM traffic of k_move_lds, {workload}", "",
+    lines = [f"# HBM traffic of {kernel}, {workload}", "",
              "Made by (one counter per run, then this summary):", "", "```", command, "```", "",
              f"Calibration: a plain device copy of {copy_mib} MiB reads FETCH_SIZE = "
              f"{per['FETCH_SIZE']['copy_raw_kib']:.0f} KiB and WRITE_SIZE = "
              f"{per['WRITE_SIZE']['copy_raw_kib']:.0f} KiB, so the counters are scaled by "
              f"{fs:.3f} and {ws:.3f}.", "",
-             f"k_move_lds over {fetch.size} launches: {fetch_b / 1e6:.1f} MB fetched and "
+             f"{kernel} over {fetch.size} launches: {fetch_b / 1e6:.1f} MB fetched and "
              f"{write_b / 1e6:.1f} MB written per launch, against {alg / 1e6:.1f} MB of "
              f"algorithmic bytes ({(fetch_b + write_b) / alg:.2f}x).", "",
              "| kernel | launches | fetch MB / launch | write MB / launch |",
@@ -507,6 +517,152 @@ def run_sweep_bench(args, dev):
     print(json.dumps(line), flush=True)
 
 
+def calibration_copy(args, dev):
+    """A plain device copy of --copy-calibration-mib MiB, the known-size reference that scales
+    the FETCH_SIZE / WRITE_SIZE counters of a --pmc run."""
+    import torch
+    if args.copy_calibration_mib <= 0:
+        return
+    words = args.copy_calibration_mib * (1 << 18)
+    src = torch.ones(words, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"calibration copy of {args.copy_calibration_mib} MiB done")
+    del src, dst
+    torch.cuda.empty_cache()
+
+
+# Algorithmic bytes of one stable scatter pass of the preparation sort, per arc: its 8-byte key
+# read once and written once (the paper's recipe has no input weights, so no weight array is
+# sorted; with input weights 4 more bytes each way).
+PREP_SCATTER_BYTES_PER_ARC = 16
+
+
+def run_prepare_bench(args, dev):
+    """Graph preparation (section 3.1.2 and Table 1): a raw R-MAT edge list (repeats and
+    self-loops included, as an edge-list file holds it) through louvain_prepare with the paper's
+    recipe (reverse edges, unit weights, a loop on every vertex, repeats combined). A step is
+    one louvain_prepare call on the edge list already in HBM."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from graphgen import rmat_edges
+    from paper_2301_12390_amd import LV_PREP_PAPER, Louvain
+    from paper_2301_12390_amd.louvain import LV_PREP_TRACE
+
+    t0 = time.perf_counter()
+    tag = f"rmat{args.prep_scale}-edges"
+    if args.graph_cache and os.path.exists(args.graph_cache):
+        with open(args.graph_cache, "rb") as f:
+            hdr = json.loads(f.read(int.from_bytes(f.read(8), "little")).decode())
+            assert hdr["workload"] == tag, (hdr["workload"], tag)
+            n, m = hdr["n"], hdr["m"]
+            src = torch.from_numpy(np.fromfile(f, dtype=np.int32, count=m)).to(dev)
+            dst = torch.from_numpy(np.fromfile(f, dtype=np.int32, count=m)).to(dev)
+        log(f"loaded the {tag} list: n={n} m={m} in {time.perf_counter() - t0:.1f}s")
+    else:
+        n, u, v = rmat_edges(args.prep_scale, device=dev)
+        src = u.to(torch.int32).contiguous()
+        dst = v.to(torch.int32).contiguous()
+        del u, v
+        torch.cuda.synchronize()
+        m = int(src.numel())
+        log(f"generated the {tag} list: n={n} m={m} in {time.perf_counter() - t0:.1f}s")
+        if args.graph_cache:
+            with open(args.graph_cache, "wb") as f:
+                b = json.dumps({"workload": tag, "n": n, "m": m}).encode()
+                f.write(len(b).to_bytes(8, "little"))
+                f.write(b)
+                src.cpu().numpy().tofile(f)
+                dst.cpu().numpy().tofile(f)
+            log(f"saved to {args.graph_cache}")
+    torch.cuda.empty_cache()
+    if args.steps <= 0:
+        return
+    calibration_copy(args, dev)
+    lv = Louvain(0)
+    flags = LV_PREP_PAPER | LV_PREP_TRACE
+    for w in range(args.warmup):
+        g = lv.prepare(n, src, dst, flags=flags)
+        log(f"warmup {w}: {g.stats['total_ms']:.1f} ms, nnz={g.nnz}")
+        del g
+    torch.cuda.synchronize()
+    stats = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        g = lv.prepare(n, src, dst, flags=flags)
+        stats.append(g.stats)
+        nnz = g.nnz
+        del g
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    ms_per_step = el * 1000.0 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, "
+        f"{m / (ms_per_step / 1000.0) / 1e9:.3f} G input edges/s")
+    arcs = stats[0]["arcs"]
+    passes = stats[0]["sort_passes"]
+    scatter_ms = sum(s_["scatter_ms"] for s_ in stats)
+    launches = passes * len(stats)
+    avg_ms = scatter_ms / max(launches, 1)
+    bytes_per_launch = PREP_SCATTER_BYTES_PER_ARC * arcs
+    achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
+    traffic = load_traffic(f"prepare-rmat{args.prep_scale}", "k_radix_onesweep")
+    phases = {k: sum(s_[k] for s_ in stats) / len(stats)
+              for k in ("expand_ms", "hist_ms", "scan_ms", "scatter_ms", "emit_ms", "total_ms")}
+    line = {
+        "metric": METRIC,
+        "value": m / (ms_per_step / 1000.0),
+        "unit": "input edges/s (graph preparation)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"prepare-rmat{args.prep_scale}", "n": n, "edges": m,
+                   "arcs_before_combining": arcs, "nnz": nnz,
+                   "recipe": "reverse edges, unit weights, self-loop per vertex, repeats "
+                             "combined (max)",
+                   "key_bits": stats[0]["key_bits"], "sort_passes": passes,
+                   "phase_ms_per_step": phases},
+        "roofline": {
+            "kernel": "k_radix_onesweep", "bound": "hbm", "achieved": achieved,
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "traffic_gbps": (traffic / (avg_ms / 1000.0) / 1e9 if traffic and avg_ms > 0
+                             else None),
+            "avg_launch_ms": avg_ms, "launches": launches,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+    }
+    lv.close()
+    if not args.no_cpu_baseline:
+        # the oracle's preparation of the edge list's first k edges, k doubling until about a
+        # third of cpu_seconds; without the n added loops, which would not shrink with k
+        hs = src.cpu().numpy()
+        hd = dst.cpu().numpy()
+        k = 1 << 20
+        done = 0
+        el3 = 0.0
+        while True:
+            t3 = time.perf_counter()
+            O.prepare(n, hs[:k], hd[:k], None, O.PREP_SYM | O.PREP_MAX)
+            el3 = time.perf_counter() - t3
+            done = k
+            if el3 >= args.cpu_seconds / 3 or 2 * k > m:
+                break
+            k *= 2
+        line["cpu_baseline"] = {
+            "value": done / el3, "unit": "input edges/s (graph preparation)", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"the oracle's preparation (reverse edges, combine repeats; the "
+                       f"{n} added loops left out) of the first {done} edges of the same edge "
+                       f"list ({el3:.1f}s, single-threaded sort)"),
+        }
+        log(f"cpu baseline: {done / el3 / 1e6:.2f} M edges/s")
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,11 +687,14 @@ def main():
     ap.add_argument("--pool", type=int, default=32, help="serving: distinct request graphs")
     ap.add_argument("--serve-batch-arcs", type=int, default=1 << 28,
                     help="serving: most arcs the server runs in one batch")
+    ap.add_argument("--prep-scale", type=int, default=25,
+                    help="prepare: R-MAT scale of the raw edge list")
     ap.add_argument("--workload", default="rmat25",
                     help="rmat25 (default), rmat22, sbm10k, rmatNN, batched (the batch of "
                          "--batch-count SBM and lattice graphs, graphs/s), serving (Poisson "
-                         "requests at --rates, p50/p99 latency) or sweep (tolerance and "
-                         "decline-factor study)")
+                         "requests at --rates, p50/p99 latency), sweep (tolerance and "
+                         "decline-factor study) or prepare (graph preparation of a raw R-MAT "
+                         "edge list of --prep-scale)")
     ap.add_argument("--substeps", type=int, default=8,
                     help="vertex classes per local-moving iteration (1 = fully synchronous)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -553,13 +712,17 @@ def main():
                     help="write the k_move_lds HBM-traffic summary of two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE; with --copy-calibration-mib) and exit")
     ap.add_argument("--command", default="", help="command text recorded in a summary")
+    ap.add_argument("--summary-title", default="R-MAT scale 25 Louvain runs",
+                    help="what a --summarize-stats summary covers")
+    ap.add_argument("--pmc-kernel", default="k_move_lds", choices=sorted(PMC_KERNELS),
+                    help="kernel a --summarize-pmc summary covers")
     args = ap.parse_args()
     if args.summarize_stats:
-        summarize_stats(*args.summarize_stats, args.command)
+        summarize_stats(*args.summarize_stats, args.command, args.summary_title)
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.command, args.workload,
-                      args.copy_calibration_mib or 1024)
+                      args.copy_calibration_mib or 1024, args.pmc_kernel)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -587,6 +750,9 @@ def main():
     if args.workload == "sweep":
         run_sweep_bench(args, dev)
         return
+    if args.workload == "prepare":
+        run_prepare_bench(args, dev)
+        return
     t0 = time.perf_counter()
     if args.graph_cache and os.path.exists(args.graph_cache):
         g = load_graph(args.graph_cache, args.workload, dev)
@@ -602,16 +768,7 @@ def main():
     if args.steps <= 0:
         return
 
-    if args.copy_calibration_mib > 0:
-        words = args.copy_calibration_mib * (1 << 18)
-        src = torch.ones(words, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy of {args.copy_calibration_mib} MiB done")
-        del src, dst
-        torch.cuda.empty_cache()
+    calibration_copy(args, dev)
 
     lv = Louvain(0)
     for w in range(args.warmup):

@@ -250,6 +250,23 @@ lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, l
 #define LV_PREP_SYMMETRIZE 0x1u /* add the reverse (v, u, w) of every edge (u, v, w), u != v */
 #define LV_PREP_SELF_LOOPS 0x2u /* add a self-loop of weight 1 on every vertex */
 #define LV_PREP_MAX 0x4u        /* repeated arcs combine by max (default: by sum) */
+#define LV_PREP_TRACE 0x8u      /* time the kernel phases with HIP events (lv_prep_stats) */
+#define LV_PREP_TILE_SORT 0x10u /* sort with a histogram pass per digit instead of the one-sweep
+                                   look-back sort (results are identical; for testing) */
+
+/* What louvain_prepare did (host). */
+typedef struct {
+  int64_t arcs;        /* arcs before combining: m (2m with LV_PREP_SYMMETRIZE) (+ n loops) */
+  int64_t nnz;         /* arcs after combining */
+  int32_t key_bits;    /* significant bits of the (source, neighbour) sort key */
+  int32_t sort_passes; /* radix passes over the key, digits of at most 8 bits */
+  float expand_ms;     /* LV_PREP_TRACE: edge list -> keyed arcs */
+  float hist_ms;       /* LV_PREP_TRACE: digit counts (all passes, or per pass) */
+  float scan_ms;       /* LV_PREP_TRACE: per-tile histogram scans (LV_PREP_TILE_SORT) */
+  float scatter_ms;    /* LV_PREP_TRACE: stable digit scatters, summed */
+  float emit_ms;       /* LV_PREP_TRACE: run heads, their scan, the CSR writes and narrowing */
+  float total_ms;      /* whole call (host clock) */
+} lv_prep_stats;
 
 /* Graph preparation (section 3.1.2 and Table 1: the inputs of the method are edge lists made
  * undirected by adding every edge's reverse, with unit weights and a self-loop on every
@@ -263,6 +280,7 @@ lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, l
  * weights_out [nnz] (uint64 if weights_64_out else uint32), rows in ascending neighbour order.
  * capacity: entries available in indices_out and weights_out. nnz_out (host): arcs of the
  * prepared graph. With indices_out and weights_out both NULL the call only counts (*nnz_out).
+ * stats (host, may be NULL): sizes, and phase times with LV_PREP_TRACE.
  * Errors: LV_EINVAL for a bad argument or flag, an endpoint outside [0, n), a zero weight, or
  * capacity < nnz (then *nnz_out holds the needed size); LV_EOVERFLOW for n >= 2^31, more than
  * 2^40 arcs, nnz >= 2^31 with int32 offsets, or a combined weight above 2^32-1 with uint32
@@ -272,7 +290,7 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
                           const int32_t* dst, const uint32_t* weights, uint32_t flags,
                           void* offsets_out, int32_t offsets_64_out, int32_t* indices_out,
                           void* weights_out, int32_t weights_64_out, int64_t capacity,
-                          int64_t* nnz_out, void* stream);
+                          int64_t* nnz_out, lv_prep_stats* stats, void* stream);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,8 @@ enum SlotId {
   S_OLDLABEL, S_DCOUNT, S_ABASE, S_TKEY, S_TW, S_GOFF0, S_GIDX0, S_GW0, S_GOFF1, S_GIDX1, S_GW1,
   S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
   S_REC, S_GID0, S_GIDA, S_GIDB, S_GBASE, S_GWORDS, S_GACT, S_APTR, S_PKEY0, S_PKEY1, S_PVAL0,
-  S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PW, S_POFF, S_COUNT_SLOTS
+  S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
+  S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -1254,16 +1255,21 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
                           const int32_t* dst, const uint32_t* weights, uint32_t flags,
                           void* offsets_out, int32_t offsets_64_out, int32_t* indices_out,
                           void* weights_out, int32_t weights_64_out, int64_t capacity,
-                          int64_t* nnz_out, void* stream) {
+                          int64_t* nnz_out, lv_prep_stats* stats, void* stream) {
   if (!ctx) return LV_EINVAL;
+  const auto t_start = std::chrono::steady_clock::now();
   ctx->err.clear();
   if (!nnz_out) return fail(ctx, LV_EINVAL, "nnz_out is NULL");
   *nnz_out = 0;
+  lv_prep_stats st_local;
+  lv_prep_stats& ps = stats ? *stats : st_local;
+  memset(&ps, 0, sizeof(ps));
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   if (n < 0 || m < 0 || capacity < 0) return fail(ctx, LV_EINVAL, "negative size");
   if (n >= ((int64_t)1 << 31)) return fail(ctx, LV_EOVERFLOW, "n must be below 2^31");
-  if (flags & ~(LV_PREP_SYMMETRIZE | LV_PREP_SELF_LOOPS | LV_PREP_MAX))
+  if (flags & ~(LV_PREP_SYMMETRIZE | LV_PREP_SELF_LOOPS | LV_PREP_MAX | LV_PREP_TRACE |
+                LV_PREP_TILE_SORT))
     return fail(ctx, LV_EINVAL, "unknown preparation flag");
   if (m > 0 && (!src || !dst)) return fail(ctx, LV_EINVAL, "src or dst is NULL");
   const bool query = !indices_out && !weights_out;
@@ -1274,6 +1280,33 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
   const int64_t N = m * (sym ? 2 : 1) + (loops ? n : 0);
   if (N >= ((int64_t)1 << 40) || N / lv::kPrepTile >= ((int64_t)1 << 31))
     return fail(ctx, LV_EOVERFLOW, "too many arcs");
+  ps.arcs = N;
+  // LV_PREP_TRACE: events at phase boundaries, phase kind of every interval
+  const bool trace = (flags & LV_PREP_TRACE) != 0;
+  int nev = 0;
+  int kinds[kEvents];
+  auto mark = [&](int kind) -> hipError_t {
+    if (!trace || nev >= kEvents) return hipSuccess;
+    kinds[nev] = kind;
+    return hipEventRecord(ctx->ev[nev++], s);
+  };
+  auto finish = [&]() -> hipError_t {
+    ps.total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                           t_start).count();
+    if (!trace || nev < 2) return hipSuccess;
+    hipError_t e = hipEventSynchronize(ctx->ev[nev - 1]);
+    if (e != hipSuccess) return e;
+    for (int i = 1; i < nev; i++) {
+      if (kinds[i] == 0) continue;  // an interval spent waiting for the host
+      float ms = 0;
+      if ((e = hipEventElapsedTime(&ms, ctx->ev[i - 1], ctx->ev[i])) != hipSuccess) return e;
+      float* dst = kinds[i] == 1 ? &ps.expand_ms : kinds[i] == 2 ? &ps.hist_ms
+                   : kinds[i] == 3 ? &ps.scan_ms : kinds[i] == 4 ? &ps.scatter_ms
+                   : &ps.emit_ms;
+      *dst += ms;
+    }
+    return hipSuccess;
+  };
   if (N == 0) {
     if (!query) {
       if (offsets_64_out)
@@ -1293,75 +1326,117 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
   unsigned int* bad = nullptr;
   CHK(wst(ctx, S_PKEY0, N, &k0));
   CHK(wst(ctx, S_PKEY1, N, &k1));
-  CHK(wst(ctx, S_PVAL0, N, &v0));
-  CHK(wst(ctx, S_PVAL1, N, &v1));
+  if (weights) {  // without input weights only the keys are sorted
+    CHK(wst(ctx, S_PVAL0, N, &v0));
+    CHK(wst(ctx, S_PVAL1, N, &v1));
+  }
   CHK(wst(ctx, S_BAD, 1, &bad));
   HIPCHK(lv::fill_i32((int32_t*)bad, 0, 1, s));
+  ps.key_bits = 2 * b;
+  HIPCHK(mark(0));
   HIPCHK(lv::prep_expand(n, m, src, dst, weights, flags, b, k0, v0, bad, s));
+  HIPCHK(mark(1));
   unsigned int hb = 0;
   HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (hb & 1u) return fail(ctx, LV_EINVAL, "an edge endpoint is out of range");
   if (hb & 2u) return fail(ctx, LV_EINVAL, "a weight is zero");
+  HIPCHK(mark(0));
   // LSD passes over the 2b key bits, digits as even as possible
   const int B = 2 * b;
-  const int passes = (B + lv::kRadixBits - 1) / lv::kRadixBits;
-  int32_t* hist = nullptr;
-  int64_t* offs = nullptr;
+  lv::SortPlan plan;
+  plan.passes = (B + lv::kRadixBits - 1) / lv::kRadixBits;
+  for (int p = 0, shift = 0; p < plan.passes; p++) {
+    plan.shift[p] = shift;
+    plan.bits[p] = (B - shift + (plan.passes - p) - 1) / (plan.passes - p);
+    shift += plan.bits[p];
+  }
+  ps.sort_passes = plan.passes;
   int64_t* scanp = nullptr;
-  const int64_t hist_n = ((int64_t)1 << lv::kRadixBits) * ntiles;
-  CHK(wst(ctx, S_PHIST, hist_n, &hist));
-  CHK(wst(ctx, S_POFFS, hist_n + 1, &offs));
-  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(hist_n + 1) + 1, &scanp));
-  int shift = 0;
-  for (int p = 0; p < passes; p++) {
-    const int bits = (B - shift + (passes - p) - 1) / (passes - p);
-    const int64_t hn = ((int64_t)1 << bits) * ntiles;
-    HIPCHK(lv::radix_hist(k0, N, shift, bits, hist, s));
-    HIPCHK(lv::scan_i32(hist, hn, offs, scanp, s));
-    HIPCHK(lv::radix_scatter(k0, v0, k1, v1, N, shift, bits, offs, s));
-    std::swap(k0, k1);
-    std::swap(v0, v1);
-    shift += bits;
+  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(((int64_t)1 << lv::kRadixBits) * ntiles + 1) + 1,
+          &scanp));
+  if (flags & LV_PREP_TILE_SORT) {
+    // per pass: per-tile histograms, their scan, the scatter
+    int32_t* hist = nullptr;
+    int64_t* offs = nullptr;
+    const int64_t hist_n = ((int64_t)1 << lv::kRadixBits) * ntiles;
+    CHK(wst(ctx, S_PHIST, hist_n, &hist));
+    CHK(wst(ctx, S_POFFS, hist_n + 1, &offs));
+    for (int p = 0; p < plan.passes; p++) {
+      const int64_t hn = ((int64_t)1 << plan.bits[p]) * ntiles;
+      HIPCHK(lv::radix_hist(k0, N, plan.shift[p], plan.bits[p], hist, s));
+      HIPCHK(mark(2));
+      HIPCHK(lv::scan_i32(hist, hn, offs, scanp, s));
+      HIPCHK(mark(3));
+      HIPCHK(lv::radix_scatter(k0, v0, k1, v1, N, plan.shift[p], plan.bits[p], offs, s));
+      HIPCHK(mark(4));
+      std::swap(k0, k1);
+      std::swap(v0, v1);
+    }
+  } else {
+    // all passes' digit counts in one read, then one look-back scatter per pass
+    ull* ghist = nullptr;
+    int64_t* gbase = nullptr;
+    ull* status = nullptr;
+    CHK(wst(ctx, S_PGHIST, lv::kMaxSortPasses * 256, &ghist));
+    CHK(wst(ctx, S_PGBASE, lv::kMaxSortPasses * 256, &gbase));
+    CHK(wst(ctx, S_PSTATUS, ntiles * 256 + 1, &status));
+    HIPCHK(lv::fill_i32((int32_t*)bad, 0, 1, s));
+    HIPCHK(lv::radix_counts(k0, N, plan, ghist, gbase, s));
+    HIPCHK(mark(2));
+    for (int p = 0; p < plan.passes; p++) {
+      HIPCHK(lv::radix_onesweep(k0, v0, k1, v1, N, plan.shift[p], plan.bits[p], gbase + 256 * p,
+                                status, bad, s));
+      HIPCHK(mark(4));
+      std::swap(k0, k1);
+      std::swap(v0, v1);
+    }
+    HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hb & 8u) return fail(ctx, LV_EHIP, "radix sort look-back did not complete");
+    HIPCHK(mark(0));
   }
   int32_t* theads = nullptr;
   int64_t* tslot = nullptr;
+  ull* tfirst = nullptr;
+  const bool cmax = (flags & LV_PREP_MAX) != 0;
   CHK(wst(ctx, S_PTILE, ntiles, &theads));
   CHK(wst(ctx, S_PSLOT, ntiles + 1, &tslot));
-  HIPCHK(lv::prep_heads(k0, N, theads, s));
+  CHK(wst(ctx, S_PFIRST, ntiles, &tfirst));
+  HIPCHK(lv::prep_heads(k0, v0, N, b, cmax, theads, tfirst, s));
   HIPCHK(lv::scan_i32(theads, ntiles, tslot, scanp, s));
+  HIPCHK(mark(5));
   int64_t nnz = 0;
   HIPCHK(hipMemcpyAsync(&nnz, tslot + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   *nnz_out = nnz;
-  if (query) return LV_OK;
+  ps.nnz = nnz;
+  if (query) {
+    HIPCHK(finish());
+    return LV_OK;
+  }
   if (capacity < nnz)
     return fail(ctx, LV_EINVAL, "capacity " + std::to_string(capacity) + " is below the " +
                                     std::to_string(nnz) + " arcs of the prepared graph");
   if (!offsets_64_out && nnz >= ((int64_t)1 << 31))
     return fail(ctx, LV_EOVERFLOW, "nnz >= 2^31 needs int64 offsets");
-  ull* wout = nullptr;
-  if (weights_64_out)
-    wout = (ull*)weights_out;
-  else
-    CHK(wst(ctx, S_PW, nnz, &wout));
-  HIPCHK(lv::fill_u64((uint64_t*)wout, 0, nnz, s));
+  HIPCHK(mark(0));
   int64_t* off64 = nullptr;
   if (offsets_64_out)
     off64 = (int64_t*)offsets_out;
   else
     CHK(wst(ctx, S_POFF, n + 1, &off64));
-  HIPCHK(lv::prep_emit(k0, v0, N, n, b, (flags & LV_PREP_MAX) != 0, tslot, off64, indices_out,
-                       wout, s));
+  HIPCHK(lv::fill_i32((int32_t*)bad, 0, 1, s));
+  HIPCHK(lv::prep_emit(k0, v0, N, n, b, cmax, !weights_64_out, tslot, theads, tfirst, off64,
+                       indices_out, weights_out, bad, s));
   if (!offsets_64_out) HIPCHK(lv::narrow_offsets(off64, (int32_t*)offsets_out, n + 1, s));
-  if (!weights_64_out) {
-    HIPCHK(lv::fill_i32((int32_t*)bad, 0, 1, s));
-    HIPCHK(lv::prep_narrow_weights(wout, (uint32_t*)weights_out, nnz, bad, s));
+  if (!weights_64_out)
     HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-  }
+  HIPCHK(mark(5));
   HIPCHK(hipStreamSynchronize(s));
   if (!weights_64_out && (hb & 4u))
     return fail(ctx, LV_EOVERFLOW, "a combined weight exceeds 32 bits; use 64-bit weights");
+  HIPCHK(finish());
   return LV_OK;
 }
 

@@ -224,6 +224,12 @@ constexpr uint32_t kPrepSym = 0x1u, kPrepLoops = 0x2u, kPrepMax = 0x4u;
 constexpr int64_t kPrepTile = 4096;  // items per workgroup of the sort and emit kernels
 constexpr int kRadixBits = 8;        // largest digit of one sort pass
 int prep_key_bits(int64_t n);        // bits of a vertex id in the sort key
+constexpr int kMaxSortPasses = 8;    // 62 key bits at most, digits of at most 8 bits
+struct SortPlan {                    // the LSD passes: digit (key >> shift[p]) & (2^bits[p] - 1)
+  int passes = 0;
+  int shift[kMaxSortPasses] = {0};
+  int bits[kMaxSortPasses] = {0};
+};
 hipError_t prep_expand(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                        const uint32_t* w, uint32_t flags, int b, uint64_t* keys, uint32_t* vals,
                        unsigned int* bad, hipStream_t s);
@@ -232,11 +238,21 @@ hipError_t radix_hist(const uint64_t* keys, int64_t N, int shift, int bits, int3
 hipError_t radix_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                          uint32_t* vout, int64_t N, int shift, int bits, const int64_t* offs,
                          hipStream_t s);
-hipError_t prep_heads(const uint64_t* keys, int64_t N, int32_t* tile_heads, hipStream_t s);
+// vals == nullptr: keys-only arcs (no input weights)
+// one-sweep sort: counts of every pass (ghist [kMaxSortPasses * 256] scratch, gbase the same
+// size, output starts), then one look-back scatter per pass (status: [tiles * 256 + 1] words;
+// a look-back that waits too long sets bit 3 of *bad)
+hipError_t radix_counts(const uint64_t* keys, int64_t N, const SortPlan& plan,
+                        unsigned long long* ghist, int64_t* gbase, hipStream_t s);
+hipError_t radix_onesweep(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                          uint32_t* vout, int64_t N, int shift, int bits, const int64_t* gbase,
+                          unsigned long long* status, unsigned int* bad, hipStream_t s);
+hipError_t prep_heads(const uint64_t* keys, const uint32_t* vals, int64_t N, int b,
+                      bool combine_max, int32_t* tile_heads, unsigned long long* tile_first,
+                      hipStream_t s);
 hipError_t prep_emit(const uint64_t* keys, const uint32_t* vals, int64_t N, int64_t n, int b,
-                     bool combine_max, const int64_t* tile_slot, int64_t* off, int32_t* idx,
-                     unsigned long long* w, hipStream_t s);
-hipError_t prep_narrow_weights(const unsigned long long* w, uint32_t* out, int64_t nnz,
-                               unsigned int* bad, hipStream_t s);
+                     bool combine_max, bool w32, const int64_t* tile_slot,
+                     const int32_t* tile_heads, const unsigned long long* tile_first,
+                     int64_t* off, int32_t* idx, void* w, unsigned int* bad, hipStream_t s);
 
 }  // namespace lv

@@ -133,6 +133,21 @@ class LvGraphResult(ctypes.Structure):
     ]
 
 
+class LvPrepStats(ctypes.Structure):
+    _fields_ = [
+        ("arcs", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("key_bits", ctypes.c_int32),
+        ("sort_passes", ctypes.c_int32),
+        ("expand_ms", ctypes.c_float),
+        ("hist_ms", ctypes.c_float),
+        ("scan_ms", ctypes.c_float),
+        ("scatter_ms", ctypes.c_float),
+        ("emit_ms", ctypes.c_float),
+        ("total_ms", ctypes.c_float),
+    ]
+
+
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -148,7 +163,8 @@ SIGNATURES = {
     "louvain_prepare": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P, _P,
                                        ctypes.c_uint32, _P, ctypes.c_int32, _P, _P,
                                        ctypes.c_int32, ctypes.c_int64,
-                                       ctypes.POINTER(ctypes.c_int64), _P]),
+                                       ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(LvPrepStats), _P]),
     "louvain_move": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.c_uint64,
                                     ctypes.c_int32, ctypes.POINTER(LvParams), _P, _P, _P,
                                     ctypes.POINTER(LvMoveStats), _P]),
@@ -223,6 +239,8 @@ DEFAULT_SUBSTEPS = 8
 LV_PREP_SYMMETRIZE = 0x1
 LV_PREP_SELF_LOOPS = 0x2
 LV_PREP_MAX = 0x4
+LV_PREP_TRACE = 0x8
+LV_PREP_TILE_SORT = 0x10
 # the paper's input graphs: reversed edges, unit weights, a self-loop on every vertex
 LV_PREP_PAPER = LV_PREP_SYMMETRIZE | LV_PREP_SELF_LOOPS | LV_PREP_MAX
 
@@ -236,6 +254,7 @@ class PreparedGraph:
     indices: torch.Tensor
     weights: torch.Tensor
     name: str = ""
+    stats: dict = None
 
     @property
     def nnz(self) -> int:
@@ -369,15 +388,17 @@ class Louvain:
         w = torch.empty(max(capacity, 1), dtype=torch.int64 if weights_64 else torch.int32,
                         device=dev)
         nnz = ctypes.c_int64(0)
+        ps = LvPrepStats()
         st = self.lib.louvain_prepare(self.h, n, m, _ptr(src) if m else None,
                                       _ptr(dst) if m else None,
                                       _ptr(weights) if weights is not None and m else None,
                                       flags, _ptr(off), 1 if offsets_64 else 0, _ptr(idx),
                                       _ptr(w), 1 if weights_64 else 0, capacity,
-                                      ctypes.byref(nnz), _stream())
+                                      ctypes.byref(nnz), ctypes.byref(ps), _stream())
         self._check(st)
         k = nnz.value
-        return PreparedGraph(n, off, idx[:k], w[:k], name="prepared")
+        stats = {f: getattr(ps, f) for f, _ in LvPrepStats._fields_}
+        return PreparedGraph(n, off, idx[:k], w[:k], name="prepared", stats=stats)
 
     def prepare_count(self, n, src, dst, flags=LV_PREP_PAPER) -> int:
         """Arcs louvain_prepare would write (the size query)."""
@@ -385,7 +406,7 @@ class Louvain:
         nnz = ctypes.c_int64(0)
         st = self.lib.louvain_prepare(self.h, n, m, _ptr(src) if m else None,
                                       _ptr(dst) if m else None, None, flags, None, 1, None,
-                                      None, 0, 0, ctypes.byref(nnz), _stream())
+                                      None, 0, 0, ctypes.byref(nnz), None, _stream())
         self._check(st)
         return nnz.value
 

@@ -73,6 +73,8 @@ int main(void) {
   S(lv_graph_result) F(lv_graph_result, iterations) F(lv_graph_result, cap_hits)
   F(lv_graph_result, n_communities) F(lv_graph_result, W) F(lv_graph_result, q_num)
   F(lv_graph_result, q)
+  S(lv_prep_stats) F(lv_prep_stats, nnz) F(lv_prep_stats, sort_passes)
+  F(lv_prep_stats, scatter_ms) F(lv_prep_stats, total_ms)
   return 0;
 }
 """
@@ -89,7 +91,7 @@ def test_struct_layout_matches_header():
         out = subprocess.check_output([exe]).decode().split("\n")
     cmap = {"lv_graph": L.LvGraph, "lv_params": L.LvParams, "lv_iter_trace": L.LvIterTrace,
             "lv_result": L.LvResult, "lv_move_stats": L.LvMoveStats,
-            "lv_graph_result": L.LvGraphResult}
+            "lv_graph_result": L.LvGraphResult, "lv_prep_stats": L.LvPrepStats}
     checked = 0
     for line in out:
         if not line:

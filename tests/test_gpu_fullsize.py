@@ -226,3 +226,40 @@ def test_batched_workload_sampled(lv):
         assert np.array_equal(memb[vptr[g]:vptr[g + 1]], top), g
         assert res[g]["qnum"] == ref["qnum"] and res[g]["iterations"] == ref["iterations"], g
     print(f"checked {len(sample)} of 2048 graphs against the oracle", flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_prepare_rmat25_edge_list_sampled(lv):
+    """Graph preparation at full size (the raw R-MAT s25 edge list, 5.4e8 edges, with the
+    paper's recipe), as bench.py --workload prepare times it: sampled rows (the longest, the
+    first, the last and a spread) against the oracle's per-row definition, and properties over
+    all rows: one loop per vertex, unit weights, strictly ascending rows, nnz = offsets[n]."""
+    from graphgen import rmat_edges
+    from paper_2301_12390_amd import LV_PREP_PAPER
+    print("generating the rmat25 edge list", flush=True)
+    n, u, v = rmat_edges(25, device="cuda:0")
+    src = u.to(torch.int32).contiguous()
+    dst = v.to(torch.int32).contiguous()
+    del u, v
+    g = lv.prepare(n, src, dst, flags=LV_PREP_PAPER)
+    torch.cuda.synchronize()
+    off = g.offsets
+    assert int(off[0]) == 0 and int(off[-1]) == g.nnz
+    deg = off[1:] - off[:-1]
+    assert int(deg.min()) >= 1
+    assert bool((g.weights == 1).all())
+    rows = torch.repeat_interleave(torch.arange(n, device="cuda:0"), deg)
+    same = rows[1:] == rows[:-1]
+    assert bool((g.indices[1:][same] > g.indices[:-1][same]).all())
+    # every vertex's loop
+    assert int(((g.indices.to(torch.int64) == rows)).sum()) == n
+    del rows, same
+    hs, hd = src.cpu().numpy(), dst.cpu().numpy()
+    ho = off.cpu().numpy()
+    hi = g.indices.cpu().numpy()
+    picks = [int(torch.argmax(deg)), 0, n - 1] + list(range(7, n, n // 5))
+    for r in picks:
+        print(f"oracle row {r}", flush=True)
+        ri, rw = O.prepare_row(n, hs, hd, None, O.PREP_SYM | O.PREP_LOOPS | O.PREP_MAX, r)
+        assert np.array_equal(hi[ho[r]:ho[r + 1]], ri), r
+        assert (rw == 1).all()

@@ -16,6 +16,7 @@ from graphgen import rmat_edges
 pytestmark = pytest.mark.gpu
 
 SYM, LOOPS, MAX = 0x1, 0x2, 0x4
+TILE_SORT = 0x10  # the per-digit histogram sort instead of the one-sweep look-back sort
 FLAG_SETS = [0, SYM, SYM | LOOPS, SYM | LOOPS | MAX, LOOPS | MAX, MAX, LOOPS]
 
 
@@ -53,7 +54,7 @@ def gpu_prepare(lv, n, src, dst, w, flags, offsets_64=True, weights_64=False):
 
 
 def check(lv, n, src, dst, w, flags, **kw):
-    ref = O.prepare(n, src, dst, w, flags)
+    ref = O.prepare(n, src, dst, w, flags & (SYM | LOOPS | MAX))
     g, off, idx, wo = gpu_prepare(lv, n, src, dst, w, flags, **kw)
     assert np.array_equal(off, ref[0]), (n, flags)
     assert np.array_equal(idx, ref[1]), (n, flags)
@@ -69,7 +70,7 @@ def test_prepare_small(lv, flags):
         check(lv, n, src, dst, w, flags)
 
 
-@pytest.mark.parametrize("flags", [SYM | LOOPS | MAX, SYM, LOOPS])
+@pytest.mark.parametrize("flags", [SYM | LOOPS | MAX, SYM, LOOPS, SYM | LOOPS | TILE_SORT])
 @pytest.mark.parametrize("fmt", [(True, False), (False, False), (True, True), (False, True)],
                          ids=["off64-w32", "off32-w32", "off64-w64", "off32-w64"])
 def test_prepare_many_tiles(lv, flags, fmt):
@@ -83,7 +84,7 @@ def test_prepare_rmat_edge_list(lv):
     # the paper's recipe on a raw R-MAT edge list (repeats, loops, skewed rows)
     n, u, v = rmat_edges(14, seed=3)
     src, dst = u.numpy().astype(np.int32), v.numpy().astype(np.int32)
-    for flags in (SYM | LOOPS | MAX, SYM | LOOPS, SYM):
+    for flags in (SYM | LOOPS | MAX, SYM | LOOPS, SYM, SYM | LOOPS | MAX | TILE_SORT):
         check(lv, n, src, dst, None, flags)
     # n not a power of two
     n, u, v = rmat_edges(13, seed=5, n=6000)
@@ -91,11 +92,11 @@ def test_prepare_rmat_edge_list(lv):
 
 
 def test_prepare_long_runs(lv):
-    # one edge repeated across several tiles: a run combined over tile edges with atomics
+    # one edge repeated across several tiles: a run its head's tile combines over the tiles after
     src = np.array([3] * 20000 + [1, 2] * 5000, dtype=np.int32)
     dst = np.array([7] * 20000 + [2, 1] * 5000, dtype=np.int32)
     w = (np.arange(src.size) % 5 + 1).astype(np.uint32)
-    for flags in (0, SYM, SYM | MAX, SYM | LOOPS):
+    for flags in (0, SYM, SYM | MAX, SYM | LOOPS, SYM | TILE_SORT):
         check(lv, 9, src, dst, w, flags)
     # a hub row spanning many tiles
     src = np.zeros(30000, dtype=np.int32)
@@ -138,7 +139,7 @@ def test_prepare_errors(lv):
         lv.prepare(3, src, torch.tensor([1, 2, 0], dtype=torch.int32, device=d),
                    torch.tensor([1, 0, 1], dtype=torch.int32, device=d))
     with pytest.raises(LouvainError, match="EINVAL"):
-        lv.prepare(3, src, src, flags=0x10)
+        lv.prepare(3, src, src, flags=0x40)
     # combined weights above 32 bits: refused for uint32 output, exact for uint64
     big = torch.tensor([np.int32(-2**31)] * 3, dtype=torch.int32, device=d)  # 2^31 each
     same = torch.tensor([0, 0, 0], dtype=torch.int32, device=d)
