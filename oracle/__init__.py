@@ -245,24 +245,25 @@ def aggregate(g: Graph, C):
 
 
 def run(g: Graph, mode: str = "sync", a: int = 2, b: int = 1, max_iterations: int = 20,
-        max_passes: int = 10, substeps: int = 1, nthreads: int = 0, levels: bool = False):
+        max_passes: int = 10, substeps: int = 1, nthreads: int = 0, levels: bool = False,
+        colour: bool = False):
     """Whole Louvain run. Returns (membership int32[n], result dict).
     mode "sync": synchronous rule, an iteration being ``substeps`` class steps;
     mode "async": sequential asynchronous rule.
     levels: also return, as result["levels"] (int32[L, n]), the membership of the input
-    vertices after each of the L aggregations (the last one equals the membership)."""
+    vertices after each of the L aggregations (the last one equals the membership).
+    colour: the classes of every pass are colour classes (``colour_classes``), not hashed."""
     top = np.zeros(max(g.n, 1), dtype=np.int32)
     r = OrcResult()
-    common = (*g.args(), ctypes.c_int32(0 if mode == "sync" else 1), ctypes.c_int32(a),
-              ctypes.c_int32(b), ctypes.c_int32(max_iterations), ctypes.c_int32(max_passes),
-              ctypes.c_int32(substeps), ctypes.c_int32(nthreads), _p(top), ctypes.byref(r))
-    if levels:
-        max_levels = max(1, min(max_passes, MAX_PASSES))
-        lv = np.zeros((max_levels, max(g.n, 1)), dtype=np.int32)
-        nl = ctypes.c_int32(0)
-        lib().orc_run_levels(*common, _p(lv), ctypes.c_int32(max_levels), ctypes.byref(nl))
-    else:
-        lib().orc_run(*common)
+    max_levels = max(1, min(max_passes, MAX_PASSES))
+    lv = np.zeros((max_levels, max(g.n, 1)), dtype=np.int32) if levels else None
+    nl = ctypes.c_int32(0)
+    lib().orc_run_opts(*g.args(), ctypes.c_int32(0 if mode == "sync" else 1), ctypes.c_int32(a),
+                       ctypes.c_int32(b), ctypes.c_int32(max_iterations),
+                       ctypes.c_int32(max_passes), ctypes.c_int32(substeps),
+                       ctypes.c_int32(nthreads), ctypes.c_int32(1 if colour else 0), _p(top),
+                       ctypes.byref(r), _p(lv) if levels else None,
+                       ctypes.c_int32(max_levels), ctypes.byref(nl))
     nt = r.n_trace
     res = {
         "passes": r.passes,
@@ -292,6 +293,21 @@ def run(g: Graph, mode: str = "sync", a: int = 2, b: int = 1, max_iterations: in
 PREP_SYM = 0x1
 PREP_LOOPS = 0x2
 PREP_MAX = 0x4
+
+
+def vertex_priority(p: int, v: int) -> int:
+    f = lib().orc_vertex_priority
+    f.restype = ctypes.c_uint64
+    return int(f(ctypes.c_int32(p), ctypes.c_int64(v)))
+
+
+def colour_classes(g: Graph, p: int, K: int):
+    """Colour class (0..K-1) of every vertex of g in pass p: first-fit colouring in descending
+    priority order, colours 0..K-2, the rest in class K-1."""
+    out = np.zeros(max(g.n, 1), dtype=np.int32)
+    lib().orc_colour(ctypes.c_int64(g.n), _p(g.off), _p(g.idx), ctypes.c_int32(p),
+                     ctypes.c_int32(K), _p(out))
+    return out[:g.n].copy()
 
 
 def prepare(n: int, src, dst, w=None, flags: int = PREP_SYM | PREP_LOOPS):

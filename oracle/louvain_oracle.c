@@ -81,6 +81,58 @@ void orc_class_lists(int64_t n, int32_t pass, int32_t K, int32_t* verts, int64_t
   start[K] = pos;
 }
 
+/* Colour classes: the graph-colouring route to partial asynchrony that section 3.2 cites. A
+ * first-fit distance-1 colouring of the current graph visits the vertices by descending
+ * priority, the priority of v in pass p being the whole 64-bit draw above (ties cannot occur:
+ * the finaliser is a bijection and the counters differ; they would go to the smaller id). Each
+ * vertex takes the smallest colour in [0, K-2] that no neighbour coloured before it holds (its
+ * higher-priority neighbours); if all K-1 are taken it joins the leftover class K-1, which,
+ * unlike the others, need not be an independent set. K = 1: every vertex in class 0. */
+uint64_t orc_vertex_priority(int32_t pass, int64_t v) {
+  return splitmix64_finaliser((uint64_t)pass + ((uint64_t)v + 1u) * 0x9E3779B97F4A7C15ull);
+}
+
+typedef struct {
+  uint64_t prio;
+  int32_t v;
+} prio_vertex;
+
+static int cmp_prio_desc(const void* a, const void* b) {
+  const prio_vertex* x = (const prio_vertex*)a;
+  const prio_vertex* y = (const prio_vertex*)b;
+  if (x->prio != y->prio) return x->prio > y->prio ? -1 : 1;
+  return x->v < y->v ? -1 : (x->v > y->v ? 1 : 0);
+}
+
+void orc_colour(int64_t n, const int64_t* off, const int32_t* idx, int32_t pass, int32_t K,
+                int32_t* colour) {
+  if (K <= 1) {
+    for (int64_t v = 0; v < n; v++) colour[v] = 0;
+    return;
+  }
+  prio_vertex* order = (prio_vertex*)malloc(sizeof(prio_vertex) * (size_t)(n > 0 ? n : 1));
+  for (int64_t v = 0; v < n; v++) {
+    order[v].prio = orc_vertex_priority(pass, v);
+    order[v].v = (int32_t)v;
+    colour[v] = -1;
+  }
+  qsort(order, (size_t)n, sizeof(prio_vertex), cmp_prio_desc);
+  const uint32_t all = K - 1 >= 32 ? 0xffffffffu : ((1u << (K - 1)) - 1u);
+  for (int64_t t = 0; t < n; t++) {
+    const int32_t v = order[t].v;
+    uint32_t used = 0;
+    for (int64_t e = off[v]; e < off[v + 1]; e++) {
+      const int32_t u = idx[e];
+      if (u != v && colour[u] >= 0 && colour[u] < K - 1) used |= 1u << colour[u];
+    }
+    int32_t c = K - 1;
+    for (int32_t k = 0; k < K - 1; k++)
+      if (!((used & all) >> k & 1u)) { c = k; break; }
+    colour[v] = c;
+  }
+  free(order);
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Degrees, total weight, modularity                                                          */
 /* ---------------------------------------------------------------------------------------- */
@@ -472,8 +524,8 @@ static int64_t* copy64(const int64_t* a, int64_t k) {
  * each pass's communities become the vertices of the next). */
 static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
                     int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
-                    int32_t substeps, int32_t nthreads, int32_t* top, orc_result* res,
-                    int32_t* levels, int32_t max_levels, int32_t* n_levels) {
+                    int32_t substeps, int32_t nthreads, int32_t colour_classes, int32_t* top,
+                    orc_result* res, int32_t* levels, int32_t max_levels, int32_t* n_levels) {
   memset(res, 0, sizeof(*res));
   if (n_levels) *n_levels = 0;
   for (int64_t v = 0; v < n; v++) top[v] = (int32_t)v;
@@ -502,6 +554,7 @@ static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const u
   uint64_t* w2 = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nnz0 > 0 ? nnz0 : 1));
   int32_t* cls_verts = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   int64_t* cls_start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(substeps + 1));
+  int32_t* colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
   if (substeps < 1) substeps = 1;
 
   for (int32_t p = 0; p < max_pass && p < ORC_MAX_PASSES; p++) {
@@ -514,13 +567,17 @@ static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const u
     res->n_pass[p] = cn;
     res->nnz_pass[p] = cnnz;
     res->passes = p + 1;
-    /* vertices of each class, ascending within a class */
+    /* vertices of each class, ascending within a class: hashed classes, or colour classes */
     {
+      if (colour_classes) orc_colour(cn, off, idx, p, substeps, colour);
       int64_t pos = 0;
       for (int32_t k = 0; k < substeps; k++) {
         cls_start[k] = pos;
-        for (int64_t v = 0; v < cn; v++)
-          if (substeps == 1 || orc_vertex_class(p, substeps, v) == k) cls_verts[pos++] = (int32_t)v;
+        for (int64_t v = 0; v < cn; v++) {
+          const int32_t cls = substeps == 1 ? 0
+                              : colour_classes ? colour[v] : orc_vertex_class(p, substeps, v);
+          if (cls == k) cls_verts[pos++] = (int32_t)v;
+        }
       }
       cls_start[substeps] = pos;
     }
@@ -583,7 +640,7 @@ static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const u
   res->n_communities = cn;
   uint64_t Wq = 0;
   orc_modularity(n, off0, idx0, w0, top, res->qnum, &Wq, NULL);
-  free(cls_start); free(cls_verts);
+  free(colour); free(cls_start); free(cls_verts);
   free(w2); free(idx2); free(off2); free(map); free(csize); free(Sig); free(C);
   free(w); free(idx); free(off); free(K);
   return 0;
@@ -592,17 +649,18 @@ static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const u
 int orc_run(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
             int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
             int32_t substeps, int32_t nthreads, int32_t* top, orc_result* res) {
-  return run_impl(n, off0, idx0, w0, mode, a, b, max_it, max_pass, substeps, nthreads, top, res,
-                  NULL, 0, NULL);
+  return run_impl(n, off0, idx0, w0, mode, a, b, max_it, max_pass, substeps, nthreads, 0, top,
+                  res, NULL, 0, NULL);
 }
 
-/* orc_run that also keeps every level of the hierarchy (levels[max_levels * n]). */
-int orc_run_levels(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
-                   int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
-                   int32_t substeps, int32_t nthreads, int32_t* top, orc_result* res,
-                   int32_t* levels, int32_t max_levels, int32_t* n_levels) {
-  return run_impl(n, off0, idx0, w0, mode, a, b, max_it, max_pass, substeps, nthreads, top, res,
-                  levels, max_levels, n_levels);
+/* orc_run with every option: colour_classes selects colour classes (orc_colour) instead of
+ * hashed ones; levels (may be NULL) keeps every level of the hierarchy (levels[max_levels*n]). */
+int orc_run_opts(int64_t n, const int64_t* off0, const int32_t* idx0, const uint64_t* w0,
+                 int32_t mode, int32_t a, int32_t b, int32_t max_it, int32_t max_pass,
+                 int32_t substeps, int32_t nthreads, int32_t colour_classes, int32_t* top,
+                 orc_result* res, int32_t* levels, int32_t max_levels, int32_t* n_levels) {
+  return run_impl(n, off0, idx0, w0, mode, a, b, max_it, max_pass, substeps, nthreads,
+                  colour_classes, top, res, levels, max_levels, n_levels);
 }
 
 /* ---------------------------------------------------------------------------------------------

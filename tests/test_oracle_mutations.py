@@ -49,6 +49,11 @@ MUTATIONS = {
                                 "idx[nnz - 1] == a[i].v"),
     "prep_loop_weight_two": ("a[k].v = (int32_t)v; a[k].w = 1; k++;",
                              "a[k].v = (int32_t)v; a[k].w = 2; k++;"),
+    "colour_ascending_priority": ("if (x->prio != y->prio) return x->prio > y->prio ? -1 : 1;",
+                                  "if (x->prio != y->prio) return x->prio < y->prio ? -1 : 1;"),
+    "colour_leftover_reuses_last": ("    int32_t c = K - 1;\n    for (int32_t k = 0; k < K - 1; k++)",
+                                    "    int32_t c = K - 2;\n    for (int32_t k = 0; k < K - 1; k++)"),
+    "colour_mask_shifted": ("used |= 1u << colour[u];", "used |= 2u << colour[u];"),
     "level_cap_off_by_one": ("if (levels && n_levels && *n_levels < max_levels) {",
                              "if (levels && n_levels && *n_levels + 1 < max_levels) {"),
 }
@@ -74,6 +79,9 @@ def battery():
     P.test_ring_of_cliques_recovered()
     P.test_levels_ring_of_k4_hand_derived()
     P.test_levels_edge_cases()
+    from . import test_oracle_colour as PC
+    for K in (2, 8, 32):
+        PC.test_matches_jones_plassmann_rounds(K)
     from . import test_oracle_prepare as PP
     PP.test_golden_small()
     for f in PP.FLAG_SETS:
