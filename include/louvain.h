@@ -89,6 +89,12 @@ typedef struct {
                                partitions with tiny workgroup tables, so that the partitioned
                                and multi-round code paths run on small graphs (results are
                                identical; slower; for testing) */
+#define LV_COLOR_CLASSES 0x10u /* colour classes instead of hashed ones (section 3.2 cites graph
+                                  colouring for partial asynchrony): in every pass the K =
+                                  substeps classes are a first-fit distance-1 colouring in
+                                  descending order of the vertices' SplitMix64 draws, colours
+                                  0..K-2 (independent sets), the rest in class K-1; computed in
+                                  Jones-Plassmann rounds on the device */
 
 typedef struct {
   int32_t tolerance_exp10; /* initial tolerance 10^-a, a >= 0 (paper's best: a = 2) */
@@ -245,6 +251,15 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
  * W = total weight, q = q_num / W^2. All outputs host; any may be NULL. */
 lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, lv_i128* q_num,
                              uint64_t* W, double* q, void* stream);
+
+/* Colour classes of a graph (LV_COLOR_CLASSES; section 3.2 cites graph colouring for partial
+ * asynchrony): classes[v] in [0, K) for pass `pass` (>= 0) and K in 1..32 classes. Vertices
+ * are visited in descending order of their SplitMix64 draws of the pass (the draw behind the
+ * hashed classes, all 64 bits); each takes the smallest colour in 0..K-2 that none of its
+ * earlier-visited neighbours holds, else class K-1. classes: [n] out (device, uint8). rounds
+ * (host, may be NULL): Jones-Plassmann rounds the device took. Errors as louvain_run. */
+lv_status louvain_colour_classes(lv_ctx* ctx, const lv_graph* g, int32_t pass, int32_t K,
+                                 uint8_t* classes, int32_t* rounds, void* stream);
 
 /* Graph preparation flags of louvain_prepare. */
 #define LV_PREP_SYMMETRIZE 0x1u /* add the reverse (v, u, w) of every edge (u, v, w), u != v */

@@ -27,7 +27,7 @@ enum SlotId {
   S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
   S_REC, S_GID0, S_GIDA, S_GIDB, S_GBASE, S_GWORDS, S_GACT, S_APTR, S_PKEY0, S_PKEY1, S_PVAL0,
   S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
-  S_COUNT_SLOTS
+  S_VCLASS, S_CCNT, S_CFLAG, S_CPOS, S_CSHORT, S_CLONG, S_CNLONG, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -253,7 +253,29 @@ struct Phase {
   bool wide = false;
   int classes = 1;
   int pass = 0;
+  bool colour = false;            // colour classes (LV_COLOR_CLASSES) instead of hashed ones
+  const uint8_t* vclass = nullptr;  // the colour classes, once computed for this phase
+  int colour_rounds = 0;
 };
+
+// Colour classes of the phase's graph and pass (computed once per phase).
+lv_status colour_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
+  const int64_t n = ph.g.n;
+  uint8_t* vc = nullptr;
+  lv::ColourBuffers cb;
+  CHK(wst(ctx, S_VCLASS, n, &vc));
+  CHK(wst(ctx, S_CCNT, n, &cb.cnt));
+  CHK(wst(ctx, S_CFLAG, n, &cb.flag));
+  CHK(wst(ctx, S_CPOS, n + 1, &cb.pos));
+  CHK(wst(ctx, S_CSHORT, n, &cb.shorts));
+  CHK(wst(ctx, S_CLONG, n, &cb.longs));
+  CHK(wst(ctx, S_CNLONG, 1, &cb.nlong));
+  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &cb.partial));
+  HIPCHK(lv::colour_classes(ph.g, ph.classes, ph.pass, ph.m.gs.gid, ph.m.gs.gbase, cb,
+                            ctx->pinned + PIN_MISC, vc, &ph.colour_rounds, s));
+  ph.vclass = vc;
+  return LV_OK;
+}
 
 // Row lists by (vertex class, degree class) and the hub tables of every class; fills ph.b,
 // ph.hp and the buffers of ph.m that depend on them.
@@ -266,9 +288,10 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   int64_t* hubarr = nullptr;
   CHK(wst(ctx, S_LIST, n, &list));
   CHK(wst(ctx, S_COUNTS, 1536, &counts));
+  if (ph.colour && K > 1 && !ph.vclass) CHK(colour_phase(ctx, ph, s));
   CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &scanp));
   HIPCHK(lv::bucket_rows(ph.g.rs, ph.g.re, nullptr, n, K, ph.pass, ph.m.gs.gid, ph.m.gs.gbase,
-                         ph.m.gs.act, list, counts,
+                         ph.m.gs.act, K > 1 ? ph.vclass : nullptr, list, counts,
                          ctx->pinned + PIN_COUNTS, ph.b, s));
   const int hf = lv::hub_first_class(ctx->max_lds, ph.wide);
   ph.m.hub_first = hf;
@@ -553,7 +576,8 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   HIPCHK(lv::zero_words(a.stats, 2, s));
   HIPCHK(lv::aggregate_prepare(g, C, csize, Sig, Kp, map, a, s));
   lv::Buckets b;
-  HIPCHK(lv::bucket_rows(nullptr, nullptr, a.A, n, 1, 0, nullptr, nullptr, nullptr, a.list,
+  HIPCHK(lv::bucket_rows(nullptr, nullptr, a.A, n, 1, 0, nullptr, nullptr, nullptr, nullptr,
+                         a.list,
                          a.counts,
                          ctx->pinned + PIN_COUNTS, b, s));
   // the super-vertex count bounds the distinct targets of any community
@@ -781,6 +805,7 @@ lv_status louvain_move(lv_ctx* ctx, const lv_graph* g, const uint64_t* Kin, uint
   ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)W * maxK < ((u128)1 << 63));
   ph.classes = p->substeps;
   ph.pass = pass_index;
+  ph.colour = (p->flags & LV_COLOR_CLASSES) != 0;
   CHK(plan_phase(ctx, ph, s));
   PhaseOut po;
   CHK(run_phase(ctx, ph, tolerance_threshold(W, p->tolerance_exp10, p->decline_exp10, pass_index),
@@ -908,6 +933,7 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)W * maxK < ((u128)1 << 63));
     ph.classes = p->substeps;
     ph.pass = pass;
+    ph.colour = (p->flags & LV_COLOR_CLASSES) != 0;
     CHK(plan_phase(ctx, ph, s));
     PhaseOut po;
     CHK(run_phase(ctx, ph, tolerance_threshold(W, p->tolerance_exp10, p->decline_exp10, pass),
@@ -1145,6 +1171,7 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)maxW * maxK < ((u128)1 << 63));
     ph.classes = p->substeps;
     ph.pass = pass;
+    ph.colour = (p->flags & LV_COLOR_CLASSES) != 0;
     bp.T.assign(G, 0);
     bp.act.assign(G, 0);
     bp.passgain.assign(G, 0);
@@ -1437,6 +1464,33 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
   if (!weights_64_out && (hb & 4u))
     return fail(ctx, LV_EOVERFLOW, "a combined weight exceeds 32 bits; use 64-bit weights");
   HIPCHK(finish());
+  return LV_OK;
+}
+
+lv_status louvain_colour_classes(lv_ctx* ctx, const lv_graph* g, int32_t pass, int32_t K,
+                                 uint8_t* classes, int32_t* rounds, void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  if (rounds) *rounds = 0;
+  HIPCHK(hipSetDevice(ctx->device));
+  if (pass < 0) return fail(ctx, LV_EINVAL, "pass must be >= 0");
+  if (K < 1 || K > lv_max_classes()) return fail(ctx, LV_EINVAL, "K must be in 1..32");
+  hipStream_t s = (hipStream_t)stream;
+  Phase ph;
+  CHK(import_graph(ctx, g, false, s, &ph.g));
+  if (ph.g.n > 0 && !classes) return fail(ctx, LV_EINVAL, "classes is NULL");
+  if (ph.g.n == 0) return LV_OK;
+  if (K == 1) {
+    HIPCHK(hipMemsetAsync(classes, 0, (size_t)ph.g.n, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return LV_OK;
+  }
+  ph.classes = K;
+  ph.pass = pass;
+  CHK(colour_phase(ctx, ph, s));
+  HIPCHK(hipMemcpyAsync(classes, ph.vclass, (size_t)ph.g.n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (rounds) *rounds = ph.colour_rounds;
   return LV_OK;
 }
 

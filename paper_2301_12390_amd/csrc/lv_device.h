@@ -63,12 +63,15 @@ __host__ __device__ inline int bucket_of(int64_t len) {
 // sequence started at state p (Steele, Lea, Flood 2014: s = mix(p + (v+1) * golden gamma)).
 constexpr int kMaxClasses = 32;
 
-__host__ __device__ inline int vertex_class(int32_t pass, int32_t K, int64_t v) {
+__host__ __device__ inline uint64_t vertex_draw(int32_t pass, int64_t v) {
   uint64_t z = (uint64_t)(uint32_t)pass + ((uint64_t)v + 1u) * 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return (int)(((z >> 32) * (uint64_t)(uint32_t)K) >> 32);
+  return z ^ (z >> 31);
+}
+
+__host__ __device__ inline int vertex_class(int32_t pass, int32_t K, int64_t v) {
+  return (int)(((vertex_draw(pass, v) >> 32) * (uint64_t)(uint32_t)K) >> 32);
 }
 
 // Community state of the local-moving phase, one record per index x in [0, n): the community

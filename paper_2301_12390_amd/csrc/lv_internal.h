@@ -97,8 +97,9 @@ hipError_t unpack_state(int64_t n, const void* rec, int32_t* C, uint64_t* Sig, i
 // host_counts: 1536 pinned words. Host result in `b` (synchronises the stream).
 hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
                        int K, int pass, const int32_t* gid, const int64_t* gbase,
-                       const uint8_t* act, int32_t* list, unsigned long long* counts,
-                       unsigned long long* host_counts, Buckets& b, hipStream_t s);
+                       const uint8_t* act, const uint8_t* vclass, int32_t* list,
+                       unsigned long long* counts, unsigned long long* host_counts, Buckets& b,
+                       hipStream_t s);
 // Two-phase plan for the items items[0 .. nh) (lengths from rs/re, or len[item]) whose keys
 // take at most `cap` distinct values; vb: value bytes; merge: one-chunk items need no phase 2.
 // arrays: kPlanWords * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.
@@ -218,6 +219,24 @@ hipError_t localize_membership(int32_t* memb, int64_t n, const int32_t* gid0,
 // *bad |= 1 if a graph's first arc is not at aptr[g], |= 2 if an arc leaves its graph.
 hipError_t validate_batch(const DevGraph& g, const int32_t* gid, const int64_t* gbase,
                           const int64_t* aptr, int64_t G, unsigned int* bad, hipStream_t s);
+
+// ---- colour classes (lv_colour.hip)
+struct ColourBuffers {
+  int32_t* cnt = nullptr;      // [n] uncoloured higher-priority neighbours
+  int64_t* flag = nullptr;     // [n] ready flags of a round
+  int64_t* pos = nullptr;      // [n+1] their scan
+  int64_t* partial = nullptr;  // scan partials for n elements
+  int32_t* shorts = nullptr;   // [n] ready vertices with short rows
+  int32_t* longs = nullptr;    // [n] ready vertices with long rows
+  unsigned long long* nlong = nullptr;  // [1]
+};
+// Class of every vertex of pass `pass` (K classes): first-fit colouring in descending priority
+// order, colours 0..K-2, the rest class K-1 (gid/gbase: ids local to each graph of a batch).
+// host_words: pinned host words for read-backs; rounds: Jones-Plassmann rounds taken.
+hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid,
+                          const int64_t* gbase, const ColourBuffers& cb,
+                          unsigned long long* host_words, uint8_t* colour, int* rounds,
+                          hipStream_t s);
 
 // ---- graph preparation (lv_prep.hip)
 constexpr uint32_t kPrepSym = 0x1u, kPrepLoops = 0x2u, kPrepMax = 0x4u;

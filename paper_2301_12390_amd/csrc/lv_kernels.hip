@@ -520,10 +520,17 @@ constexpr int kMaxSeg = kDegClasses * kMaxClasses;
 // Vertex classes hash the id of a vertex within its own graph: i - gbase[gid[i]] in a batch of
 // graphs packed with consecutive ids (gid null: one graph). In a batch, rows of graphs that are
 // not iterating (act[gid[i]] == 0) are left out of the lists.
+// vclass (may be null): the class of every vertex given (colour classes), instead of the hash.
 __device__ __forceinline__ int segment_of(int64_t L, int K, int pass, int64_t i,
-                                          const int32_t* gid, const int64_t* gbase) {
-  const int64_t loc = gid ? i - gbase[gid[i]] : i;
-  const int k = K > 1 ? vertex_class(pass, K, loc) : 0;
+                                          const int32_t* gid, const int64_t* gbase,
+                                          const uint8_t* vclass) {
+  int k = 0;
+  if (vclass) {
+    k = vclass[i];
+  } else if (K > 1) {
+    const int64_t loc = gid ? i - gbase[gid[i]] : i;
+    k = vertex_class(pass, K, loc);
+  }
   return kDegClasses * k + bucket_of(L);
 }
 
@@ -537,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, cons
                                                         const int64_t* len, int64_t m, int K,
                                                         int pass, const int32_t* gid,
                                                         const int64_t* gbase, const uint8_t* act,
-                                                        ull* counts) {
+                                                        const uint8_t* vclass, ull* counts) {
   __shared__ ull c[2 * kMaxSeg];
   const int nseg = kDegClasses * K;
   for (int t = threadIdx.x; t < 2 * kMaxSeg; t += blockDim.x) c[t] = 0;
@@ -546,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, cons
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t L = item_len(rs, re, len, i);
     if (listed(L, i, gid, act)) {
-      const int sg = segment_of(L, K, pass, i, gid, gbase);
+      const int sg = segment_of(L, K, pass, i, gid, gbase, vclass);
       atomicAdd(&c[sg], 1ull);
       atomicAdd(&c[kMaxSeg + sg], (ull)L);
     }
@@ -563,8 +570,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const
                                                        const int64_t* len, int64_t m, int K,
                                                        int pass, const int32_t* gid,
                                                        const int64_t* gbase, const uint8_t* act,
-                                                       const ull* starts, ull* cursor,
-                                                       int32_t* list) {
+                                                       const uint8_t* vclass, const ull* starts,
+                                                       ull* cursor, int32_t* list) {
   __shared__ int cnt[kMaxSeg];
   __shared__ ull base[kMaxSeg];
   const int nseg = kDegClasses * K;
@@ -577,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const
     if (i < m) {
       const int64_t L = item_len(rs, re, len, i);
       if (listed(L, i, gid, act)) {
-        sg = segment_of(L, K, pass, i, gid, gbase);
+        sg = segment_of(L, K, pass, i, gid, gbase, vclass);
         rank = atomicAdd(&cnt[sg], 1);
       }
     }
@@ -592,8 +599,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const
 
 hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len, int64_t m,
                        int K, int pass, const int32_t* gid, const int64_t* gbase,
-                       const uint8_t* act, int32_t* list, ull* counts, ull* host_counts,
-                       Buckets& b, hipStream_t s) {
+                       const uint8_t* act, const uint8_t* vclass, int32_t* list, ull* counts,
+                       ull* host_counts, Buckets& b, hipStream_t s) {
   b = Buckets();
   b.classes = K;
   if (m <= 0) return hipSuccess;
@@ -601,7 +608,7 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
   // counts layout (kMaxSeg words each): items, lengths, fill cursors, segment starts
   LV_LAUNCH(k_zero_words, 8, kBlock, 0, s, counts, (int64_t)(3 * kMaxSeg));
   LV_LAUNCH(k_bucket_count, grid_for(m, kBlock, 4096), kBlock, 0, s, rs, re, len, m, K, pass,
-            gid, gbase, act, counts);
+            gid, gbase, act, vclass, counts);
   hipError_t e = hipMemcpyAsync(host_counts, counts, 2 * kMaxSeg * sizeof(ull),
                                 hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
@@ -621,7 +628,7 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
                      s);
   if (e != hipSuccess) return e;
   LV_LAUNCH(k_bucket_fill, grid_for(m, kBlock, 8192), kBlock, 0, s, rs, re, len, m, K, pass,
-            gid, gbase, act, counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
+            gid, gbase, act, vclass, counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
   return hipGetLastError();
 }
 

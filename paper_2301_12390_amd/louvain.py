@@ -22,6 +22,7 @@ LV_VALIDATE = 0x1
 LV_TRACE = 0x2
 LV_FORCE_WIDE = 0x4
 LV_SMALL_PARTS = 0x8
+LV_COLOR_CLASSES = 0x10
 
 LV_MAX_PASSES = 64
 LV_MAX_TRACE = 1024
@@ -165,6 +166,9 @@ SIGNATURES = {
                                        ctypes.c_int32, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(LvPrepStats), _P]),
+    "louvain_colour_classes": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.c_int32,
+                                              ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int32),
+                                              _P]),
     "louvain_move": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.c_uint64,
                                     ctypes.c_int32, ctypes.POINTER(LvParams), _P, _P, _P,
                                     ctypes.POINTER(LvMoveStats), _P]),
@@ -366,6 +370,16 @@ class Louvain:
                                          ctypes.byref(nl), ctypes.byref(r), _stream())
         self._check(st)
         return membership[:g.n], levels[:nl.value, :g.n], result_dict(r)
+
+    def colour_classes(self, g, pass_index=0, K=DEFAULT_SUBSTEPS):
+        """Colour class of every vertex (uint8 tensor [n]) and the rounds taken."""
+        gs = graph_struct(g)
+        out = torch.empty(max(g.n, 1), dtype=torch.uint8, device=g.indices.device)
+        rounds = ctypes.c_int32(0)
+        st = self.lib.louvain_colour_classes(self.h, ctypes.byref(gs), pass_index, K, _ptr(out),
+                                             ctypes.byref(rounds), _stream())
+        self._check(st)
+        return out[:g.n], rounds.value
 
     def prepare(self, n, src, dst, weights=None, flags=LV_PREP_PAPER, offsets_64=True,
                 weights_64=False, capacity=None) -> PreparedGraph:
