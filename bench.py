@@ -663,6 +663,49 @@ def run_prepare_bench(args, dev):
     print(json.dumps(line), flush=True)
 
 
+def run_colour_bench(args, dev, g):
+    """Colour classes (LV_COLOR_CLASSES) on the workload graph: louvain_colour_classes for pass
+    0 timed on its own (a step), then one whole run with colour classes beside one with hashed
+    classes (Q, iterations, time)."""
+    import torch
+
+    from paper_2301_12390_amd import LV_COLOR_CLASSES, Louvain
+
+    lv = Louvain(0)
+    K = args.substeps
+    for _ in range(args.warmup):
+        lv.colour_classes(g, 0, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        c, rounds = lv.colour_classes(g, 0, K)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    sizes = torch.bincount(c.to(torch.int64), minlength=K).cpu().tolist()
+    log(f"colouring: {ms:.1f} ms, {rounds} rounds enqueued, class sizes {sizes}")
+    runs = {}
+    for name, fl in (("colour", LV_COLOR_CLASSES), ("hash", 0)):
+        lv.run(g, substeps=K, flags=fl)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, r = lv.run(g, substeps=K, flags=fl)
+        torch.cuda.synchronize()
+        runs[name] = {"ms": (time.perf_counter() - t1) * 1000.0, "q": r["q"],
+                      "passes": r["passes"], "iterations": r["iterations"]}
+        log(f"run with {name} classes: {runs[name]}")
+    lv.close()
+    line = {
+        "metric": METRIC, "value": g.n / (ms / 1000.0), "unit": "vertices coloured/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"colour-{args.workload}", "n": g.n, "nnz": g.nnz, "K": K,
+                   "rounds_enqueued": rounds, "class_sizes": sizes, "runs": runs},
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -695,6 +738,12 @@ def main():
                          "requests at --rates, p50/p99 latency), sweep (tolerance and "
                          "decline-factor study) or prepare (graph preparation of a raw R-MAT "
                          "edge list of --prep-scale)")
+    ap.add_argument("--colour-bench", action="store_true",
+                    help="time the colouring behind LV_COLOR_CLASSES on the workload graph, and "
+                         "one run with colour classes beside one with hashed classes")
+    ap.add_argument("--colour-classes", action="store_true",
+                    help="vertex classes from the device colouring (LV_COLOR_CLASSES) instead "
+                         "of the hash")
     ap.add_argument("--substeps", type=int, default=8,
                     help="vertex classes per local-moving iteration (1 = fully synchronous)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -734,7 +783,7 @@ def main():
     import torch
 
     from graphgen import config_graph
-    from paper_2301_12390_amd import LV_TRACE, Louvain
+    from paper_2301_12390_amd import LV_COLOR_CLASSES, LV_TRACE, Louvain
     from paper_2301_12390_amd import build as lib_build
 
     if not os.path.exists(lib_build.LIB):
@@ -767,19 +816,23 @@ def main():
     torch.cuda.empty_cache()
     if args.steps <= 0:
         return
+    if args.colour_bench:
+        run_colour_bench(args, dev, g)
+        return
 
     calibration_copy(args, dev)
 
     lv = Louvain(0)
+    run_flags = LV_TRACE | (LV_COLOR_CLASSES if args.colour_classes else 0)
     for w in range(args.warmup):
-        _, res = lv.run(g, substeps=args.substeps, flags=LV_TRACE)
+        _, res = lv.run(g, substeps=args.substeps, flags=run_flags)
         log(f"warmup {w}: {res['total_ms']:.1f} ms, Q={res['q']:.6f}, passes={res['passes']}, "
             f"iterations={res['iterations']}")
     torch.cuda.synchronize()
     results = []
     t_start = time.perf_counter()
     for k in range(args.steps):
-        memb, res = lv.run(g, substeps=args.substeps, flags=LV_TRACE)
+        memb, res = lv.run(g, substeps=args.substeps, flags=run_flags)
         results.append(res)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -834,6 +887,7 @@ def main():
             "offsets": str(g.offsets.dtype).replace("torch.", ""),
             "tolerance": "1e-2, declining x10 per pass",
             "substeps": args.substeps,
+            "classes": "colour" if args.colour_classes else "hash",
             "passes": r0["passes"],
             "iterations": r0["iterations"],
             "n_per_pass": r0["n_pass"],

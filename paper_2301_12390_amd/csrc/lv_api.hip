@@ -27,7 +27,7 @@ enum SlotId {
   S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
   S_REC, S_GID0, S_GIDA, S_GIDB, S_GBASE, S_GWORDS, S_GACT, S_APTR, S_PKEY0, S_PKEY1, S_PVAL0,
   S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
-  S_VCLASS, S_CCNT, S_CFLAG, S_CPOS, S_CSHORT, S_CLONG, S_CNLONG, S_COUNT_SLOTS
+  S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -265,12 +265,10 @@ lv_status colour_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   lv::ColourBuffers cb;
   CHK(wst(ctx, S_VCLASS, n, &vc));
   CHK(wst(ctx, S_CCNT, n, &cb.cnt));
-  CHK(wst(ctx, S_CFLAG, n, &cb.flag));
-  CHK(wst(ctx, S_CPOS, n + 1, &cb.pos));
-  CHK(wst(ctx, S_CSHORT, n, &cb.shorts));
-  CHK(wst(ctx, S_CLONG, n, &cb.longs));
-  CHK(wst(ctx, S_CNLONG, 1, &cb.nlong));
-  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &cb.partial));
+  CHK(wst(ctx, S_CFLAG, n, &cb.all_long));
+  CHK(wst(ctx, S_CSHORT, 2 * n, &cb.shorts));
+  CHK(wst(ctx, S_CLONG, 2 * n, &cb.longs));
+  CHK(wst(ctx, S_CNLONG, 7, &cb.counts));
   HIPCHK(lv::colour_classes(ph.g, ph.classes, ph.pass, ph.m.gs.gid, ph.m.gs.gbase, cb,
                             ctx->pinned + PIN_MISC, vc, &ph.colour_rounds, s));
   ph.vclass = vc;

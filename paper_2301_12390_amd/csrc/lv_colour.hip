@@ -11,11 +11,16 @@
 // coloured before it and no lower neighbour is, so the result equals the sequential first-fit
 // in priority order, whatever the schedule.
 //
-// Per vertex a counter of uncoloured higher-priority neighbours; each round lists the vertices
-// whose counter is zero (a flag scan and compaction, no contended appends), colours them, and
-// decrements the counters of their lower-priority neighbours. Rows of up to kColShortRow arcs
-// take a group of 16 lanes, longer ones a 1024-thread workgroup.
+// Per vertex a counter of uncoloured higher-priority neighbours. The vertices whose counter is
+// zero form the frontier of a round; colouring a vertex decrements the counters of its
+// lower-priority neighbours, and the decrement that reaches zero appends that neighbour to the
+// next round's frontier (appends aggregated per wavefront). Rounds are enqueued in batches
+// with no host synchronisation inside a batch: each kernel reads its frontier's size from
+// device memory. Rows of up to kColShortRow arcs take a group of 16 lanes, longer ones a
+// 1024-thread workgroup.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "lv_device.h"
 #include "lv_internal.h"
@@ -33,6 +38,10 @@ constexpr int64_t kColShortRow = 256;
 constexpr int kColGroup = 16;
 constexpr int kColBlock = 1024;
 constexpr uint8_t kUncoloured = 0xFF;
+constexpr int kColBatch = 32;          // rounds enqueued between two looks from the host
+constexpr unsigned kColRoundBlocks = 2048;  // largest grid of a short-row round (grid-stride)
+constexpr unsigned kColMinBlocks = 8;       // smallest
+constexpr unsigned kColLongBlocks = 256;    // largest grid of a long-row round
 
 inline unsigned blocks_for(int64_t items, int64_t per_block) {
   int64_t b = (items + per_block - 1) / per_block;
@@ -63,9 +72,31 @@ struct ColArgs {
   uint8_t* colour;   // class, kUncoloured before
 };
 
+// The frontiers: two alternating lists of each kind (short rows, long rows) and three
+// rotating counters of each kind (round r reads counter r % 3, appends to (r + 1) % 3 and
+// clears (r + 2) % 3 for the round after).
+struct Frontier {
+  int32_t* shorts[2];
+  int32_t* longs[2];
+  ull* counts;  // [6]: short counters 0..2, long counters 3..5
+};
+
+// Appends u (where `want`) to the list, one atomic per wavefront.
+__device__ __forceinline__ void append(bool want, int32_t u, int32_t* list, ull* counter) {
+  const uint64_t bal = __ballot(want);
+  if (!bal) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)bal) - 1;
+  ull base = 0;
+  if (lane == leader) base = atomicAdd(counter, (ull)__popcll(bal));
+  base = __shfl(base, leader, 64);
+  if (want) list[base + __popcll(bal & ((1ull << lane) - 1))] = u;
+}
+
 // Counters of every vertex (groups of kColGroup lanes); rows longer than kColShortRow are
 // counted by k_col_count_long, their ids appended to `longs`.
-__global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs, ull* nlong) {
+__global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs, ull* nlong,
+                                                     Frontier f) {
   const int lane = threadIdx.x & (kColGroup - 1);
   const int64_t groups = (int64_t)gridDim.x * (kBlock / kColGroup);
   for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kColGroup; v < a.n;
@@ -89,10 +120,12 @@ __global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs,
       a.cnt[v] = c;
       a.colour[v] = kUncoloured;
     }
+    append(lane == 0 && c == 0, (int32_t)v, f.shorts[0], f.counts);  // round 0's frontier
   }
 }
 
-__global__ __launch_bounds__(kColBlock) void k_col_count_long(ColArgs a, const int32_t* longs) {
+__global__ __launch_bounds__(kColBlock) void k_col_count_long(ColArgs a, const int32_t* longs,
+                                                              Frontier f) {
   __shared__ int red[kColBlock / 64];
   const int64_t v = longs[blockIdx.x];
   const uint64_t pv = vertex_draw(a.pass, local_id(v, a.gid, a.gbase));
@@ -108,28 +141,7 @@ __global__ __launch_bounds__(kColBlock) void k_col_count_long(ColArgs a, const i
     int t = 0;
     for (int i = 0; i < kColBlock / 64; i++) t += red[i];
     a.cnt[v] = t;
-  }
-}
-
-// Ready vertices of the round: uncoloured with no uncoloured higher neighbour. flag[v] counts
-// them for the short list (low 32 bits) or the long list (high 32 bits).
-__global__ void k_col_ready(ColArgs a, int64_t* flag) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < a.n;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    int64_t f = 0;
-    if (a.colour[v] == kUncoloured && a.cnt[v] == 0)
-      f = a.re[v] - a.rs[v] > kColShortRow ? ((int64_t)1 << 32) : 1;
-    flag[v] = f;
-  }
-}
-
-__global__ void k_col_compact(int64_t n, const int64_t* flag, const int64_t* pos,
-                              int32_t* shorts, int32_t* longs) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t f = flag[v];
-    if (f == 1) shorts[pos[v] & 0xffffffffll] = (int32_t)v;
-    if (f > 1) longs[pos[v] >> 32] = (int32_t)v;
+    if (t == 0) f.longs[0][atomicAdd(f.counts + 3, 1ull)] = (int32_t)v;
   }
 }
 
@@ -140,54 +152,92 @@ __device__ __forceinline__ uint8_t first_fit(uint32_t used, int K) {
   return avail ? (uint8_t)__ffs(avail) - 1 : (uint8_t)(K - 1);
 }
 
-// Colour the listed vertices: their higher neighbours are all coloured (earlier rounds); lower
-// neighbours lose one uncoloured higher neighbour each, to be listed in a later round.
-__global__ __launch_bounds__(kBlock) void k_col_colour(ColArgs a, const int32_t* list,
-                                                      int64_t count) {
+// Appends a vertex whose counter reached zero to the frontier of round `next`.
+__device__ __forceinline__ void append_ready(const ColArgs& a, bool want, int64_t u,
+                                             const Frontier& f, int next) {
+  const bool lng = want && a.re[u] - a.rs[u] > kColShortRow;
+  append(want && !lng, (int32_t)u, f.shorts[next & 1], f.counts + next % 3);
+  append(lng, (int32_t)u, f.longs[next & 1], f.counts + 3 + next % 3);
+}
+
+// Colour one vertex whose higher neighbours are all coloured, with `lanes` threads from
+// `lane`: the colours those neighbours hold (bit mask, OR-reduced by the caller), and the
+// decrements of its lower neighbours' counters. kColUnroll arcs per thread per trip, their
+// loads issued together (the rounds along the priority order's longest chain are bound by
+// this latency).
+constexpr int kColUnroll = 4;
+
+__device__ __forceinline__ uint32_t colour_scan(const ColArgs& a, int64_t v, int lane, int lanes,
+                                                const Frontier& f, int next) {
+  const uint64_t pv = vertex_draw(a.pass, local_id(v, a.gid, a.gbase));
+  uint32_t used = 0;
+  const int64_t b = a.rs[v], e = a.re[v];
+  for (int64_t x0 = b; x0 < e; x0 += (int64_t)lanes * kColUnroll) {
+    int64_t u[kColUnroll];
+    bool higher[kColUnroll], lower[kColUnroll];
+#pragma unroll
+    for (int k = 0; k < kColUnroll; k++) {
+      const int64_t x = x0 + (int64_t)k * lanes + lane;
+      u[k] = x < e ? a.idx[x] : v;
+    }
+#pragma unroll
+    for (int k = 0; k < kColUnroll; k++) {
+      const bool other = u[k] != v;
+      const bool h =
+          other && precedes(vertex_draw(a.pass, local_id(u[k], a.gid, a.gbase)), u[k], pv, v);
+      higher[k] = h;
+      lower[k] = other && !h;
+    }
+    uint8_t cu[kColUnroll];
+    bool ready[kColUnroll];
+#pragma unroll
+    for (int k = 0; k < kColUnroll; k++) {
+      cu[k] = higher[k] ? a.colour[u[k]] : kUncoloured;
+      ready[k] = lower[k] ? atomicSub(&a.cnt[u[k]], 1) == 1 : false;
+    }
+#pragma unroll
+    for (int k = 0; k < kColUnroll; k++) {
+      if (cu[k] < a.K - 1) used |= 1u << cu[k];
+      append_ready(a, ready[k], u[k], f, next);
+    }
+  }
+  return used;
+}
+
+// Round r, rows up to kColShortRow: groups of kColGroup lanes over the short frontier. Block 0
+// clears the counters of round r + 2.
+__global__ __launch_bounds__(kBlock) void k_col_round(ColArgs a, Frontier f, int r) {
+  if (blockIdx.x == 0 && threadIdx.x < 2) f.counts[3 * threadIdx.x + (r + 2) % 3] = 0;
+  const int64_t count = (int64_t)f.counts[r % 3];
+  const int32_t* list = f.shorts[r & 1];
   const int lane = threadIdx.x & (kColGroup - 1);
   const int64_t groups = (int64_t)gridDim.x * (kBlock / kColGroup);
   for (int64_t t = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kColGroup; t < count;
        t += groups) {
     const int64_t v = list[t];
-    const uint64_t pv = vertex_draw(a.pass, local_id(v, a.gid, a.gbase));
-    uint32_t used = 0;
-    for (int64_t x = a.rs[v] + lane; x < a.re[v]; x += kColGroup) {
-      const int64_t u = a.idx[x];
-      if (u == v) continue;
-      if (precedes(vertex_draw(a.pass, local_id(u, a.gid, a.gbase)), u, pv, v)) {
-        const uint8_t cu = a.colour[u];
-        if (cu < a.K - 1) used |= 1u << cu;
-      } else {
-        atomicSub(&a.cnt[u], 1);
-      }
-    }
+    uint32_t used = colour_scan(a, v, lane, kColGroup, f, r + 1);
     for (int m = kColGroup / 2; m >= 1; m >>= 1) used |= __shfl_xor(used, m, kColGroup);
     if (lane == 0) a.colour[v] = first_fit(used, a.K);
   }
 }
 
-__global__ __launch_bounds__(kColBlock) void k_col_colour_long(ColArgs a, const int32_t* list) {
+// Round r, long rows: one workgroup per vertex of the long frontier.
+__global__ __launch_bounds__(kColBlock) void k_col_round_long(ColArgs a, Frontier f, int r) {
   __shared__ uint32_t red[kColBlock / 64];
-  const int64_t v = list[blockIdx.x];
-  const uint64_t pv = vertex_draw(a.pass, local_id(v, a.gid, a.gbase));
-  uint32_t used = 0;
-  for (int64_t x = a.rs[v] + threadIdx.x; x < a.re[v]; x += kColBlock) {
-    const int64_t u = a.idx[x];
-    if (u == v) continue;
-    if (precedes(vertex_draw(a.pass, local_id(u, a.gid, a.gbase)), u, pv, v)) {
-      const uint8_t cu = a.colour[u];
-      if (cu < a.K - 1) used |= 1u << cu;
-    } else {
-      atomicSub(&a.cnt[u], 1);
+  const int64_t count = (int64_t)f.counts[3 + r % 3];
+  const int32_t* list = f.longs[r & 1];
+  for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const int64_t v = list[t];
+    uint32_t used = colour_scan(a, v, threadIdx.x, kColBlock, f, r + 1);
+    for (int m = 32; m >= 1; m >>= 1) used |= __shfl_xor(used, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = used;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t u = 0;
+      for (int i = 0; i < kColBlock / 64; i++) u |= red[i];
+      a.colour[v] = first_fit(u, a.K);
     }
-  }
-  for (int m = 32; m >= 1; m >>= 1) used |= __shfl_xor(used, m, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = used;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t u = 0;
-    for (int i = 0; i < kColBlock / 64; i++) u |= red[i];
-    a.colour[v] = first_fit(u, a.K);
+    __syncthreads();
   }
 }
 
@@ -200,37 +250,40 @@ hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid
   const int64_t n = g.n;
   if (n <= 0) return hipSuccess;
   ColArgs a{g.rs, g.re, g.idx, n, pass, K, gid, gbase, cb.cnt, colour};
+  Frontier f{{cb.shorts, cb.shorts + n}, {cb.longs, cb.longs + n}, cb.counts};
   hipError_t e;
-  if ((e = zero_words(cb.nlong, 1, s)) != hipSuccess) return e;
-  LV_LAUNCH(k_col_count, blocks_for(n, kBlock / kColGroup), kBlock, 0, s, a, cb.longs,
-            cb.nlong);
-  if ((e = hipMemcpyAsync(host_words, cb.nlong, sizeof(ull), hipMemcpyDeviceToHost, s)) !=
+  if ((e = zero_words(cb.counts, 7, s)) != hipSuccess) return e;  // 6 counters + nlong
+  ull* nlong = cb.counts + 6;
+  LV_LAUNCH(k_col_count, blocks_for(n, kBlock / kColGroup), kBlock, 0, s, a, cb.all_long, nlong,
+            f);
+  if ((e = hipMemcpyAsync(host_words, nlong, sizeof(ull), hipMemcpyDeviceToHost, s)) !=
       hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   if (host_words[0] > 0)
-    LV_LAUNCH(k_col_count_long, (unsigned)host_words[0], kColBlock, 0, s, a, cb.longs);
-  int64_t left = n;
-  while (left > 0) {
-    LV_LAUNCH(k_col_ready, blocks_for(n, kBlock), kBlock, 0, s, a, cb.flag);
-    if ((e = scan_i64(cb.flag, n, cb.pos, cb.partial, s)) != hipSuccess) return e;
-    LV_LAUNCH(k_col_compact, blocks_for(n, kBlock), kBlock, 0, s, n, cb.flag, cb.pos,
-              cb.shorts, cb.longs);
-    if ((e = hipMemcpyAsync(host_words, cb.pos + n, sizeof(int64_t), hipMemcpyDeviceToHost,
-                            s)) != hipSuccess)
+    LV_LAUNCH(k_col_count_long, (unsigned)host_words[0], kColBlock, 0, s, a, cb.all_long, f);
+  // rounds in batches; a batch ends with a look at the next round's frontier sizes, which also
+  // sizes the next batch's grids (any grid is correct: the kernels stride over their frontier)
+  int r = 0;
+  while (true) {
+    if ((e = hipMemcpyAsync(host_words, cb.counts, 6 * sizeof(ull), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
       return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const int64_t ns = (int64_t)(host_words[0] & 0xffffffffull);
-    const int64_t nl = (int64_t)(host_words[0] >> 32);
-    if (ns + nl == 0) return hipErrorUnknown;  // cannot happen: the priority order has no cycle
-    if (ns > 0)
-      LV_LAUNCH(k_col_colour, blocks_for(ns, kBlock / kColGroup), kBlock, 0, s, a, cb.shorts,
-                ns);
-    if (nl > 0) LV_LAUNCH(k_col_colour_long, (unsigned)nl, kColBlock, 0, s, a, cb.longs);
+    const ull ns = host_words[r % 3], nl = host_words[3 + r % 3];
+    if (ns == 0 && nl == 0) break;
+    if (r > n + kColBatch) return hipErrorUnknown;  // cannot happen: each round colours a vertex
+    const ull want_s = (ns + kBlock / kColGroup - 1) / (kBlock / kColGroup);
+    const unsigned gs = (unsigned)std::min<ull>(std::max<ull>(want_s, kColMinBlocks),
+                                                kColRoundBlocks);
+    const unsigned gl = (unsigned)std::min<ull>(std::max<ull>(nl, 1), kColLongBlocks);
+    for (int k = 0; k < kColBatch; k++, r++) {
+      LV_LAUNCH(k_col_round, gs, kBlock, 0, s, a, f, r);
+      LV_LAUNCH(k_col_round_long, gl, kColBlock, 0, s, a, f, r);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    left -= ns + nl;
-    (*rounds)++;
   }
+  *rounds = r;
   return hipSuccess;
 }
 

@@ -222,13 +222,11 @@ hipError_t validate_batch(const DevGraph& g, const int32_t* gid, const int64_t* 
 
 // ---- colour classes (lv_colour.hip)
 struct ColourBuffers {
-  int32_t* cnt = nullptr;      // [n] uncoloured higher-priority neighbours
-  int64_t* flag = nullptr;     // [n] ready flags of a round
-  int64_t* pos = nullptr;      // [n+1] their scan
-  int64_t* partial = nullptr;  // scan partials for n elements
-  int32_t* shorts = nullptr;   // [n] ready vertices with short rows
-  int32_t* longs = nullptr;    // [n] ready vertices with long rows
-  unsigned long long* nlong = nullptr;  // [1]
+  int32_t* cnt = nullptr;       // [n] uncoloured higher-priority neighbours
+  int32_t* all_long = nullptr;  // [n] vertices with long rows
+  int32_t* shorts = nullptr;    // [2n] two alternating frontiers of short-row vertices
+  int32_t* longs = nullptr;     // [2n] two alternating frontiers of long-row vertices
+  unsigned long long* counts = nullptr;  // [7] frontier counters and the long-row count
 };
 // Class of every vertex of pass `pass` (K classes): first-fit colouring in descending priority
 // order, colours 0..K-2, the rest class K-1 (gid/gbase: ids local to each graph of a batch).
