@@ -360,3 +360,42 @@ def prepare_row(n: int, src, dst, w, flags: int, r: int):
     else:
         np.add.at(acc, inv, ws)
     return uniq.astype(np.int32), acc
+
+
+# ----------------------------------------------------------------------------------------------
+# partition and merge (section 3.2 and the conclusion: run partitions independently, combine)
+
+
+def balanced_parts(g: Graph, P: int):
+    """Contiguous parts balanced by arcs: part k starts at the least vertex v with
+    off[v] >= floor(k * nnz / P) (part 0 at 0, the end at n)."""
+    nnz = int(g.off[-1]) if g.n else 0
+    vptr = [0]
+    for k in range(1, P):
+        vptr.append(int(np.searchsorted(g.off[:g.n], (k * nnz) // P, side="left")))
+    vptr.append(g.n)
+    return vptr
+
+
+def run_partitioned(g: Graph, vptr, mode: str = "sync", a: int = 2, b: int = 1,
+                    max_iterations: int = 20, max_passes: int = 10, substeps: int = 1,
+                    nthreads: int = 0):
+    """Partition and merge over the contiguous parts [vptr[k], vptr[k+1]). Returns
+    (membership int32[n], merge result dict, [per part: {"n_communities", "qnum"}])."""
+    P = len(vptr) - 1
+    vp = np.ascontiguousarray(vptr, dtype=np.int64)
+    top = np.zeros(max(g.n, 1), dtype=np.int32)
+    comms = np.zeros(max(P, 1), dtype=np.int64)
+    pq = np.zeros(2 * max(P, 1), dtype=np.uint64)
+    r = OrcResult()
+    lib().orc_run_partitioned(*g.args(), ctypes.c_int32(P), _p(vp),
+                              ctypes.c_int32(0 if mode == "sync" else 1), ctypes.c_int32(a),
+                              ctypes.c_int32(b), ctypes.c_int32(max_iterations),
+                              ctypes.c_int32(max_passes), ctypes.c_int32(substeps),
+                              ctypes.c_int32(nthreads), _p(top), _p(comms), _p(pq),
+                              ctypes.byref(r))
+    res = {"passes": r.passes, "iterations": [r.iterations[p] for p in range(r.passes)],
+           "n_communities": r.n_communities, "W": r.W, "qnum": _i128(r.qnum[0], r.qnum[1])}
+    parts = [{"n_communities": int(comms[k]), "qnum": _i128(int(pq[2 * k]), int(pq[2 * k + 1]))}
+             for k in range(P)]
+    return top[:g.n].copy(), res, parts

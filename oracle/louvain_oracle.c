@@ -730,3 +730,67 @@ int64_t orc_prepare(int64_t n, int64_t m, const int32_t* src, const int32_t* dst
   free(a);
   return nnz;
 }
+
+/* ---------------------------------------------------------------------------------------------
+ * Partition and merge (the remedy the paper proposes in section 3.2 and its conclusion for the
+ * poor multi-threaded scaling: run partitions of the graph independently, then combine them).
+ * Parts are the contiguous vertex ranges [vptr[k], vptr[k+1]). Each part's induced subgraph
+ * (the arcs with both ends in the part, ids local to the part) runs the whole method on its own
+ * (orc_run with the given rule and parameters). The part communities, numbered part after part,
+ * partition the whole graph; the whole graph (every arc, cross-part ones included) is
+ * aggregated by that partition, and the method runs again on the super-vertex graph: the merge.
+ * top[n]: the final membership (merge community of each vertex's part community).
+ * part_comms[P], part_qnum[2P] (may be NULL): communities and W_k^2 Q_k of every part's run;
+ * res: the merge run's result (its Q is the final partition's Q on the whole graph). */
+int orc_run_partitioned(int64_t n, const int64_t* off, const int32_t* idx, const uint64_t* w,
+                        int32_t P, const int64_t* vptr, int32_t mode, int32_t a, int32_t b,
+                        int32_t max_it, int32_t max_pass, int32_t substeps, int32_t nthreads,
+                        int32_t* top, int64_t* part_comms, uint64_t* part_qnum,
+                        orc_result* res) {
+  const int64_t nnz = n > 0 ? off[n] : 0;
+  int32_t* label = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* poff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int32_t* pidx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  uint64_t* pw = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1));
+  orc_result* pres = (orc_result*)malloc(sizeof(orc_result));
+  int64_t next_label = 0;
+  for (int32_t k = 0; k < P; k++) {
+    const int64_t v0 = vptr[k], v1 = vptr[k + 1], nk = v1 - v0;
+    /* the induced subgraph of part k, local ids */
+    int64_t e2 = 0;
+    poff[0] = 0;
+    for (int64_t v = v0; v < v1; v++) {
+      for (int64_t e = off[v]; e < off[v + 1]; e++)
+        if (idx[e] >= v0 && idx[e] < v1) {
+          pidx[e2] = (int32_t)(idx[e] - v0);
+          pw[e2] = w[e];
+          e2++;
+        }
+      poff[v - v0 + 1] = e2;
+    }
+    run_impl(nk, poff, pidx, pw, mode, a, b, max_it, max_pass, substeps, nthreads, 0,
+             label + v0, pres, NULL, 0, NULL);
+    for (int64_t v = v0; v < v1; v++) label[v] += (int32_t)next_label;
+    next_label += pres->n_communities;
+    if (part_comms) part_comms[k] = pres->n_communities;
+    if (part_qnum) {
+      part_qnum[2 * k] = pres->qnum[0];
+      part_qnum[2 * k + 1] = pres->qnum[1];
+    }
+  }
+  /* the merge: aggregate the whole graph by the part communities, run on the super graph */
+  int32_t* map = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* soff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int32_t* sidx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  uint64_t* sw = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1));
+  int64_t sn = 0, snnz = 0;
+  if (n > 0) orc_aggregate(n, off, idx, w, label, map, soff, sidx, sw, &sn, &snnz);
+  else soff[0] = 0;
+  int32_t* stop = (int32_t*)malloc(sizeof(int32_t) * (size_t)(sn > 0 ? sn : 1));
+  run_impl(sn, soff, sidx, sw, mode, a, b, max_it, max_pass, substeps, nthreads, 0, stop, res,
+           NULL, 0, NULL);
+  for (int64_t v = 0; v < n; v++) top[v] = stop[map[v]];
+  free(stop); free(sw); free(sidx); free(soff); free(map);
+  free(pres); free(pw); free(pidx); free(poff); free(label);
+  return 0;
+}

@@ -54,6 +54,12 @@ MUTATIONS = {
     "colour_leftover_reuses_last": ("    int32_t c = K - 1;\n    for (int32_t k = 0; k < K - 1; k++)",
                                     "    int32_t c = K - 2;\n    for (int32_t k = 0; k < K - 1; k++)"),
     "colour_mask_shifted": ("used |= 1u << colour[u];", "used |= 2u << colour[u];"),
+    "partition_labels_not_offset": ("for (int64_t v = v0; v < v1; v++) label[v] += (int32_t)next_label;",
+                                    "for (int64_t v = v0; v < v1; v++) label[v] += 0;"),
+    "partition_merge_skipped": ("for (int64_t v = 0; v < n; v++) top[v] = stop[map[v]];",
+                                "for (int64_t v = 0; v < n; v++) top[v] = map[v];"),
+    "partition_keeps_part_edge": ("if (idx[e] >= v0 && idx[e] < v1) {",
+                                  "if (idx[e] >= v0 && idx[e] < v1 && idx[e] != v1 - 1) {"),
     "level_cap_off_by_one": ("if (levels && n_levels && *n_levels < max_levels) {",
                              "if (levels && n_levels && *n_levels + 1 < max_levels) {"),
 }
@@ -82,6 +88,10 @@ def battery():
     from . import test_oracle_colour as PC
     for K in (2, 8, 32):
         PC.test_matches_jones_plassmann_rounds(K)
+    from . import test_oracle_partition as PT
+    PT.test_two_triangles_hand_derived()
+    PT.test_components_as_parts(8)
+    PT.test_matches_composition(4)
     from . import test_oracle_prepare as PP
     PP.test_golden_small()
     for f in PP.FLAG_SETS:
