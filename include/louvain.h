@@ -252,6 +252,23 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
 lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, lv_i128* q_num,
                              uint64_t* W, double* q, void* stream);
 
+/* Partition and merge (the remedy section 3.2 and the conclusion propose for the method's poor
+ * shared-memory scaling: run partitions of the graph independently, then combine them). The P
+ * parts are contiguous vertex ranges: part_vptr (host) [P+1] from 0 to n, non-decreasing, or
+ * NULL for parts balanced by arcs (part k starts at the least v with offsets[v] >=
+ * floor(k * nnz / P)). Each part's induced subgraph (arcs with both ends in the part) runs the
+ * whole method on its own, with ids local to the part, all parts in one batch (as
+ * louvain_run_batched). Their communities, numbered part after part, partition the graph;
+ * the whole graph, cross-part arcs included, is aggregated by that partition and the method
+ * runs again on the super-vertex graph (the merge).
+ * membership: [n] out, the final community of every vertex (dense ids). per_part (host, may be
+ * NULL): [P] results of the part runs. merge_res (host): the merge run's result; its q_num and
+ * q are the final partition's on the whole graph. P in 1..2^20. Errors as louvain_run. */
+lv_status louvain_run_partitioned(lv_ctx* ctx, const lv_graph* g, int32_t P,
+                                  const int64_t* part_vptr, const lv_params* p,
+                                  int32_t* membership, lv_graph_result* per_part,
+                                  lv_result* merge_res, void* stream);
+
 /* Colour classes of a graph (LV_COLOR_CLASSES; section 3.2 cites graph colouring for partial
  * asynchrony): classes[v] in [0, K) for pass `pass` (>= 0) and K in 1..32 classes. Vertices
  * are visited in descending order of their SplitMix64 draws of the pass (the draw behind the

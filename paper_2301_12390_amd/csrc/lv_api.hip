@@ -27,7 +27,9 @@ enum SlotId {
   S_BAD, S_AGGOFF, S_BPART, S_MPART, S_MCOUNT, S_MSTART, S_MEMBERS, S_GSCAN, S_GRE0, S_GRE1,
   S_REC, S_GID0, S_GIDA, S_GIDB, S_GBASE, S_GWORDS, S_GACT, S_APTR, S_PKEY0, S_PKEY1, S_PVAL0,
   S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
-  S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_COUNT_SLOTS
+  S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
+  S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
+  S_PM_SIDX, S_PM_SW, S_PM_M2, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -1489,6 +1491,126 @@ lv_status louvain_colour_classes(lv_ctx* ctx, const lv_graph* g, int32_t pass, i
   HIPCHK(hipMemcpyAsync(classes, ph.vclass, (size_t)ph.g.n, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   if (rounds) *rounds = ph.colour_rounds;
+  return LV_OK;
+}
+
+// Partition and merge: the parts' induced subgraphs as one batch, their communities combined,
+// the whole graph aggregated by them and run once more.
+lv_status louvain_run_partitioned(lv_ctx* ctx, const lv_graph* g, int32_t P,
+                                  const int64_t* part_vptr, const lv_params* p,
+                                  int32_t* membership, lv_graph_result* per_part,
+                                  lv_result* merge_res, void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  CHK(check_params(ctx, p));
+  if (!merge_res) return fail(ctx, LV_EINVAL, "merge_res is NULL");
+  if (P < 1 || P > (1 << 20)) return fail(ctx, LV_EINVAL, "P must be in 1..2^20");
+  memset(merge_res, 0, sizeof(*merge_res));
+  if (per_part) memset(per_part, 0, sizeof(lv_graph_result) * (size_t)P);
+  hipStream_t s = (hipStream_t)stream;
+  lv::DevGraph dg;
+  CHK(import_graph(ctx, g, (p->flags & LV_VALIDATE) != 0, s, &dg));
+  const int64_t n = dg.n;
+  if (n > 0 && !membership) return fail(ctx, LV_EINVAL, "membership is NULL");
+  if (n == 0) return LV_OK;
+  // part bounds (host and device)
+  std::vector<int64_t> vptr((size_t)P + 1), aptr((size_t)P + 1);
+  int64_t* vptr_d = nullptr;
+  CHK(wst(ctx, S_PM_VPTR, (int64_t)P + 1, &vptr_d));
+  if (part_vptr) {
+    if (part_vptr[0] != 0 || part_vptr[P] != n)
+      return fail(ctx, LV_EINVAL, "part bounds must run from 0 to n");
+    for (int32_t k = 0; k < P; k++)
+      if (part_vptr[k + 1] < part_vptr[k]) return fail(ctx, LV_EINVAL, "part bounds decrease");
+    memcpy(vptr.data(), part_vptr, sizeof(int64_t) * ((size_t)P + 1));
+    HIPCHK(hipMemcpyAsync(vptr_d, vptr.data(), sizeof(int64_t) * ((size_t)P + 1),
+                          hipMemcpyHostToDevice, s));
+  } else {
+    HIPCHK(lv::part_bounds(dg.off, n, dg.nnz, P, vptr_d, s));
+    HIPCHK(hipMemcpyAsync(vptr.data(), vptr_d, sizeof(int64_t) * ((size_t)P + 1),
+                          hipMemcpyDeviceToHost, s));
+  }
+  // the induced union: arcs whose ends share a part, same vertex ids
+  int32_t* gid = nullptr;
+  int32_t* flag = nullptr;
+  int64_t* pos = nullptr;
+  int64_t* partial = nullptr;
+  int32_t* nidx = nullptr;
+  void* nw = nullptr;
+  int64_t* noff = nullptr;
+  int64_t* aptr_d = nullptr;
+  CHK(wst(ctx, S_PM_GID, n, &gid));
+  CHK(wst(ctx, S_PM_FLAG, dg.nnz, &flag));
+  CHK(wst(ctx, S_PM_POS, dg.nnz + 1, &pos));
+  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(dg.nnz + 1) + 1, &partial));
+  CHK(wst(ctx, S_PM_IDX, dg.nnz, &nidx));
+  CHK(ws(ctx, S_PM_W, (size_t)(dg.nnz > 0 ? dg.nnz : 1) * (dg.w64 ? 8 : 4), &nw));
+  CHK(wst(ctx, S_PM_OFF, n + 1, &noff));
+  CHK(wst(ctx, S_PM_APTR, (int64_t)P + 1, &aptr_d));
+  HIPCHK(lv::graph_ids(vptr_d, P, n, gid, s));
+  HIPCHK(lv::part_induced(dg, gid, vptr_d, P, flag, pos, partial, nidx, nw, noff, aptr_d, s));
+  HIPCHK(hipMemcpyAsync(aptr.data(), aptr_d, sizeof(int64_t) * ((size_t)P + 1),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // every part on its own: one batched run
+  lv_graph ug;
+  ug.n = n;
+  ug.nnz = aptr[P];
+  ug.offsets = noff;
+  ug.indices = nidx;
+  ug.weights = nw;
+  ug.offsets_64 = 1;
+  ug.weights_64 = dg.w64 ? 1 : 0;
+  lv_params inner = *p;
+  inner.flags &= ~(LV_VALIDATE | LV_TRACE);
+  int32_t* lab = nullptr;
+  CHK(wst(ctx, S_PM_LAB, n, &lab));
+  std::vector<lv_graph_result> pr((size_t)P);
+  CHK(louvain_run_batched(ctx, &ug, P, vptr.data(), aptr.data(), &inner, lab, pr.data(),
+                          stream));
+  if (per_part) memcpy(per_part, pr.data(), sizeof(lv_graph_result) * (size_t)P);
+  // part communities numbered part after part
+  std::vector<int64_t> loff((size_t)P);
+  int64_t acc = 0;
+  for (int32_t k = 0; k < P; k++) {
+    loff[k] = acc;
+    acc += pr[k].n_communities;
+  }
+  int64_t* loff_d = nullptr;
+  CHK(wst(ctx, S_PM_LOFF, P, &loff_d));
+  HIPCHK(hipMemcpyAsync(loff_d, loff.data(), sizeof(int64_t) * (size_t)P, hipMemcpyHostToDevice,
+                        s));
+  HIPCHK(lv::part_offset_labels(lab, n, gid, loff_d, s));
+  // the merge: the whole graph aggregated by the combined communities, then the method on it
+  int32_t* map = nullptr;
+  int64_t* soff = nullptr;
+  int32_t* sidx = nullptr;
+  uint64_t* sw = nullptr;
+  CHK(wst(ctx, S_PM_MAP, n, &map));
+  CHK(wst(ctx, S_PM_SOFF, n + 1, &soff));
+  CHK(wst(ctx, S_PM_SIDX, dg.nnz, &sidx));
+  CHK(wst(ctx, S_PM_SW, dg.nnz, &sw));
+  int64_t sn = 0, snnz = 0;
+  CHK(louvain_aggregate(ctx, g, lab, map, soff, 1, sidx, sw, &sn, &snnz, stream));
+  lv_graph sg;
+  sg.n = sn;
+  sg.nnz = snnz;
+  sg.offsets = soff;
+  sg.indices = sidx;
+  sg.weights = sw;
+  sg.offsets_64 = 1;
+  sg.weights_64 = 1;
+  int32_t* m2 = nullptr;
+  CHK(wst(ctx, S_PM_M2, sn, &m2));
+  lv_params mp = *p;
+  mp.flags &= ~LV_VALIDATE;
+  CHK(louvain_run(ctx, &sg, &mp, m2, merge_res, stream));
+  // final membership: the merge community of every vertex's combined part community
+  HIPCHK(hipMemcpyAsync(membership, map, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice,
+                        s));
+  HIPCHK(lv::compose_membership(membership, n, m2, s));
+  HIPCHK(hipStreamSynchronize(s));
   return LV_OK;
 }
 

@@ -220,6 +220,20 @@ hipError_t localize_membership(int32_t* memb, int64_t n, const int32_t* gid0,
 hipError_t validate_batch(const DevGraph& g, const int32_t* gid, const int64_t* gbase,
                           const int64_t* aptr, int64_t G, unsigned int* bad, hipStream_t s);
 
+// ---- partition and merge (lv_part.hip)
+// bounds[0..P]: contiguous parts balanced by arcs (bounds[k] = least v with
+// off[v] >= floor(k * nnz / P))
+hipError_t part_bounds(const int64_t* off, int64_t n, int64_t nnz, int64_t P, int64_t* bounds,
+                       hipStream_t s);
+// The union of the parts' induced subgraphs (same vertex ids): flag [nnz] and pos [nnz+1]
+// scratch, nidx/nw [nnz] (weights of g's width), noff [n+1], aptr [P+1] part arc bounds.
+hipError_t part_induced(const DevGraph& g, const int32_t* gid, const int64_t* vptr, int64_t P,
+                        int32_t* flag, int64_t* pos, int64_t* partial, int32_t* nidx, void* nw,
+                        int64_t* noff, int64_t* aptr, hipStream_t s);
+// lab[v] += loff[gid[v]]
+hipError_t part_offset_labels(int32_t* lab, int64_t n, const int32_t* gid, const int64_t* loff,
+                              hipStream_t s);
+
 // ---- colour classes (lv_colour.hip)
 struct ColourBuffers {
   int32_t* cnt = nullptr;       // [n] uncoloured higher-priority neighbours

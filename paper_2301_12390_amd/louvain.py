@@ -169,6 +169,10 @@ SIGNATURES = {
     "louvain_colour_classes": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.c_int32,
                                               ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int32),
                                               _P]),
+    "louvain_run_partitioned": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.c_int32,
+                                               _P, ctypes.POINTER(LvParams), _P,
+                                               ctypes.POINTER(LvGraphResult),
+                                               ctypes.POINTER(LvResult), _P]),
     "louvain_move": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.c_uint64,
                                     ctypes.c_int32, ctypes.POINTER(LvParams), _P, _P, _P,
                                     ctypes.POINTER(LvMoveStats), _P]),
@@ -370,6 +374,31 @@ class Louvain:
                                          ctypes.byref(nl), ctypes.byref(r), _stream())
         self._check(st)
         return membership[:g.n], levels[:nl.value, :g.n], result_dict(r)
+
+    def run_partitioned(self, g, P=8, vptr=None, tolerance_exp10=2, decline_exp10=1,
+                        max_iterations=20, max_passes=10, substeps=DEFAULT_SUBSTEPS, flags=0):
+        """Partition and merge over P contiguous parts (vptr: host bounds, or None for parts
+        balanced by arcs). Returns (membership int32 tensor [n], merge result dict, list of
+        per-part result dicts)."""
+        gs = graph_struct(g)
+        membership = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.indices.device)
+        vp = None
+        if vptr is not None:
+            if len(vptr) != P + 1:
+                raise ValueError("vptr must have P + 1 entries")
+            vp = (ctypes.c_int64 * (P + 1))(*[int(x) for x in vptr])
+        p = params_struct(tolerance_exp10, decline_exp10, max_iterations, max_passes, substeps,
+                          flags)
+        parts = (LvGraphResult * P)()
+        r = self._result
+        st = self.lib.louvain_run_partitioned(self.h, ctypes.byref(gs), P, vp, ctypes.byref(p),
+                                              _ptr(membership), parts, ctypes.byref(r),
+                                              _stream())
+        self._check(st)
+        out = [{"passes": q.passes, "iterations": [q.iterations[i] for i in range(q.passes)],
+                "n_communities": q.n_communities, "W": q.W, "qnum": q.q_num.value(), "q": q.q}
+               for q in parts]
+        return membership[:g.n], result_dict(r), out
 
     def colour_classes(self, g, pass_index=0, K=DEFAULT_SUBSTEPS):
         """Colour class of every vertex (uint8 tensor [n]) and the rounds taken."""

@@ -263,3 +263,30 @@ def test_prepare_rmat25_edge_list_sampled(lv):
         ri, rw = O.prepare_row(n, hs, hd, None, O.PREP_SYM | O.PREP_LOOPS | O.PREP_MAX, r)
         assert np.array_equal(hi[ho[r]:ho[r + 1]], ri), r
         assert (rw == 1).all()
+
+
+@pytest.mark.timeout(900)
+def test_rmat22_partitioned_exact(lv, rmat22):
+    """Partition and merge at P = 8 (one part per XCD) on R-MAT s22, whole result exact."""
+    g, og = rmat22
+    print("oracle: partitioned run on rmat22", flush=True)
+    top, ref, parts = O.run_partitioned(og, O.balanced_parts(og, 8), substeps=K_CLASSES)
+    memb, res, pr = lv.run_partitioned(g, P=8, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    assert np.array_equal(memb.cpu().numpy(), top)
+    assert res["qnum"] == ref["qnum"] and res["iterations"] == ref["iterations"]
+    assert [p["qnum"] for p in pr] == [p["qnum"] for p in parts]
+
+
+@pytest.mark.timeout(600)
+def test_rmat25_partitioned_q(lv, rmat25):
+    """At full size: the final partition's Qnum on the input graph, recomputed by the oracle,
+    equals the merge run's (aggregation keeps Q); labels dense."""
+    g, og = rmat25
+    memb, res, pr = lv.run_partitioned(g, P=8, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    m = memb.cpu().numpy()
+    k = res["n_communities"]
+    assert m.min() >= 0 and m.max() == k - 1 and np.unique(m).size == k
+    qnum, W, _ = O.modularity(og, m)
+    assert qnum == res["qnum"] and W == res["W"]
