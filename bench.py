@@ -706,6 +706,55 @@ def run_colour_bench(args, dev, g):
     print(json.dumps(line), flush=True)
 
 
+def run_partition_bench(args, dev, g):
+    """Partition and merge on the workload graph: louvain_run_partitioned for each P of
+    --partitions beside the direct louvain_run (time, Q, the parts' and the merge's share)."""
+    import torch
+
+    from paper_2301_12390_amd import Louvain
+
+    lv = Louvain(0)
+    out = []
+    for P in [int(x) for x in args.partitions.split(",")]:
+        for _ in range(args.warmup):
+            lv.run_partitioned(g, P=P, substeps=args.substeps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, res, pr = lv.run_partitioned(g, P=P, substeps=args.substeps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        row = {"P": P, "ms": ms, "q": res["q"], "merge_ms": res["total_ms"],
+               "merge_passes": res["passes"], "merge_iterations": res["iterations"],
+               "part_communities": sum(p["n_communities"] for p in pr),
+               "max_part_iterations": max(sum(p["iterations"]) for p in pr)}
+        out.append(row)
+        log(f"P={P}: {ms:.1f} ms, Q {res['q']:.6f}, merge {res['total_ms']:.1f} ms")
+    for _ in range(args.warmup):
+        lv.run(g, substeps=args.substeps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, rd = lv.run(g, substeps=args.substeps)
+    torch.cuda.synchronize()
+    direct_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    log(f"direct: {direct_ms:.1f} ms, Q {rd['q']:.6f}")
+    lv.close()
+    best = min(out, key=lambda r: r["ms"])
+    line = {
+        "metric": METRIC, "value": g.nnz / (best["ms"] / 1000.0),
+        "unit": f"TEPS (partition and merge, P = {best['P']})", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i64",
+        "data": "synthetic",
+        "config": {"workload": f"partitioned-{args.workload}", "n": g.n, "nnz": g.nnz,
+                   "substeps": args.substeps, "runs": out,
+                   "direct": {"ms": direct_ms, "q": rd["q"], "iterations": rd["iterations"]}},
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -738,6 +787,9 @@ def main():
                          "requests at --rates, p50/p99 latency), sweep (tolerance and "
                          "decline-factor study) or prepare (graph preparation of a raw R-MAT "
                          "edge list of --prep-scale)")
+    ap.add_argument("--partitions", default="",
+                    help="time partition and merge (louvain_run_partitioned) for these part "
+                         "counts, comma separated, beside the direct run")
     ap.add_argument("--colour-bench", action="store_true",
                     help="time the colouring behind LV_COLOR_CLASSES on the workload graph, and "
                          "one run with colour classes beside one with hashed classes")
@@ -818,6 +870,9 @@ def main():
         return
     if args.colour_bench:
         run_colour_bench(args, dev, g)
+        return
+    if args.partitions:
+        run_partition_bench(args, dev, g)
         return
 
     calibration_copy(args, dev)

@@ -48,26 +48,29 @@ __global__ void k_pm_bounds(const int64_t* off, int64_t n, int64_t nnz, int64_t 
 }
 
 // flag[e] = 1 when arc e joins two vertices of the same part (gid: part of every vertex).
+// Grid-stride over segments of kPmSeg arcs (the grid is capped).
 __global__ __launch_bounds__(kBlock) void k_pm_flags(const int64_t* off, int64_t n, int64_t nnz,
                                                     const int32_t* idx, const int32_t* gid,
                                                     const int64_t* vptr, int32_t* flag) {
-  const int64_t e0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * kPmSeg;
-  if (e0 >= nnz) return;
-  const int64_t e1 = e0 + kPmSeg < nnz ? e0 + kPmSeg : nnz;
-  int64_t r = row_of_arc(off, n, e0);
-  int64_t rend = off[r + 1];
-  int32_t k = gid[r];
-  int64_t lo = vptr[k], hi = vptr[k + 1];
-  for (int64_t e = e0; e < e1; e++) {
-    if (e >= rend) {
-      r = advance_row(off, n, r + 1, e);
-      rend = off[r + 1];
-      k = gid[r];
-      lo = vptr[k];
-      hi = vptr[k + 1];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * kPmSeg;
+  for (int64_t e0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * kPmSeg; e0 < nnz;
+       e0 += stride) {
+    const int64_t e1 = e0 + kPmSeg < nnz ? e0 + kPmSeg : nnz;
+    int64_t r = row_of_arc(off, n, e0);
+    int64_t rend = off[r + 1];
+    int32_t k = gid[r];
+    int64_t lo = vptr[k], hi = vptr[k + 1];
+    for (int64_t e = e0; e < e1; e++) {
+      if (e >= rend) {
+        r = advance_row(off, n, r + 1, e);
+        rend = off[r + 1];
+        k = gid[r];
+        lo = vptr[k];
+        hi = vptr[k + 1];
+      }
+      const int64_t j = idx[e];
+      flag[e] = j >= lo && j < hi ? 1 : 0;
     }
-    const int64_t j = idx[e];
-    flag[e] = j >= lo && j < hi ? 1 : 0;
   }
 }
 

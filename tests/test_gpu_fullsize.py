@@ -279,10 +279,18 @@ def test_rmat22_partitioned_exact(lv, rmat22):
 
 
 @pytest.mark.timeout(600)
-def test_rmat25_partitioned_q(lv, rmat25):
-    """At full size: the final partition's Qnum on the input graph, recomputed by the oracle,
-    equals the merge run's (aggregation keeps Q); labels dense."""
+def test_rmat25_partitioned(lv, rmat25):
+    """At full size (1.05e9 arcs, more than one pass of any capped grid covers). P = 1: the one
+    part is the whole graph, so its run equals louvain_run exactly (membership and Qnum), a
+    property that holds at any size. P = 8: the final partition's Qnum on the input graph,
+    recomputed by the oracle, equals the merge run's (aggregation keeps Q); labels dense; and
+    every part's W is the weight of its induced subgraph, which the oracle counts directly."""
     g, og = rmat25
+    m1, r1 = lv.run(g, substeps=K_CLASSES)
+    memb, res, pr = lv.run_partitioned(g, P=1, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    assert pr[0]["qnum"] == r1["qnum"] and pr[0]["iterations"] == r1["iterations"]
+    assert pr[0]["n_communities"] == r1["n_communities"]
     memb, res, pr = lv.run_partitioned(g, P=8, substeps=K_CLASSES)
     torch.cuda.synchronize()
     m = memb.cpu().numpy()
@@ -290,3 +298,9 @@ def test_rmat25_partitioned_q(lv, rmat25):
     assert m.min() >= 0 and m.max() == k - 1 and np.unique(m).size == k
     qnum, W, _ = O.modularity(og, m)
     assert qnum == res["qnum"] and W == res["W"]
+    vptr = O.balanced_parts(og, 8)
+    for p in range(8):
+        lo, hi = vptr[p], vptr[p + 1]
+        a0, a1 = og.off[lo], og.off[hi]
+        inside = (og.idx[a0:a1] >= lo) & (og.idx[a0:a1] < hi)
+        assert pr[p]["W"] == int(og.w[a0:a1][inside].sum()), p
