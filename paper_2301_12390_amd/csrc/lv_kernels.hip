@@ -770,6 +770,38 @@ __device__ __forceinline__ void gs_add_gain(const GraphSet& gs, int32_t g, u128 
   if (gs.gS) atomic_add_u128(gs.gS + 2 * g, gain);
 }
 
+// Per-graph gain sums of a workgroup of the fused kernel (all threads call it): one atomic for
+// the block total when every mover of the block belongs to one graph (always, for graphs much
+// larger than a block), else one per mover.
+template <typename SH>
+__device__ __forceinline__ void gs_add_block(const GraphSet& gs, int32_t gr, u128 gain, u128 bsum,
+                                             SH& sh) {
+  if (!gs.gS) return;
+  const bool mover = gain != 0;
+  int32_t lo = mover ? gr : INT32_MAX, hi = mover ? gr : -1;
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int32_t a = __shfl_xor(lo, m, 64), b = __shfl_xor(hi, m, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh.gmin[threadIdx.x >> 6] = lo;
+    sh.gmax[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  for (int i = 0; i < kBlock / 64; i++) {
+    lo = sh.gmin[i] < lo ? sh.gmin[i] : lo;
+    hi = sh.gmax[i] > hi ? sh.gmax[i] : hi;
+  }
+  __syncthreads();
+  if (hi < 0) return;  // no mover
+  if (lo == hi) {
+    if (threadIdx.x == 0) atomic_add_u128(gs.gS + 2 * lo, bsum);
+  } else if (mover) {
+    atomic_add_u128(gs.gS + 2 * gr, gain);
+  }
+}
+
 template <typename WT>
 struct MoveArgs {
   const int64_t* rs;
@@ -790,6 +822,7 @@ struct MoveArgs {
 struct BlockShared {
   u128 red128[kBlock / 64];
   ull red64[kBlock / 64];
+  int32_t gmin[kBlock / 64], gmax[kBlock / 64];
   typename Gain<true>::T bg[kBlock / 64];
   int32_t bc[kBlock / 64];
   ull kd[kBlock / 64];
@@ -898,13 +931,13 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
         target = bc;
         moved = 1;
         gain = Ar::diff(bg, stay);
-        gs_add_gain(a.gs, gr, gain);
       }
     }
     a.tgt[v] = target;
   }
   // block totals go to this block's own record: no contended atomics in the hot kernel
   const u128 bsum = block_sum_u128(gain, sh.red128);
+  gs_add_block(a.gs, gr, gain, bsum, sh);
   const ull bm = block_sum_u64(moved, sh.red64);
   const ull bn = block_sum_u64(nc, sh.red64);
   if (threadIdx.x == 0) {
@@ -2483,12 +2516,27 @@ hipError_t graph_ids(const int64_t* gbase, int64_t G, int64_t n, int32_t* gid, h
 }
 
 // Per-graph sums of x (out[g], 64-bit) or of x^2 (out[2g..2g+1], 128-bit) over the vertices.
-// Each thread covers kSeg consecutive vertices and flushes when the graph changes.
+// Each thread covers kSeg consecutive vertices and flushes when the graph changes; a block whose
+// vertices all belong to one graph (graphs are contiguous ranges) adds its total once instead.
 template <bool SQ>
-__global__ void k_graph_sum(const uint64_t* x, int64_t n, const int32_t* gid, ull* out) {
+__global__ __launch_bounds__(kBlock) void k_graph_sum(const uint64_t* x, int64_t n,
+                                                     const int32_t* gid, ull* out) {
+  __shared__ u128 red[kBlock / 64];
+  const int64_t b0 = (int64_t)blockIdx.x * kBlock * kSeg;
+  const int64_t b1 = b0 + kBlock * kSeg < n ? b0 + kBlock * kSeg : n;
   const int64_t v0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * kSeg;
-  if (v0 >= n) return;
   const int64_t v1 = v0 + kSeg < n ? v0 + kSeg : n;
+  if (gid[b0] == gid[b1 - 1]) {
+    u128 acc = 0;
+    for (int64_t v = v0; v < v1; v++) acc += SQ ? (u128)x[v] * x[v] : (u128)x[v];
+    acc = block_sum_u128(acc, red);
+    if (threadIdx.x == 0 && acc) {
+      if (SQ) atomic_add_u128(out + 2 * gid[b0], acc);
+      else atomicAdd(out + gid[b0], (ull)acc);
+    }
+    return;
+  }
+  if (v0 >= n) return;
   int32_t g = gid[v0];
   u128 acc = 0;
   for (int64_t v = v0; v <= v1; v++) {
