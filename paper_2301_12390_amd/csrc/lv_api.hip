@@ -29,7 +29,7 @@ enum SlotId {
   S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
-  S_PM_SIDX, S_PM_SW, S_PM_M2, S_COUNT_SLOTS
+  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -396,7 +396,7 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
   for (int it = 0; it < max_it; it++) {
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(lv::zero_words(stats0, 8 * K, s));
-    if (bp) HIPCHK(lv::zero_words(ph.m.gs.gS, 2 * bp->G, s));
+    if (bp) HIPCHK(lv::zero_words(ph.m.gs.gS, 2 * (int64_t)lv::kGainSlices * bp->G, s));
     for (int k = 0; k < K; k++) {
       lv::MoveBuffers m = ph.m;
       m.stats = stats0 + 8 * k;
@@ -440,9 +440,11 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
     }
     ull* h = ctx->pinned + PIN_STATS;
     HIPCHK(hipMemcpyAsync(h, stats0, 8 * K * sizeof(ull), hipMemcpyDeviceToHost, s));
-    if (bp)
+    if (bp) {
+      HIPCHK(lv::fold_gain_slices(ph.m.gs.gS, bp->G, s));
       HIPCHK(hipMemcpyAsync(bp->hS, ph.m.gs.gS, 2 * bp->G * sizeof(ull), hipMemcpyDeviceToHost,
                             s));
+    }
     HIPCHK(hipStreamSynchronize(s));
     float t_fused = 0, t_wg = 0, t_hub = 0, t_upd = 0;
     if (trace) {
@@ -1084,7 +1086,8 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
   CHK(wst(ctx, S_GBASE, 3 * ((int64_t)G + 1), &gbase));
   CHK(wst(ctx, S_GID0, n0, &gid0));
   ull* Wg = gw;
-  ull* gS = gw + G;
+  ull* gS = nullptr;  // kGainSlices copies of 2G words
+  CHK(wst(ctx, S_GSLICE, 2 * (int64_t)lv::kGainSlices * G, &gS));
   ull* gself = gw + 3 * (int64_t)G;
   ull* gsq = gw + 4 * (int64_t)G;
   void* pin = nullptr;

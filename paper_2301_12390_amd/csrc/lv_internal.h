@@ -21,13 +21,15 @@ struct DevGraph {
 
 // A batch of graphs packed with consecutive vertex ids, each with its own W and iteration state
 // (gid null: a single graph, whose W is passed separately).
+constexpr int kGainSlices = 32;  // copies of the per-graph gain sums (power of two)
 struct GraphSet {
   int64_t G = 0;
   const int32_t* gid = nullptr;       // [n] graph of every vertex
   const int64_t* gbase = nullptr;     // [G+1] first vertex of every graph
   const uint64_t* Wg = nullptr;       // [G] total weight
   const uint8_t* act = nullptr;       // [G] graphs iterating in this phase
-  unsigned long long* gS = nullptr;   // [2G] gain sum of the iteration per graph (128-bit)
+  unsigned long long* gS = nullptr;   // [kGainSlices][2G] gain sums of the iteration per graph
+                                      // (128-bit), folded into the first copy after it
   unsigned long long* gself = nullptr;  // [G] weight of self super-arcs made by an aggregation
 };
 
@@ -207,6 +209,7 @@ hipError_t compact_rows(const int64_t* offp, int64_t np, int64_t nnzp, const int
 hipError_t compose_membership(int32_t* top, int64_t n, const int32_t* map, hipStream_t s);
 
 // ---- batches of graphs (consecutive vertex ranges gbase[g] .. gbase[g+1])
+hipError_t fold_gain_slices(unsigned long long* gS, int64_t G, hipStream_t s);
 hipError_t graph_ids(const int64_t* gbase, int64_t G, int64_t n, int32_t* gid, hipStream_t s);
 // out[g] += sum over graph g of x (squares: out[2g..2g+1] += sum of x^2, 128-bit)
 hipError_t graph_sums(const uint64_t* x, int64_t n, const int32_t* gid, bool squares,

@@ -766,8 +766,14 @@ __device__ __forceinline__ bool gs_vertex(const GraphSet& gs, int32_t v, uint64_
   *W = gs.Wg[x];
   return gs.act[x] != 0;
 }
+// The gain sums are kept in kGainSlices copies, a workgroup adding to the copy of its index
+// modulo kGainSlices, so that the workgroups of one large graph do not all meet on one word;
+// fold_gain_slices sums the copies into the first before the host reads them.
+__device__ __forceinline__ ull* gs_slot(const GraphSet& gs, int32_t g) {
+  return gs.gS + 2 * ((int64_t)(blockIdx.x & (kGainSlices - 1)) * gs.G + g);
+}
 __device__ __forceinline__ void gs_add_gain(const GraphSet& gs, int32_t g, u128 gain) {
-  if (gs.gS) atomic_add_u128(gs.gS + 2 * g, gain);
+  if (gs.gS) atomic_add_u128(gs_slot(gs, g), gain);
 }
 
 // Per-graph gain sums of a workgroup of the fused kernel (all threads call it): one atomic for
@@ -796,9 +802,9 @@ __device__ __forceinline__ void gs_add_block(const GraphSet& gs, int32_t gr, u12
   __syncthreads();
   if (hi < 0) return;  // no mover
   if (lo == hi) {
-    if (threadIdx.x == 0) atomic_add_u128(gs.gS + 2 * lo, bsum);
+    if (threadIdx.x == 0) atomic_add_u128(gs_slot(gs, lo), bsum);
   } else if (mover) {
-    atomic_add_u128(gs.gS + 2 * gr, gain);
+    atomic_add_u128(gs_slot(gs, gr), gain);
   }
 }
 
@@ -2509,6 +2515,25 @@ __global__ void k_graph_ids(const int64_t* gbase, int64_t G, int64_t n, int32_t*
     gid[v] = (int32_t)lo;
   }
 }
+// gS[0 .. 2G) = sum over the kGainSlices copies (128-bit, per graph).
+__global__ void k_fold_gain_slices(ull* gS, int64_t G) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < G;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    u128 t = 0;
+    for (int k = 0; k < kGainSlices; k++) {
+      const ull* p = gS + 2 * ((int64_t)k * G + g);
+      t += ((u128)p[1] << 64) | p[0];
+    }
+    gS[2 * g] = (ull)t;
+    gS[2 * g + 1] = (ull)(t >> 64);
+  }
+}
+hipError_t fold_gain_slices(ull* gS, int64_t G, hipStream_t s) {
+  if (G <= 0) return hipSuccess;
+  LV_LAUNCH(k_fold_gain_slices, grid_for(G), kBlock, 0, s, gS, G);
+  return hipGetLastError();
+}
+
 hipError_t graph_ids(const int64_t* gbase, int64_t G, int64_t n, int32_t* gid, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   LV_LAUNCH(k_graph_ids, grid_for(n), kBlock, 0, s, gbase, G, n, gid);
