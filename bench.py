@@ -382,9 +382,21 @@ def run_serving_bench(args, dev):
         memb, res = lv.run_batched(packed, vptr, aptr, substeps=args.substeps)
         return memb.cpu(), res
 
-    serve([0])  # warm-up
-    per_rate = []
-    for rate in [float(x) for x in args.rates.split(",")]:
+    def serve_one(r):
+        """One request alone through louvain_run (the one-at-a-time FIFO server)."""
+        from graphgen.csr import Csr
+        n, o, i, w = host[r]
+        m = int(i.numel())
+        off_d[:n + 1].copy_(o, non_blocking=True)
+        idx_d[:m].copy_(i, non_blocking=True)
+        w_d[:m].copy_(w, non_blocking=True)
+        memb, res = lv.run(Csr(n, off_d[:n + 1], idx_d[:m], w_d[:m]), substeps=args.substeps)
+        return memb.cpu(), res
+
+    def run_trace(rate, batching):
+        """One arrival trace (seeded per rate, identical for both servers) through a server:
+        batching admits everything that has arrived (up to the arc budget) into one batched
+        run; FIFO takes one request at a time."""
         rng = np.random.default_rng(1000 + int(rate))
         arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 2) + 16))
         arr = arr[arr <= args.serve_seconds]
@@ -407,21 +419,26 @@ def run_serving_bench(args, dev):
                 continue
             if now > stop:
                 break
-            batch, tot, totn = [], 0, 0
-            while queue and (not batch or (tot + arcs[which[queue[0]]] <= args.serve_batch_arcs
-                                           and totn + sizes[which[queue[0]]] < cap_n)):
-                r = queue.popleft()
-                batch.append(r)
-                tot += arcs[which[r]]
-                totn += sizes[which[r]]
-            serve([int(which[r]) for r in batch])
+            if batching:
+                batch, tot, totn = [], 0, 0
+                while queue and (not batch or (tot + arcs[which[queue[0]]] <= args.serve_batch_arcs
+                                               and totn + sizes[which[queue[0]]] < cap_n)):
+                    r = queue.popleft()
+                    batch.append(r)
+                    tot += arcs[which[r]]
+                    totn += sizes[which[r]]
+                serve([int(which[r]) for r in batch])
+            else:
+                batch = [queue.popleft()]
+                serve_one(int(which[batch[0]]))
             done = time.perf_counter() - start
             lat.extend(done - arr[r] for r in batch)
             batches += 1
         el = time.perf_counter() - start
         lat_ms = np.array(lat) * 1000.0
         rec = {
-            "rate": rate, "offered": int(arr.size), "completed": len(lat),
+            "rate": rate, "server": "batching" if batching else "fifo",
+            "offered": int(arr.size), "completed": len(lat),
             "unfinished": int(arr.size - len(lat)),
             "completed_per_s": len(lat) / el,
             "p50_ms": float(np.percentile(lat_ms, 50)) if lat else None,
@@ -429,10 +446,18 @@ def run_serving_bench(args, dev):
             "batches": batches, "mean_batch": len(lat) / max(batches, 1),
             "seconds": el,
         }
-        per_rate.append(rec)
-        log(f"rate {rate:g}/s: {rec['completed']} of {rec['offered']} done, "
+        log(f"{rec['server']} rate {rate:g}/s: {rec['completed']} of {rec['offered']} done, "
             f"{rec['completed_per_s']:.1f}/s, p50 {rec['p50_ms']:.1f} ms, "
             f"p99 {rec['p99_ms']:.1f} ms, {batches} batches")
+        return rec
+
+    serve([0])  # warm-up
+    serve_one(0)
+    per_rate, fifo = [], []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        per_rate.append(run_trace(rate, True))
+        if not args.no_fifo:
+            fifo.append(run_trace(rate, False))
     lv.close()
     first = per_rate[0]
     line = {
@@ -456,6 +481,7 @@ def run_serving_bench(args, dev):
             "batch_arc_budget": args.serve_batch_arcs,
             "substeps": args.substeps,
             "rates": per_rate,
+            "fifo_rates": fifo,
         },
         "roofline": None,
     }
@@ -777,6 +803,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serving: seconds of arrivals per rate (the queue then drains)")
     ap.add_argument("--pool", type=int, default=32, help="serving: distinct request graphs")
+    ap.add_argument("--no-fifo", action="store_true",
+                    help="serving: skip the one-at-a-time FIFO server on the same traces")
     ap.add_argument("--serve-batch-arcs", type=int, default=1 << 28,
                     help="serving: most arcs the server runs in one batch")
     ap.add_argument("--prep-scale", type=int, default=25,
