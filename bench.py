@@ -331,16 +331,16 @@ def run_batched_bench(args, dev):
 
 def run_serving_bench(args, dev):
     """Serving: Poisson arrivals of requests drawn from a pool of pre-generated graphs held in
-    pinned host memory. The server admits whatever has arrived, copies those graphs to the GPU,
-    runs them as one louvain_run_batched call and copies the memberships back; latency is
-    arrival to membership on the host (queueing, H2D and D2H included)."""
-    from collections import deque
-
+    pinned host memory, submitted at their arrival times to the library's request server
+    (louvain_server_*). Latency is arrival to membership in host memory (queueing, packing, H2D
+    and D2H included), from the server's own clock. Every trace runs through three servers:
+    continuous batching (--serve-slots runs in flight, each batching up to --serve-batch-arcs),
+    batch-at-a-time (one slot that batches), and one-at-a-time FIFO (one slot, no batching)."""
     import numpy as np
     import torch
 
     from graphgen import serving_pool
-    from paper_2301_12390_amd import Louvain
+    from paper_2301_12390_amd import Server
 
     t0 = time.perf_counter()
     pool = serving_pool(args.pool, device=dev)
@@ -355,117 +355,80 @@ def run_serving_bench(args, dev):
     torch.cuda.empty_cache()
     log(f"request pool: {len(host)} graphs, n {min(sizes)}..{max(sizes)}, mean arcs "
         f"{sum(arcs) / len(arcs):.0f}, generated in {time.perf_counter() - t0:.1f}s")
-    cap_arcs = max(args.serve_batch_arcs, max(arcs))
-    cap_n = max(args.serve_batch_arcs // 8, max(sizes)) + 1
-    off_d = torch.empty(cap_n + 1, dtype=torch.int64, device=dev)
-    idx_d = torch.empty(cap_arcs, dtype=torch.int32, device=dev)
-    w_d = torch.empty(cap_arcs, dtype=torch.int32, device=dev)
-    lv = Louvain(0)
 
-    def serve(batch):
-        """H2D copy of the requests' graphs into one packed CSR, run, membership to host."""
-        from graphgen.csr import Csr
-        vptr, aptr = [0], [0]
-        for r in batch:
-            n, o, i, w = host[r]
-            v0, a0 = vptr[-1], aptr[-1]
-            m = int(i.numel())
-            off_d[v0:v0 + n].copy_(o[:-1], non_blocking=True)
-            off_d[v0:v0 + n] += a0
-            idx_d[a0:a0 + m].copy_(i, non_blocking=True)
-            idx_d[a0:a0 + m] += v0
-            w_d[a0:a0 + m].copy_(w, non_blocking=True)
-            vptr.append(v0 + n)
-            aptr.append(a0 + m)
-        off_d[vptr[-1]] = aptr[-1]
-        packed = Csr(vptr[-1], off_d[:vptr[-1] + 1], idx_d[:aptr[-1]], w_d[:aptr[-1]])
-        memb, res = lv.run_batched(packed, vptr, aptr, substeps=args.substeps)
-        return memb.cpu(), res
-
-    def serve_one(r):
-        """One request alone through louvain_run (the one-at-a-time FIFO server)."""
-        from graphgen.csr import Csr
-        n, o, i, w = host[r]
-        m = int(i.numel())
-        off_d[:n + 1].copy_(o, non_blocking=True)
-        idx_d[:m].copy_(i, non_blocking=True)
-        w_d[:m].copy_(w, non_blocking=True)
-        memb, res = lv.run(Csr(n, off_d[:n + 1], idx_d[:m], w_d[:m]), substeps=args.substeps)
-        return memb.cpu(), res
-
-    def run_trace(rate, batching):
-        """One arrival trace (seeded per rate, identical for both servers) through a server:
-        batching admits everything that has arrived (up to the arc budget) into one batched
-        run; FIFO takes one request at a time."""
+    def run_trace(rate, name, slots, batch_arcs):
+        """One arrival trace (seeded per rate, the same for every server) through a server.
+        Arrivals stop at serve_seconds; requests not done by twice that are counted
+        unfinished (the server is then destroyed, which drops them)."""
         rng = np.random.default_rng(1000 + int(rate))
         arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 2) + 16))
         arr = arr[arr <= args.serve_seconds]
         which = rng.integers(0, len(host), size=arr.size)
-        queue = deque()
-        lat = []
-        batches = 0
-        nxt = 0
-        start = time.perf_counter()
-        stop = args.serve_seconds * 2  # admission ends at serve_seconds; the queue drains until
-        while True:
-            now = time.perf_counter() - start
-            while nxt < arr.size and arr[nxt] <= now:
-                queue.append(nxt)
-                nxt += 1
-            if not queue:
-                if nxt >= arr.size:
-                    break
-                time.sleep(max(0.0, arr[nxt] - now))
-                continue
-            if now > stop:
+        srv = Server(0, slots=slots, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
+                     batch_arcs=batch_arcs, substeps=args.substeps)
+        # warm-up: every slot's buffers and workspace grown on the largest pool graph
+        big = int(np.argmax(arcs))
+        for t in [srv.submit(*host[big]) for _ in range(slots)]:
+            srv.wait(t)
+        base = srv.stats()
+        tickets = []
+        start = srv.clock_ns()
+        for i in range(arr.size):
+            lag = arr[i] - (srv.clock_ns() - start) * 1e-9
+            if lag > 0:
+                time.sleep(lag)
+            tickets.append(srv.submit(*host[int(which[i])]))
+        deadline = start + int(args.serve_seconds * 2 * 1e9)
+        lat, done_at, batches = [], [], []
+        for i, t in enumerate(tickets):
+            left_ms = (deadline - srv.clock_ns()) // 1_000_000
+            r = srv.wait(t, timeout_ms=max(int(left_ms), 0))
+            if r is None:
                 break
-            if batching:
-                batch, tot, totn = [], 0, 0
-                while queue and (not batch or (tot + arcs[which[queue[0]]] <= args.serve_batch_arcs
-                                               and totn + sizes[which[queue[0]]] < cap_n)):
-                    r = queue.popleft()
-                    batch.append(r)
-                    tot += arcs[which[r]]
-                    totn += sizes[which[r]]
-                serve([int(which[r]) for r in batch])
-            else:
-                batch = [queue.popleft()]
-                serve_one(int(which[batch[0]]))
-            done = time.perf_counter() - start
-            lat.extend(done - arr[r] for r in batch)
-            batches += 1
-        el = time.perf_counter() - start
-        lat_ms = np.array(lat) * 1000.0
+            out = r[1]
+            if out["status"] != 0:
+                raise RuntimeError(f"request {i} failed: {out['error']}")
+            lat.append((out["done_ns"] - (start + int(arr[i] * 1e9))) * 1e-6)
+            done_at.append(out["done_ns"])
+            batches.append(out["batch_graphs"])
+        st = srv.stats()
+        end = max(done_at) if done_at else srv.clock_ns()
+        srv.close()
+        el = (end - start) * 1e-9
+        lat_ms = np.array(lat)
         rec = {
-            "rate": rate, "server": "batching" if batching else "fifo",
+            "rate": rate, "server": name, "slots": slots, "batch_arcs": batch_arcs,
             "offered": int(arr.size), "completed": len(lat),
             "unfinished": int(arr.size - len(lat)),
-            "completed_per_s": len(lat) / el,
+            "completed_per_s": len(lat) / max(el, 1e-9),
             "p50_ms": float(np.percentile(lat_ms, 50)) if lat else None,
             "p99_ms": float(np.percentile(lat_ms, 99)) if lat else None,
-            "batches": batches, "mean_batch": len(lat) / max(batches, 1),
+            "runs": st["runs"] - base["runs"],
+            "mean_batch": float(np.mean(batches)) if batches else None,
+            "peak_running": st["peak_running"],
+            "peak_held_gb": st["peak_held_bytes"] / 2**30,
             "seconds": el,
         }
-        log(f"{rec['server']} rate {rate:g}/s: {rec['completed']} of {rec['offered']} done, "
+        log(f"{name} rate {rate:g}/s: {rec['completed']} of {rec['offered']} done, "
             f"{rec['completed_per_s']:.1f}/s, p50 {rec['p50_ms']:.1f} ms, "
-            f"p99 {rec['p99_ms']:.1f} ms, {batches} batches")
+            f"p99 {rec['p99_ms']:.1f} ms, {rec['runs']} runs, mean batch "
+            f"{rec['mean_batch']:.2f}, peak running {rec['peak_running']}")
         return rec
 
-    serve([0])  # warm-up
-    serve_one(0)
-    per_rate, fifo = [], []
+    servers = [("continuous", args.serve_slots, args.serve_batch_arcs)]
+    if not args.no_fifo:
+        servers += [("batch_at_a_time", 1, args.serve_batch_arcs), ("fifo", 1, 0)]
+    per = {name: [] for name, _, _ in servers}
     for rate in [float(x) for x in args.rates.split(",")]:
-        per_rate.append(run_trace(rate, True))
-        if not args.no_fifo:
-            fifo.append(run_trace(rate, False))
-    lv.close()
-    first = per_rate[0]
+        for name, slots, ba in servers:
+            per[name].append(run_trace(rate, name, slots, ba))
+    first = per["continuous"][0]
     line = {
         "metric": METRIC,
         "value": first["p99_ms"],
         "unit": "ms (p99 latency at the first rate)",
         "n_gpus": 1,
-        "steps": len(per_rate),
+        "steps": len(per["continuous"]),
         "warmup": 1,
         "ms_per_step": first["p50_ms"],
         "higher_is_better": False,
@@ -478,10 +441,13 @@ def run_serving_bench(args, dev):
             "pool_graphs": len(host),
             "pool_mean_arcs": sum(arcs) / len(arcs),
             "serve_seconds": args.serve_seconds,
+            "slots": args.serve_slots,
             "batch_arc_budget": args.serve_batch_arcs,
+            "hbm_budget_gb": args.serve_budget_gb,
             "substeps": args.substeps,
-            "rates": per_rate,
-            "fifo_rates": fifo,
+            "rates": per["continuous"],
+            "batch_at_a_time_rates": per.get("batch_at_a_time", []),
+            "fifo_rates": per.get("fifo", []),
         },
         "roofline": None,
     }
@@ -800,11 +766,15 @@ def main():
                     help="sweep: largest graph (arcs) given the asynchronous oracle's Q")
     ap.add_argument("--rates", default="50,200,800",
                     help="serving: request rates (per second), comma separated")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="serving: seconds of arrivals per rate (the queue then drains)")
     ap.add_argument("--pool", type=int, default=32, help="serving: distinct request graphs")
     ap.add_argument("--no-fifo", action="store_true",
-                    help="serving: skip the one-at-a-time FIFO server on the same traces")
+                    help="serving: skip the batch-at-a-time and one-at-a-time servers")
+    ap.add_argument("--serve-slots", type=int, default=4,
+                    help="serving: runs in flight at once in the continuous-batching server")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0,
+                    help="serving: device memory budget of the server (GiB)")
     ap.add_argument("--serve-batch-arcs", type=int, default=1 << 28,
                     help="serving: most arcs the server runs in one batch")
     ap.add_argument("--prep-scale", type=int, default=25,

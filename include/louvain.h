@@ -58,7 +58,9 @@ typedef enum {
   LV_ENOMEM = -2,    /* device allocation failed */
   LV_EHIP = -3,      /* a HIP runtime call or kernel launch failed */
   LV_EOVERFLOW = -4, /* n >= 2^31, nnz >= 2^31 with int32 offsets, or W > 2^62 */
-  LV_EBUDGET = -5    /* the workspace would exceed the context's HBM budget */
+  LV_EBUDGET = -5,   /* the workspace would exceed the context's HBM budget */
+  LV_ECANCELLED = -6, /* a server request dropped because the server was destroyed first */
+  LV_ETIMEOUT = -7    /* louvain_server_wait: the request had not completed in time */
 } lv_status;
 
 /* 128-bit two's-complement integer: value = hi * 2^64 + lo. */
@@ -323,6 +325,93 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
                           void* offsets_out, int32_t offsets_64_out, int32_t* indices_out,
                           void* weights_out, int32_t weights_64_out, int64_t capacity,
                           int64_t* nnz_out, lv_prep_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Request server: continuous batching of independent graphs over one device.
+ *
+ * Requests are whole runs (louvain_run) on graphs held in host memory. The server keeps
+ * `slots` runs in flight at once, each on its own context and HIP stream, so that the work of
+ * different requests overlaps on the device. A slot that becomes free takes the requests at
+ * the head of the queue (first come, first served) up to batch_arcs arcs and runs them as one
+ * louvain_run_batched call (one request alone goes through louvain_run); requests that arrive
+ * while others run are admitted as soon as a slot and device memory are free. Every result
+ * equals that of louvain_run on the graph alone (louvain_run_batched's guarantee), whatever
+ * else shares its batch or the device.
+ *
+ * Admission is by device memory: a slot holds its packing buffers and its context's workspace
+ * (both grow-only) and reserves, before each run, an upper bound of what it will hold after it
+ * (about 60 bytes per arc and 300 per vertex, measured on the method's workspace); the
+ * reservations of all slots stay within hbm_budget_bytes. A request whose bound alone exceeds
+ * the budget fails with LV_EBUDGET; when a request waits for memory, idle slots release
+ * theirs and no slot starts other work until it has been admitted.
+ *
+ * Request graphs: lv_graph with HOST pointers (offsets int32 or int64, weights uint32 only),
+ * checked on the device while they are packed (offsets from 0 to nnz and non-decreasing,
+ * neighbours in [0, n), weights >= 1); a request that fails the check ends with LV_EINVAL and
+ * the rest of its batch runs without it. Symmetry is the caller's contract, as for louvain_run.
+ * The graph's host arrays and the membership buffer must stay valid and untouched until
+ * louvain_server_wait has returned the request (pinned host memory copies fastest).
+ * A server is thread-safe: any thread may submit and wait.
+ */
+typedef struct lv_server lv_server;
+
+typedef struct {
+  int32_t slots;             /* runs in flight at once, 1..16 */
+  int32_t reserved;
+  uint64_t hbm_budget_bytes; /* device memory of all slots together; 0 = no limit */
+  int64_t batch_arcs;        /* most arcs of one batched run (a larger request runs alone);
+                                0 = one request per run */
+  lv_params params;          /* of every request (LV_TRACE is ignored) */
+} lv_server_config;
+
+/* What became of one request (host). Times are louvain_server_clock_ns() readings. */
+typedef struct {
+  int32_t status;            /* lv_status of the request */
+  int32_t slot;              /* slot that ran it (-1 if it never ran) */
+  int32_t batch_graphs;      /* requests of the run it was part of */
+  int32_t reserved;
+  int64_t batch_arcs;        /* arcs of that run */
+  int64_t submit_ns;         /* louvain_server_submit */
+  int64_t start_ns;          /* its run began (admitted, packing started) */
+  int64_t done_ns;           /* its membership was in host memory */
+  lv_graph_result result;    /* as louvain_run_batched's per-graph result */
+  char error[160];           /* text of a failure ("" on success) */
+} lv_request_result;
+
+typedef struct {
+  int64_t submitted, completed, failed; /* requests; completed counts failures too */
+  int64_t runs;              /* louvain_run / louvain_run_batched calls */
+  int64_t batched_requests;  /* requests that shared their run with others */
+  int32_t slots;
+  int32_t peak_running;      /* most slots running at the same time */
+  int32_t trims;             /* times a slot released its memory for a waiting request */
+  int32_t bound_misses;      /* runs after which a slot held more than it had reserved (0) */
+  uint64_t committed_bytes;  /* device memory reserved by the slots now */
+  uint64_t peak_committed_bytes;
+  uint64_t peak_held_bytes;  /* most device memory all slots held together (measured) */
+} lv_server_stats;
+
+/* Starts the server's slots on `device` (contexts, streams and one host thread per slot).
+ * LV_EINVAL for a bad device, config or parameter set; LV_EHIP if the device fails. */
+lv_status louvain_server_create(int device, const lv_server_config* cfg, lv_server** out);
+/* Drops the queued requests (LV_ECANCELLED), waits for the runs in flight, frees everything.
+ * Tickets not yet waited for become invalid. */
+void louvain_server_destroy(lv_server* server);
+/* Queues a request: g (host pointers, see above) and membership (host, [n] out: dense
+ * community ids, as louvain_run). ticket (host) out: the handle for louvain_server_wait.
+ * LV_EINVAL for a malformed descriptor (null pointers, n outside [0, 2^31), nnz < 0, n == 0
+ * with arcs, uint64 weights); LV_ECANCELLED once the server is being destroyed. */
+lv_status louvain_server_submit(lv_server* server, const lv_graph* g, int32_t* membership,
+                                uint64_t* ticket);
+/* Waits up to timeout_ms (< 0: no limit, 0: poll) for a request; on LV_OK `out` holds its
+ * outcome and the ticket is released. LV_ETIMEOUT if it is still queued or running (the ticket
+ * stays valid); LV_EINVAL for an unknown or already returned ticket. */
+lv_status louvain_server_wait(lv_server* server, uint64_t ticket, int64_t timeout_ms,
+                              lv_request_result* out);
+/* Counters of the server (host). */
+lv_status louvain_server_stats(lv_server* server, lv_server_stats* out);
+/* The server's clock: monotonic nanoseconds (CLOCK_MONOTONIC). */
+int64_t louvain_server_clock_ns(void);
 
 #ifdef __cplusplus
 }

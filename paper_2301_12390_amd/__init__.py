@@ -19,5 +19,6 @@ from .louvain import (  # noqa: F401
     Louvain,
     LouvainError,
     PreparedGraph,
+    Server,
     load_library,
 )

@@ -39,6 +39,16 @@ struct Slot {
 
 }  // namespace
 
+const char* lv::params_error(const lv_params* p) {
+  if (!p) return "params is NULL";
+  if (p->tolerance_exp10 < 0 || p->decline_exp10 < 0)
+    return "tolerance and decline exponents must be >= 0";
+  if (p->max_iterations < 1) return "max_iterations must be >= 1";
+  if (p->max_passes < 1 || p->max_passes > LV_MAX_PASSES) return "max_passes must be in 1..64";
+  if (p->substeps < 1 || p->substeps > 32) return "substeps must be in 1..32";
+  return nullptr;
+}
+
 // Partition size divisor (as a shift) under LV_SMALL_PARTS.
 constexpr int kSmallPartShift = 6;
 
@@ -169,15 +179,8 @@ u128 tolerance_threshold(uint64_t W, int a, int b, int p) {
 constexpr int lv_max_classes() { return 32; }
 
 lv_status check_params(lv_ctx* ctx, const lv_params* p) {
-  if (!p) return fail(ctx, LV_EINVAL, "params is NULL");
-  if (p->tolerance_exp10 < 0 || p->decline_exp10 < 0)
-    return fail(ctx, LV_EINVAL, "tolerance and decline exponents must be >= 0");
-  if (p->max_iterations < 1) return fail(ctx, LV_EINVAL, "max_iterations must be >= 1");
-  if (p->max_passes < 1 || p->max_passes > LV_MAX_PASSES)
-    return fail(ctx, LV_EINVAL, "max_passes must be in 1..64");
-  if (p->substeps < 1 || p->substeps > lv_max_classes())
-    return fail(ctx, LV_EINVAL, "substeps must be in 1..32");
-  return LV_OK;
+  const char* e = lv::params_error(p);
+  return e ? fail(ctx, LV_EINVAL, e) : LV_OK;
 }
 
 // Checks the graph descriptor and produces a device view with int64 offsets.

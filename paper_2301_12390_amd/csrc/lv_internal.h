@@ -4,7 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/louvain.h"
+
 namespace lv {
+
+// Why a parameter set is invalid, or nullptr if it is valid.
+const char* params_error(const lv_params* p);
 
 // A graph on the device: row v spans arcs [rs[v], re[v]) of idx/w. For a CSR, rs = off and
 // re = off + 1 (off has n+1 int64 entries; int32 inputs are widened once per call) and `off`

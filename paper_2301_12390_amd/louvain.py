@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "liblouvain.so")
 
 LV_OK = 0
 STATUS = {0: "LV_OK", -1: "LV_EINVAL", -2: "LV_ENOMEM", -3: "LV_EHIP", -4: "LV_EOVERFLOW",
-          -5: "LV_EBUDGET"}
+          -5: "LV_EBUDGET", -6: "LV_ECANCELLED", -7: "LV_ETIMEOUT"}
+LV_ETIMEOUT = -7
 
 LV_VALIDATE = 0x1
 LV_TRACE = 0x2
@@ -149,6 +150,48 @@ class LvPrepStats(ctypes.Structure):
     ]
 
 
+class LvServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("batch_arcs", ctypes.c_int64),
+        ("params", LvParams),
+    ]
+
+
+class LvRequestResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("slot", ctypes.c_int32),
+        ("batch_graphs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("batch_arcs", ctypes.c_int64),
+        ("submit_ns", ctypes.c_int64),
+        ("start_ns", ctypes.c_int64),
+        ("done_ns", ctypes.c_int64),
+        ("result", LvGraphResult),
+        ("error", ctypes.c_char * 160),
+    ]
+
+
+class LvServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("runs", ctypes.c_int64),
+        ("batched_requests", ctypes.c_int64),
+        ("slots", ctypes.c_int32),
+        ("peak_running", ctypes.c_int32),
+        ("trims", ctypes.c_int32),
+        ("bound_misses", ctypes.c_int32),
+        ("committed_bytes", ctypes.c_uint64),
+        ("peak_committed_bytes", ctypes.c_uint64),
+        ("peak_held_bytes", ctypes.c_uint64),
+    ]
+
+
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -187,6 +230,15 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(LvParams), _P,
                                            ctypes.POINTER(LvGraphResult), _P]),
+    "louvain_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(LvServerConfig),
+                                             ctypes.POINTER(_P)]),
+    "louvain_server_destroy": (None, [_P]),
+    "louvain_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P,
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+    "louvain_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int64,
+                                           ctypes.POINTER(LvRequestResult)]),
+    "louvain_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(LvServerStats)]),
+    "louvain_server_clock_ns": (ctypes.c_int64, []),
 }
 
 _LIB = None
@@ -525,3 +577,89 @@ class Louvain:
                                          ctypes.byref(W), ctypes.byref(qd), _stream())
         self._check(st)
         return q.value(), int(W.value), float(qd.value)
+
+
+def graph_result_dict(r: LvGraphResult) -> dict:
+    P = r.passes
+    return {"passes": P, "iterations_total": r.iterations_total,
+            "iterations": [r.iterations[i] for i in range(P)], "cap_hits": r.cap_hits,
+            "n_communities": r.n_communities, "W": r.W, "qnum": r.q_num.value(), "q": r.q}
+
+
+class Server:
+    """The library's request server (louvain_server_*): ``slots`` runs in flight at once, each
+    batching the queued requests up to ``batch_arcs`` arcs, device memory admitted against
+    ``hbm_budget`` bytes (0 = no limit). Requests are CSRs in host memory (CPU tensors; pinned
+    ones copy fastest); the server keeps them referenced until they are waited for."""
+
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0,
+                 batch_arcs: int = 1 << 28, tolerance_exp10=2, decline_exp10=1,
+                 max_iterations=20, max_passes=10, substeps=DEFAULT_SUBSTEPS, flags=0):
+        self.lib = load_library()
+        cfg = LvServerConfig(slots, 0, hbm_budget, batch_arcs,
+                             params_struct(tolerance_exp10, decline_exp10, max_iterations,
+                                           max_passes, substeps, flags))
+        h = ctypes.c_void_p()
+        st = self.lib.louvain_server_create(device, ctypes.byref(cfg), ctypes.byref(h))
+        if st != LV_OK:
+            raise LouvainError(st, "louvain_server_create failed")
+        self.h = h
+        self._held = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.louvain_server_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        self.close()
+
+    def clock_ns(self) -> int:
+        return int(self.lib.louvain_server_clock_ns())
+
+    def submit(self, n, offsets, indices, weights, membership=None) -> int:
+        """Queues one graph (host tensors: offsets int32/int64 [n+1], indices int32, weights
+        int32 holding uint32 bits). Returns the ticket; the membership (int32 [n], host) comes
+        back from wait()."""
+        for t in (offsets, indices, weights):
+            if t.is_cuda or not t.is_contiguous():
+                raise ValueError("request tensors must be contiguous host tensors")
+        if offsets.dtype not in (torch.int32, torch.int64) or indices.dtype != torch.int32 \
+                or weights.dtype != torch.int32:
+            raise ValueError("offsets int32/int64, indices int32, weights int32 (uint32 bits)")
+        if membership is None:
+            membership = torch.empty(max(int(n), 1), dtype=torch.int32,
+                                     pin_memory=offsets.is_pinned())
+        m = int(indices.numel())
+        g = LvGraph(int(n), m, offsets.data_ptr(), indices.data_ptr() if m else 0,
+                    weights.data_ptr() if m else 0, 1 if offsets.dtype == torch.int64 else 0, 0)
+        t = ctypes.c_uint64()
+        st = self.lib.louvain_server_submit(self.h, ctypes.byref(g), _ptr(membership),
+                                            ctypes.byref(t))
+        if st != LV_OK:
+            raise LouvainError(st, "louvain_server_submit refused the request")
+        self._held[t.value] = (offsets, indices, weights, membership, int(n))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(membership int32 host tensor [n], outcome dict) of a request, or None on a time-out.
+        The outcome has the request's status, error text, slot, batch and clock readings, and
+        the per-graph result of the run."""
+        r = LvRequestResult()
+        st = self.lib.louvain_server_wait(self.h, ticket, timeout_ms, ctypes.byref(r))
+        if st == LV_ETIMEOUT:
+            return None
+        if st != LV_OK:
+            raise LouvainError(st, f"louvain_server_wait: unknown ticket {ticket}")
+        _, _, _, memb, n = self._held.pop(ticket)
+        out = {"status": r.status, "error": r.error.decode(), "slot": r.slot,
+               "batch_graphs": r.batch_graphs, "batch_arcs": r.batch_arcs,
+               "submit_ns": r.submit_ns, "start_ns": r.start_ns, "done_ns": r.done_ns}
+        out.update(graph_result_dict(r.result))
+        return memb[:n], out
+
+    def stats(self) -> dict:
+        s = LvServerStats()
+        self.lib.louvain_server_stats(self.h, ctypes.byref(s))
+        return {f: getattr(s, f) for f, _ in LvServerStats._fields_}

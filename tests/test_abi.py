@@ -31,7 +31,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = header_functions()
-    assert len(names) == 13, names
+    assert len(names) == 19, names
     for name in names:
         assert hasattr(lib, name), name
 
@@ -75,6 +75,12 @@ int main(void) {
   F(lv_graph_result, q)
   S(lv_prep_stats) F(lv_prep_stats, nnz) F(lv_prep_stats, sort_passes)
   F(lv_prep_stats, scatter_ms) F(lv_prep_stats, total_ms)
+  S(lv_server_config) F(lv_server_config, hbm_budget_bytes) F(lv_server_config, batch_arcs)
+  F(lv_server_config, params)
+  S(lv_request_result) F(lv_request_result, batch_arcs) F(lv_request_result, done_ns)
+  F(lv_request_result, result) F(lv_request_result, error)
+  S(lv_server_stats) F(lv_server_stats, slots) F(lv_server_stats, bound_misses)
+  F(lv_server_stats, peak_held_bytes)
   return 0;
 }
 """
@@ -91,7 +97,9 @@ def test_struct_layout_matches_header():
         out = subprocess.check_output([exe]).decode().split("\n")
     cmap = {"lv_graph": L.LvGraph, "lv_params": L.LvParams, "lv_iter_trace": L.LvIterTrace,
             "lv_result": L.LvResult, "lv_move_stats": L.LvMoveStats,
-            "lv_graph_result": L.LvGraphResult, "lv_prep_stats": L.LvPrepStats}
+            "lv_graph_result": L.LvGraphResult, "lv_prep_stats": L.LvPrepStats,
+            "lv_server_config": L.LvServerConfig, "lv_request_result": L.LvRequestResult,
+            "lv_server_stats": L.LvServerStats}
     checked = 0
     for line in out:
         if not line:

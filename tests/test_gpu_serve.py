@@ -1,0 +1,270 @@
+"""The request server (louvain_server_*): every request's result, run in a mix of others that
+share its batch and the device, equals the oracle's run on the graph alone and the library's
+louvain_run on it alone (membership, exact Qnum, passes and iterations); malformed requests fail
+alone; admission keeps the slots' device memory within the budget; the serving workload's pool
+(graphs of 1e3..4e6 vertices) at full size.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from graphgen import (add_self_loops, erdos_renyi, lattice_shortcuts, planted_hubs, ring_of_cliques,
+                      rmat, sbm, single_edge, two_triangles)
+from graphgen.csr import Csr
+
+pytestmark = pytest.mark.gpu
+
+K_CLASSES = 8
+
+
+def host(g: Csr, pin=True):
+    """(n, offsets, indices, weights) as contiguous host tensors."""
+    t = [g.offsets.cpu().contiguous(), g.indices.cpu().contiguous(), g.weights.cpu().contiguous()]
+    if pin:
+        t = [x.pin_memory() for x in t]
+    return (g.n, *t)
+
+
+def mix():
+    return [
+        two_triangles(),
+        Csr(0, torch.zeros(1, dtype=torch.int32), torch.zeros(0, dtype=torch.int32),
+            torch.zeros(0, dtype=torch.int32), name="empty0"),
+        single_edge(),
+        Csr(7, torch.zeros(8, dtype=torch.int64), torch.zeros(0, dtype=torch.int32),
+            torch.zeros(0, dtype=torch.int32), name="arcless7"),
+        ring_of_cliques(8, 5),
+        add_self_loops(erdos_renyi(300, 0.03, seed=4, weights=(1, 9))),
+        sbm(3000, 30, 8.0, 2.0, seed=2, weights=(1, 16)),
+        lattice_shortcuts(2000, seed=3),
+        rmat(12, seed=7),
+        planted_hubs(rmat(10, seed=2), [3000], seed=1),
+        sbm(5000, 50, 8.0, 2.0, seed=5, weights=(1, 16)),
+        rmat(13, seed=9, weights=(1, 16)),
+        ring_of_cliques(30, 5),
+        lattice_shortcuts(700, seed=8),
+    ]
+
+
+def oracle_alone(g):
+    return O.run(O.Graph.from_csr(g), "sync", substeps=K_CLASSES)
+
+
+def check_against_oracle(g, memb, out):
+    assert out["status"] == 0, out["error"]
+    if g.n == 0:
+        return
+    if g.nnz == 0:
+        assert np.array_equal(memb.numpy(), np.arange(g.n)), g.name
+        assert out["passes"] == 0 and out["qnum"] == 0
+        return
+    top, ref = oracle_alone(g)
+    assert np.array_equal(memb.numpy(), top), g.name
+    assert out["qnum"] == ref["qnum"] and out["iterations"] == ref["iterations"], g.name
+
+
+@pytest.mark.parametrize("slots,batch_arcs", [(3, 60000), (1, 0), (4, 1 << 28)])
+def test_mix_equals_oracle_alone(gpu_device, slots, batch_arcs):
+    from paper_2301_12390_amd import Server
+    graphs = mix() * 2
+    srv = Server(0, slots=slots, batch_arcs=batch_arcs, substeps=K_CLASSES)
+    try:
+        tickets = [srv.submit(*host(g, pin=(i % 2 == 0))) for i, g in enumerate(graphs)]
+        outs = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    for g, (memb, out) in zip(graphs, outs):
+        check_against_oracle(g, memb, out)
+    assert st["completed"] == len(graphs) and st["failed"] == 0
+    assert st["bound_misses"] == 0 and st["peak_held_bytes"] <= st["peak_committed_bytes"]
+    if batch_arcs == 0:
+        assert all(o["batch_graphs"] == 1 for _, o in outs) and st["runs"] == len(graphs)
+    else:
+        assert st["batched_requests"] > 0
+        assert all(o["batch_arcs"] <= max(batch_arcs, g.nnz) for g, (_, o) in zip(graphs, outs))
+    if slots > 1 and batch_arcs < 100000:
+        # the queue holds several batches, so the slots run at once (with larger batches one
+        # slot may take the whole burst)
+        assert st["peak_running"] >= 2, st
+    print(st, flush=True)
+
+
+def test_mix_equals_run_alone(gpu_device):
+    """Larger graphs: the server's results against louvain_run on each graph alone."""
+    from paper_2301_12390_amd import Louvain, Server
+    graphs = [rmat(16, seed=s, weights=(1, 16)) for s in (1, 2)]
+    graphs += [sbm(60000, 600, 8.0, 2.0, seed=s, weights=(1, 16)) for s in (3, 4)]
+    graphs += [lattice_shortcuts(50000, seed=5), planted_hubs(rmat(14, seed=6), [20000, 9000])]
+    lv = Louvain(0)
+    alone = []
+    for g in graphs:
+        m, r = lv.run(g.to("cuda:0"), substeps=K_CLASSES)
+        torch.cuda.synchronize()
+        alone.append((m.cpu().numpy(), r))
+    lv.close()
+    srv = Server(0, slots=3, batch_arcs=1_500_000, substeps=K_CLASSES)
+    try:
+        tickets = [srv.submit(*host(g)) for g in graphs * 2]
+        outs = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for k, (memb, out) in enumerate(outs):
+        m, r = alone[k % len(graphs)]
+        assert out["status"] == 0, out["error"]
+        assert np.array_equal(memb.numpy(), m), k
+        assert out["qnum"] == r["qnum"] and out["iterations"] == r["iterations"], k
+        assert out["n_communities"] == r["n_communities"] and out["W"] == r["W"]
+
+
+def test_bad_requests_fail_alone(gpu_device):
+    from paper_2301_12390_amd import Server
+    good = [sbm(3000, 30, 8.0, 2.0, seed=2, weights=(1, 16)), rmat(11, seed=4), two_triangles()]
+    base = rmat(10, seed=3)
+    n, off, idx, w = host(base, pin=False)
+    bad_idx = idx.clone()
+    bad_idx[17] = n  # neighbour outside [0, n)
+    neg_idx = idx.clone()
+    neg_idx[3] = -1
+    bad_w = w.clone()
+    bad_w[5] = 0  # zero weight
+    bad_off = off.clone()
+    k = int(np.nonzero(np.diff(off.numpy()[1:]) > 0)[0][0]) + 1  # offsets[k] < offsets[k+1]
+    bad_off[k], bad_off[k + 1] = bad_off[k + 1].item(), bad_off[k].item()  # not non-decreasing
+    short_off = off.clone()
+    short_off[-1] = short_off[-1] - 1  # offsets[n] != nnz
+    bad = [(n, off, bad_idx, w), (n, off, neg_idx, w), (n, off, idx, bad_w), (n, bad_off, idx, w),
+           (n, short_off, idx, w)]
+    srv = Server(0, slots=2, batch_arcs=1 << 28, substeps=K_CLASSES)
+    try:
+        order = []
+        for k in range(len(bad)):
+            order.append(("good", k % len(good), srv.submit(*host(good[k % len(good)]))))
+            order.append(("bad", k, srv.submit(*bad[k])))
+        outs = [(kind, k, srv.wait(t)) for kind, k, t in order]
+        st = srv.stats()
+    finally:
+        srv.close()
+    for kind, k, (memb, out) in outs:
+        if kind == "bad":
+            assert out["status"] == -1 and out["error"], (k, out)
+        else:
+            check_against_oracle(good[k], memb, out)
+    assert st["failed"] == len(bad)
+
+
+def test_submit_checks_and_tickets(gpu_device):
+    from paper_2301_12390_amd import LouvainError, Server
+    from paper_2301_12390_amd.louvain import LvGraph
+    g = rmat(10, seed=1)
+    srv = Server(0, slots=1, substeps=K_CLASSES)
+    try:
+        lib, h = srv.lib, srv.h
+        n, off, idx, w = host(g)
+        t = ctypes.c_uint64()
+        memb = torch.empty(n, dtype=torch.int32)
+        w64 = w.to(torch.int64)
+        for desc in [LvGraph(n, idx.numel(), off.data_ptr(), idx.data_ptr(), w64.data_ptr(), 0, 1),
+                     LvGraph(-1, 0, off.data_ptr(), 0, 0, 0, 0),
+                     LvGraph(0, 5, off.data_ptr(), idx.data_ptr(), w.data_ptr(), 0, 0),
+                     LvGraph(n, idx.numel(), 0, idx.data_ptr(), w.data_ptr(), 0, 0),
+                     LvGraph(n, idx.numel(), off.data_ptr(), 0, w.data_ptr(), 0, 0)]:
+            assert lib.louvain_server_submit(h, ctypes.byref(desc), memb.data_ptr(),
+                                             ctypes.byref(t)) == -1
+        desc = LvGraph(n, idx.numel(), off.data_ptr(), idx.data_ptr(), w.data_ptr(), 0, 0)
+        assert lib.louvain_server_submit(h, ctypes.byref(desc), None, ctypes.byref(t)) == -1
+        ticket = srv.submit(n, off, idx, w)
+        res = srv.wait(ticket, timeout_ms=0)  # a poll: done or not yet
+        if res is None:
+            res = srv.wait(ticket)
+        assert res[1]["status"] == 0
+        with pytest.raises(LouvainError, match="EINVAL"):
+            srv.wait(ticket)
+        with pytest.raises(LouvainError, match="EINVAL"):
+            srv.wait(12345)
+        # destroying with requests still queued cancels them and returns
+        for _ in range(6):
+            srv.submit(n, off, idx, w)
+    finally:
+        srv.close()
+    with pytest.raises(LouvainError, match="EINVAL"):
+        Server(0, slots=0)
+    with pytest.raises(LouvainError, match="EINVAL"):
+        Server(0, slots=2, substeps=33)
+
+
+def test_budget_admission(gpu_device):
+    """A budget that holds one small request at a time serialises the slots (idle slots release
+    their memory for a waiting request); a request beyond the budget fails alone."""
+    from paper_2301_12390_amd import Server
+    graphs = [sbm(3000, 30, 8.0, 2.0, seed=s, weights=(1, 16)) for s in range(6)]
+    big = rmat(15, seed=1)
+    budget = 64 << 20  # one request's bound (~50 MiB), not two
+    srv = Server(0, slots=3, hbm_budget=budget, batch_arcs=0, substeps=K_CLASSES)
+    try:
+        tickets = [srv.submit(*host(g)) for g in graphs]
+        tb = srv.submit(*host(big))
+        outs = [srv.wait(t) for t in tickets]
+        _, ob = srv.wait(tb)
+        st = srv.stats()
+    finally:
+        srv.close()
+    for g, (memb, out) in zip(graphs, outs):
+        check_against_oracle(g, memb, out)
+    assert ob["status"] == -5 and "budget" in ob["error"]
+    assert st["peak_committed_bytes"] <= budget and st["peak_held_bytes"] <= budget
+    assert st["peak_running"] == 1 and st["bound_misses"] == 0
+    assert st["trims"] >= 1
+    print(st, flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_serving_pool_mix_equals_alone(gpu_device):
+    """The serving workload's pool (32 graphs, n log-uniform in [1e3, 4e6], R-MAT or SBM,
+    weights 1..16) through 4 slots with the bench's 2^28-arc batches, every graph twice and in
+    shuffled order: each result equals louvain_run on the graph alone; those of up to 2e5 arcs
+    also equal the oracle's run. The slots' device memory stays within the reserved bounds."""
+    from graphgen import serving_pool
+    from paper_2301_12390_amd import Louvain, Server
+    print("generating the serving pool on the GPU", flush=True)
+    pool = serving_pool(32, device="cuda:0")
+    lv = Louvain(0)
+    alone = []
+    for g in pool:
+        m, r = lv.run(g, substeps=K_CLASSES)
+        torch.cuda.synchronize()
+        alone.append((m.cpu().numpy(), r))
+    lv.close()
+    hosts = [host(g) for g in pool]
+    cpu_pool = [g.to("cpu") for g in pool]
+    del pool
+    torch.cuda.empty_cache()
+    print("alone runs done", flush=True)
+    order = np.random.default_rng(7).permutation(np.repeat(np.arange(32), 2))
+    srv = Server(0, slots=4, batch_arcs=1 << 28, substeps=K_CLASSES)
+    try:
+        tickets = [(int(k), srv.submit(*hosts[k])) for k in order]
+        outs = [(k, srv.wait(t)) for k, t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    print(st, flush=True)
+    for k, (memb, out) in outs:
+        m, r = alone[k]
+        assert out["status"] == 0, out["error"]
+        assert np.array_equal(memb.numpy(), m), k
+        assert out["qnum"] == r["qnum"] and out["iterations"] == r["iterations"], k
+    assert st["bound_misses"] == 0 and st["peak_held_bytes"] <= st["peak_committed_bytes"]
+    assert st["batched_requests"] > 0 and st["peak_running"] >= 2
+    checked = 0
+    for k, g in enumerate(cpu_pool):
+        if g.nnz <= 200_000:
+            top, ref = oracle_alone(g)
+            assert np.array_equal(alone[k][0], top), k
+            assert alone[k][1]["qnum"] == ref["qnum"], k
+            checked += 1
+    print(f"{checked} pool graphs also checked against the oracle", flush=True)
