@@ -417,7 +417,7 @@ def run_serving_bench(args, dev):
 
     servers = [("continuous", args.serve_slots, args.serve_batch_arcs)]
     if not args.no_fifo:
-        servers += [("batch_at_a_time", 1, args.serve_batch_arcs), ("fifo", 1, 0)]
+        servers += [("batch_at_a_time", 1, args.serve_single_batch_arcs), ("fifo", 1, 0)]
     per = {name: [] for name, _, _ in servers}
     for rate in [float(x) for x in args.rates.split(",")]:
         for name, slots, ba in servers:
@@ -443,6 +443,7 @@ def run_serving_bench(args, dev):
             "serve_seconds": args.serve_seconds,
             "slots": args.serve_slots,
             "batch_arc_budget": args.serve_batch_arcs,
+            "single_slot_batch_arc_budget": args.serve_single_batch_arcs,
             "hbm_budget_gb": args.serve_budget_gb,
             "substeps": args.substeps,
             "rates": per["continuous"],
@@ -771,12 +772,14 @@ def main():
     ap.add_argument("--pool", type=int, default=32, help="serving: distinct request graphs")
     ap.add_argument("--no-fifo", action="store_true",
                     help="serving: skip the batch-at-a-time and one-at-a-time servers")
-    ap.add_argument("--serve-slots", type=int, default=4,
+    ap.add_argument("--serve-slots", type=int, default=6,
                     help="serving: runs in flight at once in the continuous-batching server")
+    ap.add_argument("--serve-single-batch-arcs", type=int, default=1 << 28,
+                    help="serving: most arcs of one run of the batch-at-a-time server")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0,
                     help="serving: device memory budget of the server (GiB)")
-    ap.add_argument("--serve-batch-arcs", type=int, default=1 << 28,
-                    help="serving: most arcs the server runs in one batch")
+    ap.add_argument("--serve-batch-arcs", type=int, default=1 << 25,
+                    help="serving: most arcs of one run of the continuous-batching server")
     ap.add_argument("--prep-scale", type=int, default=25,
                     help="prepare: R-MAT scale of the raw edge list")
     ap.add_argument("--workload", default="rmat25",

@@ -340,8 +340,9 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
  *
  * Admission is by device memory: a slot holds its packing buffers and its context's workspace
  * (both grow-only) and reserves, before each run, an upper bound of what it will hold after it
- * (about 60 bytes per arc and 300 per vertex, measured on the method's workspace); the
- * reservations of all slots stay within hbm_budget_bytes. A request whose bound alone exceeds
+ * (its buffers exactly, and for the workspace 320 bytes per vertex, 72 per arc, 640 per graph
+ * and 48 MiB, at the largest batch it has run); the reservations of all slots stay within
+ * hbm_budget_bytes. A request whose bound alone exceeds
  * the budget fails with LV_EBUDGET; when a request waits for memory, idle slots release
  * theirs and no slot starts other work until it has been admitted.
  *
