@@ -1155,13 +1155,15 @@ template <bool WIDE, typename WT, int LOG2H>
 static hipError_t launch_wg(const WgArgs<WT>& a, int64_t rows, hipStream_t s) {
   constexpr size_t vb = sizeof(typename Gain<WIDE>::V);
   constexpr bool SIGC = ((size_t)1 << LOG2H) * (4 + vb + 8) <= kWgSigLds;
-  const size_t shm = ((size_t)1 << LOG2H) * (4 + vb + (SIGC ? 8 : 0));
-  static bool attr = false;
-  if (!attr) {
+  constexpr size_t shm = ((size_t)1 << LOG2H) * (4 + vb + (SIGC ? 8 : 0));
+  // once per instantiation; a function-local static initialiser is thread-safe, and contexts
+  // on different host threads launch these kernels concurrently
+  static const bool attr = [] {
     (void)hipFuncSetAttribute((const void*)k_move_wg<WIDE, WT, LOG2H, SIGC>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   LV_LAUNCH((k_move_wg<WIDE, WT, LOG2H, SIGC>), (unsigned)rows, kWgBlock, shm, s, a);
   return hipGetLastError();
 }
@@ -1774,12 +1776,12 @@ static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, cons
   a.tgt = m.tgt;
   a.stats = m.stats;
   a.gs = m.gs;
-  static bool attr = false;
-  if (!attr) {
+  static const bool attr = [] {  // once, thread-safe (see launch_wg)
     allow_part_lds(k_hub_part<WT, V>, vb);
     allow_part_lds(k_hub_reduce<WIDE, WT>, vb);
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   const size_t shm = part_lds_bytes(vb);
   LV_LAUNCH((k_hub_part<WT, V>), (unsigned)pp.blocks, kPartBlock, shm, s, a);
   LV_LAUNCH((k_hub_reduce<WIDE, WT>), (unsigned)pp.parts, kPartBlock, shm, s, a);
@@ -2414,12 +2416,12 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPl
   a.gid = ag.gs.gid;
   a.gself = ag.gs.gself;
   a.cap = part_round_cap(kMergeLog2H, pp.shift);
-  static bool attr = false;
-  if (!attr) {
+  static const bool attr = [] {  // once, thread-safe (see launch_wg)
     allow_part_lds(k_merge_part<WT>, 8);
     allow_part_lds(k_merge_reduce<WT>, 8);
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   const size_t shm = part_lds_bytes(8);
   LV_LAUNCH(k_merge_part<WT>, (unsigned)pp.blocks, kPartBlock, shm, s, a);
   if (pp.parts > 0) LV_LAUNCH(k_merge_reduce<WT>, (unsigned)pp.parts, kPartBlock, shm, s, a);

@@ -268,3 +268,37 @@ def test_serving_pool_mix_equals_alone(gpu_device):
             assert alone[k][1]["qnum"] == ref["qnum"], k
             checked += 1
     print(f"{checked} pool graphs also checked against the oracle", flush=True)
+
+
+def test_threads_submit_and_wait(gpu_device):
+    """Several host threads submit and wait on one server at once (the server is thread-safe):
+    every result equals the oracle's run alone."""
+    import threading
+    from paper_2301_12390_amd import Server
+    graphs = mix()
+    hosts = [host(g) for g in graphs]
+    srv = Server(0, slots=3, batch_arcs=40000, substeps=K_CLASSES)
+    results = {}
+    errors = []
+
+    def client(t):
+        try:
+            for k in range(len(graphs)):
+                i = (k + 5 * t) % len(graphs)
+                results[(t, k)] = (i, srv.wait(srv.submit(*hosts[i])))
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(t,)) for t in range(4)]
+    try:
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(timeout=300)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert not errors, errors
+    assert len(results) == 4 * len(graphs) and st["completed"] == 4 * len(graphs)
+    for (i, (memb, out)) in results.values():
+        check_against_oracle(graphs[i], memb, out)
