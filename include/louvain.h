@@ -358,7 +358,9 @@ typedef struct lv_server lv_server;
 
 typedef struct {
   int32_t slots;             /* runs in flight at once, 1..16 */
-  int32_t reserved;
+  int32_t fail_run;          /* fault injection for tests: run number fail_run (counting from
+                                1; 0 = none) fails with LV_ENOMEM as if its packing buffers
+                                could not be allocated, before it touches the device */
   uint64_t hbm_budget_bytes; /* device memory of all slots together; 0 = no limit */
   int64_t batch_arcs;        /* most arcs of one batched run (a larger request runs alone);
                                 0 = one request per run */
@@ -409,6 +411,10 @@ lv_status louvain_server_submit(lv_server* server, const lv_graph* g, int32_t* m
  * stays valid); LV_EINVAL for an unknown or already returned ticket. */
 lv_status louvain_server_wait(lv_server* server, uint64_t ticket, int64_t timeout_ms,
                               lv_request_result* out);
+/* Drops a request that is still queued: it completes with LV_ECANCELLED (collect it with
+ * louvain_server_wait) and *cancelled (host, may be NULL) is 1. A request already running or
+ * done is not affected (*cancelled = 0). LV_EINVAL for an unknown ticket. */
+lv_status louvain_server_cancel(lv_server* server, uint64_t ticket, int32_t* cancelled);
 /* Counters of the server (host). */
 lv_status louvain_server_stats(lv_server* server, lv_server_stats* out);
 /* The server's clock: monotonic nanoseconds (CLOCK_MONOTONIC). */

@@ -155,6 +155,7 @@ struct lv_server {
   bool stopping = false;
   int mem_waiters = 0;
   int running = 0;
+  int64_t run_seq = 0;  // runs admitted so far
   uint64_t committed = 0;
   uint64_t held_total = 0;
   lv_server_stats stats{};
@@ -258,7 +259,8 @@ void take_batch(lv_server* S, Slot* s, std::vector<Request*>& batch) {
 // One run of a batch on slot s (no lock held); false if nothing ran. Fills the results of the
 // requests in `batch` on return. When some requests fail the packing checks, only those stay in
 // `batch` (with LV_EINVAL) and the others go to `again`, to be queued again.
-bool run_batch(lv_server* S, Slot* s, std::vector<Request*>& batch, std::vector<Request*>& again) {
+bool run_batch(lv_server* S, Slot* s, int64_t seq, std::vector<Request*>& batch,
+               std::vector<Request*>& again) {
   const int32_t G = (int32_t)batch.size();
   const int64_t t0 = now_ns();
   std::vector<int64_t> vptr(G + 1, 0), aptr(G + 1, 0), rawb(G, 0);
@@ -284,6 +286,8 @@ bool run_batch(lv_server* S, Slot* s, std::vector<Request*>& batch, std::vector<
     return false;
   };
   if (!s->ctx) return fail_all(LV_EHIP, "the slot's context could not be created");
+  if (S->cfg.fail_run > 0 && seq == S->cfg.fail_run)
+    return fail_all(LV_ENOMEM, "injected failure of run " + std::to_string(seq));
   const size_t meta_bytes = (size_t)(3 * G + 2) * 8 + (size_t)(2 * G) * 4;
   if (grow(s->raw, (size_t)rawbytes) != LV_OK || grow(s->off, (size_t)(N + 1) * 8) != LV_OK ||
       grow(s->idx, (size_t)A * 4) != LV_OK || grow(s->w, (size_t)A * 4) != LV_OK ||
@@ -479,9 +483,10 @@ void worker(lv_server* S, Slot* s) {
     S->stats.peak_committed_bytes = std::max(S->stats.peak_committed_bytes, S->committed);
     S->running++;
     S->stats.peak_running = std::max(S->stats.peak_running, S->running);
+    const int64_t seq = ++S->run_seq;
     lk.unlock();
     std::vector<Request*> again;
-    const bool ran = run_batch(S, s, batch, again);
+    const bool ran = run_batch(S, s, seq, batch, again);
     const uint64_t held = own_bytes(s) + (s->ctx ? louvain_workspace_bytes(s->ctx) : 0);
     lk.lock();
     S->running--;
@@ -622,6 +627,23 @@ lv_status louvain_server_wait(lv_server* S, uint64_t ticket, int64_t timeout_ms,
   *out = r->res;
   S->requests.erase(ticket);
   delete r;
+  return LV_OK;
+}
+
+lv_status louvain_server_cancel(lv_server* S, uint64_t ticket, int32_t* cancelled) {
+  if (cancelled) *cancelled = 0;
+  if (!S) return LV_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->requests.find(ticket);
+  if (it == S->requests.end()) return LV_EINVAL;
+  Request* r = it->second;
+  auto q = std::find(S->queue.begin(), S->queue.end(), r);
+  if (q == S->queue.end()) return LV_OK;  // running or done
+  S->queue.erase(q);
+  set_error(r, LV_ECANCELLED, "cancelled before it ran");
+  finish(S, r);
+  S->cv_done.notify_all();
+  if (cancelled) *cancelled = 1;
   return LV_OK;
 }
 

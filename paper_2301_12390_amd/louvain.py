@@ -153,7 +153,7 @@ class LvPrepStats(ctypes.Structure):
 class LvServerConfig(ctypes.Structure):
     _fields_ = [
         ("slots", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fail_run", ctypes.c_int32),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("batch_arcs", ctypes.c_int64),
         ("params", LvParams),
@@ -237,6 +237,8 @@ SIGNATURES = {
                                              ctypes.POINTER(ctypes.c_uint64)]),
     "louvain_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int64,
                                            ctypes.POINTER(LvRequestResult)]),
+    "louvain_server_cancel": (ctypes.c_int, [_P, ctypes.c_uint64,
+                                             ctypes.POINTER(ctypes.c_int32)]),
     "louvain_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(LvServerStats)]),
     "louvain_server_clock_ns": (ctypes.c_int64, []),
 }
@@ -594,9 +596,10 @@ class Server:
 
     def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0,
                  batch_arcs: int = 1 << 28, tolerance_exp10=2, decline_exp10=1,
-                 max_iterations=20, max_passes=10, substeps=DEFAULT_SUBSTEPS, flags=0):
+                 max_iterations=20, max_passes=10, substeps=DEFAULT_SUBSTEPS, flags=0,
+                 fail_run=0):
         self.lib = load_library()
-        cfg = LvServerConfig(slots, 0, hbm_budget, batch_arcs,
+        cfg = LvServerConfig(slots, fail_run, hbm_budget, batch_arcs,
                              params_struct(tolerance_exp10, decline_exp10, max_iterations,
                                            max_passes, substeps, flags))
         h = ctypes.c_void_p()
@@ -658,6 +661,15 @@ class Server:
                "submit_ns": r.submit_ns, "start_ns": r.start_ns, "done_ns": r.done_ns}
         out.update(graph_result_dict(r.result))
         return memb[:n], out
+
+    def cancel(self, ticket: int) -> bool:
+        """Drops a request that is still queued (it then completes with LV_ECANCELLED); False
+        if it is already running or done."""
+        c = ctypes.c_int32(0)
+        st = self.lib.louvain_server_cancel(self.h, ticket, ctypes.byref(c))
+        if st != LV_OK:
+            raise LouvainError(st, f"louvain_server_cancel: unknown ticket {ticket}")
+        return bool(c.value)
 
     def stats(self) -> dict:
         s = LvServerStats()

@@ -31,7 +31,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = header_functions()
-    assert len(names) == 19, names
+    assert len(names) == 20, names
     for name in names:
         assert hasattr(lib, name), name
 
@@ -76,7 +76,7 @@ int main(void) {
   S(lv_prep_stats) F(lv_prep_stats, nnz) F(lv_prep_stats, sort_passes)
   F(lv_prep_stats, scatter_ms) F(lv_prep_stats, total_ms)
   S(lv_server_config) F(lv_server_config, hbm_budget_bytes) F(lv_server_config, batch_arcs)
-  F(lv_server_config, params)
+  F(lv_server_config, fail_run) F(lv_server_config, params)
   S(lv_request_result) F(lv_request_result, batch_arcs) F(lv_request_result, done_ns)
   F(lv_request_result, result) F(lv_request_result, error)
   S(lv_server_stats) F(lv_server_stats, slots) F(lv_server_stats, bound_misses)

@@ -302,3 +302,51 @@ def test_threads_submit_and_wait(gpu_device):
     assert len(results) == 4 * len(graphs) and st["completed"] == 4 * len(graphs)
     for (i, (memb, out)) in results.values():
         check_against_oracle(graphs[i], memb, out)
+
+
+def test_cancel_queued_requests(gpu_device):
+    """With one slot busy, requests still queued can be cancelled: they complete with
+    LV_ECANCELLED and the others are unaffected; a finished request cannot be cancelled."""
+    from paper_2301_12390_amd import LouvainError, Server
+    graphs = [rmat(14, seed=s, weights=(1, 16)) for s in range(6)]
+    hosts = [host(g) for g in graphs]
+    srv = Server(0, slots=1, batch_arcs=0, substeps=K_CLASSES)
+    try:
+        tickets = [srv.submit(*h) for h in hosts]
+        dropped = [srv.cancel(t) for t in tickets[4:]]
+        outs = [srv.wait(t) for t in tickets]
+        with pytest.raises(LouvainError, match="EINVAL"):
+            srv.cancel(tickets[0])  # already returned by wait
+        t = srv.submit(*hosts[0])
+        srv.wait(t)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert dropped == [True, True]  # the slot is still on the first requests
+    for k, (memb, out) in enumerate(outs):
+        if k >= 4:
+            assert out["status"] == -6 and out["slot"] == -1, out
+        else:
+            check_against_oracle(graphs[k], memb, out)
+    assert st["failed"] == 2 and st["runs"] == 5
+
+
+def test_injected_failure_leaves_others_intact(gpu_device):
+    """Fault injection: the second run fails as if its device allocation had failed; its
+    request ends with LV_ENOMEM and every other request still equals the oracle alone."""
+    from paper_2301_12390_amd import Server
+    graphs = [g for g in mix() if g.nnz > 0][:6]
+    srv = Server(0, slots=1, batch_arcs=0, substeps=K_CLASSES, fail_run=2)
+    try:
+        tickets = [srv.submit(*host(g)) for g in graphs]
+        outs = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    failed = [k for k, (_, o) in enumerate(outs) if o["status"] != 0]
+    assert failed == [1], [o["status"] for _, o in outs]
+    assert outs[1][1]["status"] == -2 and "injected" in outs[1][1]["error"]
+    for k, (memb, out) in enumerate(outs):
+        if k != 1:
+            check_against_oracle(graphs[k], memb, out)
+    assert st["failed"] == 1 and st["runs"] == len(graphs) - 1
