@@ -398,7 +398,8 @@ typedef struct {
  * LV_EINVAL for a bad device, config or parameter set; LV_EHIP if the device fails. */
 lv_status louvain_server_create(int device, const lv_server_config* cfg, lv_server** out);
 /* Drops the queued requests (LV_ECANCELLED), waits for the runs in flight, frees everything.
- * Tickets not yet waited for become invalid. */
+ * Tickets not yet waited for become invalid. No other call on the server may be in progress
+ * (a thread blocked in louvain_server_wait included). */
 void louvain_server_destroy(lv_server* server);
 /* Queues a request: g (host pointers, see above) and membership (host, [n] out: dense
  * community ids, as louvain_run). ticket (host) out: the handle for louvain_server_wait.

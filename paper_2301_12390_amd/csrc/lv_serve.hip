@@ -285,7 +285,10 @@ bool run_batch(lv_server* S, Slot* s, int64_t seq, std::vector<Request*>& batch,
     }
     return false;
   };
-  if (!s->ctx) return fail_all(LV_EHIP, "the slot's context could not be created");
+  if (!s->ctx && louvain_ctx_create(S->device, 0, &s->ctx) != LV_OK) {
+    s->ctx = nullptr;  // tried again by the slot's next run
+    return fail_all(LV_EHIP, "the slot's context could not be created");
+  }
   if (S->cfg.fail_run > 0 && seq == S->cfg.fail_run)
     return fail_all(LV_ENOMEM, "injected failure of run " + std::to_string(seq));
   const size_t meta_bytes = (size_t)(3 * G + 2) * 8 + (size_t)(2 * G) * 4;
