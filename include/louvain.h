@@ -350,6 +350,8 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
  * checked on the device while they are packed (offsets from 0 to nnz and non-decreasing,
  * neighbours in [0, n), weights >= 1); a request that fails the check ends with LV_EINVAL and
  * the rest of its batch runs without it. Symmetry is the caller's contract, as for louvain_run.
+ * A failure of the run itself ends every request of that run with its status (LV_EOVERFLOW for
+ * a graph whose total weight exceeds 2^62, which takes about 2^30 arcs of weight near 2^32).
  * The graph's host arrays and the membership buffer must stay valid and untouched until
  * louvain_server_wait has returned the request (pinned host memory copies fastest).
  * A server is thread-safe: any thread may submit and wait.

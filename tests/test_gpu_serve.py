@@ -350,3 +350,20 @@ def test_injected_failure_leaves_others_intact(gpu_device):
         if k != 1:
             check_against_oracle(graphs[k], memb, out)
     assert st["failed"] == 1 and st["runs"] == len(graphs) - 1
+
+
+def test_colour_class_requests(gpu_device):
+    """A server whose parameters select colour classes: each request equals the oracle's
+    colour-class run on the graph alone."""
+    from paper_2301_12390_amd import LV_COLOR_CLASSES, Server
+    graphs = [g for g in mix() if g.nnz > 0]
+    srv = Server(0, slots=2, batch_arcs=50000, substeps=K_CLASSES, flags=LV_COLOR_CLASSES)
+    try:
+        outs = [srv.wait(t) for t in [srv.submit(*host(g)) for g in graphs]]
+    finally:
+        srv.close()
+    for g, (memb, out) in zip(graphs, outs):
+        assert out["status"] == 0, out["error"]
+        top, ref = O.run(O.Graph.from_csr(g), "sync", substeps=K_CLASSES, colour=True)
+        assert np.array_equal(memb.numpy(), top), g.name
+        assert out["qnum"] == ref["qnum"] and out["iterations"] == ref["iterations"], g.name
