@@ -600,8 +600,19 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   a.w32 = check32 && hm[2] < ((ull)1 << 32);
   HIPCHK(lv::fill_i64(a.dcount, 0, np + 1, s));
   CHK(wst(ctx, S_MPART, lv::merge_lds_blocks(b), &a.block_partial));
-  HIPCHK(lv::merge_lds(g, b, a, s));
   const int64_t nh = b.lstart[DEG] - b.lstart[7];  // communities of more than 1024 arcs
+  // The LDS merge (communities of up to 1024 arcs) and the two-phase merge (larger ones) write
+  // disjoint rows and counts and add to the self-arc sum atomically. When both have real work
+  // the LDS merge runs on a side stream, overlapping the other's planning and kernels.
+  int64_t small_arcs = 0;
+  for (int j = 0; j < 7; j++) small_arcs += b.arcs[j];
+  const bool fork = nh > 0 && small_arcs >= ((int64_t)1 << 20);
+  hipStream_t s_lds = fork ? ctx->side[0] : s;
+  if (fork) {
+    HIPCHK(hipEventRecord(ctx->fork[0], s));
+    HIPCHK(hipStreamWaitEvent(s_lds, ctx->fork[0], 0));
+  }
+  HIPCHK(lv::merge_lds(g, b, a, s_lds));
   if (nh > 0) {
     lv::PartPlan pp;
     CHK(wst(ctx, S_HUBARR, lv::kPlanWords * (nh + 1), &a.hub_arrays));
@@ -613,6 +624,10 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
     CHK(wst(ctx, S_HOFF, pp.hoff_entries, &a.hoff));
     CHK(wst(ctx, S_NFLUSH, pp.blocks, &a.nflush));
     HIPCHK(lv::merge_hubs(g, b, pp, a, s));
+  }
+  if (fork) {
+    HIPCHK(hipEventRecord(ctx->join0[0], s_lds));
+    HIPCHK(hipStreamWaitEvent(s, ctx->join0[0], 0));
   }
   HIPCHK(lv::sum_i64(a.dcount, np, a.stats + 1, s));
   HIPCHK(hipMemcpyAsync(hm, a.stats, 2 * sizeof(ull), hipMemcpyDeviceToHost, s));

@@ -121,8 +121,11 @@ hipError_t zero_words(ull* a, int64_t n, hipStream_t s) {
 // =============================================================================================
 // Reductions over vertex arrays
 
+// One atomic of each kind per block: per-wave atomics on the two words contend at the memory
+// side once there are thousands of blocks.
 __global__ __launch_bounds__(kBlock) void k_sum_max(const uint64_t* a, int64_t n, ull* out) {
   __shared__ ull red[kBlock / 64];
+  __shared__ ull wmax[kBlock / 64];
   ull sum = 0, mx = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -136,12 +139,17 @@ __global__ __launch_bounds__(kBlock) void k_sum_max(const uint64_t* a, int64_t n
     ull o = __shfl_xor(mx, m, 64);
     mx = o > mx ? o : mx;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(&out[1], mx);
-  if (threadIdx.x == 0 && bs) atomicAdd(&out[0], bs);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; w++) mx = wmax[w] > mx ? wmax[w] : mx;
+    if (mx) atomicMax(&out[1], mx);
+    if (bs) atomicAdd(&out[0], bs);
+  }
 }
 hipError_t sum_max_u64(const uint64_t* a, int64_t n, ull* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  LV_LAUNCH(k_sum_max, grid_for(n, kBlock, 4096), kBlock, 0, s, a, n, out);
+  LV_LAUNCH(k_sum_max, grid_for(n, kBlock, 1024), kBlock, 0, s, a, n, out);
   return hipGetLastError();
 }
 
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_squares(const uint64_t* a, int64
 }
 hipError_t sum_squares_u64(const uint64_t* a, int64_t n, ull* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  LV_LAUNCH(k_sum_squares, grid_for(n, kBlock, 4096), kBlock, 0, s, a, n, out);
+  LV_LAUNCH(k_sum_squares, grid_for(n, kBlock, 1024), kBlock, 0, s, a, n, out);
   return hipGetLastError();
 }
 
@@ -565,7 +573,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket_count(const int64_t* rs, cons
   }
 }
 
-// starts: first list position per segment; cursor: per-segment fill counters (zero).
+// starts: first list position per segment; cursor: per-segment fill counters (zero). A block
+// ranks a chunk of kFillItems items per thread in LDS and then claims each segment's share of
+// the chunk with one global atomic, so that the few segment cursors are not hit once per tile
+// of every block.
+constexpr int kFillItems = 16;
 __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const int64_t* re,
                                                        const int64_t* len, int64_t m, int K,
                                                        int pass, const int32_t* gid,
@@ -575,24 +587,33 @@ __global__ __launch_bounds__(kBlock) void k_bucket_fill(const int64_t* rs, const
   __shared__ int cnt[kMaxSeg];
   __shared__ ull base[kMaxSeg];
   const int nseg = kDegClasses * K;
-  for (int64_t tile = (int64_t)blockIdx.x * kBlock; tile < m;
-       tile += (int64_t)gridDim.x * kBlock) {
+  constexpr int64_t kChunk = (int64_t)kBlock * kFillItems;
+  for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < m; c0 += (int64_t)gridDim.x * kChunk) {
     for (int t = threadIdx.x; t < nseg; t += blockDim.x) cnt[t] = 0;
     __syncthreads();
-    const int64_t i = tile + threadIdx.x;
-    int sg = -1, rank = 0;
-    if (i < m) {
-      const int64_t L = item_len(rs, re, len, i);
-      if (listed(L, i, gid, act)) {
-        sg = segment_of(L, K, pass, i, gid, gbase, vclass);
-        rank = atomicAdd(&cnt[sg], 1);
+    int sg[kFillItems], rank[kFillItems];
+#pragma unroll
+    for (int u = 0; u < kFillItems; u++) {
+      const int64_t i = c0 + (int64_t)u * kBlock + threadIdx.x;
+      sg[u] = -1;
+      rank[u] = 0;
+      if (i < m) {
+        const int64_t L = item_len(rs, re, len, i);
+        if (listed(L, i, gid, act)) {
+          sg[u] = segment_of(L, K, pass, i, gid, gbase, vclass);
+          rank[u] = atomicAdd(&cnt[sg[u]], 1);
+        }
       }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nseg; t += blockDim.x)
       if (cnt[t]) base[t] = atomicAdd(&cursor[t], (ull)cnt[t]);
     __syncthreads();
-    if (sg >= 0) list[(int64_t)starts[sg] + (int64_t)base[sg] + rank] = (int32_t)i;
+#pragma unroll
+    for (int u = 0; u < kFillItems; u++)
+      if (sg[u] >= 0)
+        list[(int64_t)starts[sg[u]] + (int64_t)base[sg[u]] + rank[u]] =
+            (int32_t)(c0 + (int64_t)u * kBlock + threadIdx.x);
     __syncthreads();
   }
 }
@@ -627,7 +648,8 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
   e = hipMemcpyAsync(counts + 3 * kMaxSeg, hstarts, nseg * sizeof(ull), hipMemcpyHostToDevice,
                      s);
   if (e != hipSuccess) return e;
-  LV_LAUNCH(k_bucket_fill, grid_for(m, kBlock, 8192), kBlock, 0, s, rs, re, len, m, K, pass,
+  LV_LAUNCH(k_bucket_fill, grid_for(m, (int64_t)kBlock * kFillItems, 8192), kBlock, 0, s, rs,
+            re, len, m, K, pass,
             gid, gbase, act, vclass, counts + 3 * kMaxSeg, counts + 2 * kMaxSeg, list);
   return hipGetLastError();
 }
