@@ -29,7 +29,7 @@ enum SlotId {
   S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
-  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_COUNT_SLOTS
+  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -765,7 +765,9 @@ lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, l
   CHK(wst(ctx, S_SIG, dg.n, &Sig));
   HIPCHK(lv::fill_u64(K, 0, dg.n, s));
   HIPCHK(lv::fill_u64(Sig, 0, dg.n, s));
-  HIPCHK(lv::row_sums(dg, K, s));
+  int64_t* rtile = nullptr;
+  CHK(wst(ctx, S_RTILE, lv::row_sum_tiles(dg.nnz) + 1, &rtile));
+  HIPCHK(lv::row_sums(dg, K, rtile, s));
   HIPCHK(lv::sigma_by_label(K, C, dg.n, Sig, s));
   ull* st = nullptr;
   CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
@@ -808,7 +810,9 @@ lv_status louvain_move(lv_ctx* ctx, const lv_graph* g, const uint64_t* Kin, uint
     uint64_t* Kw = nullptr;
     CHK(wst(ctx, S_K, ph.g.n, &Kw));
     HIPCHK(lv::fill_u64(Kw, 0, ph.g.n, s));
-    HIPCHK(lv::row_sums(ph.g, Kw, s));
+    int64_t* rtile = nullptr;
+    CHK(wst(ctx, S_RTILE, lv::row_sum_tiles(ph.g.nnz) + 1, &rtile));
+    HIPCHK(lv::row_sums(ph.g, Kw, rtile, s));
     K = Kw;
   }
   uint64_t W = 0, maxK = 0;
@@ -923,7 +927,9 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
   CHK(wst(ctx, S_CSIZE, n0, &csize));
   CHK(wst(ctx, S_MAP, n0, &map));
   HIPCHK(lv::fill_u64(K, 0, n0, s));
-  HIPCHK(lv::row_sums(g0, K, s));
+  int64_t* rtile = nullptr;
+  CHK(wst(ctx, S_RTILE, lv::row_sum_tiles(g0.nnz) + 1, &rtile));
+  HIPCHK(lv::row_sums(g0, K, rtile, s));
   uint64_t W = 0, maxK = 0;
   CHK(weight_stats(ctx, K, n0, s, &W, &maxK));
   res->W = W;
@@ -1141,7 +1147,9 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
   CHK(wst(ctx, S_CSIZE, n0, &csize));
   CHK(wst(ctx, S_MAP, n0, &map));
   HIPCHK(lv::fill_u64(K, 0, n0, s));
-  HIPCHK(lv::row_sums(g0, K, s));
+  int64_t* rtile = nullptr;
+  CHK(wst(ctx, S_RTILE, lv::row_sum_tiles(g0.nnz) + 1, &rtile));
+  HIPCHK(lv::row_sums(g0, K, rtile, s));
   uint64_t Wtot = 0, maxK = 0;
   CHK(weight_stats(ctx, K, n0, s, &Wtot, &maxK));
   HIPCHK(lv::zero_words(Wg, G, s));

@@ -90,7 +90,9 @@ hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* pa
                           hipStream_t s);  // counts x[i] > 0
 
 // ---- pass set-up
-hipError_t row_sums(const DevGraph& g, uint64_t* K, hipStream_t s);  // K must be zero
+// K must be zero; tile_rows: row_sum_tiles(g.nnz) + 1 words of scratch
+hipError_t row_sums(const DevGraph& g, uint64_t* K, int64_t* tile_rows, hipStream_t s);
+int64_t row_sum_tiles(int64_t nnz);
 // Community state as 16-byte records {C[x], csize[x], Sigma[x]} (see lv_device.h).
 constexpr size_t kRecBytes = 16;
 hipError_t init_state(int64_t n, const uint64_t* K, void* rec, hipStream_t s);

@@ -342,15 +342,32 @@ constexpr int64_t kSeg = 16;
 constexpr int64_t kRowTile = 4096;
 constexpr int64_t kShortRow = 32;
 
+// tile_rows[t] = the row holding arc t * kRowTile, for every tile t (each arc lies in exactly
+// one non-empty row, so every tile gets one writer); tile_rows[tiles] = n - 1.
+__global__ __launch_bounds__(kBlock) void k_tile_rows(const int64_t* off, int64_t n,
+                                                     int64_t tiles, int64_t* tile_rows) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b0 = off[r], b1 = off[r + 1];
+    if (b1 <= b0) continue;
+    const int64_t t1 = (b1 + kRowTile - 1) / kRowTile;
+    for (int64_t t = (b0 + kRowTile - 1) / kRowTile; t < t1; t++) tile_rows[t] = r;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) tile_rows[tiles] = n - 1;
+}
+
+// The rows a tile touches run from tile_rows[b] to tile_rows[b + 1] (that last one may start
+// at the next tile and then contributes nothing here).
 template <typename WT>
-__global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t n, int64_t nnz,
-                                                    const WT* w, uint64_t* K) {
+__global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t nnz,
+                                                    const int64_t* tile_rows, const WT* w,
+                                                    uint64_t* K) {
   __shared__ int64_t span[2];
   __shared__ int64_t longs[kRowTile / kShortRow + 2];
   __shared__ int nlong;
   const int64_t lo = (int64_t)blockIdx.x * kRowTile;
   const int64_t hi = lo + kRowTile < nnz ? lo + kRowTile : nnz;
-  if (threadIdx.x < 2) span[threadIdx.x] = row_of_arc(off, n, threadIdx.x == 0 ? lo : hi - 1);
+  if (threadIdx.x < 2) span[threadIdx.x] = tile_rows[blockIdx.x + threadIdx.x];
   if (threadIdx.x == 0) nlong = 0;
   __syncthreads();
   for (int64_t r = span[0] + threadIdx.x; r <= span[1]; r += kBlock) {
@@ -382,15 +399,19 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t
   }
 }
 
-hipError_t row_sums(const DevGraph& g, uint64_t* K, hipStream_t s) {
+int64_t row_sum_tiles(int64_t nnz) { return (nnz + kRowTile - 1) / kRowTile; }
+
+hipError_t row_sums(const DevGraph& g, uint64_t* K, int64_t* tile_rows, hipStream_t s) {
   if (g.nnz <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((g.nnz + kRowTile - 1) / kRowTile);
+  const int64_t tiles = row_sum_tiles(g.nnz);
+  LV_LAUNCH(k_tile_rows, grid_for(g.n), kBlock, 0, s, g.off, g.n, tiles, tile_rows);
+  const unsigned grid = (unsigned)tiles;
   if (g.w64)
-    LV_LAUNCH(k_row_sums<uint64_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, (const uint64_t*)g.w,
-              K);
+    LV_LAUNCH(k_row_sums<uint64_t>, grid, kBlock, 0, s, g.off, g.nnz, tile_rows,
+              (const uint64_t*)g.w, K);
   else
-    LV_LAUNCH(k_row_sums<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, (const uint32_t*)g.w,
-              K);
+    LV_LAUNCH(k_row_sums<uint32_t>, grid, kBlock, 0, s, g.off, g.nnz, tile_rows,
+              (const uint32_t*)g.w, K);
   return hipGetLastError();
 }
 
