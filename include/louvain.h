@@ -327,7 +327,9 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
                           int64_t* nnz_out, lv_prep_stats* stats, void* stream);
 
 /* ---------------------------------------------------------------------------------------
- * Request server: continuous batching of independent graphs over one device.
+ * Request server: continuous batching of independent graphs over one device. It is not a step
+ * of the paper's method but a serving pattern around it: every request is the whole method
+ * of section 3.2 on one graph.
  *
  * Requests are whole runs (louvain_run) on graphs held in host memory. The server keeps
  * `slots` runs in flight at once, each on its own context and HIP stream, so that the work of
@@ -342,9 +344,9 @@ lv_status louvain_prepare(lv_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
  * (both grow-only) and reserves, before each run, an upper bound of what it will hold after it
  * (its buffers exactly, and for the workspace 320 bytes per vertex, 72 per arc, 640 per graph
  * and 48 MiB, at the largest batch it has run); the reservations of all slots stay within
- * hbm_budget_bytes. A request whose bound alone exceeds
- * the budget fails with LV_EBUDGET; when a request waits for memory, idle slots release
- * theirs and no slot starts other work until it has been admitted.
+ * hbm_budget_bytes. A request whose bound alone exceeds the budget fails with LV_EBUDGET;
+ * when a request waits for memory, idle slots release theirs and no slot starts other work
+ * until it has been admitted.
  *
  * Request graphs: lv_graph with HOST pointers (offsets int32 or int64, weights uint32 only),
  * checked on the device while they are packed (offsets from 0 to nnz and non-decreasing,
@@ -411,7 +413,8 @@ lv_status louvain_server_submit(lv_server* server, const lv_graph* g, int32_t* m
                                 uint64_t* ticket);
 /* Waits up to timeout_ms (< 0: no limit, 0: poll) for a request; on LV_OK `out` holds its
  * outcome and the ticket is released. LV_ETIMEOUT if it is still queued or running (the ticket
- * stays valid); LV_EINVAL for an unknown or already returned ticket. */
+ * stays valid); LV_EINVAL for an unknown or already returned ticket, or one that another
+ * thread is waiting for (one waiter per ticket). */
 lv_status louvain_server_wait(lv_server* server, uint64_t ticket, int64_t timeout_ms,
                               lv_request_result* out);
 /* Drops a request that is still queued: it completes with LV_ECANCELLED (collect it with
