@@ -588,6 +588,35 @@ def graph_result_dict(r: LvGraphResult) -> dict:
             "n_communities": r.n_communities, "W": r.W, "qnum": r.q_num.value(), "q": r.q}
 
 
+def request_struct(n, offsets, indices, weights, membership=None):
+    """(lv_graph with host pointers, membership tensor) for louvain_server_submit, after the
+    checks the library cannot make on host memory: the arrays' sizes against n and each other,
+    so that the server never reads or writes past a request's buffers."""
+    n = int(n)
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    for t in (offsets, indices, weights):
+        if t.is_cuda or not t.is_contiguous():
+            raise ValueError("request tensors must be contiguous host tensors")
+    if offsets.dtype not in (torch.int32, torch.int64) or indices.dtype != torch.int32 \
+            or weights.dtype != torch.int32:
+        raise ValueError("offsets int32/int64, indices int32, weights int32 (uint32 bits)")
+    if offsets.numel() != n + 1 and not (n == 0 and offsets.numel() == 0):
+        raise ValueError(f"offsets has {offsets.numel()} entries, n + 1 = {n + 1} expected")
+    if indices.numel() != weights.numel():
+        raise ValueError("indices and weights differ in length")
+    if membership is None:
+        membership = torch.empty(max(n, 1), dtype=torch.int32, pin_memory=offsets.is_pinned())
+    elif membership.is_cuda or not membership.is_contiguous() or \
+            membership.dtype != torch.int32 or membership.numel() < n:
+        raise ValueError("membership must be a contiguous int32 host tensor of n entries")
+    m = int(indices.numel())
+    g = LvGraph(n, m, offsets.data_ptr() if offsets.numel() else 0,
+                indices.data_ptr() if m else 0, weights.data_ptr() if m else 0,
+                1 if offsets.dtype == torch.int64 else 0, 0)
+    return g, membership
+
+
 class Server:
     """The library's request server (louvain_server_*): ``slots`` runs in flight at once, each
     batching the queued requests up to ``batch_arcs`` arcs, device memory admitted against
@@ -625,18 +654,7 @@ class Server:
         """Queues one graph (host tensors: offsets int32/int64 [n+1], indices int32, weights
         int32 holding uint32 bits). Returns the ticket; the membership (int32 [n], host) comes
         back from wait()."""
-        for t in (offsets, indices, weights):
-            if t.is_cuda or not t.is_contiguous():
-                raise ValueError("request tensors must be contiguous host tensors")
-        if offsets.dtype not in (torch.int32, torch.int64) or indices.dtype != torch.int32 \
-                or weights.dtype != torch.int32:
-            raise ValueError("offsets int32/int64, indices int32, weights int32 (uint32 bits)")
-        if membership is None:
-            membership = torch.empty(max(int(n), 1), dtype=torch.int32,
-                                     pin_memory=offsets.is_pinned())
-        m = int(indices.numel())
-        g = LvGraph(int(n), m, offsets.data_ptr(), indices.data_ptr() if m else 0,
-                    weights.data_ptr() if m else 0, 1 if offsets.dtype == torch.int64 else 0, 0)
+        g, membership = request_struct(n, offsets, indices, weights, membership)
         t = ctypes.c_uint64()
         st = self.lib.louvain_server_submit(self.h, ctypes.byref(g), _ptr(membership),
                                             ctypes.byref(t))

@@ -1,6 +1,6 @@
-"""Host logic of bench.py, without a GPU: the one-GPU refusal, the graph cache format, and the
-rocprofv3 summaries (counter scaling by the calibration copy, per-launch bytes, the source
-hash that invalidates a stale traffic figure)."""
+"""Host logic without a GPU: bench.py's one-GPU refusal, its graph cache format and its
+rocprofv3 summaries (counter scaling by the calibration copy, per-launch bytes, the source hash
+that invalidates a stale traffic figure); and the binding's checks of server requests."""
 
 import json
 import os
@@ -129,3 +129,36 @@ def test_stats_summary(tmp_path):
     assert "k_move_lds" in lines[0] and "75.0%" in lines[0]
     assert "k_apply_moves" in lines[1] and "25.0%" in lines[1]
     assert "vectorized_elementwise" not in text
+
+
+def test_server_request_checks():
+    """The binding's host-side checks of a server request (no GPU needed): sizes against n,
+    dtypes, devices; a good request maps onto lv_graph."""
+    from paper_2301_12390_amd.louvain import request_struct
+    i32, i64 = torch.int32, torch.int64
+    off = torch.tensor([0, 2, 3, 4], dtype=i64)
+    idx = torch.tensor([1, 2, 0, 0], dtype=i32)
+    w = torch.ones(4, dtype=i32)
+    g, memb = request_struct(3, off, idx, w)
+    assert (g.n, g.nnz, g.offsets_64, g.weights_64) == (3, 4, 1, 0)
+    assert memb.dtype == i32 and memb.numel() == 3
+    g, _ = request_struct(3, off.to(i32), idx, w)
+    assert g.offsets_64 == 0
+    g, _ = request_struct(0, torch.zeros(1, dtype=i32), idx[:0], w[:0])
+    assert g.n == 0 and g.nnz == 0
+    bad = [
+        (4, off, idx, w, None),                           # offsets too short for n
+        (2, off, idx, w, None),                           # offsets too long for n
+        (3, off, idx, w[:3], None),                       # weights shorter than indices
+        (3, off, idx.to(i64), w, None),                   # 64-bit indices
+        (3, off, idx, w.to(i64), None),                   # 64-bit weights
+        (3, off.to(torch.float32), idx, w, None),         # float offsets
+        (3, off, idx, w, torch.empty(2, dtype=i32)),      # membership too short
+        (3, off, idx, w, torch.empty(3, dtype=i64)),      # membership of the wrong type
+        (-1, off, idx, w, None),
+        (3, off, idx[:0], w, None),                       # indices shorter than weights
+        (3, off, torch.stack([idx, idx], 1)[:, 0], w, None),  # not contiguous
+    ]
+    for n, o, i, ww, m in bad:
+        with pytest.raises(ValueError):
+            request_struct(n, o, i, ww, m)
