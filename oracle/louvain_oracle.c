@@ -32,8 +32,10 @@
  *   - the total modularity change of an iteration is 2*S/W^2 with S the sum of the applied
  *     gains; the phase repeats while it exceeds tolerance_p = 10^-(a + b*p) in pass p, i.e.
  *     while S > floor(W^2 / (2 * 10^(a+b*p)));
- *   - pass_tolerance is 0: a pass that moves nothing ends the run; aggregation that does not
- *     shrink the graph, or the pass limit, also ends it;
+ *   - pass_tolerance is 0: the passes go on while a pass raises modularity. A pass that does
+ *     not (no vertex moved, or simultaneous synchronous moves that together did not raise it)
+ *     ends the run and is not kept: the result is the level before it. Aggregation that does
+ *     not shrink the graph, or the pass limit, also ends the run;
  *   - aggregation renumbers used community labels by ascending rank.
  */
 #include <stdint.h>
@@ -561,6 +563,14 @@ static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const u
     /* every vertex starts in its own community; K of a super-vertex is its row sum */
     orc_degrees(cn, off, w, K);
     for (int64_t i = 0; i < cn; i++) { C[i] = (int32_t)i; Sig[i] = K[i]; csize[i] = 1; }
+    /* modularity before the pass: every vertex of the current graph alone, i.e. the partition
+     * of the previous level (aggregation keeps modularity) */
+    i128 q_before;
+    {
+      uint64_t qb[2], Wq = 0;
+      orc_modularity(cn, off, idx, w, C, qb, &Wq, NULL);
+      q_before = (i128)((u128)qb[0] | ((u128)qb[1] << 64));
+    }
     uint64_t Tw[2];
     orc_threshold(W, a, b, p, Tw);
     u128 T = (u128)Tw[0] | ((u128)Tw[1] << 64);
@@ -581,7 +591,6 @@ static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const u
       }
       cls_start[substeps] = pos;
     }
-    i128 pass_gain = 0;
     int32_t iters = 0, below_tolerance = 0;
     for (int32_t it = 0; it < max_it; it++) {
       uint64_t Sw[2];
@@ -610,17 +619,20 @@ static int run_impl(int64_t n, const int64_t* off0, const int32_t* idx0, const u
         res->trace_ncand[t] = ncand;
       }
       iters++;
-      pass_gain += S;
       if (!((u128)S > T)) { below_tolerance = 1; break; } /* the moves just made are kept */
     }
     if (!below_tolerance) res->cap_hits++; /* the phase ran out of iterations */
     res->iterations[p] = iters;
     res->iterations_total += iters;
+    i128 q_after;
     {
       uint64_t Wq = 0;
       orc_modularity(cn, off, idx, w, C, res->qnum_pass + 2 * p, &Wq, NULL);
+      q_after = (i128)((u128)res->qnum_pass[2 * p] | ((u128)res->qnum_pass[2 * p + 1] << 64));
     }
-    if (pass_gain == 0) break; /* no vertex moved: nothing to aggregate */
+    /* pass_tolerance = 0: a pass whose increase in modularity is not above it ends the run and
+     * its partition is dropped (when nothing moved, it is the previous level anyway) */
+    if (!(q_after > q_before)) break;
     int64_t nn = 0, nnz2 = 0;
     orc_aggregate(cn, off, idx, w, C, map, off2, idx2, w2, &nn, &nnz2);
     for (int64_t v = 0; v < n; v++) top[v] = map[top[v]];

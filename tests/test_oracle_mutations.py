@@ -60,6 +60,14 @@ MUTATIONS = {
                                 "for (int64_t v = 0; v < n; v++) top[v] = map[v];"),
     "partition_keeps_part_edge": ("if (idx[e] >= v0 && idx[e] < v1) {",
                                   "if (idx[e] >= v0 && idx[e] < v1 && idx[e] != v1 - 1) {"),
+    "class_pass_index": (": colour_classes ? colour[v] : orc_vertex_class(p, substeps, v);",
+                         ": colour_classes ? colour[v] : orc_vertex_class(0, substeps, v);"),
+    "pass_keeps_non_increasing": ("if (!(q_after > q_before)) break;",
+                                  "if (q_after == q_before) break;"),
+    "gain_product_wraps_64": ("i128 g = (i128)W * (i128)acc[c] - Ki * (i128)Sig[c];",
+                              "i128 g = (i128)(W * acc[c]) - Ki * (i128)Sig[c];"),
+    "modularity_product_wraps_64": ("i128 q = (i128)((u128)W * sigma) - (i128)sq;",
+                                    "i128 q = (i128)(W * sigma) - (i128)sq;"),
     "level_cap_off_by_one": ("if (levels && n_levels && *n_levels < max_levels) {",
                              "if (levels && n_levels && *n_levels + 1 < max_levels) {"),
 }
@@ -85,6 +93,10 @@ def battery():
     P.test_ring_of_cliques_recovered()
     P.test_levels_ring_of_k4_hand_derived()
     P.test_levels_edge_cases()
+    P.test_pass_that_lowers_modularity_is_dropped()
+    P.test_run_classes_are_the_hashed_classes()
+    P.test_big_weights_modularity_and_single_moves()
+    P.test_big_weights_sync_async_aggregation()
     from . import test_oracle_colour as PC
     for K in (2, 8, 32):
         PC.test_matches_jones_plassmann_rounds(K)

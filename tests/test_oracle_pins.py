@@ -638,3 +638,193 @@ def test_levels_edge_cases():
     g = O.Graph.from_csr(ring_of_cliques(64, 3))
     top, res = O.run(g, "sync", max_passes=1, levels=True)
     assert len(res["levels"]) == 1 and (res["levels"][0] == top).all()
+
+
+# ----------------------------------------------------------------------------------------------
+# pass_tolerance = 0: a pass that does not raise modularity ends the run and is not kept
+
+
+def aggregate_by_definition(g: O.Graph, C):
+    """Super-vertex graph of labels C written from the definition: labels ranked ascending,
+    super-arc (a, b) weighing the sum of the arcs (i, j) with ranks (a, b)."""
+    labels = sorted(set(int(c) for c in C))
+    rank = {c: r for r, c in enumerate(labels)}
+    acc = {}
+    for i, j, w in arcs_of(g):
+        key = (rank[int(C[i])], rank[int(C[j])])
+        acc[key] = acc.get(key, 0) + w
+    n2 = len(labels)
+    rows = [sorted((b, w) for (a, b), w in acc.items() if a == r) for r in range(n2)]
+    off = np.zeros(n2 + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.array([b for r in rows for b, _ in r], dtype=np.int32)
+    w = np.array([x for r in rows for _, x in r], dtype=np.uint64)
+    return [rank[int(c)] for c in C], O.Graph(n2, off, idx, w)
+
+
+def phase_bruteforce(g: O.Graph, p: int, a: int = 2, b: int = 1, max_it: int = 20):
+    """One fully synchronous local-moving phase of pass p from singletons, every decision by
+    brute force over modularity differences; stops when S <= floor(W^2 / (2*10^(a+b*p))) or
+    after max_it iterations. Returns (C, iterations)."""
+    W = sum(w for _, _, w in arcs_of(g))
+    T = (W * W) // (2 * 10 ** (a + b * p))
+    C = np.arange(g.n, dtype=np.int32)
+    for it in range(max_it):
+        C, S = sync_decisions_bruteforce(g, C)
+        if S <= T:
+            return C, it + 1
+    return C, max_it
+
+
+def test_pass_that_lowers_modularity_is_dropped():
+    """A 9-vertex graph on which the synchronous rule's second pass oscillates into a partition
+    of lower modularity than the first level. Both phases are recomputed here by brute force
+    (decisions from modularity differences, aggregation from its definition, Q from the pairwise
+    definition); the run must return the first level, report the second pass's Q, and stop."""
+    g = O.Graph.from_csr(erdos_renyi(9, 0.45, seed=5098, weights=(1, 5)))
+    W = sum(w for _, _, w in arcs_of(g))
+    q_single = q_pairwise(g, np.arange(g.n))
+    C0, it0 = phase_bruteforce(g, 0)
+    level1, g1 = aggregate_by_definition(g, C0)
+    q1 = q_pairwise(g, C0)
+    C1, it1 = phase_bruteforce(g1, 1)
+    q2 = q_pairwise(g, [int(C1[level1[v]]) for v in range(g.n)])
+    assert q1 > q_single and q2 <= q1  # the second pass does not raise modularity
+    assert (it0, it1) == (3, 20)
+    top, res = O.run(g, "sync")
+    assert top.tolist() == level1
+    assert Fraction(res["qnum"], W * W) == q1
+    assert res["passes"] == 2 and res["iterations"] == [it0, it1]
+    assert [Fraction(x, W * W) for x in res["qnum_pass"]] == [q1, q2]
+    top, res = O.run(g, "sync", levels=True)
+    assert res["levels"].tolist() == [level1]
+
+
+def test_kept_levels_raise_modularity():
+    """Q strictly increases from level to level of every run (K = 1 and K = 8 classes, and the
+    asynchronous rule), the first level above the singletons; the last pass, if it reports a Q
+    that is not higher than the level before it, added no level."""
+    from graphgen import lattice_shortcuts, rmat
+    graphs = small_graphs() + [O.Graph.from_csr(sbm(3000, 30, 8.0, 2.0, seed=2, weights=(1, 16))),
+                               O.Graph.from_csr(lattice_shortcuts(2000, seed=3)),
+                               O.Graph.from_csr(rmat(12, seed=7))]
+    dropped = 0
+    for g in graphs:
+        q_single, W, _ = O.modularity(g, np.arange(g.n, dtype=np.int32))
+        for mode, K in (("sync", 1), ("sync", 8), ("async", 1)):
+            top, res = O.run(g, mode, substeps=K, levels=True)
+            if W == 0:
+                continue
+            L = res["levels"]
+            seq = [q_single] + [O.modularity(g, L[l])[0] for l in range(len(L))]
+            assert all(seq[l + 1] > seq[l] for l in range(len(seq) - 1)), (g.n, mode, K)
+            assert res["qnum"] == seq[-1]
+            assert res["qnum_pass"][:len(L)] == seq[1:]
+            if len(L) < res["passes"]:
+                assert res["qnum_pass"][len(L)] <= seq[-1]
+                dropped += res["qnum_pass"][len(L)] < seq[-1]
+            if mode == "async":
+                assert len(L) + 1 >= res["passes"]
+    # the fully synchronous rule lowers modularity in some pass of this corpus (R-MAT s12)
+    assert dropped >= 1
+
+
+# ----------------------------------------------------------------------------------------------
+# the run loop's hashed vertex classes (the schedule the GPU runs)
+
+
+def py_vertex_class(p: int, K: int, v: int) -> int:
+    from graphgen.rng import GAMMA, MASK64, mix_int
+    return ((mix_int((p + (v + 1) * GAMMA) & MASK64) >> 32) * K) >> 32
+
+
+def class_steps_python(g: O.Graph, p: int, K: int):
+    """First iteration of pass p from singletons: K synchronous steps over classes computed here
+    with Python integers. Returns (S, moved, candidate pairs)."""
+    st = O.State(g)
+    S = moved = nc = 0
+    for k in range(K):
+        vs = [v for v in range(g.n) if py_vertex_class(p, K, v) == k]
+        a, b, c = O.sync_step(g, st, vs)
+        S, moved, nc = S + a, moved + b, nc + c
+    return S, moved, nc
+
+
+def test_run_classes_are_the_hashed_classes():
+    g = O.Graph.from_csr(sbm(1200, 12, 8.0, 2.0, seed=4, weights=(1, 16)))
+    K = 8
+    top, res = O.run(g, "sync", substeps=K, max_passes=2)
+    assert res["passes"] == 2
+    first = {}
+    for t, p in enumerate(res["trace_pass"]):
+        first.setdefault(p, t)
+    t0, t1 = first[0], first[1]
+    assert (res["trace_S"][t0], res["trace_moved"][t0], res["trace_ncand"][t0]) == \
+        class_steps_python(g, 0, K)
+    # pass 1 runs on the aggregate of pass 0's level, with the classes of pass 1
+    top1, _ = O.run(g, "sync", substeps=K, max_passes=1)
+    _, g1 = aggregate_by_definition(g, top1)
+    S1 = class_steps_python(g1, 1, K)
+    assert S1[1] > 0
+    assert (res["trace_S"][t1], res["trace_moved"][t1], res["trace_ncand"][t1]) == S1
+
+
+# ----------------------------------------------------------------------------------------------
+# weights near 2^62 in total: every product W * k and K * Sigma exceeds 64 bits
+
+
+def big_weight_graphs():
+    """small_graphs() with every weight w replaced by (w << s) - (40503 w mod 2^15), s chosen so
+    that W lies just below 2^62 (symmetric: the new weight is a function of the old)."""
+    out = []
+    for g in small_graphs():
+        w = g.w.astype(object)
+        W0 = int(sum(int(x) for x in w))
+        s = 62 - W0.bit_length()
+        nw = np.array([(int(x) << s) - ((40503 * int(x)) & 0x7FFF) for x in w], dtype=np.uint64)
+        g2 = O.Graph(g.n, g.off.copy(), g.idx.copy(), nw)
+        W = int(sum(int(x) for x in nw))
+        K = [0] * g.n
+        for i, _, x in arcs_of(g2):
+            K[i] += x
+        assert 2 ** 60 < W <= 2 ** 62 and W * max(K) >= 2 ** 64
+        out.append(g2)
+    return out
+
+
+def test_big_weights_modularity_and_single_moves():
+    for gi, g in enumerate(big_weight_graphs()):
+        C = random_partition(g.n, 3, 900 + gi)
+        qnum, W, _ = O.modularity(g, C)
+        assert Fraction(qnum, W * W) == q_pairwise(g, C)
+        st = O.State(g, C)
+        q0 = q_pairwise(g, C)
+        for i in range(g.n):
+            gains, stay = O.vertex_gains(g, st, i)
+            for c, gval in gains.items():
+                C2 = C.copy()
+                C2[i] = c
+                assert q_pairwise(g, C2) - q0 == Fraction(2 * (gval - stay), W * W), (gi, i, c)
+
+
+def test_big_weights_sync_async_aggregation():
+    for gi, g in enumerate(big_weight_graphs()):
+        for C in (np.arange(g.n, dtype=np.int32), random_partition(g.n, 4, 950 + gi)):
+            st = O.State(g, C)
+            S, moved, _ = O.sync_iteration(g, st)
+            Cn, Sb = sync_decisions_bruteforce(g, C)
+            assert np.array_equal(st.C, Cn) and S == Sb, gi
+        st = O.State(g)
+        q_prev, _, _ = O.modularity(g, st.C)
+        for _ in range(4):
+            S, _ = O.async_iteration(g, st)
+            q, _, _ = O.modularity(g, st.C)
+            assert q - q_prev == 2 * S
+            q_prev = q
+        check_aggregation(g, random_partition(g.n, 3, 970 + gi))
+    for g in big_weight_graphs()[:4]:
+        qo = q_opt_bruteforce(g)
+        for mode in ("sync", "async"):
+            top, res = O.run(g, mode)
+            assert Fraction(res["qnum"], res["W"] ** 2) <= qo
+            assert O.modularity(g, top)[0] == res["qnum"]
