@@ -57,7 +57,8 @@ typedef enum {
   LV_EINVAL = -1,    /* null pointer, negative size, bad parameter, or invalid graph */
   LV_ENOMEM = -2,    /* device allocation failed */
   LV_EHIP = -3,      /* a HIP runtime call or kernel launch failed */
-  LV_EOVERFLOW = -4, /* n >= 2^31, nnz >= 2^31 with int32 offsets, or W > 2^62 */
+  LV_EOVERFLOW = -4, /* n >= 2^31, nnz >= 2^31 with int32 offsets, or W > 2^62 (W is the
+                        exact sum of the weights, so a 64-bit wrap-around is detected too) */
   LV_EBUDGET = -5,   /* the workspace would exceed the context's HBM budget */
   LV_ECANCELLED = -6, /* a server request dropped because the server was destroyed first */
   LV_ETIMEOUT = -7    /* louvain_server_wait: the request had not completed in time */
@@ -144,7 +145,9 @@ typedef struct {
   int32_t iterations[LV_MAX_PASSES];
   int64_t n_pass[LV_MAX_PASSES];          /* vertices of the graph pass p ran on */
   int64_t nnz_pass[LV_MAX_PASSES];        /* arcs of that graph */
-  lv_i128 qnum_pass[LV_MAX_PASSES];       /* W^2*Q after pass p's local-moving phase */
+  lv_i128 qnum_pass[LV_MAX_PASSES];       /* W^2*Q after pass p's local-moving phase (a last
+                                             pass whose value is not above the level before it
+                                             was dropped: see louvain_run) */
   int32_t cap_hits;                       /* phases stopped by max_iterations */
   int32_t n_trace;                        /* records in trace[] (first LV_MAX_TRACE) */
   int64_t n_communities;                  /* communities of the result */
@@ -189,8 +192,10 @@ const char* louvain_last_error(const lv_ctx* ctx);
 /* Bytes of device workspace currently held by the context. */
 uint64_t louvain_workspace_bytes(const lv_ctx* ctx);
 
-/* Whole method (section 3.2): passes of local-moving + aggregation until a pass moves nothing,
- * aggregation stops shrinking the graph, or max_passes is reached.
+/* Whole method (section 3.2): passes of local-moving + aggregation while every pass raises
+ * modularity (pass_tolerance = 0). A pass that does not (nothing moved, or simultaneous moves
+ * that together did not raise Q) ends the run and is dropped: the result is the level before
+ * it. Aggregation that does not shrink the graph, or max_passes, also ends the run.
  * membership: [n] out, the community of every input vertex in the last level of the
  * dendrogram (dense ids 0..n_communities-1; the identity if no pass aggregated).
  * res (host): passes, iterations, per-iteration trace, W and exact Q. */
@@ -241,7 +246,8 @@ lv_status louvain_aggregate(lv_ctx* ctx, const lv_graph* g, const int32_t* C, in
  * Every graph has its own W, tolerance schedule, convergence and stop rules, and its vertex
  * classes hash ids local to the graph, so its result equals louvain_run on that graph alone.
  * membership: [n] out, community of every vertex as a dense id local to its graph.
- * per_graph (host): [G] results. G >= 1; errors as louvain_run (a graph with W > 2^62 gives
+ * per_graph (host): [G] results. G >= 1; errors as louvain_run (a graph with W > 2^62, or a batch
+ * whose total weight reaches 2^64, gives
  * LV_EOVERFLOW for the whole batch). LV_TRACE is ignored. */
 lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
                               const int64_t* graph_vptr, const int64_t* graph_aptr,

@@ -29,7 +29,7 @@ enum SlotId {
   S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
-  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_COUNT_SLOTS
+  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -244,6 +244,32 @@ lv_status weight_stats(lv_ctx* ctx, const uint64_t* K, int64_t n, hipStream_t s,
   HIPCHK(hipStreamSynchronize(s));
   *W = ctx->pinned[PIN_MISC];
   *maxK = ctx->pinned[PIN_MISC + 1];
+  return LV_OK;
+}
+
+// The exact (128-bit) total of g's arc weights. Row sums and W are 64-bit words; they are exact
+// whenever this total is below 2^64. Skipped (*total = 0) when uint32 weights on at most 2^30
+// arcs bound it below 2^62 anyway.
+lv_status total_weight(lv_ctx* ctx, const lv::DevGraph& g, hipStream_t s, u128* total) {
+  *total = 0;
+  if (g.nnz <= 0 || (!g.w64 && g.nnz <= ((int64_t)1 << 30))) return LV_OK;
+  ull* st = nullptr;
+  CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
+  HIPCHK(lv::zero_words(st + ST_MISC, 2, s));
+  HIPCHK(lv::total_weight_u128(g, st + ST_MISC, s));
+  HIPCHK(hipMemcpyAsync(ctx->pinned + PIN_MISC, st + ST_MISC, 2 * sizeof(ull),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *total = ((u128)ctx->pinned[PIN_MISC + 1] << 64) | ctx->pinned[PIN_MISC];
+  return LV_OK;
+}
+
+// LV_EOVERFLOW unless the total weight of g is at most 2^62 (C21: every gain, Sigma product and
+// iteration sum then fits 128 bits, and no 64-bit row sum or W can have wrapped).
+lv_status check_total_weight(lv_ctx* ctx, const lv::DevGraph& g, hipStream_t s) {
+  u128 t = 0;
+  CHK(total_weight(ctx, g, s, &t));
+  if (t > ((u128)1 << 62)) return fail(ctx, LV_EOVERFLOW, "total weight exceeds 2^62");
   return LV_OK;
 }
 
@@ -759,6 +785,7 @@ lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, l
   lv::DevGraph dg;
   CHK(import_graph(ctx, g, false, s, &dg));
   if (dg.n > 0 && !C) return fail(ctx, LV_EINVAL, "C is NULL");
+  CHK(check_total_weight(ctx, dg, s));
   uint64_t* K = nullptr;
   uint64_t* Sig = nullptr;
   CHK(wst(ctx, S_K, dg.n, &K));
@@ -805,6 +832,7 @@ lv_status louvain_move(lv_ctx* ctx, const lv_graph* g, const uint64_t* Kin, uint
     return fail(ctx, LV_EINVAL, "C, Sigma or csize is NULL");
   if (stats) memset(stats, 0, sizeof(*stats));
   if (ph.g.n == 0) return LV_OK;
+  CHK(check_total_weight(ctx, ph.g, s));
   const uint64_t* K = Kin;
   if (!K) {
     uint64_t* Kw = nullptr;
@@ -930,10 +958,11 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
   int64_t* rtile = nullptr;
   CHK(wst(ctx, S_RTILE, lv::row_sum_tiles(g0.nnz) + 1, &rtile));
   HIPCHK(lv::row_sums(g0, K, rtile, s));
+  HIPCHK(lv::iota_i32(membership, n0, s));
+  CHK(check_total_weight(ctx, g0, s));
   uint64_t W = 0, maxK = 0;
   CHK(weight_stats(ctx, K, n0, s, &W, &maxK));
   res->W = W;
-  HIPCHK(lv::iota_i32(membership, n0, s));
   if (W > ((uint64_t)1 << 62)) return fail(ctx, LV_EOVERFLOW, "total weight exceeds 2^62");
   if (W == 0) {
     HIPCHK(hipStreamSynchronize(s));
@@ -944,8 +973,9 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
 
   lv::DevGraph cur = g0;
   int64_t n_comm = n0;
+  // W^2 Q of the current level (before pass 0: every vertex alone)
   i128 qnum = 0;
-  bool have_q = false;
+  CHK(singleton_qnum(ctx, g0, K, W, s, &qnum));
   int which = 0;  // next super-graph buffer set
   void* rec = nullptr;
   CHK(ws(ctx, S_REC, (size_t)n0 * lv::kRecBytes, &rec));
@@ -972,10 +1002,6 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     if (po.hit_cap) res->cap_hits++;
     if (po.gain_sum == 0) {
       // no vertex moved: the partition is that of the previous level
-      if (!have_q) {
-        CHK(singleton_qnum(ctx, cur, K, W, s, &qnum));
-        have_q = true;
-      }
       res->qnum_pass[pass] = to_i128(qnum);
       break;
     }
@@ -996,18 +1022,7 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s,
                   (p->flags & LV_FORCE_WIDE) == 0));
     HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
-    HIPCHK(lv::compose_membership(membership, n0, map, s));
-    if (levels && nlev < max_levels) {
-      HIPCHK(hipMemcpyAsync(levels + (size_t)nlev * (size_t)n0, membership,
-                            sizeof(int32_t) * (size_t)n0, hipMemcpyDeviceToDevice, s));
-      nlev++;
-    }
-    if (trace) {
-      HIPCHK(hipEventRecord(ctx->ev[EV_AGG + 1], s));
-      HIPCHK(hipEventSynchronize(ctx->ev[EV_AGG + 1]));
-      HIPCHK(hipEventElapsedTime(&res->aggregate_ms[pass], ctx->ev[EV_AGG], ctx->ev[EV_AGG + 1]));
-    }
-    // W^2 Q of this pass = that of singletons on the super-vertex graph
+    // W^2 Q reached by this pass = that of singletons on the super-vertex graph
     ull* st = nullptr;
     CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
     ull* d = st + ST_MISC;
@@ -1016,12 +1031,24 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     HIPCHK(lv::sum_squares_u64(K, np, d, s));
     HIPCHK(lv::sum_max_u64(K, np, d + 2, s));
     HIPCHK(hipMemcpyAsync(h, d, 4 * sizeof(ull), hipMemcpyDeviceToHost, s));
+    if (trace) HIPCHK(hipEventRecord(ctx->ev[EV_AGG + 1], s));
     HIPCHK(hipStreamSynchronize(s));
+    if (trace)
+      HIPCHK(hipEventElapsedTime(&res->aggregate_ms[pass], ctx->ev[EV_AGG], ctx->ev[EV_AGG + 1]));
     const u128 sq = ((u128)h[1] << 64) | h[0];
-    qnum = (i128)((u128)W * self) - (i128)sq;
-    have_q = true;
+    const i128 q_pass = (i128)((u128)W * self) - (i128)sq;
+    res->qnum_pass[pass] = to_i128(q_pass);
+    // pass_tolerance = 0 (section 3.2): a pass whose moves did not raise modularity ends the
+    // run, and its partition is not kept (the membership stays at the previous level)
+    if (!(q_pass > qnum)) break;
+    qnum = q_pass;
     maxK = h[3];
-    res->qnum_pass[pass] = to_i128(qnum);
+    HIPCHK(lv::compose_membership(membership, n0, map, s));
+    if (levels && nlev < max_levels) {
+      HIPCHK(hipMemcpyAsync(levels + (size_t)nlev * (size_t)n0, membership,
+                            sizeof(int32_t) * (size_t)n0, hipMemcpyDeviceToDevice, s));
+      nlev++;
+    }
     const bool shrunk = np < cur.n;
     lv::DevGraph nxt;
     nxt.n = np;
@@ -1115,9 +1142,10 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
   ull* gself = gw + 3 * (int64_t)G;
   ull* gsq = gw + 4 * (int64_t)G;
   void* pin = nullptr;
-  CHK(batch_pinned(ctx, (size_t)G * (6 * sizeof(ull) + 1) + 64, &pin));
+  CHK(batch_pinned(ctx, (size_t)G * (6 * sizeof(ull) + 2) + 64, &pin));
   ull* hw = (ull*)pin;                       // 4G words of read-backs
   uint8_t* hact = (uint8_t*)(hw + 4 * (int64_t)G);
+  uint8_t* hkeep = hact + G;
   HIPCHK(hipMemcpyAsync(gbase, graph_vptr, ((size_t)G + 1) * sizeof(int64_t),
                         hipMemcpyHostToDevice, s));
   HIPCHK(lv::graph_ids(gbase, G, n0, gid0, s));
@@ -1150,24 +1178,47 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
   int64_t* rtile = nullptr;
   CHK(wst(ctx, S_RTILE, lv::row_sum_tiles(g0.nnz) + 1, &rtile));
   HIPCHK(lv::row_sums(g0, K, rtile, s));
+  {
+    // every 64-bit sum below (row sums, per-graph W, their total) is exact when the batch's
+    // total weight is below 2^64
+    u128 t = 0;
+    CHK(total_weight(ctx, g0, s, &t));
+    if (t >> 64) return fail(ctx, LV_EOVERFLOW, "the batch's total weight reaches 2^64");
+  }
   uint64_t Wtot = 0, maxK = 0;
   CHK(weight_stats(ctx, K, n0, s, &Wtot, &maxK));
+  // per graph: W, and W^2 Q of every vertex alone (self-loop weight and sum of K^2)
+  uint64_t* selfw = Sig;  // scratch until the first pass
+  HIPCHK(lv::fill_u64(selfw, 0, n0, s));
+  HIPCHK(lv::self_weights(g0, selfw, s));
   HIPCHK(lv::zero_words(Wg, G, s));
+  HIPCHK(lv::zero_words(gself, 3 * (int64_t)G, s));
   HIPCHK(lv::graph_sums(K, n0, gid0, false, Wg, s));
+  HIPCHK(lv::graph_sums(selfw, n0, gid0, false, gself, s));
+  HIPCHK(lv::graph_sums(K, n0, gid0, true, gsq, s));
   HIPCHK(hipMemcpyAsync(hw, Wg, (size_t)G * sizeof(ull), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hw + G, gself, 3 * (size_t)G * sizeof(ull), hipMemcpyDeviceToHost, s));
   HIPCHK(lv::iota_i32(membership, n0, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<uint64_t> W(G);
   std::vector<uint8_t> done(G);
-  std::vector<i128> qnum(G, 0);
+  std::vector<i128> qnum(G, 0);  // W^2 Q of every graph's current level
   uint64_t maxW = 0;
   for (int32_t g = 0; g < G; g++) {
     W[g] = hw[g];
     per_graph[g].W = W[g];
     done[g] = W[g] == 0;  // no arcs: identity membership, Q = 0, no pass
     maxW = std::max(maxW, W[g]);
+    const u128 sq = ((u128)hw[2 * G + 2 * (int64_t)g + 1] << 64) | hw[2 * G + 2 * (int64_t)g];
+    qnum[g] = (i128)((u128)W[g] * hw[G + g]) - (i128)sq;
   }
   if (maxW > ((uint64_t)1 << 62)) return fail(ctx, LV_EOVERFLOW, "a graph's weight exceeds 2^62");
+  // graphs whose last pass was dropped (it did not raise modularity): their membership stays at
+  // the level that pass ran on, whose first super-vertex is gtop[g]
+  std::vector<uint8_t> kept(G, 0);
+  std::vector<int64_t> gtop(graph_vptr, graph_vptr + G);
+  uint8_t* keep_d = nullptr;
+  bool any_kept = false;
 
   lv::DevGraph cur = g0;
   const int32_t* gid = gid0;
@@ -1252,7 +1303,6 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s,
                   (p->flags & LV_FORCE_WIDE) == 0));
     HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
-    HIPCHK(lv::compose_membership(membership, n0, map, s));
     HIPCHK(lv::next_gbase(ab.newid, gb_cur, G, gb_next, s));
     HIPCHK(lv::graph_ids(gb_next, G, np, ngid, s));
     HIPCHK(lv::zero_words(gsq, 2 * (int64_t)G, s));
@@ -1274,14 +1324,35 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     maxK = hw[3 * (int64_t)G + 1];
+    bool newly_kept = false;
     for (int32_t g = 0; g < G; g++) {
-      per_graph[g].n_communities = nb_new[g + 1] - nb_new[g];
       bp.size[g] = nb_new[g + 1] - nb_new[g];
-      if (!ran[g]) continue;
-      const u128 sq = ((u128)hw[G + 2 * (int64_t)g + 1] << 64) | hw[G + 2 * (int64_t)g];
-      qnum[g] = (i128)((u128)W[g] * hw[g]) - (i128)sq;
-      if (nb_new[g + 1] - nb_new[g] == nb_old[g + 1] - nb_old[g]) done[g] = 1;  // no shrink
+      if (kept[g]) continue;
+      if (ran[g]) {
+        const u128 sq = ((u128)hw[G + 2 * (int64_t)g + 1] << 64) | hw[G + 2 * (int64_t)g];
+        const i128 q_pass = (i128)((u128)W[g] * hw[g]) - (i128)sq;
+        if (bp.passgain[g] != 0 && !(q_pass > qnum[g])) {
+          // pass_tolerance = 0: the pass moved vertices without raising modularity; it is
+          // dropped and the graph's membership stays at the level it ran on
+          kept[g] = 1;
+          done[g] = 1;
+          newly_kept = true;
+          continue;
+        }
+        qnum[g] = q_pass;
+        if (nb_new[g + 1] - nb_new[g] == nb_old[g + 1] - nb_old[g]) done[g] = 1;  // no shrink
+      }
+      per_graph[g].n_communities = nb_new[g + 1] - nb_new[g];
+      gtop[g] = nb_new[g];
     }
+    if (newly_kept) {
+      if (!keep_d) CHK(wst(ctx, S_GKEEP, G, &keep_d));
+      memcpy(hkeep, kept.data(), (size_t)G);
+      HIPCHK(hipMemcpyAsync(keep_d, hkeep, (size_t)G, hipMemcpyHostToDevice, s));
+      any_kept = true;
+    }
+    if (any_kept) HIPCHK(lv::compose_membership_masked(membership, n0, map, gid0, keep_d, s));
+    else HIPCHK(lv::compose_membership(membership, n0, map, s));
     lv::DevGraph nxt;
     nxt.n = np;
     nxt.nnz = nnzp;
@@ -1296,7 +1367,11 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     gb_cur = gb_next;
     which ^= 1;
   }
-  HIPCHK(lv::localize_membership(membership, n0, gid0, gb_cur, s));
+  int64_t* gtop_d = nullptr;
+  CHK(wst(ctx, S_GTOP, G, &gtop_d));
+  HIPCHK(hipMemcpyAsync(gtop_d, gtop.data(), (size_t)G * sizeof(int64_t), hipMemcpyHostToDevice,
+                        s));
+  HIPCHK(lv::localize_membership(membership, n0, gid0, gtop_d, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int32_t g = 0; g < G; g++) {
     per_graph[g].q_num = to_i128(qnum[g]);

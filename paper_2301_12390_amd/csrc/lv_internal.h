@@ -77,6 +77,8 @@ hipError_t widen_weights(const uint32_t* in, uint64_t* out, int64_t m, hipStream
 hipError_t sum_max_u64(const uint64_t* a, int64_t n, unsigned long long* out, hipStream_t s);
 // out[0..1] += sum(a[i]^2) as a 128-bit value
 hipError_t sum_squares_u64(const uint64_t* a, int64_t n, unsigned long long* out, hipStream_t s);
+// out[0..1] += sum of all arc weights of g as a 128-bit value
+hipError_t total_weight_u128(const DevGraph& g, unsigned long long* out, hipStream_t s);
 // Validation: sets *bad nonzero if an index is out of range, a weight is 0, or offsets
 // decrease.
 hipError_t validate_graph(const DevGraph& g, unsigned int* bad, hipStream_t s);
@@ -164,6 +166,8 @@ int64_t move_lds_blocks(const Buckets& b, int cls, int hub_first);
 // out[0] += sum of w over arcs (r, j) with C[r] == C[j] (C == nullptr: r == j, i.e. loops)
 hipError_t intra_weight(const DevGraph& g, const int32_t* C, unsigned long long* out,
                         hipStream_t s);
+// selfw[r] += weight of row r's self-loops (selfw zeroed; needs g.off)
+hipError_t self_weights(const DevGraph& g, uint64_t* selfw, hipStream_t s);
 hipError_t sigma_by_label(const uint64_t* K, const int32_t* C, int64_t n, uint64_t* Sig,
                           hipStream_t s);  // Sig zeroed; Sig[C[i]] += K[i]
 hipError_t count_labels(const int32_t* C, int64_t n, int32_t* csize, hipStream_t s);  // zeroed
@@ -214,6 +218,9 @@ hipError_t compact_rows(const int64_t* offp, int64_t np, int64_t nnzp, const int
                         const int64_t* astart, const int32_t* tkey, const uint64_t* tw,
                         int32_t* idx_out, uint64_t* w_out, hipStream_t s);
 hipError_t compose_membership(int32_t* top, int64_t n, const int32_t* map, hipStream_t s);
+// top[v] = map[top[v]] except for the vertices v of graphs with keep[gid0[v]] != 0
+hipError_t compose_membership_masked(int32_t* top, int64_t n, const int32_t* map,
+                                     const int32_t* gid0, const uint8_t* keep, hipStream_t s);
 
 // ---- batches of graphs (consecutive vertex ranges gbase[g] .. gbase[g+1])
 hipError_t fold_gain_slices(unsigned long long* gS, int64_t G, hipStream_t s);

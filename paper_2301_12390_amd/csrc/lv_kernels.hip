@@ -170,6 +170,29 @@ hipError_t sum_squares_u64(const uint64_t* a, int64_t n, ull* out, hipStream_t s
   return hipGetLastError();
 }
 
+// out[0..1] += the 128-bit sum of all arc weights. Row sums and W are 64-bit words; this exact
+// total tells the host whether any of them could have wrapped (they cannot when it is <= 2^62).
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_total_weight(const WT* w, int64_t nnz, ull* out) {
+  __shared__ u128 red[kBlock / 64];
+  u128 acc = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    acc += (u128)ld_stream(w + e);
+  acc = block_sum_u128(acc, red);
+  if (threadIdx.x == 0 && acc) atomic_add_u128(out, acc);
+}
+hipError_t total_weight_u128(const DevGraph& g, ull* out, hipStream_t s) {
+  if (g.nnz <= 0) return hipSuccess;
+  if (g.w64)
+    LV_LAUNCH(k_total_weight<uint64_t>, grid_for(g.nnz, kBlock, 4096), kBlock, 0, s,
+              (const uint64_t*)g.w, g.nnz, out);
+  else
+    LV_LAUNCH(k_total_weight<uint32_t>, grid_for(g.nnz, kBlock, 4096), kBlock, 0, s,
+              (const uint32_t*)g.w, g.nnz, out);
+  return hipGetLastError();
+}
+
 template <typename WT>
 __global__ void k_validate(const int64_t* off, int64_t n, int64_t nnz, const int32_t* idx,
                            const WT* w, unsigned int* bad) {
@@ -455,6 +478,37 @@ hipError_t intra_weight(const DevGraph& g, const int32_t* C, ull* out, hipStream
   else
     LV_LAUNCH(k_intra_weight<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
               (const uint32_t*)g.w, C, out);
+  return hipGetLastError();
+}
+
+// selfw[r] += weight of the self-loops of row r (selfw zeroed), over arc segments.
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_self_weights(const int64_t* off, int64_t n,
+                                                        int64_t nnz, const int32_t* idx,
+                                                        const WT* w, uint64_t* selfw) {
+  const int64_t e0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * kSeg;
+  if (e0 >= nnz) return;
+  const int64_t e1 = e0 + kSeg < nnz ? e0 + kSeg : nnz;
+  int64_t r = row_of_arc(off, n, e0);
+  int64_t rend = off[r + 1];
+  for (int64_t e = e0; e < e1; e++) {
+    if (e >= rend) {
+      r = advance_row(off, n, r + 1, e);
+      rend = off[r + 1];
+    }
+    if (idx[e] == (int32_t)r) atomicAdd((ull*)&selfw[r], (ull)w[e]);
+  }
+}
+hipError_t self_weights(const DevGraph& g, uint64_t* selfw, hipStream_t s) {
+  if (g.nnz <= 0) return hipSuccess;
+  const int64_t threads = (g.nnz + kSeg - 1) / kSeg;
+  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
+  if (g.w64)
+    LV_LAUNCH(k_self_weights<uint64_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
+              (const uint64_t*)g.w, selfw);
+  else
+    LV_LAUNCH(k_self_weights<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
+              (const uint32_t*)g.w, selfw);
   return hipGetLastError();
 }
 
@@ -2691,6 +2745,19 @@ __global__ void k_compose(int32_t* top, int64_t n, const int32_t* map) {
 hipError_t compose_membership(int32_t* top, int64_t n, const int32_t* map, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   LV_LAUNCH(k_compose, grid_for(n), kBlock, 0, s, top, n, map);
+  return hipGetLastError();
+}
+// As k_compose, leaving the vertices of graphs with keep[g] != 0 at their current level.
+__global__ void k_compose_masked(int32_t* top, int64_t n, const int32_t* map,
+                                 const int32_t* gid0, const uint8_t* keep) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (!keep[gid0[i]]) top[i] = map[top[i]];
+}
+hipError_t compose_membership_masked(int32_t* top, int64_t n, const int32_t* map,
+                                     const int32_t* gid0, const uint8_t* keep, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  LV_LAUNCH(k_compose_masked, grid_for(n), kBlock, 0, s, top, n, map, gid0, keep);
   return hipGetLastError();
 }
 

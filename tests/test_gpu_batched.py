@@ -143,3 +143,21 @@ def test_batch_validation(lv):
     # the valid batch still runs on the same context
     m, r = lv.run_batched(dev, vptr, aptr, flags=LV_VALIDATE)
     assert r[0]["qnum"] == r[1]["qnum"]
+
+
+def test_batch_with_dropped_passes(lv):
+    """Fully synchronous runs in which a pass ends below the level before it (that pass is
+    dropped: pass 0 of R-MAT s12, pass 1 of the ring of 16 K4, pass 2 of SBM-10k) beside graphs
+    whose passes all raise Q: every graph equals its single run, so each dropped graph keeps its
+    own earlier level while the others go on."""
+    from graphgen import config_graph
+    graphs = [ring_of_cliques(16, 4), rmat(12, seed=7), two_triangles(), config_graph("sbm10k"),
+              ring_of_cliques(64, 3)]
+    dropped = 0
+    for g in graphs:
+        _, ref = O.run(O.Graph.from_csr(g), "sync", substeps=1, levels=True)
+        kept = len(ref["levels"])
+        dropped += kept < ref["passes"] and ref["qnum_pass"][kept] < ref["qnum"]
+    assert dropped == 3
+    check_batch(lv, graphs, substeps=1)
+    check_batch(lv, graphs[::-1], substeps=1, flags=LV_SMALL_PARTS)
