@@ -1,12 +1,20 @@
 """Parity at the benchmark's full sizes.
 
-* R-MAT scale 25 (1.05e9 arcs, the timed workload): the whole first local-moving iteration of
-  pass 0 (8 class steps) against the oracle, element by element; the modularity of a whole
-  GPU run recomputed by the oracle; aggregation checked on every vertex's map, every
-  super-vertex's degree and total weight, and on sampled super-rows computed by definition.
+* R-MAT scale 25 (1.05e9 arcs, the timed workload): the whole run against the oracle's whole
+  run stored in ``golden/rmat25_run.json`` (membership SHA-256, Qnum of every pass, every
+  iteration's S, moves and candidate pairs; written by ``golden/make_rmat25_golden.py``, which
+  calls only the oracle), and the quality gate against the stored sequential asynchronous run;
+  the whole first local-moving iteration of pass 0 (8 class steps) against the oracle, element
+  by element; the modularity of a whole GPU run recomputed by the oracle; aggregation checked
+  on every vertex's map, every super-vertex's degree and total weight, and on sampled
+  super-rows computed by definition.
 * R-MAT scale 22 (1.28e8 arcs): a whole run against the oracle's whole run, and the quality gate
   against the sequential asynchronous oracle.
 """
+
+import hashlib
+import json
+import os
 
 import numpy as np
 import pytest
@@ -50,6 +58,39 @@ def rmat25_iter0(rmat25):
     print("oracle: iteration 0 of pass 0 on rmat25", flush=True)
     S, moved, nc = O.substep_iteration(og, st, 0, K_CLASSES, classes)
     return st0, st, (S, moved, nc)
+
+
+GOLDEN25 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat25_run.json")
+
+
+@pytest.mark.timeout(600)
+def test_rmat25_whole_run_matches_golden(lv, rmat25):
+    """The timed configuration end to end: louvain_run on R-MAT s25 (8 classes, tolerance 10^-2
+    declining x10) equals the oracle's stored run bit for bit, and its Q is within 0.01 of the
+    sequential asynchronous run's (section 3.2 compares the two rules' quality)."""
+    from graphgen.lean import csr_sha256_np
+    gold = json.load(open(GOLDEN25))
+    g, og = rmat25
+    assert (g.n, g.nnz) == (gold["graph"]["n"], gold["graph"]["nnz"])
+    print("hashing the rmat25 CSR", flush=True)
+    assert csr_sha256_np(og.n, og.off, og.idx, og.w) == gold["graph"]["csr_sha256"]
+    memb, res = lv.run(g, substeps=K_CLASSES)
+    torch.cuda.synchronize()
+    ref = gold["sync"]
+    m = memb.cpu().numpy()
+    assert hashlib.sha256(np.ascontiguousarray(m, dtype="<i4").tobytes()).hexdigest() == \
+        ref["membership_sha256"]
+    assert res["W"] == gold["graph"]["W"]
+    assert res["qnum"] == ref["qnum"] and res["qnum_pass"] == ref["qnum_pass"]
+    assert res["passes"] == ref["passes"] and res["iterations"] == ref["iterations"]
+    assert res["n_pass"] == ref["n_pass"] and res["nnz_pass"] == ref["nnz_pass"]
+    assert res["n_communities"] == ref["n_communities"] and res["cap_hits"] == ref["cap_hits"]
+    assert [t["S"] for t in res["trace"]] == ref["trace_S"]
+    assert [t["moved"] for t in res["trace"]] == ref["trace_moved"]
+    assert [t["candidates"] for t in res["trace"]] == ref["trace_ncand"]
+    q_async = gold["async"]["q"]
+    print(f"rmat25: Q gpu {res['q']:.6f}, Q async {q_async:.6f}", flush=True)
+    assert res["q"] >= q_async - 0.01
 
 
 @pytest.mark.timeout(600)
@@ -220,12 +261,19 @@ def test_batched_workload_sampled(lv):
         assert m.min() >= 0 and m.max() == res[g]["n_communities"] - 1, g
     sizes = np.array([gr.n for gr in graphs])
     sample = sorted(set(np.argsort(sizes)[-4:].tolist()) | set(range(0, 2048, 97)))
+    worst = 1.0
     for g in sample:
         gr = graphs[g].to("cpu")
-        top, ref = O.run(O.Graph.from_csr(gr), "sync", substeps=K_CLASSES)
+        og = O.Graph.from_csr(gr)
+        top, ref = O.run(og, "sync", substeps=K_CLASSES)
         assert np.array_equal(memb[vptr[g]:vptr[g + 1]], top), g
         assert res[g]["qnum"] == ref["qnum"] and res[g]["iterations"] == ref["iterations"], g
-    print(f"checked {len(sample)} of 2048 graphs against the oracle", flush=True)
+        # quality gate: within 0.01 of the sequential asynchronous rule on the same graph
+        _, ra = O.run(og, "async")
+        assert res[g]["q"] >= ra["q"] - 0.01, (g, res[g]["q"], ra["q"])
+        worst = min(worst, res[g]["q"] - ra["q"])
+    print(f"checked {len(sample)} of 2048 graphs against the oracle; worst Q - Q_async "
+          f"{worst:+.5f}", flush=True)
 
 
 @pytest.mark.timeout(900)
