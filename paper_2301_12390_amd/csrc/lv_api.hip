@@ -665,20 +665,21 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   return LV_OK;
 }
 
-// Qnum of singletons on g: W * (self-loop weight) - sum K^2.
-lv_status singleton_qnum(lv_ctx* ctx, const lv::DevGraph& g, const uint64_t* K, uint64_t W,
-                         hipStream_t s, i128* q) {
+// Qnum of singletons on g: W * (self-loop weight) - sum K^2, from the per-row self-loop
+// weights selfw that row_sums wrote.
+lv_status singleton_qnum(lv_ctx* ctx, const lv::DevGraph& g, const uint64_t* K,
+                         const uint64_t* selfw, uint64_t W, hipStream_t s, i128* q) {
   ull* st = nullptr;
   CHK(wst(ctx, S_STATS, STATS_WORDS, &st));
   ull* d = st + ST_MISC;
   ull* h = ctx->pinned + PIN_MISC;
-  HIPCHK(lv::zero_words(d, 3, s));
-  HIPCHK(lv::intra_weight(g, nullptr, d, s));
-  HIPCHK(lv::sum_squares_u64(K, g.n, d + 1, s));
-  HIPCHK(hipMemcpyAsync(h, d, 3 * sizeof(ull), hipMemcpyDeviceToHost, s));
+  HIPCHK(lv::zero_words(d, 4, s));
+  HIPCHK(lv::sum_squares_u64(K, g.n, d, s));       // d[0..1]
+  HIPCHK(lv::sum_max_u64(selfw, g.n, d + 2, s));   // d[2] (d[3]: max, unused)
+  HIPCHK(hipMemcpyAsync(h, d, 4 * sizeof(ull), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const u128 sq = ((u128)h[2] << 64) | h[1];
-  *q = (i128)((u128)W * h[0]) - (i128)sq;
+  const u128 sq = ((u128)h[1] << 64) | h[0];
+  *q = (i128)((u128)W * h[2]) - (i128)sq;
   return LV_OK;
 }
 
@@ -955,9 +956,10 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
   CHK(wst(ctx, S_CSIZE, n0, &csize));
   CHK(wst(ctx, S_MAP, n0, &map));
   HIPCHK(lv::fill_u64(K, 0, n0, s));
+  HIPCHK(lv::fill_u64(Sig, 0, n0, s));  // self-loop weight of every row until pass 0 starts
   int64_t* rtile = nullptr;
   CHK(wst(ctx, S_RTILE, lv::row_sum_tiles(g0.nnz) + 1, &rtile));
-  HIPCHK(lv::row_sums(g0, K, rtile, s));
+  HIPCHK(lv::row_sums(g0, K, rtile, s, Sig));
   HIPCHK(lv::iota_i32(membership, n0, s));
   CHK(check_total_weight(ctx, g0, s));
   uint64_t W = 0, maxK = 0;
@@ -975,7 +977,7 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
   int64_t n_comm = n0;
   // W^2 Q of the current level (before pass 0: every vertex alone)
   i128 qnum = 0;
-  CHK(singleton_qnum(ctx, g0, K, W, s, &qnum));
+  CHK(singleton_qnum(ctx, g0, K, Sig, W, s, &qnum));
   int which = 0;  // next super-graph buffer set
   void* rec = nullptr;
   CHK(ws(ctx, S_REC, (size_t)n0 * lv::kRecBytes, &rec));
@@ -1175,9 +1177,11 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
   CHK(wst(ctx, S_CSIZE, n0, &csize));
   CHK(wst(ctx, S_MAP, n0, &map));
   HIPCHK(lv::fill_u64(K, 0, n0, s));
+  uint64_t* selfw = Sig;  // self-loop weight of every row until the first pass
+  HIPCHK(lv::fill_u64(selfw, 0, n0, s));
   int64_t* rtile = nullptr;
   CHK(wst(ctx, S_RTILE, lv::row_sum_tiles(g0.nnz) + 1, &rtile));
-  HIPCHK(lv::row_sums(g0, K, rtile, s));
+  HIPCHK(lv::row_sums(g0, K, rtile, s, selfw));
   {
     // every 64-bit sum below (row sums, per-graph W, their total) is exact when the batch's
     // total weight is below 2^64
@@ -1188,9 +1192,6 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
   uint64_t Wtot = 0, maxK = 0;
   CHK(weight_stats(ctx, K, n0, s, &Wtot, &maxK));
   // per graph: W, and W^2 Q of every vertex alone (self-loop weight and sum of K^2)
-  uint64_t* selfw = Sig;  // scratch until the first pass
-  HIPCHK(lv::fill_u64(selfw, 0, n0, s));
-  HIPCHK(lv::self_weights(g0, selfw, s));
   HIPCHK(lv::zero_words(Wg, G, s));
   HIPCHK(lv::zero_words(gself, 3 * (int64_t)G, s));
   HIPCHK(lv::graph_sums(K, n0, gid0, false, Wg, s));

@@ -92,8 +92,10 @@ hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* pa
                           hipStream_t s);  // counts x[i] > 0
 
 // ---- pass set-up
-// K must be zero; tile_rows: row_sum_tiles(g.nnz) + 1 words of scratch
-hipError_t row_sums(const DevGraph& g, uint64_t* K, int64_t* tile_rows, hipStream_t s);
+// K must be zero; tile_rows: row_sum_tiles(g.nnz) + 1 words of scratch. selfw (zeroed, or
+// null): per row, the weight of its self-loops.
+hipError_t row_sums(const DevGraph& g, uint64_t* K, int64_t* tile_rows, hipStream_t s,
+                    uint64_t* selfw = nullptr);
 int64_t row_sum_tiles(int64_t nnz);
 // Community state as 16-byte records {C[x], csize[x], Sigma[x]} (see lv_device.h).
 constexpr size_t kRecBytes = 16;
@@ -166,8 +168,6 @@ int64_t move_lds_blocks(const Buckets& b, int cls, int hub_first);
 // out[0] += sum of w over arcs (r, j) with C[r] == C[j] (C == nullptr: r == j, i.e. loops)
 hipError_t intra_weight(const DevGraph& g, const int32_t* C, unsigned long long* out,
                         hipStream_t s);
-// selfw[r] += weight of row r's self-loops (selfw zeroed; needs g.off)
-hipError_t self_weights(const DevGraph& g, uint64_t* selfw, hipStream_t s);
 hipError_t sigma_by_label(const uint64_t* K, const int32_t* C, int64_t n, uint64_t* Sig,
                           hipStream_t s);  // Sig zeroed; Sig[C[i]] += K[i]
 hipError_t count_labels(const int32_t* C, int64_t n, int32_t* csize, hipStream_t s);  // zeroed

@@ -380,11 +380,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_rows(const int64_t* off, int64_
 }
 
 // The rows a tile touches run from tile_rows[b] to tile_rows[b + 1] (that last one may start
-// at the next tile and then contributes nothing here).
-template <typename WT>
+// at the next tile and then contributes nothing here). With SELF, selfw[r] receives the weight
+// of row r's self-loops the same way (one more coalesced read, of the indices).
+template <typename WT, bool SELF>
 __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t nnz,
                                                     const int64_t* tile_rows, const WT* w,
-                                                    uint64_t* K) {
+                                                    const int32_t* idx, uint64_t* K,
+                                                    uint64_t* selfw) {
   __shared__ int64_t span[2];
   __shared__ int64_t longs[kRowTile / kShortRow + 2];
   __shared__ int nlong;
@@ -401,10 +403,19 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t
       longs[atomicAdd(&nlong, 1)] = r;
       continue;
     }
-    ull acc = 0;
-    for (int64_t e = e0; e < e1; e++) acc += (ull)w[e];
-    if (b0 >= lo && b1 <= hi) K[r] = acc;
-    else atomicAdd((ull*)&K[r], acc);
+    ull acc = 0, sl = 0;
+    for (int64_t e = e0; e < e1; e++) {
+      const ull x = (ull)w[e];
+      acc += x;
+      if (SELF && idx[e] == (int32_t)r) sl += x;
+    }
+    if (b0 >= lo && b1 <= hi) {
+      K[r] = acc;
+      if (SELF) selfw[r] = sl;
+    } else {
+      atomicAdd((ull*)&K[r], acc);
+      if (SELF && sl) atomicAdd((ull*)&selfw[r], sl);
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -412,29 +423,49 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t
     const int64_t r = longs[i];
     const int64_t b0 = off[r], b1 = off[r + 1];
     const int64_t e0 = b0 > lo ? b0 : lo, e1 = b1 < hi ? b1 : hi;
-    ull acc = 0;
-    for (int64_t e = e0 + lane; e < e1; e += 64) acc += (ull)ld_stream(w + e);
+    ull acc = 0, sl = 0;
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
+      const ull x = (ull)ld_stream(w + e);
+      acc += x;
+      if (SELF && ld_stream(idx + e) == (int32_t)r) sl += x;
+    }
     acc = group_sum_u64<64>(acc);
+    if (SELF) sl = group_sum_u64<64>(sl);
     if (lane == 0) {
-      if (b0 >= lo && b1 <= hi) K[r] = acc;
-      else atomicAdd((ull*)&K[r], acc);
+      if (b0 >= lo && b1 <= hi) {
+        K[r] = acc;
+        if (SELF) selfw[r] = sl;
+      } else {
+        atomicAdd((ull*)&K[r], acc);
+        if (SELF && sl) atomicAdd((ull*)&selfw[r], sl);
+      }
     }
   }
 }
 
 int64_t row_sum_tiles(int64_t nnz) { return (nnz + kRowTile - 1) / kRowTile; }
 
-hipError_t row_sums(const DevGraph& g, uint64_t* K, int64_t* tile_rows, hipStream_t s) {
+hipError_t row_sums(const DevGraph& g, uint64_t* K, int64_t* tile_rows, hipStream_t s,
+                    uint64_t* selfw) {
   if (g.nnz <= 0) return hipSuccess;
   const int64_t tiles = row_sum_tiles(g.nnz);
   LV_LAUNCH(k_tile_rows, grid_for(g.n), kBlock, 0, s, g.off, g.n, tiles, tile_rows);
   const unsigned grid = (unsigned)tiles;
-  if (g.w64)
-    LV_LAUNCH(k_row_sums<uint64_t>, grid, kBlock, 0, s, g.off, g.nnz, tile_rows,
-              (const uint64_t*)g.w, K);
-  else
-    LV_LAUNCH(k_row_sums<uint32_t>, grid, kBlock, 0, s, g.off, g.nnz, tile_rows,
-              (const uint32_t*)g.w, K);
+  if (g.w64) {
+    if (selfw)
+      LV_LAUNCH((k_row_sums<uint64_t, true>), grid, kBlock, 0, s, g.off, g.nnz, tile_rows,
+                (const uint64_t*)g.w, g.idx, K, selfw);
+    else
+      LV_LAUNCH((k_row_sums<uint64_t, false>), grid, kBlock, 0, s, g.off, g.nnz, tile_rows,
+                (const uint64_t*)g.w, g.idx, K, selfw);
+  } else {
+    if (selfw)
+      LV_LAUNCH((k_row_sums<uint32_t, true>), grid, kBlock, 0, s, g.off, g.nnz, tile_rows,
+                (const uint32_t*)g.w, g.idx, K, selfw);
+    else
+      LV_LAUNCH((k_row_sums<uint32_t, false>), grid, kBlock, 0, s, g.off, g.nnz, tile_rows,
+                (const uint32_t*)g.w, g.idx, K, selfw);
+  }
   return hipGetLastError();
 }
 
@@ -478,37 +509,6 @@ hipError_t intra_weight(const DevGraph& g, const int32_t* C, ull* out, hipStream
   else
     LV_LAUNCH(k_intra_weight<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
               (const uint32_t*)g.w, C, out);
-  return hipGetLastError();
-}
-
-// selfw[r] += weight of the self-loops of row r (selfw zeroed), over arc segments.
-template <typename WT>
-__global__ __launch_bounds__(kBlock) void k_self_weights(const int64_t* off, int64_t n,
-                                                        int64_t nnz, const int32_t* idx,
-                                                        const WT* w, uint64_t* selfw) {
-  const int64_t e0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * kSeg;
-  if (e0 >= nnz) return;
-  const int64_t e1 = e0 + kSeg < nnz ? e0 + kSeg : nnz;
-  int64_t r = row_of_arc(off, n, e0);
-  int64_t rend = off[r + 1];
-  for (int64_t e = e0; e < e1; e++) {
-    if (e >= rend) {
-      r = advance_row(off, n, r + 1, e);
-      rend = off[r + 1];
-    }
-    if (idx[e] == (int32_t)r) atomicAdd((ull*)&selfw[r], (ull)w[e]);
-  }
-}
-hipError_t self_weights(const DevGraph& g, uint64_t* selfw, hipStream_t s) {
-  if (g.nnz <= 0) return hipSuccess;
-  const int64_t threads = (g.nnz + kSeg - 1) / kSeg;
-  const unsigned grid = (unsigned)((threads + kBlock - 1) / kBlock);
-  if (g.w64)
-    LV_LAUNCH(k_self_weights<uint64_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
-              (const uint64_t*)g.w, selfw);
-  else
-    LV_LAUNCH(k_self_weights<uint32_t>, grid, kBlock, 0, s, g.off, g.n, g.nnz, g.idx,
-              (const uint32_t*)g.w, selfw);
   return hipGetLastError();
 }
 
