@@ -260,6 +260,22 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
 lv_status louvain_modularity(lv_ctx* ctx, const lv_graph* g, const int32_t* C, lv_i128* q_num,
                              uint64_t* W, double* q, void* stream);
 
+/* Bytes of the fixed device array behind louvain_modularity_noalloc (per device). */
+#define LV_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* louvain_modularity without any device allocation, for callers that cannot allocate during
+ * the call (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as louvain_modularity, but the temporaries (row sums and
+ * Sigma, n words each; widened offsets for int32 CSRs, n + 1 words; a tile table of nnz / 4096
+ * words; 32 reduction words) live in a fixed array of LV_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it has a context on, from louvain_ctx_create until the process ends.
+ * A graph needing more returns LV_EBUDGET (about 4M vertices with int64 offsets, 2.7M with
+ * int32). The context's workspace is neither used nor grown. Every call on one device shares
+ * that device's array: calls that overlap on the same device (other streams, other host
+ * threads, other contexts) race and must be serialised by the caller. */
+lv_status louvain_modularity_noalloc(lv_ctx* ctx, const lv_graph* g, const int32_t* C,
+                                     lv_i128* q_num, uint64_t* W, double* q, void* stream);
+
 /* Partition and merge (the remedy section 3.2 and the conclusion propose for the method's poor
  * shared-memory scaling: run partitions of the graph independently, then combine them). The P
  * parts are contiguous vertex ranges: part_vptr (host) [P+1] from 0 to n, non-decreasing, or

@@ -58,6 +58,7 @@ constexpr int PIN_COUNTS = 0;     // host: 1536 words of class counts
 constexpr int PIN_HUB = 1536;     // host: hub plan totals
 constexpr int PIN_STATS = 1544;   // host: per-step iteration stats (8 words per class step)
 constexpr int PIN_MISC = 1808;    // host: other read-backs
+constexpr int PIN_NOALLOC = 2016; // host: 16 words of louvain_modularity_noalloc read-backs
 constexpr int PIN_WORDS = 2048;
 constexpr int DEG = 12;           // degree classes per vertex class (list segment stride)
 constexpr int STATS_WORDS = 512;
@@ -82,6 +83,10 @@ struct lv_ctx {
   hipStream_t side[2] = {};
   hipEvent_t fork[32] = {}, join0[32] = {}, join1[32] = {};
 };
+
+int lv::ctx_device(const lv_ctx* ctx) { return ctx->device; }
+void lv::ctx_set_error(lv_ctx* ctx, const char* msg) { ctx->err = msg; }
+unsigned long long* lv::ctx_pinned_words(lv_ctx* ctx) { return ctx->pinned + PIN_NOALLOC; }
 
 namespace {
 
@@ -730,6 +735,11 @@ lv_status louvain_ctx_create(int device, uint64_t hbm_budget_bytes, lv_ctx** out
     return LV_EHIP;
   }
   memset(ctx->pinned, 0, PIN_WORDS * sizeof(ull));
+  // this device's copy of louvain_modularity_noalloc's fixed array (looked up once per device)
+  if (lv::noalloc_setup(device) != hipSuccess) {
+    louvain_ctx_destroy(ctx);
+    return LV_EHIP;
+  }
   for (int i = 0; i < kEvents; i++) {
     if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
       louvain_ctx_destroy(ctx);

@@ -11,6 +11,16 @@ namespace lv {
 // Why a parameter set is invalid, or nullptr if it is valid.
 const char* params_error(const lv_params* p);
 
+// Context accessors for entry points outside lv_api.hip.
+int ctx_device(const lv_ctx* ctx);
+void ctx_set_error(lv_ctx* ctx, const char* msg);
+unsigned long long* ctx_pinned_words(lv_ctx* ctx);  // 16 pinned host words of the context
+
+// The fixed device array of louvain_modularity_noalloc (lv_noalloc.hip): noalloc_setup looks up
+// the current device's copy once (call with `device` current); noalloc_scratch returns it.
+hipError_t noalloc_setup(int device);
+void* noalloc_scratch(int device);
+
 // A graph on the device: row v spans arcs [rs[v], re[v]) of idx/w. For a CSR, rs = off and
 // re = off + 1 (off has n+1 int64 entries; int32 inputs are widened once per call) and `off`
 // is set; super-vertex graphs keep rows where the aggregation wrote them (off is null).

@@ -225,6 +225,10 @@ SIGNATURES = {
     "louvain_modularity": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P, ctypes.POINTER(LvI128),
                                           ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_double), _P]),
+    "louvain_modularity_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), _P,
+                                                  ctypes.POINTER(LvI128),
+                                                  ctypes.POINTER(ctypes.c_uint64),
+                                                  ctypes.POINTER(ctypes.c_double), _P]),
     "louvain_run_batched": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int64),
@@ -577,6 +581,19 @@ class Louvain:
         qd = ctypes.c_double()
         st = self.lib.louvain_modularity(self.h, ctypes.byref(gs), _ptr(C), ctypes.byref(q),
                                          ctypes.byref(W), ctypes.byref(qd), _stream())
+        self._check(st)
+        return q.value(), int(W.value), float(qd.value)
+
+    def modularity_noalloc(self, g, C):
+        """(Qnum, W, q) of membership C through louvain_modularity_noalloc (no device
+        allocation during the call; temporaries in the library's fixed per-device array)."""
+        gs = graph_struct(g)
+        q = LvI128()
+        W = ctypes.c_uint64()
+        qd = ctypes.c_double()
+        st = self.lib.louvain_modularity_noalloc(self.h, ctypes.byref(gs), _ptr(C),
+                                                 ctypes.byref(q), ctypes.byref(W),
+                                                 ctypes.byref(qd), _stream())
         self._check(st)
         return q.value(), int(W.value), float(qd.value)
 
