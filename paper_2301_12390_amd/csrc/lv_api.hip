@@ -647,11 +647,13 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   if (nh > 0) {
     lv::PartPlan pp;
     CHK(wst(ctx, S_HUBARR, lv::kPlanWords * (nh + 1), &a.hub_arrays));
-    HIPCHK(lv::plan_parts(nullptr, nullptr, a.A, a.list + b.lstart[7], nh, np, 8, true,
+    // pair values of the weight width the super-vertex graph gets (both bound by Sigma)
+    const int vb = a.w32 ? 4 : 8;
+    HIPCHK(lv::plan_parts(nullptr, nullptr, a.A, a.list + b.lstart[7], nh, np, vb, true,
                           ctx->part_shift, a.hub_arrays, a.partial, ctx->pinned + PIN_HUB, pp, s));
-    const int64_t pairs = pp.chunks * lv::part_chunk(8);
+    const int64_t pairs = pp.chunks * lv::part_chunk(vb);
     CHK(wst(ctx, S_PK, pairs, &a.pk));
-    CHK(wst(ctx, S_PV, pairs, &a.pv));
+    CHK(ws(ctx, S_PV, (size_t)pairs * vb, &a.pv));
     CHK(wst(ctx, S_HOFF, pp.hoff_entries, &a.hoff));
     CHK(wst(ctx, S_NFLUSH, pp.blocks, &a.nflush));
     HIPCHK(lv::merge_hubs(g, b, pp, a, s));

@@ -207,7 +207,7 @@ struct AggBuffers {
   unsigned long long* block_partial = nullptr;  // 1 word per block of the LDS merge kernel
   int64_t* hub_arrays = nullptr;         // kPlanWords * (hubs + 1)
   int32_t* pk = nullptr;                 // phase-1 pairs of the large communities
-  unsigned long long* pv = nullptr;
+  void* pv = nullptr;                    // their values: uint32 when w32, else uint64
   int32_t* hoff = nullptr;               // their segment bounds
   int32_t* nflush = nullptr;             // table flushes of every phase-1 workgroup
   GraphSet gs;                           // batches: gid (of labels) and gself are used

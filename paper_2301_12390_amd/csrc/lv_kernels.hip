@@ -2234,11 +2234,12 @@ hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& ag, 
   return g.w64 ? merge_lds_t<uint64_t>(g, b, ag, s) : merge_lds_t<uint32_t>(g, b, ag, s);
 }
 
-// Communities of more than 1024 arcs: the two-phase path over their flat arc ranges (values are
-// 8-byte weight sums). Phase 1 covers part_chunk(8) flat arcs per workgroup, each thread a run
-// of consecutive flat arcs (one member search, then a forward walk); a community of one chunk is
-// finished there, others are finished by one phase-2 workgroup per partition.
-template <typename WT>
+// Communities of more than 1024 arcs: the two-phase path over their flat arc ranges. Values are
+// weight sums of V (4 bytes when every community's Sigma, which bounds them, is below 2^32,
+// else 8): phase 1 covers part_chunk(sizeof(V)) flat arcs per workgroup (8192 or 4096), each
+// thread a run of consecutive flat arcs (one member search, then a forward walk); a community of
+// one chunk is finished there, others are finished by one phase-2 workgroup per partition.
+template <typename WT, typename V>
 struct MergeHubArgs {
   const int64_t* rs;
   const int32_t* idx;
@@ -2263,7 +2264,7 @@ struct MergeHubArgs {
   const int64_t* rper;
   const int64_t* nparts;
   int32_t* pk;
-  ull* pv;
+  V* pv;
   int32_t* hoff;
   int32_t* nflush;
   int cap;
@@ -2271,14 +2272,18 @@ struct MergeHubArgs {
   ull* gself;
 };
 
-constexpr int kMergeChunk = part_chunk(8);
-constexpr int kMergeLog2H = part_log2h(8);
-constexpr int kMergePerThread = kMergeChunk / kPartBlock;
+template <typename V>
+struct MergeShape {
+  static constexpr int kChunk = part_chunk((int)sizeof(V));
+  static constexpr int kLog2H = part_log2h((int)sizeof(V));
+  static constexpr int kPerThread = kChunk / kPartBlock;
+};
 
 // Write the LDS table's entries to the community's output row at row + base + (claimed
 // position), base = atomicAdd(dcount, entries) when `shared_row`, else 0 with *dcount = entries.
 // Returns the weight of the entry keyed `me` (this thread's share). flags[2..3]: shared ints.
-__device__ ull merge_emit_table(const int32_t* keys, const ull* vals, int H, int32_t me,
+template <typename V>
+__device__ ull merge_emit_table(const int32_t* keys, const V* vals, int H, int32_t me,
                                 int32_t* okey, WOut ow, int64_t* dcount, bool shared_row,
                                 int* flags, int64_t* base_sh, ull* gself) {
   int mine = 0;
@@ -2307,9 +2312,9 @@ __device__ ull merge_emit_table(const int32_t* keys, const ull* vals, int H, int
     if (key == kEmpty) continue;
     const int64_t pos = base + atomicAdd(&flags[3], 1);
     okey[pos] = key;
-    ow.put(pos, vals[s]);
+    ow.put(pos, (ull)vals[s]);
     if (key == me) {
-      self = vals[s];
+      self = (ull)vals[s];
       if (gself) atomicAdd(gself, self);
     }
   }
@@ -2330,12 +2335,15 @@ __device__ __forceinline__ ull part_block_sum(ull x, ull* red) {
 // Chunk k of community c's flat arc range: each thread a run of kMergePerThread consecutive flat
 // arcs (one member search, then a forward walk), keyed by the target's new id. The members
 // covering the chunk are located once per chunk, so each thread searches only among them.
-template <typename WT>
+template <typename WT, typename V>
 struct MergeChunk {
-  const MergeHubArgs<WT>* a;
+  static constexpr int kMergeChunk = MergeShape<V>::kChunk;
+  static constexpr int kMergeLog2H = MergeShape<V>::kLog2H;
+  static constexpr int kMergePerThread = MergeShape<V>::kPerThread;
+  const MergeHubArgs<WT, V>* a;
   int64_t m0, a0, L;
   int mc;
-  __device__ void operator()(int64_t k, int32_t* keys, ull* vals, int* flags) {
+  __device__ void operator()(int64_t k, int32_t* keys, V* vals, int* flags) {
     __shared__ int span[2];
     const int64_t c0 = k * kMergeChunk;
     const int64_t c1 = c0 + kMergeChunk < L ? c0 + kMergeChunk : L;
@@ -2368,25 +2376,27 @@ struct MergeChunk {
         }
       }
       int32_t j[kMergePerThread];
-      ull wv[kMergePerThread];
+      V wv[kMergePerThread];
 #pragma unroll
       for (int u = 0; u < kMergePerThread; u++) {
         j[u] = e[u] >= 0 ? a->idx[e[u]] : 0;
-        wv[u] = e[u] >= 0 ? (ull)a->w[e[u]] : 0;
+        wv[u] = e[u] >= 0 ? (V)a->w[e[u]] : 0;
       }
       int32_t key[kMergePerThread];
 #pragma unroll
       for (int u = 0; u < kMergePerThread; u++) key[u] = e[u] >= 0 ? a->map[j[u]] : kEmpty;
 #pragma unroll
       for (int u = 0; u < kMergePerThread; u++)
-        if (key[u] != kEmpty) fresh += table_add<ull>(keys, vals, kMergeLog2H, key[u], wv[u]);
+        if (key[u] != kEmpty) fresh += table_add<V>(keys, vals, kMergeLog2H, key[u], wv[u]);
     }
     if (fresh) atomicAdd(&flags[0], fresh);
   }
 };
 
-template <typename WT>
-__global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
+template <typename WT, typename V>
+__global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT, V> a) {
+  constexpr int kMergeChunk = MergeShape<V>::kChunk;
+  constexpr int kMergeLog2H = MergeShape<V>::kLog2H;
   constexpr int H = 1 << kMergeLog2H;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int wsum[kPartBlock / 64 + 1];
@@ -2394,8 +2404,8 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
   __shared__ int64_t base_sh;
   __shared__ ull red[kPartBlock / 64];
   int32_t* keys = (int32_t*)smem;
-  ull* vals = (ull*)(smem + (size_t)H * 4);
-  int* cnt = (int*)(smem + (size_t)H * 12);
+  V* vals = (V*)(smem + (size_t)H * 4);
+  int* cnt = (int*)(smem + (size_t)H * (4 + sizeof(V)));
   const int64_t b = blockIdx.x;
   const int64_t h = find_segment(a.block_start, a.nh, b);
   const int64_t i = b - a.block_start[h];
@@ -2403,7 +2413,7 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
   const int64_t row0 = a.chunk_start[h], nck = a.chunk_start[h + 1] - row0;
   const int64_t k0 = i * R, k1 = k0 + R < nck ? k0 + R : nck;
   const int32_t c = a.hubs[h];
-  MergeChunk<WT> acc;
+  MergeChunk<WT, V> acc;
   acc.a = &a;
   acc.m0 = a.mstart[c];
   acc.mc = (int)(a.mstart[c + 1] - acc.m0);
@@ -2411,7 +2421,7 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
   acc.L = a.A[c];
   if (nck == 1) {
     // the whole community in one table: write its row directly
-    part_table_clear<ull>(keys, vals, H);
+    part_table_clear<V>(keys, vals, H);
     __syncthreads();
     acc(0, keys, vals, flags);
     __syncthreads();
@@ -2424,13 +2434,14 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT> a) {
     return;
   }
   const int P = (int)a.nparts[h];
-  const int nf = part_walk<ull, kMergeLog2H>(acc, k0, k1, P, keys, vals, cnt, wsum, flags,
+  const int nf = part_walk<V, kMergeLog2H>(acc, k0, k1, P, keys, vals, cnt, wsum, flags,
                                              a.hoff + a.hoff_start[h] + k0 * (P + 1),
                                              a.pk + (row0 + k0) * kMergeChunk,
                                              a.pv + (row0 + k0) * kMergeChunk);
   if (threadIdx.x == 0) a.nflush[b] = nf;
 }
 
+template <typename V>
 struct MergeFin {
   int32_t me;
   int32_t* okey;
@@ -2440,13 +2451,15 @@ struct MergeFin {
   int64_t* base_sh;
   ull* gself;
   ull self;
-  __device__ void operator()(const int32_t* keys, const ull* vals, int H) {
+  __device__ void operator()(const int32_t* keys, const V* vals, int H) {
     self += merge_emit_table(keys, vals, H, me, okey, ow, dcount, true, flags, base_sh, gself);
   }
 };
 
-template <typename WT>
-__global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT> a) {
+template <typename WT, typename V>
+__global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT, V> a) {
+  constexpr int kMergeChunk = MergeShape<V>::kChunk;
+  constexpr int kMergeLog2H = MergeShape<V>::kLog2H;
   constexpr int H = 1 << kMergeLog2H;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int wsum[kPartBlock / 64 + 1];
@@ -2454,8 +2467,8 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT> a)
   __shared__ int64_t base_sh;
   __shared__ ull red[kPartBlock / 64];
   int32_t* keys = (int32_t*)smem;
-  ull* vals = (ull*)(smem + (size_t)H * 4);
-  unsigned char* aux = smem + (size_t)H * 12;
+  V* vals = (V*)(smem + (size_t)H * 4);
+  unsigned char* aux = smem + (size_t)H * (4 + sizeof(V));
   const int64_t b = blockIdx.x;
   const int64_t h = find_segment(a.part_start, a.nh, b);
   const int p = (int)(b - a.part_start[h]);
@@ -2463,7 +2476,7 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT> a)
   const int64_t c0 = a.chunk_start[h], nck = a.chunk_start[h + 1] - c0;
   const int32_t c = a.hubs[h];
   const int64_t a0 = a.astart[c];
-  MergeFin fin;
+  MergeFin<V> fin;
   fin.me = (int32_t)a.newid[c];
   fin.okey = a.okey + a0;
   fin.ow = a.ow.at(a0);
@@ -2472,17 +2485,18 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT> a)
   fin.base_sh = &base_sh;
   fin.gself = a.gself ? a.gself + a.gid[c] : nullptr;
   fin.self = 0;
-  part_reduce<ull, kMergeLog2H>(a.pk + c0 * kMergeChunk, a.pv + c0 * kMergeChunk,
+  part_reduce<V, kMergeLog2H>(a.pk + c0 * kMergeChunk, a.pv + c0 * kMergeChunk,
                                 a.hoff + a.hoff_start[h], a.nflush + a.block_start[h], nck,
                                 a.rper[h], P, p, a.cap, keys, vals, aux, wsum, flags, fin);
   const ull bs = part_block_sum(fin.self, red);
   if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
 }
 
-template <typename WT>
+template <typename WT, typename V>
 static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPlan& pp,
                                const AggBuffers& ag, hipStream_t s) {
-  MergeHubArgs<WT> a;
+  constexpr int vb = (int)sizeof(V);
+  MergeHubArgs<WT, V> a;
   a.rs = g.rs;
   a.idx = g.idx;
   a.w = (const WT*)g.w;
@@ -2507,28 +2521,33 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPl
   a.rper = pp.rper;
   a.nparts = pp.nparts;
   a.pk = ag.pk;
-  a.pv = ag.pv;
+  a.pv = (V*)ag.pv;
   a.hoff = ag.hoff;
   a.nflush = ag.nflush;
   a.gid = ag.gs.gid;
   a.gself = ag.gs.gself;
-  a.cap = part_round_cap(kMergeLog2H, pp.shift);
+  a.cap = part_round_cap(MergeShape<V>::kLog2H, pp.shift);
   static const bool attr = [] {  // once, thread-safe (see launch_wg)
-    allow_part_lds(k_merge_part<WT>, 8);
-    allow_part_lds(k_merge_reduce<WT>, 8);
+    allow_part_lds(k_merge_part<WT, V>, vb);
+    allow_part_lds(k_merge_reduce<WT, V>, vb);
     return true;
   }();
   (void)attr;
-  const size_t shm = part_lds_bytes(8);
-  LV_LAUNCH(k_merge_part<WT>, (unsigned)pp.blocks, kPartBlock, shm, s, a);
-  if (pp.parts > 0) LV_LAUNCH(k_merge_reduce<WT>, (unsigned)pp.parts, kPartBlock, shm, s, a);
+  const size_t shm = part_lds_bytes(vb);
+  LV_LAUNCH((k_merge_part<WT, V>), (unsigned)pp.blocks, kPartBlock, shm, s, a);
+  if (pp.parts > 0)
+    LV_LAUNCH((k_merge_reduce<WT, V>), (unsigned)pp.parts, kPartBlock, shm, s, a);
   return hipGetLastError();
 }
 
 hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const PartPlan& pp,
                       const AggBuffers& ag, hipStream_t s) {
   if (pp.nh <= 0) return hipSuccess;
-  return g.w64 ? merge_hubs_t<uint64_t>(g, b, pp, ag, s) : merge_hubs_t<uint32_t>(g, b, pp, ag, s);
+  if (ag.w32)
+    return g.w64 ? merge_hubs_t<uint64_t, uint32_t>(g, b, pp, ag, s)
+                 : merge_hubs_t<uint32_t, uint32_t>(g, b, pp, ag, s);
+  return g.w64 ? merge_hubs_t<uint64_t, ull>(g, b, pp, ag, s)
+               : merge_hubs_t<uint32_t, ull>(g, b, pp, ag, s);
 }
 
 // Rows of the super-vertex graph where the merge left them.
@@ -2760,5 +2779,11 @@ hipError_t compose_membership_masked(int32_t* top, int64_t n, const int32_t* map
   LV_LAUNCH(k_compose_masked, grid_for(n), kBlock, 0, s, top, n, map, gid0, keep);
   return hipGetLastError();
 }
+
+// Kernel-argument structs are passed by value: keep each far inside the 4 KiB kernarg segment.
+static_assert(sizeof(MoveArgs<uint64_t>) <= 1024 && sizeof(WgArgs<uint64_t>) <= 1024 &&
+                  sizeof(HubArgs<uint64_t, u128>) <= 1024 && sizeof(MergeArgs<uint64_t>) <= 1024 &&
+                  sizeof(MergeHubArgs<uint64_t, ull>) <= 1024,
+              "kernel arguments must stay small");
 
 }  // namespace lv
