@@ -9,6 +9,7 @@ ABI in ``include/louvain.h``. ``louvain`` is the Python binding.
 from .louvain import (  # noqa: F401
     LV_COLOR_CLASSES,
     LV_FORCE_WIDE,
+    LV_GRAPH_REPLAY,
     LV_PREP_MAX,
     LV_PREP_PAPER,
     LV_PREP_SELF_LOOPS,

@@ -82,6 +82,9 @@ struct lv_ctx {
   // path on side[1], forked from and joined back into the caller's stream
   hipStream_t side[2] = {};
   hipEvent_t fork[32] = {}, join0[32] = {}, join1[32] = {};
+  // small phases replay an iteration as a HIP graph on `cap`, after gin and before gout
+  hipStream_t cap = nullptr;
+  hipEvent_t gin = nullptr, gout = nullptr;
 };
 
 int lv::ctx_device(const lv_ctx* ctx) { return ctx->device; }
@@ -395,10 +398,111 @@ struct PhaseOut {
   int64_t last_candidates = 0;
 };
 
-// Local-moving iterations; each is `classes` synchronous class steps.
+// One local-moving iteration's kernels, its K synchronous class steps, enqueued on stream s
+// (which may be capturing): clears the step statistics (and the batch's gain sums), then per
+// class step the three move tiers, the record reduction and the community update.
+lv_status issue_iteration(lv_ctx* ctx, Phase& ph, bool trace, hipStream_t s, BatchPhase* bp) {
+  const int K = ph.classes;
+  const int hf = ph.m.hub_first;
+  ull* stats0 = ph.m.stats;
+  HIPCHK(lv::zero_words(stats0, 8 * K, s));
+  if (bp) HIPCHK(lv::zero_words(ph.m.gs.gS, 2 * (int64_t)lv::kGainSlices * bp->G, s));
+  for (int k = 0; k < K; k++) {
+    lv::MoveBuffers m = ph.m;
+    m.stats = stats0 + 8 * k;
+    hipEvent_t* ev = ctx->ev + kEvStep * k;
+    // the three tiers decide disjoint vertices from the same state: when at least two of them
+    // have real work they run concurrently, forked onto the side streams and joined back
+    int64_t ta = 0, tb = 0, tc = 0;
+    for (int j = 0; j < DEG; j++) {
+      const int64_t arcs = ph.b.arcs[DEG * k + j];
+      if (j < 7) ta += arcs;
+      else if (j < hf) tb += arcs;
+      else tc += arcs;
+    }
+    const int64_t kBig = (int64_t)1 << 20;
+    const bool par = (ta >= kBig) + (tb >= kBig) + (tc >= kBig) >= 2;
+    hipStream_t s1 = par ? ctx->side[0] : s, s2 = par ? ctx->side[1] : s;
+    if (par) {
+      HIPCHK(hipEventRecord(ctx->fork[k], s));
+      HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
+      HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
+    }
+    if (trace) HIPCHK(hipEventRecord(ev[0], s));
+    HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
+    if (trace) HIPCHK(hipEventRecord(ev[1], s));
+    if (trace) HIPCHK(hipEventRecord(ev[2], s1));
+    HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
+    if (trace) HIPCHK(hipEventRecord(ev[3], s1));
+    if (trace) HIPCHK(hipEventRecord(ev[4], s2));
+    HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s2));
+    if (trace) HIPCHK(hipEventRecord(ev[5], s2));
+    if (par) {
+      HIPCHK(hipEventRecord(ctx->join0[k], s1));
+      HIPCHK(hipEventRecord(ctx->join1[k], s2));
+      HIPCHK(hipStreamWaitEvent(s, ctx->join0[k], 0));
+      HIPCHK(hipStreamWaitEvent(s, ctx->join1[k], 0));
+    }
+    if (trace) HIPCHK(hipEventRecord(ev[6], s));
+    HIPCHK(lv::reduce_move_partials(ph.b, k, m, s));
+    HIPCHK(lv::apply_moves(ph.b, k, m, s));
+    if (trace) HIPCHK(hipEventRecord(ev[7], s));
+  }
+  return LV_OK;
+}
+
+// An instantiated graph of one iteration, destroyed when it goes out of scope or is replaced.
+struct IterGraph {
+  hipGraphExec_t exec = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  ~IterGraph() { reset(); }
+};
+
+// Captures issue_iteration on the context's capture stream into g->exec. The kernels' arguments
+// are fixed for the phase (row lists, plans and buffers), and everything that changes between
+// iterations lives in device memory, so one capture serves every iteration of the phase until
+// the rows are listed again.
+lv_status capture_iteration(lv_ctx* ctx, Phase& ph, BatchPhase* bp, IterGraph* g) {
+  g->reset();
+  // the capture stream and its events are made on first use only: every stream a context
+  // creates takes its turn among the process's hardware queues, and contexts that never replay
+  // (the default) keep the streams they had without it
+  if (!ctx->cap) {
+    HIPCHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->gin, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->gout, hipEventDisableTiming));
+  }
+  HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+  const lv_status st = issue_iteration(ctx, ph, false, ctx->cap, bp);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+  if (st != LV_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail_hip(ctx, "hipStreamEndCapture", e);
+  const hipError_t ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    g->exec = nullptr;
+    return fail_hip(ctx, "hipGraphInstantiate", ei);
+  }
+  return LV_OK;
+}
+
+// Local-moving iterations; each is `classes` synchronous class steps. With LV_GRAPH_REPLAY a
+// phase on at most kGraphArcs arcs runs its first iteration directly and replays the later ones
+// as a captured HIP graph on the capture stream, ordered after and before the caller's stream
+// by events (not under LV_TRACE); otherwise every kernel is launched directly.
+constexpr int64_t kGraphArcs = (int64_t)1 << 24;
+
 lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, hipStream_t s,
                     lv_result* res, PhaseOut* out, BatchPhase* bp = nullptr) {
   const bool trace = (flags & LV_TRACE) != 0;
+  const bool use_graph = !trace && (flags & LV_GRAPH_REPLAY) && ph.g.nnz <= kGraphArcs;
   const int K = ph.classes;
   const int hf = ph.m.hub_first;
   // the work of each kernel family per iteration (fixed within the phase)
@@ -427,50 +531,18 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
   ull* stats0 = ph.m.stats;
   *out = PhaseOut();
   out->hit_cap = true;
+  IterGraph graph;
   for (int it = 0; it < max_it; it++) {
     auto t0 = std::chrono::steady_clock::now();
-    HIPCHK(lv::zero_words(stats0, 8 * K, s));
-    if (bp) HIPCHK(lv::zero_words(ph.m.gs.gS, 2 * (int64_t)lv::kGainSlices * bp->G, s));
-    for (int k = 0; k < K; k++) {
-      lv::MoveBuffers m = ph.m;
-      m.stats = stats0 + 8 * k;
-      hipEvent_t* ev = ctx->ev + kEvStep * k;
-      // the three tiers decide disjoint vertices from the same state: when at least two of them
-      // have real work they run concurrently, forked onto the side streams and joined back
-      int64_t ta = 0, tb = 0, tc = 0;
-      for (int j = 0; j < DEG; j++) {
-        const int64_t arcs = ph.b.arcs[DEG * k + j];
-        if (j < 7) ta += arcs;
-        else if (j < hf) tb += arcs;
-        else tc += arcs;
-      }
-      const int64_t kBig = (int64_t)1 << 20;
-      const bool par = (ta >= kBig) + (tb >= kBig) + (tc >= kBig) >= 2;
-      hipStream_t s1 = par ? ctx->side[0] : s, s2 = par ? ctx->side[1] : s;
-      if (par) {
-        HIPCHK(hipEventRecord(ctx->fork[k], s));
-        HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
-        HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
-      }
-      if (trace) HIPCHK(hipEventRecord(ev[0], s));
-      HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
-      if (trace) HIPCHK(hipEventRecord(ev[1], s));
-      if (trace) HIPCHK(hipEventRecord(ev[2], s1));
-      HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
-      if (trace) HIPCHK(hipEventRecord(ev[3], s1));
-      if (trace) HIPCHK(hipEventRecord(ev[4], s2));
-      HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s2));
-      if (trace) HIPCHK(hipEventRecord(ev[5], s2));
-      if (par) {
-        HIPCHK(hipEventRecord(ctx->join0[k], s1));
-        HIPCHK(hipEventRecord(ctx->join1[k], s2));
-        HIPCHK(hipStreamWaitEvent(s, ctx->join0[k], 0));
-        HIPCHK(hipStreamWaitEvent(s, ctx->join1[k], 0));
-      }
-      if (trace) HIPCHK(hipEventRecord(ev[6], s));
-      HIPCHK(lv::reduce_move_partials(ph.b, k, m, s));
-      HIPCHK(lv::apply_moves(ph.b, k, m, s));
-      if (trace) HIPCHK(hipEventRecord(ev[7], s));
+    if (use_graph && it > 0) {
+      if (!graph.exec) CHK(capture_iteration(ctx, ph, bp, &graph));
+      HIPCHK(hipEventRecord(ctx->gin, s));
+      HIPCHK(hipStreamWaitEvent(ctx->cap, ctx->gin, 0));
+      HIPCHK(hipGraphLaunch(graph.exec, ctx->cap));
+      HIPCHK(hipEventRecord(ctx->gout, ctx->cap));
+      HIPCHK(hipStreamWaitEvent(s, ctx->gout, 0));
+    } else {
+      CHK(issue_iteration(ctx, ph, trace, s, bp));
     }
     ull* h = ctx->pinned + PIN_STATS;
     HIPCHK(hipMemcpyAsync(h, stats0, 8 * K * sizeof(ull), hipMemcpyDeviceToHost, s));
@@ -567,6 +639,7 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
       if (2 * live < bp->listed) {
         CHK(plan_phase(ctx, ph, s));
         bp->listed = live;
+        graph.reset();
       }
       continue;
     }
@@ -780,6 +853,9 @@ void louvain_ctx_destroy(lv_ctx* ctx) {
   }
   for (int i = 0; i < 2; i++)
     if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+  if (ctx->gin) (void)hipEventDestroy(ctx->gin);
+  if (ctx->gout) (void)hipEventDestroy(ctx->gout);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->bpin) (void)hipHostFree(ctx->bpin);
   delete ctx;

@@ -24,6 +24,7 @@ LV_TRACE = 0x2
 LV_FORCE_WIDE = 0x4
 LV_SMALL_PARTS = 0x8
 LV_COLOR_CLASSES = 0x10
+LV_GRAPH_REPLAY = 0x20
 
 LV_MAX_PASSES = 64
 LV_MAX_TRACE = 1024

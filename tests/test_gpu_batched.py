@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 LV_VALIDATE = 0x1
 LV_FORCE_WIDE = 0x4
 LV_SMALL_PARTS = 0x8
+LV_GRAPH_REPLAY = 0x20
 
 
 @pytest.fixture(scope="module")
@@ -88,7 +89,7 @@ def check_batch(lv, graphs, flags=0, substeps=8, **kw):
 
 
 @pytest.mark.parametrize("K", [1, 8])
-@pytest.mark.parametrize("flags", [0, LV_FORCE_WIDE, LV_SMALL_PARTS])
+@pytest.mark.parametrize("flags", [0, LV_FORCE_WIDE, LV_SMALL_PARTS, LV_GRAPH_REPLAY])
 def test_batch_matches_single_runs(lv, flags, K):
     check_batch(lv, BATCH, flags=flags, substeps=K)
 

@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 
 LV_FORCE_WIDE = 0x4
 LV_SMALL_PARTS = 0x8  # many hash partitions with tiny tables: multi-partition, multi-round paths
+LV_GRAPH_REPLAY = 0x20  # iterations of small phases replayed as captured HIP graphs
 
 
 @pytest.fixture(scope="module")
@@ -234,6 +235,14 @@ def check_run(lv, g, flags=0, substeps=8, **kw):
 @pytest.mark.parametrize("g", CORPUS, ids=IDS)
 def test_run(lv, g, K):
     check_run(lv, g, substeps=K)
+
+
+@pytest.mark.parametrize("K", [1, 8])
+@pytest.mark.parametrize("g", CORPUS, ids=IDS)
+def test_run_graph_replay(lv, g, K):
+    # iterations after the first replayed as a HIP graph captured once per phase: the same
+    # results as direct launches (both are compared with the oracle)
+    check_run(lv, g, flags=LV_GRAPH_REPLAY, substeps=K)
 
 
 @pytest.mark.parametrize("K", [2, 3, 32])
