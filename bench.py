@@ -37,6 +37,12 @@ PMC_KERNELS = {
 }
 
 
+def lib_flags(args):
+    """Library flags every workload passes (LV_GRAPH_REPLAY with --graph-replay)."""
+    from paper_2301_12390_amd import LV_GRAPH_REPLAY
+    return LV_GRAPH_REPLAY if getattr(args, "graph_replay", False) else 0
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -94,6 +100,110 @@ def load_traffic(workload, kernel="k_move_lds"):
     if d.get("workload") != workload or d.get("kernel_src_sha256") != kernel_src_sha(kernel):
         return None
     return d.get("bytes_per_launch")
+
+
+# The kernels of each move tier and of aggregation, for the per-tier PMC summary.
+TIER_KERNELS = {
+    "fused": ("k_move_lds",),
+    "wg": ("k_move_grp7", "k_move_wg"),
+    "hub": ("k_hub_part", "k_hub_reduce", "k_hub_decide"),
+    "agg": ("k_merge_lds", "k_merge_part", "k_merge_reduce", "k_count_members", "k_fill_members",
+            "k_label_ranges", "k_super_rows"),
+}
+TIERS_PMC = os.path.join(ROOT, "profiles", "move_tiers_rmat25_pmc.md")
+
+
+def tiers_src_sha():
+    return hashlib.sha256(open(os.path.join(CSRC, "lv_kernels.hip"), "rb").read()).hexdigest()
+
+
+def load_tier_traffic(workload, tier):
+    """Measured HBM bytes per launch of a tier (its kernels' FETCH_SIZE + WRITE_SIZE per class
+    step or per aggregation) from the committed per-tier PMC summary, if it was taken on this
+    workload with the current kernel source."""
+    try:
+        text = open(TIERS_PMC).read()
+        d = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
+        return None
+    if d.get("workload") != workload or d.get("kernel_src_sha256") != tiers_src_sha():
+        return None
+    return d["tiers"].get(tier, {}).get("bytes_per_launch")
+
+
+def summarize_tiers_pmc(fetch_csv, write_csv, bench_json, out_path, command, workload, copy_mib):
+    """Per-tier HBM traffic of two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
+    `bench.py --steps 1 --warmup 0`: each counter scaled by what it reads for the plain copy of
+    copy_mib MiB, summed over the tier's kernels and divided by the tier's launches in the run."""
+    import numpy as np
+    per = {}
+    for ctr, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in _read_csv(path) if r["Counter_Name"] == ctr]
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+                and int(r["Grid_Size"]) > 0]
+        if not copy:
+            raise SystemExit(f"{path}: no calibration copy dispatch")
+        scale = copy_mib * 1024.0 / max(copy)
+        by_kernel = {}
+        for r in rows:
+            by_kernel.setdefault(_short_name(r["Kernel_Name"]).replace("void ", ""), []).append(
+                float(r["Counter_Value"]) * 1024 * scale)
+        per[ctr] = {"copy_raw_kib": max(copy), "scale": scale, "by_kernel": by_kernel}
+    bj = json.load(open(bench_json))
+    tl = {t["tier"]: t for t in bj["roofline_tiers"]}
+
+    def tier_of(name):
+        for tier, ks in TIER_KERNELS.items():
+            if any(name.startswith(k + "<") or name == k for k in ks):
+                return tier
+        return None
+
+    tiers = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        for k, vals in per[ctr]["by_kernel"].items():
+            t = tier_of(k)
+            if t is None:
+                continue
+            tiers.setdefault(t, {"fetch": 0.0, "write": 0.0})
+            tiers[t]["fetch" if ctr == "FETCH_SIZE" else "write"] += float(np.sum(vals))
+    for t, v in tiers.items():
+        n = tl[t]["launches"] if t in tl else 0
+        v["launches"] = n
+        v["bytes_per_launch"] = (v["fetch"] + v["write"]) / n if n else None
+        v["algorithmic_bytes_per_launch"] = tl[t]["bytes_per_launch"] if t in tl else None
+        v["measured_over_algorithmic"] = (v["bytes_per_launch"] / v["algorithmic_bytes_per_launch"]
+                                          if n and v["algorithmic_bytes_per_launch"] else None)
+    d = {"workload": workload, "kernel_src_sha256": tiers_src_sha(), "tiers": tiers,
+         "calibration": {"copy_bytes": copy_mib << 20,
+                         "fetch_raw_kib": per["FETCH_SIZE"]["copy_raw_kib"],
+                         "fetch_scale": per["FETCH_SIZE"]["scale"],
+                         "write_raw_kib": per["WRITE_SIZE"]["copy_raw_kib"],
+                         "write_scale": per["WRITE_SIZE"]["scale"]}}
+    lines = [f"# HBM traffic of the move tiers and of aggregation, {workload}", "",
+             "Made by (one counter per run, then this summary):", "", "```", command, "```", "",
+             f"Calibration: a plain device copy of {copy_mib} MiB reads FETCH_SIZE = "
+             f"{per['FETCH_SIZE']['copy_raw_kib']:.0f} KiB and WRITE_SIZE = "
+             f"{per['WRITE_SIZE']['copy_raw_kib']:.0f} KiB, so the counters are scaled by "
+             f"{per['FETCH_SIZE']['scale']:.3f} and {per['WRITE_SIZE']['scale']:.3f}.", "",
+             "A launch is one class step's kernels of a move tier, or one pass's aggregation.", "",
+             "| tier | kernels | launches | measured MB / launch | algorithmic MB / launch | "
+             "measured / algorithmic |", "|---|---|---:|---:|---:|---:|"]
+    for t in ("fused", "wg", "hub", "agg"):
+        if t not in tiers or not tiers[t]["launches"]:
+            continue
+        v = tiers[t]
+        lines.append(f"| {t} | {', '.join(TIER_KERNELS[t])} | {v['launches']} | "
+                     f"{v['bytes_per_launch'] / 1e6:.1f} | "
+                     f"{v['algorithmic_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{v['measured_over_algorithmic']:.2f}x |")
+    lines += ["", "| kernel | dispatches | fetch MB / dispatch | write MB / dispatch |",
+              "|---|---:|---:|---:|"]
+    fk, wk = per["FETCH_SIZE"]["by_kernel"], per["WRITE_SIZE"]["by_kernel"]
+    for k in sorted(fk, key=lambda k: -sum(fk[k]))[:14]:
+        lines.append(f"| `{k}` | {len(fk[k])} | {np.mean(fk[k]) / 1e6:.1f} | "
+                     f"{np.mean(wk.get(k, [0.0])) / 1e6:.1f} |")
+    lines += ["", "```json", json.dumps(d, indent=1), "```"]
+    open(out_path, "w").write("\n".join(lines) + "\n")
 
 
 def cpu_baseline(g, res_trace, seconds, substeps, n_arcs_input):
@@ -235,6 +345,12 @@ def summarize_pmc(fetch_csv, write_csv, bench_json, out_path, command, workload,
 def run_batched_bench(args, dev):
     """The batched workload: graphs/s of one louvain_run_batched call over the whole batch,
     against louvain_run called graph by graph (timed once over the whole batch)."""
+    print(json.dumps(batched_measure(args, dev, args.steps, args.warmup,
+                                     not args.no_cpu_baseline)), flush=True)
+
+
+def batched_measure(args, dev, steps, warmup, with_cpu):
+    """The batched workload's JSON record (see run_batched_bench)."""
     import torch
 
     import oracle as O
@@ -249,15 +365,17 @@ def run_batched_bench(args, dev):
     log(f"generated {G} graphs: n={packed.n} nnz={packed.nnz} in "
         f"{time.perf_counter() - t0:.1f}s")
     lv = Louvain(0)
-    for w in range(args.warmup):
-        _, res = lv.run_batched(packed, vptr, aptr, substeps=args.substeps)
+    for w in range(warmup):
+        _, res = lv.run_batched(packed, vptr, aptr, substeps=args.substeps,
+                                 flags=lib_flags(args))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(args.steps):
-        memb, res = lv.run_batched(packed, vptr, aptr, substeps=args.substeps)
+    for _ in range(steps):
+        memb, res = lv.run_batched(packed, vptr, aptr, substeps=args.substeps,
+                                 flags=lib_flags(args))
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
-    ms_per_step = el * 1000.0 / args.steps
+    ms_per_step = el * 1000.0 / steps
     gps = G / (ms_per_step / 1000.0)
     log(f"batched: {ms_per_step:.1f} ms per batch, {gps:.1f} graphs/s")
     # one by one, over the same graphs already in HBM
@@ -267,7 +385,7 @@ def run_batched_bench(args, dev):
         t2 = time.perf_counter()
         q_single = []
         for g in graphs:
-            _, r = lv.run(g, substeps=args.substeps)
+            _, r = lv.run(g, substeps=args.substeps, flags=lib_flags(args))
             q_single.append(r["qnum"])
         torch.cuda.synchronize()
         obo = time.perf_counter() - t2
@@ -280,8 +398,8 @@ def run_batched_bench(args, dev):
         "value": gps,
         "unit": "graphs/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -303,7 +421,7 @@ def run_batched_bench(args, dev):
         "roofline": None,
     }
     lv.close()
-    if not args.no_cpu_baseline:
+    if with_cpu:
         # the oracle's whole runs on the batch's graphs in order, until ~cpu_seconds
         done_arcs = 0
         k = 0
@@ -326,10 +444,15 @@ def run_batched_bench(args, dev):
                        f"batch's {packed.nnz} arcs"),
         }
         log(f"cpu baseline: {line['cpu_baseline']['value']:.2f} graphs/s")
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def run_serving_bench(args, dev):
+    """Serving (see serving_measure), printed as its own JSON line."""
+    print(json.dumps(serving_measure(args, dev)), flush=True)
+
+
+def serving_measure(args, dev, seconds=None, servers=None):
     """Serving: Poisson arrivals of requests drawn from a pool of pre-generated graphs held in
     pinned host memory, submitted at their arrival times to the library's request server
     (louvain_server_*). Latency is arrival to membership in host memory (queueing, packing, H2D
@@ -356,16 +479,18 @@ def run_serving_bench(args, dev):
     log(f"request pool: {len(host)} graphs, n {min(sizes)}..{max(sizes)}, mean arcs "
         f"{sum(arcs) / len(arcs):.0f}, generated in {time.perf_counter() - t0:.1f}s")
 
+    serve_seconds = args.serve_seconds if seconds is None else seconds
+
     def run_trace(rate, name, slots, batch_arcs):
         """One arrival trace (seeded per rate, the same for every server) through a server.
         Arrivals stop at serve_seconds; requests not done by twice that are counted
         unfinished (the server is then destroyed, which drops them)."""
         rng = np.random.default_rng(1000 + int(rate))
-        arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 2) + 16))
-        arr = arr[arr <= args.serve_seconds]
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * serve_seconds * 2) + 16))
+        arr = arr[arr <= serve_seconds]
         which = rng.integers(0, len(host), size=arr.size)
         srv = Server(0, slots=slots, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
-                     batch_arcs=batch_arcs, substeps=args.substeps)
+                     batch_arcs=batch_arcs, substeps=args.substeps, flags=lib_flags(args))
         # warm-up: every slot's buffers and workspace grown on the largest pool graph
         big = int(np.argmax(arcs))
         for t in [srv.submit(*host[big]) for _ in range(slots)]:
@@ -378,7 +503,7 @@ def run_serving_bench(args, dev):
             if lag > 0:
                 time.sleep(lag)
             tickets.append(srv.submit(*host[int(which[i])]))
-        deadline = start + int(args.serve_seconds * 2 * 1e9)
+        deadline = start + int(serve_seconds * 2 * 1e9)
         lat, done_at, batches = [], [], []
         for i, t in enumerate(tickets):
             left_ms = (deadline - srv.clock_ns()) // 1_000_000
@@ -415,9 +540,11 @@ def run_serving_bench(args, dev):
             f"{rec['mean_batch']:.2f}, peak running {rec['peak_running']}")
         return rec
 
-    servers = [("continuous", args.serve_slots, args.serve_batch_arcs)]
-    if not args.no_fifo:
-        servers += [("batch_at_a_time", 1, args.serve_single_batch_arcs), ("fifo", 1, 0)]
+    all_servers = [("continuous", args.serve_slots, args.serve_batch_arcs),
+                   ("batch_at_a_time", 1, args.serve_single_batch_arcs), ("fifo", 1, 0)]
+    if servers is None:
+        servers = ["continuous"] + ([] if args.no_fifo else ["batch_at_a_time", "fifo"])
+    servers = [x for x in all_servers if x[0] in servers]
     per = {name: [] for name, _, _ in servers}
     for rate in [float(x) for x in args.rates.split(",")]:
         for name, slots, ba in servers:
@@ -440,7 +567,7 @@ def run_serving_bench(args, dev):
             "workload": "serving",
             "pool_graphs": len(host),
             "pool_mean_arcs": sum(arcs) / len(arcs),
-            "serve_seconds": args.serve_seconds,
+            "serve_seconds": serve_seconds,
             "slots": args.serve_slots,
             "batch_arc_budget": args.serve_batch_arcs,
             "single_slot_batch_arc_budget": args.serve_single_batch_arcs,
@@ -452,7 +579,7 @@ def run_serving_bench(args, dev):
         },
         "roofline": None,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def run_sweep_bench(args, dev):
@@ -508,6 +635,56 @@ def run_sweep_bench(args, dev):
         "roofline": None,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_table_bench(args, dev):
+    """The per-config table of the baseline: for each --table-graphs workload, its size, W and
+    SHA-256; the synchronous oracle (O1, --substeps classes, all host threads) and the
+    sequential asynchronous oracle (O2, one core) timed on the host, each once after building
+    its input; and the GPU run (median of 5 after one warm-up): time, TEPS, Q."""
+    import statistics
+
+    import torch
+
+    import oracle as O
+    from graphgen import config_graph, csr_sha256
+    from paper_2301_12390_amd import Louvain
+
+    lv = Louvain(0)
+    rows = []
+    for name in args.table_graphs.split(","):
+        g = config_graph(name, device=dev)
+        torch.cuda.synchronize()
+        lv.run(g, substeps=args.substeps, flags=lib_flags(args))
+        ms = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r = lv.run(g, substeps=args.substeps, flags=lib_flags(args))
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1000.0)
+        gpu_ms = statistics.median(ms)
+        gc = g.to("cpu")
+        og = O.Graph.from_csr(gc)
+        t0 = time.perf_counter()
+        _, r1 = O.run(og, "sync", substeps=args.substeps)
+        o1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, r2 = O.run(og, "async")
+        o2 = time.perf_counter() - t0
+        row = {"graph": name, "n": g.n, "nnz": g.nnz, "W": r["W"], "csr_sha256": csr_sha256(gc),
+               "o1_s": o1, "o1_teps": g.nnz / o1, "o1_q": r1["q"],
+               "o1_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+               "o2_s": o2, "o2_teps": g.nnz / o2, "o2_q": r2["q"],
+               "gpu_ms": gpu_ms, "gpu_teps": g.nnz / (gpu_ms / 1000.0), "gpu_q": r["q"],
+               "gpu_equals_o1": r["qnum"] == r1["qnum"]}
+        rows.append(row)
+        log(f"{name}: {row}")
+        del g, gc, og
+        torch.cuda.empty_cache()
+    lv.close()
+    print(json.dumps({"metric": METRIC, "config": {"workload": "table", "rows": rows}}),
+          flush=True)
 
 
 def calibration_copy(args, dev):
@@ -765,6 +942,8 @@ def main():
                     help="sweep: decline exponents b (factor 10^b) at tolerance 1e-2")
     ap.add_argument("--sweep-async-arcs", type=int, default=20000000,
                     help="sweep: largest graph (arcs) given the asynchronous oracle's Q")
+    ap.add_argument("--table-graphs", default="sbm10k,rmat22",
+                    help="table: workloads of the per-config baseline table")
     ap.add_argument("--rates", default="50,200,800",
                     help="serving: request rates (per second), comma separated")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -799,6 +978,17 @@ def main():
                          "of the hash")
     ap.add_argument("--substeps", type=int, default=8,
                     help="vertex classes per local-moving iteration (1 = fully synchronous)")
+    ap.add_argument("--no-trace", action="store_true",
+                    help="time runs without LV_TRACE's per-kernel events (latency of small "
+                         "graphs; no roofline)")
+    ap.add_argument("--graph-replay", action="store_true",
+                    help="replay small phases' iterations as captured HIP graphs "
+                         "(LV_GRAPH_REPLAY) instead of launching every kernel directly")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload: skip the fully synchronous run, the batched "
+                         "workload and the serving traces that the line also reports")
+    ap.add_argument("--extra-serve-seconds", type=float, default=5.0,
+                    help="default workload: seconds of arrivals per rate of its serving traces")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-cache", default="",
@@ -813,6 +1003,11 @@ def main():
                     metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "OUT_MD"),
                     help="write the k_move_lds HBM-traffic summary of two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE; with --copy-calibration-mib) and exit")
+    ap.add_argument("--summarize-tiers-pmc", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "OUT_MD"),
+                    help="write the per-tier HBM-traffic summary of two rocprofv3 --pmc runs "
+                         "of bench.py --steps 1 --warmup 0 --no-extra (FETCH_SIZE, WRITE_SIZE; "
+                         "with --copy-calibration-mib) and exit")
     ap.add_argument("--command", default="", help="command text recorded in a summary")
     ap.add_argument("--summary-title", default="R-MAT scale 25 Louvain runs",
                     help="what a --summarize-stats summary covers")
@@ -821,6 +1016,10 @@ def main():
     args = ap.parse_args()
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats, args.command, args.summary_title)
+        return
+    if args.summarize_tiers_pmc:
+        summarize_tiers_pmc(*args.summarize_tiers_pmc, args.command, args.workload,
+                            args.copy_calibration_mib or 1024)
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.command, args.workload,
@@ -855,6 +1054,9 @@ def main():
     if args.workload == "prepare":
         run_prepare_bench(args, dev)
         return
+    if args.workload == "table":
+        run_table_bench(args, dev)
+        return
     t0 = time.perf_counter()
     if args.graph_cache and os.path.exists(args.graph_cache):
         g = load_graph(args.graph_cache, args.workload, dev)
@@ -879,7 +1081,9 @@ def main():
     calibration_copy(args, dev)
 
     lv = Louvain(0)
-    run_flags = LV_TRACE | (LV_COLOR_CLASSES if args.colour_classes else 0)
+    run_flags = ((0 if args.no_trace else LV_TRACE) |
+                 (LV_COLOR_CLASSES if args.colour_classes else 0) |
+                 lib_flags(args))
     for w in range(args.warmup):
         _, res = lv.run(g, substeps=args.substeps, flags=run_flags)
         log(f"warmup {w}: {res['total_ms']:.1f} ms, Q={res['q']:.6f}, passes={res['passes']}, "
@@ -896,31 +1100,30 @@ def main():
     teps = g.nnz / (ms_per_step / 1000.0)
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {teps / 1e9:.3f} GTEPS")
 
-    # roofline of k_move_lds (the fused LDS-table move kernel) over the timed region
-    o_bytes = 8 if g.offsets.dtype == torch.int64 else 4
-    f_ms = f_launch = f_bytes = 0.0
-    wg_ms = hub_ms = upd_ms = agg_ms = 0.0
-    wide = False
-    for r in results:
-        for t in r["trace"]:
-            f_ms += t["fused_ms"]
-            wg_ms += t["wg_ms"]
-            hub_ms += t["hub_ms"]
-            upd_ms += t["update_ms"]
-            f_launch += t["fused_launches"]
-            f_bytes += ((o_bytes + BYTES_PER_VERTEX_BASE) * t["fused_vertices"]
-                        + BYTES_PER_ARC * t["fused_arcs"]
-                        + BYTES_PER_CANDIDATE * t["fused_candidates"])
-            wide = wide or bool(t["wide"])
-        agg_ms += sum(r["aggregate_ms"])
-    avg_launch_ms = f_ms / max(f_launch, 1)
-    bytes_per_launch = f_bytes / max(f_launch, 1)
-    achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if f_ms > 0 else 0.0
-    traffic = load_traffic(args.workload)
+    if args.no_trace:
+        # latency runs: no per-kernel events, so no roofline
+        line = {"metric": METRIC, "value": teps, "unit": "TEPS", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "i64", "data": "synthetic",
+                "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz,
+                           "substeps": args.substeps, "graph_replay": args.graph_replay,
+                           "passes": results[0]["passes"],
+                           "iterations": results[0]["iterations"], "Q": results[0]["q"]},
+                "roofline": None}
+        lv.close()
+        print(json.dumps(line), flush=True)
+        return
+    tiers = tier_rooflines(results, g.offsets.dtype == torch.int64)
+    dom = max(tiers, key=lambda t: t["ms_total"])
+    for t in tiers:
+        t["traffic"] = load_tier_traffic(args.workload, t["tier"])
+    traffic = dom["traffic"]
     r0 = results[0]
     scanned = sum(t["fused_arcs"] + t["wg_arcs"] + t["hub_arcs"] for t in r0["trace"])
     move_ms = sum(t["fused_ms"] + t["wg_ms"] + t["hub_ms"] for t in r0["trace"])
     move_teps = scanned / max(move_ms / 1000.0, 1e-12)
+    wide = any(t["wide"] for r in results for t in r["trace"])
 
     line = {
         "metric": METRIC,
@@ -952,29 +1155,39 @@ def main():
             "Q": r0["q"],
         },
         "roofline": {
-            "kernel": "k_move_lds",
+            "kernel": dom["kernel"],
             "bound": "hbm",
-            "achieved": achieved,
+            "achieved": dom["achieved_gbps"],
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS,
+            "frac": dom["achieved_gbps"] / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "traffic_gbps": (traffic / (avg_launch_ms / 1000.0) / 1e9
-                             if traffic and avg_launch_ms > 0 else None),
-            "avg_launch_ms": avg_launch_ms,
-            "launches": int(f_launch),
-            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "traffic_gbps": (traffic / (dom["avg_launch_ms"] / 1000.0) / 1e9
+                             if traffic and dom["avg_launch_ms"] > 0 else None),
+            "avg_launch_ms": dom["avg_launch_ms"],
+            "launches": dom["launches"],
+            "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
         },
-        "breakdown_ms_per_step": {
-            "k_move_lds": f_ms / args.steps,
-            "k_move_wg": wg_ms / args.steps,
-            "hub_kernels": hub_ms / args.steps,
-            "update": upd_ms / args.steps,
-            "aggregate": agg_ms / args.steps,
-        },
+        "roofline_tiers": tiers,
+        "breakdown_ms_per_step": {t["tier"]: t["ms_total"] / args.steps for t in tiers},
         "move_teps": move_teps,
     }
     del memb
+    if not args.no_extra:
+        # the fully synchronous rule (one class per iteration) on the same graph, one run
+        lv.run(g, substeps=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, r1 = lv.run(g, substeps=1)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t1
+        line["sync_k1"] = {"ms": el1 * 1000.0, "teps": g.nnz / el1, "q": r1["q"],
+                           "passes": r1["passes"], "iterations": r1["iterations"],
+                           "qnum_pass": [str(x) for x in r1["qnum_pass"]],
+                           "cap_hits": r1["cap_hits"]}
+        log(f"fully synchronous (K = 1): {line['sync_k1']['ms']:.1f} ms, Q {r1['q']:.6f}, "
+            f"iterations {r1['iterations']}")
+    lv.close()
     if not args.no_cpu_baseline:
         log("cpu baseline: copying the graph to the host")
         gc = g.to("cpu")
@@ -983,8 +1196,91 @@ def main():
         line["cpu_baseline"] = cpu_baseline(gc, r0["trace"], args.cpu_seconds, args.substeps,
                                             gc.nnz)
         log(f"cpu baseline: {line['cpu_baseline']['value'] / 1e6:.2f} MTEPS")
-    lv.close()
+        del gc
+    else:
+        del g
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        # the other two parts of the metric: batched graphs/s against one graph at a time, and
+        # serving latency against a one-at-a-time FIFO server, on the same GPU
+        b = batched_measure(args, dev, 3, 1, False)
+        line["batched"] = {k: b["config"][k] for k in
+                           ("graphs", "nnz", "one_by_one_graphs_per_s", "speedup_vs_one_by_one",
+                            "identical_to_one_by_one", "mean_q")}
+        line["batched"]["graphs_per_s"] = b["value"]
+        line["batched"]["ms_per_batch"] = b["ms_per_step"]
+        torch.cuda.empty_cache()
+        sv = serving_measure(args, dev, seconds=args.extra_serve_seconds,
+                             servers=("continuous", "fifo"))["config"]
+        keep = ("rate", "completed_per_s", "p50_ms", "p99_ms", "offered", "completed",
+                "unfinished", "mean_batch")
+        line["serving"] = {
+            "seconds_of_arrivals": sv["serve_seconds"], "pool_graphs": sv["pool_graphs"],
+            "pool_mean_arcs": sv["pool_mean_arcs"],
+            "continuous": [{k: r[k] for k in keep} for r in sv["rates"]],
+            "one_at_a_time_fifo": [{k: r[k] for k in keep} for r in sv["fifo_rates"]],
+        }
     print(json.dumps(line), flush=True)
+
+
+# Algorithmic bytes of the move tiers (what the method must move, not cache lines): per decided
+# vertex its row bounds (o = 8 B for the input's int64 offsets, 16 B for the start and end
+# arrays of a super-vertex graph) and C[v] 4, K[v] 8, Sigma[own] 8, csize[own] 4,
+# csize[best] 4, decision 4 -> o + 32 B; per arc neighbour id 4, weight 4, C[neighbour] 4 ->
+# 12 B; per distinct candidate community Sigma[c] 8 B. Aggregation of a pass's graph: per arc
+# neighbour id 4, weight 4, super id of the neighbour 4 -> 12 B; per vertex C 4 and super id
+# 4 -> 8 B; per super-arc written id 4 and weight 4 -> 8 B.
+AGG_BYTES_PER_ARC = 12
+AGG_BYTES_PER_VERTEX = 8
+AGG_BYTES_PER_SUPER_ARC = 8
+
+
+def tier_rooflines(results, offsets_64):
+    """Per move tier (one launch = one class step's kernels of the tier) and for aggregation
+    (one launch = one pass's aggregation): algorithmic bytes per launch over the HIP-event time
+    of the launch on the stream it ran on, summed over the timed runs. The three move tiers of
+    a class step run concurrently on three streams, so each tier's time is stretched by the
+    others and the rates are lower bounds of what each tier achieves alone."""
+    acc = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0} for k in ("fused", "wg", "hub", "agg")}
+    for r in results:
+        for t in r["trace"]:
+            o = 8 if (t["pass"] == 0 and offsets_64) else (4 if t["pass"] == 0 else 16)
+            hub_cand = t["candidates"] - t["fused_candidates"] - t["wg_candidates"]
+            for key, v, a, c, ms, nl in (
+                    ("fused", t["fused_vertices"], t["fused_arcs"], t["fused_candidates"],
+                     t["fused_ms"], t["fused_launches"]),
+                    ("wg", t["wg_vertices"], t["wg_arcs"], t["wg_candidates"], t["wg_ms"],
+                     t["wg_launches"]),
+                    ("hub", t["hub_vertices"], t["hub_arcs"], hub_cand, t["hub_ms"],
+                     t["hub_launches"])):
+                if nl <= 0:
+                    continue
+                acc[key]["ms"] += ms
+                acc[key]["launches"] += nl
+                acc[key]["bytes"] += ((o + BYTES_PER_VERTEX_BASE) * v + BYTES_PER_ARC * a
+                                      + BYTES_PER_CANDIDATE * c)
+        for p in range(r["passes"] - 1):
+            if r["aggregate_ms"][p] <= 0:
+                continue
+            acc["agg"]["ms"] += r["aggregate_ms"][p]
+            acc["agg"]["launches"] += 1
+            acc["agg"]["bytes"] += (AGG_BYTES_PER_ARC * r["nnz_pass"][p]
+                                    + AGG_BYTES_PER_VERTEX * r["n_pass"][p]
+                                    + AGG_BYTES_PER_SUPER_ARC * r["nnz_pass"][p + 1])
+    names = {"fused": "k_move_lds", "wg": "k_move_grp7+k_move_wg",
+             "hub": "k_hub_part+k_hub_reduce+k_hub_decide",
+             "agg": "aggregation (k_merge_part, k_merge_lds, k_merge_reduce, ...)"}
+    out = []
+    for key, a in acc.items():
+        if a["launches"] == 0:
+            continue
+        avg = a["ms"] / a["launches"]
+        bpl = a["bytes"] / a["launches"]
+        gbps = bpl / (avg / 1000.0) / 1e9 if avg > 0 else 0.0
+        out.append({"tier": key, "kernel": names[key], "ms_total": a["ms"],
+                    "launches": a["launches"], "avg_launch_ms": avg, "bytes_per_launch": bpl,
+                    "achieved_gbps": gbps, "frac": gbps / HBM_PEAK_GBPS})
+    return out
 
 
 if __name__ == "__main__":
