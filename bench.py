@@ -664,14 +664,17 @@ def run_table_bench(args, dev):
             torch.cuda.synchronize()
             ms.append((time.perf_counter() - t0) * 1000.0)
         gpu_ms = statistics.median(ms)
+        log(f"{name}: GPU {gpu_ms:.2f} ms, Q {r['q']:.6f}; oracle runs next")
         gc = g.to("cpu")
         og = O.Graph.from_csr(gc)
         t0 = time.perf_counter()
         _, r1 = O.run(og, "sync", substeps=args.substeps)
         o1 = time.perf_counter() - t0
+        log(f"{name}: synchronous oracle {o1:.1f} s")
         t0 = time.perf_counter()
         _, r2 = O.run(og, "async")
         o2 = time.perf_counter() - t0
+        log(f"{name}: asynchronous oracle {o2:.1f} s")
         row = {"graph": name, "n": g.n, "nnz": g.nnz, "W": r["W"], "csr_sha256": csr_sha256(gc),
                "o1_s": o1, "o1_teps": g.nnz / o1, "o1_q": r1["q"],
                "o1_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
