@@ -704,12 +704,15 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   a.w32 = check32 && hm[2] < ((ull)1 << 32);
   HIPCHK(lv::fill_i64(a.dcount, 0, np + 1, s));
   CHK(wst(ctx, S_MPART, lv::merge_lds_blocks(b), &a.block_partial));
-  const int64_t nh = b.lstart[DEG] - b.lstart[7];  // communities of more than 1024 arcs
-  // The LDS merge (communities of up to 1024 arcs) and the two-phase merge (larger ones) write
-  // disjoint rows and counts and add to the self-arc sum atomically. When both have real work
-  // the LDS merge runs on a side stream, overlapping the other's planning and kernels.
+  // Communities of up to 1024 arcs: the LDS merge; classes 7 .. pf - 1: one workgroup each
+  // (merge_mid); longer ones: the two-phase merge.
+  const int pf = lv::merge_part_first_class(ctx->max_lds, a.w32);
+  const int64_t nh = b.lstart[DEG] - b.lstart[pf];
+  // The three write disjoint rows and counts and add to the self-arc sum atomically. When the
+  // two-phase merge and the others both have real work, the others run on a side stream,
+  // overlapping its planning and kernels.
   int64_t small_arcs = 0;
-  for (int j = 0; j < 7; j++) small_arcs += b.arcs[j];
+  for (int j = 0; j < pf; j++) small_arcs += b.arcs[j];
   const bool fork = nh > 0 && small_arcs >= ((int64_t)1 << 20);
   hipStream_t s_lds = fork ? ctx->side[0] : s;
   if (fork) {
@@ -717,19 +720,20 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
     HIPCHK(hipStreamWaitEvent(s_lds, ctx->fork[0], 0));
   }
   HIPCHK(lv::merge_lds(g, b, a, s_lds));
+  HIPCHK(lv::merge_mid(g, b, a, pf, s_lds));
   if (nh > 0) {
     lv::PartPlan pp;
     CHK(wst(ctx, S_HUBARR, lv::kPlanWords * (nh + 1), &a.hub_arrays));
     // pair values of the weight width the super-vertex graph gets (both bound by Sigma)
     const int vb = a.w32 ? 4 : 8;
-    HIPCHK(lv::plan_parts(nullptr, nullptr, a.A, a.list + b.lstart[7], nh, np, vb, true,
+    HIPCHK(lv::plan_parts(nullptr, nullptr, a.A, a.list + b.lstart[pf], nh, np, vb, true,
                           ctx->part_shift, a.hub_arrays, a.partial, ctx->pinned + PIN_HUB, pp, s));
     const int64_t pairs = pp.chunks * lv::part_chunk(vb);
     CHK(wst(ctx, S_PK, pairs, &a.pk));
     CHK(ws(ctx, S_PV, (size_t)pairs * vb, &a.pv));
     CHK(wst(ctx, S_HOFF, pp.hoff_entries, &a.hoff));
     CHK(wst(ctx, S_NFLUSH, pp.blocks, &a.nflush));
-    HIPCHK(lv::merge_hubs(g, b, pp, a, s));
+    HIPCHK(lv::merge_hubs(g, b, pp, a, pf, s));
   }
   if (fork) {
     HIPCHK(hipEventRecord(ctx->join0[0], s_lds));

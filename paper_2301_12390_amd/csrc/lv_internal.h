@@ -218,8 +218,13 @@ hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t*
                              const AggBuffers& a, hipStream_t s);
 hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& a, hipStream_t s);
 int64_t merge_lds_blocks(const Buckets& b);  // sizes block_partial
+// Communities of classes 7 .. part_first - 1 (one workgroup each, whole table in LDS); the
+// two-phase merge takes classes part_first and up (merge_part_first_class: 7, 8 or 9).
+int merge_part_first_class(size_t max_lds_per_block, bool w32);
+hipError_t merge_mid(const DevGraph& g, const Buckets& b, const AggBuffers& a, int part_first,
+                     hipStream_t s);
 hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const PartPlan& pp,
-                      const AggBuffers& a, hipStream_t s);
+                      const AggBuffers& a, int part_first, hipStream_t s);
 // rs[a], re[a] of the super-vertex graph's rows in okey/ow
 hipError_t super_rows(int64_t np, const AggBuffers& a, int64_t* rs, int64_t* re, hipStream_t s);
 hipError_t sum_i64(const int64_t* a, int64_t n, unsigned long long* out, hipStream_t s);

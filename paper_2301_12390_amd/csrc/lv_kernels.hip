@@ -2052,6 +2052,7 @@ struct MergeArgs {
   WOut ow;
   int64_t* dcount;   // distinct targets per new id
   ull* partial;      // per block: weight of its self super-arcs
+  ull* stats;        // [0] weight of self super-arcs (added to directly by the mid merge)
   const int32_t* list;
   int64_t bstart[8];
   int64_t lstart[8];
@@ -2232,6 +2233,164 @@ static hipError_t merge_lds_t(const DevGraph& g, const Buckets& b, const AggBuff
 
 hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& ag, hipStream_t s) {
   return g.w64 ? merge_lds_t<uint64_t>(g, b, ag, s) : merge_lds_t<uint32_t>(g, b, ag, s);
+}
+
+// Communities of bucket class 7 or 8 (1025 to 4096 arcs): one workgroup per community, listed
+// directly, with the whole community in one LDS table of twice its arc bound. Its members are
+// staged in LDS first (first flat arc as a 16-bit offset, and the displacement from flat arc
+// to row position), so locating the member of an arc is an LDS search: a workgroup's chain of
+// dependent global loads is the community's bounds, its member list, and per arc the arc
+// itself and its target's new id. Lanes take consecutive flat arcs, U of them per round.
+template <int K>
+struct MidShape {
+  static_assert(K == 7 || K == 8, "mid merge classes");
+  static constexpr int kLog2H = wg_log2h(K);  // 2^12 or 2^13 slots: twice the arc bound
+  static constexpr int kBlock = K == 7 ? 256 : 1024;
+  static constexpr int kMembers = 1 << (kLog2H - 1);  // members <= arcs <= H / 2
+};
+
+template <int K>
+__host__ __device__ constexpr size_t mid_lds_bytes(int vb) {
+  return (size_t)MidShape<K>::kMembers * (8 + 2) +
+         ((size_t)1 << MidShape<K>::kLog2H) * (4 + (size_t)vb);
+}
+
+template <typename WT, typename V, int K>
+__global__ __launch_bounds__(MidShape<K>::kBlock) void k_merge_mid(MergeArgs<WT> a,
+                                                                   int64_t lbase) {
+  constexpr int LOG2H = MidShape<K>::kLog2H;
+  constexpr int H = 1 << LOG2H;
+  constexpr int M = MidShape<K>::kMembers;
+  constexpr int B = MidShape<K>::kBlock;
+  constexpr int U = 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int cnt;
+  __shared__ ull red[B / 64];
+  int64_t* disp = (int64_t*)smem;            // [M] row position of flat arc t = disp[i] + t
+  int32_t* keys = (int32_t*)(disp + M);      // [H]
+  V* vals = (V*)(keys + H);                  // [H]
+  int16_t* mfirst = (int16_t*)(vals + H);    // [M] first flat arc of each member
+  const int32_t c = a.list[lbase + blockIdx.x];
+  const int64_t m0 = a.mstart[c];
+  const int mc = (int)(a.mstart[c + 1] - m0);
+  const int64_t a0 = a.astart[c];
+  const int L = (int)a.A[c];
+  const int32_t me = (int32_t)a.newid[c];
+  for (int s = threadIdx.x; s < H; s += B) {
+    keys[s] = kEmpty;
+    vals[s] = 0;
+  }
+  for (int i = threadIdx.x; i < mc; i += B) {
+    const int64_t first = a.gscan[m0 + i] - a0;
+    mfirst[i] = (int16_t)first;
+    disp[i] = a.rs[a.members[m0 + i]] - first;
+  }
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < L; t += U * B) {
+    int64_t e[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int tu = t + u * B;
+      e[u] = tu < L ? disp[member_at(mfirst, mc, tu)] + tu : -1;
+    }
+    int32_t j[U];
+    V wv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      j[u] = e[u] >= 0 ? a.idx[e[u]] : 0;
+      wv[u] = e[u] >= 0 ? (V)a.w[e[u]] : 0;
+    }
+    int32_t key[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) key[u] = e[u] >= 0 ? a.map[j[u]] : kEmpty;
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (key[u] != kEmpty) table_add<V>(keys, vals, LOG2H, key[u], wv[u]);
+  }
+  __syncthreads();
+  ull self = 0;
+  for (int s = threadIdx.x; s < H; s += B) {
+    const int32_t key = keys[s];
+    if (key == kEmpty) continue;
+    const int p = atomicAdd(&cnt, 1);
+    a.okey[a0 + p] = key;
+    a.ow.put(a0 + p, (ull)vals[s]);
+    if (key == me) {
+      self = (ull)vals[s];
+      if (a.gself) atomicAdd(&a.gself[a.gid[c]], self);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) a.dcount[me] = cnt;
+  self = group_sum_u64<64>(self);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = self;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ull t = 0;
+    for (int i = 0; i < B / 64; i++) t += red[i];
+    if (t) atomicAdd(&a.stats[0], t);
+  }
+}
+
+int merge_part_first_class(size_t max_lds, bool w32) {
+  const int vb = w32 ? 4 : 8;
+  if (mid_lds_bytes<7>(vb) + 2048 > max_lds) return 7;
+  if (mid_lds_bytes<8>(vb) + 2048 > max_lds) return 8;
+  return 9;
+}
+
+template <typename WT, typename V, int K>
+static hipError_t launch_mid(const MergeArgs<WT>& a, const Buckets& b, hipStream_t s) {
+  const int64_t rows = b.count[K];
+  if (rows <= 0) return hipSuccess;
+  constexpr size_t shm = mid_lds_bytes<K>((int)sizeof(V));
+  static const bool attr = [] {  // once, thread-safe (see launch_wg)
+    (void)hipFuncSetAttribute((const void*)k_merge_mid<WT, V, K>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    return true;
+  }();
+  (void)attr;
+  LV_LAUNCH((k_merge_mid<WT, V, K>), (unsigned)rows, MidShape<K>::kBlock, shm, s, a,
+            b.lstart[K]);
+  return hipGetLastError();
+}
+
+template <typename WT, typename V>
+static hipError_t merge_mid_t(const DevGraph& g, const Buckets& b, const AggBuffers& ag,
+                              int part_first, hipStream_t s) {
+  MergeArgs<WT> a;
+  a.rs = g.rs;
+  a.idx = g.idx;
+  a.w = (const WT*)g.w;
+  a.map = ag.map;
+  a.members = ag.members;
+  a.mstart = ag.mstart;
+  a.gscan = ag.gscan;
+  a.astart = ag.astart;
+  a.A = ag.A;
+  a.newid = ag.newid;
+  a.okey = ag.okey;
+  a.ow.w64 = ag.ow;
+  a.ow.w32 = ag.w32 ? (uint32_t*)ag.ow : nullptr;
+  a.dcount = ag.dcount;
+  a.stats = ag.stats;
+  a.list = ag.list;
+  a.gid = ag.gs.gid;
+  a.gself = ag.gs.gself;
+  hipError_t e = hipSuccess;
+  if (part_first > 7 && (e = launch_mid<WT, V, 7>(a, b, s)) != hipSuccess) return e;
+  if (part_first > 8 && (e = launch_mid<WT, V, 8>(a, b, s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t merge_mid(const DevGraph& g, const Buckets& b, const AggBuffers& ag, int part_first,
+                     hipStream_t s) {
+  if (ag.w32)
+    return g.w64 ? merge_mid_t<uint64_t, uint32_t>(g, b, ag, part_first, s)
+                 : merge_mid_t<uint32_t, uint32_t>(g, b, ag, part_first, s);
+  return g.w64 ? merge_mid_t<uint64_t, ull>(g, b, ag, part_first, s)
+               : merge_mid_t<uint32_t, ull>(g, b, ag, part_first, s);
 }
 
 // Communities of more than 1024 arcs: the two-phase path over their flat arc ranges. Values are
@@ -2494,7 +2653,7 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT, V>
 
 template <typename WT, typename V>
 static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPlan& pp,
-                               const AggBuffers& ag, hipStream_t s) {
+                               const AggBuffers& ag, int part_first, hipStream_t s) {
   constexpr int vb = (int)sizeof(V);
   MergeHubArgs<WT, V> a;
   a.rs = g.rs;
@@ -2512,7 +2671,7 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPl
   a.ow.w32 = ag.w32 ? (uint32_t*)ag.ow : nullptr;
   a.dcount = ag.dcount;
   a.stats = ag.stats;
-  a.hubs = ag.list + b.lstart[kFusedClasses];
+  a.hubs = ag.list + b.lstart[part_first];
   a.nh = pp.nh;
   a.chunk_start = pp.chunk_start;
   a.block_start = pp.block_start;
@@ -2541,13 +2700,13 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPl
 }
 
 hipError_t merge_hubs(const DevGraph& g, const Buckets& b, const PartPlan& pp,
-                      const AggBuffers& ag, hipStream_t s) {
+                      const AggBuffers& ag, int part_first, hipStream_t s) {
   if (pp.nh <= 0) return hipSuccess;
   if (ag.w32)
-    return g.w64 ? merge_hubs_t<uint64_t, uint32_t>(g, b, pp, ag, s)
-                 : merge_hubs_t<uint32_t, uint32_t>(g, b, pp, ag, s);
-  return g.w64 ? merge_hubs_t<uint64_t, ull>(g, b, pp, ag, s)
-               : merge_hubs_t<uint32_t, ull>(g, b, pp, ag, s);
+    return g.w64 ? merge_hubs_t<uint64_t, uint32_t>(g, b, pp, ag, part_first, s)
+                 : merge_hubs_t<uint32_t, uint32_t>(g, b, pp, ag, part_first, s);
+  return g.w64 ? merge_hubs_t<uint64_t, ull>(g, b, pp, ag, part_first, s)
+               : merge_hubs_t<uint32_t, ull>(g, b, pp, ag, part_first, s);
 }
 
 // Rows of the super-vertex graph where the merge left them.

@@ -211,6 +211,41 @@ def test_aggregate(lv, g, offsets_64):
         assert np.array_equal(w_c, g2.w)
 
 
+@pytest.mark.parametrize("offsets_64", [True, False])
+def test_aggregate_community_classes(lv, offsets_64):
+    # communities of about 60 to 20,000 arcs, scattered over the vertex ids, so that every
+    # aggregation tier gets some: up to 1024 arcs, 1025-2048, 2049-4096 (one workgroup each),
+    # 4097-8192 and longer (two-phase)
+    g = erdos_renyi(4000, 0.005, seed=11, weights=(1, 9))
+    if offsets_64:
+        g = g.with_offsets(torch.int64)
+    sizes = [3, 30, 60, 120, 250, 500, 1000]
+    blocks, v, k = [], 0, 0
+    while v < g.n:
+        s = min(sizes[k % len(sizes)], g.n - v)
+        blocks.append(np.full(s, k, dtype=np.int32))
+        v += s
+        k += 1
+    rng = np.random.default_rng(17)
+    labels = rng.permutation(g.n)[:k].astype(np.int32)
+    C = labels[np.concatenate(blocks)][rng.permutation(g.n)]
+    deg = np.diff(g.offsets.numpy())
+    arcs = np.bincount(C, weights=deg, minlength=g.n)
+    for lo, hi in [(1024, 2048), (2048, 4096), (4096, 8192), (8192, 1 << 40)]:
+        assert ((arcs > lo) & (arcs <= hi)).any(), (lo, hi)
+    og = O.Graph.from_csr(g)
+    mp, (n2, off, idx, w) = lv.aggregate(g.to("cuda:0"), torch.from_numpy(C).to("cuda:0"),
+                                         offsets_64=offsets_64)
+    mo, g2 = O.aggregate(og, C)
+    assert np.array_equal(mp.cpu().numpy(), mo)
+    assert n2 == g2.n
+    off_c, idx_c, w_c = canonical_rows_fast(n2, off.cpu().numpy(), idx.cpu().numpy(),
+                                            w.cpu().numpy())
+    assert np.array_equal(off_c, g2.off)
+    assert np.array_equal(idx_c, g2.idx)
+    assert np.array_equal(w_c, g2.w)
+
+
 def check_run(lv, g, flags=0, substeps=8, **kw):
     og = O.Graph.from_csr(g)
     okw = {{"tolerance_exp10": "a", "decline_exp10": "b"}.get(k, k): v for k, v in kw.items()}
