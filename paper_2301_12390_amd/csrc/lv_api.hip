@@ -29,7 +29,7 @@ enum SlotId {
   S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
-  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_COUNT_SLOTS
+  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_CFM, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -428,15 +428,17 @@ lv_status issue_iteration(lv_ctx* ctx, Phase& ph, bool trace, hipStream_t s, Bat
       HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
       HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
     }
-    if (trace) HIPCHK(hipEventRecord(ev[0], s));
-    HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
-    if (trace) HIPCHK(hipEventRecord(ev[1], s));
-    if (trace) HIPCHK(hipEventRecord(ev[2], s1));
-    HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
-    if (trace) HIPCHK(hipEventRecord(ev[3], s1));
+    // the hub tier first: it is the longest, and its workgroups each need most of a CU's LDS,
+    // which they only find before the many small workgroups of the other tiers fill the CUs
     if (trace) HIPCHK(hipEventRecord(ev[4], s2));
     HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s2));
     if (trace) HIPCHK(hipEventRecord(ev[5], s2));
+    if (trace) HIPCHK(hipEventRecord(ev[2], s1));
+    HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
+    if (trace) HIPCHK(hipEventRecord(ev[3], s1));
+    if (trace) HIPCHK(hipEventRecord(ev[0], s));
+    HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
+    if (trace) HIPCHK(hipEventRecord(ev[1], s));
     if (par) {
       HIPCHK(hipEventRecord(ctx->join0[k], s1));
       HIPCHK(hipEventRecord(ctx->join1[k], s2));
@@ -733,6 +735,7 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
     CHK(ws(ctx, S_PV, (size_t)pairs * vb, &a.pv));
     CHK(wst(ctx, S_HOFF, pp.hoff_entries, &a.hoff));
     CHK(wst(ctx, S_NFLUSH, pp.blocks, &a.nflush));
+    CHK(wst(ctx, S_CFM, pp.chunks, &a.cfm));
     HIPCHK(lv::merge_hubs(g, b, pp, a, pf, s));
   }
   if (fork) {

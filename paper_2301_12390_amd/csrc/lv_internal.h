@@ -210,6 +210,7 @@ struct AggBuffers {
   void* pv = nullptr;                    // their values: uint32 when w32, else uint64
   int32_t* hoff = nullptr;               // their segment bounds
   int32_t* nflush = nullptr;             // table flushes of every phase-1 workgroup
+  int32_t* cfm = nullptr;                // first member of every chunk row
   GraphSet gs;                           // batches: gid (of labels) and gself are used
 };
 // Renumbering, member lists and flat arc ranges (everything before the merge).
@@ -219,7 +220,7 @@ hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t*
 hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& a, hipStream_t s);
 int64_t merge_lds_blocks(const Buckets& b);  // sizes block_partial
 // Communities of classes 7 .. part_first - 1 (one workgroup each, whole table in LDS); the
-// two-phase merge takes classes part_first and up (merge_part_first_class: 7, 8 or 9).
+// two-phase merge takes classes part_first and up (merge_part_first_class: 7 to 10).
 int merge_part_first_class(size_t max_lds_per_block, bool w32);
 hipError_t merge_mid(const DevGraph& g, const Buckets& b, const AggBuffers& a, int part_first,
                      hipStream_t s);

@@ -2235,23 +2235,27 @@ hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& ag, 
   return g.w64 ? merge_lds_t<uint64_t>(g, b, ag, s) : merge_lds_t<uint32_t>(g, b, ag, s);
 }
 
-// Communities of bucket class 7 or 8 (1025 to 4096 arcs): one workgroup per community, listed
-// directly, with the whole community in one LDS table of twice its arc bound. Its members are
-// staged in LDS first (first flat arc as a 16-bit offset, and the displacement from flat arc
-// to row position), so locating the member of an arc is an LDS search: a workgroup's chain of
-// dependent global loads is the community's bounds, its member list, and per arc the arc
-// itself and its target's new id. Lanes take consecutive flat arcs, U of them per round.
+// Communities of bucket classes 7 to 9 (1025 to 8192 arcs): one workgroup per community,
+// listed directly, with the whole community in one LDS table of twice its arc bound. Its
+// members' first flat arcs are staged in LDS (16-bit offsets), so locating the member of an arc
+// is an LDS search; class 7 also stages each member's displacement from flat arc to row
+// position, while classes 8 and 9 ("lean", to fit two or one workgroups per CU) read the
+// member's vertex and row start per arc from global memory (cached: a wave's lanes mostly share
+// one member). A workgroup's chain of dependent global loads is the community's bounds, its
+// member list, and per arc the arc itself and its target's new id. Lanes take consecutive flat
+// arcs, U of them per round.
 template <int K>
 struct MidShape {
-  static_assert(K == 7 || K == 8, "mid merge classes");
-  static constexpr int kLog2H = wg_log2h(K);  // 2^12 or 2^13 slots: twice the arc bound
+  static_assert(K >= 7 && K <= 9, "mid merge classes");
+  static constexpr int kLog2H = K == 7 ? 12 : K == 8 ? 13 : 14;  // twice the arc bound
   static constexpr int kBlock = K == 7 ? 256 : 1024;
+  static constexpr bool kLean = K >= 8;
   static constexpr int kMembers = 1 << (kLog2H - 1);  // members <= arcs <= H / 2
 };
 
 template <int K>
 __host__ __device__ constexpr size_t mid_lds_bytes(int vb) {
-  return (size_t)MidShape<K>::kMembers * (8 + 2) +
+  return (size_t)MidShape<K>::kMembers * ((MidShape<K>::kLean ? 0 : 8) + 2) +
          ((size_t)1 << MidShape<K>::kLog2H) * (4 + (size_t)vb);
 }
 
@@ -2262,14 +2266,15 @@ __global__ __launch_bounds__(MidShape<K>::kBlock) void k_merge_mid(MergeArgs<WT>
   constexpr int H = 1 << LOG2H;
   constexpr int M = MidShape<K>::kMembers;
   constexpr int B = MidShape<K>::kBlock;
+  constexpr bool LEAN = MidShape<K>::kLean;
   constexpr int U = 4;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int cnt;
   __shared__ ull red[B / 64];
-  int64_t* disp = (int64_t*)smem;            // [M] row position of flat arc t = disp[i] + t
-  int32_t* keys = (int32_t*)(disp + M);      // [H]
-  V* vals = (V*)(keys + H);                  // [H]
-  int16_t* mfirst = (int16_t*)(vals + H);    // [M] first flat arc of each member
+  int64_t* disp = (int64_t*)smem;                      // [M] (not lean) flat arc t of member
+  int32_t* keys = (int32_t*)(disp + (LEAN ? 0 : M));   // [H]  i sits at row position disp[i] + t
+  V* vals = (V*)(keys + H);                            // [H]
+  int16_t* mfirst = (int16_t*)(vals + H);              // [M] first flat arc of each member
   const int32_t c = a.list[lbase + blockIdx.x];
   const int64_t m0 = a.mstart[c];
   const int mc = (int)(a.mstart[c + 1] - m0);
@@ -2283,7 +2288,7 @@ __global__ __launch_bounds__(MidShape<K>::kBlock) void k_merge_mid(MergeArgs<WT>
   for (int i = threadIdx.x; i < mc; i += B) {
     const int64_t first = a.gscan[m0 + i] - a0;
     mfirst[i] = (int16_t)first;
-    disp[i] = a.rs[a.members[m0 + i]] - first;
+    if (!LEAN) disp[i] = a.rs[a.members[m0 + i]] - first;
   }
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -2292,7 +2297,11 @@ __global__ __launch_bounds__(MidShape<K>::kBlock) void k_merge_mid(MergeArgs<WT>
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int tu = t + u * B;
-      e[u] = tu < L ? disp[member_at(mfirst, mc, tu)] + tu : -1;
+      e[u] = -1;
+      if (tu < L) {
+        const int i = member_at(mfirst, mc, tu);
+        e[u] = LEAN ? a.rs[a.members[m0 + i]] + (tu - mfirst[i]) : disp[i] + tu;
+      }
     }
     int32_t j[U];
     V wv[U];
@@ -2337,7 +2346,8 @@ int merge_part_first_class(size_t max_lds, bool w32) {
   const int vb = w32 ? 4 : 8;
   if (mid_lds_bytes<7>(vb) + 2048 > max_lds) return 7;
   if (mid_lds_bytes<8>(vb) + 2048 > max_lds) return 8;
-  return 9;
+  if (mid_lds_bytes<9>(vb) + 2048 > max_lds) return 9;
+  return 10;
 }
 
 template <typename WT, typename V, int K>
@@ -2381,6 +2391,7 @@ static hipError_t merge_mid_t(const DevGraph& g, const Buckets& b, const AggBuff
   hipError_t e = hipSuccess;
   if (part_first > 7 && (e = launch_mid<WT, V, 7>(a, b, s)) != hipSuccess) return e;
   if (part_first > 8 && (e = launch_mid<WT, V, 8>(a, b, s)) != hipSuccess) return e;
+  if (part_first > 9 && (e = launch_mid<WT, V, 9>(a, b, s)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -2426,6 +2437,7 @@ struct MergeHubArgs {
   V* pv;
   int32_t* hoff;
   int32_t* nflush;
+  int32_t* cfm;      // per chunk row: its first member (index among its community's members)
   int cap;
   const int32_t* gid;  // batches: graph of every label, and per-graph self super-arc weights
   ull* gself;
@@ -2491,66 +2503,90 @@ __device__ __forceinline__ ull part_block_sum(ull x, ull* red) {
   return t;
 }
 
-// Chunk k of community c's flat arc range: each thread a run of kMergePerThread consecutive flat
-// arcs (one member search, then a forward walk), keyed by the target's new id. The members
-// covering the chunk are located once per chunk, so each thread searches only among them.
+// Chunk k of community c's flat arc range. The members covering the chunk (from the chunk's
+// first member, found beforehand by k_chunk_members) have their first flat arcs staged in LDS
+// as 16-bit offsets from the chunk start (the first member's clamped to 0; its true first arc
+// kept apart), in the aux region that table flushes use between chunks. Lanes then take
+// consecutive flat arcs, U per round: the member of an arc is an LDS search, its row start a
+// load shared by the lanes of that member, and the arc loads of a wave are contiguous within a
+// row.
 template <typename WT, typename V>
 struct MergeChunk {
   static constexpr int kMergeChunk = MergeShape<V>::kChunk;
   static constexpr int kMergeLog2H = MergeShape<V>::kLog2H;
-  static constexpr int kMergePerThread = MergeShape<V>::kPerThread;
   const MergeHubArgs<WT, V>* a;
-  int64_t m0, a0, L;
+  int64_t m0, a0, L, row0;
   int mc;
+  int16_t* mf;  // aux LDS, kMergeChunk + 1 entries
+  static_assert(kAuxInts * 4 >= (kMergeChunk + 1) * 2, "chunk members fit the aux LDS");
+  static_assert(kMergeChunk < 32768, "16-bit offsets within a chunk");
   __device__ void operator()(int64_t k, int32_t* keys, V* vals, int* flags) {
+    constexpr int U = 4;
     __shared__ int span[2];
+    __shared__ int64_t f0;
     const int64_t c0 = k * kMergeChunk;
-    const int64_t c1 = c0 + kMergeChunk < L ? c0 + kMergeChunk : L;
-    if (threadIdx.x < 2)
-      span[threadIdx.x] = member_at(a->gscan + m0, mc, a0 + (threadIdx.x == 0 ? c0 : c1 - 1));
+    const int n = (int)(c0 + kMergeChunk < L ? kMergeChunk : L - c0);
+    if (threadIdx.x == 0) {
+      const int i0 = a->cfm[row0 + k];
+      span[0] = i0;
+      // members up to the one holding the next chunk's first arc (or the last member)
+      span[1] = c0 + kMergeChunk < L ? a->cfm[row0 + k + 1] : mc - 1;
+      f0 = a->gscan[m0 + i0] - a0;
+    }
     __syncthreads();
-    const int64_t t0 = c0 + (int64_t)threadIdx.x * kMergePerThread;
-    const int64_t t1 = t0 + kMergePerThread < c1 ? t0 + kMergePerThread : c1;
+    const int s0 = span[0];
+    const int nm = span[1] - s0 + 1;
+    for (int i = threadIdx.x; i < nm; i += kPartBlock) {
+      const int64_t f = a->gscan[m0 + s0 + i] - a0 - c0;
+      mf[i] = (int16_t)(f > 0 ? f : 0);
+    }
+    __syncthreads();
+    const int64_t first0 = f0;
     int fresh = 0;
-    if (t0 < t1) {
-      // member holding flat arc t0 (first flat arcs are a0 + gscan offsets)
-      int i = member_in(a->gscan + m0, span[0], span[1] + 1, a0 + t0);
-      int64_t next = i + 1 < mc ? a->gscan[m0 + i + 1] - a0 : L;
-      int64_t first = a->gscan[m0 + i] - a0;
-      int32_t v = a->members[m0 + i];
-      // positions of this thread's arcs, then their loads and gathers together
-      int64_t e[kMergePerThread];
+    for (int t = threadIdx.x; t < n; t += U * kPartBlock) {
+      int64_t e[U];
 #pragma unroll
-      for (int u = 0; u < kMergePerThread; u++) {
-        const int64_t t = t0 + u;
+      for (int u = 0; u < U; u++) {
+        const int tu = t + u * kPartBlock;
         e[u] = -1;
-        if (t < t1) {
-          while (t >= next) {
-            i++;
-            first = next;
-            next = i + 1 < mc ? a->gscan[m0 + i + 1] - a0 : L;
-            v = a->members[m0 + i];
-          }
-          e[u] = a->rs[v] + (t - first);
+        if (tu < n) {
+          const int i = member_at(mf, nm, tu);
+          const int64_t f = i == 0 ? first0 : c0 + mf[i];
+          e[u] = a->rs[a->members[m0 + s0 + i]] + (c0 + tu - f);
         }
       }
-      int32_t j[kMergePerThread];
-      V wv[kMergePerThread];
+      int32_t j[U];
+      V wv[U];
 #pragma unroll
-      for (int u = 0; u < kMergePerThread; u++) {
+      for (int u = 0; u < U; u++) {
         j[u] = e[u] >= 0 ? a->idx[e[u]] : 0;
         wv[u] = e[u] >= 0 ? (V)a->w[e[u]] : 0;
       }
-      int32_t key[kMergePerThread];
+      int32_t key[U];
 #pragma unroll
-      for (int u = 0; u < kMergePerThread; u++) key[u] = e[u] >= 0 ? a->map[j[u]] : kEmpty;
+      for (int u = 0; u < U; u++) key[u] = e[u] >= 0 ? a->map[j[u]] : kEmpty;
 #pragma unroll
-      for (int u = 0; u < kMergePerThread; u++)
+      for (int u = 0; u < U; u++)
         if (key[u] != kEmpty) fresh += table_add<V>(keys, vals, kMergeLog2H, key[u], wv[u]);
     }
     if (fresh) atomicAdd(&flags[0], fresh);
   }
 };
+
+// First member of every chunk row of the two-phase merge (one thread per row).
+template <typename WT, typename V>
+__global__ void k_chunk_members(MergeHubArgs<WT, V> a, int64_t rows) {
+  constexpr int Q = MergeShape<V>::kChunk;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t h = find_segment(a.chunk_start, a.nh, r);
+    const int32_t c = a.hubs[h];
+    const int64_t m0 = a.mstart[c];
+    const int mc = (int)(a.mstart[c + 1] - m0);
+    const int64_t t = a.astart[c] + (r - a.chunk_start[h]) * Q;
+    a.cfm[r] = member_at(a.gscan + m0, mc, t);
+  }
+}
 
 template <typename WT, typename V>
 __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT, V> a) {
@@ -2578,6 +2614,8 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_part(MergeHubArgs<WT, V> a
   acc.mc = (int)(a.mstart[c + 1] - acc.m0);
   acc.a0 = a.astart[c];
   acc.L = a.A[c];
+  acc.row0 = row0;
+  acc.mf = (int16_t*)cnt;
   if (nck == 1) {
     // the whole community in one table: write its row directly
     part_table_clear<V>(keys, vals, H);
@@ -2685,6 +2723,7 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPl
   a.nflush = ag.nflush;
   a.gid = ag.gs.gid;
   a.gself = ag.gs.gself;
+  a.cfm = ag.cfm;
   a.cap = part_round_cap(MergeShape<V>::kLog2H, pp.shift);
   static const bool attr = [] {  // once, thread-safe (see launch_wg)
     allow_part_lds(k_merge_part<WT, V>, vb);
@@ -2693,6 +2732,7 @@ static hipError_t merge_hubs_t(const DevGraph& g, const Buckets& b, const PartPl
   }();
   (void)attr;
   const size_t shm = part_lds_bytes(vb);
+  LV_LAUNCH((k_chunk_members<WT, V>), grid_for(pp.chunks), kBlock, 0, s, a, pp.chunks);
   LV_LAUNCH((k_merge_part<WT, V>), (unsigned)pp.blocks, kPartBlock, shm, s, a);
   if (pp.parts > 0)
     LV_LAUNCH((k_merge_reduce<WT, V>), (unsigned)pp.parts, kPartBlock, shm, s, a);
