@@ -428,17 +428,15 @@ lv_status issue_iteration(lv_ctx* ctx, Phase& ph, bool trace, hipStream_t s, Bat
       HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
       HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
     }
-    // the hub tier first: it is the longest, and its workgroups each need most of a CU's LDS,
-    // which they only find before the many small workgroups of the other tiers fill the CUs
-    if (trace) HIPCHK(hipEventRecord(ev[4], s2));
-    HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s2));
-    if (trace) HIPCHK(hipEventRecord(ev[5], s2));
-    if (trace) HIPCHK(hipEventRecord(ev[2], s1));
-    HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
-    if (trace) HIPCHK(hipEventRecord(ev[3], s1));
     if (trace) HIPCHK(hipEventRecord(ev[0], s));
     HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
     if (trace) HIPCHK(hipEventRecord(ev[1], s));
+    if (trace) HIPCHK(hipEventRecord(ev[2], s1));
+    HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
+    if (trace) HIPCHK(hipEventRecord(ev[3], s1));
+    if (trace) HIPCHK(hipEventRecord(ev[4], s2));
+    HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s2));
+    if (trace) HIPCHK(hipEventRecord(ev[5], s2));
     if (par) {
       HIPCHK(hipEventRecord(ctx->join0[k], s1));
       HIPCHK(hipEventRecord(ctx->join1[k], s2));

@@ -352,6 +352,27 @@ hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* pa
 }
 
 // =============================================================================================
+// Largest member index i in [0, mc) with start[i] <= t (start[0] = 0 <= t).
+template <typename T>
+__device__ __forceinline__ int member_at(const T* start, int mc, int64_t t) {
+  int lo = 0, hi = mc;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)start[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Largest member index i in [lo, hi) with start[i] <= t, given start[lo] <= t.
+template <typename T>
+__device__ __forceinline__ int member_in(const T* start, int lo, int hi, int64_t t) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)start[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Arc-segment kernels: thread t covers arcs [t*kSeg, (t+1)*kSeg), finds the row of its first
 // arc by binary search over the offsets and walks forward. Work is balanced by arcs, so hub
 // rows do not serialise on one thread.
@@ -359,11 +380,16 @@ hipError_t scan_flags_pos(const int32_t* x, int64_t n, int64_t* out, int64_t* pa
 constexpr int64_t kSeg = 16;
 
 // Row sums: workgroup b sums the arcs of its range [lo, hi) of kRowTile arcs, attributing them
-// to the rows they belong to: up to kShortRow arcs of a row one per thread, longer stretches one
-// per wavefront (coalesced). A row lying wholly inside the range is stored; the (at most two)
-// rows crossing its ends are added atomically. K must be zero (rows of no arcs keep 0).
+// to the rows they belong to. When the range spans at most kRowSpanLds rows (empty ones
+// included), their offsets are staged in LDS and the lanes read consecutive arcs: each lane
+// finds its arc's row by an LDS search, a segmented scan over the wave sums each row's run of
+// lanes, and the last lane of a run adds it to the row's LDS total. Otherwise, up to kShortRow
+// arcs of a row one per thread, longer stretches one per wavefront. A row lying wholly inside
+// the range is stored; the (at most two) rows crossing its ends are added atomically. K must
+// be zero (rows of no arcs keep 0).
 constexpr int64_t kRowTile = 4096;
 constexpr int64_t kShortRow = 32;
+constexpr int kRowSpanLds = 1024;
 
 // tile_rows[t] = the row holding arc t * kRowTile, for every tile t (each arc lies in exactly
 // one non-empty row, so every tile gets one writer); tile_rows[tiles] = n - 1.
@@ -390,11 +416,65 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t
   __shared__ int64_t span[2];
   __shared__ int64_t longs[kRowTile / kShortRow + 2];
   __shared__ int nlong;
+  __shared__ int64_t roff[kRowSpanLds + 1];
+  __shared__ ull racc[kRowSpanLds];
+  __shared__ ull rself[SELF ? kRowSpanLds : 1];
   const int64_t lo = (int64_t)blockIdx.x * kRowTile;
   const int64_t hi = lo + kRowTile < nnz ? lo + kRowTile : nnz;
   if (threadIdx.x < 2) span[threadIdx.x] = tile_rows[blockIdx.x + threadIdx.x];
   if (threadIdx.x == 0) nlong = 0;
   __syncthreads();
+  const int64_t r0 = span[0];
+  const int nr = (int)(span[1] - r0 + 1 < kRowSpanLds + 1 ? span[1] - r0 + 1 : kRowSpanLds + 1);
+  if (nr <= kRowSpanLds) {
+    for (int i = threadIdx.x; i <= nr; i += kBlock) roff[i] = off[r0 + i];
+    for (int i = threadIdx.x; i < nr; i += kBlock) {
+      racc[i] = 0;
+      if (SELF) rself[i] = 0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = lo; base < hi; base += kBlock) {  // block-uniform trip count
+      const int64_t e = base + threadIdx.x;
+      int r = -1;
+      ull x = 0, sl = 0;
+      if (e < hi) {
+        r = member_at(roff, nr, e);
+        x = (ull)ld_stream(w + e);
+        if (SELF && ld_stream(idx + e) == (int32_t)(r0 + r)) sl = x;
+      }
+      // rows are non-decreasing along the lanes: a segmented inclusive scan by row
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const ull y = __shfl_up(x, d, 64);
+        const ull ys = SELF ? __shfl_up(sl, d, 64) : 0ull;
+        const int ry = __shfl_up(r, d, 64);
+        if (lane >= d && ry == r) {
+          x += y;
+          if (SELF) sl += ys;
+        }
+      }
+      const int rn = __shfl_down(r, 1, 64);
+      if (r >= 0 && (lane == 63 || rn != r)) {
+        atomicAdd(&racc[r], x);
+        if (SELF && sl) atomicAdd(&rself[r], sl);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr; i += kBlock) {
+      const int64_t b0 = roff[i], b1 = roff[i + 1];
+      if (b1 <= b0) continue;
+      const int64_t r = r0 + i;
+      if (b0 >= lo && b1 <= hi) {
+        K[r] = racc[i];
+        if (SELF) selfw[r] = rself[i];
+      } else {
+        atomicAdd((ull*)&K[r], racc[i]);
+        if (SELF && rself[i]) atomicAdd((ull*)&selfw[r], rself[i]);
+      }
+    }
+    return;
+  }
   for (int64_t r = span[0] + threadIdx.x; r <= span[1]; r += kBlock) {
     const int64_t b0 = off[r], b1 = off[r + 1];
     const int64_t e0 = b0 > lo ? b0 : lo, e1 = b1 < hi ? b1 : hi;
@@ -1896,22 +1976,57 @@ hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const PartPla
                : move_hubs_t<false, uint32_t>(g, b, cls, pp, m, s);
 }
 
+// Adds (dk, dsz) to the Sigma and size of community x for every lane with x >= 0. Lanes of a
+// wave that name the same community are combined first, a few groups per wave (the leader of
+// each group makes one atomic of the group's sum), since the movers of a step often join the
+// same few large communities; the remaining lanes add their own. Called by whole waves.
+__device__ __forceinline__ void add_grouped(VRec* rec, int32_t x, ull dk, int dsz) {
+  bool pending = x >= 0;
+  const int lane = threadIdx.x & 63;
+#pragma unroll 1
+  for (int round = 0; round < 4; round++) {
+    const uint64_t live = __ballot(pending);
+    if (!live) return;
+    const int leader = __ffsll((long long)live) - 1;
+    const int32_t x0 = __shfl(x, leader, 64);
+    const bool mine = pending && x == x0;
+    const int cnt = __popcll(__ballot(mine));
+    const ull sum = group_sum_u64<64>(mine ? dk : 0ull);
+    if (lane == leader) {
+      atomicAdd((ull*)&rec[x0].sig, sum);
+      atomicAdd(&rec[x0].size, dsz * cnt);
+    }
+    if (mine) pending = false;
+  }
+  if (pending) {
+    atomicAdd((ull*)&rec[x].sig, dk);
+    atomicAdd(&rec[x].size, dsz);
+  }
+}
+
 // Apply a class step's decisions: C, Sigma and csize after the step. Integer atomics commute,
 // so the result is independent of the order of the movers.
 __global__ void k_apply_moves(const int32_t* verts, int64_t count, const int32_t* tgt,
                               const uint64_t* K, VRec* rec) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = verts[i];
-    const int32_t c = tgt[v];
-    const int32_t d = rec[v].c;
-    if (c == d) continue;
-    const ull k = (ull)K[v];
-    rec[v].c = c;
-    atomicAdd(&rec[c].sig, k);
-    atomicAdd(&rec[d].sig, (ull)(0ull - k));
-    atomicAdd(&rec[c].size, 1);
-    atomicSub(&rec[d].size, 1);
+  // whole blocks iterate together (the grouping works on whole waves)
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < count;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    int32_t c = -1, d = -1;
+    ull k = 0;
+    if (i < count) {
+      const int32_t v = verts[i];
+      c = tgt[v];
+      d = rec[v].c;
+      if (c != d) {
+        k = (ull)K[v];
+        rec[v].c = c;
+      } else {
+        c = d = -1;
+      }
+    }
+    add_grouped(rec, c, k, 1);
+    add_grouped(rec, d, 0ull - k, -1);
   }
 }
 
@@ -1937,23 +2052,57 @@ hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStrea
 // output arrays: the super-vertex graph keeps the rows where they were produced (row a spans
 // [rs[a], re[a]) of those arrays), so no compaction pass is needed between passes.
 
+// Claims cnt slots of counter ctr[x] for every lane with x >= 0 and returns the lane's slot:
+// lanes of a wave that name the same label share one atomic (a few groups per wave, as in
+// add_grouped: after the first pass the members of a level are mostly in a few large
+// communities), the rest claim their own. Called by whole waves.
+__device__ __forceinline__ int32_t claim_grouped(int32_t* ctr, int32_t x) {
+  bool pending = x >= 0;
+  int32_t slot = -1;
+  const int lane = threadIdx.x & 63;
+#pragma unroll 1
+  for (int round = 0; round < 4; round++) {
+    const uint64_t live = __ballot(pending);
+    if (!live) return slot;
+    const int leader = __ffsll((long long)live) - 1;
+    const int32_t x0 = __shfl(x, leader, 64);
+    const bool mine = pending && x == x0;
+    const uint64_t gm = __ballot(mine);
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[x0], __popcll(gm));
+    base = __shfl(base, leader, 64);
+    if (mine) {
+      slot = base + __popcll(gm & ((1ull << lane) - 1ull));
+      pending = false;
+    }
+  }
+  if (pending) slot = atomicAdd(&ctr[x], 1);
+  return slot;
+}
+
 // Vertices with arcs per label.
 __global__ void k_count_members(const int64_t* rs, const int64_t* re, const int32_t* C,
                                 int64_t n, int32_t* mcount) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    if (re[i] > rs[i]) atomicAdd(&mcount[C[i]], 1);
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = b + threadIdx.x;
+    (void)claim_grouped(mcount, i < n && re[i] > rs[i] ? C[i] : -1);
+  }
 }
 
 // map[v] = new id of v's community; members with arcs placed in their community's slot range.
 __global__ void k_fill_members(const int64_t* rs, const int64_t* re, const int32_t* C, int64_t n,
                                const int64_t* newid, const int64_t* mstart, int32_t* mcur,
                                int32_t* map, int32_t* members) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = C[i];
-    map[i] = (int32_t)newid[c];
-    if (re[i] > rs[i]) members[mstart[c] + atomicAdd(&mcur[c], 1)] = (int32_t)i;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = b + threadIdx.x;
+    int32_t c = -1;
+    if (i < n) {
+      c = C[i];
+      map[i] = (int32_t)newid[c];
+      if (!(re[i] > rs[i])) c = -1;
+    }
+    const int32_t slot = claim_grouped(mcur, c);
+    if (c >= 0) members[mstart[c] + slot] = (int32_t)i;
   }
 }
 
@@ -1996,27 +2145,6 @@ hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t*
   LV_LAUNCH(k_label_ranges, grid_for(n), kBlock, 0, s, n, csize, a.newid, a.mstart, a.gscan,
             Sig, a.oldlabel, Kp, a.astart, a.A);
   return hipGetLastError();
-}
-
-// Largest member index i in [0, mc) with start[i] <= t (start[0] = 0 <= t).
-template <typename T>
-__device__ __forceinline__ int member_at(const T* start, int mc, int64_t t) {
-  int lo = 0, hi = mc;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((int64_t)start[mid] <= t) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-// Largest member index i in [lo, hi) with start[i] <= t, given start[lo] <= t.
-template <typename T>
-__device__ __forceinline__ int member_in(const T* start, int lo, int hi, int64_t t) {
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((int64_t)start[mid] <= t) lo = mid; else hi = mid;
-  }
-  return lo;
 }
 
 // Super-arc weights: 32-bit when every community's Sigma (which bounds the weight of each of

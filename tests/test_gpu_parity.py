@@ -187,6 +187,27 @@ def test_modularity(lv, g):
         assert abs(qd - qo / (Wo * Wo)) <= 4e-16 * max(1.0, abs(qd))
 
 
+@pytest.mark.parametrize("iso", [0, 2, 20])
+def test_row_sums_row_spans(lv, iso):
+    # row sums (through W and the singleton Qnum) when a tile of arcs spans few rows, about a
+    # thousand, or many thousands of rows (isolated vertices between the rows with arcs), so
+    # that both the LDS-staged and the per-row paths run, with self-loops in the rows
+    base = erdos_renyi(3000, 0.004, seed=21, weights=(1, 7), self_loops=True)
+    n = base.n * (iso + 1)
+    off = base.offsets.numpy().astype(np.int64)
+    deg = np.diff(off)
+    rows = np.repeat(np.arange(base.n) * (iso + 1), deg)
+    cols = base.indices.numpy().astype(np.int64) * (iso + 1)
+    g = csr_from_arcs(n, torch.from_numpy(rows), torch.from_numpy(cols), base.weights,
+                      name=f"er3000x{iso + 1}")
+    og = O.Graph.from_csr(g)
+    C = np.arange(n, dtype=np.int32)
+    q, W, _ = lv.modularity(g.to("cuda:0"), torch.from_numpy(C).to("cuda:0"))
+    qo, Wo, _ = O.modularity(og, C)
+    assert (q, W) == (qo, Wo)
+    check_run(lv, g)
+
+
 @pytest.mark.parametrize("g", CORPUS, ids=IDS)
 @pytest.mark.parametrize("offsets_64", [True, False])
 def test_aggregate(lv, g, offsets_64):
