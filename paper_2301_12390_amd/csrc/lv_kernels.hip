@@ -1976,57 +1976,64 @@ hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const PartPla
                : move_hubs_t<false, uint32_t>(g, b, cls, pp, m, s);
 }
 
-// Adds (dk, dsz) to the Sigma and size of community x for every lane with x >= 0. Lanes of a
-// wave that name the same community are combined first, a few groups per wave (the leader of
-// each group makes one atomic of the group's sum), since the movers of a step often join the
-// same few large communities; the remaining lanes add their own. Called by whole waves.
-__device__ __forceinline__ void add_grouped(VRec* rec, int32_t x, ull dk, int dsz) {
-  bool pending = x >= 0;
-  const int lane = threadIdx.x & 63;
-#pragma unroll 1
-  for (int round = 0; round < 4; round++) {
-    const uint64_t live = __ballot(pending);
-    if (!live) return;
-    const int leader = __ffsll((long long)live) - 1;
-    const int32_t x0 = __shfl(x, leader, 64);
-    const bool mine = pending && x == x0;
-    const int cnt = __popcll(__ballot(mine));
-    const ull sum = group_sum_u64<64>(mine ? dk : 0ull);
-    if (lane == leader) {
-      atomicAdd((ull*)&rec[x0].sig, sum);
-      atomicAdd(&rec[x0].size, dsz * cnt);
-    }
-    if (mine) pending = false;
-  }
-  if (pending) {
-    atomicAdd((ull*)&rec[x].sig, dk);
-    atomicAdd(&rec[x].size, dsz);
+// Slot of label x in a workgroup's LDS combining table of 2^LOG2 slots (open addressing; the
+// table has room for every label the workgroup inserts before it is flushed).
+template <int LOG2>
+__device__ __forceinline__ int comb_slot(int32_t* keys, int32_t x) {
+  uint32_t s = slot_of(x, LOG2);
+  while (true) {
+    const int32_t prev = atomicCAS(&keys[s], kEmpty, x);
+    if (prev == kEmpty || prev == x) return (int)s;
+    s = (s + 1u) & ((1u << LOG2) - 1u);
   }
 }
 
-// Apply a class step's decisions: C, Sigma and csize after the step. Integer atomics commute,
-// so the result is independent of the order of the movers.
-__global__ void k_apply_moves(const int32_t* verts, int64_t count, const int32_t* tgt,
-                              const uint64_t* K, VRec* rec) {
-  // whole blocks iterate together (the grouping works on whole waves)
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < count;
-       base += (int64_t)gridDim.x * blockDim.x) {
+// Apply a class step's decisions: C, Sigma and csize after the step. Each workgroup combines
+// its movers' changes per community in LDS (a mover adds K to its new community and takes it
+// from its old one) and then makes one atomic per community it touched: the movers of a step
+// often join the same few large communities, whose words would otherwise take one atomic per
+// mover. Integer sums commute, so the result is independent of the order of the movers.
+constexpr int kApplyLog2 = 10;  // 1024 slots for the 2 * kBlock communities of a tile
+__global__ __launch_bounds__(kBlock) void k_apply_moves(const int32_t* verts, int64_t count,
+                                                       const int32_t* tgt, const uint64_t* K,
+                                                       VRec* rec) {
+  constexpr int S = 1 << kApplyLog2;
+  __shared__ int32_t ckey[S];
+  __shared__ ull csig[S];
+  __shared__ int32_t ccnt[S];
+  // whole workgroups iterate together (the table is shared)
+  for (int64_t base = blockIdx.x * (int64_t)kBlock; base < count;
+       base += (int64_t)gridDim.x * kBlock) {
+    for (int t = threadIdx.x; t < S; t += kBlock) {
+      ckey[t] = kEmpty;
+      csig[t] = 0;
+      ccnt[t] = 0;
+    }
+    __syncthreads();
     const int64_t i = base + threadIdx.x;
-    int32_t c = -1, d = -1;
-    ull k = 0;
     if (i < count) {
       const int32_t v = verts[i];
-      c = tgt[v];
-      d = rec[v].c;
+      const int32_t c = tgt[v];
+      const int32_t d = rec[v].c;
       if (c != d) {
-        k = (ull)K[v];
+        const ull k = (ull)K[v];
         rec[v].c = c;
-      } else {
-        c = d = -1;
+        const int sc = comb_slot<kApplyLog2>(ckey, c);
+        atomicAdd(&csig[sc], k);
+        atomicAdd(&ccnt[sc], 1);
+        const int sd = comb_slot<kApplyLog2>(ckey, d);
+        atomicAdd(&csig[sd], 0ull - k);
+        atomicAdd(&ccnt[sd], -1);
       }
     }
-    add_grouped(rec, c, k, 1);
-    add_grouped(rec, d, 0ull - k, -1);
+    __syncthreads();
+    for (int t = threadIdx.x; t < S; t += kBlock) {
+      const int32_t x = ckey[t];
+      if (x == kEmpty) continue;
+      if (csig[t]) atomicAdd((ull*)&rec[x].sig, csig[t]);
+      if (ccnt[t]) atomicAdd(&rec[x].size, ccnt[t]);
+    }
+    __syncthreads();
   }
 }
 
@@ -2052,57 +2059,69 @@ hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStrea
 // output arrays: the super-vertex graph keeps the rows where they were produced (row a spans
 // [rs[a], re[a]) of those arrays), so no compaction pass is needed between passes.
 
-// Claims cnt slots of counter ctr[x] for every lane with x >= 0 and returns the lane's slot:
-// lanes of a wave that name the same label share one atomic (a few groups per wave, as in
-// add_grouped: after the first pass the members of a level are mostly in a few large
-// communities), the rest claim their own. Called by whole waves.
-__device__ __forceinline__ int32_t claim_grouped(int32_t* ctr, int32_t x) {
-  bool pending = x >= 0;
-  int32_t slot = -1;
-  const int lane = threadIdx.x & 63;
-#pragma unroll 1
-  for (int round = 0; round < 4; round++) {
-    const uint64_t live = __ballot(pending);
-    if (!live) return slot;
-    const int leader = __ffsll((long long)live) - 1;
-    const int32_t x0 = __shfl(x, leader, 64);
-    const bool mine = pending && x == x0;
-    const uint64_t gm = __ballot(mine);
-    int32_t base = 0;
-    if (lane == leader) base = atomicAdd(&ctr[x0], __popcll(gm));
-    base = __shfl(base, leader, 64);
-    if (mine) {
-      slot = base + __popcll(gm & ((1ull << lane) - 1ull));
-      pending = false;
-    }
-  }
-  if (pending) slot = atomicAdd(&ctr[x], 1);
-  return slot;
-}
+// Both member kernels combine per label within a workgroup first (LDS table, one global
+// atomic per label per workgroup): after the first pass the members of a level mostly belong
+// to a few large communities, whose counters would otherwise take one atomic per member.
+constexpr int kMemberLog2 = 9;  // 512 slots for the kBlock labels of a tile
 
 // Vertices with arcs per label.
-__global__ void k_count_members(const int64_t* rs, const int64_t* re, const int32_t* C,
-                                int64_t n, int32_t* mcount) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(kBlock) void k_count_members(const int64_t* rs, const int64_t* re,
+                                                         const int32_t* C, int64_t n,
+                                                         int32_t* mcount) {
+  constexpr int S = 1 << kMemberLog2;
+  __shared__ int32_t ckey[S];
+  __shared__ int32_t ccnt[S];
+  for (int64_t b = blockIdx.x * (int64_t)kBlock; b < n; b += (int64_t)gridDim.x * kBlock) {
+    for (int t = threadIdx.x; t < S; t += kBlock) {
+      ckey[t] = kEmpty;
+      ccnt[t] = 0;
+    }
+    __syncthreads();
     const int64_t i = b + threadIdx.x;
-    (void)claim_grouped(mcount, i < n && re[i] > rs[i] ? C[i] : -1);
+    if (i < n && re[i] > rs[i]) atomicAdd(&ccnt[comb_slot<kMemberLog2>(ckey, C[i])], 1);
+    __syncthreads();
+    for (int t = threadIdx.x; t < S; t += kBlock)
+      if (ckey[t] != kEmpty) atomicAdd(&mcount[ckey[t]], ccnt[t]);
+    __syncthreads();
   }
 }
 
-// map[v] = new id of v's community; members with arcs placed in their community's slot range.
-__global__ void k_fill_members(const int64_t* rs, const int64_t* re, const int32_t* C, int64_t n,
-                               const int64_t* newid, const int64_t* mstart, int32_t* mcur,
-                               int32_t* map, int32_t* members) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+// map[v] = new id of v's community; members with arcs placed in their community's slot range
+// (a workgroup claims each label's share with one atomic; its members take consecutive slots).
+__global__ __launch_bounds__(kBlock) void k_fill_members(const int64_t* rs, const int64_t* re,
+                                                        const int32_t* C, int64_t n,
+                                                        const int64_t* newid,
+                                                        const int64_t* mstart, int32_t* mcur,
+                                                        int32_t* map, int32_t* members) {
+  constexpr int S = 1 << kMemberLog2;
+  __shared__ int32_t ckey[S];
+  __shared__ int32_t ccnt[S];
+  __shared__ int32_t cbase[S];
+  for (int64_t b = blockIdx.x * (int64_t)kBlock; b < n; b += (int64_t)gridDim.x * kBlock) {
+    for (int t = threadIdx.x; t < S; t += kBlock) {
+      ckey[t] = kEmpty;
+      ccnt[t] = 0;
+    }
+    __syncthreads();
     const int64_t i = b + threadIdx.x;
     int32_t c = -1;
+    int slot = 0, rank = 0;
     if (i < n) {
       c = C[i];
       map[i] = (int32_t)newid[c];
-      if (!(re[i] > rs[i])) c = -1;
+      if (re[i] > rs[i]) {
+        slot = comb_slot<kMemberLog2>(ckey, c);
+        rank = atomicAdd(&ccnt[slot], 1);
+      } else {
+        c = -1;
+      }
     }
-    const int32_t slot = claim_grouped(mcur, c);
-    if (c >= 0) members[mstart[c] + slot] = (int32_t)i;
+    __syncthreads();
+    for (int t = threadIdx.x; t < S; t += kBlock)
+      if (ckey[t] != kEmpty) cbase[t] = atomicAdd(&mcur[ckey[t]], ccnt[t]);
+    __syncthreads();
+    if (c >= 0) members[mstart[c] + cbase[slot] + rank] = (int32_t)i;
+    __syncthreads();
   }
 }
 
