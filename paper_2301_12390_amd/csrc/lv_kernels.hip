@@ -380,16 +380,11 @@ __device__ __forceinline__ int member_in(const T* start, int lo, int hi, int64_t
 constexpr int64_t kSeg = 16;
 
 // Row sums: workgroup b sums the arcs of its range [lo, hi) of kRowTile arcs, attributing them
-// to the rows they belong to. When the range spans at most kRowSpanLds rows (empty ones
-// included), their offsets are staged in LDS and the lanes read consecutive arcs: each lane
-// finds its arc's row by an LDS search, a segmented scan over the wave sums each row's run of
-// lanes, and the last lane of a run adds it to the row's LDS total. Otherwise, up to kShortRow
-// arcs of a row one per thread, longer stretches one per wavefront. A row lying wholly inside
-// the range is stored; the (at most two) rows crossing its ends are added atomically. K must
-// be zero (rows of no arcs keep 0).
+// to the rows they belong to: up to kShortRow arcs of a row one per thread, longer stretches one
+// per wavefront (coalesced). A row lying wholly inside the range is stored; the (at most two)
+// rows crossing its ends are added atomically. K must be zero (rows of no arcs keep 0).
 constexpr int64_t kRowTile = 4096;
 constexpr int64_t kShortRow = 32;
-constexpr int kRowSpanLds = 1024;
 
 // tile_rows[t] = the row holding arc t * kRowTile, for every tile t (each arc lies in exactly
 // one non-empty row, so every tile gets one writer); tile_rows[tiles] = n - 1.
@@ -416,65 +411,11 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t
   __shared__ int64_t span[2];
   __shared__ int64_t longs[kRowTile / kShortRow + 2];
   __shared__ int nlong;
-  __shared__ int64_t roff[kRowSpanLds + 1];
-  __shared__ ull racc[kRowSpanLds];
-  __shared__ ull rself[SELF ? kRowSpanLds : 1];
   const int64_t lo = (int64_t)blockIdx.x * kRowTile;
   const int64_t hi = lo + kRowTile < nnz ? lo + kRowTile : nnz;
   if (threadIdx.x < 2) span[threadIdx.x] = tile_rows[blockIdx.x + threadIdx.x];
   if (threadIdx.x == 0) nlong = 0;
   __syncthreads();
-  const int64_t r0 = span[0];
-  const int nr = (int)(span[1] - r0 + 1 < kRowSpanLds + 1 ? span[1] - r0 + 1 : kRowSpanLds + 1);
-  if (nr <= kRowSpanLds) {
-    for (int i = threadIdx.x; i <= nr; i += kBlock) roff[i] = off[r0 + i];
-    for (int i = threadIdx.x; i < nr; i += kBlock) {
-      racc[i] = 0;
-      if (SELF) rself[i] = 0;
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    for (int64_t base = lo; base < hi; base += kBlock) {  // block-uniform trip count
-      const int64_t e = base + threadIdx.x;
-      int r = -1;
-      ull x = 0, sl = 0;
-      if (e < hi) {
-        r = member_at(roff, nr, e);
-        x = (ull)ld_stream(w + e);
-        if (SELF && ld_stream(idx + e) == (int32_t)(r0 + r)) sl = x;
-      }
-      // rows are non-decreasing along the lanes: a segmented inclusive scan by row
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const ull y = __shfl_up(x, d, 64);
-        const ull ys = SELF ? __shfl_up(sl, d, 64) : 0ull;
-        const int ry = __shfl_up(r, d, 64);
-        if (lane >= d && ry == r) {
-          x += y;
-          if (SELF) sl += ys;
-        }
-      }
-      const int rn = __shfl_down(r, 1, 64);
-      if (r >= 0 && (lane == 63 || rn != r)) {
-        atomicAdd(&racc[r], x);
-        if (SELF && sl) atomicAdd(&rself[r], sl);
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += kBlock) {
-      const int64_t b0 = roff[i], b1 = roff[i + 1];
-      if (b1 <= b0) continue;
-      const int64_t r = r0 + i;
-      if (b0 >= lo && b1 <= hi) {
-        K[r] = racc[i];
-        if (SELF) selfw[r] = rself[i];
-      } else {
-        atomicAdd((ull*)&K[r], racc[i]);
-        if (SELF && rself[i]) atomicAdd((ull*)&selfw[r], rself[i]);
-      }
-    }
-    return;
-  }
   for (int64_t r = span[0] + threadIdx.x; r <= span[1]; r += kBlock) {
     const int64_t b0 = off[r], b1 = off[r + 1];
     const int64_t e0 = b0 > lo ? b0 : lo, e1 = b1 < hi ? b1 : hi;

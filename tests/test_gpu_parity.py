@@ -189,9 +189,9 @@ def test_modularity(lv, g):
 
 @pytest.mark.parametrize("iso", [0, 2, 20])
 def test_row_sums_row_spans(lv, iso):
-    # row sums (through W and the singleton Qnum) when a tile of arcs spans few rows, about a
-    # thousand, or many thousands of rows (isolated vertices between the rows with arcs), so
-    # that both the LDS-staged and the per-row paths run, with self-loops in the rows
+    # row sums (through W and the singleton Qnum) when a 4096-arc tile spans a few hundred, about
+    # a thousand, or several thousand rows (isolated vertices between the rows with arcs), with
+    # self-loops in the rows, and a whole run on each
     base = erdos_renyi(3000, 0.004, seed=21, weights=(1, 7), self_loops=True)
     n = base.n * (iso + 1)
     off = base.offsets.numpy().astype(np.int64)
