@@ -29,7 +29,8 @@ enum SlotId {
   S_PVAL1, S_PHIST, S_POFFS, S_PTILE, S_PSLOT, S_PFIRST, S_POFF, S_PGHIST, S_PGBASE, S_PSTATUS,
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
-  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_CFM, S_COUNT_SLOTS
+  S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_CFM, S_LFLAG, S_NOARC,
+  S_LIVEB, S_REP0, S_REP1, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -656,11 +657,12 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
 // to okey/ow (g.nnz entries) at their community's flat position. Outputs: map[n], Kp[n'] (if
 // Sig), the buffers describing the rows (*out), n', nnz' and the weight of the self super-arcs.
 // With allow_w32 and Sig, the super-arc weights are written as uint32 when every Sigma is below
-// 2^32 (out->w32 tells which).
+// 2^32 (out->w32 tells which). With live_only, only communities with arcs get new ids (map -1
+// for the others; see the live numbering in lv_kernels.hip).
 lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const int32_t* csize,
                     const uint64_t* Sig, int32_t* map, int32_t* okey, uint64_t* ow, uint64_t* Kp,
                     lv::AggBuffers* out, int64_t* n_out, int64_t* nnz_out, uint64_t* self_out,
-                    hipStream_t s, bool allow_w32 = false) {
+                    hipStream_t s, bool allow_w32 = false, bool live_only = false) {
   const int64_t n = g.n;
   lv::AggBuffers a;
   a.gs = out->gs;  // batches: graph of every label and per-graph self super-arc weights
@@ -683,7 +685,7 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   a.ow = ow;
   a.stats = st + ST_MISC + 8;
   HIPCHK(lv::zero_words(a.stats, 2, s));
-  HIPCHK(lv::aggregate_prepare(g, C, csize, Sig, Kp, map, a, s));
+  HIPCHK(lv::aggregate_prepare(g, C, csize, Sig, Kp, map, a, live_only, s));
   lv::Buckets b;
   HIPCHK(lv::bucket_rows(nullptr, nullptr, a.A, n, 1, 0, nullptr, nullptr, nullptr, nullptr,
                          a.list,
@@ -1074,6 +1076,19 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
   int which = 0;  // next super-graph buffer set
   void* rec = nullptr;
   CHK(ws(ctx, S_REC, (size_t)n0 * lv::kRecBytes, &rec));
+  // Live numbering from the first aggregation on (see lv_kernels.hip): the vertices without
+  // arcs (n_noarc) leave the working graph, which keeps the order of the others. rep: the
+  // representatives of the working graph's super-vertices; noarc_before: prefix count of the
+  // vertices without arcs. Not with colour classes, whose colouring reads the vertex ids.
+  const bool live = (p->flags & LV_COLOR_CLASSES) == 0;
+  bool relabelled = false;  // membership holds live ids (-1: no arcs)
+  int64_t n_noarc = 0;
+  int32_t* rep = nullptr;
+  int rep_which = 0;
+  int64_t* noarc_before = nullptr;
+  int32_t* lflag = nullptr;
+  int64_t* live_before = nullptr;
+  int64_t* scanp0 = nullptr;
   for (int pass = 0; pass < p->max_passes; pass++) {
     HIPCHK(lv::init_state(cur.n, K, rec, s));
     Phase ph;
@@ -1085,6 +1100,13 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     ph.classes = p->substeps;
     ph.pass = pass;
     ph.colour = (p->flags & LV_COLOR_CLASSES) != 0;
+    const int64_t n_canon = cur.n + (relabelled ? n_noarc : 0);  // vertices in the method's ids
+    if (relabelled && n_noarc > 0 && p->substeps > 1) {
+      uint8_t* vc = nullptr;  // hashed classes by the method's ids
+      CHK(wst(ctx, S_VCLASS, cur.n, &vc));
+      HIPCHK(lv::live_classes(cur.n, pass, p->substeps, rep, noarc_before, vc, s));
+      ph.vclass = vc;
+    }
     CHK(plan_phase(ctx, ph, s));
     PhaseOut po;
     CHK(run_phase(ctx, ph, tolerance_threshold(W, p->tolerance_exp10, p->decline_exp10, pass),
@@ -1092,7 +1114,7 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     res->passes = pass + 1;
     res->iterations[pass] = po.iterations;
     res->iterations_total += po.iterations;
-    res->n_pass[pass] = cur.n;
+    res->n_pass[pass] = n_canon;
     res->nnz_pass[pass] = cur.nnz;
     if (po.hit_cap) res->cap_hits++;
     if (po.gain_sum == 0) {
@@ -1115,7 +1137,7 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     lv::AggBuffers ab;
     HIPCHK(lv::unpack_state(cur.n, rec, C, Sig, csize, s));
     CHK(aggregate(ctx, cur, C, csize, Sig, map, nidx, nw, K, &ab, &np, &nnzp, &self, s,
-                  (p->flags & LV_FORCE_WIDE) == 0));
+                  (p->flags & LV_FORCE_WIDE) == 0, live));
     HIPCHK(lv::super_rows(np, ab, nrs, nre, s));
     // W^2 Q reached by this pass = that of singletons on the super-vertex graph
     ull* st = nullptr;
@@ -1138,13 +1160,41 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     if (!(q_pass > qnum)) break;
     qnum = q_pass;
     maxK = h[3];
+    if (live) {
+      if (!relabelled) {
+        // the first kept aggregation is pass 0's: its vertices without arcs got no new id
+        int32_t* r0 = nullptr;
+        int32_t* r1 = nullptr;
+        CHK(wst(ctx, S_REP0, n0, &r0));
+        CHK(wst(ctx, S_REP1, n0, &r1));
+        CHK(wst(ctx, S_LFLAG, n0, &lflag));
+        CHK(wst(ctx, S_NOARC, n0 + 1, &noarc_before));
+        CHK(wst(ctx, S_LIVEB, n0 + 1, &live_before));
+        CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n0 + 1) + 1, &scanp0));
+        HIPCHK(lv::no_arc_prefix(g0, lflag, noarc_before, scanp0, s));
+        HIPCHK(hipMemcpyAsync(h, noarc_before + n0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        n_noarc = (int64_t)h[0];
+        relabelled = true;
+      }
+      int32_t* rnext = nullptr;
+      CHK(wst(ctx, rep_which ? S_REP1 : S_REP0, n0, &rnext));
+      HIPCHK(lv::next_rep(np, ab.oldlabel, rep, rnext, s));
+      rep = rnext;
+      rep_which ^= 1;
+    }
     HIPCHK(lv::compose_membership(membership, n0, map, s));
     if (levels && nlev < max_levels) {
-      HIPCHK(hipMemcpyAsync(levels + (size_t)nlev * (size_t)n0, membership,
-                            sizeof(int32_t) * (size_t)n0, hipMemcpyDeviceToDevice, s));
+      int32_t* lev = levels + (size_t)nlev * (size_t)n0;
+      if (relabelled && n_noarc > 0)
+        HIPCHK(lv::canon_membership(n0, membership, np, rep, noarc_before, lflag, live_before,
+                                    scanp0, lev, s));
+      else
+        HIPCHK(hipMemcpyAsync(lev, membership, sizeof(int32_t) * (size_t)n0,
+                              hipMemcpyDeviceToDevice, s));
       nlev++;
     }
-    const bool shrunk = np < cur.n;
+    const bool shrunk = np + (relabelled ? n_noarc : 0) < n_canon;
     lv::DevGraph nxt;
     nxt.n = np;
     nxt.nnz = nnzp;
@@ -1155,10 +1205,13 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     nxt.w = nw;
     nxt.w64 = !ab.w32;
     cur = nxt;
-    n_comm = np;
+    n_comm = np + (relabelled ? n_noarc : 0);
     which ^= 1;
     if (!shrunk) break;
   }
+  if (relabelled && n_noarc > 0)  // back to the method's numbering, in place
+    HIPCHK(lv::canon_membership(n0, membership, cur.n, rep, noarc_before, lflag, live_before,
+                                scanp0, membership, s));
   res->n_communities = n_comm;
   res->q_num = to_i128(qnum);
   res->q = q_of(qnum, W);

@@ -216,7 +216,19 @@ struct AggBuffers {
 // Renumbering, member lists and flat arc ranges (everything before the merge).
 hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t* csize,
                              const uint64_t* Sig, uint64_t* Kp, int32_t* map,
-                             const AggBuffers& a, hipStream_t s);
+                             const AggBuffers& a, bool live_only, hipStream_t s);
+// Live numbering (only communities with arcs get new ids; see lv_kernels.hip): the next level's
+// representatives, the prefix count of vertices without arcs, the hashed classes by the
+// method's ids, and the membership in the method's numbering.
+hipError_t next_rep(int64_t np, const int32_t* oldlabel, const int32_t* rep, int32_t* rep_next,
+                    hipStream_t s);
+hipError_t no_arc_prefix(const DevGraph& g, int32_t* flag, int64_t* noarc_before,
+                         int64_t* partial, hipStream_t s);
+hipError_t live_classes(int64_t nl, int32_t pass, int32_t K, const int32_t* rep,
+                        const int64_t* noarc_before, uint8_t* vclass, hipStream_t s);
+hipError_t canon_membership(int64_t n0, const int32_t* top, int64_t nl, const int32_t* rep,
+                            const int64_t* noarc_before, int32_t* flag, int64_t* live_before,
+                            int64_t* partial, int32_t* out, hipStream_t s);
 hipError_t merge_lds(const DevGraph& g, const Buckets& b, const AggBuffers& a, hipStream_t s);
 int64_t merge_lds_blocks(const Buckets& b);  // sizes block_partial
 // Communities of classes 7 .. part_first - 1 (one workgroup each, whole table in LDS); the

@@ -2027,8 +2027,9 @@ __global__ __launch_bounds__(kBlock) void k_count_members(const int64_t* rs, con
   }
 }
 
-// map[v] = new id of v's community; members with arcs placed in their community's slot range
-// (a workgroup claims each label's share with one atomic; its members take consecutive slots).
+// map[v] = new id of v's community (-1 if the community gets none); members with arcs placed in
+// their community's slot range (a workgroup claims each label's share with one atomic; its
+// members take consecutive slots).
 __global__ __launch_bounds__(kBlock) void k_fill_members(const int64_t* rs, const int64_t* re,
                                                         const int32_t* C, int64_t n,
                                                         const int64_t* newid,
@@ -2049,7 +2050,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_members(const int64_t* rs, cons
     int slot = 0, rank = 0;
     if (i < n) {
       c = C[i];
-      map[i] = (int32_t)newid[c];
+      map[i] = newid[c + 1] > newid[c] ? (int32_t)newid[c] : -1;
       if (re[i] > rs[i]) {
         slot = comb_slot<kMemberLog2>(ckey, c);
         rank = atomicAdd(&ccnt[slot], 1);
@@ -2066,16 +2067,16 @@ __global__ __launch_bounds__(kBlock) void k_fill_members(const int64_t* rs, cons
   }
 }
 
-// Per used label: its new id's tables, its flat arc range and arc count.
-__global__ void k_label_ranges(int64_t n, const int32_t* csize, const int64_t* newid,
-                               const int64_t* mstart, const int64_t* gscan, const uint64_t* Sig,
-                               int32_t* oldlabel, uint64_t* Kp, int64_t* astart, int64_t* A) {
+// Per label: its flat arc range and arc count; per label with a new id, that id's tables.
+__global__ void k_label_ranges(int64_t n, const int64_t* newid, const int64_t* mstart,
+                               const int64_t* gscan, const uint64_t* Sig, int32_t* oldlabel,
+                               uint64_t* Kp, int64_t* astart, int64_t* A) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a0 = gscan[mstart[c]];
     astart[c] = a0;
     A[c] = gscan[mstart[c + 1]] - a0;
-    if (csize[c] > 0) {
+    if (newid[c + 1] > newid[c]) {
       const int64_t a = newid[c];
       oldlabel[a] = (int32_t)c;
       if (Kp) Kp[a] = Sig[c];
@@ -2085,13 +2086,15 @@ __global__ void k_label_ranges(int64_t n, const int32_t* csize, const int64_t* n
 
 hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t* csize,
                              const uint64_t* Sig, uint64_t* Kp, int32_t* map,
-                             const AggBuffers& a, hipStream_t s) {
+                             const AggBuffers& a, bool live_only, hipStream_t s) {
   const int64_t n = g.n;
   if (n <= 0) return hipSuccess;
   hipError_t e;
-  if ((e = scan_flags_pos(csize, n, a.newid, a.partial, s)) != hipSuccess) return e;
   LV_LAUNCH(k_fill_i32, grid_for(n), kBlock, 0, s, a.mcount, 0, n);
   LV_LAUNCH(k_count_members, grid_for(n), kBlock, 0, s, g.rs, g.re, C, n, a.mcount);
+  // new ids: rank of the used labels, or (live_only) of the labels whose members have arcs
+  if ((e = scan_flags_pos(live_only ? a.mcount : csize, n, a.newid, a.partial, s)) != hipSuccess)
+    return e;
   if ((e = scan_impl(ReadI32{a.mcount}, n, a.mstart, a.partial, s)) != hipSuccess) return e;
   LV_LAUNCH(k_fill_i32, grid_for(n), kBlock, 0, s, a.mcount, 0, n);  // reused as cursors
   LV_LAUNCH(k_fill_members, grid_for(n), kBlock, 0, s, g.rs, g.re, C, n, a.newid, a.mstart,
@@ -2102,8 +2105,96 @@ hipError_t aggregate_prepare(const DevGraph& g, const int32_t* C, const int32_t*
   if ((e = scan_impl(ReadMemberDegGuard{a.members, g.rs, g.re, a.mstart + n}, n, a.gscan,
                      a.partial, s)) != hipSuccess)
     return e;
-  LV_LAUNCH(k_label_ranges, grid_for(n), kBlock, 0, s, n, csize, a.newid, a.mstart, a.gscan,
-            Sig, a.oldlabel, Kp, a.astart, a.A);
+  LV_LAUNCH(k_label_ranges, grid_for(n), kBlock, 0, s, n, a.newid, a.mstart, a.gscan, Sig,
+            a.oldlabel, Kp, a.astart, a.A);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Live numbering. A vertex without arcs never moves and is never a candidate, so a run may give
+// new ids only to communities with arcs (aggregate_prepare with live_only), in the order of
+// their labels. That keeps every comparison of labels, and so every decision, as in the
+// numbering of the method (new id = rank of every used label), which is recovered where it is
+// needed from rep[x], the original vertex that labels super-vertex x's line of communities: the
+// numbering's order of super-vertices is the order of their representatives, and its id of x
+// is x plus the number of vertices without arcs (one singleton community each, at every level)
+// whose id is below rep[x].
+
+// rep of the next level: that of each new id's old label (rep null: the old label itself).
+__global__ void k_next_rep(int64_t np, const int32_t* oldlabel, const int32_t* rep,
+                           int32_t* rep_next) {
+  for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < np;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = oldlabel[a];
+    rep_next[a] = rep ? rep[c] : c;
+  }
+}
+
+// flag[v] = 1 for the vertices of g without arcs.
+__global__ void k_no_arc_flags(const int64_t* rs, const int64_t* re, int64_t n, int32_t* flag) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    flag[v] = re[v] > rs[v] ? 0 : 1;
+}
+
+// flag[rep[x]] = 1 for every super-vertex x (flag zero before).
+__global__ void k_mark_reps(int64_t nl, const int32_t* rep, int32_t* flag) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nl;
+       x += (int64_t)gridDim.x * blockDim.x)
+    flag[rep[x]] = 1;
+}
+
+// Hashed class of every super-vertex by its id in the method's numbering.
+__global__ void k_live_classes(int64_t nl, int32_t pass, int32_t K, const int32_t* rep,
+                               const int64_t* noarc_before, uint8_t* vclass) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nl;
+       x += (int64_t)gridDim.x * blockDim.x)
+    vclass[x] = (uint8_t)vertex_class(pass, K, x + noarc_before[rep[x]]);
+}
+
+// Membership in the method's numbering from the live one (top[v] < 0: v has no arcs).
+// live_before[y]: super-vertices whose representative is below y.
+__global__ void k_canon_membership(int64_t n0, const int32_t* top, const int32_t* rep,
+                                   const int64_t* noarc_before, const int64_t* live_before,
+                                   int32_t* out) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n0;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = top[v];
+    out[v] = x >= 0 ? (int32_t)(x + noarc_before[rep[x]])
+                    : (int32_t)(live_before[v] + noarc_before[v]);
+  }
+}
+
+hipError_t next_rep(int64_t np, const int32_t* oldlabel, const int32_t* rep, int32_t* rep_next,
+                    hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  LV_LAUNCH(k_next_rep, grid_for(np), kBlock, 0, s, np, oldlabel, rep, rep_next);
+  return hipGetLastError();
+}
+
+hipError_t no_arc_prefix(const DevGraph& g, int32_t* flag, int64_t* noarc_before,
+                         int64_t* partial, hipStream_t s) {
+  LV_LAUNCH(k_no_arc_flags, grid_for(g.n), kBlock, 0, s, g.rs, g.re, g.n, flag);
+  return scan_flags_pos(flag, g.n, noarc_before, partial, s);
+}
+
+hipError_t live_classes(int64_t nl, int32_t pass, int32_t K, const int32_t* rep,
+                        const int64_t* noarc_before, uint8_t* vclass, hipStream_t s) {
+  if (nl <= 0) return hipSuccess;
+  LV_LAUNCH(k_live_classes, grid_for(nl), kBlock, 0, s, nl, pass, K, rep, noarc_before, vclass);
+  return hipGetLastError();
+}
+
+hipError_t canon_membership(int64_t n0, const int32_t* top, int64_t nl, const int32_t* rep,
+                            const int64_t* noarc_before, int32_t* flag, int64_t* live_before,
+                            int64_t* partial, int32_t* out, hipStream_t s) {
+  if (n0 <= 0) return hipSuccess;
+  LV_LAUNCH(k_fill_i32, grid_for(n0), kBlock, 0, s, flag, 0, n0);
+  if (nl > 0) LV_LAUNCH(k_mark_reps, grid_for(nl), kBlock, 0, s, nl, rep, flag);
+  hipError_t e = scan_flags_pos(flag, n0, live_before, partial, s);
+  if (e != hipSuccess) return e;
+  LV_LAUNCH(k_canon_membership, grid_for(n0), kBlock, 0, s, n0, top, rep, noarc_before,
+            live_before, out);
   return hipGetLastError();
 }
 
@@ -3045,8 +3136,10 @@ hipError_t validate_batch(const DevGraph& g, const int32_t* gid, const int64_t* 
 
 __global__ void k_compose(int32_t* top, int64_t n, const int32_t* map) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    top[i] = map[top[i]];
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = top[i];
+    top[i] = x >= 0 ? map[x] : -1;  // -1: a vertex without arcs in the live numbering
+  }
 }
 hipError_t compose_membership(int32_t* top, int64_t n, const int32_t* map, hipStream_t s) {
   if (n <= 0) return hipSuccess;
