@@ -30,7 +30,7 @@ enum SlotId {
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
   S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_CFM, S_LFLAG, S_NOARC,
-  S_LIVEB, S_REP0, S_REP1, S_COUNT_SLOTS
+  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -56,11 +56,11 @@ constexpr int kSmallPartShift = 6;
 // Word offsets in the device stats slot and in the pinned host buffer.
 constexpr int ST_MISC = 256;      // device: [256, 264) scratch sums, 264 aggregation self-loops
 constexpr int PIN_COUNTS = 0;     // host: 1536 words of class counts
-constexpr int PIN_HUB = 1536;     // host: hub plan totals
 constexpr int PIN_STATS = 1544;   // host: per-step iteration stats (8 words per class step)
 constexpr int PIN_MISC = 1808;    // host: other read-backs
 constexpr int PIN_NOALLOC = 2016; // host: 16 words of louvain_modularity_noalloc read-backs
-constexpr int PIN_WORDS = 2048;
+constexpr int PIN_PLANS = 2048;   // host: 4 totals per list of a batched two-phase plan
+constexpr int PIN_WORDS = 2048 + 4 * 32;
 constexpr int DEG = 12;           // degree classes per vertex class (list segment stride)
 constexpr int STATS_WORDS = 512;
 constexpr int kEvStep = 8;  // timing events per class step
@@ -322,12 +322,10 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   const int K = ph.classes;
   int32_t* list = nullptr;
   ull* counts = nullptr;
-  int64_t* scanp = nullptr;
   int64_t* hubarr = nullptr;
   CHK(wst(ctx, S_LIST, n, &list));
   CHK(wst(ctx, S_COUNTS, 1536, &counts));
   if (ph.colour && K > 1 && !ph.vclass) CHK(colour_phase(ctx, ph, s));
-  CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n + 1) + 1, &scanp));
   HIPCHK(lv::bucket_rows(ph.g.rs, ph.g.re, nullptr, n, K, ph.pass, ph.m.gs.gid, ph.m.gs.gbase,
                          ph.m.gs.act, K > 1 ? ph.vclass : nullptr, list, counts,
                          ctx->pinned + PIN_COUNTS, ph.b, s));
@@ -342,12 +340,24 @@ lv_status plan_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   // the pair, bound and partial buffers are shared by the class steps: sized for the largest
   const int vb = ph.wide ? 8 : 4;
   int64_t max_chunks = 0, max_walkers = 0, max_parts = 0, max_hoff = 0, off = 0;
+  const int32_t* items[32];
+  int64_t nhs[32];
+  int64_t* arrs[32];
   for (int k = 0; k < K; k++) {
-    const int64_t nh = hub_rows(k);
-    HIPCHK(lv::plan_parts(ph.g.rs, ph.g.re, nullptr, list + ph.b.lstart[DEG * k + hf], nh, n, vb,
-                          false, ctx->part_shift, hubarr + off, scanp, ctx->pinned + PIN_HUB,
-                          ph.hp[k], s));
-    off += lv::kPlanWords * (nh + 1);
+    items[k] = list + ph.b.lstart[DEG * k + hf];
+    nhs[k] = hub_rows(k);
+    arrs[k] = hubarr + off;
+    off += lv::kPlanWords * (nhs[k] + 1);
+  }
+  if (nh_total > 0) {  // every class's plan in one launch and one read-back
+    int64_t* tot = nullptr;
+    CHK(wst(ctx, S_PLANTOT, 4 * 32, &tot));
+    HIPCHK(lv::plan_parts_batch(ph.g.rs, ph.g.re, nullptr, items, nhs, K, n, vb, false,
+                                ctx->part_shift, arrs, tot, ctx->pinned + PIN_PLANS, ph.hp, s));
+  } else {
+    for (int k = 0; k < K; k++) ph.hp[k] = lv::PartPlan();
+  }
+  for (int k = 0; k < K; k++) {
     max_chunks = std::max(max_chunks, ph.hp[k].chunks);
     max_walkers = std::max(max_walkers, ph.hp[k].blocks);
     max_parts = std::max(max_parts, ph.hp[k].parts);
@@ -728,8 +738,12 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
     CHK(wst(ctx, S_HUBARR, lv::kPlanWords * (nh + 1), &a.hub_arrays));
     // pair values of the weight width the super-vertex graph gets (both bound by Sigma)
     const int vb = a.w32 ? 4 : 8;
-    HIPCHK(lv::plan_parts(nullptr, nullptr, a.A, a.list + b.lstart[pf], nh, np, vb, true,
-                          ctx->part_shift, a.hub_arrays, a.partial, ctx->pinned + PIN_HUB, pp, s));
+    int64_t* tot = nullptr;
+    CHK(wst(ctx, S_PLANTOT, 4 * 32, &tot));
+    const int32_t* items = a.list + b.lstart[pf];
+    int64_t* arrs = a.hub_arrays;
+    HIPCHK(lv::plan_parts_batch(nullptr, nullptr, a.A, &items, &nh, 1, np, vb, true,
+                                ctx->part_shift, &arrs, tot, ctx->pinned + PIN_PLANS, &pp, s));
     const int64_t pairs = pp.chunks * lv::part_chunk(vb);
     CHK(wst(ctx, S_PK, pairs, &a.pk));
     CHK(ws(ctx, S_PV, (size_t)pairs * vb, &a.pv));
@@ -1186,12 +1200,14 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     HIPCHK(lv::compose_membership(membership, n0, map, s));
     if (levels && nlev < max_levels) {
       int32_t* lev = levels + (size_t)nlev * (size_t)n0;
-      if (relabelled && n_noarc > 0)
+      if (relabelled && n_noarc > 0) {
+        CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n0 + 1) + 1, &scanp0));
         HIPCHK(lv::canon_membership(n0, membership, np, rep, noarc_before, lflag, live_before,
                                     scanp0, lev, s));
-      else
+      } else {
         HIPCHK(hipMemcpyAsync(lev, membership, sizeof(int32_t) * (size_t)n0,
                               hipMemcpyDeviceToDevice, s));
+      }
       nlev++;
     }
     const bool shrunk = np + (relabelled ? n_noarc : 0) < n_canon;
@@ -1209,9 +1225,11 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
     which ^= 1;
     if (!shrunk) break;
   }
-  if (relabelled && n_noarc > 0)  // back to the method's numbering, in place
+  if (relabelled && n_noarc > 0) {  // back to the method's numbering, in place
+    CHK(wst(ctx, S_SCANP, lv::scan_partial_elems(n0 + 1) + 1, &scanp0));
     HIPCHK(lv::canon_membership(n0, membership, cur.n, rep, noarc_before, lflag, live_before,
                                 scanp0, membership, s));
+  }
   res->n_communities = n_comm;
   res->q_num = to_i128(qnum);
   res->q = q_of(qnum, W);

@@ -123,16 +123,17 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
                        const uint8_t* act, const uint8_t* vclass, int32_t* list,
                        unsigned long long* counts, unsigned long long* host_counts, Buckets& b,
                        hipStream_t s);
-// Two-phase plan for the items items[0 .. nh) (lengths from rs/re, or len[item]) whose keys
-// take at most `cap` distinct values; vb: value bytes; merge: one-chunk items need no phase 2.
-// arrays: kPlanWords * (nh + 1) int64, partial: scan scratch; host_buf: 3 pinned words.
-// Synchronises the stream.
-// shift > 0 (testing) divides the partition size by 2^shift and caps the phase-2 tables so
-// that partitions take several rounds.
-hipError_t plan_parts(const int64_t* rs, const int64_t* re, const int64_t* len,
-                      const int32_t* items, int64_t nh, int64_t cap, int vb, bool merge,
-                      int shift, int64_t* arrays, int64_t* partial,
-                      unsigned long long* host_buf, PartPlan& pp, hipStream_t s);
+// Two-phase plans of K <= 32 item lists in one launch and one read-back. List k holds the items
+// items[k][0 .. nh[k]) (lengths from rs/re, or len[item]) whose keys take at most `cap`
+// distinct values; vb: value bytes; merge: one-chunk items need no phase 2. arrays[k]:
+// kPlanWords * (nh[k] + 1) int64; totals: 4 * K device words; host_buf: 4 * K pinned words.
+// Synchronises the stream. shift > 0 (testing) divides the partition size by 2^shift and caps
+// the phase-2 tables so that partitions take several rounds.
+hipError_t plan_parts_batch(const int64_t* rs, const int64_t* re, const int64_t* len,
+                            const int32_t* const* items, const int64_t* nh, int K, int64_t cap,
+                            int vb, bool merge, int shift, int64_t* const* arrays,
+                            int64_t* totals, unsigned long long* host_buf, PartPlan* pp,
+                            hipStream_t s);
 
 // ---- local-moving iteration
 struct MoveBuffers {

@@ -759,70 +759,164 @@ hipError_t bucket_rows(const int64_t* rs, const int64_t* re, const int64_t* len,
 // of the aggregation, which phase 1 finishes by itself).
 constexpr int64_t kPartBlocksPerItem = 256;
 
-__global__ void k_part_sizes(const int64_t* rs, const int64_t* re, const int64_t* len,
-                             const int32_t* items, int64_t nh, int64_t cap, int vb, int merge,
-                             int shift, int64_t* nck, int64_t* nblk, int64_t* rper,
-                             int64_t* nparts, int64_t* hsz, int64_t* p2) {
+struct PartSizes {
+  int64_t c, R, nblk, P, hsz, p2;
+};
+
+__device__ __forceinline__ PartSizes part_sizes_of(int64_t L, int64_t cap, int vb, int merge,
+                                                   int shift) {
   const int64_t Q = part_chunk(vb);
   const int64_t T = (((int64_t)1 << part_log2h(vb)) / 2) >> shift;
-  for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < nh;
-       h += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t L = item_len(rs, re, len, items[h]);
-    const int64_t c = (L + Q - 1) / Q;
-    const int64_t per = shift ? 4 : kPartBlocksPerItem;  // testing: several chunks per walker
-    const int64_t R = (c + per - 1) / per;
-    const int64_t D = L < cap ? L : cap;
-    int64_t P = 1;
-    if (c > 1)
-      while (P * T < D && P < kMaxParts) P <<= 1;
-    nck[h] = c;
-    rper[h] = R;
-    nblk[h] = (c + R - 1) / R;
-    nparts[h] = P;
-    hsz[h] = c * (P + 1);
-    p2[h] = (merge && c == 1) ? 0 : P;
+  PartSizes z;
+  z.c = (L + Q - 1) / Q;
+  const int64_t per = shift ? 4 : kPartBlocksPerItem;  // testing: several chunks per walker
+  z.R = (z.c + per - 1) / per;
+  const int64_t D = L < cap ? L : cap;
+  z.P = 1;
+  if (z.c > 1)
+    while (z.P * T < D && z.P < kMaxParts) z.P <<= 1;
+  z.nblk = (z.c + z.R - 1) / z.R;
+  z.hsz = z.c * (z.P + 1);
+  z.p2 = (merge && z.c == 1) ? 0 : z.P;
+  return z;
+}
+
+// The plans of up to kPlanBatch item lists in one launch, one 1024-thread workgroup per list:
+// the sizes of k_part_sizes and the four exclusive scans of plan_parts (chunk, walker,
+// partition and bound-row starts), in tiles of 1024 items with a running carry. The four totals
+// of list k go to totals[4k .. 4k + 4).
+constexpr int kPlanBatch = 32;
+constexpr int kPlanBlock = 1024;
+struct PlanBatchArgs {
+  const int64_t* rs;
+  const int64_t* re;
+  const int64_t* len;
+  const int32_t* items[kPlanBatch];
+  int64_t nh[kPlanBatch];
+  int64_t* arrays[kPlanBatch];
+  int64_t* totals;
+  int64_t cap;
+  int vb, merge, shift;
+};
+static_assert(sizeof(PlanBatchArgs) <= 1024, "kernel arguments");
+
+__global__ __launch_bounds__(kPlanBlock) void k_plan_batch(PlanBatchArgs a) {
+  constexpr int NW = kPlanBlock / 64;
+  __shared__ int64_t wtot[4][NW + 1];
+  __shared__ int64_t carry[4];
+  const int k = blockIdx.x;
+  const int64_t nh = a.nh[k];
+  int64_t* arr = a.arrays[k];
+  int64_t* nck = arr;
+  int64_t* nblk = arr + nh;
+  int64_t* hsz = arr + 2 * nh;
+  int64_t* p2 = arr + 3 * nh;
+  int64_t* rper = arr + 4 * nh;
+  int64_t* nparts = arr + 5 * nh;
+  int64_t* st[4] = {arr + 6 * nh, arr + 7 * nh + 1, arr + 8 * nh + 2, arr + 9 * nh + 3};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < 4) carry[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nh; base += kPlanBlock) {  // block-uniform trip count
+    const int64_t h = base + threadIdx.x;
+    int64_t v[4] = {0, 0, 0, 0};
+    if (h < nh) {
+      const PartSizes z = part_sizes_of(item_len(a.rs, a.re, a.len, a.items[k][h]), a.cap, a.vb,
+                                        a.merge, a.shift);
+      nck[h] = z.c;
+      rper[h] = z.R;
+      nblk[h] = z.nblk;
+      nparts[h] = z.P;
+      hsz[h] = z.hsz;
+      p2[h] = z.p2;
+      v[0] = z.c;
+      v[1] = z.nblk;
+      v[2] = z.p2;
+      v[3] = z.hsz;
+    }
+    int64_t inc[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      int64_t x = v[q];
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      inc[q] = x;
+      if (lane == 63) wtot[q][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      int64_t t = 0;
+      for (int w = 0; w < NW; w++) {
+        const int64_t x = wtot[threadIdx.x][w];
+        wtot[threadIdx.x][w] = t;
+        t += x;
+      }
+      wtot[threadIdx.x][NW] = t;
+    }
+    __syncthreads();
+    if (h < nh)
+#pragma unroll
+      for (int q = 0; q < 4; q++) st[q][h] = carry[q] + wtot[q][wave] + inc[q] - v[q];
+    __syncthreads();
+    if (threadIdx.x < 4) carry[threadIdx.x] += wtot[threadIdx.x][NW];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) {
+    st[threadIdx.x][nh] = carry[threadIdx.x];
+    a.totals[4 * k + threadIdx.x] = carry[threadIdx.x];
   }
 }
 
-hipError_t plan_parts(const int64_t* rs, const int64_t* re, const int64_t* len,
-                      const int32_t* items, int64_t nh, int64_t cap, int vb, bool merge,
-                      int shift, int64_t* arrays, int64_t* partial, ull* host_buf,
-                      PartPlan& pp, hipStream_t s) {
-  pp = PartPlan();
-  pp.nh = nh;
-  pp.vb = vb;
-  pp.shift = shift;
-  if (nh <= 0) return hipSuccess;
-  int64_t* nck = arrays;
-  int64_t* nblk = arrays + nh;
-  int64_t* hsz = arrays + 2 * nh;
-  int64_t* p2 = arrays + 3 * nh;
-  pp.rper = arrays + 4 * nh;
-  pp.nparts = arrays + 5 * nh;
-  pp.chunk_start = arrays + 6 * nh;
-  pp.block_start = pp.chunk_start + (nh + 1);
-  pp.part_start = pp.block_start + (nh + 1);
-  pp.hoff_start = pp.part_start + (nh + 1);
-  LV_LAUNCH(k_part_sizes, grid_for(nh), kBlock, 0, s, rs, re, len, items, nh, cap, vb,
-            merge ? 1 : 0, shift, nck, nblk, pp.rper, pp.nparts, hsz, p2);
-  hipError_t e;
-  if ((e = scan_i64(nck, nh, pp.chunk_start, partial, s)) != hipSuccess) return e;
-  if ((e = scan_i64(nblk, nh, pp.block_start, partial, s)) != hipSuccess) return e;
-  if ((e = scan_i64(p2, nh, pp.part_start, partial, s)) != hipSuccess) return e;
-  if ((e = scan_i64(hsz, nh, pp.hoff_start, partial, s)) != hipSuccess) return e;
-  int64_t* const src[4] = {pp.chunk_start + nh, pp.block_start + nh, pp.part_start + nh,
-                           pp.hoff_start + nh};
-  for (int i = 0; i < 4; i++) {
-    e = hipMemcpyAsync(&host_buf[i], src[i], sizeof(int64_t), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
+hipError_t plan_parts_batch(const int64_t* rs, const int64_t* re, const int64_t* len,
+                            const int32_t* const* items, const int64_t* nh, int K, int64_t cap,
+                            int vb, bool merge, int shift, int64_t* const* arrays,
+                            int64_t* totals, ull* host_buf, PartPlan* pp, hipStream_t s) {
+  if (K <= 0 || K > kPlanBatch) return hipErrorInvalidValue;
+  PlanBatchArgs a;
+  a.rs = rs;
+  a.re = re;
+  a.len = len;
+  for (int k = 0; k < kPlanBatch; k++) {
+    a.items[k] = k < K ? items[k] : nullptr;
+    a.nh[k] = k < K ? nh[k] : 0;
+    a.arrays[k] = k < K ? arrays[k] : nullptr;
   }
+  a.totals = totals;
+  a.cap = cap;
+  a.vb = vb;
+  a.merge = merge ? 1 : 0;
+  a.shift = shift;
+  LV_LAUNCH(k_plan_batch, (unsigned)K, kPlanBlock, 0, s, a);
+  hipError_t e = hipMemcpyAsync(host_buf, totals, 4 * K * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  pp.chunks = (int64_t)host_buf[0];
-  pp.blocks = (int64_t)host_buf[1];
-  pp.parts = (int64_t)host_buf[2];
-  pp.hoff_entries = (int64_t)host_buf[3];
+  for (int k = 0; k < K; k++) {
+    PartPlan& p = pp[k];
+    p = PartPlan();
+    p.nh = nh[k];
+    p.vb = vb;
+    p.shift = shift;
+    if (nh[k] <= 0) continue;
+    int64_t* arr = arrays[k];
+    const int64_t n = nh[k];
+    p.rper = arr + 4 * n;
+    p.nparts = arr + 5 * n;
+    p.chunk_start = arr + 6 * n;
+    p.block_start = p.chunk_start + (n + 1);
+    p.part_start = p.block_start + (n + 1);
+    p.hoff_start = p.part_start + (n + 1);
+    p.chunks = (int64_t)host_buf[4 * k];
+    p.blocks = (int64_t)host_buf[4 * k + 1];
+    p.parts = (int64_t)host_buf[4 * k + 2];
+    p.hoff_entries = (int64_t)host_buf[4 * k + 3];
+  }
   return hipSuccess;
 }
+
 
 // =============================================================================================
 // Synchronous local-moving iteration, LDS-table path (rows of up to 1024 arcs).
