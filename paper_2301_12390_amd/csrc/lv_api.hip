@@ -455,8 +455,7 @@ lv_status issue_iteration(lv_ctx* ctx, Phase& ph, bool trace, hipStream_t s, Bat
       HIPCHK(hipStreamWaitEvent(s, ctx->join1[k], 0));
     }
     if (trace) HIPCHK(hipEventRecord(ev[6], s));
-    HIPCHK(lv::reduce_move_partials(ph.b, k, m, s));
-    HIPCHK(lv::apply_moves(ph.b, k, m, s));
+    HIPCHK(lv::apply_moves(ph.b, k, m, s));  // also sums the step's decision records
     if (trace) HIPCHK(hipEventRecord(ev[7], s));
   }
   return LV_OK;

@@ -166,11 +166,11 @@ hipError_t move_fused(const DevGraph& g, const Buckets& b, int cls, const MoveBu
 // class 7, a 1024-thread workgroup per row above).
 hipError_t move_wg(const DevGraph& g, const Buckets& b, int cls, const MoveBuffers& m, bool wide,
                    hipStream_t s);
-// Reduction of the block records of move_fused and move_wg into m.stats (after both).
-hipError_t reduce_move_partials(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s);
 // Hub kernels over the hub rows of vertex class `cls` (plan hp made for those rows).
 hipError_t move_hubs(const DevGraph& g, const Buckets& b, int cls, const PartPlan& pp,
                      const MoveBuffers& m, bool wide, hipStream_t s);
+// The class step's decisions applied to the records, and the block records of move_fused and
+// move_wg summed into m.stats (after all three tiers).
 hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s);
 // Block records the LDS move kernels of class cls write (sizes block_partial).
 int64_t move_lds_blocks(const Buckets& b, int cls, int hub_first);

@@ -1187,34 +1187,6 @@ __global__ __launch_bounds__(kBlock) void k_move_lds(MoveArgs<WT> a) {
   }
 }
 
-// Sum of the move kernels' per-block records into the class step's statistics: [0..1] gain
-// sum, [2] moves, [3] candidate pairs, [4] those of the fused kernel (records < nfused),
-// [5] those of the workgroup kernel.
-__global__ __launch_bounds__(kBlock) void k_reduce_move_partials(const ull* part, int64_t nb,
-                                                                int64_t nfused, ull* stats) {
-  __shared__ u128 red[kBlock / 64];
-  __shared__ ull red64[kBlock / 64];
-  u128 sg = 0;
-  ull sm = 0, sf = 0, sw = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nb;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const ull* p = part + 4 * i;
-    sg += ((u128)p[1] << 64) | p[0];
-    sm += p[2];
-    if (i < nfused) sf += p[3]; else sw += p[3];
-  }
-  sg = block_sum_u128(sg, red);
-  sm = block_sum_u64(sm, red64);
-  sf = block_sum_u64(sf, red64);
-  sw = block_sum_u64(sw, red64);
-  if (threadIdx.x == 0) {
-    if (sg) atomic_add_u128(stats, sg);
-    if (sm) atomicAdd(&stats[2], sm);
-    if (sf + sw) atomicAdd(&stats[3], sf + sw);
-    if (sf) atomicAdd(&stats[4], sf);
-    if (sw) atomicAdd(&stats[5], sw);
-  }
-}
 
 // Workgroup-per-row tier (degree classes 7..9): one 1024-thread workgroup decides one vertex
 // with an LDS table of 2^LOG2H slots (twice the longest row of the class).
@@ -1468,15 +1440,6 @@ static hipError_t move_wg_t(const DevGraph& g, const Buckets& b, int cls, const 
     records += rows;
   }
   return hipSuccess;
-}
-
-hipError_t reduce_move_partials(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s) {
-  const int64_t fused = fused_blocks(b, cls);
-  const int64_t records = move_lds_blocks(b, cls, m.hub_first);
-  if (records == 0) return hipSuccess;
-  LV_LAUNCH(k_reduce_move_partials, grid_for(records, kBlock, 256), kBlock, 0, s,
-            m.block_partial, records, fused, m.stats);
-  return hipGetLastError();
 }
 
 int64_t move_lds_blocks(const Buckets& b, int cls, int hub_first) {
@@ -2028,14 +1991,44 @@ __device__ __forceinline__ int comb_slot(int32_t* keys, int32_t x) {
 // from its old one) and then makes one atomic per community it touched: the movers of a step
 // often join the same few large communities, whose words would otherwise take one atomic per
 // mover. Integer sums commute, so the result is independent of the order of the movers.
+// The same launch also sums the move kernels' per-block records into the class step's
+// statistics, in its first kApplyReduceBlocks workgroups: [0..1] gain sum, [2] moves, [3]
+// candidate pairs, [4] those of the fused kernel (records < nfused), [5] those of the
+// workgroup kernel.
 constexpr int kApplyLog2 = 10;  // 1024 slots for the 2 * kBlock communities of a tile
+constexpr int kApplyReduceBlocks = 256;
 __global__ __launch_bounds__(kBlock) void k_apply_moves(const int32_t* verts, int64_t count,
                                                        const int32_t* tgt, const uint64_t* K,
-                                                       VRec* rec) {
+                                                       VRec* rec, const ull* part, int64_t nb,
+                                                       int64_t nfused, ull* stats) {
   constexpr int S = 1 << kApplyLog2;
   __shared__ int32_t ckey[S];
   __shared__ ull csig[S];
   __shared__ int32_t ccnt[S];
+  __shared__ u128 red[kBlock / 64];
+  __shared__ ull red64[kBlock / 64];
+  const int64_t rblocks = gridDim.x < kApplyReduceBlocks ? gridDim.x : kApplyReduceBlocks;
+  if (nb > 0 && blockIdx.x < rblocks) {  // block-uniform
+    u128 sg = 0;
+    ull sm = 0, sf = 0, sw = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nb; i += rblocks * kBlock) {
+      const ull* p = part + 4 * i;
+      sg += ((u128)p[1] << 64) | p[0];
+      sm += p[2];
+      if (i < nfused) sf += p[3]; else sw += p[3];
+    }
+    sg = block_sum_u128(sg, red);
+    sm = block_sum_u64(sm, red64);
+    sf = block_sum_u64(sf, red64);
+    sw = block_sum_u64(sw, red64);
+    if (threadIdx.x == 0) {
+      if (sg) atomic_add_u128(stats, sg);
+      if (sm) atomicAdd(&stats[2], sm);
+      if (sf + sw) atomicAdd(&stats[3], sf + sw);
+      if (sf) atomicAdd(&stats[4], sf);
+      if (sw) atomicAdd(&stats[5], sw);
+    }
+  }
   // whole workgroups iterate together (the table is shared)
   for (int64_t base = blockIdx.x * (int64_t)kBlock; base < count;
        base += (int64_t)gridDim.x * kBlock) {
@@ -2075,9 +2068,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(const int32_t* verts, in
 hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStream_t s) {
   const int64_t first = b.lstart[kDegClasses * cls];
   const int64_t count = b.lstart[kDegClasses * cls + kDegClasses] - first;
-  if (count <= 0) return hipSuccess;
-  LV_LAUNCH(k_apply_moves, grid_for(count, kBlock, 8192), kBlock, 0, s, m.list + first, count,
-            m.tgt, m.K, (VRec*)m.rec);
+  const int64_t fused = fused_blocks(b, cls);
+  const int64_t records = move_lds_blocks(b, cls, m.hub_first);
+  if (count <= 0 && records == 0) return hipSuccess;
+  const unsigned grid = count > 0 ? grid_for(count, kBlock, 8192)
+                                  : grid_for(records, kBlock, kApplyReduceBlocks);
+  LV_LAUNCH(k_apply_moves, grid, kBlock, 0, s, m.list + first, count, m.tgt, m.K, (VRec*)m.rec,
+            m.block_partial, records, fused, m.stats);
   return hipGetLastError();
 }
 
