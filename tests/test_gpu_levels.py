@@ -19,6 +19,8 @@ from .test_gpu_parity import CORPUS, HUB_IDS, HUBS, IDS, LV_FORCE_WIDE, LV_SMALL
 
 pytestmark = pytest.mark.gpu
 
+LV_COLOR_CLASSES = 0x10
+
 
 @pytest.fixture(scope="module")
 def lv(gpu_device):
@@ -33,6 +35,8 @@ def lv(gpu_device):
 def check_levels(lv, g, flags=0, substeps=8, **kw):
     og = O.Graph.from_csr(g)
     okw = {{"tolerance_exp10": "a", "decline_exp10": "b"}.get(k, k): v for k, v in kw.items()}
+    if flags & LV_COLOR_CLASSES:
+        okw["colour"] = True
     top, ref = O.run(og, "sync", substeps=substeps, levels=True, **okw)
     dg = g.to("cuda:0")
     memb, levels, res = lv.run_levels(dg, flags=flags, substeps=substeps, **kw)
@@ -87,6 +91,34 @@ def test_levels_parameters(lv):
     g = sbm(4000, 40, 8.0, 2.0, seed=9, weights=(1, 16))
     for kw in [dict(tolerance_exp10=0), dict(tolerance_exp10=6, decline_exp10=2)]:
         check_levels(lv, g, **kw)
+
+
+def spread(g, factor, offset, name):
+    # g's vertex v becomes factor * v + offset in a graph of factor * n + offset + 1 vertices:
+    # every other id (id 0 and the last one among them when offset > 0) has no arcs
+    from graphgen import csr_from_arcs
+    off = g.offsets.cpu().numpy().astype(np.int64)
+    src = np.repeat(np.arange(g.n), np.diff(off)) * factor + offset
+    dst = g.indices.cpu().numpy().astype(np.int64) * factor + offset
+    n = g.n * factor + offset + 1
+    return csr_from_arcs(n, torch.from_numpy(src), torch.from_numpy(dst), g.weights.cpu(),
+                         name=name)
+
+
+
+@pytest.mark.parametrize("flags,K", [(0, 1), (0, 8), (LV_COLOR_CLASSES, 8)],
+                         ids=["K1", "K8", "colour"])
+def test_levels_vertices_without_arcs(lv, flags, K):
+    # vertices without arcs leave the working graph after the first aggregation; every level,
+    # the per-pass vertex counts and the final membership stay those of the method's numbering
+    cases = [
+        spread(ring_of_cliques(30, 5), 3, 1, "cliques-x3"),
+        spread(sbm(2000, 20, 8.0, 2.0, seed=7, weights=(1, 9)), 20, 7, "sbm-x20"),
+        spread(ring_of_cliques(8, 5), 1, 3, "cliques-head3"),
+    ]
+    for g in cases:
+        L, res = check_levels(lv, g, flags=flags, substeps=K)
+        assert L.shape[0] >= 1, g.name
 
 
 def test_levels_empty_and_edgeless(lv):
