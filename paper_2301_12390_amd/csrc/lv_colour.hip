@@ -39,7 +39,7 @@ constexpr int kColGroup = 16;
 constexpr int kColBlock = 1024;
 constexpr uint8_t kUncoloured = 0xFF;
 constexpr int kColBatch = 32;          // rounds enqueued between two looks from the host
-constexpr unsigned kColRoundBlocks = 2048;  // largest grid of a short-row round (grid-stride)
+constexpr unsigned kColRoundBlocks = 512;   // largest short-row part of a round (grid-stride)
 constexpr unsigned kColMinBlocks = 8;       // smallest
 constexpr unsigned kColLongBlocks = 256;    // largest grid of a long-row round
 
@@ -94,9 +94,11 @@ __device__ __forceinline__ void append(bool want, int32_t u, int32_t* list, ull*
 }
 
 // Counters of every vertex (groups of kColGroup lanes); rows longer than kColShortRow are
-// counted by k_col_count_long, their ids appended to `longs`.
+// counted by k_col_count_long, their ids appended to `longs`. ready[v] = 1 marks the short-row
+// vertices of round 0's frontier (gathered by k_col_compact: one atomic per wavefront on the
+// frontier counter, for ~10^7 vertices, serialised on that word for ~0.1 s).
 __global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs, ull* nlong,
-                                                     Frontier f) {
+                                                     int32_t* ready) {
   const int lane = threadIdx.x & (kColGroup - 1);
   const int64_t groups = (int64_t)gridDim.x * (kBlock / kColGroup);
   for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kColGroup; v < a.n;
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs,
     if (e - b > kColShortRow) {
       if (lane == 0) {
         a.colour[v] = kUncoloured;
+        ready[v] = 0;
         longs[atomicAdd(nlong, 1ull)] = (int32_t)v;
       }
       continue;
@@ -119,8 +122,48 @@ __global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs,
     if (lane == 0) {
       a.cnt[v] = c;
       a.colour[v] = kUncoloured;
+      ready[v] = c == 0;
     }
-    append(lane == 0 && c == 0, (int32_t)v, f.shorts[0], f.counts);  // round 0's frontier
+  }
+}
+
+// Round 0's short frontier from the ready flags: each workgroup takes kCompactTile vertices,
+// ranks its ready ones (wavefront prefix counts) and claims their list range with one atomic.
+constexpr int kCompactPer = 16;
+constexpr int64_t kCompactTile = (int64_t)kBlock * kCompactPer;
+__global__ __launch_bounds__(kBlock) void k_col_compact(const int32_t* ready, int64_t n,
+                                                       int32_t* list, ull* counter) {
+  __shared__ int wsum[kBlock / 64];
+  __shared__ ull base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t t0 = blockIdx.x * kCompactTile; t0 < n; t0 += (int64_t)gridDim.x * kCompactTile) {
+    const int64_t v0 = t0 + (int64_t)threadIdx.x * kCompactPer;
+    int mine = 0;
+#pragma unroll
+    for (int k = 0; k < kCompactPer; k++) mine += v0 + k < n && ready[v0 + k] ? 1 : 0;
+    int incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < kBlock / 64; w++) {
+        const int x = wsum[w];
+        wsum[w] = tot;
+        tot += x;
+      }
+      base = tot ? atomicAdd(counter, (ull)tot) : 0;
+    }
+    __syncthreads();
+    ull pos = base + wsum[wave] + incl - mine;
+#pragma unroll
+    for (int k = 0; k < kCompactPer; k++)
+      if (v0 + k < n && ready[v0 + k]) list[pos++] = (int32_t)(v0 + k);
+    __syncthreads();
   }
 }
 
@@ -162,13 +205,14 @@ __device__ __forceinline__ void append_ready(const ColArgs& a, bool want, int64_
 
 // Colour one vertex whose higher neighbours are all coloured, with `lanes` threads from
 // `lane`: the colours those neighbours hold (bit mask, OR-reduced by the caller), and the
-// decrements of its lower neighbours' counters. kColUnroll arcs per thread per trip, their
-// loads issued together (the rounds along the priority order's longest chain are bound by
-// this latency).
-constexpr int kColUnroll = 4;
-
+// decrements of its lower neighbours' counters. U arcs per thread per trip, their loads issued
+// together (the rounds along the priority order's longest chain are bound by this latency).
+// U = 4 for both kinds of rows: 16 for long rows measured slower (more registers for the whole
+// round kernel, whose short-row part then holds fewer wavefronts).
+template <int U>
 __device__ __forceinline__ uint32_t colour_scan(const ColArgs& a, int64_t v, int lane, int lanes,
                                                 const Frontier& f, int next) {
+  constexpr int kColUnroll = U;
   const uint64_t pv = vertex_draw(a.pass, local_id(v, a.gid, a.gbase));
   uint32_t used = 0;
   const int64_t b = a.rs[v], e = a.re[v];
@@ -204,31 +248,39 @@ __device__ __forceinline__ uint32_t colour_scan(const ColArgs& a, int64_t v, int
   return used;
 }
 
-// Round r, rows up to kColShortRow: groups of kColGroup lanes over the short frontier. Block 0
-// clears the counters of round r + 2.
-__global__ __launch_bounds__(kBlock) void k_col_round(ColArgs a, Frontier f, int r) {
-  if (blockIdx.x == 0 && threadIdx.x < 2) f.counts[3 * threadIdx.x + (r + 2) % 3] = 0;
-  const int64_t count = (int64_t)f.counts[r % 3];
+// Short-row vertices of round r's frontier, groups of G lanes over the first gs workgroups.
+template <int G>
+__device__ __forceinline__ void col_short(const ColArgs& a, const Frontier& f, int r,
+                                          unsigned gs, int64_t count) {
   const int32_t* list = f.shorts[r & 1];
-  const int lane = threadIdx.x & (kColGroup - 1);
-  const int64_t groups = (int64_t)gridDim.x * (kBlock / kColGroup);
-  for (int64_t t = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kColGroup; t < count;
-       t += groups) {
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t groups = (int64_t)gs * (kColBlock / G);
+  for (int64_t t = (blockIdx.x * (int64_t)kColBlock + threadIdx.x) / G; t < count; t += groups) {
     const int64_t v = list[t];
-    uint32_t used = colour_scan(a, v, lane, kColGroup, f, r + 1);
-    for (int m = kColGroup / 2; m >= 1; m >>= 1) used |= __shfl_xor(used, m, kColGroup);
+    uint32_t used = colour_scan<4>(a, v, lane, G, f, r + 1);
+    for (int m = G / 2; m >= 1; m >>= 1) used |= __shfl_xor(used, m, G);
     if (lane == 0) a.colour[v] = first_fit(used, a.K);
   }
 }
 
-// Round r, long rows: one workgroup per vertex of the long frontier.
-__global__ __launch_bounds__(kColBlock) void k_col_round_long(ColArgs a, Frontier f, int r) {
+// Round r in one launch of kColBlock-thread workgroups: the first gs take the short frontier
+// (groups of kColGroup lanes), the others the long frontier (a workgroup per vertex). Block 0
+// clears the counters of round r + 2.
+__global__ __launch_bounds__(kColBlock) void k_col_round(ColArgs a, Frontier f, int r,
+                                                         unsigned gs) {
   __shared__ uint32_t red[kColBlock / 64];
+  if (blockIdx.x < gs) {  // workgroup-uniform
+    if (blockIdx.x == 0 && threadIdx.x < 2) f.counts[3 * threadIdx.x + (r + 2) % 3] = 0;
+    const int64_t count = (int64_t)f.counts[r % 3];
+    col_short<kColGroup>(a, f, r, gs, count);
+    return;
+  }
   const int64_t count = (int64_t)f.counts[3 + r % 3];
   const int32_t* list = f.longs[r & 1];
-  for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+  const unsigned gl = gridDim.x - gs;
+  for (int64_t t = blockIdx.x - gs; t < count; t += gl) {
     const int64_t v = list[t];
-    uint32_t used = colour_scan(a, v, threadIdx.x, kColBlock, f, r + 1);
+    uint32_t used = colour_scan<4>(a, v, threadIdx.x, kColBlock, f, r + 1);
     for (int m = 32; m >= 1; m >>= 1) used |= __shfl_xor(used, m, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = used;
     __syncthreads();
@@ -254,8 +306,11 @@ hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid
   hipError_t e;
   if ((e = zero_words(cb.counts, 7, s)) != hipSuccess) return e;  // 6 counters + nlong
   ull* nlong = cb.counts + 6;
+  int32_t* ready = cb.shorts + n;  // round 0 appends to shorts[1] only after this is read
   LV_LAUNCH(k_col_count, blocks_for(n, kBlock / kColGroup), kBlock, 0, s, a, cb.all_long, nlong,
-            f);
+            ready);
+  LV_LAUNCH(k_col_compact, blocks_for(n, kCompactTile), kBlock, 0, s, ready, n, f.shorts[0],
+            f.counts);
   if ((e = hipMemcpyAsync(host_words, nlong, sizeof(ull), hipMemcpyDeviceToHost, s)) !=
       hipSuccess)
     return e;
@@ -273,14 +328,12 @@ hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid
     const ull ns = host_words[r % 3], nl = host_words[3 + r % 3];
     if (ns == 0 && nl == 0) break;
     if (r > n + kColBatch) return hipErrorUnknown;  // cannot happen: each round colours a vertex
-    const ull want_s = (ns + kBlock / kColGroup - 1) / (kBlock / kColGroup);
+    const ull want_s = (ns + kColBlock / kColGroup - 1) / (kColBlock / kColGroup);
     const unsigned gs = (unsigned)std::min<ull>(std::max<ull>(want_s, kColMinBlocks),
                                                 kColRoundBlocks);
     const unsigned gl = (unsigned)std::min<ull>(std::max<ull>(nl, 1), kColLongBlocks);
-    for (int k = 0; k < kColBatch; k++, r++) {
-      LV_LAUNCH(k_col_round, gs, kBlock, 0, s, a, f, r);
-      LV_LAUNCH(k_col_round_long, gl, kColBlock, 0, s, a, f, r);
-    }
+    for (int k = 0; k < kColBatch; k++, r++)
+      LV_LAUNCH(k_col_round, gs + gl, kColBlock, 0, s, a, f, r, gs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   *rounds = r;
