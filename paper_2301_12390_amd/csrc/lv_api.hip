@@ -304,7 +304,7 @@ lv_status colour_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   uint8_t* vc = nullptr;
   lv::ColourBuffers cb;
   CHK(wst(ctx, S_VCLASS, n, &vc));
-  CHK(wst(ctx, S_CCNT, n, &cb.cnt));
+  CHK(wst(ctx, S_CCNT, 2 * n, &cb.slot));
   CHK(wst(ctx, S_CFLAG, n, &cb.all_long));
   CHK(wst(ctx, S_CSHORT, 2 * n, &cb.shorts));
   CHK(wst(ctx, S_CLONG, 2 * n, &cb.longs));

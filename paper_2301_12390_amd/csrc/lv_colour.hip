@@ -5,19 +5,30 @@
 //
 // The colouring is first-fit in descending priority order, the priority of a vertex being its
 // 64-bit SplitMix64 draw of the pass (ties cannot occur; they would go to the smaller id),
-// colours 0..K-2, and class K-1 for a vertex that finds all K-1 taken. It is computed the
-// Jones-Plassmann way, in rounds: a vertex is coloured in the round after its last
-// higher-priority neighbour, from the colours of those neighbours. Every higher neighbour is
-// coloured before it and no lower neighbour is, so the result equals the sequential first-fit
-// in priority order, whatever the schedule.
+// colours 0..K-2, and class K-1 for a vertex that finds all K-1 taken. It is computed in
+// rounds, the Jones-Plassmann way with one shortcut: a vertex is coloured in the round after
+// its colour became fixed, which is when its last higher-priority neighbour was coloured, or
+// earlier, when the higher neighbours coloured so far already hold all of 0..K-2. A colour
+// depends on the higher neighbours' colours only, so the result equals the sequential first
+// fit in priority order, whatever the schedule.
 //
-// Per vertex a counter of uncoloured higher-priority neighbours. The vertices whose counter is
-// zero form the frontier of a round; colouring a vertex decrements the counters of its
-// lower-priority neighbours, and the decrement that reaches zero appends that neighbour to the
-// next round's frontier (appends aggregated per wavefront). Rounds are enqueued in batches
-// with no host synchronisation inside a batch: each kernel reads its frontier's size from
-// device memory. Rows of up to kColShortRow arcs take a group of 16 lanes, longer ones a
-// 1024-thread workgroup.
+// Per vertex an 8-byte slot: a counter of uncoloured higher-priority neighbours and a mask of
+// the colours those already coloured hold. Colouring a vertex pushes to each lower-priority
+// neighbour: it ORs its colour into the mask (not the leftover class, which first fit never
+// takes) and decrements the counter. A vertex is ready, and joins the next round's frontier,
+// on whichever comes first of two events: its counter reaches zero (every higher neighbour is
+// coloured, and the mask holds all their colours), or its mask fills up with colours 0..K-2
+// (first fit can only give it the leftover class K-1, whatever the uncoloured higher
+// neighbours take later). The event's thread claims the vertex with bit 31 of the mask, so the
+// later event of a vertex appends nothing. The mask event breaks the long priority chains
+// through high-degree vertices: on R-MAT graphs most of those end in the leftover class, and
+// the rounds drop from thousands to about a hundred. The colour of a frontier vertex is the
+// first fit of its mask: no gather of the neighbours' colours.
+//
+// Frontier appends are staged per workgroup. Rounds are enqueued in batches with no host
+// synchronisation inside a batch: each kernel reads its frontier's size from device memory.
+// Rows of up to kColShortRow arcs take a group of 16 lanes, longer ones a 1024-thread
+// workgroup.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,9 +79,20 @@ struct ColArgs {
   int K;
   const int32_t* gid;
   const int64_t* gbase;
-  int32_t* cnt;      // uncoloured higher-priority neighbours
+  int32_t* slot;     // [2v]: uncoloured higher-priority neighbours; [2v + 1]: their colours
   uint8_t* colour;   // class, kUncoloured before
 };
+
+constexpr uint32_t kClaimed = 0x80000000u;  // mask bit of a vertex appended to a frontier
+
+// Colours 0..K-2 (the mask of a vertex that can only take the leftover class)
+__device__ __forceinline__ uint32_t all_colours(int K) {
+  return K - 1 >= 32 ? 0xffffffffu : (1u << (K - 1)) - 1u;
+}
+
+__device__ __forceinline__ void set_slot(const ColArgs& a, int64_t v, int32_t count) {
+  *reinterpret_cast<int2*>(a.slot + 2 * v) = make_int2(count, 0);
+}
 
 // The frontiers: two alternating lists of each kind (short rows, long rows) and three
 // rotating counters of each kind (round r reads counter r % 3, appends to (r + 1) % 3 and
@@ -93,38 +115,92 @@ __device__ __forceinline__ void append(bool want, int32_t u, int32_t* list, ull*
   if (want) list[base + __popcll(bal & ((1ull << lane) - 1))] = u;
 }
 
+// Appends staged in LDS per workgroup and flushed at its end with one atomic per list: a
+// round's frontier holds ~10^5 vertices, and an atomic per wavefront on the one global counter
+// of a list (serialised at ~10^8 per second) cost ~1 ms a round. Entries past a stage's
+// capacity go straight to the global list.
+constexpr int kStageShort = 4096;
+constexpr int kStageLong = 512;
+
+struct Stage {
+  int32_t* list;   // LDS entries
+  int* count;      // LDS count (may pass cap: the excess went to the global list)
+  int cap;
+};
+
+__device__ __forceinline__ void stage_append(bool want, int32_t u, const Stage& st,
+                                             int32_t* list, ull* counter) {
+  const uint64_t bal = __ballot(want);
+  if (!bal) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)bal) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(st.count, __popcll(bal));
+  base = __shfl(base, leader, 64);
+  const int pos = base + __popcll(bal & ((1ull << lane) - 1));
+  if (want && pos < st.cap) st.list[pos] = u;
+  append(want && pos >= st.cap, u, list, counter);
+}
+
+// Copies a workgroup's staged entries to the global list (after a barrier).
+__device__ __forceinline__ void stage_flush(const Stage& st, int32_t* list, ull* counter,
+                                            ull* base) {
+  const int cnt = min(*st.count, st.cap);
+  if (threadIdx.x == 0) *base = cnt ? atomicAdd(counter, (ull)cnt) : 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) list[*base + i] = st.list[i];
+}
+
 // Counters of every vertex (groups of kColGroup lanes); rows longer than kColShortRow are
-// counted by k_col_count_long, their ids appended to `longs`. ready[v] = 1 marks the short-row
-// vertices of round 0's frontier (gathered by k_col_compact: one atomic per wavefront on the
-// frontier counter, for ~10^7 vertices, serialised on that word for ~0.1 s).
+// counted by k_col_count_long, their ids appended to `longs` (staged per workgroup). ready[v] =
+// 1 marks the short-row vertices of round 0's frontier (gathered by k_col_compact: one atomic
+// per wavefront on the frontier counter, for ~10^7 vertices, serialised on that word for
+// ~0.1 s).
+constexpr int kCountStage = 1024;
+constexpr unsigned kCountBlocks = 8192;
 __global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs, ull* nlong,
                                                      int32_t* ready) {
+  __shared__ int32_t st_long[kCountStage];
+  __shared__ int n_long;
+  __shared__ ull base;
+  if (threadIdx.x == 0) n_long = 0;
+  __syncthreads();
+  const Stage sl{st_long, &n_long, kCountStage};
   const int lane = threadIdx.x & (kColGroup - 1);
   const int64_t groups = (int64_t)gridDim.x * (kBlock / kColGroup);
   for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kColGroup; v < a.n;
        v += groups) {
     const int64_t b = a.rs[v], e = a.re[v];
-    if (e - b > kColShortRow) {
+    const bool is_long = e - b > kColShortRow;
+    stage_append(lane == 0 && is_long, (int32_t)v, sl, longs, nlong);
+    if (is_long) {
       if (lane == 0) {
         a.colour[v] = kUncoloured;
+        set_slot(a, v, 0);  // counted by k_col_count_long
         ready[v] = 0;
-        longs[atomicAdd(nlong, 1ull)] = (int32_t)v;
       }
       continue;
     }
     const uint64_t pv = vertex_draw(a.pass, local_id(v, a.gid, a.gbase));
-    int c = 0;
+    int c = 0;  // higher neighbours + 2^16 * all neighbours (a row here has at most 256 arcs)
     for (int64_t x = b + lane; x < e; x += kColGroup) {
       const int64_t u = a.idx[x];
-      if (u != v && precedes(vertex_draw(a.pass, local_id(u, a.gid, a.gbase)), u, pv, v)) c++;
+      if (u != v)
+        c += precedes(vertex_draw(a.pass, local_id(u, a.gid, a.gbase)), u, pv, v) ? 0x10001
+                                                                                  : 0x10000;
     }
     for (int m = kColGroup / 2; m >= 1; m >>= 1) c += __shfl_xor(c, m, kColGroup);
     if (lane == 0) {
-      a.cnt[v] = c;
-      a.colour[v] = kUncoloured;
-      ready[v] = c == 0;
+      // no neighbour: first fit over nothing is colour 0, with no push to make, so such a
+      // vertex stays out of the frontier (on R-MAT s25 half the vertices)
+      const bool alone = c == 0;
+      set_slot(a, v, c & 0xffff);
+      a.colour[v] = alone ? 0 : kUncoloured;
+      ready[v] = !alone && (c & 0xffff) == 0;
     }
   }
+  __syncthreads();
+  stage_flush(sl, longs, nlong, &base);
 }
 
 // Round 0's short frontier from the ready flags: each workgroup takes kCompactTile vertices,
@@ -183,7 +259,7 @@ __global__ __launch_bounds__(kColBlock) void k_col_count_long(ColArgs a, const i
   if (threadIdx.x == 0) {
     int t = 0;
     for (int i = 0; i < kColBlock / 64; i++) t += red[i];
-    a.cnt[v] = t;
+    a.slot[2 * v] = t;
     if (t == 0) f.longs[0][atomicAdd(f.counts + 3, 1ull)] = (int32_t)v;
   }
 }
@@ -191,75 +267,69 @@ __global__ __launch_bounds__(kColBlock) void k_col_count_long(ColArgs a, const i
 // First fit over the colours `used` (bit k: colour k held by a higher neighbour): the smallest
 // free colour below K-1, else the leftover class K-1.
 __device__ __forceinline__ uint8_t first_fit(uint32_t used, int K) {
-  const uint32_t avail = ~used & (K - 1 >= 32 ? 0xffffffffu : ((1u << (K - 1)) - 1u));
+  const uint32_t avail = ~used & all_colours(K);
   return avail ? (uint8_t)__ffs(avail) - 1 : (uint8_t)(K - 1);
 }
 
-// Appends a vertex whose counter reached zero to the frontier of round `next`.
+// Appends a ready vertex (`want`) to the frontier of round `next`.
 __device__ __forceinline__ void append_ready(const ColArgs& a, bool want, int64_t u,
-                                             const Frontier& f, int next) {
+                                             const Frontier& f, int next, const Stage& ss,
+                                             const Stage& sl) {
   const bool lng = want && a.re[u] - a.rs[u] > kColShortRow;
-  append(want && !lng, (int32_t)u, f.shorts[next & 1], f.counts + next % 3);
-  append(lng, (int32_t)u, f.longs[next & 1], f.counts + 3 + next % 3);
+  stage_append(want && !lng, (int32_t)u, ss, f.shorts[next & 1], f.counts + next % 3);
+  stage_append(lng, (int32_t)u, sl, f.longs[next & 1], f.counts + 3 + next % 3);
 }
 
-// Colour one vertex whose higher neighbours are all coloured, with `lanes` threads from
-// `lane`: the colours those neighbours hold (bit mask, OR-reduced by the caller), and the
-// decrements of its lower neighbours' counters. U arcs per thread per trip, their loads issued
-// together (the rounds along the priority order's longest chain are bound by this latency).
-// U = 4 for both kinds of rows: 16 for long rows measured slower (more registers for the whole
-// round kernel, whose short-row part then holds fewer wavefronts).
+// Colours frontier vertex v and pushes to its lower neighbours, with `lanes` threads from
+// `lane`. U arcs per thread per trip, their loads and atomics issued together. U = 4 for both kinds of rows:
+// 16 for long rows measured slower (more registers for the whole round kernel, whose short-row
+// part then holds fewer wavefronts).
 template <int U>
-__device__ __forceinline__ uint32_t colour_scan(const ColArgs& a, int64_t v, int lane, int lanes,
-                                                const Frontier& f, int next) {
-  constexpr int kColUnroll = U;
+__device__ __forceinline__ void colour_push(const ColArgs& a, int64_t v, int lane, int lanes,
+                                            const Frontier& f, int next, const Stage& ss,
+                                            const Stage& sl) {
+  const uint8_t c = first_fit(a.slot[2 * v + 1], a.K);
+  if (lane == 0) a.colour[v] = c;
+  const uint32_t bit = c < a.K - 1 ? 1u << c : 0u;
+  const uint32_t full = all_colours(a.K);
   const uint64_t pv = vertex_draw(a.pass, local_id(v, a.gid, a.gbase));
-  uint32_t used = 0;
   const int64_t b = a.rs[v], e = a.re[v];
-  for (int64_t x0 = b; x0 < e; x0 += (int64_t)lanes * kColUnroll) {
-    int64_t u[kColUnroll];
-    bool higher[kColUnroll], lower[kColUnroll];
+  for (int64_t x0 = b; x0 < e; x0 += (int64_t)lanes * U) {
+    int64_t u[U];
 #pragma unroll
-    for (int k = 0; k < kColUnroll; k++) {
+    for (int k = 0; k < U; k++) {
       const int64_t x = x0 + (int64_t)k * lanes + lane;
       u[k] = x < e ? a.idx[x] : v;
     }
+    bool lower[U];
 #pragma unroll
-    for (int k = 0; k < kColUnroll; k++) {
-      const bool other = u[k] != v;
-      const bool h =
-          other && precedes(vertex_draw(a.pass, local_id(u[k], a.gid, a.gbase)), u[k], pv, v);
-      higher[k] = h;
-      lower[k] = other && !h;
-    }
-    uint8_t cu[kColUnroll];
-    bool ready[kColUnroll];
+    for (int k = 0; k < U; k++)
+      lower[k] = u[k] != v &&
+                 precedes(pv, v, vertex_draw(a.pass, local_id(u[k], a.gid, a.gbase)), u[k]);
+    // A plain read of the slot first: a push to a claimed vertex changes nothing (its colour
+    // is fixed), and neither does an OR of a colour the mask holds. Bits are only ever set while
+    // the colouring runs, so a stale read just skips less.
+    int2 st[U];
 #pragma unroll
-    for (int k = 0; k < kColUnroll; k++) {
-      cu[k] = higher[k] ? a.colour[u[k]] : kUncoloured;
-      ready[k] = lower[k] ? atomicSub(&a.cnt[u[k]], 1) == 1 : false;
+    for (int k = 0; k < U; k++)
+      st[k] = lower[k] ? *reinterpret_cast<const int2*>(a.slot + 2 * u[k]) : make_int2(0, kClaimed);
+    uint32_t was[U];
+    int32_t left[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      const uint32_t m = (uint32_t)st[k].y;
+      const bool live = !(m & kClaimed);
+      was[k] = live && (bit & ~m) ? atomicOr((uint32_t*)a.slot + 2 * u[k] + 1, bit) : full;
+      left[k] = live ? atomicSub(a.slot + 2 * u[k], 1) : 0;
     }
 #pragma unroll
-    for (int k = 0; k < kColUnroll; k++) {
-      if (cu[k] < a.K - 1) used |= 1u << cu[k];
-      append_ready(a, ready[k], u[k], f, next);
+    for (int k = 0; k < U; k++) {
+      // the counter's last decrement, or the colour that completes the mask
+      bool ready = left[k] == 1 || ((was[k] & full) != full && ((was[k] | bit) & full) == full);
+      if (ready)
+        ready = !(atomicOr((uint32_t*)a.slot + 2 * u[k] + 1, kClaimed) & kClaimed);
+      append_ready(a, ready, u[k], f, next, ss, sl);
     }
-  }
-  return used;
-}
-
-// Short-row vertices of round r's frontier, groups of G lanes over the first gs workgroups.
-template <int G>
-__device__ __forceinline__ void col_short(const ColArgs& a, const Frontier& f, int r,
-                                          unsigned gs, int64_t count) {
-  const int32_t* list = f.shorts[r & 1];
-  const int lane = threadIdx.x & (G - 1);
-  const int64_t groups = (int64_t)gs * (kColBlock / G);
-  for (int64_t t = (blockIdx.x * (int64_t)kColBlock + threadIdx.x) / G; t < count; t += groups) {
-    const int64_t v = list[t];
-    uint32_t used = colour_scan<4>(a, v, lane, G, f, r + 1);
-    for (int m = G / 2; m >= 1; m >>= 1) used |= __shfl_xor(used, m, G);
-    if (lane == 0) a.colour[v] = first_fit(used, a.K);
   }
 }
 
@@ -268,29 +338,33 @@ __device__ __forceinline__ void col_short(const ColArgs& a, const Frontier& f, i
 // clears the counters of round r + 2.
 __global__ __launch_bounds__(kColBlock) void k_col_round(ColArgs a, Frontier f, int r,
                                                          unsigned gs) {
-  __shared__ uint32_t red[kColBlock / 64];
+  __shared__ int32_t st_short[kStageShort], st_long[kStageLong];
+  __shared__ int n_short, n_long;
+  __shared__ ull base;
+  if (threadIdx.x == 0) n_short = n_long = 0;
+  __syncthreads();
+  const Stage ss{st_short, &n_short, kStageShort}, sl{st_long, &n_long, kStageLong};
+  const int next = r + 1;
   if (blockIdx.x < gs) {  // workgroup-uniform
     if (blockIdx.x == 0 && threadIdx.x < 2) f.counts[3 * threadIdx.x + (r + 2) % 3] = 0;
     const int64_t count = (int64_t)f.counts[r % 3];
-    col_short<kColGroup>(a, f, r, gs, count);
-    return;
+    const int32_t* list = f.shorts[r & 1];
+    const int lane = threadIdx.x & (kColGroup - 1);
+    const int64_t groups = (int64_t)gs * (kColBlock / kColGroup);
+    for (int64_t t = (blockIdx.x * (int64_t)kColBlock + threadIdx.x) / kColGroup; t < count;
+         t += groups)
+      colour_push<4>(a, list[t], lane, kColGroup, f, next, ss, sl);
+  } else {
+    const int64_t count = (int64_t)f.counts[3 + r % 3];
+    const int32_t* list = f.longs[r & 1];
+    const unsigned gl = gridDim.x - gs;
+    for (int64_t t = blockIdx.x - gs; t < count; t += gl)
+      colour_push<4>(a, list[t], threadIdx.x, kColBlock, f, next, ss, sl);
   }
-  const int64_t count = (int64_t)f.counts[3 + r % 3];
-  const int32_t* list = f.longs[r & 1];
-  const unsigned gl = gridDim.x - gs;
-  for (int64_t t = blockIdx.x - gs; t < count; t += gl) {
-    const int64_t v = list[t];
-    uint32_t used = colour_scan<4>(a, v, threadIdx.x, kColBlock, f, r + 1);
-    for (int m = 32; m >= 1; m >>= 1) used |= __shfl_xor(used, m, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = used;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t u = 0;
-      for (int i = 0; i < kColBlock / 64; i++) u |= red[i];
-      a.colour[v] = first_fit(u, a.K);
-    }
-    __syncthreads();
-  }
+  __syncthreads();
+  stage_flush(ss, f.shorts[next & 1], f.counts + next % 3, &base);
+  __syncthreads();
+  stage_flush(sl, f.longs[next & 1], f.counts + 3 + next % 3, &base);
 }
 
 }  // namespace
@@ -300,15 +374,16 @@ hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid
                           uint8_t* colour, int* rounds, hipStream_t s) {
   *rounds = 0;
   const int64_t n = g.n;
+  if (K < 2 || K > 32) return hipErrorInvalidValue;  // K = 1 is one class, no colouring
   if (n <= 0) return hipSuccess;
-  ColArgs a{g.rs, g.re, g.idx, n, pass, K, gid, gbase, cb.cnt, colour};
+  ColArgs a{g.rs, g.re, g.idx, n, pass, K, gid, gbase, cb.slot, colour};
   Frontier f{{cb.shorts, cb.shorts + n}, {cb.longs, cb.longs + n}, cb.counts};
   hipError_t e;
   if ((e = zero_words(cb.counts, 7, s)) != hipSuccess) return e;  // 6 counters + nlong
   ull* nlong = cb.counts + 6;
   int32_t* ready = cb.shorts + n;  // round 0 appends to shorts[1] only after this is read
-  LV_LAUNCH(k_col_count, blocks_for(n, kBlock / kColGroup), kBlock, 0, s, a, cb.all_long, nlong,
-            ready);
+  LV_LAUNCH(k_col_count, std::min(blocks_for(n, kBlock / kColGroup), kCountBlocks), kBlock, 0, s,
+            a, cb.all_long, nlong, ready);
   LV_LAUNCH(k_col_compact, blocks_for(n, kCompactTile), kBlock, 0, s, ready, n, f.shorts[0],
             f.counts);
   if ((e = hipMemcpyAsync(host_words, nlong, sizeof(ull), hipMemcpyDeviceToHost, s)) !=

@@ -282,7 +282,8 @@ hipError_t part_offset_labels(int32_t* lab, int64_t n, const int32_t* gid, const
 
 // ---- colour classes (lv_colour.hip)
 struct ColourBuffers {
-  int32_t* cnt = nullptr;       // [n] uncoloured higher-priority neighbours
+  int32_t* slot = nullptr;      // [2n] per vertex: uncoloured higher-priority neighbours, and
+                                //   the mask of the colours the coloured ones hold
   int32_t* all_long = nullptr;  // [n] vertices with long rows
   int32_t* shorts = nullptr;    // [2n] two alternating frontiers of short-row vertices
   int32_t* longs = nullptr;     // [2n] two alternating frontiers of long-row vertices

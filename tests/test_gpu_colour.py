@@ -40,7 +40,51 @@ def test_colouring(lv, g, K):
         c, rounds = lv.colour_classes(dg, p, K)
         torch.cuda.synchronize()
         assert np.array_equal(c.cpu().numpy().astype(np.int32), O.colour_classes(og, p, K)), p
-        assert g.nnz == 0 or rounds >= 1
+        # vertices without a neighbour take colour 0 in the counting pass; any other vertex
+        # is coloured by a round
+        assert rounds >= (1 if has_neighbour(g) else 0)
+
+
+def has_neighbour(g):
+    off = g.offsets.cpu().numpy().astype(np.int64)
+    src = np.repeat(np.arange(g.n), np.diff(off))
+    return bool((g.indices.cpu().numpy().astype(np.int64) != src).any())
+
+
+def isolated_mix(seed):
+    # an Erdos-Renyi graph whose vertex v becomes 3v + 1, plus self loops on every fifth other
+    # vertex: a third of the ids hold arcs, the rest none or only a self loop
+    from graphgen import csr_from_arcs, erdos_renyi
+    base = erdos_renyi(400, 0.015, seed=seed, weights=(1, 5))
+    off = base.offsets.numpy().astype(np.int64)
+    src = np.repeat(np.arange(base.n), np.diff(off)) * 3 + 1
+    dst = base.indices.numpy().astype(np.int64) * 3 + 1
+    n = base.n * 3 + 2
+    loops = np.array([v for v in range(0, n, 5) if v % 3 != 1], np.int64)
+    src = np.concatenate([src, loops])
+    dst = np.concatenate([dst, loops])
+    w = torch.cat([base.weights, torch.full((len(loops),), 2, dtype=base.weights.dtype)])
+    return csr_from_arcs(n, torch.from_numpy(src), torch.from_numpy(dst), w,
+                         name=f"isolated-mix-{seed}")
+
+
+@pytest.mark.parametrize("K", [2, 8, 32])
+def test_colouring_vertices_without_neighbours(lv, K):
+    for seed in (1, 2):
+        g = isolated_mix(seed)
+        og = O.Graph.from_csr(g)
+        for p in (0, 2):
+            c, rounds = lv.colour_classes(g.to("cuda:0"), p, K)
+            torch.cuda.synchronize()
+            assert np.array_equal(c.cpu().numpy().astype(np.int32), O.colour_classes(og, p, K))
+            assert rounds >= 1
+    # only self loops: every vertex is colour 0, and no round runs
+    from graphgen import csr_from_arcs
+    v = torch.arange(50, dtype=torch.int64)
+    g = csr_from_arcs(50, v, v, torch.ones(50, dtype=torch.int64), name="loops-only")
+    c, rounds = lv.colour_classes(g.to("cuda:0"), 0, K)
+    torch.cuda.synchronize()
+    assert (c.cpu() == 0).all() and rounds == 0
 
 
 @pytest.mark.parametrize("gi", [0, 1], ids=HUB_IDS)

@@ -5,6 +5,8 @@
 * networkx's greedy colouring with the same vertex order (first-fit, no cap);
 * a Jones-Plassmann simulation in rounds (a vertex is coloured once every higher-priority
   neighbour is), written here independently, equals the sequential definition;
+* so does the shortcut the GPU's rounds take (a vertex is also coloured, with the leftover
+  class, once its coloured higher-priority neighbours hold all of 0..K-2), in fewer rounds;
 * invariants: classes 0..K-2 are independent sets, first-fit (every smaller colour is held by a
   higher-priority neighbour), the leftover class only when all K-1 colours are taken.
 """
@@ -56,6 +58,44 @@ def jp_rounds(g, p, K):
             col[v] = next((c for c in range(K - 1) if c not in used), K - 1)
         rounds += 1
     return np.array(col, dtype=np.int32), rounds
+
+
+def jp_rounds_shortcut(g, p, K):
+    """Rounds with the shortcut: a vertex is ready when its higher-priority neighbours are all
+    coloured, or when those coloured so far hold all of 0..K-2; a ready vertex takes the first
+    fit over its coloured higher-priority neighbours' colours (capped as above)."""
+    n = g.n
+    key = [(prio(p, v), -v) for v in range(n)]
+    higher = [[u for u in neighbours(g, v) if key[u] > key[v]] for v in range(n)]
+    col = [-1] * n
+    rounds = 0
+    while any(c < 0 for c in col):
+        ready = []
+        for v in range(n):
+            if col[v] >= 0:
+                continue
+            held = {col[u] for u in higher[v] if col[u] >= 0}
+            if all(col[u] >= 0 for u in higher[v]) or set(range(K - 1)) <= held:
+                ready.append((v, held))
+        assert ready, "the priority order has no cycle"
+        for v, held in ready:
+            col[v] = next((c for c in range(K - 1) if c not in held), K - 1)
+        rounds += 1
+    return np.array(col, dtype=np.int32), rounds
+
+
+@pytest.mark.parametrize("K", [2, 4, 8, 32])
+def test_shortcut_rounds_equal_sequential_first_fit(K):
+    fewer = 0
+    for gi, g in enumerate(graphs()):
+        for p in (0, 3):
+            got, r_short = jp_rounds_shortcut(g, p, K)
+            assert np.array_equal(O.colour_classes(g, p, K), got), (gi, p, K)
+            _, r_plain = jp_rounds(g, p, K)
+            assert r_short <= r_plain
+            fewer += r_short < r_plain
+    if K <= 8:
+        assert fewer > 0  # the shortcut fires on these graphs
 
 
 @pytest.mark.parametrize("K", [2, 4, 8, 32])

@@ -100,6 +100,7 @@ def battery():
     from . import test_oracle_colour as PC
     for K in (2, 8, 32):
         PC.test_matches_jones_plassmann_rounds(K)
+        PC.test_shortcut_rounds_equal_sequential_first_fit(K)
     from . import test_oracle_partition as PT
     PT.test_two_triangles_hand_derived()
     PT.test_components_as_parts(8)
