@@ -30,7 +30,7 @@ enum SlotId {
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
   S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_CFM, S_LFLAG, S_NOARC,
-  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_COUNT_SLOTS
+  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_LAB, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -1103,11 +1103,14 @@ static lv_status run_single(lv_ctx* ctx, const lv_graph* g, const lv_params* p,
   int64_t* live_before = nullptr;
   int64_t* scanp0 = nullptr;
   for (int pass = 0; pass < p->max_passes; pass++) {
-    HIPCHK(lv::init_state(cur.n, K, rec, s));
+    int32_t* lab = nullptr;  // the records' communities, copied where the copy stays in cache
+    if (cur.n <= lv::kLabMaxVertices) CHK(wst(ctx, S_LAB, cur.n, &lab));
+    HIPCHK(lv::init_state(cur.n, K, rec, lab, s));
     Phase ph;
     ph.g = cur;
     ph.m.K = K;
     ph.m.rec = rec;
+    ph.m.lab = lab;
     ph.m.W = W;
     ph.wide = (p->flags & LV_FORCE_WIDE) || !((u128)W * maxK < ((u128)1 << 63));
     ph.classes = p->substeps;
@@ -1400,7 +1403,7 @@ lv_status louvain_run_batched(lv_ctx* ctx, const lv_graph* packed, int32_t G,
     bool any = false;
     for (int32_t g = 0; g < G; g++) any = any || !done[g];
     if (!any) break;
-    HIPCHK(lv::init_state(cur.n, K, rec, s));
+    HIPCHK(lv::init_state(cur.n, K, rec, nullptr, s));
     Phase ph;
     ph.g = cur;
     ph.m.K = K;

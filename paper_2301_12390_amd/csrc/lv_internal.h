@@ -109,7 +109,7 @@ hipError_t row_sums(const DevGraph& g, uint64_t* K, int64_t* tile_rows, hipStrea
 int64_t row_sum_tiles(int64_t nnz);
 // Community state as 16-byte records {C[x], csize[x], Sigma[x]} (see lv_device.h).
 constexpr size_t kRecBytes = 16;
-hipError_t init_state(int64_t n, const uint64_t* K, void* rec, hipStream_t s);
+hipError_t init_state(int64_t n, const uint64_t* K, void* rec, int32_t* lab, hipStream_t s);
 hipError_t pack_state(int64_t n, const int32_t* C, const uint64_t* Sig, const int32_t* csize,
                       void* rec, hipStream_t s);
 hipError_t unpack_state(int64_t n, const void* rec, int32_t* C, uint64_t* Sig, int32_t* csize,
@@ -139,6 +139,8 @@ hipError_t plan_parts_batch(const int64_t* rs, const int64_t* re, const int64_t*
 struct MoveBuffers {
   const uint64_t* K = nullptr;
   void* rec = nullptr;                  // [n] community state records
+  int32_t* lab = nullptr;               // [n] copy of every record's community, or null
+                                        //   (graphs of up to kLabMaxVertices vertices)
   uint64_t W = 0;
   const int32_t* list = nullptr;
   int32_t* tgt = nullptr;               // [n] decision of every vertex of the class step
@@ -154,6 +156,11 @@ struct MoveBuffers {
   int hub_first = 10;                     // first degree class on the two-phase hub path
   GraphSet gs;                            // batch of graphs, if any
 };
+
+// Largest graph whose move kernels read neighbour communities from a 4-byte copy (8 MiB) instead
+// of the 16-byte records: larger copies no longer stay in the caches, and measured slower
+// (R-MAT s22's pass 0, 4.2M vertices: 22.8 against 22.6 ms per run; s25's pass 0 slower too).
+constexpr int64_t kLabMaxVertices = (int64_t)1 << 21;
 
 // First degree class that takes the two-phase hub path, given the largest LDS allocation a
 // workgroup may make and the table value width (wide: 8-byte values).
