@@ -63,7 +63,7 @@ constexpr int PIN_PLANS = 2048;   // host: 4 totals per list of a batched two-ph
 constexpr int PIN_WORDS = 2048 + 4 * 32;
 constexpr int DEG = 12;           // degree classes per vertex class (list segment stride)
 constexpr int STATS_WORDS = 512;
-constexpr int kEvStep = 8;  // timing events per class step
+constexpr int kEvStep = 5;  // timing events per class step
 constexpr int kEvents = kEvStep * 32 + 2;
 constexpr int EV_AGG = kEvStep * 32;
 
@@ -79,6 +79,7 @@ struct lv_ctx {
   size_t bpin_bytes = 0;
   ull* pinned = nullptr;  // host-pinned words for small read-backs
   hipEvent_t ev[kEvents] = {};  // kEvStep per class step, then 2 for aggregation
+  bool step_par[32] = {};       // class step k forked its tiers onto the side streams
   // the move tiers of a class step run concurrently: the workgroup tier on side[0], the hub
   // path on side[1], forked from and joined back into the caller's stream
   hipStream_t side[2] = {};
@@ -439,24 +440,26 @@ lv_status issue_iteration(lv_ctx* ctx, Phase& ph, bool trace, hipStream_t s, Bat
       HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
       HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
     }
+    // timing (trace): a start event, one after each tier on its own stream, one after the
+    // update; a tier starts at the fork when the tiers are concurrent, else where the one
+    // before it ended (few events: each is a marker on its queue, a bubble before the next
+    // kernel, and five per class step already cost a run ~3 ms of ~200)
     if (trace) HIPCHK(hipEventRecord(ev[0], s));
     HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
     if (trace) HIPCHK(hipEventRecord(ev[1], s));
-    if (trace) HIPCHK(hipEventRecord(ev[2], s1));
     HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
-    if (trace) HIPCHK(hipEventRecord(ev[3], s1));
-    if (trace) HIPCHK(hipEventRecord(ev[4], s2));
+    if (trace) HIPCHK(hipEventRecord(ev[2], s1));
     HIPCHK(lv::move_hubs(ph.g, ph.b, k, ph.hp[k], m, ph.wide, s2));
-    if (trace) HIPCHK(hipEventRecord(ev[5], s2));
+    if (trace) HIPCHK(hipEventRecord(ev[3], s2));
     if (par) {
       HIPCHK(hipEventRecord(ctx->join0[k], s1));
       HIPCHK(hipEventRecord(ctx->join1[k], s2));
       HIPCHK(hipStreamWaitEvent(s, ctx->join0[k], 0));
       HIPCHK(hipStreamWaitEvent(s, ctx->join1[k], 0));
     }
-    if (trace) HIPCHK(hipEventRecord(ev[6], s));
     HIPCHK(lv::apply_moves(ph.b, k, m, s));  // also sums the step's decision records
-    if (trace) HIPCHK(hipEventRecord(ev[7], s));
+    if (trace) HIPCHK(hipEventRecord(ev[4], s));
+    ctx->step_par[k] = par;
   }
   return LV_OK;
 }
@@ -566,15 +569,22 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
     if (trace) {
       for (int k = 0; k < K; k++) {
         hipEvent_t* ev = ctx->ev + kEvStep * k;
-        float x = 0;
-        HIPCHK(hipEventElapsedTime(&x, ev[0], ev[1]));
-        t_fused += x;
-        HIPCHK(hipEventElapsedTime(&x, ev[2], ev[3]));
-        t_wg += x;
-        HIPCHK(hipEventElapsedTime(&x, ev[4], ev[5]));
-        t_hub += x;
-        HIPCHK(hipEventElapsedTime(&x, ev[6], ev[7]));
-        t_upd += x;
+        float f = 0, w = 0, h = 0, e = 0;  // ends of the tiers and of the step, from the start
+        HIPCHK(hipEventElapsedTime(&f, ev[0], ev[1]));
+        HIPCHK(hipEventElapsedTime(&w, ev[0], ev[2]));
+        HIPCHK(hipEventElapsedTime(&h, ev[0], ev[3]));
+        HIPCHK(hipEventElapsedTime(&e, ev[0], ev[4]));
+        if (ctx->step_par[k]) {  // concurrent: all three start at the fork
+          t_fused += f;
+          t_wg += w;
+          t_hub += h;
+          t_upd += e - std::max(f, std::max(w, h));
+        } else {                 // one stream: fused, wg, hub, update in turn
+          t_fused += f;
+          t_wg += w - f;
+          t_hub += h - w;
+          t_upd += e - h;
+        }
       }
     }
     i128 S = 0;
@@ -835,8 +845,11 @@ lv_status louvain_ctx_create(int device, uint64_t hbm_budget_bytes, lv_ctx** out
     louvain_ctx_destroy(ctx);
     return LV_EHIP;
   }
+  // Timing events only: no system-scope fence when they are recorded (with one, every record
+  // wrote back the caches, which cost an R-MAT s25 run ~4 ms of its ~200). Nothing reads device
+  // data through them; every read-back has its own copy and stream synchronisation.
   for (int i = 0; i < kEvents; i++) {
-    if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
+    if (hipEventCreateWithFlags(&ctx->ev[i], hipEventDisableSystemFence) != hipSuccess) {
       louvain_ctx_destroy(ctx);
       return LV_EHIP;
     }

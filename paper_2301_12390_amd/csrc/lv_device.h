@@ -174,8 +174,6 @@ __device__ __forceinline__ bool better(T g, int32_t c, T bg, int32_t bc) {
   return g > bg || (g == bg && c < bc);
 }
 
-// Marks a table slot whose community's Sigma was not seen with the key (Sigma <= W <= 2^62).
-constexpr unsigned long long kNoSig = ~0ull;
 
 // ---------------------------------------------------------------------------------------------
 // Open-addressing tables (linear probing, multiplicative hashing on the top bits).

@@ -933,17 +933,16 @@ hipError_t plan_parts_batch(const int64_t* rs, const int64_t* re, const int64_t*
 // Adds arcs e0 + lane, e0 + lane + S, ... (< e1) of vertex v's row to an LDS table keyed by the
 // neighbour's community, self-loops skipped. Each lane first issues U independent index loads and
 // U independent record gathers, then makes its U table updates, so that U gathers per lane are
-// in flight instead of one. With SIGC, a neighbour that labels its own community also stores that
-// community's Sigma in sigs. With lab (a 4-byte copy of every record's community, kept for
+// in flight instead of one. With lab (a 4-byte copy of every record's community, kept for
 // graphs of up to kLabMaxVertices vertices), the community comes from lab instead of the
 // 16-byte record: the gathers then fall in a table a quarter the size, which the caches hold
 // (R-MAT s25's pass 1, 1.85M vertices: its iterations 17.3 -> 15.6 ms), and Sigma comes from
 // the candidate evaluation's own gather. Returns the number of slots this lane claimed.
-template <typename V, typename WT, int U, bool SIGC>
+template <typename V, typename WT, int U>
 __device__ __forceinline__ int accumulate_row(const int32_t* idx, const WT* w, const VRec* rec,
                                               const int32_t* lab, int32_t v, int64_t e0,
                                               int64_t e1, int lane, int S, int32_t* keys,
-                                              V* vals, ull* sigs, int log2h) {
+                                              V* vals, int log2h) {
   int fresh = 0;
   for (int64_t e = e0 + lane; e < e1; e += (int64_t)U * S) {
     int32_t j[U];
@@ -954,23 +953,14 @@ __device__ __forceinline__ int accumulate_row(const int32_t* idx, const WT* w, c
       j[u] = eu < e1 ? ld_stream(idx + eu) : v;
       wv[u] = eu < e1 ? (V)ld_stream(w + eu) : (V)0;
     }
-    VRec r[U];
+    int32_t c[U];
 #pragma unroll
-    for (int u = 0; u < U; u++) {
-      if (lab) {
-        r[u].c = j[u] != v ? lab[j[u]] : kEmpty;
-      } else if (SIGC) {
-        if (j[u] != v) r[u] = rec[j[u]];
-      } else {
-        r[u].c = j[u] != v ? rec[j[u]].c : kEmpty;
-      }
-    }
+    for (int u = 0; u < U; u++)
+      c[u] = j[u] == v ? kEmpty : lab ? lab[j[u]] : rec[j[u]].c;
 #pragma unroll
     for (int u = 0; u < U; u++) {
       if (j[u] == v) continue;
-      uint32_t slot;
-      fresh += table_add<V>(keys, vals, log2h, r[u].c, wv[u], &slot);
-      if (SIGC && !lab && r[u].c == j[u]) sigs[slot] = r[u].sig;
+      fresh += table_add<V>(keys, vals, log2h, c[u], wv[u]);
     }
   }
   return fresh;
@@ -1088,8 +1078,7 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
   // lanes per row cover a class's longest row in one round for classes 0..4; rows of classes 5
   // and up take several arcs per lane, gathered together
   constexpr int U = (1 << LOG2H) / 2 > G ? 4 : 1;
-  accumulate_row<V, WT, U, false>(a.idx, a.w, a.rec, a.lab, v, e0, e1, lane, G, gk, gv, nullptr,
-                                  LOG2H);
+  accumulate_row<V, WT, U>(a.idx, a.w, a.rec, a.lab, v, e0, e1, lane, G, gk, gv, LOG2H);
   __syncthreads();
   T bg = Ar::lowest();
   int32_t bc = INT32_MAX;
@@ -1199,11 +1188,11 @@ __global__ __launch_bounds__(kBlock) void k_move_lds(MoveArgs<WT> a) {
 
 
 // Workgroup-per-row tier (degree classes 7..9): one 1024-thread workgroup decides one vertex
-// with an LDS table of 2^LOG2H slots (twice the longest row of the class).
+// with an LDS table of 2^LOG2H slots (twice the longest row of the class). The table has no
+// Sigma cache: with one (8 more bytes per slot, which cost the class-8 kernel half its
+// occupancy), this tier took 32.3 and 13.6 ms per s25 iteration of passes 0 and 1, without it
+// 29.0 and 10.4 ms.
 constexpr int kWgBlock = 1024;
-// LDS a workgroup-tier table may take with its Sigma cache (any device the library accepts has
-// at least part_lds_bytes(4) + 4096 bytes per workgroup)
-constexpr size_t kWgSigLds = 144 * 1024;
 
 template <typename WT>
 struct WgArgs {
@@ -1221,9 +1210,7 @@ struct WgArgs {
   GraphSet gs;
 };
 
-// SIGC: the table also caches Sigma of candidates seen through a neighbour labelling its own
-// community (when the LDS allows the extra 8 bytes per slot).
-template <bool WIDE, typename WT, int LOG2H, bool SIGC>
+template <bool WIDE, typename WT, int LOG2H>
 __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
   typedef Gain<WIDE> Ar;
   typedef typename Ar::T T;
@@ -1237,20 +1224,18 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
   __shared__ ull snc[NW];
   int32_t* keys = (int32_t*)smem;
   V* vals = (V*)(smem + (size_t)H * sizeof(int32_t));
-  ull* sigs = (ull*)(smem + (size_t)H * (sizeof(int32_t) + sizeof(V)));
   const int32_t v = a.rows[blockIdx.x];
   for (int s = threadIdx.x; s < H; s += kWgBlock) {
     keys[s] = kEmpty;
     vals[s] = 0;
-    if (SIGC) sigs[s] = kNoSig;
   }
   __syncthreads();
   uint64_t W = a.W;
   int32_t gr = 0;
   const bool on = gs_vertex(a.gs, v, &W, &gr);
   const int64_t e0 = a.rs[v], e1 = on ? a.re[v] : e0;
-  accumulate_row<V, WT, 4, SIGC>(a.idx, a.w, a.rec, a.lab, v, e0, e1, threadIdx.x, kWgBlock,
-                                 keys, vals, sigs, LOG2H);
+  accumulate_row<V, WT, 4>(a.idx, a.w, a.rec, a.lab, v, e0, e1, threadIdx.x, kWgBlock, keys,
+                           vals, LOG2H);
   __syncthreads();
   const int32_t d = a.rec[v].c;
   const uint64_t Ki = a.K[v];
@@ -1266,8 +1251,7 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
       continue;
     }
     nc++;
-    const ull sc = SIGC ? sigs[s] : kNoSig;
-    const T g = Ar::of(W, kv, Ki, sc != kNoSig ? sc : a.rec[c].sig);
+    const T g = Ar::of(W, kv, Ki, a.rec[c].sig);
     if (better(g, c, bg, bc)) {
       bg = g;
       bc = c;
@@ -1349,17 +1333,16 @@ int hub_first_class(size_t max_lds, bool wide) {
 template <bool WIDE, typename WT, int LOG2H>
 static hipError_t launch_wg(const WgArgs<WT>& a, int64_t rows, hipStream_t s) {
   constexpr size_t vb = sizeof(typename Gain<WIDE>::V);
-  constexpr bool SIGC = ((size_t)1 << LOG2H) * (4 + vb + 8) <= kWgSigLds;
-  constexpr size_t shm = ((size_t)1 << LOG2H) * (4 + vb + (SIGC ? 8 : 0));
+  constexpr size_t shm = ((size_t)1 << LOG2H) * (4 + vb);
   // once per instantiation; a function-local static initialiser is thread-safe, and contexts
   // on different host threads launch these kernels concurrently
   static const bool attr = [] {
-    (void)hipFuncSetAttribute((const void*)k_move_wg<WIDE, WT, LOG2H, SIGC>,
+    (void)hipFuncSetAttribute((const void*)k_move_wg<WIDE, WT, LOG2H>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     return true;
   }();
   (void)attr;
-  LV_LAUNCH((k_move_wg<WIDE, WT, LOG2H, SIGC>), (unsigned)rows, kWgBlock, shm, s, a);
+  LV_LAUNCH((k_move_wg<WIDE, WT, LOG2H>), (unsigned)rows, kWgBlock, shm, s, a);
   return hipGetLastError();
 }
 
@@ -1719,9 +1702,8 @@ struct HubChunk {
     constexpr int Q = part_chunk((int)sizeof(V));
     const int64_t c0 = e0 + k * Q;
     const int64_t c1 = c0 + Q < e1 ? c0 + Q : e1;
-    const int fresh = accumulate_row<V, WT, 4, false>(a->idx, a->w, a->rec, a->lab, v, c0, c1,
-                                                      threadIdx.x,
-                                                      kPartBlock, keys, vals, nullptr, LOG2H);
+    const int fresh = accumulate_row<V, WT, 4>(a->idx, a->w, a->rec, a->lab, v, c0, c1,
+                                               threadIdx.x, kPartBlock, keys, vals, LOG2H);
     if (fresh) atomicAdd(&flags[0], fresh);
   }
   __device__ void operator()(int64_t k, int32_t* keys, V* vals, int* flags) {
