@@ -440,11 +440,12 @@ lv_status issue_iteration(lv_ctx* ctx, Phase& ph, bool trace, hipStream_t s, Bat
       HIPCHK(hipStreamWaitEvent(s1, ctx->fork[k], 0));
       HIPCHK(hipStreamWaitEvent(s2, ctx->fork[k], 0));
     }
-    // timing (trace): a start event, one after each tier on its own stream, one after the
-    // update; a tier starts at the fork when the tiers are concurrent, else where the one
-    // before it ended (few events: each is a marker on its queue, a bubble before the next
-    // kernel, and five per class step already cost a run ~3 ms of ~200)
-    if (trace) HIPCHK(hipEventRecord(ev[0], s));
+    // timing (trace): one event after each tier on its own stream and one after the update,
+    // which is also the next class step's start (class step 0 records its own); a tier starts
+    // at the fork when the tiers are concurrent, else where the one before it ended. Few
+    // events: each is a marker on its queue, a bubble before the next kernel, and five per
+    // class step cost an s25 run ~2 ms of ~200.
+    if (trace && k == 0) HIPCHK(hipEventRecord(ev[0], s));
     HIPCHK(lv::move_fused(ph.g, ph.b, k, m, ph.wide, s));
     if (trace) HIPCHK(hipEventRecord(ev[1], s));
     HIPCHK(lv::move_wg(ph.g, ph.b, k, m, ph.wide, s1));
@@ -569,11 +570,12 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
     if (trace) {
       for (int k = 0; k < K; k++) {
         hipEvent_t* ev = ctx->ev + kEvStep * k;
+        hipEvent_t start = k == 0 ? ev[0] : ctx->ev[kEvStep * (k - 1) + 4];
         float f = 0, w = 0, h = 0, e = 0;  // ends of the tiers and of the step, from the start
-        HIPCHK(hipEventElapsedTime(&f, ev[0], ev[1]));
-        HIPCHK(hipEventElapsedTime(&w, ev[0], ev[2]));
-        HIPCHK(hipEventElapsedTime(&h, ev[0], ev[3]));
-        HIPCHK(hipEventElapsedTime(&e, ev[0], ev[4]));
+        HIPCHK(hipEventElapsedTime(&f, start, ev[1]));
+        HIPCHK(hipEventElapsedTime(&w, start, ev[2]));
+        HIPCHK(hipEventElapsedTime(&h, start, ev[3]));
+        HIPCHK(hipEventElapsedTime(&e, start, ev[4]));
         if (ctx->step_par[k]) {  // concurrent: all three start at the fork
           t_fused += f;
           t_wg += w;
