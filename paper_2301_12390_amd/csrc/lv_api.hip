@@ -311,7 +311,8 @@ lv_status colour_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   CHK(wst(ctx, S_CLONG, 2 * n, &cb.longs));
   CHK(wst(ctx, S_CNLONG, 7, &cb.counts));
   HIPCHK(lv::colour_classes(ph.g, ph.classes, ph.pass, ph.m.gs.gid, ph.m.gs.gbase, cb,
-                            ctx->pinned + PIN_MISC, vc, &ph.colour_rounds, s));
+                            ctx->pinned + PIN_MISC, vc, &ph.colour_rounds, ctx->part_shift != 0,
+                            s));
   ph.vclass = vc;
   return LV_OK;
 }
@@ -1762,6 +1763,7 @@ lv_status louvain_colour_classes(lv_ctx* ctx, const lv_graph* g, int32_t pass, i
   if (pass < 0) return fail(ctx, LV_EINVAL, "pass must be >= 0");
   if (K < 1 || K > lv_max_classes()) return fail(ctx, LV_EINVAL, "K must be in 1..32");
   hipStream_t s = (hipStream_t)stream;
+  ctx->part_shift = 0;
   Phase ph;
   CHK(import_graph(ctx, g, false, s, &ph.g));
   if (ph.g.n > 0 && !classes) return fail(ctx, LV_EINVAL, "classes is NULL");

@@ -118,9 +118,11 @@ __device__ __forceinline__ void append(bool want, int32_t u, int32_t* list, ull*
 // Appends staged in LDS per workgroup and flushed at its end with one atomic per list: a
 // round's frontier holds ~10^5 vertices, and an atomic per wavefront on the one global counter
 // of a list (serialised at ~10^8 per second) cost ~1 ms a round. Entries past a stage's
-// capacity go straight to the global list.
+// capacity go straight to the global list (a testing mode shrinks the capacities to
+// kSmallStage so that this path runs on small graphs).
 constexpr int kStageShort = 4096;
 constexpr int kStageLong = 512;
+constexpr int kSmallStage = 4;
 
 struct Stage {
   int32_t* list;   // LDS entries
@@ -159,13 +161,13 @@ __device__ __forceinline__ void stage_flush(const Stage& st, int32_t* list, ull*
 constexpr int kCountStage = 1024;
 constexpr unsigned kCountBlocks = 8192;
 __global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs, ull* nlong,
-                                                     int32_t* ready) {
+                                                     int32_t* ready, int cap) {
   __shared__ int32_t st_long[kCountStage];
   __shared__ int n_long;
   __shared__ ull base;
   if (threadIdx.x == 0) n_long = 0;
   __syncthreads();
-  const Stage sl{st_long, &n_long, kCountStage};
+  const Stage sl{st_long, &n_long, cap};
   const int lane = threadIdx.x & (kColGroup - 1);
   const int64_t groups = (int64_t)gridDim.x * (kBlock / kColGroup);
   for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kColGroup; v < a.n;
@@ -337,13 +339,14 @@ __device__ __forceinline__ void colour_push(const ColArgs& a, int64_t v, int lan
 // (groups of kColGroup lanes), the others the long frontier (a workgroup per vertex). Block 0
 // clears the counters of round r + 2.
 __global__ __launch_bounds__(kColBlock) void k_col_round(ColArgs a, Frontier f, int r,
-                                                         unsigned gs) {
+                                                         unsigned gs, int cap_short,
+                                                         int cap_long) {
   __shared__ int32_t st_short[kStageShort], st_long[kStageLong];
   __shared__ int n_short, n_long;
   __shared__ ull base;
   if (threadIdx.x == 0) n_short = n_long = 0;
   __syncthreads();
-  const Stage ss{st_short, &n_short, kStageShort}, sl{st_long, &n_long, kStageLong};
+  const Stage ss{st_short, &n_short, cap_short}, sl{st_long, &n_long, cap_long};
   const int next = r + 1;
   if (blockIdx.x < gs) {  // workgroup-uniform
     if (blockIdx.x == 0 && threadIdx.x < 2) f.counts[3 * threadIdx.x + (r + 2) % 3] = 0;
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(kColBlock) void k_col_round(ColArgs a, Frontier f, 
 
 hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid,
                           const int64_t* gbase, const ColourBuffers& cb, ull* host_words,
-                          uint8_t* colour, int* rounds, hipStream_t s) {
+                          uint8_t* colour, int* rounds, bool small_stages, hipStream_t s) {
   *rounds = 0;
   const int64_t n = g.n;
   if (K < 2 || K > 32) return hipErrorInvalidValue;  // K = 1 is one class, no colouring
@@ -382,8 +385,11 @@ hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid
   if ((e = zero_words(cb.counts, 7, s)) != hipSuccess) return e;  // 6 counters + nlong
   ull* nlong = cb.counts + 6;
   int32_t* ready = cb.shorts + n;  // round 0 appends to shorts[1] only after this is read
+  const int cap_count = small_stages ? kSmallStage : kCountStage;
+  const int cap_short = small_stages ? kSmallStage : kStageShort;
+  const int cap_long = small_stages ? kSmallStage : kStageLong;
   LV_LAUNCH(k_col_count, std::min(blocks_for(n, kBlock / kColGroup), kCountBlocks), kBlock, 0, s,
-            a, cb.all_long, nlong, ready);
+            a, cb.all_long, nlong, ready, cap_count);
   LV_LAUNCH(k_col_compact, blocks_for(n, kCompactTile), kBlock, 0, s, ready, n, f.shorts[0],
             f.counts);
   if ((e = hipMemcpyAsync(host_words, nlong, sizeof(ull), hipMemcpyDeviceToHost, s)) !=
@@ -408,7 +414,7 @@ hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid
                                                 kColRoundBlocks);
     const unsigned gl = (unsigned)std::min<ull>(std::max<ull>(nl, 1), kColLongBlocks);
     for (int k = 0; k < kColBatch; k++, r++)
-      LV_LAUNCH(k_col_round, gs + gl, kColBlock, 0, s, a, f, r, gs);
+      LV_LAUNCH(k_col_round, gs + gl, kColBlock, 0, s, a, f, r, gs, cap_short, cap_long);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   *rounds = r;

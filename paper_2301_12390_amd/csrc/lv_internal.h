@@ -298,11 +298,12 @@ struct ColourBuffers {
 };
 // Class of every vertex of pass `pass` (K classes): first-fit colouring in descending priority
 // order, colours 0..K-2, the rest class K-1 (gid/gbase: ids local to each graph of a batch).
-// host_words: pinned host words for read-backs; rounds: Jones-Plassmann rounds taken.
+// host_words: pinned host words for read-backs; rounds: Jones-Plassmann rounds taken;
+// small_stages (testing): tiny per-workgroup append stages, so that their overflow path runs.
 hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid,
                           const int64_t* gbase, const ColourBuffers& cb,
                           unsigned long long* host_words, uint8_t* colour, int* rounds,
-                          hipStream_t s);
+                          bool small_stages, hipStream_t s);
 
 // ---- graph preparation (lv_prep.hip)
 constexpr uint32_t kPrepSym = 0x1u, kPrepLoops = 0x2u, kPrepMax = 0x4u;

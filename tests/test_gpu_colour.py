@@ -149,6 +149,15 @@ def test_colour_run_hubs(lv, gi, flags):
     check_colour_run(lv, HUBS[gi], 8, flags)
 
 
+@pytest.mark.parametrize("K", [2, 8])
+@pytest.mark.parametrize("g", [g for g in CORPUS if g.n >= 1000], ids=[g.name for g in CORPUS
+                                                                     if g.n >= 1000])
+def test_colour_run_small_stages(lv, g, K):
+    # LV_SMALL_PARTS also shrinks the colouring's per-workgroup append stages to a few entries,
+    # so most frontier appends take the overflow path straight to the global lists
+    check_colour_run(lv, g, K, 0x8)
+
+
 def test_colour_run_levels(lv):
     g = rmat(13, seed=9)
     og = O.Graph.from_csr(g)
