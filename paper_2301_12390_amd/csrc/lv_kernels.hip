@@ -424,11 +424,23 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t
       longs[atomicAdd(&nlong, 1)] = r;
       continue;
     }
+    // up to kSumBatch loads in flight per thread (a row's arcs are read in turn, not by
+    // neighbouring lanes, so each thread hides its own latency)
+    constexpr int kSumBatch = 8;
     ull acc = 0, sl = 0;
-    for (int64_t e = e0; e < e1; e++) {
-      const ull x = (ull)w[e];
-      acc += x;
-      if (SELF && idx[e] == (int32_t)r) sl += x;
+    for (int64_t e = e0; e < e1; e += kSumBatch) {
+      ull x[kSumBatch];
+      int32_t j[kSumBatch];
+#pragma unroll
+      for (int q = 0; q < kSumBatch; q++) {
+        x[q] = e + q < e1 ? (ull)w[e + q] : 0;
+        if (SELF) j[q] = e + q < e1 ? idx[e + q] : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < kSumBatch; q++) {
+        acc += x[q];
+        if (SELF && j[q] == (int32_t)r) sl += x[q];
+      }
     }
     if (b0 >= lo && b1 <= hi) {
       K[r] = acc;
@@ -444,11 +456,22 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(const int64_t* off, int64_t
     const int64_t r = longs[i];
     const int64_t b0 = off[r], b1 = off[r + 1];
     const int64_t e0 = b0 > lo ? b0 : lo, e1 = b1 < hi ? b1 : hi;
+    constexpr int kWaveBatch = 8;  // loads in flight per lane
     ull acc = 0, sl = 0;
-    for (int64_t e = e0 + lane; e < e1; e += 64) {
-      const ull x = (ull)ld_stream(w + e);
-      acc += x;
-      if (SELF && ld_stream(idx + e) == (int32_t)r) sl += x;
+    for (int64_t e = e0 + lane; e < e1; e += 64 * kWaveBatch) {
+      ull x[kWaveBatch];
+      int32_t j[kWaveBatch];
+#pragma unroll
+      for (int q = 0; q < kWaveBatch; q++) {
+        const int64_t eq = e + 64 * q;
+        x[q] = eq < e1 ? (ull)ld_stream(w + eq) : 0;
+        if (SELF) j[q] = eq < e1 ? ld_stream(idx + eq) : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < kWaveBatch; q++) {
+        acc += x[q];
+        if (SELF && j[q] == (int32_t)r) sl += x[q];
+      }
     }
     acc = group_sum_u64<64>(acc);
     if (SELF) sl = group_sum_u64<64>(sl);
