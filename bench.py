@@ -1176,6 +1176,33 @@ def main():
         "move_teps": move_teps,
     }
     del memb
+    # the random-access ceiling, measured after the timed runs on a table the size of the
+    # first pass's community records (16 bytes per vertex): the move tiers' gathers per second
+    # set against it (the records of later passes are smaller, so this ceiling is the lowest
+    # the run meets)
+    table = 16 * g.n
+    ceiling = lv.probe_gather(table, 1)
+    line["gather_ceiling"] = {"probe": "louvain_probe_gather: 4.2M threads x 64 random "
+                                       "4-byte gathers", "table_bytes": table, "slices": 1,
+                              "gathers_per_s": ceiling,
+                              "gathers_per_s_xcd_sliced": lv.probe_gather(table, 8)}
+    for t in tiers:
+        if "gathers_per_s" in t and ceiling > 0:
+            t["gather_frac"] = t["gathers_per_s"] / ceiling
+    # the whole move phase: every iteration's gathers (all tiers) over its wall time
+    mg = sum(t["fused_arcs"] + t["wg_arcs"] + t["hub_arcs"] + t["candidates"]
+             for r in results for t in r["trace"])
+    mms = sum(t["iter_ms"] for r in results for t in r["trace"])
+    if mms > 0 and ceiling > 0:
+        line["move_phase_gathers"] = {"gathers": mg / len(results), "ms": mms / len(results),
+                                      "gathers_per_s": mg / (mms / 1000.0),
+                                      "frac_of_ceiling": mg / (mms / 1000.0) / ceiling}
+    if "gathers_per_s" in dom and ceiling > 0:
+        line["roofline_gather"] = {"kernel": dom["kernel"], "bound": "random gathers",
+                                   "achieved": dom["gathers_per_s"], "peak": ceiling,
+                                   "unit": "gathers/s", "frac": dom["gather_frac"]}
+    log(f"gather ceiling: {ceiling / 1e9:.1f}e9/s over {table / 2**20:.0f} MiB; dominant tier "
+        f"{dom['tier']} at {dom.get('gathers_per_s', 0) / 1e9:.1f}e9/s")
     if not args.no_extra:
         # the fully synchronous rule (one class per iteration) on the same graph, one run
         lv.run(g, substeps=1)
@@ -1244,7 +1271,8 @@ def tier_rooflines(results, offsets_64):
     of the launch on the stream it ran on, summed over the timed runs. The three move tiers of
     a class step run concurrently on three streams, so each tier's time is stretched by the
     others and the rates are lower bounds of what each tier achieves alone."""
-    acc = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0} for k in ("fused", "wg", "hub", "agg")}
+    acc = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0, "gathers": 0.0}
+           for k in ("fused", "wg", "hub", "agg")}
     for r in results:
         for t in r["trace"]:
             o = 8 if (t["pass"] == 0 and offsets_64) else (4 if t["pass"] == 0 else 16)
@@ -1262,6 +1290,8 @@ def tier_rooflines(results, offsets_64):
                 acc[key]["launches"] += nl
                 acc[key]["bytes"] += ((o + BYTES_PER_VERTEX_BASE) * v + BYTES_PER_ARC * a
                                       + BYTES_PER_CANDIDATE * c)
+                # random gathers: a neighbour's community per arc, a candidate's Sigma
+                acc[key]["gathers"] += a + c
         for p in range(r["passes"] - 1):
             if r["aggregate_ms"][p] <= 0:
                 continue
@@ -1280,9 +1310,13 @@ def tier_rooflines(results, offsets_64):
         avg = a["ms"] / a["launches"]
         bpl = a["bytes"] / a["launches"]
         gbps = bpl / (avg / 1000.0) / 1e9 if avg > 0 else 0.0
-        out.append({"tier": key, "kernel": names[key], "ms_total": a["ms"],
-                    "launches": a["launches"], "avg_launch_ms": avg, "bytes_per_launch": bpl,
-                    "achieved_gbps": gbps, "frac": gbps / HBM_PEAK_GBPS})
+        t = {"tier": key, "kernel": names[key], "ms_total": a["ms"],
+             "launches": a["launches"], "avg_launch_ms": avg, "bytes_per_launch": bpl,
+             "achieved_gbps": gbps, "frac": gbps / HBM_PEAK_GBPS}
+        if a["gathers"] > 0 and avg > 0:
+            t["gathers_per_launch"] = a["gathers"] / a["launches"]
+            t["gathers_per_s"] = t["gathers_per_launch"] / (avg / 1000.0)
+        out.append(t)
     return out
 
 

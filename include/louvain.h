@@ -308,6 +308,18 @@ lv_status louvain_run_partitioned(lv_ctx* ctx, const lv_graph* g, int32_t P,
 lv_status louvain_colour_classes(lv_ctx* ctx, const lv_graph* g, int32_t pass, int32_t K,
                                  uint8_t* classes, int32_t* rounds, void* stream);
 
+/* Measurement, not part of the method: the device's rate of random 4-byte gathers, the
+ * ceiling the local-moving and aggregation kernels run against (each arc reads a neighbour's
+ * record or label at a position with no locality). Every thread of a 4.2M-thread grid makes 64
+ * gathers at hashed positions of a table of table_bytes bytes, rounded down to a multiple of
+ * 4 * slices. With slices > 1, workgroup b gathers only from slice b mod slices; with
+ * slices = 8 each XCD's L2 then holds one eighth of the table. The table (contents
+ * irrelevant) is taken from the context's workspace. rate (host): gathers per second, the best
+ * of three timed launches after a warm-up. Errors: LV_EINVAL for slices outside 1..64, a table
+ * of fewer than 4 * slices bytes or a NULL rate; LV_ENOMEM beyond the budget. */
+lv_status louvain_probe_gather(lv_ctx* ctx, uint64_t table_bytes, int32_t slices, double* rate,
+                               void* stream);
+
 /* Graph preparation flags of louvain_prepare. */
 #define LV_PREP_SYMMETRIZE 0x1u /* add the reverse (v, u, w) of every edge (u, v, w), u != v */
 #define LV_PREP_SELF_LOOPS 0x2u /* add a self-loop of weight 1 on every vertex */

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in ("lv_kernels.hip", "lv_prep.hip", "lv_colour.hip",
                                           "lv_part.hip", "lv_serve.hip",
-                                          "lv_noalloc.hip", "lv_api.hip")]
+                                          "lv_noalloc.hip", "lv_probe.hip", "lv_api.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("lv_device.h", "lv_internal.h")] + [
     os.path.join(ROOT, "include", "louvain.h")]
 LIB = os.path.join(HERE, "liblouvain.so")

@@ -30,7 +30,7 @@ enum SlotId {
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
   S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_CFM, S_LFLAG, S_NOARC,
-  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_LAB, S_COUNT_SLOTS
+  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_LAB, S_PROBE_T, S_PROBE_O, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -1779,6 +1779,38 @@ lv_status louvain_colour_classes(lv_ctx* ctx, const lv_graph* g, int32_t pass, i
   HIPCHK(hipMemcpyAsync(classes, ph.vclass, (size_t)ph.g.n, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   if (rounds) *rounds = ph.colour_rounds;
+  return LV_OK;
+}
+
+lv_status louvain_probe_gather(lv_ctx* ctx, uint64_t table_bytes, int32_t slices, double* rate,
+                               void* stream) {
+  if (!ctx) return LV_EINVAL;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!rate) return fail(ctx, LV_EINVAL, "rate is NULL");
+  *rate = 0;
+  if (slices < 1 || slices > 64) return fail(ctx, LV_EINVAL, "slices must be in 1..64");
+  const uint64_t n = table_bytes / 4 / (uint64_t)slices * (uint64_t)slices;
+  if (n < (uint64_t)slices) return fail(ctx, LV_EINVAL, "the table holds fewer than slices ints");
+  if (n > ((uint64_t)1 << 40)) return fail(ctx, LV_EINVAL, "table_bytes is too large");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* table = nullptr;
+  int32_t* out = nullptr;
+  CHK(wst(ctx, S_PROBE_T, (int64_t)n, &table));
+  CHK(wst(ctx, S_PROBE_O, lv::probe_threads(), &out));
+  HIPCHK(hipMemsetAsync(table, 0, n * sizeof(int32_t), s));
+  HIPCHK(lv::gather_probe(table, n, (uint32_t)slices, out, s));  // warm-up
+  float best = 0;
+  for (int r = 0; r < 3; r++) {
+    HIPCHK(hipEventRecord(ctx->ev[0], s));
+    HIPCHK(lv::gather_probe(table, n, (uint32_t)slices, out, s));
+    HIPCHK(hipEventRecord(ctx->ev[1], s));
+    HIPCHK(hipEventSynchronize(ctx->ev[1]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    if (ms > 0 && (best == 0 || ms < best)) best = ms;
+  }
+  if (best > 0) *rate = (double)lv::probe_gathers() / (best * 1e-3);
   return LV_OK;
 }
 

@@ -287,6 +287,15 @@ hipError_t part_induced(const DevGraph& g, const int32_t* gid, const int64_t* vp
 hipError_t part_offset_labels(int32_t* lab, int64_t n, const int32_t* gid, const int64_t* loff,
                               hipStream_t s);
 
+// ---- gather-rate probe (lv_probe.hip): measurement, not part of the method
+// Threads and gathers of one probe launch (out holds probe_threads() ints).
+int64_t probe_threads();
+int64_t probe_gathers();
+// One launch over table[0, n): slices > 0, n >= slices; workgroup b gathers from slice
+// b mod slices of n / slices entries.
+hipError_t gather_probe(const int32_t* table, uint64_t n, uint32_t slices, int32_t* out,
+                        hipStream_t s);
+
 // ---- colour classes (lv_colour.hip)
 struct ColourBuffers {
   int32_t* slot = nullptr;      // [2n] per vertex: uncoloured higher-priority neighbours, and

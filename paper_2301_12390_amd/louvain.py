@@ -213,6 +213,8 @@ SIGNATURES = {
     "louvain_colour_classes": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.c_int32,
                                               ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int32),
                                               _P]),
+    "louvain_probe_gather": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_double), _P]),
     "louvain_run_partitioned": (ctypes.c_int, [_P, ctypes.POINTER(LvGraph), ctypes.c_int32,
                                                _P, ctypes.POINTER(LvParams), _P,
                                                ctypes.POINTER(LvGraphResult),
@@ -468,6 +470,16 @@ class Louvain:
                                              ctypes.byref(rounds), _stream())
         self._check(st)
         return out[:g.n], rounds.value
+
+    def probe_gather(self, table_bytes, slices=1):
+        """Random 4-byte gathers per second over a table of table_bytes bytes (measurement:
+        the ceiling the move and merge kernels run against; slices > 1 confines workgroup b to
+        slice b mod slices)."""
+        rate = ctypes.c_double(0)
+        st = self.lib.louvain_probe_gather(self.h, int(table_bytes), int(slices),
+                                           ctypes.byref(rate), _stream())
+        self._check(st)
+        return rate.value
 
     def prepare(self, n, src, dst, weights=None, flags=LV_PREP_PAPER, offsets_64=True,
                 weights_64=False, capacity=None) -> PreparedGraph:
