@@ -224,6 +224,12 @@ def test_rmat22_whole_run_exact(lv, rmat22):
     assert [t["S"] for t in res["trace"]] == ref["trace_S"]
     assert [t["moved"] for t in res["trace"]] == ref["trace_moved"]
     assert res["qnum_pass"] == ref["qnum_pass"] and res["nnz_pass"] == ref["nnz_pass"]
+    # per-kernel events: the tiers of s22's class steps run concurrently on three streams
+    from .test_gpu_parity import check_trace_times
+    traced, res3 = lv.run(g, substeps=K_CLASSES, flags=0x2)
+    torch.cuda.synchronize()
+    check_trace_times(res3, traced, memb)
+    assert sum(t["hub_ms"] for t in res3["trace"]) > 0
     # the dendrogram, level by level
     memb2, levels, res2 = lv.run_levels(g, substeps=K_CLASSES)
     torch.cuda.synchronize()

@@ -386,6 +386,29 @@ def test_empty_and_edgeless(lv):
     assert res["qnum"] == ref["qnum"]
 
 
+def check_trace_times(res, memb_traced, memb_plain):
+    # per-kernel events change nothing, and every time derived from them is non-negative and
+    # within its iteration (tier times from the class steps' shared start and end events)
+    assert torch.equal(memb_traced, memb_plain)
+    for t in res["trace"]:
+        for k in ("fused_ms", "wg_ms", "hub_ms", "update_ms"):
+            assert 0 <= t[k] <= t["iter_ms"] + 0.5, (k, t)
+    for p in range(res["passes"] - 1):
+        assert res["aggregate_ms"][p] >= 0
+
+
+@pytest.mark.parametrize("g", [g for g in CORPUS if g.n >= 1000], ids=[g.name for g in CORPUS
+                                                                     if g.n >= 1000])
+def test_trace_times_serial_tiers(lv, g):
+    # small graphs run their tiers one after another on one stream
+    dg = g.to("cuda:0")
+    plain, _ = lv.run(dg, substeps=8)
+    traced, res = lv.run(dg, substeps=8, flags=0x2)
+    torch.cuda.synchronize()
+    check_trace_times(res, traced, plain)
+    assert sum(t["fused_ms"] for t in res["trace"]) > 0
+
+
 def test_errors(lv):
     from paper_2301_12390_amd import LouvainError
     g = two_triangles().to("cuda:0")
