@@ -30,7 +30,7 @@ enum SlotId {
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
   S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_CFM, S_LFLAG, S_NOARC,
-  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_LAB, S_PROBE_T, S_PROBE_O, S_COUNT_SLOTS
+  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_LAB, S_PROBE_T, S_PROBE_O, S_MAP16, S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -726,6 +726,12 @@ lv_status aggregate(lv_ctx* ctx, const lv::DevGraph& g, const int32_t* C, const 
   HIPCHK(hipStreamSynchronize(s));
   const int64_t np = (int64_t)hm[0];
   a.w32 = check32 && hm[2] < ((ull)1 << 32);
+  // few super-vertices: the merges gather new ids from a 16-bit copy of the map (also taken
+  // under LV_SMALL_PARTS, so that small test graphs use it)
+  if (np < (int64_t)0xFFFF && (n >= ((int64_t)1 << 20) || ctx->part_shift != 0)) {
+    CHK(wst(ctx, S_MAP16, n, &a.map16));
+    HIPCHK(lv::narrow_map(map, n, a.map16, s));
+  }
   HIPCHK(lv::fill_i64(a.dcount, 0, np + 1, s));
   CHK(wst(ctx, S_MPART, lv::merge_lds_blocks(b), &a.block_partial));
   // Communities of up to 1024 arcs: the LDS merge; classes 7 .. pf - 1: one workgroup each

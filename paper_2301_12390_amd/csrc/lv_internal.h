@@ -204,6 +204,7 @@ struct AggBuffers {
   int32_t* members = nullptr;  // [n] vertices with arcs, grouped by label
   int64_t* gscan = nullptr;    // [n+1] first flat arc of each member slot
   int32_t* map = nullptr;      // [n] new id of each vertex
+  uint16_t* map16 = nullptr;   // [n] the same in 16 bits (0xFFFF: no arcs), or null
   // output rows (at astart[c] for community c) and scratch
   int32_t* okey = nullptr;     // [nnz]
   uint64_t* ow = nullptr;      // [nnz] (read as uint32 [nnz] when w32)
@@ -286,6 +287,9 @@ hipError_t part_induced(const DevGraph& g, const int32_t* gid, const int64_t* vp
 // lab[v] += loff[gid[v]]
 hipError_t part_offset_labels(int32_t* lab, int64_t n, const int32_t* gid, const int64_t* loff,
                               hipStream_t s);
+
+// The aggregation map in 16 bits (0xFFFF for -1), for fewer than 0xFFFF super-vertices.
+hipError_t narrow_map(const int32_t* map, int64_t n, uint16_t* out, hipStream_t s);
 
 // ---- gather-rate probe (lv_probe.hip): measurement, not part of the method
 // Threads and gathers of one probe launch (out holds probe_threads() ints).
