@@ -30,7 +30,8 @@ enum SlotId {
   S_VCLASS, S_CCNT, S_CFLAG, S_CSHORT, S_CLONG, S_CNLONG, S_PM_VPTR, S_PM_GID, S_PM_FLAG,
   S_PM_POS, S_PM_IDX, S_PM_W, S_PM_OFF, S_PM_APTR, S_PM_LAB, S_PM_LOFF, S_PM_MAP, S_PM_SOFF,
   S_PM_SIDX, S_PM_SW, S_PM_M2, S_GSLICE, S_RTILE, S_GKEEP, S_GTOP, S_CFM, S_LFLAG, S_NOARC,
-  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_LAB, S_PROBE_T, S_PROBE_O, S_MAP16, S_COUNT_SLOTS
+  S_LIVEB, S_REP0, S_REP1, S_PLANTOT, S_LAB, S_PROBE_T, S_PROBE_O, S_MAP16, S_CMID,
+  S_COUNT_SLOTS
 };
 
 struct Slot {
@@ -306,10 +307,11 @@ lv_status colour_phase(lv_ctx* ctx, Phase& ph, hipStream_t s) {
   lv::ColourBuffers cb;
   CHK(wst(ctx, S_VCLASS, n, &vc));
   CHK(wst(ctx, S_CCNT, 2 * n, &cb.slot));
-  CHK(wst(ctx, S_CFLAG, n, &cb.all_long));
+  CHK(wst(ctx, S_CFLAG, 2 * n, &cb.all_long));
   CHK(wst(ctx, S_CSHORT, 2 * n, &cb.shorts));
+  CHK(wst(ctx, S_CMID, 2 * n, &cb.mids));
   CHK(wst(ctx, S_CLONG, 2 * n, &cb.longs));
-  CHK(wst(ctx, S_CNLONG, 7, &cb.counts));
+  CHK(wst(ctx, S_CNLONG, 11, &cb.counts));
   HIPCHK(lv::colour_classes(ph.g, ph.classes, ph.pass, ph.m.gs.gid, ph.m.gs.gbase, cb,
                             ctx->pinned + PIN_MISC, vc, &ph.colour_rounds, ctx->part_shift != 0,
                             s));

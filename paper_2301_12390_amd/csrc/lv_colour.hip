@@ -27,8 +27,8 @@
 //
 // Frontier appends are staged per workgroup. Rounds are enqueued in batches with no host
 // synchronisation inside a batch: each kernel reads its frontier's size from device memory.
-// Rows of up to kColShortRow arcs take a group of 16 lanes, longer ones a 1024-thread
-// workgroup.
+// Rows of up to kColShortRow arcs take a group of 16 lanes, rows of up to kColMidRow a
+// wavefront, longer ones a 1024-thread workgroup.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,6 +53,11 @@ constexpr int kColBatch = 32;          // rounds enqueued between two looks from
 constexpr unsigned kColRoundBlocks = 512;   // largest short-row part of a round (grid-stride)
 constexpr unsigned kColMinBlocks = 8;       // smallest
 constexpr unsigned kColLongBlocks = 256;    // largest grid of a long-row round
+// Smallest mid- and long-row parts of a round: a batch sizes its grids from its first round,
+// and the hubs' rows become ready in bulk later (one workgroup left to them took 196 ms on
+// R-MAT s25's hub round); idle workgroups exit after one read.
+constexpr unsigned kColMidMin = 128;
+constexpr unsigned kColLongMin = 128;
 
 inline unsigned blocks_for(int64_t items, int64_t per_block) {
   int64_t b = (items + per_block - 1) / per_block;
@@ -94,13 +99,22 @@ __device__ __forceinline__ void set_slot(const ColArgs& a, int64_t v, int32_t co
   *reinterpret_cast<int2*>(a.slot + 2 * v) = make_int2(count, 0);
 }
 
-// The frontiers: two alternating lists of each kind (short rows, long rows) and three
-// rotating counters of each kind (round r reads counter r % 3, appends to (r + 1) % 3 and
-// clears (r + 2) % 3 for the round after).
+// Row kinds: short rows (up to kColShortRow arcs) take a group of kColGroup lanes, mid rows (up
+// to kColMidRow arcs) a wavefront, long rows a kColBlock-thread workgroup.
+constexpr int64_t kColMidRow = 4096;
+enum { kShort = 0, kMid = 1, kLong = 2, kKinds = 3 };
+__device__ __forceinline__ int row_kind(int64_t len) {
+  return len <= kColShortRow ? kShort : len <= kColMidRow ? kMid : kLong;
+}
+
+// The frontiers: two alternating lists of each kind and three rotating counters of each kind
+// (round r reads counter r % 3, appends to (r + 1) % 3 and clears (r + 2) % 3 for the round
+// after).
 struct Frontier {
-  int32_t* shorts[2];
-  int32_t* longs[2];
-  ull* counts;  // [6]: short counters 0..2, long counters 3..5
+  int32_t* list[kKinds][2];
+  ull* counts;  // [9]: the counter of kind k for round r at 3k + r % 3
+  __device__ __forceinline__ int32_t* at(int k, int r) const { return list[k][r & 1]; }
+  __device__ __forceinline__ ull* counter(int k, int r) const { return counts + 3 * k + r % 3; }
 };
 
 // Appends u (where `want`) to the list, one atomic per wavefront.
@@ -121,6 +135,7 @@ __device__ __forceinline__ void append(bool want, int32_t u, int32_t* list, ull*
 // capacity go straight to the global list (a testing mode shrinks the capacities to
 // kSmallStage so that this path runs on small graphs).
 constexpr int kStageShort = 4096;
+constexpr int kStageMid = 1024;
 constexpr int kStageLong = 512;
 constexpr int kSmallStage = 4;
 
@@ -153,32 +168,34 @@ __device__ __forceinline__ void stage_flush(const Stage& st, int32_t* list, ull*
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) list[*base + i] = st.list[i];
 }
 
-// Counters of every vertex (groups of kColGroup lanes); rows longer than kColShortRow are
-// counted by k_col_count_long, their ids appended to `longs` (staged per workgroup). ready[v] =
-// 1 marks the short-row vertices of round 0's frontier (gathered by k_col_compact: one atomic
-// per wavefront on the frontier counter, for ~10^7 vertices, serialised on that word for
-// ~0.1 s).
+// Counters of every vertex with a short row (groups of kColGroup lanes); mid and long rows are
+// counted by k_col_count_mid and k_col_count_long, their ids appended to `mids` and `longs`
+// (staged per workgroup; nrows[0], nrows[1] count them). ready[v] = 1 marks the short-row
+// vertices of round 0's frontier (gathered by k_col_compact: one atomic per wavefront on the
+// frontier counter, for ~10^7 vertices, serialised on that word for ~0.1 s).
 constexpr int kCountStage = 1024;
 constexpr unsigned kCountBlocks = 8192;
-__global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs, ull* nlong,
-                                                     int32_t* ready, int cap) {
-  __shared__ int32_t st_long[kCountStage];
-  __shared__ int n_long;
+__global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* mids, int32_t* longs,
+                                                     ull* nrows, int32_t* ready, int cap_mid,
+                                                     int cap_long) {
+  __shared__ int32_t st_mid[kCountStage], st_long[kCountStage / 4];
+  __shared__ int n_mid, n_long;
   __shared__ ull base;
-  if (threadIdx.x == 0) n_long = 0;
+  if (threadIdx.x == 0) n_mid = n_long = 0;
   __syncthreads();
-  const Stage sl{st_long, &n_long, cap};
+  const Stage sm{st_mid, &n_mid, cap_mid}, sl{st_long, &n_long, cap_long};
   const int lane = threadIdx.x & (kColGroup - 1);
   const int64_t groups = (int64_t)gridDim.x * (kBlock / kColGroup);
   for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kColGroup; v < a.n;
        v += groups) {
     const int64_t b = a.rs[v], e = a.re[v];
-    const bool is_long = e - b > kColShortRow;
-    stage_append(lane == 0 && is_long, (int32_t)v, sl, longs, nlong);
-    if (is_long) {
+    const int kind = row_kind(e - b);
+    stage_append(lane == 0 && kind == kMid, (int32_t)v, sm, mids, nrows);
+    stage_append(lane == 0 && kind == kLong, (int32_t)v, sl, longs, nrows + 1);
+    if (kind != kShort) {
       if (lane == 0) {
         a.colour[v] = kUncoloured;
-        set_slot(a, v, 0);  // counted by k_col_count_long
+        set_slot(a, v, 0);  // counted by k_col_count_mid or k_col_count_long
         ready[v] = 0;
       }
       continue;
@@ -202,7 +219,9 @@ __global__ __launch_bounds__(kBlock) void k_col_count(ColArgs a, int32_t* longs,
     }
   }
   __syncthreads();
-  stage_flush(sl, longs, nlong, &base);
+  stage_flush(sm, mids, nrows, &base);
+  __syncthreads();
+  stage_flush(sl, longs, nrows + 1, &base);
 }
 
 // Round 0's short frontier from the ready flags: each workgroup takes kCompactTile vertices,
@@ -245,6 +264,38 @@ __global__ __launch_bounds__(kBlock) void k_col_compact(const int32_t* ready, in
   }
 }
 
+// Counters of the mid rows, a wavefront each (grid-stride over the list); those with no higher
+// neighbour form round 0's mid frontier (staged per workgroup).
+constexpr unsigned kColMidBlocks = 512;  // largest grid of a mid-row kernel
+__global__ __launch_bounds__(kColBlock) void k_col_count_mid(ColArgs a, const int32_t* mids,
+                                                             int64_t count, Frontier f,
+                                                             int cap) {
+  __shared__ int32_t st[kStageMid];
+  __shared__ int nst;
+  __shared__ ull base;
+  if (threadIdx.x == 0) nst = 0;
+  __syncthreads();
+  const Stage sm{st, &nst, cap};
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (kColBlock / 64);
+  for (int64_t t = (blockIdx.x * (int64_t)kColBlock + threadIdx.x) / 64; t < count;
+       t += waves) {  // uniform over the wavefront
+    const int64_t v = mids[t];
+    const uint64_t pv = vertex_draw(a.pass, local_id(v, a.gid, a.gbase));
+    const int64_t e = a.re[v];
+    int c = 0;
+    for (int64_t x = a.rs[v] + lane; x < e; x += 64) {
+      const int64_t u = a.idx[x];
+      if (u != v && precedes(vertex_draw(a.pass, local_id(u, a.gid, a.gbase)), u, pv, v)) c++;
+    }
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, 64);
+    if (lane == 0) a.slot[2 * v] = c;
+    stage_append(lane == 0 && c == 0, (int32_t)v, sm, f.at(kMid, 0), f.counter(kMid, 0));
+  }
+  __syncthreads();
+  stage_flush(sm, f.at(kMid, 0), f.counter(kMid, 0), &base);
+}
+
 __global__ __launch_bounds__(kColBlock) void k_col_count_long(ColArgs a, const int32_t* longs,
                                                               Frontier f) {
   __shared__ int red[kColBlock / 64];
@@ -262,7 +313,7 @@ __global__ __launch_bounds__(kColBlock) void k_col_count_long(ColArgs a, const i
     int t = 0;
     for (int i = 0; i < kColBlock / 64; i++) t += red[i];
     a.slot[2 * v] = t;
-    if (t == 0) f.longs[0][atomicAdd(f.counts + 3, 1ull)] = (int32_t)v;
+    if (t == 0) f.at(kLong, 0)[atomicAdd(f.counter(kLong, 0), 1ull)] = (int32_t)v;
   }
 }
 
@@ -273,23 +324,23 @@ __device__ __forceinline__ uint8_t first_fit(uint32_t used, int K) {
   return avail ? (uint8_t)__ffs(avail) - 1 : (uint8_t)(K - 1);
 }
 
-// Appends a ready vertex (`want`) to the frontier of round `next`.
+// Appends a ready vertex (`want`) to the frontier of its kind for round `next`.
 __device__ __forceinline__ void append_ready(const ColArgs& a, bool want, int64_t u,
-                                             const Frontier& f, int next, const Stage& ss,
-                                             const Stage& sl) {
-  const bool lng = want && a.re[u] - a.rs[u] > kColShortRow;
-  stage_append(want && !lng, (int32_t)u, ss, f.shorts[next & 1], f.counts + next % 3);
-  stage_append(lng, (int32_t)u, sl, f.longs[next & 1], f.counts + 3 + next % 3);
+                                             const Frontier& f, int next, const Stage* st) {
+  const int kind = want ? row_kind(a.re[u] - a.rs[u]) : -1;
+#pragma unroll
+  for (int k = 0; k < kKinds; k++)
+    stage_append(kind == k, (int32_t)u, st[k], f.at(k, next), f.counter(k, next));
 }
 
 // Colours frontier vertex v and pushes to its lower neighbours, with `lanes` threads from
-// `lane`. U arcs per thread per trip, their loads and atomics issued together. U = 4 for both kinds of rows:
-// 16 for long rows measured slower (more registers for the whole round kernel, whose short-row
-// part then holds fewer wavefronts).
+// `lane` (appends staged in `stages`, one per row kind). U arcs per thread per trip, their
+// loads and atomics issued together. U = 4 for every kind of row: 16 for long rows measured
+// slower (more registers for the whole round kernel, whose short-row part then holds fewer
+// wavefronts).
 template <int U>
 __device__ __forceinline__ void colour_push(const ColArgs& a, int64_t v, int lane, int lanes,
-                                            const Frontier& f, int next, const Stage& ss,
-                                            const Stage& sl) {
+                                            const Frontier& f, int next, const Stage* stages) {
   const uint8_t c = first_fit(a.slot[2 * v + 1], a.K);
   if (lane == 0) a.colour[v] = c;
   const uint32_t bit = c < a.K - 1 ? 1u << c : 0u;
@@ -330,44 +381,53 @@ __device__ __forceinline__ void colour_push(const ColArgs& a, int64_t v, int lan
       bool ready = left[k] == 1 || ((was[k] & full) != full && ((was[k] | bit) & full) == full);
       if (ready)
         ready = !(atomicOr((uint32_t*)a.slot + 2 * u[k] + 1, kClaimed) & kClaimed);
-      append_ready(a, ready, u[k], f, next, ss, sl);
+      append_ready(a, ready, u[k], f, next, stages);
     }
   }
 }
 
 // Round r in one launch of kColBlock-thread workgroups: the first gs take the short frontier
-// (groups of kColGroup lanes), the others the long frontier (a workgroup per vertex). Block 0
-// clears the counters of round r + 2.
+// (groups of kColGroup lanes), the next gm the mid frontier (a wavefront per vertex), the others
+// the long frontier (a workgroup per vertex). Block 0 clears the counters of round r + 2.
 __global__ __launch_bounds__(kColBlock) void k_col_round(ColArgs a, Frontier f, int r,
-                                                         unsigned gs, int cap_short,
-                                                         int cap_long) {
-  __shared__ int32_t st_short[kStageShort], st_long[kStageLong];
-  __shared__ int n_short, n_long;
+                                                         unsigned gs, unsigned gm, int cap_short,
+                                                         int cap_mid, int cap_long) {
+  __shared__ int32_t st_short[kStageShort], st_mid[kStageMid], st_long[kStageLong];
+  __shared__ int nst[kKinds];
   __shared__ ull base;
-  if (threadIdx.x == 0) n_short = n_long = 0;
+  if (threadIdx.x < kKinds) nst[threadIdx.x] = 0;
   __syncthreads();
-  const Stage ss{st_short, &n_short, cap_short}, sl{st_long, &n_long, cap_long};
+  const Stage st[kKinds] = {{st_short, &nst[kShort], cap_short},
+                            {st_mid, &nst[kMid], cap_mid},
+                            {st_long, &nst[kLong], cap_long}};
   const int next = r + 1;
   if (blockIdx.x < gs) {  // workgroup-uniform
-    if (blockIdx.x == 0 && threadIdx.x < 2) f.counts[3 * threadIdx.x + (r + 2) % 3] = 0;
-    const int64_t count = (int64_t)f.counts[r % 3];
-    const int32_t* list = f.shorts[r & 1];
+    if (blockIdx.x == 0 && threadIdx.x < kKinds) f.counts[3 * threadIdx.x + (r + 2) % 3] = 0;
+    const int64_t count = (int64_t)*f.counter(kShort, r);
+    const int32_t* list = f.at(kShort, r);
     const int lane = threadIdx.x & (kColGroup - 1);
     const int64_t groups = (int64_t)gs * (kColBlock / kColGroup);
     for (int64_t t = (blockIdx.x * (int64_t)kColBlock + threadIdx.x) / kColGroup; t < count;
          t += groups)
-      colour_push<4>(a, list[t], lane, kColGroup, f, next, ss, sl);
+      colour_push<4>(a, list[t], lane, kColGroup, f, next, st);
+  } else if (blockIdx.x < gs + gm) {
+    const int64_t count = (int64_t)*f.counter(kMid, r);
+    const int32_t* list = f.at(kMid, r);
+    const int64_t waves = (int64_t)gm * (kColBlock / 64);
+    for (int64_t t = ((blockIdx.x - gs) * (int64_t)kColBlock + threadIdx.x) / 64; t < count;
+         t += waves)
+      colour_push<4>(a, list[t], threadIdx.x & 63, 64, f, next, st);
   } else {
-    const int64_t count = (int64_t)f.counts[3 + r % 3];
-    const int32_t* list = f.longs[r & 1];
-    const unsigned gl = gridDim.x - gs;
-    for (int64_t t = blockIdx.x - gs; t < count; t += gl)
-      colour_push<4>(a, list[t], threadIdx.x, kColBlock, f, next, ss, sl);
+    const int64_t count = (int64_t)*f.counter(kLong, r);
+    const int32_t* list = f.at(kLong, r);
+    const unsigned gl = gridDim.x - gs - gm;
+    for (int64_t t = blockIdx.x - gs - gm; t < count; t += gl)
+      colour_push<4>(a, list[t], threadIdx.x, kColBlock, f, next, st);
   }
-  __syncthreads();
-  stage_flush(ss, f.shorts[next & 1], f.counts + next % 3, &base);
-  __syncthreads();
-  stage_flush(sl, f.longs[next & 1], f.counts + 3 + next % 3, &base);
+  for (int k = 0; k < kKinds; k++) {
+    __syncthreads();
+    stage_flush(st[k], f.at(k, next), f.counter(k, next), &base);
+  }
 }
 
 }  // namespace
@@ -380,41 +440,48 @@ hipError_t colour_classes(const DevGraph& g, int K, int pass, const int32_t* gid
   if (K < 2 || K > 32) return hipErrorInvalidValue;  // K = 1 is one class, no colouring
   if (n <= 0) return hipSuccess;
   ColArgs a{g.rs, g.re, g.idx, n, pass, K, gid, gbase, cb.slot, colour};
-  Frontier f{{cb.shorts, cb.shorts + n}, {cb.longs, cb.longs + n}, cb.counts};
+  Frontier f{{{cb.shorts, cb.shorts + n}, {cb.mids, cb.mids + n}, {cb.longs, cb.longs + n}},
+             cb.counts};
   hipError_t e;
-  if ((e = zero_words(cb.counts, 7, s)) != hipSuccess) return e;  // 6 counters + nlong
-  ull* nlong = cb.counts + 6;
+  if ((e = zero_words(cb.counts, 11, s)) != hipSuccess) return e;  // 9 counters + 2 row counts
+  ull* nrows = cb.counts + 9;
   int32_t* ready = cb.shorts + n;  // round 0 appends to shorts[1] only after this is read
-  const int cap_count = small_stages ? kSmallStage : kCountStage;
-  const int cap_short = small_stages ? kSmallStage : kStageShort;
-  const int cap_long = small_stages ? kSmallStage : kStageLong;
+  const int cap = small_stages ? kSmallStage : 0;  // 0: each stage's full size
   LV_LAUNCH(k_col_count, std::min(blocks_for(n, kBlock / kColGroup), kCountBlocks), kBlock, 0, s,
-            a, cb.all_long, nlong, ready, cap_count);
-  LV_LAUNCH(k_col_compact, blocks_for(n, kCompactTile), kBlock, 0, s, ready, n, f.shorts[0],
-            f.counts);
-  if ((e = hipMemcpyAsync(host_words, nlong, sizeof(ull), hipMemcpyDeviceToHost, s)) !=
+            a, cb.all_long, cb.all_long + n, nrows, ready, cap ? cap : kCountStage,
+            cap ? cap : kCountStage / 4);
+  LV_LAUNCH(k_col_compact, blocks_for(n, kCompactTile), kBlock, 0, s, ready, n, f.list[kShort][0],
+            cb.counts);
+  if ((e = hipMemcpyAsync(host_words, nrows, 2 * sizeof(ull), hipMemcpyDeviceToHost, s)) !=
       hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  if (host_words[0] > 0)
-    LV_LAUNCH(k_col_count_long, (unsigned)host_words[0], kColBlock, 0, s, a, cb.all_long, f);
+  const ull nmid = host_words[0], nlong = host_words[1];
+  if (nmid > 0)
+    LV_LAUNCH(k_col_count_mid, (unsigned)std::min<ull>((nmid + 15) / 16, kColMidBlocks),
+              kColBlock, 0, s, a, cb.all_long, (int64_t)nmid, f, cap ? cap : kStageMid);
+  if (nlong > 0)
+    LV_LAUNCH(k_col_count_long, (unsigned)nlong, kColBlock, 0, s, a, cb.all_long + n, f);
   // rounds in batches; a batch ends with a look at the next round's frontier sizes, which also
   // sizes the next batch's grids (any grid is correct: the kernels stride over their frontier)
   int r = 0;
   while (true) {
-    if ((e = hipMemcpyAsync(host_words, cb.counts, 6 * sizeof(ull), hipMemcpyDeviceToHost, s)) !=
+    if ((e = hipMemcpyAsync(host_words, cb.counts, 9 * sizeof(ull), hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
       return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const ull ns = host_words[r % 3], nl = host_words[3 + r % 3];
-    if (ns == 0 && nl == 0) break;
+    const ull ns = host_words[r % 3], nm = host_words[3 + r % 3], nl = host_words[6 + r % 3];
+    if (ns == 0 && nm == 0 && nl == 0) break;
     if (r > n + kColBatch) return hipErrorUnknown;  // cannot happen: each round colours a vertex
     const ull want_s = (ns + kColBlock / kColGroup - 1) / (kColBlock / kColGroup);
     const unsigned gs = (unsigned)std::min<ull>(std::max<ull>(want_s, kColMinBlocks),
                                                 kColRoundBlocks);
-    const unsigned gl = (unsigned)std::min<ull>(std::max<ull>(nl, 1), kColLongBlocks);
+    const unsigned gm = (unsigned)std::min<ull>(std::max<ull>((nm + 15) / 16, kColMidMin),
+                                                kColMidBlocks);
+    const unsigned gl = (unsigned)std::min<ull>(std::max<ull>(nl, kColLongMin), kColLongBlocks);
     for (int k = 0; k < kColBatch; k++, r++)
-      LV_LAUNCH(k_col_round, gs + gl, kColBlock, 0, s, a, f, r, gs, cap_short, cap_long);
+      LV_LAUNCH(k_col_round, gs + gm + gl, kColBlock, 0, s, a, f, r, gs, gm,
+                cap ? cap : kStageShort, cap ? cap : kStageMid, cap ? cap : kStageLong);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   *rounds = r;

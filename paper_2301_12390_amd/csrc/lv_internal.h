@@ -304,10 +304,11 @@ hipError_t gather_probe(const int32_t* table, uint64_t n, uint32_t slices, int32
 struct ColourBuffers {
   int32_t* slot = nullptr;      // [2n] per vertex: uncoloured higher-priority neighbours, and
                                 //   the mask of the colours the coloured ones hold
-  int32_t* all_long = nullptr;  // [n] vertices with long rows
+  int32_t* all_long = nullptr;  // [2n] vertices with mid rows, then (from n) with long rows
   int32_t* shorts = nullptr;    // [2n] two alternating frontiers of short-row vertices
+  int32_t* mids = nullptr;      // [2n] two alternating frontiers of mid-row vertices
   int32_t* longs = nullptr;     // [2n] two alternating frontiers of long-row vertices
-  unsigned long long* counts = nullptr;  // [7] frontier counters and the long-row count
+  unsigned long long* counts = nullptr;  // [11] frontier counters, mid and long row counts
 };
 // Class of every vertex of pass `pass` (K classes): first-fit colouring in descending priority
 // order, colours 0..K-2, the rest class K-1 (gid/gbase: ids local to each graph of a batch).
