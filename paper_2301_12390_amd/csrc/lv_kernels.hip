@@ -1619,8 +1619,12 @@ __device__ int part_walk(Acc& acc, int64_t k0, int64_t k1, int P, int32_t* keys,
 // from hrow) belong to its phase-1 workgroups, R consecutive rows each, of which workgroup i
 // used the first nflush[i]; its pairs are at pk/pv + (i * R) * Q. cap <= part_cap(LOG2H), so
 // the claims made before every thread sees the overflow still find free slots. flags: 4 shared
-// ints (claimed slots, overflow, and two for fin).
-template <typename V, int LOG2H, typename Fin>
+// ints (claimed slots, overflow, and two for fin). With FIT > 0, when the item's rows fit one
+// tile, the table is sized to the partition: the smallest power of two (at least 256 slots)
+// holding 2^FIT times its pairs, so all its keys fit one round, and a partition of few keys
+// clears and scans few slots (partitions are sized by the item's length, as if every key were
+// distinct, and once communities have formed they hold far fewer).
+template <typename V, int LOG2H, int FIT, typename Fin>
 __device__ void part_reduce(const int32_t* pk, const V* pv, const int32_t* hrow,
                             const int32_t* nflush, int64_t nck, int64_t R, int P, int p, int cap,
                             int32_t* keys, V* vals, unsigned char* aux, int* wsum, int* flags,
@@ -1633,10 +1637,38 @@ __device__ void part_reduce(const int32_t* pk, const V* pv, const int32_t* hrow,
   const int lp = ilog2_i64(P);
   const uint64_t pbeg = (uint64_t)p << (32 - lp);
   const uint64_t pend = (uint64_t)(p + 1) << (32 - lp);
+  // the segment bounds of the rows of tile t0 into sbeg / sstart (exclusive scan); returns the
+  // tile's pairs of partition p
+  auto load_tile = [&](int64_t t0, int nt) -> int {
+    for (int i = threadIdx.x; i < nt; i += kPartBlock) {
+      const int64_t r = t0 + i;
+      const int64_t blk = r / R;
+      int len = 0;
+      if (r - blk * R < nflush[blk]) {
+        const int32_t* row = hrow + r * (int64_t)(P + 1);
+        const int32_t s0 = row[p];
+        sbeg[i] = blk * R * Q + s0;
+        len = row[p + 1] - s0;
+      }
+      sstart[i] = len;
+    }
+    __syncthreads();
+    return block_scan_excl(sstart, nt, wsum);
+  };
+  int log2h = LOG2H;
+  if (FIT > 0 && nck <= kPartTile) {
+    const int total = load_tile(0, (int)nck);
+    int l = 8;
+    while (l < LOG2H && (1 << l) < ((int64_t)total << FIT)) l++;
+    log2h = l;
+    __syncthreads();
+  }
+  const int Hs = 1 << log2h;
+  const int capr = cap < part_cap(log2h) ? cap : part_cap(log2h);
   uint64_t lo = pbeg, width = pend - pbeg;
   while (lo < pend) {
     const uint64_t hi = lo + width < pend ? lo + width : pend;
-    part_table_clear<V>(keys, vals, H);
+    part_table_clear<V>(keys, vals, Hs);
     if (threadIdx.x == 0) {
       flags[0] = 0;
       flags[1] = 0;
@@ -1644,20 +1676,7 @@ __device__ void part_reduce(const int32_t* pk, const V* pv, const int32_t* hrow,
     __syncthreads();
     for (int64_t t0 = 0; t0 < nck; t0 += kPartTile) {
       const int nt = (int)(nck - t0 < kPartTile ? nck - t0 : kPartTile);
-      for (int i = threadIdx.x; i < nt; i += kPartBlock) {
-        const int64_t r = t0 + i;
-        const int64_t blk = r / R;
-        int len = 0;
-        if (r - blk * R < nflush[blk]) {
-          const int32_t* row = hrow + r * (int64_t)(P + 1);
-          const int32_t s0 = row[p];
-          sbeg[i] = blk * R * Q + s0;
-          len = row[p + 1] - s0;
-        }
-        sstart[i] = len;
-      }
-      __syncthreads();
-      const int total = block_scan_excl(sstart, nt, wsum);
+      const int total = load_tile(t0, nt);
       for (int f = threadIdx.x; f < total; f += kPartBlock) {
         if (*(volatile int*)&flags[1]) break;
         int a = 0, b = nt;  // sstart[a] <= f < sstart[b] (segment a is the non-empty one)
@@ -1669,7 +1688,7 @@ __device__ void part_reduce(const int32_t* pk, const V* pv, const int32_t* hrow,
         const int32_t key = pk[pos];
         const uint64_t hk = fmix32((uint32_t)key);
         if (hk >= lo && hk < hi)
-          table_add_capped<V>(keys, vals, LOG2H, key, pv[pos], &flags[0], cap, &flags[1]);
+          table_add_capped<V>(keys, vals, log2h, key, pv[pos], &flags[0], capr, &flags[1]);
       }
       __syncthreads();
     }
@@ -1679,7 +1698,7 @@ __device__ void part_reduce(const int32_t* pk, const V* pv, const int32_t* hrow,
       width = (hi - lo) / 2 > 0 ? (hi - lo) / 2 : 1;
       continue;
     }
-    fin(keys, vals, H);
+    fin(keys, vals, Hs);
     __syncthreads();
     lo = hi;
   }
@@ -1837,9 +1856,9 @@ __global__ __launch_bounds__(kPartBlock) void k_hub_reduce(
   fin.bc = INT32_MAX;
   fin.kd = 0;
   fin.nc = 0;
-  part_reduce<V, LOG2H>(a.pk + c0 * Q, a.pv + c0 * Q, a.hoff + a.hoff_start[h],
-                        a.nflush + a.block_start[h], nck, a.rper[h], P, p, a.cap, keys, vals,
-                        aux, wsum, flags, fin);
+  part_reduce<V, LOG2H, 1>(a.pk + c0 * Q, a.pv + c0 * Q, a.hoff + a.hoff_start[h],
+                           a.nflush + a.block_start[h], nck, a.rper[h], P, p, a.cap, keys, vals,
+                           aux, wsum, flags, fin);
   T bg = fin.bg;
   int32_t bc = fin.bc;
   ull kd = fin.kd, nc = fin.nc;
@@ -3002,9 +3021,9 @@ __global__ __launch_bounds__(kPartBlock) void k_merge_reduce(MergeHubArgs<WT, V>
   fin.base_sh = &base_sh;
   fin.gself = a.gself ? a.gself + a.gid[c] : nullptr;
   fin.self = 0;
-  part_reduce<V, kMergeLog2H>(a.pk + c0 * kMergeChunk, a.pv + c0 * kMergeChunk,
-                                a.hoff + a.hoff_start[h], a.nflush + a.block_start[h], nck,
-                                a.rper[h], P, p, a.cap, keys, vals, aux, wsum, flags, fin);
+  part_reduce<V, kMergeLog2H, 0>(a.pk + c0 * kMergeChunk, a.pv + c0 * kMergeChunk,
+                                   a.hoff + a.hoff_start[h], a.nflush + a.block_start[h], nck,
+                                   a.rper[h], P, p, a.cap, keys, vals, aux, wsum, flags, fin);
   const ull bs = part_block_sum(fin.self, red);
   if (threadIdx.x == 0 && bs) atomicAdd(&a.stats[0], bs);
 }
