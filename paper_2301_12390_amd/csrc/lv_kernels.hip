@@ -2069,31 +2069,35 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(const int32_t* verts, in
       if (sw) atomicAdd(&stats[5], sw);
     }
   }
-  // whole workgroups iterate together (the table is shared)
+  // The table is cleared once; each tile's flush empties the slots it used. A tile without
+  // movers (most of them once the step's class has settled) touches no slot and is skipped
+  // after one vote. Whole workgroups iterate together (the table is shared).
+  for (int t = threadIdx.x; t < S; t += kBlock) {
+    ckey[t] = kEmpty;
+    csig[t] = 0;
+    ccnt[t] = 0;
+  }
+  __syncthreads();
   for (int64_t base = blockIdx.x * (int64_t)kBlock; base < count;
        base += (int64_t)gridDim.x * kBlock) {
-    for (int t = threadIdx.x; t < S; t += kBlock) {
-      ckey[t] = kEmpty;
-      csig[t] = 0;
-      ccnt[t] = 0;
-    }
-    __syncthreads();
     const int64_t i = base + threadIdx.x;
+    int32_t v = 0, c = 0, d = 0;
     if (i < count) {
-      const int32_t v = verts[i];
-      const int32_t c = tgt[v];
-      const int32_t d = rec[v].c;
-      if (c != d) {
-        const ull k = (ull)K[v];
-        rec[v].c = c;
-        if (lab) lab[v] = c;
-        const int sc = comb_slot<kApplyLog2>(ckey, c);
-        atomicAdd(&csig[sc], k);
-        atomicAdd(&ccnt[sc], 1);
-        const int sd = comb_slot<kApplyLog2>(ckey, d);
-        atomicAdd(&csig[sd], 0ull - k);
-        atomicAdd(&ccnt[sd], -1);
-      }
+      v = verts[i];
+      c = tgt[v];
+      d = rec[v].c;
+    }
+    if (!__syncthreads_or(c != d)) continue;
+    if (c != d) {
+      const ull k = (ull)K[v];
+      rec[v].c = c;
+      if (lab) lab[v] = c;
+      const int sc = comb_slot<kApplyLog2>(ckey, c);
+      atomicAdd(&csig[sc], k);
+      atomicAdd(&ccnt[sc], 1);
+      const int sd = comb_slot<kApplyLog2>(ckey, d);
+      atomicAdd(&csig[sd], 0ull - k);
+      atomicAdd(&ccnt[sd], -1);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < S; t += kBlock) {
@@ -2101,6 +2105,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(const int32_t* verts, in
       if (x == kEmpty) continue;
       if (csig[t]) atomicAdd((ull*)&rec[x].sig, csig[t]);
       if (ccnt[t]) atomicAdd(&rec[x].size, ccnt[t]);
+      ckey[t] = kEmpty;
+      csig[t] = 0;
+      ccnt[t] = 0;
     }
     __syncthreads();
   }
