@@ -143,7 +143,7 @@ struct MoveBuffers {
                                         //   (graphs of up to kLabMaxVertices vertices)
   uint64_t W = 0;
   const int32_t* list = nullptr;
-  int32_t* tgt = nullptr;               // [n] decision of every vertex of the class step
+  int32_t* tgt = nullptr;               // [n] class-step decisions, by list position
   unsigned long long* block_partial = nullptr;  // 4 words per block of the LDS move kernel
   // per class step, 8 words: [0..1] S, [2] moved, [3] candidates, [4] candidates of the fused
   // kernel, [5] candidates of the workgroup kernel

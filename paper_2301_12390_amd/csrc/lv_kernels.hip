@@ -1041,6 +1041,9 @@ __device__ __forceinline__ void gs_add_block(const GraphSet& gs, int32_t gr, u12
   }
 }
 
+// A class step's decision for a vertex that keeps its community.
+constexpr int32_t kStay = -1;
+
 template <typename WT>
 struct MoveArgs {
   const int64_t* rs;
@@ -1054,7 +1057,7 @@ struct MoveArgs {
   const int32_t* list;
   int64_t bstart[8];  // first block of class k; bstart[7] = total blocks
   int64_t lstart[8];  // first list position of class k; lstart[7] = end of class 6
-  int32_t* tgt;       // decision of every vertex: its community after the step
+  int32_t* tgt;       // decisions by list position: the new community of a mover, else kStay
   ull* partial;       // per block: gain sum (2 words), moves, candidate pairs
   GraphSet gs;        // batch of graphs (gs.gid null: one graph, W above)
 };
@@ -1173,7 +1176,7 @@ __device__ __forceinline__ void move_group(const MoveArgs<WT>& a, int64_t lb, in
         gain = Ar::diff(bg, stay);
       }
     }
-    a.tgt[v] = target;
+    a.tgt[lbase + li] = moved ? target : kStay;
   }
   // block totals go to this block's own record: no contended atomics in the hot kernel
   const u128 bsum = block_sum_u128(gain, sh.red128);
@@ -1228,7 +1231,7 @@ struct WgArgs {
   const int32_t* lab;
   uint64_t W;
   const int32_t* rows;  // the class's rows
-  int32_t* tgt;
+  int32_t* tgt;         // their decisions, by row (as MoveArgs)
   ull* partial;         // this launch's block records
   GraphSet gs;
 };
@@ -1322,7 +1325,7 @@ __global__ __launch_bounds__(kWgBlock) void k_move_wg(WgArgs<WT> a) {
         gs_add_gain(a.gs, gr, gain);
       }
     }
-    a.tgt[v] = target;
+    a.tgt[blockIdx.x] = moved ? target : kStay;
     ull* o = a.partial + 4 * (int64_t)blockIdx.x;
     o[0] = (ull)gain;
     o[1] = (ull)(gain >> 64);
@@ -1444,6 +1447,7 @@ static hipError_t move_wg_t(const DevGraph& g, const Buckets& b, int cls, const 
     const int64_t rows = b.count[base + k];
     if (rows == 0) continue;
     wa.rows = m.list + b.lstart[base + k];
+    wa.tgt = m.tgt + b.lstart[base + k];
     wa.partial = m.block_partial + 4 * records;
     hipError_t e = hipSuccess;
     if (k == 7) {
@@ -1728,7 +1732,7 @@ struct HubArgs {
   int32_t* nflush;   // flushes of every phase-1 workgroup
   int cap;           // phase-2 claim cap per round
   ull* partial;      // 5 words per phase-2 workgroup: gain lo, gain hi, community, kd, candidates
-  int32_t* tgt;
+  int32_t* tgt;      // decisions of the hubs, by hub (as MoveArgs)
   ull* stats;
   GraphSet gs;
 };
@@ -1942,7 +1946,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_decide(HubArgs<WT, typename Gain
         gs_add_gain(a.gs, gr, gain);
       }
     }
-    a.tgt[v] = target;
+    a.tgt[h] = moved ? target : kStay;
   }
   const u128 bs = block_sum_u128(gain, red);
   const ull ns = block_sum_u64(nc, red64);
@@ -1988,7 +1992,7 @@ static hipError_t move_hubs_t(const DevGraph& g, const Buckets& b, int cls, cons
   a.nflush = m.nflush;
   a.cap = part_round_cap(part_log2h(vb), pp.shift);
   a.partial = m.partial;
-  a.tgt = m.tgt;
+  a.tgt = m.tgt + b.lstart[kDegClasses * cls + m.hub_first];
   a.stats = m.stats;
   a.gs = m.gs;
   static const bool attr = [] {  // once, thread-safe (see launch_wg)
@@ -2034,7 +2038,8 @@ __device__ __forceinline__ int comb_slot(int32_t* keys, int32_t x) {
 // The same launch also sums the move kernels' per-block records into the class step's
 // statistics, in its first kApplyReduceBlocks workgroups: [0..1] gain sum, [2] moves, [3]
 // candidate pairs, [4] those of the fused kernel (records < nfused), [5] those of the
-// workgroup kernel.
+// workgroup kernel. Decisions come by list position (tgt[i] for verts[i]), so they are read
+// in order, and only a mover's record is gathered.
 constexpr int kApplyLog2 = 10;  // 1024 slots for the 2 * kBlock communities of a tile
 constexpr int kApplyReduceBlocks = 256;
 __global__ __launch_bounds__(kBlock) void k_apply_moves(const int32_t* verts, int64_t count,
@@ -2081,11 +2086,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(const int32_t* verts, in
   for (int64_t base = blockIdx.x * (int64_t)kBlock; base < count;
        base += (int64_t)gridDim.x * kBlock) {
     const int64_t i = base + threadIdx.x;
-    int32_t v = 0, c = 0, d = 0;
+    int32_t v = 0, c = kStay, d = kStay;
     if (i < count) {
-      v = verts[i];
-      c = tgt[v];
-      d = rec[v].c;
+      c = tgt[i];
+      if (c != kStay) {
+        v = verts[i];
+        d = rec[v].c;
+      }
     }
     if (!__syncthreads_or(c != d)) continue;
     if (c != d) {
@@ -2121,8 +2128,8 @@ hipError_t apply_moves(const Buckets& b, int cls, const MoveBuffers& m, hipStrea
   if (count <= 0 && records == 0) return hipSuccess;
   const unsigned grid = count > 0 ? grid_for(count, kBlock, 8192)
                                   : grid_for(records, kBlock, kApplyReduceBlocks);
-  LV_LAUNCH(k_apply_moves, grid, kBlock, 0, s, m.list + first, count, m.tgt, m.K, (VRec*)m.rec,
-            m.lab, m.block_partial, records, fused, m.stats);
+  LV_LAUNCH(k_apply_moves, grid, kBlock, 0, s, m.list + first, count, m.tgt + first, m.K,
+            (VRec*)m.rec, m.lab, m.block_partial, records, fused, m.stats);
   return hipGetLastError();
 }
 
