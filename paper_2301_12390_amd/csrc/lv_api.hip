@@ -657,11 +657,12 @@ lv_status run_phase(lv_ctx* ctx, Phase& ph, u128 T, int max_it, uint32_t flags, 
       memcpy(bp->hact, bp->act.data(), (size_t)bp->G);
       HIPCHK(hipMemcpyAsync((void*)ph.m.gs.act, bp->hact, (size_t)bp->G, hipMemcpyHostToDevice,
                             s));
-      // once most listed vertices belong to graphs that stopped, list only the others again
+      // once a quarter of the listed vertices belong to graphs that stopped, list only the
+      // others again (their rows cost a class step's kernels even with no arcs to read)
       int64_t live = 0;
       for (int64_t g = 0; g < bp->G; g++)
         if (bp->act[g]) live += bp->size[g];
-      if (2 * live < bp->listed) {
+      if (4 * live < 3 * bp->listed) {
         CHK(plan_phase(ctx, ph, s));
         bp->listed = live;
         graph.reset();
