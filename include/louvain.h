@@ -37,10 +37,11 @@
  * with host outputs synchronise `stream` before returning. The library owns only its context
  * workspace (tables, scan temporaries, super-vertex graphs), charged to the HBM budget given
  * at creation. `stream` is a hipStream_t. The library enqueues nothing on the null stream of
- * its own accord and never synchronises the device: all its work goes to `stream` and to
- * non-blocking side streams that it forks from and joins back to `stream` with events. A
- * caller whose own stream is the default one (torch's default stream) passes NULL, and the
- * work then runs there.
+ * its own accord and never synchronises the device: a call's work goes to its `stream` and to
+ * non-blocking side streams that it forks from and joins back to `stream` with events, and
+ * the server's slots (louvain_server_*) run on non-blocking streams of their own. A caller
+ * whose own stream is the default one (torch's default stream) passes NULL, and the work then
+ * runs there.
  *
  * Errors: every function returns an lv_status; no exception crosses the boundary. On error
  * the outputs are unspecified and the context stays usable (after a sticky HIP error it
